@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the Stokes kernel sums on one MI355X.
+
+Headline workload (the benchmark spec's target is stated at 262k points): the
+spindle geometry -- 4096 straight fibers x 64 CGL nodes = 262,144 points
+radiating from two poles at (+-4, 0, 0), lengths U(1, 6), eps = 0.005 --
+with the Stokeslet + doublet single-layer sum to every node (self-pairs
+excluded), timed as K consecutive GMRES-iteration matvecs, each with its own
+pre-generated seeded force vector N(0,1)/L.  One step = one matvec (source
+preparation + pair sum + chunk reduction).  The mixed FP32/FP64 path is
+`value`; the FP64 path is timed on the same inputs beside it.
+
+Also reported: the roofline of the dominant kernel (counted algorithmic flops
+per launch / kernel time from HIP events on the launch stream), a short
+Poisson serving run (continuous batching of mobility solves) for p50/p99 solve
+latency, and the CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 40] [--warmup 3] [--no-serving] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+METRIC = "Gpair-interactions/s and %VALU peak (mixed vs FP64); p50/p99 solve latency"
+FLOPS_PER_PAIR_SL = 34       # Stokeslet + doublet, counted (add/sub/mul 1, FMA 2, rsqrt 1)
+PEAK_FP32_NONPACKED = 78.6   # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz (no packed FP32)
+PEAK_FP32_PUBLISHED = 157.3  # TFLOP/s: published FP32 vector peak (needs packed FP32)
+PEAK_FP64 = 78.6             # TFLOP/s: published FP64 vector peak
+NEAR_R = 0.06                # mixed path: pairs closer than this (or 2 fiber radii) go FP64
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=150)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_matvecs(S, torch, xyz, forces, fib, flen, eps, mixed, steps, warmup):
+    """Run warmup + steps matvecs; returns (seconds, kernel_ms_total, launches, out of step 0)."""
+    out = torch.empty_like(forces[0])
+    kw = dict(src_fiber=fib, fiber_len=flen, eps=eps, mixed=mixed, near_r=NEAR_R, out=out)
+    for w in range(warmup):
+        S.sl_eval(xyz, forces[w % len(forces)], **kw)
+    torch.cuda.synchronize()
+    first = S.sl_eval(xyz, forces[0], **dict(kw, out=torch.empty_like(forces[0])))
+    torch.cuda.synchronize()
+    S.profile_read()                       # drop anything recorded so far
+    S.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        S.sl_eval(xyz, forces[k % len(forces)], **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.profile_enable(False)
+    ms, launches = S.profile_read()
+    return t1 - t0, ms, launches, first
+
+
+def serving_run(S, n_req, log_fn):
+    from paper_1602_05650_amd import workloads as W
+    reqs = [W.serving_request(3, rid) for rid in range(n_req)]
+    pairs = sum(r["iters"] * r["fibers"].n * (r["fibers"].n - r["fibers"].nodes_per_fiber)
+                for r in reqs)
+
+    def submit(sess, r):
+        fs = r["fibers"]
+        return sess.submit(fs.xyz, fs.tangent, fs.length, r["rhs"], fs.nodes_per_fiber, fs.eps,
+                           r["iters"], tag=r["rid"])
+
+    with S.Session(hbm_budget_bytes=4 << 30, max_slots=64, mixed=True) as sess:
+        # calibration: saturate with the first 24 requests, measure capacity (requests/s)
+        n_cal = min(24, n_req)
+        t0 = time.perf_counter()
+        ts = [submit(sess, r) for r in reqs[:n_cal]]
+        for t in ts:
+            sess.wait(t)
+        cap = n_cal / (time.perf_counter() - t0)
+        rate = 0.7 * cap
+        arrivals = W.serving_stream(3, n_req, rate)
+        log_fn(f"serving: capacity {cap:.1f} req/s (calibration), Poisson rate {rate:.1f} req/s")
+        tickets = [None] * n_req
+        t_sub = [0.0] * n_req
+
+        def producer():
+            start = time.perf_counter()
+            for i, r in enumerate(reqs):
+                dt = arrivals[i] - (time.perf_counter() - start)
+                if dt > 0:
+                    time.sleep(dt)
+                t_sub[i] = time.monotonic_ns()
+                tickets[i] = submit(sess, r)
+
+        th = threading.Thread(target=producer)
+        t_start = time.perf_counter()
+        th.start()
+        lat = []
+        for i in range(n_req):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            _, st = sess.wait(tickets[i])
+            lat.append((st["t_finish_ns"] - st["t_submit_ns"]) * 1e-6)
+        th.join()
+        wall = time.perf_counter() - t_start
+    lat = np.array(lat)
+    return {
+        "requests": n_req, "rate_req_per_s": round(rate, 2), "capacity_req_per_s": round(cap, 2),
+        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "mean_ms": round(float(lat.mean()), 2),
+        "throughput_req_per_s": round(n_req / wall, 2),
+        "gpair_per_s": round(pairs / wall / 1e9, 1),
+        "precision": "mixed sums, FP64 GMRES", "hbm_budget_gib": 4, "max_slots": 64,
+        "workload": "Poisson stream; N_f log-uniform [32, 2048] fibers x {16,32,64} nodes; "
+                    "20-60 GMRES iterations; same-fiber excluded, Clenshaw-Curtis weights",
+    }
+
+
+def cpu_baseline(c, seconds, log_fn):
+    import oracle
+    oracle.build(force=False)
+    fs = c["fibers"]
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    from paper_1602_05650_amd import workloads as W
+    idx = W.subsample(2, fs.n, 4096)
+    kw = dict(src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps, excl=1, nthreads=nthreads)
+    t0 = time.perf_counter()
+    oracle.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx[:32]], trg_self=idx[:32], **kw)
+    dt = time.perf_counter() - t0
+    n_t = int(min(len(idx), max(64, 32 * seconds / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx[:n_t]], trg_self=idx[:n_t], **kw)
+    dt = time.perf_counter() - t0
+    pairs = n_t * (fs.n - 1)
+    log_fn(f"cpu oracle: {n_t} targets x {fs.n} sources in {dt:.2f} s on {nthreads} threads")
+    return {"value": round(pairs / dt / 1e9, 4), "unit": "Gpair/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{n_t} seeded targets of the spindle workload x all {fs.n} sources, "
+                      f"FP64 brute force, self-pairs excluded ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a ROCm GPU")
+    from paper_1602_05650_amd import stokes as S
+    from paper_1602_05650_amd import workloads as W
+
+    t_gen = time.perf_counter()
+    c = W.config2()
+    fs = c["fibers"]
+    n = fs.n
+    rng = np.random.Generator(np.random.PCG64([2, 40]))
+    n_forces = max(1, min(args.steps, 40))
+    forces_h = [rng.standard_normal((3, n)) / fs.length[fs.fiber][None, :] for _ in range(n_forces)]
+    forces_h[0] = c["force"]
+    dev = torch.device("cuda:0")
+    xyz = torch.from_numpy(fs.xyz).to(dev)
+    fib = torch.from_numpy(fs.fiber).to(dev)
+    flen = torch.from_numpy(fs.length).to(dev)
+    forces = [torch.from_numpy(f).to(dev) for f in forces_h]
+    torch.cuda.synchronize()
+    log(f"spindle workload: {n} points, {fs.n_fib} fibers, generated in "
+        f"{time.perf_counter() - t_gen:.1f} s")
+    pairs = n * (n - 1)
+
+    res = {}
+    for mixed in ([True, False] if args.only == "both" else [args.only == "mixed"]):
+        sec, kms, launches, first = time_matvecs(S, torch, xyz, forces, fib, flen, fs.eps, mixed,
+                                                 args.steps, args.warmup)
+        res[mixed] = dict(sec=sec, kms=kms, launches=launches, first=first)
+        tag = "mixed" if mixed else "fp64"
+        log(f"{tag}: {args.steps} matvecs in {sec * 1e3:.1f} ms -> "
+            f"{args.steps * pairs / sec / 1e9:.1f} Gpair/s; kernel {kms / max(launches, 1):.3f} ms "
+            f"x {launches}")
+    head = True if True in res else False
+    r = res[head]
+    value = args.steps * pairs / r["sec"] / 1e9
+    k_avg = r["kms"] / max(r["launches"], 1) * 1e-3
+    achieved = pairs * FLOPS_PER_PAIR_SL / k_avg / 1e12
+    peak = PEAK_FP32_NONPACKED if head else PEAK_FP64
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gpair/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["sec"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "spindle: 4096 fibers x 64 CGL nodes = 262144 points, poles (+-4,0,0), "
+                        "L~U(1,6), eps=0.005, single layer (Stokeslet + doublet) to all nodes, "
+                        "self-pairs excluded, one matvec per step with a fresh seeded force",
+            "n_points": n, "pairs_per_step": pairs,
+            "path": "mixed FP32+Kahan, FP64 near pairs" if head else "FP64",
+            "near_r": NEAR_R,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 2),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": None,
+            "kernel": "sl_mixed_kernel" if head else "sl_fp64_kernel",
+            "flops_per_pair": FLOPS_PER_PAIR_SL,
+            "kernel_ms": round(k_avg * 1e3, 4),
+            "frac_of_published_fp32_packed_peak": round(achieved / PEAK_FP32_PUBLISHED, 4)
+            if head else None,
+        },
+    }
+    if True in res and False in res:
+        f64 = res[False]
+        k64 = f64["kms"] / max(f64["launches"], 1) * 1e-3
+        a64 = pairs * FLOPS_PER_PAIR_SL / k64 / 1e12
+        u32 = res[True]["first"].cpu().numpy()
+        u64 = f64["first"].cpu().numpy()
+        out["fp64"] = {
+            "value": round(args.steps * pairs / f64["sec"] / 1e9, 2), "unit": "Gpair/s",
+            "ms_per_step": round(f64["sec"] / args.steps * 1e3, 3),
+            "kernel_ms": round(k64 * 1e3, 4), "achieved_tflops": round(a64, 2),
+            "frac_of_fp64_peak": round(a64 / PEAK_FP64, 4),
+        }
+        out["mixed_over_fp64"] = round(f64["sec"] / res[True]["sec"], 3)
+        out["err_mixed_vs_fp64_relmax"] = float(f"{np.abs(u32 - u64).max() / np.abs(u64).max():.3e}")
+    if not args.no_serving:
+        try:
+            out["serving"] = serving_run(S, args.serving_requests, log)
+        except Exception as e:  # report, do not hide
+            out["serving"] = {"error": repr(e)}
+            log("serving run failed:", repr(e))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, log)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,272 @@
+/*
+ * stokes.h -- C ABI of libstokes.so: free-space Stokes kernel sums for
+ * slender-body fiber suspensions on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Nazockdast, Rahimian, Zorin, Shelley, "A fast platform for
+ * simulating flexible fiber suspensions applied to cell mechanics"
+ * (arXiv:1602.05650).  The library evaluates, directly and on the GPU, the
+ * kernel sums that the paper's solver needs at every GMRES iteration:
+ *   - the Stokeslet + source-doublet sum over fiber nodes (section 2,
+ *     eq. oseen and eq. main-sb-vel; the fiber-fiber part of the
+ *     complementary flow, eq. complementary-uf),
+ *   - the stresslet double-layer sum over surface quadrature points
+ *     (eq. stresslet, eq. double-layer, with the on-surface singularity
+ *     subtraction of section "Singular integrals over surfaces"),
+ *   - the local slender-body operator and its inverse (eq. main-sb-local),
+ *   - the fiber mobility solve by preconditioned GMRES (section "Linear
+ *     solver and preconditioner", eq. prec) and a continuous-batching
+ *     serving session that runs many such solves at once.
+ *
+ * Conventions common to every entry point
+ *   Status      every function returns int: STOKES_OK (0) or a positive
+ *               STOKES_E_* code.  stokes_status_string() names a code,
+ *               stokes_last_error() returns a thread-local message for the
+ *               last failure on the calling thread.  No C++ exception
+ *               crosses the ABI.  On a validation error nothing is launched
+ *               and the outputs are untouched.
+ *   Pointers    the *_eval, stokes_local_sbt and stokes_mobility_solve
+ *               entry points take DEVICE pointers (memory of the current HIP
+ *               device) and a HIP stream passed as void* (NULL = the legacy
+ *               default stream).  They are asynchronous on that stream unless
+ *               a diagnostics struct or STOKES_CHECK_INPUTS is passed, which
+ *               makes the call wait for the stream.  Sessions take HOST
+ *               pointers and copy them.
+ *   Layout      point sets are structure-of-arrays float64: n points are
+ *               three planes x[0..n) y[0..n) z[0..n) stored back to back
+ *               (element (c, i) at index c*n + i).  Outputs use the same
+ *               layout.
+ *   Ownership   the caller owns every input and output buffer and keeps it
+ *               alive until the stream work completes.  The library owns a
+ *               per-(device, stream) scratch workspace that grows on demand
+ *               (growing it waits for that stream) and is freed by
+ *               stokes_release_workspace().  Calls on different streams may
+ *               run concurrently; calls on one stream are ordered.
+ *   Precision   STOKES_PREC_FP64: every pair in FP64.  STOKES_PREC_MIXED:
+ *               pairs farther than the near radius in FP32 with
+ *               Kahan-compensated FP32 accumulation per target; nearer pairs
+ *               (by the same FP32 distance test, so each pair is counted
+ *               once) are recomputed in FP64 from the FP64 coordinates.
+ *   Results     for fixed inputs and flags every result is bitwise
+ *               reproducible: the source partition and the reduction order
+ *               depend only on the problem sizes.
+ */
+#ifndef STOKES_H_
+#define STOKES_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define STOKES_OK          0
+#define STOKES_E_INVAL     1  /* invalid argument (null pointer with n > 0, n < 0, mu <= 0, eps outside (0, 0.5), ...) */
+#define STOKES_E_NOMEM     2  /* device or host allocation failed, or a request can never fit a session's budget */
+#define STOKES_E_DEVICE    3  /* a HIP call failed; stokes_last_error() holds hipGetErrorString */
+#define STOKES_E_NONFINITE 4  /* STOKES_CHECK_INPUTS found a NaN or Inf in an input */
+#define STOKES_E_BUSY      5  /* session queue full */
+#define STOKES_E_CANCELED  6  /* request cancelled, or session destroyed with the request pending */
+#define STOKES_E_TIMEOUT   7  /* stokes_session_wait timed out; the request is still running */
+#define STOKES_E_NOTFOUND  8  /* unknown or already collected ticket */
+
+/* ---- flags ------------------------------------------------------------- */
+#define STOKES_PREC_FP64        0u   /* every pair in FP64 (default) */
+#define STOKES_PREC_MIXED       1u   /* FP32 far pairs + Kahan, FP64 near pairs */
+#define STOKES_EXCL_SELF_POINT  2u   /* skip source trg_self[i] for target i (self-pairs excluded) */
+#define STOKES_EXCL_SAME_FIBER  4u   /* skip every source of the target's fiber (eq. complementary-uf) */
+#define STOKES_NO_DOUBLET       8u   /* single layer: Stokeslet only (drop the eps^2/2 doublet) */
+#define STOKES_ACCUMULATE      16u   /* add into u_out instead of overwriting it */
+#define STOKES_CHECK_INPUTS    32u   /* scan device inputs first (finite values, fiber ids); synchronous */
+#define STOKES_ONSURF_RAW      64u   /* double layer: no singularity subtraction on the surface */
+
+/* Optional counters filled by the *_eval calls (passing one makes the call synchronous). */
+typedef struct stokes_diag {
+    int64_t pairs;       /* (target, source) pairs in the sum; excluded pairs are not counted */
+    int64_t near_pairs;  /* pairs recomputed in FP64 by the mixed path (0 for FP64) */
+    int64_t coincident;  /* non-excluded pairs at zero distance: skipped, never Inf */
+} stokes_diag;
+
+/*
+ * stokes_sl_eval -- single-layer (Stokeslet + doublet) sum over fiber nodes.
+ *
+ *   u_i = sum_{j not excluded}  w_j [ G(d) f_j + c_j W(d) f_j ],   d = x_i - y_j
+ *   G(d) f = (1/(8 pi mu)) (f/|d| + d (d.f)/|d|^3)           eq. oseen
+ *   W(d) f = (1/(8 pi mu)) (f/|d|^3 - 3 d (d.f)/|d|^5)        eq. main-sb-vel (doublet)
+ *   c_j    = (eps L_{m(j)})^2 / 2                             eq. main-sb-vel, eps = a/L
+ *
+ * n_src       number of sources (fiber nodes), >= 0.
+ * src_xyz     [3*n_src]  source positions (SoA).
+ * src_force   [3*n_src]  force f_j at each node (SoA).
+ * src_weight  [n_src] or NULL (all 1): quadrature weight w_j, e.g. Clenshaw-Curtis x L/2.
+ * src_fiber   [n_src] or NULL: fiber id of each node, non-decreasing, in [0, n_fib),
+ *             nodes of one fiber contiguous.  Required for STOKES_EXCL_SAME_FIBER.
+ * n_fib       number of fibers (length of fiber_len); 0 if src_fiber is NULL.
+ * fiber_len   [n_fib] or NULL (all 1): fiber lengths L_m.  With src_fiber NULL,
+ *             fiber_len[0] (if given) is used for every node.
+ * n_trg       number of targets; ignored (= n_src) when trg_xyz is NULL.
+ * trg_xyz     [3*n_trg] target positions, or NULL: the targets are the sources.
+ * trg_self    [n_trg] or NULL: source index that target i must skip under
+ *             STOKES_EXCL_SELF_POINT (-1: none).  NULL means i when the
+ *             targets are the sources, none otherwise.
+ * trg_fiber   [n_trg] or NULL: fiber id of target i for STOKES_EXCL_SAME_FIBER
+ *             (-1: none).  NULL means src_fiber[i] when the targets are the sources.
+ * mu          viscosity, > 0.     eps  slenderness a/L, in (0, 0.5).
+ * near_r      mixed path only: pairs with |d| < max(near_r, 2 eps L_{m(j)}) are
+ *             evaluated in FP64 (the spec rule is two fiber radii; a
+ *             larger radius trades speed for accuracy).  <= 0: two radii.
+ * flags       STOKES_PREC_*, at most one STOKES_EXCL_*, STOKES_NO_DOUBLET,
+ *             STOKES_ACCUMULATE, STOKES_CHECK_INPUTS.
+ * u_out       [3*n_trg] velocities (SoA, FP64), written or accumulated.
+ * stream      hipStream_t or NULL.     diag  NULL or counters (synchronous).
+ */
+int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double* src_force,
+                   const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
+                   const double* fiber_len,
+                   int64_t n_trg, const double* trg_xyz, const int64_t* trg_self,
+                   const int32_t* trg_fiber,
+                   double mu, double eps, double near_r, uint32_t flags,
+                   double* u_out, void* stream, stokes_diag* diag);
+
+/*
+ * stokes_dl_eval -- double-layer (stresslet) sum over surface quadrature points.
+ *
+ *   u_i = (3/(4 pi)) sum_{s != self(i)} w_s (d . qt_s)(d . n_s) d / |d|^5,   d = x_i - y_s
+ *
+ * eq. double-layer with the stresslet of eq. stresslet.  Sign reading: with
+ * the OUTWARD unit normal n, a constant density q gives -q inside the
+ * surface, 0 outside and -q/2 on it (principal value): the paper's stresslet
+ * with the normal pointing into the fluid enclosed by the periphery, the
+ * convention that makes eq. main-cortex-density consistent.  The viscosity
+ * factor of eq. stresslet is dropped (q is a velocity).
+ *
+ * Default (subtraction): for a target with self(i) >= 0 (a surface point),
+ * qt_s = q_s - q_{self(i)} and -q_{self(i)}/2 is added afterwards, which
+ * returns the principal value (section "Singular integrals over surfaces").
+ * STOKES_ONSURF_RAW: qt_s = q_s and the self point is only left out.
+ * Off-surface targets (self < 0) always use qt_s = q_s.
+ *
+ * n_src       number of surface points.   src_xyz [3*n_src] positions.
+ * src_normal  [3*n_src] outward unit normals.    src_weight [n_src] area weights.
+ * src_q       [3*n_src] density q.
+ * n_trg / trg_xyz   targets, or trg_xyz NULL: the targets are the surface points.
+ * trg_self    [n_trg] or NULL: surface index of target i (-1: off surface).
+ *             NULL means i when the targets are the surface points, else -1.
+ * near_r      mixed path only: pairs with |d| < near_r are evaluated in FP64.
+ *             <= 0 selects 0.02.
+ * flags       STOKES_PREC_*, STOKES_ONSURF_RAW, STOKES_ACCUMULATE, STOKES_CHECK_INPUTS.
+ */
+int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double* src_normal,
+                   const double* src_weight, const double* src_q,
+                   int64_t n_trg, const double* trg_xyz, const int64_t* trg_self,
+                   double near_r, uint32_t flags,
+                   double* u_out, void* stream, stokes_diag* diag);
+
+/*
+ * stokes_local_sbt -- local slender-body operator at every node (FP64):
+ *   inverse = 0:  out = M f = (1/(8 pi mu)) [ -ln(eps^2 e)(I + t t) + 2 (I - t t) ] f
+ *   inverse = 1:  out = M^{-1} f = 8 pi mu [ t t / (2 kappa) + (I - t t)/(kappa + 2) ] f,
+ *                 kappa = -ln(eps^2 e)  (the 3x3 node blocks of the block-Jacobi
+ *                 preconditioner, eq. prec, for the local operator)
+ * eq. main-sb-local.  n nodes; tangent [3*n] unit tangents X_s; f, out [3*n];
+ * out may alias f.  Asynchronous on stream.
+ */
+int stokes_local_sbt(int64_t n, const double* tangent, const double* f, double eps, double mu,
+                     int inverse, double* out, void* stream);
+
+/*
+ * stokes_mobility_solve -- fiber mobility solve on device pointers.
+ *
+ * Finds forces f with  M f + u_bar[f] = V  at every fiber node, where M is the
+ * local slender-body operator (eq. main-sb-local, without the finite-part
+ * term) and u_bar[f] the flow of all OTHER fibers (eq. complementary-uf):
+ * the Stokeslet + doublet sum with Clenshaw-Curtis weights x L/2 and the own
+ * fiber excluded.  Right-preconditioned GMRES (section "Linear solver and
+ * preconditioner") with the local blocks M^{-1} as preconditioner, x0 = 0,
+ * classical Gram-Schmidt applied twice, Givens rotations, in FP64; `iters`
+ * iterations unless the Krylov space is exhausted (exact breakdown).
+ *
+ * n_fib, nodes_per_fib   fibers and CGL nodes per fiber (2..64); N = n_fib*nodes_per_fib.
+ * xyz, tangent           [3*N] node positions and unit tangents, fiber-contiguous,
+ *                        node k of a fiber at alpha_k = cos(k pi/(nodes-1)).
+ * fiber_len              [n_fib] lengths.     rhs  [3*N] fiber velocities V.
+ * iters                  1..STOKES_MAX_ITERS.  flags: STOKES_PREC_* for the sums,
+ *                        STOKES_NO_DOUBLET.
+ * f_out                  [3*N] forces.   resid_out: NULL or host double, the final
+ *                        least-squares residual norm.  iters_out: NULL or host int.
+ * Synchronous (waits for the stream at the end).
+ */
+#define STOKES_MAX_ITERS 128
+int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
+                          const double* tangent, const double* fiber_len, const double* rhs,
+                          double eps, double mu, int32_t iters, uint32_t flags,
+                          double* f_out, double* resid_out, int32_t* iters_out, void* stream);
+
+/* ---- serving: continuous batching of mobility solves ------------------- */
+typedef struct stokes_session stokes_session;
+
+typedef struct stokes_session_cfg {
+    int64_t hbm_budget_bytes;  /* device memory the session may hold for requests (> 0) */
+    int32_t max_slots;         /* requests in flight at once, 1..256 */
+    int32_t max_queue;         /* submitted but not admitted requests, >= 1 */
+    uint32_t flags;            /* STOKES_PREC_* and STOKES_NO_DOUBLET for every request */
+    int32_t device;            /* HIP device ordinal */
+} stokes_session_cfg;
+
+typedef struct stokes_solve_req {   /* HOST pointers; copied by stokes_session_submit */
+    int32_t n_fib;
+    int32_t nodes_per_fib;          /* 2..64 */
+    const double* xyz;              /* [3*N] SoA node positions */
+    const double* tangent;          /* [3*N] SoA unit tangents */
+    const double* fiber_len;        /* [n_fib] */
+    const double* rhs;              /* [3*N] SoA fiber velocities V */
+    double eps;
+    double mu;
+    int32_t iters;                  /* GMRES iterations, 1..STOKES_MAX_ITERS */
+    uint64_t tag;                   /* returned in the stats */
+} stokes_solve_req;
+
+typedef struct stokes_solve_stats {
+    int64_t t_submit_ns;            /* CLOCK_MONOTONIC stamps */
+    int64_t t_admit_ns;
+    int64_t t_finish_ns;
+    int32_t iters;                  /* iterations run */
+    int32_t status;                 /* STOKES_OK or an error code */
+    double residual;                /* final least-squares residual norm */
+    uint64_t tag;
+} stokes_solve_stats;
+
+/* Create a session (a worker thread, one stream, device slot memory on demand). */
+int stokes_session_create(const stokes_session_cfg* cfg, stokes_session** out);
+/* Copy a request and queue it; returns at once.  E_NOMEM if it can never fit the
+ * budget, E_BUSY if the queue is full, E_INVAL for bad sizes. */
+int stokes_session_submit(stokes_session* s, const stokes_solve_req* req, uint64_t* ticket);
+/* Wait for a ticket (timeout_ms < 0: forever).  f_out: NULL or host [3*N]. */
+int stokes_session_wait(stokes_session* s, uint64_t ticket, double* f_out,
+                        stokes_solve_stats* st, int32_t timeout_ms);
+/* Cancel a queued or running request; its wait returns STOKES_E_CANCELED. */
+int stokes_session_cancel(stokes_session* s, uint64_t ticket);
+/* Stop the worker; pending requests finish with STOKES_E_CANCELED. */
+int stokes_session_destroy(stokes_session* s);
+
+/* ---- measurement ---------------------------------------------------------- */
+/* While enabled, every launch of a main pair-sum kernel (single or double layer,
+ * FP64 or mixed, one-shot or batched) is bracketed by two HIP events recorded on
+ * the stream it is launched on.  stokes_profile_read waits for those events,
+ * returns the summed kernel milliseconds and the number of launches since the
+ * last read, and resets both.  Host pointers; either may be NULL. */
+int stokes_profile_enable(int on);
+int stokes_profile_read(double* ms, int64_t* launches);
+
+/* ---- misc --------------------------------------------------------------- */
+const char* stokes_status_string(int status);
+const char* stokes_last_error(void);
+/* Free every scratch workspace of the calling process (waits for the device). */
+int stokes_release_workspace(void);
+/* Library version: major*10000 + minor*100 + patch. */
+int stokes_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKES_H_ */

@@ -2,16 +2,7 @@
 
 The compute path is the HIP library ``libstokes.so`` (C ABI declared in
 ``include/stokes.h``); ``paper_1602_05650_amd.stokes`` is its thin ctypes
-binding.  ``workloads`` holds the seeded synthetic geometries.
+binding (importing it loads the library and fails loudly if it is missing).
+``paper_1602_05650_amd.workloads`` holds the seeded synthetic geometries.
+Submodules are imported on demand, so the generators need no GPU library.
 """
-__all__ = ["stokes", "workloads"]
-
-
-def __getattr__(name):
-    if name == "stokes":
-        from . import stokes as _s
-        return _s
-    if name == "workloads":
-        from . import workloads as _w
-        return _w
-    raise AttributeError(name)

@@ -1,0 +1,137 @@
+// Batched FP64 GMRES for the fiber mobility problem (shared by the one-shot
+// solve and the serving session).
+//
+// Every request lives in a "slot": its geometry, Krylov basis and small
+// Hessenberg state in device memory, described by a SlotDesc in a device
+// table.  Each GMRES step is a fixed sequence of kernels; every kernel walks a
+// work list of (slot, item) pairs with a grid-stride loop, so one launch
+// serves all requests in flight and the sequence can be captured once in a
+// HIP graph (the tables live at fixed addresses; only their contents change).
+// A slot's arithmetic depends only on its own data and on a partition fixed
+// by its own sizes, never on the other slots: results are the same alone and
+// in any batch, bit for bit.
+#pragma once
+
+#include <vector>
+
+#include "stokes_internal.hpp"
+#include "sum_device.hpp"
+
+namespace stokes {
+
+constexpr int MAX_SLOTS = 256;
+constexpr int KMAX = STOKES_MAX_ITERS;
+
+struct SlotDesc {
+    int32_t N;            // nodes
+    int32_t n_fib, npf;   // fibers, nodes per fiber
+    int32_t k;            // iteration budget
+    int32_t j;            // iteration computed this step (finalize: iterations done)
+    int32_t B;            // dot-product blocks (fixed by N)
+    int32_t n_items_vec;  // ceil(3N / 256)
+    int32_t n_items_node; // ceil(N / 256)
+    int32_t n_items_sl;   // SL work items (target blocks x chunks)
+    int32_t sid;          // slot index (row of the status table)
+    double eps, mu, kappa, pref, near_r;
+    SumArgs sl;           // single-layer sum over the slot's own nodes
+    const double* xyz;    // [3][N]
+    const double* tan;    // [3][N]
+    const double* flen;   // [n_fib]
+    const double* rhs;    // [3][N]
+    int32_t* fib;         // [N]
+    double* wq;           // [N] Clenshaw-Curtis weight x L/2
+    double* V;            // [(k+1)][3N]
+    double* z;            // [3][N]  M^{-1} v_j
+    double* w;            // [3][N]
+    double* x;            // [3][N]  solution
+    double* dotp;         // [(k+1)][B] dot partials
+    double* normp;        // [B]
+    double* hA;           // [k+1]
+    double* hB;           // [k+1]
+    double* H;            // [(k+1) x k], column-major, ld = k+1
+    double* cs;           // [k]
+    double* sn;           // [k]
+    double* g;            // [k+1]
+    double* y;            // [k]
+    SrcSL64* s64;
+    SrcSL32* s32;
+    float* near_t;
+    Tile* tiles;
+    int2* excl;
+    double* partial;
+};
+
+// Work list of one kernel: slots taking part and the prefix sum of their items.
+struct WorkList {
+    int32_t n;
+    int32_t pad;
+    int32_t slot[MAX_SLOTS];
+    int64_t prefix[MAX_SLOTS + 1];
+};
+
+enum WL {
+    WL_PRE = 0,  // z = M^{-1} v_j, pack sources          items: ceil(N/256)
+    WL_SL,       // single-layer sum                       items: target blocks x chunks
+    WL_RED,      // w = M z + sum of chunk partials        items: ceil(N/256)
+    WL_DOT,      // partial dots of V[0..j] with w         items: B
+    WL_ONE,      // one block per slot (reductions, Givens) items: 1
+    WL_VEC,      // elementwise over 3N                    items: ceil(3N/256)
+    WL_COUNT
+};
+
+struct StepTables {
+    WorkList wl[WL_COUNT];
+};
+
+// Status row per slot, read back after every step: hn, beta, residual, breakdown.
+constexpr int NSTAT = 4;
+
+struct SlotPlan {
+    Partition P;
+    int32_t B;
+    size_t bytes;
+};
+SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed);
+
+class Batch {
+public:
+    Batch() = default;
+    ~Batch();
+    Batch(const Batch&) = delete;
+    Batch& operator=(const Batch&) = delete;
+    int init(hipStream_t st, bool mixed, bool doublet, bool use_graph);
+    // Lay a request out in `mem` (slot_plan bytes) and copy its inputs there
+    // (hipMemcpyDefault: host inputs must be pinned for the copy to be async).
+    int attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, double eps, double mu,
+               double near_r, const double* xyz, const double* tan, const double* flen,
+               const double* rhs);
+    // Geometry set-up, beta = |rhs| and v_0 for newly attached slots.
+    int start(const std::vector<int>& slots);
+    // One GMRES iteration for every listed slot, then read the status rows back.
+    int step(const std::vector<int>& slots);
+    // Solutions of the listed slots into their x buffers (iterations done in desc.j).
+    int finalize(const std::vector<int>& slots);
+    const double* status(int s) const { return host_stat_ + NSTAT * s; }
+    SlotDesc& desc(int s) { return host_desc_[s]; }
+    hipStream_t stream() const { return st_; }
+    bool mixed() const { return mixed_; }
+
+private:
+    int upload();
+    int launch_step(bool capture);
+    void set_list(WL w, const std::vector<int>& slots);
+    int read_status(const std::vector<int>& slots);
+
+    hipStream_t st_ = nullptr;
+    bool mixed_ = false, doublet_ = true, use_graph_ = false;
+    SlotDesc* host_desc_ = nullptr;   // pinned [MAX_SLOTS]
+    SlotDesc* dev_desc_ = nullptr;
+    StepTables* host_tab_ = nullptr;  // pinned
+    StepTables* dev_tab_ = nullptr;
+    double* host_stat_ = nullptr;     // pinned [MAX_SLOTS * NSTAT]
+    double* dev_stat_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+};
+
+}  // namespace stokes

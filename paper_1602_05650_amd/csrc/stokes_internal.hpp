@@ -1,0 +1,120 @@
+// Internal declarations shared by the translation units of libstokes.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "stokes.h"
+
+namespace stokes {
+
+// ---- error reporting ------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define STOKES_HIP(call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+    } while (0)
+
+// ---- kernel timing for measurement (stokes_profile_enable) -----------------
+// prof_begin/prof_end bracket one launch of a main pair-sum kernel with HIP
+// events on its stream when profiling is on; they do nothing otherwise.
+void prof_begin(hipStream_t st);
+void prof_end(hipStream_t st);
+
+// ---- scratch workspace, one per (device, stream) -------------------------
+// get() returns device memory of at least `bytes`, growing the buffer when
+// needed (growing waits for `stream` so the old buffer is no longer in use).
+struct Workspace {
+    void* dev = nullptr;
+    size_t bytes = 0;
+    void* host = nullptr;      // small pinned host buffer for status read-back
+};
+int workspace_get(hipStream_t stream, size_t bytes, Workspace** out);
+
+// Bump allocator over a workspace buffer (256-byte aligned slices).
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+    template <class T>
+    T* take(size_t n) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += n * sizeof(T);
+        return p;
+    }
+    static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+};
+
+// ---- geometry of the kernel sums -----------------------------------------
+constexpr int TILE = 32;      // sources per tile (one 32-node fiber in the benchmark geometries)
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;    // 4 waves per block
+
+// A tile of TILE consecutive sources with its bounding sphere.
+struct __align__(16) Tile {
+    double ox, oy, oz;   // FP64 origin: centre of the bounding box
+    double reach2;       // FP64 path: a target closer than sqrt(reach2) may coincide with a source
+    float reach2_f;      // mixed path: a target closer than this may have a near pair
+    int32_t j0, j1;      // sources [j0, j1)
+    int32_t pad;
+};
+
+// Single-layer source, premultiplied: s = w f / (8 pi mu), c = (eps L)^2/2, c3 = -3 c.
+struct __align__(64) SrcSL64 { double x, y, z, c, sx, sy, sz, c3; };
+// Same in FP32 with tile-local coordinates (position minus the tile origin).
+struct __align__(32) SrcSL32 { float x, y, z, c, sx, sy, sz, c3; };
+// Double-layer source: n' = (3/(4 pi)) w n.
+struct __align__(32) SrcDL64 { double x, y, z, qx, qy, qz, nx, ny, nz, pad0, pad1, pad2; };
+struct __align__(16) SrcDL32 { float x, y, z, qx, qy, qz, nx, ny, nz, pad0, pad1, pad2; };
+
+// Work partition of one sum: targets in waves of 64*R, sources in chunks of
+// whole tiles.  Depends only on the problem sizes (bitwise reproducibility).
+struct Partition {
+    int R;
+    int64_t n_t;
+    int32_t n_tiles;
+    int32_t tiles_per_chunk;
+    int32_t n_chunks;
+    int32_t n_tblocks;
+};
+Partition make_partition(int64_t n_t, int64_t n_s, int R);
+
+// ---- launch entry points used by the solver and the session ---------------
+struct SLProblem {
+    int64_t n_s;
+    const double* sxyz;
+    const double* force;
+    const double* weight;      // may be null
+    const int32_t* sfib;       // may be null
+    int32_t n_fib;
+    const double* flen;        // may be null
+    int64_t n_t;
+    const double* txyz;        // never null here (resolved by the caller)
+    int64_t t_stride;
+    const int2* excl;          // may be null: no exclusion
+    double mu, eps, near_r;
+    bool mixed, doublet, accumulate;
+    double* u;                 // [3][n_t], stride n_t
+};
+
+// Sizes of the scratch needed by sl_launch for a problem.
+size_t sl_scratch_bytes(int64_t n_s, int64_t n_t, bool mixed);
+// Enqueue the single-layer sum; scratch must hold sl_scratch_bytes().
+// counters: null or 3 u64 on device (near pairs, coincident, excluded), accumulated.
+int sl_launch(const SLProblem& p, void* scratch, unsigned long long* counters, hipStream_t st);
+
+// Fiber start/end index per fiber id, then per-target exclusion ranges.
+int fiber_bounds_launch(int64_t n_s, const int32_t* sfib, int32_t n_fib, int2* bounds,
+                        hipStream_t st);
+int excl_same_fiber_launch(int64_t n_t, const int32_t* tfib, const int2* bounds, int32_t n_fib,
+                           int2* excl, hipStream_t st);
+
+}  // namespace stokes

@@ -1,0 +1,707 @@
+// Fiber mobility solve: right-preconditioned GMRES in FP64 on the device.
+//
+//   A f = M f + u_bar[f] = V           (eq. main-sb-local without the finite-part
+//                                       term; u_bar from all other fibers,
+//                                       eq. complementary-uf)
+//   P = M (the local 3x3 node blocks of the block-Jacobi preconditioner, eq. prec)
+//   GMRES (Saad) on A P^{-1} y = V from y0 = 0: Arnoldi with classical
+//   Gram-Schmidt applied twice, Givens rotations, x = P^{-1} V_m y.
+//
+// Every kernel here works on a batch of requests (see solver_batch.hpp).
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "solver_batch.hpp"
+
+namespace stokes {
+
+constexpr int G_ELEM = 512;   // grid of the elementwise kernels in graph mode
+constexpr int G_SL = 2048;    // grid of the single-layer kernel in graph mode
+constexpr int G_ONE = MAX_SLOTS;
+
+__device__ __forceinline__ int find_slot(const WorkList& wl, int64_t item) {
+    int lo = 0, hi = wl.n - 1;
+    while (lo < hi) {   // largest s with prefix[s] <= item
+        const int mid = (lo + hi + 1) >> 1;
+        if (wl.prefix[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Deterministic block reduction (fixed tree) of one value per thread; result in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) lds[t] += lds[t + s];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// Clenshaw-Curtis weight of node kk on the p+1 CGL nodes cos(k pi/p) (Waldvogel's
+// closed form): w_k = (c_k/p) (1 - sum_{j=1}^{p/2} b_j cos(2 j k pi/p) / (4 j^2 - 1)).
+__device__ double cc_weight(int kk, int p) {
+    if (p == 1) return 1.0;
+    double s = 0.0;
+    for (int j = 1; j <= p / 2; ++j) {
+        const double b = (2 * j == p) ? 1.0 : 2.0;
+        s += b * cos(2.0 * j * kk * 3.14159265358979323846 / p) / (4.0 * j * j - 1.0);
+    }
+    const double c = (kk == 0 || kk == p) ? 1.0 : 2.0;
+    return c / p * (1.0 - s);
+}
+
+// out = a f + b t (t.f): M (inverse = 0) or M^{-1} (inverse = 1), eq. main-sb-local.
+__device__ __forceinline__ void apply_local(double kap, double mu, bool inverse, double tx,
+                                            double ty, double tz, double& fx, double& fy,
+                                            double& fz) {
+    const double pi8mu = 8.0 * 3.14159265358979323846 * mu;
+    double a, b;
+    if (!inverse) {
+        a = (kap + 2.0) / pi8mu;
+        b = (kap - 2.0) / pi8mu;
+    } else {
+        a = pi8mu / (kap + 2.0);
+        b = pi8mu / (2.0 * kap) - a;
+    }
+    const double tf = tx * fx + ty * fy + tz * fz;
+    fx = a * fx + b * tf * tx;
+    fy = a * fy + b * tf * ty;
+    fz = a * fz + b * tf * tz;
+}
+
+// Partial dot products of m vectors A[i] (stride) with w over block b's range.
+__device__ void dot_partials(const double* A, int64_t stride, int m, const double* w, int64_t n,
+                             int B, int b, double* out, double* lds) {
+    const int64_t L = (n + B - 1) / B;
+    const int64_t e0 = (int64_t)b * L;
+    const int64_t e1 = min(n, e0 + L);
+    for (int i = 0; i < m; ++i) {
+        const double* a = A + (int64_t)i * stride;
+        double s = 0.0;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) s = fma(a[e], w[e], s);
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) out[(int64_t)i * B + b] = s;
+    }
+}
+
+// ---- set-up kernels (eager, at admission) ------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_geom(const SlotDesc* D, const StepTables* T) {
+    const WorkList& wl = T->wl[WL_PRE];
+    const int64_t total = wl.prefix[wl.n];
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (i < d.N) {
+            const int f = (int)(i / d.npf);
+            const int kk = (int)(i % d.npf);
+            d.fib[i] = f;
+            d.wq[i] = cc_weight(kk, d.npf - 1) * 0.5 * d.flen[f];
+            d.excl[i] = make_int2(f * d.npf, f * d.npf + d.npf);
+        }
+    }
+}
+
+// Bounding spheres of the source tiles (after k_geom: reads the fiber ids).
+__global__ __launch_bounds__(BLOCK) void k_tiles(const SlotDesc* D, const StepTables* T) {
+    const WorkList& wl = T->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t t = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (t < d.sl.n_tiles)
+            tile_prep_one((int)t, d.N, d.xyz, d.near_r, d.sl.s32 ? 2.0 * d.eps : 0.0, d.fib,
+                          d.n_fib, d.flen, d.tiles);
+    }
+}
+
+// beta = |rhs| partials (WL_DOT), then beta and v_0 (WL_ONE, WL_VEC).
+__global__ __launch_bounds__(BLOCK) void k_init_norm(const SlotDesc* D, const StepTables* T) {
+    __shared__ double lds[BLOCK];
+    const WorkList& wl = T->wl[WL_DOT];
+    const int64_t total = wl.prefix[wl.n];
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        dot_partials(d.rhs, 0, 1, d.rhs, 3 * (int64_t)d.N, d.B, (int)(it - wl.prefix[si]), d.normp,
+                     lds);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_init_beta(const SlotDesc* D, const StepTables* T,
+                                                     double* stat) {
+    const WorkList& wl = T->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int b = 0; b < d.B; ++b) s += d.normp[b];
+            const double beta = sqrt(s);
+            d.g[0] = beta;
+            for (int i = 1; i <= d.k; ++i) d.g[i] = 0.0;
+            double* st = stat + NSTAT * d.sid;
+            st[0] = 0.0;
+            st[1] = beta;
+            st[2] = beta;
+            st[3] = beta == 0.0 ? 1.0 : 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_init_v0(const SlotDesc* D, const StepTables* T) {
+    const WorkList& wl = T->wl[WL_VEC];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t e = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (e < 3 * (int64_t)d.N) {
+            const double beta = d.g[0];
+            d.V[e] = beta > 0.0 ? d.rhs[e] / beta : 0.0;
+        }
+    }
+}
+
+// ---- step kernels ------------------------------------------------------------------
+// z = M^{-1} v_j and the packed single-layer sources s = pref * wq * z.
+__global__ __launch_bounds__(BLOCK) void k_pre(const SlotDesc* D, const StepTables* T, int doublet) {
+    const WorkList& wl = T->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (i >= d.N) continue;
+        const int64_t N = d.N;
+        const double* v = d.V + (int64_t)d.j * 3 * N;
+        double fx = v[i], fy = v[N + i], fz = v[2 * N + i];
+        apply_local(d.kappa, d.mu, true, d.tan[i], d.tan[N + i], d.tan[2 * N + i], fx, fy, fz);
+        d.z[i] = fx;
+        d.z[N + i] = fy;
+        d.z[2 * N + i] = fz;
+        sl_src_prep_one(i, N, d.xyz, d.z, d.wq, d.fib, d.n_fib, d.flen, d.pref, d.eps, doublet,
+                        d.near_r, d.tiles, d.s64, d.s32, d.near_t);
+    }
+}
+
+template <bool MIXED, bool DOUBLET>
+__global__ __launch_bounds__(BLOCK) void k_sl(const SlotDesc* D, const StepTables* T) {
+    const WorkList& wl = T->wl[WL_SL];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int local = (int)(it - wl.prefix[si]);
+        const int tb = local % d.sl.n_tblocks;
+        const int chunk = local / d.sl.n_tblocks;
+        if (MIXED)
+            sl_mixed_wave<2, DOUBLET>(d.sl, tb, chunk);
+        else
+            sl_fp64_wave<2, DOUBLET>(d.sl, tb, chunk);
+    }
+}
+
+// w = M z + (sum of the chunk partials, in chunk order).
+__global__ __launch_bounds__(BLOCK) void k_red(const SlotDesc* D, const StepTables* T) {
+    const WorkList& wl = T->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (i >= d.N) continue;
+        const int64_t N = d.N;
+        double u[3] = {0.0, 0.0, 0.0};
+        const int nch = d.n_items_sl / d.sl.n_tblocks;
+        for (int k = 0; k < nch; ++k) {
+            const double* p = d.partial + (int64_t)k * 3 * N;
+            u[0] += p[i];
+            u[1] += p[N + i];
+            u[2] += p[2 * N + i];
+        }
+        double mx = d.z[i], my = d.z[N + i], mz = d.z[2 * N + i];
+        apply_local(d.kappa, d.mu, false, d.tan[i], d.tan[N + i], d.tan[2 * N + i], mx, my, mz);
+        d.w[i] = mx + u[0];
+        d.w[N + i] = my + u[1];
+        d.w[2 * N + i] = mz + u[2];
+    }
+}
+
+// which = 0: partials of V[0..j].w ; which = 1: same (second Gram-Schmidt pass);
+// which = 2: partials of w.w (norm).
+__global__ __launch_bounds__(BLOCK) void k_dot(const SlotDesc* D, const StepTables* T, int which) {
+    __shared__ double lds[BLOCK];
+    const WorkList& wl = T->wl[WL_DOT];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int b = (int)(it - wl.prefix[si]);
+        const int64_t n = 3 * (int64_t)d.N;
+        if (which == 2)
+            dot_partials(d.w, 0, 1, d.w, n, d.B, b, d.normp, lds);
+        else
+            dot_partials(d.V, n, d.j + 1, d.w, n, d.B, b, d.dotp, lds);
+    }
+}
+
+// h = (sum over blocks of the partials), in block order.  which: 0 -> hA, 1 -> hB.
+__global__ __launch_bounds__(BLOCK) void k_dred(const SlotDesc* D, const StepTables* T, int which) {
+    const WorkList& wl = T->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+        double* h = which ? d.hB : d.hA;
+        for (int i = threadIdx.x; i <= d.j; i += BLOCK) {
+            double s = 0.0;
+            for (int b = 0; b < d.B; ++b) s += d.dotp[(int64_t)i * d.B + b];
+            h[i] = s;
+        }
+    }
+}
+
+// w -= sum_i V[i] h[i]  (i ascending), h = hA or hB.
+__global__ __launch_bounds__(BLOCK) void k_axpy(const SlotDesc* D, const StepTables* T, int which) {
+    const WorkList& wl = T->wl[WL_VEC];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t n = 3 * (int64_t)d.N;
+        const int64_t e = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (e >= n) continue;
+        const double* h = which ? d.hB : d.hA;
+        double acc = 0.0;
+        for (int i = 0; i <= d.j; ++i) acc = fma(d.V[(int64_t)i * n + e], h[i], acc);
+        d.w[e] = d.w[e] - acc;
+    }
+}
+
+// Hessenberg column j, previous rotations, new rotation, residual |g_{j+1}|.
+__global__ __launch_bounds__(BLOCK) void k_givens(const SlotDesc* D, const StepTables* T,
+                                                  double* stat) {
+    const WorkList& wl = T->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+        if (threadIdx.x != 0) continue;
+        const int j = d.j;
+        double s = 0.0;
+        for (int b = 0; b < d.B; ++b) s += d.normp[b];
+        const double hn = sqrt(s);
+        double* col = d.H + (int64_t)j * (d.k + 1);
+        for (int i = 0; i <= j; ++i) col[i] = d.hA[i] + d.hB[i];
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            const double a = col[i], c = col[i + 1];
+            col[i] = d.cs[i] * a + d.sn[i] * c;
+            col[i + 1] = -d.sn[i] * a + d.cs[i] * c;
+        }
+        const double den = hypot(col[j], col[j + 1]);
+        d.cs[j] = col[j] / den;
+        d.sn[j] = col[j + 1] / den;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        d.g[j + 1] = -d.sn[j] * d.g[j];
+        d.g[j] = d.cs[j] * d.g[j];
+        double* st = stat + NSTAT * d.sid;
+        st[0] = hn;
+        st[2] = fabs(d.g[j + 1]);
+        st[3] = hn == 0.0 ? 1.0 : 0.0;
+    }
+}
+
+// v_{j+1} = w / h_{j+1,j}
+__global__ __launch_bounds__(BLOCK) void k_scale(const SlotDesc* D, const StepTables* T,
+                                                 const double* stat) {
+    const WorkList& wl = T->wl[WL_VEC];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t n = 3 * (int64_t)d.N;
+        const int64_t e = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (e >= n) continue;
+        const double hn = stat[NSTAT * d.sid];
+        d.V[(int64_t)(d.j + 1) * n + e] = hn > 0.0 ? d.w[e] / hn : 0.0;
+    }
+}
+
+// ---- finalisation ----------------------------------------------------------------
+// Back substitution R y = g over the m = d.j iterations done.
+__global__ __launch_bounds__(BLOCK) void k_backsub(const SlotDesc* D, const StepTables* T) {
+    const WorkList& wl = T->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+        if (threadIdx.x != 0) continue;
+        const int m = d.j;
+        const int ld = d.k + 1;
+        for (int i = m - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (int l = i + 1; l < m; ++l) s += d.H[(int64_t)l * ld + i] * d.y[l];
+            d.y[i] = (d.g[i] - s) / d.H[(int64_t)i * ld + i];
+        }
+    }
+}
+
+// x = M^{-1} (V_m y) at every node.
+__global__ __launch_bounds__(BLOCK) void k_solution(const SlotDesc* D, const StepTables* T) {
+    const WorkList& wl = T->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const SlotDesc& d = D[wl.slot[si]];
+        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        if (i >= d.N) continue;
+        const int64_t N = d.N, n = 3 * N;
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < d.j; ++l) {
+            const double yl = d.y[l];
+            const double* Vl = d.V + (int64_t)l * n;
+            v[0] = fma(Vl[i], yl, v[0]);
+            v[1] = fma(Vl[N + i], yl, v[1]);
+            v[2] = fma(Vl[2 * N + i], yl, v[2]);
+        }
+        apply_local(d.kappa, d.mu, true, d.tan[i], d.tan[N + i], d.tan[2 * N + i], v[0], v[1], v[2]);
+        d.x[i] = v[0];
+        d.x[N + i] = v[1];
+        d.x[2 * N + i] = v[2];
+    }
+}
+
+// ---- host side ---------------------------------------------------------------------
+
+static int32_t dot_blocks(int64_t n) {
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (n + 4095) / 4096));
+}
+
+SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed) {
+    SlotPlan sp{};
+    const int64_t N = (int64_t)n_fib * npf;
+    sp.P = make_partition(N, N, 2);
+    sp.B = dot_blocks(3 * N);
+    const int64_t n = 3 * N;
+    size_t b = 0;
+    auto add = [&](size_t bytes) { b += Carve::round(bytes) + 256; };
+    add(n * 8);               // xyz
+    add(n * 8);               // tan
+    add(n_fib * 8);           // flen
+    add(n * 8);               // rhs
+    add(N * 4);               // fib
+    add(N * 8);               // wq
+    add((size_t)(k + 1) * n * 8);  // V
+    add(n * 8);               // z
+    add(n * 8);               // w
+    add(n * 8);               // x
+    add((size_t)(k + 1) * sp.B * 8);  // dotp
+    add(sp.B * 8);            // normp
+    add((k + 1) * 8);         // hA
+    add((k + 1) * 8);         // hB
+    add((size_t)(k + 1) * k * 8);  // H
+    add(k * 8);               // cs
+    add(k * 8);               // sn
+    add((k + 1) * 8);         // g
+    add(k * 8);               // y
+    add(sp.P.n_tiles * sizeof(Tile));
+    add(N * sizeof(SrcSL64));
+    add(mixed ? N * sizeof(SrcSL32) : 0);
+    add(mixed ? N * 4 : 0);   // near_t
+    add(N * sizeof(int2));    // excl
+    add((size_t)sp.P.n_chunks * n * 8);  // partial
+    sp.bytes = b + 4096;
+    return sp;
+}
+
+Batch::~Batch() {
+    if (exec_) (void)hipGraphExecDestroy(exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    if (dev_desc_) (void)hipFree(dev_desc_);
+    if (dev_tab_) (void)hipFree(dev_tab_);
+    if (dev_stat_) (void)hipFree(dev_stat_);
+    if (host_desc_) (void)hipHostFree(host_desc_);
+    if (host_tab_) (void)hipHostFree(host_tab_);
+    if (host_stat_) (void)hipHostFree(host_stat_);
+}
+
+int Batch::init(hipStream_t st, bool mixed, bool doublet, bool use_graph) {
+    st_ = st;
+    mixed_ = mixed;
+    doublet_ = doublet;
+    use_graph_ = use_graph;
+    STOKES_HIP(hipHostMalloc((void**)&host_desc_, sizeof(SlotDesc) * MAX_SLOTS, hipHostMallocDefault));
+    STOKES_HIP(hipHostMalloc((void**)&host_tab_, sizeof(StepTables), hipHostMallocDefault));
+    STOKES_HIP(hipHostMalloc((void**)&host_stat_, sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault));
+    STOKES_HIP(hipMalloc((void**)&dev_desc_, sizeof(SlotDesc) * MAX_SLOTS));
+    STOKES_HIP(hipMalloc((void**)&dev_tab_, sizeof(StepTables)));
+    STOKES_HIP(hipMalloc((void**)&dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS));
+    memset(host_desc_, 0, sizeof(SlotDesc) * MAX_SLOTS);
+    memset(host_tab_, 0, sizeof(StepTables));
+    memset(host_stat_, 0, sizeof(double) * NSTAT * MAX_SLOTS);
+    return STOKES_OK;
+}
+
+int Batch::attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, double eps, double mu,
+                  double near_r, const double* xyz, const double* tan, const double* flen,
+                  const double* rhs) {
+    const SlotPlan sp = slot_plan(n_fib, npf, k, mixed_);
+    const int64_t N = (int64_t)n_fib * npf, n = 3 * N;
+    Carve c(mem);
+    SlotDesc d{};
+    d.N = (int32_t)N;
+    d.n_fib = n_fib;
+    d.npf = npf;
+    d.k = k;
+    d.j = 0;
+    d.B = sp.B;
+    d.n_items_vec = (int32_t)((n + BLOCK - 1) / BLOCK);
+    d.n_items_node = (int32_t)((N + BLOCK - 1) / BLOCK);
+    d.n_items_sl = sp.P.n_tblocks * sp.P.n_chunks;
+    d.sid = s;
+    d.eps = eps;
+    d.mu = mu;
+    d.kappa = -log(eps * eps * M_E);
+    d.pref = 1.0 / (8.0 * 3.14159265358979323846 * mu);
+    d.near_r = mixed_ ? std::max(near_r, 0.0) : 0.0;
+    double* xyz_d = c.take<double>(n);
+    double* tan_d = c.take<double>(n);
+    double* flen_d = c.take<double>(n_fib);
+    double* rhs_d = c.take<double>(n);
+    d.xyz = xyz_d;
+    d.tan = tan_d;
+    d.flen = flen_d;
+    d.rhs = rhs_d;
+    d.fib = c.take<int32_t>(N);
+    d.wq = c.take<double>(N);
+    d.V = c.take<double>((size_t)(k + 1) * n);
+    d.z = c.take<double>(n);
+    d.w = c.take<double>(n);
+    d.x = c.take<double>(n);
+    d.dotp = c.take<double>((size_t)(k + 1) * sp.B);
+    d.normp = c.take<double>(sp.B);
+    d.hA = c.take<double>(k + 1);
+    d.hB = c.take<double>(k + 1);
+    d.H = c.take<double>((size_t)(k + 1) * k);
+    d.cs = c.take<double>(k);
+    d.sn = c.take<double>(k);
+    d.g = c.take<double>(k + 1);
+    d.y = c.take<double>(k);
+    d.tiles = c.take<Tile>(sp.P.n_tiles);
+    d.s64 = c.take<SrcSL64>(N);
+    d.s32 = c.take<SrcSL32>(mixed_ ? N : 0);
+    d.near_t = c.take<float>(mixed_ ? N : 0);
+    d.excl = c.take<int2>(N);
+    d.partial = c.take<double>((size_t)sp.P.n_chunks * n);
+    if (c.off > sp.bytes) return fail(STOKES_E_INVAL, "slot layout exceeds its plan");
+    if (!mixed_) {
+        d.s32 = nullptr;
+        d.near_t = nullptr;
+    }
+    SumArgs& a = d.sl;
+    a.tx = xyz_d;
+    a.t_stride = N;
+    a.n_t = N;
+    a.excl = d.excl;
+    a.tiles = d.tiles;
+    a.n_tiles = sp.P.n_tiles;
+    a.tiles_per_chunk = sp.P.tiles_per_chunk;
+    a.n_tblocks = sp.P.n_tblocks;
+    a.s64 = d.s64;
+    a.s32 = d.s32;
+    a.near_t = d.near_t;
+    a.n_s = N;
+    a.partial = d.partial;
+    a.counters = nullptr;
+    STOKES_HIP(hipMemcpyAsync(xyz_d, xyz, n * 8, hipMemcpyDefault, st_));
+    STOKES_HIP(hipMemcpyAsync(tan_d, tan, n * 8, hipMemcpyDefault, st_));
+    STOKES_HIP(hipMemcpyAsync(flen_d, flen, (size_t)n_fib * 8, hipMemcpyDefault, st_));
+    STOKES_HIP(hipMemcpyAsync(rhs_d, rhs, n * 8, hipMemcpyDefault, st_));
+    host_desc_[s] = d;
+    return STOKES_OK;
+}
+
+void Batch::set_list(WL w, const std::vector<int>& slots) {
+    WorkList& L = host_tab_->wl[w];
+    L.n = (int32_t)slots.size();
+    L.prefix[0] = 0;
+    for (size_t q = 0; q < slots.size(); ++q) {
+        const SlotDesc& d = host_desc_[slots[q]];
+        int64_t items = 0;
+        switch (w) {
+            case WL_PRE: items = d.n_items_node; break;   // >= tiles / BLOCK as well
+            case WL_SL: items = d.n_items_sl; break;
+            case WL_RED: items = d.n_items_node; break;
+            case WL_DOT: items = d.B; break;
+            case WL_ONE: items = 1; break;
+            case WL_VEC: items = d.n_items_vec; break;
+            default: break;
+        }
+        L.slot[q] = slots[q];
+        L.prefix[q + 1] = L.prefix[q] + items;
+    }
+}
+
+int Batch::upload() {
+    STOKES_HIP(hipMemcpyAsync(dev_desc_, host_desc_, sizeof(SlotDesc) * MAX_SLOTS,
+                              hipMemcpyHostToDevice, st_));
+    STOKES_HIP(hipMemcpyAsync(dev_tab_, host_tab_, sizeof(StepTables), hipMemcpyHostToDevice, st_));
+    return STOKES_OK;
+}
+
+static unsigned grid_for(const WorkList& L, int cap) {
+    const int64_t t = L.prefix[L.n];
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(t, cap));
+}
+
+int Batch::read_status(const std::vector<int>& slots) {
+    (void)slots;
+    STOKES_HIP(hipMemcpyAsync(host_stat_, dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS,
+                              hipMemcpyDeviceToHost, st_));
+    STOKES_HIP(hipStreamSynchronize(st_));
+    return STOKES_OK;
+}
+
+int Batch::start(const std::vector<int>& slots) {
+    if (slots.empty()) return STOKES_OK;
+    set_list(WL_PRE, slots);
+    set_list(WL_DOT, slots);
+    set_list(WL_ONE, slots);
+    set_list(WL_VEC, slots);
+    int rc = upload();
+    if (rc) return rc;
+    const StepTables& T = *host_tab_;
+    hipLaunchKernelGGL(k_geom, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_tiles, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_init_norm, dim3(grid_for(T.wl[WL_DOT], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_init_beta, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_, dev_stat_);
+    hipLaunchKernelGGL(k_init_v0, dim3(grid_for(T.wl[WL_VEC], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    STOKES_HIP(hipGetLastError());
+    return read_status(slots);
+}
+
+int Batch::launch_step(bool graph_sizes) {
+    const StepTables& T = *host_tab_;
+    auto g = [&](WL w, int cap) { return graph_sizes ? (unsigned)cap : grid_for(T.wl[w], cap); };
+    const dim3 b(BLOCK);
+    hipLaunchKernelGGL(k_pre, dim3(g(WL_PRE, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, doublet_ ? 1 : 0);
+    if (!graph_sizes) prof_begin(st_);   // (events are not recorded into a captured graph)
+    if (mixed_) {
+        if (doublet_) hipLaunchKernelGGL((k_sl<true, true>), dim3(g(WL_SL, G_SL)), b, 0, st_, dev_desc_, dev_tab_);
+        else hipLaunchKernelGGL((k_sl<true, false>), dim3(g(WL_SL, G_SL)), b, 0, st_, dev_desc_, dev_tab_);
+    } else {
+        if (doublet_) hipLaunchKernelGGL((k_sl<false, true>), dim3(g(WL_SL, G_SL)), b, 0, st_, dev_desc_, dev_tab_);
+        else hipLaunchKernelGGL((k_sl<false, false>), dim3(g(WL_SL, G_SL)), b, 0, st_, dev_desc_, dev_tab_);
+    }
+    if (!graph_sizes) prof_end(st_);
+    hipLaunchKernelGGL(k_red, dim3(g(WL_PRE, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_dot, dim3(g(WL_DOT, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, pass);
+        hipLaunchKernelGGL(k_dred, dim3(g(WL_ONE, G_ONE)), b, 0, st_, dev_desc_, dev_tab_, pass);
+        hipLaunchKernelGGL(k_axpy, dim3(g(WL_VEC, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, pass);
+    }
+    hipLaunchKernelGGL(k_dot, dim3(g(WL_DOT, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, 2);
+    hipLaunchKernelGGL(k_givens, dim3(g(WL_ONE, G_ONE)), b, 0, st_, dev_desc_, dev_tab_, dev_stat_);
+    hipLaunchKernelGGL(k_scale, dim3(g(WL_VEC, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, (const double*)dev_stat_);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+int Batch::step(const std::vector<int>& slots) {
+    if (slots.empty()) return STOKES_OK;
+    set_list(WL_PRE, slots);
+    set_list(WL_SL, slots);
+    set_list(WL_RED, slots);
+    set_list(WL_DOT, slots);
+    set_list(WL_ONE, slots);
+    set_list(WL_VEC, slots);
+    int rc = upload();
+    if (rc) return rc;
+    if (use_graph_) {
+        if (!exec_) {
+            STOKES_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+            rc = launch_step(true);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(st_, &gr);
+            if (rc) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            graph_ = gr;
+            STOKES_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        }
+        STOKES_HIP(hipGraphLaunch(exec_, st_));
+    } else {
+        if ((rc = launch_step(false))) return rc;
+    }
+    return read_status(slots);
+}
+
+int Batch::finalize(const std::vector<int>& slots) {
+    if (slots.empty()) return STOKES_OK;
+    set_list(WL_PRE, slots);
+    set_list(WL_ONE, slots);
+    int rc = upload();
+    if (rc) return rc;
+    const StepTables& T = *host_tab_;
+    hipLaunchKernelGGL(k_backsub, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_solution, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+}  // namespace stokes
+
+using namespace stokes;
+
+extern "C" int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
+                                     const double* tangent, const double* fiber_len,
+                                     const double* rhs, double eps, double mu, int32_t iters,
+                                     uint32_t flags, double* f_out, double* resid_out,
+                                     int32_t* iters_out, void* stream) {
+    if (flags & ~(STOKES_PREC_MIXED | STOKES_NO_DOUBLET))
+        return fail(STOKES_E_INVAL, "stokes_mobility_solve: unknown flag bits");
+    if (n_fib < 0 || nodes_per_fib < 2 || nodes_per_fib > 64)
+        return fail(STOKES_E_INVAL, "stokes_mobility_solve: need n_fib >= 0 and 2 <= nodes_per_fib <= 64");
+    if (iters < 1 || iters > STOKES_MAX_ITERS)
+        return fail(STOKES_E_INVAL, "stokes_mobility_solve: iters out of range");
+    if (!(mu > 0.0)) return fail(STOKES_E_INVAL, "stokes_mobility_solve: mu must be > 0");
+    if (!(eps > 0.0 && eps < 0.5)) return fail(STOKES_E_INVAL, "stokes_mobility_solve: eps must be in (0, 0.5)");
+    const int64_t N = (int64_t)n_fib * nodes_per_fib;
+    if (N >= (int64_t)1 << 30) return fail(STOKES_E_INVAL, "stokes_mobility_solve: too many nodes");
+    if (N > 0 && (!xyz || !tangent || !fiber_len || !rhs || !f_out))
+        return fail(STOKES_E_INVAL, "stokes_mobility_solve: null pointer");
+    if (N == 0) {
+        if (resid_out) *resid_out = 0.0;
+        if (iters_out) *iters_out = 0;
+        return STOKES_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool mixed = flags & STOKES_PREC_MIXED;
+    const SlotPlan sp = slot_plan(n_fib, nodes_per_fib, iters, mixed);
+    Workspace* ws = nullptr;
+    int rc = workspace_get(st, sp.bytes, &ws);
+    if (rc) return rc;
+    Batch b;
+    if ((rc = b.init(st, mixed, !(flags & STOKES_NO_DOUBLET), false))) return rc;
+    if ((rc = b.attach(0, ws->dev, n_fib, nodes_per_fib, iters, eps, mu, 0.0, xyz, tangent,
+                       fiber_len, rhs)))
+        return rc;
+    std::vector<int> one{0};
+    if ((rc = b.start(one))) return rc;
+    int done = 0;
+    double resid = b.status(0)[2];
+    if (b.status(0)[3] == 0.0) {
+        for (int j = 0; j < iters; ++j) {
+            b.desc(0).j = j;
+            if ((rc = b.step(one))) return rc;
+            done = j + 1;
+            resid = b.status(0)[2];
+            if (b.status(0)[3] != 0.0) break;   // exact breakdown
+        }
+    }
+    b.desc(0).j = done;
+    if ((rc = b.finalize(one))) return rc;
+    STOKES_HIP(hipMemcpyAsync(f_out, b.desc(0).x, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    STOKES_HIP(hipStreamSynchronize(st));
+    if (resid_out) *resid_out = resid;
+    if (iters_out) *iters_out = done;
+    return STOKES_OK;
+}

@@ -1,0 +1,607 @@
+// Kernel sums of the free-space Stokes fundamental solutions on gfx950.
+//
+// Single layer (Stokeslet + doublet, eq. oseen and eq. main-sb-vel) and
+// double layer (stresslet, eq. stresslet / eq. double-layer, with the
+// on-surface singularity subtraction) as direct O(N M) sums.
+//
+// Execution scheme (all kernels are VALU-bound; there is no dense
+// contraction here, so no MFMA):
+//   * targets: each lane owns R targets (register blocking), a wave 64 R
+//     consecutive targets, a block 4 waves;
+//   * sources: grouped in tiles of TILE = 32 consecutive points (one fiber of
+//     32 nodes, or a compact 4 x 8 patch of the sphere grid) and in chunks of
+//     whole tiles; the grid is (target blocks) x (source chunks), and each
+//     chunk writes an FP64 partial that a second kernel adds in chunk order,
+//     so results are bitwise reproducible;
+//   * every lane of a wave walks the same source, so sources are read with
+//     wave-uniform addresses: the compiler turns them into scalar loads and
+//     the pair arithmetic takes them straight from SGPRs (the broadcast costs
+//     no vector instruction and no LDS traffic);
+//   * per (wave, tile) a bounding-sphere test decides whether any lane may
+//     meet an excluded, coincident or (mixed path) near pair in the tile; if
+//     none can, the tile runs a branch-free loop, otherwise a checked loop.
+//
+// Mixed path: coordinates are rounded to FP32 relative to the tile origin
+// (target: fl32(x - o) computed in FP64 once per tile; source: fl32(y - o)),
+// so the FP32 difference d keeps relative accuracy ~ 2^-24 (1 + tile
+// radius / |d|).  Pairs with FP32 |d|^2 below the source's near threshold are
+// masked out of the FP32 loop and recomputed in FP64 from the FP64 inputs;
+// the same FP32 test decides both, so every pair is counted exactly once.
+// The FP32 tile partial is added to a Kahan-compensated FP32 pair (S, C) per
+// target component; chunk partials are FP64.
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "stokes_internal.hpp"
+#include "sum_device.hpp"
+
+namespace stokes {
+
+// ---- preparation kernels -------------------------------------------------------
+
+// Bounding sphere of each tile.  near_r_tile: extra reach for the mixed path
+// (largest near radius of the tile's sources); per-source near radius is
+// max(near_r, near_fac * L_fiber) when flen/sfib are given.
+__global__ void tile_prep_kernel(int64_t n_s, const double* __restrict__ sx, int32_t n_tiles,
+                                 double near_r, double near_fac, const int32_t* __restrict__ sfib,
+                                 int32_t n_fib, const double* __restrict__ flen, Tile* tiles) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_tiles) tile_prep_one(t, n_s, sx, near_r, near_fac, sfib, n_fib, flen, tiles);
+}
+
+__global__ void sl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
+                                   const double* __restrict__ f, const double* __restrict__ w,
+                                   const int32_t* __restrict__ sfib, int32_t n_fib,
+                                   const double* __restrict__ flen, double pref, double eps,
+                                   int doublet, double near_r, const Tile* __restrict__ tiles,
+                                   SrcSL64* s64, SrcSL32* s32, float* near_t) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n_s)
+        sl_src_prep_one(j, n_s, sx, f, w, sfib, n_fib, flen, pref, eps, doublet, near_r, tiles,
+                        s64, s32, near_t);
+}
+
+__global__ void dl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
+                                   const double* __restrict__ nrm, const double* __restrict__ w,
+                                   const double* __restrict__ q, const Tile* __restrict__ tiles,
+                                   SrcDL64* s64, SrcDL32* s32) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_s) return;
+    const double k = 3.0 / (4.0 * PI_D) * w[j];
+    SrcDL64 s;
+    s.x = sx[j];
+    s.y = sx[n_s + j];
+    s.z = sx[2 * n_s + j];
+    s.qx = q[j];
+    s.qy = q[n_s + j];
+    s.qz = q[2 * n_s + j];
+    s.nx = k * nrm[j];
+    s.ny = k * nrm[n_s + j];
+    s.nz = k * nrm[2 * n_s + j];
+    s.pad0 = s.pad1 = s.pad2 = 0.0;
+    s64[j] = s;
+    if (s32) {
+        const Tile& T = tiles[j / TILE];
+        SrcDL32 h;
+        h.x = (float)(s.x - T.ox);
+        h.y = (float)(s.y - T.oy);
+        h.z = (float)(s.z - T.oz);
+        h.qx = (float)s.qx;
+        h.qy = (float)s.qy;
+        h.qz = (float)s.qz;
+        h.nx = (float)s.nx;
+        h.ny = (float)s.ny;
+        h.nz = (float)s.nz;
+        h.pad0 = h.pad1 = h.pad2 = 0.0f;
+        s32[j] = h;
+    }
+}
+
+// Excluded range of a target from a self index (self-pair or on-surface point).
+__global__ void excl_self_kernel(int64_t n_t, const int64_t* __restrict__ tself, int identity,
+                                 int64_t n_s, int2* excl, unsigned long long* counters) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long cnt = 0;
+    if (i < n_t) {
+        int64_t s = tself ? tself[i] : (identity ? i : -1);
+        int2 e = make_int2(0, 0);
+        if (s >= 0 && s < n_s) {
+            e = make_int2((int)s, (int)s + 1);
+            cnt = 1;
+        }
+        excl[i] = e;
+    }
+    if (counters) wave_count(counters + 2, cnt);
+}
+
+__global__ void fill_int2_kernel(int2* p, int64_t n, int2 v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Start/end source index of every fiber (fiber ids non-decreasing).
+__global__ void fiber_bounds_kernel(int64_t n_s, const int32_t* __restrict__ sfib, int32_t n_fib,
+                                    int2* bounds) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_s) return;
+    const int f = sfib[j];
+    if (f < 0 || f >= n_fib) return;
+    if (j == 0 || sfib[j - 1] != f) bounds[f].x = (int)j;
+    if (j == n_s - 1 || sfib[j + 1] != f) bounds[f].y = (int)(j + 1);
+}
+
+__global__ void excl_fiber_kernel(int64_t n_t, const int32_t* __restrict__ tfib,
+                                  const int2* __restrict__ bounds, int32_t n_fib, int2* excl,
+                                  unsigned long long* counters) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long cnt = 0;
+    if (i < n_t) {
+        const int f = tfib[i];
+        int2 e = make_int2(0, 0);
+        if (f >= 0 && f < n_fib) {
+            e = bounds[f];
+            if (e.y < e.x) e = make_int2(0, 0);
+        }
+        excl[i] = e;
+        cnt = (unsigned long long)(e.y - e.x);
+    }
+    if (counters) wave_count(counters + 2, cnt);
+}
+
+// out = (accumulate ? out : 0) + sum_k partial[k]  (+ jump term), chunk order fixed.
+__global__ void reduce_kernel(int64_t n_t, int32_t n_chunks, const double* __restrict__ partial,
+                              int accumulate, double* out, int64_t out_stride,
+                              const int2* __restrict__ excl, const double* __restrict__ q,
+                              int64_t n_s, double jump) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_t) return;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < n_chunks; ++k) {
+        const double* p = partial + (int64_t)k * 3 * n_t;
+        v[0] += p[i];
+        v[1] += p[n_t + i];
+        v[2] += p[2 * n_t + i];
+    }
+    if (q && excl) {
+        const int2 e = excl[i];
+        if (e.y > e.x) {
+            v[0] += jump * q[e.x];
+            v[1] += jump * q[n_s + e.x];
+            v[2] += jump * q[2 * n_s + e.x];
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        double* o = out + c * out_stride + i;
+        *o = accumulate ? *o + v[c] : v[c];
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+// Non-finite / range scan; sets bits in *flag (1 = non-finite, 2 = bad fiber ids).
+__global__ void check_finite_kernel(const double* __restrict__ p, int64_t n, int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(p[i])) atomicOr(flag, 1);
+}
+__global__ void check_fiber_kernel(const int32_t* __restrict__ fib, int64_t n, int32_t n_fib,
+                                   int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int f = fib[i];
+    bool bad = (f < 0 || f >= n_fib);
+    if (i > 0 && fib[i - 1] > f) bad = true;
+    if (bad) atomicOr(flag, 2);
+}
+
+// ---- host side -----------------------------------------------------------------
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+constexpr int R_SL64 = 2, R_SL32 = 2, R_DL64 = 2, R_DL32 = 2;
+constexpr int64_t TARGET_BLOCKS = 2048;
+
+Partition make_partition(int64_t n_t, int64_t n_s, int R) {
+    Partition p{};
+    p.R = R;
+    p.n_t = n_t;
+    p.n_tiles = (int32_t)((n_s + TILE - 1) / TILE);
+    const int64_t waves = (n_t + 64 * R - 1) / (64 * R);
+    p.n_tblocks = (int32_t)((waves + 3) / 4);
+    if (p.n_tiles == 0 || n_t == 0) {
+        p.tiles_per_chunk = 1;
+        p.n_chunks = 0;
+        return p;
+    }
+    int64_t ch = (TARGET_BLOCKS + p.n_tblocks - 1) / p.n_tblocks;
+    ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / 4));
+    ch = std::max<int64_t>(1, std::min<int64_t>(ch, p.n_tiles));
+    p.tiles_per_chunk = (int32_t)((p.n_tiles + ch - 1) / ch);
+    p.n_chunks = (p.n_tiles + p.tiles_per_chunk - 1) / p.tiles_per_chunk;
+    return p;
+}
+
+// Scratch layout of one sum (both layers use the same carve order).
+struct SumScratch {
+    Tile* tiles;
+    void* s64;
+    void* s32;
+    float* near_t;
+    int2* excl;
+    int2* fbounds;
+    double* partial;
+    unsigned long long* counters;
+    int* flag;
+};
+
+static size_t sum_scratch_bytes(int64_t n_s, int64_t n_t, int32_t n_fib, size_t s64b, size_t s32b,
+                                int32_t n_chunks) {
+    const int64_t n_tiles = (n_s + TILE - 1) / TILE;
+    size_t b = 0;
+    b += Carve::round(n_tiles * sizeof(Tile)) + 256;
+    b += Carve::round(n_s * s64b) + 256;
+    b += Carve::round(n_s * s32b) + 256;
+    b += Carve::round(n_s * sizeof(float)) + 256;
+    b += Carve::round(n_t * sizeof(int2)) + 256;
+    b += Carve::round((size_t)std::max<int32_t>(n_fib, 1) * sizeof(int2)) + 256;
+    b += Carve::round((size_t)n_chunks * 3 * n_t * sizeof(double)) + 256;
+    b += 512;
+    return b;
+}
+
+static SumScratch carve_sum(void* base, int64_t n_s, int64_t n_t, int32_t n_fib, size_t s64b,
+                            size_t s32b, int32_t n_chunks) {
+    Carve c(base);
+    SumScratch s;
+    const int64_t n_tiles = (n_s + TILE - 1) / TILE;
+    s.tiles = c.take<Tile>(n_tiles);
+    s.s64 = c.take<char>(n_s * s64b);
+    s.s32 = s32b ? c.take<char>(n_s * s32b) : nullptr;
+    s.near_t = c.take<float>(n_s);
+    s.excl = c.take<int2>(n_t);
+    s.fbounds = c.take<int2>(std::max<int32_t>(n_fib, 1));
+    s.partial = c.take<double>((size_t)n_chunks * 3 * n_t);
+    s.counters = c.take<unsigned long long>(4);
+    s.flag = c.take<int>(4);
+    return s;
+}
+
+size_t sl_scratch_bytes(int64_t n_s, int64_t n_t, bool mixed) {
+    const Partition p = make_partition(n_t, n_s, mixed ? R_SL32 : R_SL64);
+    return sum_scratch_bytes(n_s, n_t, 0, sizeof(SrcSL64), mixed ? sizeof(SrcSL32) : 0,
+                             p.n_chunks);
+}
+
+// The register blocking R must match the one the partition was made with.
+static void launch_sl_kernel(bool mixed, bool doublet, unsigned grid, const SumArgs& a,
+                             hipStream_t st) {
+    if (mixed) {
+        if (doublet)
+            hipLaunchKernelGGL((sl_mixed_kernel<R_SL32, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else
+            hipLaunchKernelGGL((sl_mixed_kernel<R_SL32, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    } else {
+        if (doublet)
+            hipLaunchKernelGGL((sl_fp64_kernel<R_SL64, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else
+            hipLaunchKernelGGL((sl_fp64_kernel<R_SL64, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    }
+}
+
+// Core launcher: exclusion ranges must already be in `excl` (or null).
+static int sl_core(const SLProblem& p, const Partition& P, const SumScratch& S, const int2* excl,
+                   unsigned long long* counters, hipStream_t st) {
+    if (P.n_chunks > 0) {
+        const double pref = 1.0 / (8.0 * PI_D * p.mu);
+        hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, p.n_s,
+                           p.sxyz, P.n_tiles, p.mixed ? std::max(p.near_r, 0.0) : 0.0,
+                           p.mixed ? 2.0 * p.eps : 0.0, p.sfib, p.n_fib, p.flen, S.tiles);
+        hipLaunchKernelGGL(sl_src_prep_kernel, dim3(nblk(p.n_s)), dim3(256), 0, st, p.n_s, p.sxyz,
+                           p.force, p.weight, p.sfib, p.n_fib, p.flen, pref, p.eps,
+                           p.doublet ? 1 : 0, std::max(p.near_r, 0.0), S.tiles,
+                           static_cast<SrcSL64*>(S.s64),
+                           p.mixed ? static_cast<SrcSL32*>(S.s32) : nullptr, S.near_t);
+        SumArgs a{};
+        a.tx = p.txyz;
+        a.t_stride = p.t_stride;
+        a.n_t = p.n_t;
+        a.excl = excl;
+        a.tiles = S.tiles;
+        a.n_tiles = P.n_tiles;
+        a.tiles_per_chunk = P.tiles_per_chunk;
+        a.n_tblocks = P.n_tblocks;
+        a.s64 = S.s64;
+        a.s32 = S.s32;
+        a.near_t = S.near_t;
+        a.n_s = p.n_s;
+        a.partial = S.partial;
+        a.counters = counters;
+        const unsigned grid = (unsigned)((int64_t)P.n_tblocks * P.n_chunks);
+        prof_begin(st);
+        launch_sl_kernel(p.mixed, p.doublet, grid, a, st);
+        prof_end(st);
+        STOKES_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(reduce_kernel, dim3(nblk(p.n_t)), dim3(256), 0, st, p.n_t, P.n_chunks,
+                       S.partial, p.accumulate ? 1 : 0, p.u, p.n_t, (const int2*)nullptr,
+                       (const double*)nullptr, (int64_t)0, 0.0);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+int sl_launch(const SLProblem& p, void* scratch, unsigned long long* counters, hipStream_t st) {
+    const Partition P = make_partition(p.n_t, p.n_s, p.mixed ? R_SL32 : R_SL64);
+    const SumScratch S = carve_sum(scratch, p.n_s, p.n_t, 0, sizeof(SrcSL64),
+                                   p.mixed ? sizeof(SrcSL32) : 0, P.n_chunks);
+    return sl_core(p, P, S, p.excl, counters, st);
+}
+
+int fiber_bounds_launch(int64_t n_s, const int32_t* sfib, int32_t n_fib, int2* bounds,
+                        hipStream_t st) {
+    if (n_fib > 0)
+        hipLaunchKernelGGL(fill_int2_kernel, dim3(nblk(n_fib)), dim3(256), 0, st, bounds,
+                           (int64_t)n_fib, make_int2(0, 0));
+    if (n_s > 0)
+        hipLaunchKernelGGL(fiber_bounds_kernel, dim3(nblk(n_s)), dim3(256), 0, st, n_s, sfib, n_fib,
+                           bounds);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+int excl_same_fiber_launch(int64_t n_t, const int32_t* tfib, const int2* bounds, int32_t n_fib,
+                           int2* excl, hipStream_t st) {
+    if (n_t > 0)
+        hipLaunchKernelGGL(excl_fiber_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, tfib, bounds,
+                           n_fib, excl, (unsigned long long*)nullptr);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+// ---- validation helpers ---------------------------------------------------------
+static bool bad_ptr(const void* p, int64_t n) { return p == nullptr && n > 0; }
+
+struct Check {
+    int* flag;
+    hipStream_t st;
+    void finite(const double* p, int64_t n) {
+        if (p && n > 0)
+            hipLaunchKernelGGL(check_finite_kernel, dim3(nblk(n)), dim3(256), 0, st, p, n, flag);
+    }
+    void fiber(const int32_t* p, int64_t n, int32_t n_fib) {
+        if (p && n > 0)
+            hipLaunchKernelGGL(check_fiber_kernel, dim3(nblk(n)), dim3(256), 0, st, p, n, n_fib,
+                               flag);
+    }
+};
+
+static int read_flag(Workspace* ws, int* flag, hipStream_t st, int* out) {
+    STOKES_HIP(hipMemcpyAsync(ws->host, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    STOKES_HIP(hipStreamSynchronize(st));
+    *out = *static_cast<int*>(ws->host);
+    return STOKES_OK;
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+static int finish_diag(Workspace* ws, unsigned long long* counters, hipStream_t st, int64_t n_t,
+                       int64_t n_s, stokes_diag* diag) {
+    STOKES_HIP(hipMemcpyAsync(ws->host, counters, 3 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, st));
+    STOKES_HIP(hipStreamSynchronize(st));
+    const unsigned long long* h = static_cast<const unsigned long long*>(ws->host);
+    diag->near_pairs = (int64_t)h[0];
+    diag->coincident = (int64_t)h[1];
+    diag->pairs = n_t * n_s - (int64_t)h[2] - (int64_t)h[1];
+    return STOKES_OK;
+}
+
+}  // namespace stokes
+
+using namespace stokes;
+
+extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double* src_force,
+                              const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
+                              const double* fiber_len, int64_t n_trg, const double* trg_xyz,
+                              const int64_t* trg_self, const int32_t* trg_fiber, double mu,
+                              double eps, double near_r, uint32_t flags, double* u_out,
+                              void* stream, stokes_diag* diag) {
+    const uint32_t known = STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_EXCL_SAME_FIBER |
+                           STOKES_NO_DOUBLET | STOKES_ACCUMULATE | STOKES_CHECK_INPUTS;
+    if (flags & ~known) return fail(STOKES_E_INVAL, "stokes_sl_eval: unknown flag bits");
+    const bool self_mode = flags & STOKES_EXCL_SELF_POINT;
+    const bool fiber_mode = flags & STOKES_EXCL_SAME_FIBER;
+    if (self_mode && fiber_mode)
+        return fail(STOKES_E_INVAL, "stokes_sl_eval: choose one exclusion mode");
+    if (n_src < 0) return fail(STOKES_E_INVAL, "stokes_sl_eval: n_src < 0");
+    const bool same = (trg_xyz == nullptr);
+    const int64_t n_t = same ? n_src : n_trg;
+    if (n_t < 0) return fail(STOKES_E_INVAL, "stokes_sl_eval: n_trg < 0");
+    if (n_src >= (int64_t)1 << 31 || n_t >= (int64_t)1 << 31)
+        return fail(STOKES_E_INVAL, "stokes_sl_eval: more than 2^31-1 sources or targets");
+    if (bad_ptr(src_xyz, n_src) || bad_ptr(src_force, n_src))
+        return fail(STOKES_E_INVAL, "stokes_sl_eval: null source array");
+    if (bad_ptr(u_out, n_t)) return fail(STOKES_E_INVAL, "stokes_sl_eval: null u_out");
+    if (!(mu > 0.0) || !std::isfinite(mu)) return fail(STOKES_E_INVAL, "stokes_sl_eval: mu must be > 0");
+    if (!(eps > 0.0 && eps < 0.5)) return fail(STOKES_E_INVAL, "stokes_sl_eval: eps must be in (0, 0.5)");
+    if (!std::isfinite(near_r)) return fail(STOKES_E_INVAL, "stokes_sl_eval: near_r not finite");
+    if (n_fib < 0) return fail(STOKES_E_INVAL, "stokes_sl_eval: n_fib < 0");
+    if (src_fiber && n_fib == 0 && n_src > 0)
+        return fail(STOKES_E_INVAL, "stokes_sl_eval: src_fiber given with n_fib = 0");
+    if (fiber_mode && (src_fiber == nullptr && n_src > 0))
+        return fail(STOKES_E_INVAL, "stokes_sl_eval: STOKES_EXCL_SAME_FIBER needs src_fiber");
+    if (fiber_mode && !same && trg_fiber == nullptr && n_t > 0)
+        return fail(STOKES_E_INVAL, "stokes_sl_eval: STOKES_EXCL_SAME_FIBER needs trg_fiber");
+    if (n_t == 0) {
+        if (diag) *diag = stokes_diag{0, 0, 0};
+        return STOKES_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool mixed = flags & STOKES_PREC_MIXED;
+    const Partition P = make_partition(n_t, n_src, mixed ? R_SL32 : R_SL64);
+    const int32_t nf = src_fiber ? n_fib : 0;
+    Workspace* ws = nullptr;
+    int rc = workspace_get(st, sum_scratch_bytes(n_src, n_t, nf, sizeof(SrcSL64),
+                                                 mixed ? sizeof(SrcSL32) : 0, P.n_chunks), &ws);
+    if (rc) return rc;
+    const SumScratch S = carve_sum(ws->dev, n_src, n_t, nf, sizeof(SrcSL64),
+                                   mixed ? sizeof(SrcSL32) : 0, P.n_chunks);
+    if (flags & STOKES_CHECK_INPUTS) {
+        hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, S.flag);
+        Check c{S.flag, st};
+        c.finite(src_xyz, 3 * n_src);
+        c.finite(src_force, 3 * n_src);
+        c.finite(src_weight, n_src);
+        c.finite(fiber_len, nf);
+        if (!same) c.finite(trg_xyz, 3 * n_t);
+        c.fiber(src_fiber, n_src, n_fib);
+        STOKES_HIP(hipGetLastError());
+        int f = 0;
+        if ((rc = read_flag(ws, S.flag, st, &f))) return rc;
+        if (f & 2) return fail(STOKES_E_INVAL, "stokes_sl_eval: fiber ids out of range or decreasing");
+        if (f & 1) return fail(STOKES_E_NONFINITE, "stokes_sl_eval: non-finite input");
+    }
+    unsigned long long* counters = diag ? S.counters : nullptr;
+    if (counters) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, counters, 4);
+    const int2* excl = nullptr;
+    if (self_mode) {
+        if (trg_self || same) {
+            hipLaunchKernelGGL(excl_self_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, trg_self,
+                               same ? 1 : 0, n_src, S.excl, counters);
+            excl = S.excl;
+        }
+    } else if (fiber_mode && n_src > 0) {
+        if ((rc = fiber_bounds_launch(n_src, src_fiber, n_fib, S.fbounds, st))) return rc;
+        const int32_t* tf = trg_fiber ? trg_fiber : src_fiber;
+        hipLaunchKernelGGL(excl_fiber_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, tf,
+                           S.fbounds, n_fib, S.excl, counters);
+        excl = S.excl;
+    }
+    STOKES_HIP(hipGetLastError());
+    SLProblem p{};
+    p.n_s = n_src;
+    p.sxyz = src_xyz;
+    p.force = src_force;
+    p.weight = src_weight;
+    p.sfib = src_fiber;
+    p.n_fib = nf;
+    p.flen = fiber_len;
+    p.n_t = n_t;
+    p.txyz = same ? src_xyz : trg_xyz;
+    p.t_stride = same ? n_src : n_t;
+    p.excl = excl;
+    p.mu = mu;
+    p.eps = eps;
+    p.near_r = near_r;
+    p.mixed = mixed;
+    p.doublet = !(flags & STOKES_NO_DOUBLET);
+    p.accumulate = flags & STOKES_ACCUMULATE;
+    p.u = u_out;
+    if ((rc = sl_core(p, P, S, excl, counters, st))) return rc;
+    if (diag) return finish_diag(ws, counters, st, n_t, n_src, diag);
+    return STOKES_OK;
+}
+
+static void launch_dl_kernel(bool mixed, bool sub, unsigned grid, const SumArgs& a, hipStream_t st) {
+    if (mixed) {
+        if (sub)
+            hipLaunchKernelGGL((dl_mixed_kernel<R_DL32, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else
+            hipLaunchKernelGGL((dl_mixed_kernel<R_DL32, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    } else {
+        if (sub)
+            hipLaunchKernelGGL((dl_fp64_kernel<R_DL64, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else
+            hipLaunchKernelGGL((dl_fp64_kernel<R_DL64, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    }
+}
+
+extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double* src_normal,
+                              const double* src_weight, const double* src_q, int64_t n_trg,
+                              const double* trg_xyz, const int64_t* trg_self, double near_r,
+                              uint32_t flags, double* u_out, void* stream, stokes_diag* diag) {
+    const uint32_t known = STOKES_PREC_MIXED | STOKES_ONSURF_RAW | STOKES_ACCUMULATE |
+                           STOKES_CHECK_INPUTS;
+    if (flags & ~known) return fail(STOKES_E_INVAL, "stokes_dl_eval: unknown flag bits");
+    if (n_src < 0) return fail(STOKES_E_INVAL, "stokes_dl_eval: n_src < 0");
+    const bool same = (trg_xyz == nullptr);
+    const int64_t n_t = same ? n_src : n_trg;
+    if (n_t < 0) return fail(STOKES_E_INVAL, "stokes_dl_eval: n_trg < 0");
+    if (n_src >= (int64_t)1 << 31 || n_t >= (int64_t)1 << 31)
+        return fail(STOKES_E_INVAL, "stokes_dl_eval: more than 2^31-1 sources or targets");
+    if (bad_ptr(src_xyz, n_src) || bad_ptr(src_normal, n_src) || bad_ptr(src_weight, n_src) ||
+        bad_ptr(src_q, n_src))
+        return fail(STOKES_E_INVAL, "stokes_dl_eval: null source array");
+    if (bad_ptr(u_out, n_t)) return fail(STOKES_E_INVAL, "stokes_dl_eval: null u_out");
+    if (!std::isfinite(near_r)) return fail(STOKES_E_INVAL, "stokes_dl_eval: near_r not finite");
+    if (n_t == 0) {
+        if (diag) *diag = stokes_diag{0, 0, 0};
+        return STOKES_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool mixed = flags & STOKES_PREC_MIXED;
+    const bool sub = !(flags & STOKES_ONSURF_RAW);
+    const double nr = near_r > 0.0 ? near_r : 0.02;
+    const Partition P = make_partition(n_t, n_src, mixed ? R_DL32 : R_DL64);
+    Workspace* ws = nullptr;
+    int rc = workspace_get(st, sum_scratch_bytes(n_src, n_t, 0, sizeof(SrcDL64),
+                                                 mixed ? sizeof(SrcDL32) : 0, P.n_chunks), &ws);
+    if (rc) return rc;
+    const SumScratch S = carve_sum(ws->dev, n_src, n_t, 0, sizeof(SrcDL64),
+                                   mixed ? sizeof(SrcDL32) : 0, P.n_chunks);
+    if (flags & STOKES_CHECK_INPUTS) {
+        hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, S.flag);
+        Check c{S.flag, st};
+        c.finite(src_xyz, 3 * n_src);
+        c.finite(src_normal, 3 * n_src);
+        c.finite(src_weight, n_src);
+        c.finite(src_q, 3 * n_src);
+        if (!same) c.finite(trg_xyz, 3 * n_t);
+        STOKES_HIP(hipGetLastError());
+        int f = 0;
+        if ((rc = read_flag(ws, S.flag, st, &f))) return rc;
+        if (f & 1) return fail(STOKES_E_NONFINITE, "stokes_dl_eval: non-finite input");
+    }
+    unsigned long long* counters = diag ? S.counters : nullptr;
+    if (counters) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, counters, 4);
+    hipLaunchKernelGGL(excl_self_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, trg_self,
+                       same ? 1 : 0, n_src, S.excl, counters);
+    const double* tx = same ? src_xyz : trg_xyz;
+    const int64_t ts = same ? n_src : n_t;
+    if (P.n_chunks > 0) {
+        hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, n_src,
+                           src_xyz, P.n_tiles, mixed ? nr : 0.0, 0.0, (const int32_t*)nullptr, 0,
+                           (const double*)nullptr, S.tiles);
+        hipLaunchKernelGGL(dl_src_prep_kernel, dim3(nblk(n_src)), dim3(256), 0, st, n_src, src_xyz,
+                           src_normal, src_weight, src_q, S.tiles, static_cast<SrcDL64*>(S.s64),
+                           mixed ? static_cast<SrcDL32*>(S.s32) : nullptr);
+        SumArgs a{};
+        a.tx = tx;
+        a.t_stride = ts;
+        a.n_t = n_t;
+        a.excl = S.excl;
+        a.tiles = S.tiles;
+        a.n_tiles = P.n_tiles;
+        a.tiles_per_chunk = P.tiles_per_chunk;
+        a.n_tblocks = P.n_tblocks;
+        a.s64 = S.s64;
+        a.s32 = S.s32;
+        a.near_t_uniform = (float)(nr * nr);
+        a.q = src_q;
+        a.n_s = n_src;
+        a.partial = S.partial;
+        a.counters = counters;
+        const unsigned grid = (unsigned)((int64_t)P.n_tblocks * P.n_chunks);
+        prof_begin(st);
+        launch_dl_kernel(mixed, sub, grid, a, st);
+        prof_end(st);
+    }
+    hipLaunchKernelGGL(reduce_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, P.n_chunks,
+                       S.partial, (flags & STOKES_ACCUMULATE) ? 1 : 0, u_out, n_t,
+                       (const int2*)S.excl, sub ? src_q : (const double*)nullptr, n_src, -0.5);
+    STOKES_HIP(hipGetLastError());
+    if (diag) return finish_diag(ws, counters, st, n_t, n_src, diag);
+    return STOKES_OK;
+}

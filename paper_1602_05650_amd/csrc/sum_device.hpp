@@ -1,0 +1,646 @@
+// Device code of the kernel sums, shared by the one-shot launches and the
+// batched (serving) kernels.  See stokes_sums.hip for the execution scheme.
+#pragma once
+
+#include "stokes_internal.hpp"
+
+namespace stokes {
+
+constexpr double PI_D = 3.14159265358979323846264338327950288;
+
+// ---- small device helpers -------------------------------------------------
+
+// 1/sqrt(x) to full FP64 accuracy: hardware estimate plus one third-order
+// Newton-Raphson correction y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = x * y;
+    const double e = fma(-h, y, 1.0);
+    const double p = fma(e, 0.375, 0.5);
+    return fma(y * e, p, y);
+}
+
+__device__ __forceinline__ bool in_range(int j, int lo, int hi) {
+    return (unsigned)(j - lo) < (unsigned)(hi - lo);
+}
+
+__device__ __forceinline__ void kahan_add(float& S, float& C, float v) {
+    const float y = v - C;
+    const float t = S + y;
+    C = (t - S) - y;
+    S = t;
+}
+
+// Single-layer pair, FP64: u += s/r + c s/r^3 + d (d.s) (1/r^3 - 3c/r^5).
+template <bool DOUBLET>
+__device__ __forceinline__ void sl_pair64(double dx, double dy, double dz, double ri,
+                                          const SrcSL64& s, double& ux, double& uy, double& uz) {
+    const double ri2 = ri * ri;
+    const double ri3 = ri * ri2;
+    const double ds = fma(dx, s.sx, fma(dy, s.sy, dz * s.sz));
+    double A, E;
+    if (DOUBLET) {
+        const double ri5 = ri3 * ri2;
+        A = fma(s.c, ri3, ri);
+        E = fma(s.c3, ri5, ri3);
+    } else {
+        A = ri;
+        E = ri3;
+    }
+    const double B = ds * E;
+    ux = fma(A, s.sx, ux);
+    uy = fma(A, s.sy, uy);
+    uz = fma(A, s.sz, uz);
+    ux = fma(B, dx, ux);
+    uy = fma(B, dy, uy);
+    uz = fma(B, dz, uz);
+}
+
+template <bool DOUBLET>
+__device__ __forceinline__ void sl_pair32(float dx, float dy, float dz, float ri,
+                                          const SrcSL32& s, float& ux, float& uy, float& uz) {
+    const float ri2 = ri * ri;
+    const float ri3 = ri * ri2;
+    const float ds = fmaf(dx, s.sx, fmaf(dy, s.sy, dz * s.sz));
+    float A, E;
+    if (DOUBLET) {
+        const float ri5 = ri3 * ri2;
+        A = fmaf(s.c, ri3, ri);
+        E = fmaf(s.c3, ri5, ri3);
+    } else {
+        A = ri;
+        E = ri3;
+    }
+    const float B = ds * E;
+    ux = fmaf(A, s.sx, ux);
+    uy = fmaf(A, s.sy, uy);
+    uz = fmaf(A, s.sz, uz);
+    ux = fmaf(B, dx, ux);
+    uy = fmaf(B, dy, uy);
+    uz = fmaf(B, dz, uz);
+}
+
+// Double-layer pair: u += (d.qt)(d.n') d / r^5 with n' = (3/(4 pi)) w n.
+template <bool SUB>
+__device__ __forceinline__ void dl_pair64(double dx, double dy, double dz, double ri,
+                                          const SrcDL64& s, double q0x, double q0y, double q0z,
+                                          double& ux, double& uy, double& uz) {
+    const double qx = SUB ? s.qx - q0x : s.qx;
+    const double qy = SUB ? s.qy - q0y : s.qy;
+    const double qz = SUB ? s.qz - q0z : s.qz;
+    const double dq = fma(dx, qx, fma(dy, qy, dz * qz));
+    const double dn = fma(dx, s.nx, fma(dy, s.ny, dz * s.nz));
+    const double ri2 = ri * ri;
+    const double ri5 = ri2 * ri2 * ri;
+    const double e = dq * dn * ri5;
+    ux = fma(e, dx, ux);
+    uy = fma(e, dy, uy);
+    uz = fma(e, dz, uz);
+}
+
+template <bool SUB>
+__device__ __forceinline__ void dl_pair32(float dx, float dy, float dz, float ri, const SrcDL32& s,
+                                          float q0x, float q0y, float q0z, float& ux, float& uy,
+                                          float& uz) {
+    const float qx = SUB ? s.qx - q0x : s.qx;
+    const float qy = SUB ? s.qy - q0y : s.qy;
+    const float qz = SUB ? s.qz - q0z : s.qz;
+    const float dq = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
+    const float dn = fmaf(dx, s.nx, fmaf(dy, s.ny, dz * s.nz));
+    const float ri2 = ri * ri;
+    const float ri5 = ri2 * ri2 * ri;
+    const float e = dq * dn * ri5;
+    ux = fmaf(e, dx, ux);
+    uy = fmaf(e, dy, uy);
+    uz = fmaf(e, dz, uz);
+}
+
+__device__ __forceinline__ void wave_count(unsigned long long* ctr, unsigned long long v) {
+    // one atomic per wave and counter (integer: order-independent)
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, v);
+}
+
+// ---- kernel arguments -------------------------------------------------------
+struct SumArgs {
+    const double* tx;        // target planes: tx[c * t_stride + i]
+    int64_t t_stride;
+    int64_t n_t;
+    const int2* excl;        // per-target excluded source range [lo, hi), or null
+    const Tile* tiles;
+    int32_t n_tiles;
+    int32_t tiles_per_chunk;
+    int32_t n_tblocks;
+    const void* s64;         // SrcSL64 / SrcDL64
+    const void* s32;         // SrcSL32 / SrcDL32 (mixed)
+    const float* near_t;     // SL mixed: per-source FP32 near threshold on |d|^2
+    float near_t_uniform;    // DL mixed: threshold on |d|^2
+    const double* q;         // DL: density planes (for q_self), stride n_s
+    int64_t n_s;
+    double* partial;         // [n_chunks][3][n_t]
+    unsigned long long* counters;  // null or {near, coincident, excluded}
+};
+
+// ---- single layer, FP64 -------------------------------------------------------
+template <int R, bool DOUBLET>
+__device__ __forceinline__ void sl_fp64_wave(const SumArgs& a, int tb, int chunk) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
+    if (wbase >= a.n_t) return;
+
+    double X[R], Y[R], Z[R], ux[R], uy[R], uz[R];
+    int lo[R], hi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t i = wbase + lane + 64 * r;
+        if (i >= a.n_t) i = a.n_t - 1;
+        X[r] = a.tx[i];
+        Y[r] = a.tx[a.t_stride + i];
+        Z[r] = a.tx[2 * a.t_stride + i];
+        const int2 e = a.excl ? a.excl[i] : make_int2(0, 0);
+        lo[r] = e.x;
+        hi[r] = e.y;
+        ux[r] = uy[r] = uz[r] = 0.0;
+    }
+    unsigned long long ncoin = 0;
+    const SrcSL64* __restrict__ src = static_cast<const SrcSL64*>(a.s64);
+    const int t0 = chunk * a.tiles_per_chunk;
+    const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = a.tiles[t];
+        bool need = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = X[r] - T.ox, dy = Y[r] - T.oy, dz = Z[r] - T.oz;
+            need |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
+            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+        }
+        if (__ballot(need) == 0) {
+#pragma unroll 4
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcSL64 s = src[j];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double dx = X[r] - s.x, dy = Y[r] - s.y, dz = Z[r] - s.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    sl_pair64<DOUBLET>(dx, dy, dz, rsqrt64(r2), s, ux[r], uy[r], uz[r]);
+                }
+            }
+        } else {
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcSL64 s = src[j];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double dx = X[r] - s.x, dy = Y[r] - s.y, dz = Z[r] - s.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    const bool ex = in_range(j, lo[r], hi[r]);
+                    const bool zero = (r2 == 0.0);
+                    ncoin += (!ex && zero && (wbase + lane + 64 * r < a.n_t)) ? 1 : 0;
+                    const double ri = (ex || zero) ? 0.0 : rsqrt64(zero ? 1.0 : r2);
+                    sl_pair64<DOUBLET>(dx, dy, dz, ri, s, ux[r], uy[r], uz[r]);
+                }
+            }
+        }
+    }
+    double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = wbase + lane + 64 * r;
+        if (i < a.n_t) {
+            out[i] = ux[r];
+            out[a.n_t + i] = uy[r];
+            out[2 * a.n_t + i] = uz[r];
+        }
+    }
+    if (a.counters) wave_count(a.counters + 1, ncoin);
+}
+
+// ---- single layer, mixed FP32 / FP64 -------------------------------------------
+template <int R, bool DOUBLET>
+__device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chunk) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
+    if (wbase >= a.n_t) return;
+
+    double X[R], Y[R], Z[R], nx[R], ny[R], nz[R];
+    float Sx[R], Sy[R], Sz[R], Cx[R], Cy[R], Cz[R];
+    int lo[R], hi[R];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t i = wbase + lane + 64 * r;
+        valid[r] = i < a.n_t;
+        if (!valid[r]) i = a.n_t - 1;
+        X[r] = a.tx[i];
+        Y[r] = a.tx[a.t_stride + i];
+        Z[r] = a.tx[2 * a.t_stride + i];
+        const int2 e = a.excl ? a.excl[i] : make_int2(0, 0);
+        lo[r] = e.x;
+        hi[r] = e.y;
+        nx[r] = ny[r] = nz[r] = 0.0;
+        Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
+    }
+    unsigned long long nnear = 0, ncoin = 0;
+    const SrcSL32* __restrict__ src = static_cast<const SrcSL32*>(a.s32);
+    const SrcSL64* __restrict__ src64 = static_cast<const SrcSL64*>(a.s64);
+    const int t0 = chunk * a.tiles_per_chunk;
+    const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = a.tiles[t];
+        float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
+        bool need = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            xs[r] = (float)(X[r] - T.ox);
+            ys[r] = (float)(Y[r] - T.oy);
+            zs[r] = (float)(Z[r] - T.oz);
+            need |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
+            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+            px[r] = py[r] = pz[r] = 0.0f;
+        }
+        if (__ballot(need) == 0) {
+#pragma unroll 4
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcSL32 s = src[j];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    sl_pair32<DOUBLET>(dx, dy, dz, __builtin_amdgcn_rsqf(r2), s, px[r], py[r], pz[r]);
+                }
+            }
+        } else {
+            uint32_t m[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) m[r] = 0u;
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcSL32 s = src[j];
+                const float tj = a.near_t[j];
+                const uint32_t bit = 1u << (j - T.j0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const bool bad = (r2 < tj) | in_range(j, lo[r], hi[r]);
+                    m[r] |= bad ? bit : 0u;
+                    const float ri = bad ? 0.0f : __builtin_amdgcn_rsqf(r2);
+                    sl_pair32<DOUBLET>(dx, dy, dz, ri, s, px[r], py[r], pz[r]);
+                }
+            }
+            // FP64 recomputation of the masked (near) pairs from the FP64 inputs
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                uint32_t mm = m[r];
+                while (mm) {
+                    const int k = __builtin_ctz(mm);
+                    mm &= mm - 1;
+                    const int j = T.j0 + k;
+                    if (in_range(j, lo[r], hi[r])) continue;
+                    const SrcSL64 s = src64[j];
+                    const double dx = X[r] - s.x, dy = Y[r] - s.y, dz = Z[r] - s.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    if (r2 == 0.0) {
+                        ncoin += valid[r] ? 1 : 0;
+                        continue;
+                    }
+                    nnear += valid[r] ? 1 : 0;
+                    sl_pair64<DOUBLET>(dx, dy, dz, rsqrt64(r2), s, nx[r], ny[r], nz[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            kahan_add(Sx[r], Cx[r], px[r]);
+            kahan_add(Sy[r], Cy[r], py[r]);
+            kahan_add(Sz[r], Cz[r], pz[r]);
+        }
+    }
+    double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = wbase + lane + 64 * r;
+        if (valid[r]) {
+            out[i] = ((double)Sx[r] - (double)Cx[r]) + nx[r];
+            out[a.n_t + i] = ((double)Sy[r] - (double)Cy[r]) + ny[r];
+            out[2 * a.n_t + i] = ((double)Sz[r] - (double)Cz[r]) + nz[r];
+        }
+    }
+    if (a.counters) {
+        wave_count(a.counters + 0, nnear);
+        wave_count(a.counters + 1, ncoin);
+    }
+}
+
+// ---- double layer, FP64 -----------------------------------------------------
+template <int R, bool SUB>
+__device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
+    if (wbase >= a.n_t) return;
+
+    double X[R], Y[R], Z[R], ux[R], uy[R], uz[R], qx[R], qy[R], qz[R];
+    int lo[R], hi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t i = wbase + lane + 64 * r;
+        if (i >= a.n_t) i = a.n_t - 1;
+        X[r] = a.tx[i];
+        Y[r] = a.tx[a.t_stride + i];
+        Z[r] = a.tx[2 * a.t_stride + i];
+        const int2 e = a.excl ? a.excl[i] : make_int2(0, 0);
+        lo[r] = e.x;
+        hi[r] = e.y;
+        qx[r] = qy[r] = qz[r] = 0.0;
+        if (SUB && e.y > e.x) {
+            qx[r] = a.q[e.x];
+            qy[r] = a.q[a.n_s + e.x];
+            qz[r] = a.q[2 * a.n_s + e.x];
+        }
+        ux[r] = uy[r] = uz[r] = 0.0;
+    }
+    unsigned long long ncoin = 0;
+    const SrcDL64* __restrict__ src = static_cast<const SrcDL64*>(a.s64);
+    const int t0 = chunk * a.tiles_per_chunk;
+    const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = a.tiles[t];
+        bool need = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = X[r] - T.ox, dy = Y[r] - T.oy, dz = Z[r] - T.oz;
+            need |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
+            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+        }
+        if (__ballot(need) == 0) {
+#pragma unroll 2
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcDL64 s = src[j];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double dx = X[r] - s.x, dy = Y[r] - s.y, dz = Z[r] - s.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, qx[r], qy[r], qz[r], ux[r], uy[r], uz[r]);
+                }
+            }
+        } else {
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcDL64 s = src[j];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double dx = X[r] - s.x, dy = Y[r] - s.y, dz = Z[r] - s.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    const bool ex = in_range(j, lo[r], hi[r]);
+                    const bool zero = (r2 == 0.0);
+                    ncoin += (!ex && zero && (wbase + lane + 64 * r < a.n_t)) ? 1 : 0;
+                    const double ri = (ex || zero) ? 0.0 : rsqrt64(zero ? 1.0 : r2);
+                    dl_pair64<SUB>(dx, dy, dz, ri, s, qx[r], qy[r], qz[r], ux[r], uy[r], uz[r]);
+                }
+            }
+        }
+    }
+    double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = wbase + lane + 64 * r;
+        if (i < a.n_t) {
+            out[i] = ux[r];
+            out[a.n_t + i] = uy[r];
+            out[2 * a.n_t + i] = uz[r];
+        }
+    }
+    if (a.counters) wave_count(a.counters + 1, ncoin);
+}
+
+// ---- double layer, mixed FP32 / FP64 -------------------------------------------
+template <int R, bool SUB>
+__device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chunk) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
+    if (wbase >= a.n_t) return;
+
+    double X[R], Y[R], Z[R], nx[R], ny[R], nz[R], qx[R], qy[R], qz[R];
+    float fqx[R], fqy[R], fqz[R];
+    float Sx[R], Sy[R], Sz[R], Cx[R], Cy[R], Cz[R];
+    int lo[R], hi[R];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t i = wbase + lane + 64 * r;
+        valid[r] = i < a.n_t;
+        if (!valid[r]) i = a.n_t - 1;
+        X[r] = a.tx[i];
+        Y[r] = a.tx[a.t_stride + i];
+        Z[r] = a.tx[2 * a.t_stride + i];
+        const int2 e = a.excl ? a.excl[i] : make_int2(0, 0);
+        lo[r] = e.x;
+        hi[r] = e.y;
+        qx[r] = qy[r] = qz[r] = 0.0;
+        if (SUB && e.y > e.x) {
+            qx[r] = a.q[e.x];
+            qy[r] = a.q[a.n_s + e.x];
+            qz[r] = a.q[2 * a.n_s + e.x];
+        }
+        fqx[r] = (float)qx[r];
+        fqy[r] = (float)qy[r];
+        fqz[r] = (float)qz[r];
+        nx[r] = ny[r] = nz[r] = 0.0;
+        Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
+    }
+    unsigned long long nnear = 0, ncoin = 0;
+    const SrcDL32* __restrict__ src = static_cast<const SrcDL32*>(a.s32);
+    const SrcDL64* __restrict__ src64 = static_cast<const SrcDL64*>(a.s64);
+    const float tn = a.near_t_uniform;
+    const int t0 = chunk * a.tiles_per_chunk;
+    const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = a.tiles[t];
+        float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
+        bool need = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            xs[r] = (float)(X[r] - T.ox);
+            ys[r] = (float)(Y[r] - T.oy);
+            zs[r] = (float)(Z[r] - T.oz);
+            need |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
+            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+            px[r] = py[r] = pz[r] = 0.0f;
+        }
+        if (__ballot(need) == 0) {
+#pragma unroll 4
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcDL32 s = src[j];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    dl_pair32<SUB>(dx, dy, dz, __builtin_amdgcn_rsqf(r2), s, fqx[r], fqy[r], fqz[r],
+                                   px[r], py[r], pz[r]);
+                }
+            }
+        } else {
+            uint32_t m[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) m[r] = 0u;
+            for (int j = T.j0; j < T.j1; ++j) {
+                const SrcDL32 s = src[j];
+                const uint32_t bit = 1u << (j - T.j0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const bool bad = (r2 < tn) | in_range(j, lo[r], hi[r]);
+                    m[r] |= bad ? bit : 0u;
+                    const float ri = bad ? 0.0f : __builtin_amdgcn_rsqf(r2);
+                    dl_pair32<SUB>(dx, dy, dz, ri, s, fqx[r], fqy[r], fqz[r], px[r], py[r], pz[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                uint32_t mm = m[r];
+                while (mm) {
+                    const int k = __builtin_ctz(mm);
+                    mm &= mm - 1;
+                    const int j = T.j0 + k;
+                    if (in_range(j, lo[r], hi[r])) continue;
+                    const SrcDL64 s = src64[j];
+                    const double dx = X[r] - s.x, dy = Y[r] - s.y, dz = Z[r] - s.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    if (r2 == 0.0) {
+                        ncoin += valid[r] ? 1 : 0;
+                        continue;
+                    }
+                    nnear += valid[r] ? 1 : 0;
+                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, qx[r], qy[r], qz[r], nx[r], ny[r], nz[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            kahan_add(Sx[r], Cx[r], px[r]);
+            kahan_add(Sy[r], Cy[r], py[r]);
+            kahan_add(Sz[r], Cz[r], pz[r]);
+        }
+    }
+    double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = wbase + lane + 64 * r;
+        if (valid[r]) {
+            out[i] = ((double)Sx[r] - (double)Cx[r]) + nx[r];
+            out[a.n_t + i] = ((double)Sy[r] - (double)Cy[r]) + ny[r];
+            out[2 * a.n_t + i] = ((double)Sz[r] - (double)Cz[r]) + nz[r];
+        }
+    }
+    if (a.counters) {
+        wave_count(a.counters + 0, nnear);
+        wave_count(a.counters + 1, ncoin);
+    }
+}
+
+
+// ---- preparation (per tile / per source) ----
+__device__ __forceinline__ void tile_prep_one(int t, int64_t n_s, const double* __restrict__ sx,
+                                              double near_r, double near_fac,
+                                              const int32_t* __restrict__ sfib, int32_t n_fib,
+                                              const double* __restrict__ flen, Tile* tiles) {
+    const int j0 = t * TILE;
+    const int j1 = (int)min((int64_t)j0 + TILE, n_s);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double nr = near_r;
+    for (int j = j0; j < j1; ++j) {
+        for (int c = 0; c < 3; ++c) {
+            const double v = sx[c * n_s + j];
+            lo[c] = fmin(lo[c], v);
+            hi[c] = fmax(hi[c], v);
+        }
+        if (near_fac > 0.0) {
+            double L = 1.0;
+            if (flen) {
+                int f = sfib ? sfib[j] : 0;
+                if (f >= 0 && f < (sfib ? n_fib : 1)) L = flen[f];
+            }
+            nr = fmax(nr, near_fac * L);
+        }
+    }
+    Tile T;
+    T.ox = 0.5 * (lo[0] + hi[0]);
+    T.oy = 0.5 * (lo[1] + hi[1]);
+    T.oz = 0.5 * (lo[2] + hi[2]);
+    double rad2 = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double dx = sx[j] - T.ox, dy = sx[n_s + j] - T.oy, dz = sx[2 * n_s + j] - T.oz;
+        rad2 = fmax(rad2, dx * dx + dy * dy + dz * dz);
+    }
+    const double rad = sqrt(rad2);
+    const double r64 = rad * (1.0 + 1e-9) + 1e-300;
+    T.reach2 = r64 * r64;
+    const double rm = (rad + nr) * (1.0 + 1e-5) + 1e-30;
+    T.reach2_f = (float)(rm * rm) * (1.0f + 1e-6f);
+    T.j0 = j0;
+    T.j1 = j1;
+    T.pad = 0;
+    tiles[t] = T;
+}
+
+__device__ __forceinline__ void sl_src_prep_one(int64_t j, int64_t n_s, const double* __restrict__ sx,
+                                                const double* __restrict__ f,
+                                                const double* __restrict__ w,
+                                                const int32_t* __restrict__ sfib, int32_t n_fib,
+                                                const double* __restrict__ flen, double pref,
+                                                double eps, int doublet, double near_r,
+                                                const Tile* __restrict__ tiles, SrcSL64* s64,
+                                                SrcSL32* s32, float* near_t) {
+    double L = 1.0;
+    if (flen) {
+        const int fb = sfib ? sfib[j] : 0;
+        if (fb >= 0 && fb < (sfib ? n_fib : 1)) L = flen[fb];
+    }
+    const double wj = w ? w[j] : 1.0;
+    const double a = eps * L;
+    const double c = doublet ? 0.5 * a * a : 0.0;
+    SrcSL64 s;
+    s.x = sx[j];
+    s.y = sx[n_s + j];
+    s.z = sx[2 * n_s + j];
+    s.c = c;
+    s.c3 = -3.0 * c;
+    s.sx = pref * wj * f[j];
+    s.sy = pref * wj * f[n_s + j];
+    s.sz = pref * wj * f[2 * n_s + j];
+    s64[j] = s;
+    if (s32) {
+        const Tile& T = tiles[j / TILE];
+        SrcSL32 h;
+        h.x = (float)(s.x - T.ox);
+        h.y = (float)(s.y - T.oy);
+        h.z = (float)(s.z - T.oz);
+        h.c = (float)c;
+        h.c3 = (float)(-3.0 * c);
+        h.sx = (float)s.sx;
+        h.sy = (float)s.sy;
+        h.sz = (float)s.sz;
+        s32[j] = h;
+        const double nr = fmax(near_r, 2.0 * a);
+        near_t[j] = (float)(nr * nr);
+    }
+}
+
+// One block of BLOCK threads runs four waves of target block tb on chunk `chunk`.
+template <int R, bool DOUBLET>
+__global__ __launch_bounds__(BLOCK) void sl_fp64_kernel(SumArgs a) {
+    sl_fp64_wave<R, DOUBLET>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
+}
+template <int R, bool DOUBLET>
+__global__ __launch_bounds__(BLOCK) void sl_mixed_kernel(SumArgs a) {
+    sl_mixed_wave<R, DOUBLET>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
+}
+template <int R, bool SUB>
+__global__ __launch_bounds__(BLOCK) void dl_fp64_kernel(SumArgs a) {
+    dl_fp64_wave<R, SUB>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
+}
+template <int R, bool SUB>
+__global__ __launch_bounds__(BLOCK) void dl_mixed_kernel(SumArgs a) {
+    dl_mixed_wave<R, SUB>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
+}
+
+}  // namespace stokes

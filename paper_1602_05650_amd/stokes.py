@@ -1,0 +1,320 @@
+"""ctypes binding of libstokes.so (C ABI in include/stokes.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Device arrays are torch tensors on a ROCm device
+(float64 SoA planes of shape (3, n), int32 fiber ids, int64 self indices);
+streams are torch.cuda streams.  If the library is missing this module raises
+at import: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstokes.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY, E_CANCELED, E_TIMEOUT, E_NOTFOUND = range(9)
+PREC_FP64 = 0
+PREC_MIXED = 1
+EXCL_SELF_POINT = 2
+EXCL_SAME_FIBER = 4
+NO_DOUBLET = 8
+ACCUMULATE = 16
+CHECK_INPUTS = 32
+ONSURF_RAW = 64
+MAX_ITERS = 128
+
+
+class StokesError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{status_string(code)}: {msg}")
+        self.code = code
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
+                ("coincident", ctypes.c_int64)]
+
+
+class SessionCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("device", ctypes.c_int32)]
+
+
+class SolveReq(ctypes.Structure):
+    _fields_ = [("n_fib", ctypes.c_int32), ("nodes_per_fib", ctypes.c_int32),
+                ("xyz", ctypes.c_void_p), ("tangent", ctypes.c_void_p),
+                ("fiber_len", ctypes.c_void_p), ("rhs", ctypes.c_void_p),
+                ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("tag", ctypes.c_uint64)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_finish_ns", ctypes.c_int64), ("iters", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("tag", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libstokes.so not built ({LIB_PATH}); run __graft_entry__.build() "
+                          "or python paper_1602_05650_amd/csrc/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                           ctypes.c_double)
+    sig = {
+        "stokes_sl_eval": [I64, P, P, P, P, I32, P, I64, P, P, P, D, D, D, U32, P, P, P],
+        "stokes_dl_eval": [I64, P, P, P, P, I64, P, P, D, U32, P, P, P],
+        "stokes_local_sbt": [I64, P, P, D, D, ctypes.c_int, P, P],
+        "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, I32, U32, P, P, P, P],
+        "stokes_session_create": [P, P],
+        "stokes_session_submit": [P, P, P],
+        "stokes_session_wait": [P, ctypes.c_uint64, P, P, I32],
+        "stokes_session_cancel": [P, ctypes.c_uint64],
+        "stokes_session_destroy": [P],
+        "stokes_release_workspace": [],
+        "stokes_version": [],
+        "stokes_profile_enable": [ctypes.c_int],
+        "stokes_profile_read": [P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.stokes_status_string.argtypes = [ctypes.c_int]
+    lib.stokes_status_string.restype = ctypes.c_char_p
+    lib.stokes_last_error.argtypes = []
+    lib.stokes_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def status_string(code: int) -> str:
+    return _lib.stokes_status_string(int(code)).decode()
+
+
+def last_error() -> str:
+    return _lib.stokes_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise StokesError(rc, last_error())
+
+
+def _dev(t: Optional[torch.Tensor], dtype, name, shape=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def sl_eval(src_xyz, src_force, *, src_weight=None, src_fiber=None, fiber_len=None, n_fib=None,
+            trg_xyz=None, trg_self=None, trg_fiber=None, mu=1.0, eps=0.01, near_r=0.0,
+            mixed=False, excl="self", doublet=True, accumulate=False, out=None,
+            check_inputs=False, diag=False, stream=None):
+    """Single-layer (Stokeslet + doublet) sum; returns (3, n_trg) float64 [, Diag].
+
+    With src_fiber given, the fiber count is fiber_len's length, or n_fib."""
+    src_xyz = _dev(src_xyz, torch.float64, "src_xyz")
+    ns = src_xyz.shape[1]
+    _dev(src_force, torch.float64, "src_force", (3, ns))
+    _dev(src_weight, torch.float64, "src_weight", (ns,))
+    _dev(src_fiber, torch.int32, "src_fiber", (ns,))
+    _dev(fiber_len, torch.float64, "fiber_len")
+    _dev(trg_xyz, torch.float64, "trg_xyz")
+    nt = ns if trg_xyz is None else trg_xyz.shape[1]
+    _dev(trg_self, torch.int64, "trg_self", (nt,))
+    _dev(trg_fiber, torch.int32, "trg_fiber", (nt,))
+    if out is None:
+        out = (torch.zeros if accumulate else torch.empty)((3, nt), dtype=torch.float64,
+                                                           device=src_xyz.device)
+    _dev(out, torch.float64, "out", (3, nt))
+    if nt == 0:          # an empty tensor has no data pointer, and NULL targets mean "the sources"
+        return (out, Diag()) if diag else out
+    flags = PREC_MIXED if mixed else PREC_FP64
+    flags |= {"self": EXCL_SELF_POINT, "fiber": EXCL_SAME_FIBER, None: 0, "none": 0}[excl]
+    flags |= 0 if doublet else NO_DOUBLET
+    flags |= ACCUMULATE if accumulate else 0
+    flags |= CHECK_INPUTS if check_inputs else 0
+    if src_fiber is None:
+        n_fib = 0
+    elif fiber_len is not None:
+        n_fib = fiber_len.shape[0]
+    elif n_fib is None:
+        raise ValueError("src_fiber given: pass fiber_len or n_fib")
+    d = Diag() if diag else None
+    rc = _lib.stokes_sl_eval(ns, _ptr(src_xyz), _ptr(src_force), _ptr(src_weight),
+                             _ptr(src_fiber), n_fib, _ptr(fiber_len), nt, _ptr(trg_xyz),
+                             _ptr(trg_self), _ptr(trg_fiber), float(mu), float(eps),
+                             float(near_r), flags, _ptr(out), _stream(stream),
+                             ctypes.byref(d) if d is not None else None)
+    _check(rc)
+    return (out, d) if diag else out
+
+
+def dl_eval(src_xyz, src_normal, src_weight, src_q, *, trg_xyz=None, trg_self=None,
+            near_r=0.0, mixed=False, subtract=True, accumulate=False, out=None,
+            check_inputs=False, diag=False, stream=None):
+    """Double-layer (stresslet) sum; returns (3, n_trg) float64 [, Diag]."""
+    src_xyz = _dev(src_xyz, torch.float64, "src_xyz")
+    ns = src_xyz.shape[1]
+    _dev(src_normal, torch.float64, "src_normal", (3, ns))
+    _dev(src_weight, torch.float64, "src_weight", (ns,))
+    _dev(src_q, torch.float64, "src_q", (3, ns))
+    _dev(trg_xyz, torch.float64, "trg_xyz")
+    nt = ns if trg_xyz is None else trg_xyz.shape[1]
+    _dev(trg_self, torch.int64, "trg_self", (nt,))
+    if out is None:
+        out = (torch.zeros if accumulate else torch.empty)((3, nt), dtype=torch.float64,
+                                                           device=src_xyz.device)
+    _dev(out, torch.float64, "out", (3, nt))
+    if nt == 0:
+        return (out, Diag()) if diag else out
+    flags = (PREC_MIXED if mixed else PREC_FP64) | (0 if subtract else ONSURF_RAW)
+    flags |= ACCUMULATE if accumulate else 0
+    flags |= CHECK_INPUTS if check_inputs else 0
+    d = Diag() if diag else None
+    rc = _lib.stokes_dl_eval(ns, _ptr(src_xyz), _ptr(src_normal), _ptr(src_weight), _ptr(src_q),
+                             nt, _ptr(trg_xyz), _ptr(trg_self), float(near_r), flags, _ptr(out),
+                             _stream(stream), ctypes.byref(d) if d is not None else None)
+    _check(rc)
+    return (out, d) if diag else out
+
+
+def local_sbt(tangent, f, eps, mu=1.0, inverse=False, out=None, stream=None):
+    """Local slender-body operator M f (or M^{-1} f) at every node, (3, n) float64."""
+    tangent = _dev(tangent, torch.float64, "tangent")
+    n = tangent.shape[1]
+    _dev(f, torch.float64, "f", (3, n))
+    if out is None:
+        out = torch.empty_like(f)
+    _dev(out, torch.float64, "out", (3, n))
+    _check(_lib.stokes_local_sbt(n, _ptr(tangent), _ptr(f), float(eps), float(mu),
+                                 1 if inverse else 0, _ptr(out), _stream(stream)))
+    return out
+
+
+def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1.0, mixed=False,
+                   doublet=True, stream=None):
+    """GMRES mobility solve on device tensors; returns (f, residual, iterations)."""
+    xyz = _dev(xyz, torch.float64, "xyz")
+    n = xyz.shape[1]
+    _dev(tangent, torch.float64, "tangent", (3, n))
+    _dev(fiber_len, torch.float64, "fiber_len")
+    _dev(rhs, torch.float64, "rhs", (3, n))
+    n_fib = fiber_len.shape[0]
+    out = torch.empty_like(rhs)
+    res = ctypes.c_double(0.0)
+    it = ctypes.c_int32(0)
+    flags = (PREC_MIXED if mixed else PREC_FP64) | (0 if doublet else NO_DOUBLET)
+    _check(_lib.stokes_mobility_solve(n_fib, nodes_per_fib, _ptr(xyz), _ptr(tangent),
+                                      _ptr(fiber_len), _ptr(rhs), float(eps), float(mu),
+                                      int(iters), flags, _ptr(out), ctypes.byref(res),
+                                      ctypes.byref(it), _stream(stream)))
+    return out, res.value, it.value
+
+
+def profile_enable(on=True):
+    """Bracket every launch of the main pair-sum kernels with HIP events (on the call's stream)."""
+    _check(_lib.stokes_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(milliseconds, launches) of the main pair-sum kernels since the last read; resets."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(_lib.stokes_profile_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def release_workspace():
+    _check(_lib.stokes_release_workspace())
+
+
+def version() -> int:
+    return _lib.stokes_version()
+
+
+class Session:
+    """Continuous-batching mobility-solve session (host arrays in, host arrays out)."""
+
+    def __init__(self, hbm_budget_bytes=4 << 30, max_slots=64, max_queue=4096, mixed=False,
+                 doublet=True, device=0):
+        cfg = SessionCfg(int(hbm_budget_bytes), int(max_slots), int(max_queue),
+                         (PREC_MIXED if mixed else PREC_FP64) | (0 if doublet else NO_DOUBLET),
+                         int(device))
+        self._h = ctypes.c_void_p()
+        _check(_lib.stokes_session_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._shapes = {}
+
+    def submit(self, xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1.0, tag=0):
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xyz, tangent, fiber_len, rhs)]
+        n = arrs[0].shape[1]
+        req = SolveReq(int(arrs[2].shape[0]), int(nodes_per_fib),
+                       arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                       arrs[3].ctypes.data, float(eps), float(mu), int(iters), int(tag))
+        t = ctypes.c_uint64(0)
+        _check(_lib.stokes_session_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._shapes[t.value] = n
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        """Returns (f (3, N) numpy, stats dict); raises StokesError on failure."""
+        import numpy as np
+        n = self._shapes.get(ticket, 0)
+        out = np.empty((3, n), dtype=np.float64)
+        st = SolveStats()
+        rc = _lib.stokes_session_wait(self._h, ctypes.c_uint64(ticket),
+                                      out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
+                                      int(timeout_ms))
+        if rc != E_TIMEOUT:
+            self._shapes.pop(ticket, None)
+        _check(rc)
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+        return out, stats
+
+    def cancel(self, ticket):
+        _check(_lib.stokes_session_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, None
+            _check(_lib.stokes_session_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every entry point the header declares.
+
+CPU only: loading libstokes.so does not touch a GPU, and argument validation
+returns before any device call, so the status contract is checked here too.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stokes.h")
+LIB = os.path.join(ROOT, "paper_1602_05650_amd", "libstokes.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(stokes_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_required_entry_points():
+    names = declared()
+    for req in ["stokes_sl_eval", "stokes_dl_eval", "stokes_session_submit", "stokes_session_create",
+                "stokes_session_wait", "stokes_session_cancel", "stokes_session_destroy",
+                "stokes_status_string", "stokes_local_sbt", "stokes_mobility_solve"]:
+        assert req in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first (__graft_entry__.build())"
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_status_strings_and_validation_without_gpu():
+    from paper_1602_05650_amd import stokes as S
+    assert S.status_string(S.OK) == "STOKES_OK"
+    assert S.status_string(S.E_NONFINITE) == "STOKES_E_NONFINITE"
+    assert S.status_string(99) == "STOKES_E_UNKNOWN"
+    L = S._lib
+    # n_src < 0
+    assert L.stokes_sl_eval(-1, None, None, None, None, 0, None, 0, None, None, None,
+                            1.0, 0.01, 0.0, 0, None, None, None) == S.E_INVAL
+    assert "n_src" in S.last_error()
+    # eps outside (0, 0.5)
+    assert L.stokes_sl_eval(0, None, None, None, None, 0, None, 0, None, None, None,
+                            1.0, 0.7, 0.0, 0, None, None, None) == S.E_INVAL
+    # mu <= 0
+    assert L.stokes_sl_eval(0, None, None, None, None, 0, None, 0, None, None, None,
+                            0.0, 0.01, 0.0, 0, None, None, None) == S.E_INVAL
+    # both exclusion modes
+    assert L.stokes_sl_eval(0, None, None, None, None, 0, None, 0, None, None, None, 1.0, 0.01,
+                            0.0, S.EXCL_SELF_POINT | S.EXCL_SAME_FIBER, None, None, None) == S.E_INVAL
+    # unknown flag bits
+    assert L.stokes_dl_eval(0, None, None, None, None, 0, None, None, 0.0, 1 << 20, None, None,
+                            None) == S.E_INVAL
+    # null arrays with n > 0
+    assert L.stokes_dl_eval(4, None, None, None, None, 0, None, None, 0.0, 0, None, None,
+                            None) == S.E_INVAL
+    # empty problems are fine and touch nothing
+    assert L.stokes_sl_eval(0, None, None, None, None, 0, None, 0, ctypes.c_void_p(8), None, None,
+                            1.0, 0.01, 0.0, 0, None, None, None) == S.OK
+    assert L.stokes_local_sbt(0, None, None, 0.01, 1.0, 0, None, None) == S.OK
+    assert L.stokes_local_sbt(3, None, None, 0.01, 1.0, 0, None, None) == S.E_INVAL
+    assert L.stokes_mobility_solve(1, 1, None, None, None, None, 0.01, 1.0, 5, 0, None, None,
+                                   None, None) == S.E_INVAL
+    assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0, 0, None, None,
+                                   None, None) == S.E_INVAL
+    assert L.stokes_session_create(None, None) == S.E_INVAL
+    assert L.stokes_session_destroy(None) == S.E_INVAL
+
+
+def test_version():
+    from paper_1602_05650_amd import stokes as S
+    assert S.version() >= 10000

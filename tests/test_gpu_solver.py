@@ -1,0 +1,172 @@
+"""GPU mobility solve (device GMRES) and the serving session against the oracle."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1602_05650_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05650_amd import stokes
+    return stokes
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _oracle_solve(oracle_mod, req, iters=None):
+    fs = req["fibers"]
+    x, hist, m = oracle_mod.mobility_solve(req["rhs"], fs.xyz, fs.tangent, fs.fiber, fs.length,
+                                           fs.nodes_per_fiber, fs.eps, iters or req["iters"])
+    return x, hist, m
+
+
+@pytest.mark.parametrize("n_fib,nodes,iters", [(8, 16, 12), (40, 32, 25), (3, 64, 30), (1, 7, 5)])
+def test_mobility_solve_fp64_vs_oracle(S, oracle_mod, n_fib, nodes, iters):
+    req = W.serving_request(9, n_fib * 100 + nodes, n_fib=n_fib, nodes=nodes, iters=iters)
+    fs = req["fibers"]
+    ref, hist, m = _oracle_solve(oracle_mod, req)
+    f, res, it = S.mobility_solve(dev(fs.xyz), dev(fs.tangent), dev(fs.length), dev(req["rhs"]),
+                                  fs.nodes_per_fiber, fs.eps, iters)
+    f = f.cpu().numpy()
+    assert it == m
+    assert rel(f, ref) <= 1e-10
+    assert abs(res - hist[-1]) <= 1e-8 * hist[0] + 1e-6 * hist[-1]
+
+
+def test_mobility_solve_mixed(S, oracle_mod):
+    req = W.serving_request(9, 7, n_fib=60, nodes=32, iters=30)
+    fs = req["fibers"]
+    ref, hist, m = _oracle_solve(oracle_mod, req)
+    f, res, it = S.mobility_solve(dev(fs.xyz), dev(fs.tangent), dev(fs.length), dev(req["rhs"]),
+                                  fs.nodes_per_fiber, fs.eps, 30, mixed=True)
+    err = rel(f.cpu().numpy(), ref)
+    print(f"mixed mobility solve rel err {err:.3e}")
+    assert err <= 1e-5
+
+
+def _submit(sess, req):
+    fs = req["fibers"]
+    return sess.submit(fs.xyz, fs.tangent, fs.length, req["rhs"], fs.nodes_per_fiber, fs.eps,
+                       req["iters"], tag=req["rid"])
+
+
+def test_session_matches_oracle_and_alone_equals_mix(S, oracle_mod):
+    reqs = [W.serving_request(3, rid, n_fib=n, nodes=p, iters=k)
+            for rid, (n, p, k) in enumerate([(32, 16, 20), (50, 32, 24), (33, 64, 21), (90, 16, 35),
+                                             (40, 32, 22), (64, 16, 28)])]
+    alone = []
+    with S.Session(hbm_budget_bytes=1 << 30, max_slots=1) as s1:
+        for r in reqs:
+            alone.append(s1.wait(_submit(s1, r))[0])
+    with S.Session(hbm_budget_bytes=1 << 30, max_slots=8) as s8:
+        tickets = [_submit(s8, r) for r in reqs]
+        mixed = [s8.wait(t) for t in tickets]
+    for r, a, (m, st) in zip(reqs, alone, mixed):
+        assert np.array_equal(a, m), f"request {r['rid']} differs alone vs in the mix"
+        assert st["status"] == 0 and st["iters"] == r["iters"] and st["tag"] == r["rid"]
+        assert st["t_submit_ns"] <= st["t_admit_ns"] <= st["t_finish_ns"]
+    for r, a in zip(reqs[:3], alone[:3]):
+        ref, _, _ = _oracle_solve(oracle_mod, r)
+        assert rel(a, ref) <= 1e-10
+    # one-shot solve uses the same kernels and partition: bitwise the same
+    r = reqs[1]
+    fs = r["fibers"]
+    f, _, _ = S.mobility_solve(dev(fs.xyz), dev(fs.tangent), dev(fs.length), dev(r["rhs"]),
+                               fs.nodes_per_fiber, fs.eps, r["iters"])
+    assert np.array_equal(f.cpu().numpy(), alone[1])
+
+
+def test_session_mixed_alone_equals_mix(S):
+    reqs = [W.serving_request(4, rid, n_fib=n, nodes=p, iters=k)
+            for rid, (n, p, k) in enumerate([(40, 32, 20), (70, 16, 25), (33, 64, 22)])]
+    with S.Session(hbm_budget_bytes=1 << 30, max_slots=1, mixed=True) as s1:
+        alone = [s1.wait(_submit(s1, r))[0] for r in reqs]
+    with S.Session(hbm_budget_bytes=1 << 30, max_slots=4, mixed=True) as s4:
+        ts = [_submit(s4, r) for r in reqs]
+        mix = [s4.wait(t)[0] for t in ts]
+    for a, m in zip(alone, mix):
+        assert np.array_equal(a, m)
+
+
+def test_session_budget_binds_and_errors(S):
+    reqs = [W.serving_request(5, rid, n_fib=n, nodes=32, iters=20)
+            for rid, n in enumerate([100, 120, 80, 110])]
+    from paper_1602_05650_amd import stokes as SS
+    # budget just above the largest request: requests run one after another
+    biggest = max(r["fibers"].n for r in reqs)
+    with S.Session(hbm_budget_bytes=64 << 20, max_slots=8) as s:
+        ts = [_submit(s, r) for r in reqs]
+        stats = [s.wait(t)[1] for t in ts]
+        assert all(st["status"] == 0 for st in stats)
+    # over budget: refused at submit
+    with S.Session(hbm_budget_bytes=1 << 20, max_slots=2) as s:
+        with pytest.raises(SS.StokesError) as ei:
+            _submit(s, reqs[0])
+        assert ei.value.code == SS.E_NOMEM
+    assert biggest > 0
+
+
+def test_session_cancel_and_destroy_with_pending(S):
+    from paper_1602_05650_amd import stokes as SS
+    big = W.serving_request(6, 0, n_fib=1500, nodes=32, iters=60)
+    small = W.serving_request(6, 1, n_fib=20, nodes=16, iters=10)
+    s = S.Session(hbm_budget_bytes=2 << 30, max_slots=1)
+    t_big = _submit(s, big)
+    t_small = _submit(s, small)        # queued behind the big one (one slot)
+    s.cancel(t_small)
+    with pytest.raises(SS.StokesError) as ei:
+        s.wait(t_small)
+    assert ei.value.code == SS.E_CANCELED
+    s.cancel(t_big)
+    with pytest.raises(SS.StokesError) as ei:
+        s.wait(t_big)
+    assert ei.value.code == SS.E_CANCELED
+    # destroy while a request is pending: a waiting thread gets E_CANCELED
+    t3 = _submit(s, big)
+    box = {}
+
+    def waiter():
+        try:
+            s.wait(t3)
+            box["rc"] = 0
+        except SS.StokesError as e:
+            box["rc"] = e.code
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    time.sleep(0.05)
+    s.close()
+    th.join(timeout=60)
+    assert box.get("rc") in (SS.E_CANCELED, 0)
+    # unknown ticket
+    with S.Session(hbm_budget_bytes=1 << 24, max_slots=1) as s2:
+        with pytest.raises(SS.StokesError) as ei:
+            s2.wait(12345)
+        assert ei.value.code == SS.E_NOTFOUND
+
+
+def test_session_timeout(S):
+    from paper_1602_05650_amd import stokes as SS
+    big = W.serving_request(7, 0, n_fib=2000, nodes=64, iters=60)
+    with S.Session(hbm_budget_bytes=4 << 30, max_slots=1) as s:
+        t = _submit(s, big)
+        with pytest.raises(SS.StokesError) as ei:
+            s.wait(t, timeout_ms=1)
+        assert ei.value.code == SS.E_TIMEOUT
+        f, st = s.wait(t)
+        assert st["status"] == 0 and np.all(np.isfinite(f))
