@@ -29,10 +29,30 @@ import numpy as np
 
 METRIC = "Gpair-interactions/s and %VALU peak (mixed vs FP64); p50/p99 solve latency"
 FLOPS_PER_PAIR_SL = 34       # Stokeslet + doublet, counted (add/sub/mul 1, FMA 2, rsqrt 1)
-PEAK_FP32_NONPACKED = 78.6   # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz (no packed FP32)
-PEAK_FP32_PUBLISHED = 157.3  # TFLOP/s: published FP32 vector peak (needs packed FP32)
+PEAK_FP32 = 157.3            # TFLOP/s: published FP32 vector peak, 256 CU x 128 lanes x 2 x 2.4 GHz
 PEAK_FP64 = 78.6             # TFLOP/s: published FP64 vector peak
-NEAR_R = 0.06                # mixed path: pairs closer than this (or 2 fiber radii) go FP64
+NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go FP64
+
+# HBM traffic of one sl_mixed_kernel launch on this workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by the
+# factors that make a 256 MiB elementwise copy in the same run read and write
+# 256 MiB (FETCH x 1.99981, WRITE x 0.999998); see
+# profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
+# sources with this digest: after any change the field reports null.
+TRAFFIC = {"digest": "e66b77938a5be82a", "bytes": 407746252}
+KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
+                  "paper_1602_05650_amd/csrc/stokes_sums.hip",
+                  "paper_1602_05650_amd/csrc/stokes_internal.hpp"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -44,7 +64,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--only", choices=["mixed", "fp64", "both", "none"], default="both")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one elementwise copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -139,7 +161,7 @@ def cpu_baseline(c, seconds, log_fn):
     fs = c["fibers"]
     nthreads = max(1, min(16, os.cpu_count() or 1))
     from paper_1602_05650_amd import workloads as W
-    idx = W.subsample(2, fs.n, 4096)
+    idx = W.subsample(2, fs.n, 65536)
     kw = dict(src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps, excl=1, nthreads=nthreads)
     t0 = time.perf_counter()
     oracle.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx[:32]], trg_self=idx[:32], **kw)
@@ -168,6 +190,9 @@ def main():
     from paper_1602_05650_amd import stokes as S
     from paper_1602_05650_amd import workloads as W
 
+    if args.only == "none":          # serving run alone (for profiling it)
+        print(json.dumps({"serving": serving_run(S, args.serving_requests, log)}), flush=True)
+        return
     t_gen = time.perf_counter()
     c = W.config2()
     fs = c["fibers"]
@@ -182,6 +207,13 @@ def main():
     flen = torch.from_numpy(fs.length).to(dev)
     forces = [torch.from_numpy(f).to(dev) for f in forces_h]
     torch.cuda.synchronize()
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)          # reads and writes exactly MIB MiB each
+        torch.cuda.synchronize()
+        del src, dst
     log(f"spindle workload: {n} points, {fs.n_fib} fibers, generated in "
         f"{time.perf_counter() - t_gen:.1f} s")
     pairs = n * (n - 1)
@@ -200,7 +232,7 @@ def main():
     value = args.steps * pairs / r["sec"] / 1e9
     k_avg = r["kms"] / max(r["launches"], 1) * 1e-3
     achieved = pairs * FLOPS_PER_PAIR_SL / k_avg / 1e12
-    peak = PEAK_FP32_NONPACKED if head else PEAK_FP64
+    peak = PEAK_FP32 if head else PEAK_FP64
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -228,12 +260,13 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": (TRAFFIC["bytes"] if head and kernel_digest() == TRAFFIC["digest"]
+                        else None),
             "kernel": "sl_mixed_kernel" if head else "sl_fp64_kernel",
             "flops_per_pair": FLOPS_PER_PAIR_SL,
             "kernel_ms": round(k_avg * 1e3, 4),
-            "frac_of_published_fp32_packed_peak": round(achieved / PEAK_FP32_PUBLISHED, 4)
-            if head else None,
+            "peak_basis": "published vector peak of the kernel's precision (FP32 for the mixed "
+                          "kernel: 256 CUs x 128 FP32 lanes x 2 flops x 2.4 GHz)",
         },
     }
     if True in res and False in res:

@@ -57,6 +57,17 @@ struct Carve {
 constexpr int TILE = 32;      // sources per tile (one 32-node fiber in the benchmark geometries)
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;    // 4 waves per block
+// Targets per lane (register blocking) of each pair kernel, and the number of
+// blocks a launch aims for (many small work items keep all 256 CUs busy to
+// the end; measured on gfx950: R = 1 with ~32k blocks is fastest for both
+// precisions, because occupancy matters more here than reuse of the SGPR
+// source operands).
+constexpr int R_SL64 = 1, R_SL32 = 1, R_DL64 = 1, R_DL32 = 1;
+constexpr int64_t TARGET_BLOCKS = 32768;
+// Serving slots share the GPU with other requests, so each uses fewer chunks
+// (less partial-sum memory per request).
+constexpr int64_t TARGET_BLOCKS_SLOT = 4096;
+constexpr int MIN_TILES_PER_CHUNK = 8;
 
 // A tile of TILE consecutive sources with its bounding sphere.
 struct __align__(16) Tile {
@@ -85,7 +96,7 @@ struct Partition {
     int32_t n_chunks;
     int32_t n_tblocks;
 };
-Partition make_partition(int64_t n_t, int64_t n_s, int R);
+Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks = TARGET_BLOCKS);
 
 // ---- launch entry points used by the solver and the session ---------------
 struct SLProblem {

@@ -200,9 +200,9 @@ __global__ __launch_bounds__(BLOCK) void k_sl(const SlotDesc* D, const StepTable
         const int tb = local % d.sl.n_tblocks;
         const int chunk = local / d.sl.n_tblocks;
         if (MIXED)
-            sl_mixed_wave<2, DOUBLET>(d.sl, tb, chunk);
+            sl_mixed_wave<R_SL32, DOUBLET>(d.sl, tb, chunk);
         else
-            sl_fp64_wave<2, DOUBLET>(d.sl, tb, chunk);
+            sl_fp64_wave<R_SL64, DOUBLET>(d.sl, tb, chunk);
     }
 }
 
@@ -376,7 +376,7 @@ static int32_t dot_blocks(int64_t n) {
 SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed) {
     SlotPlan sp{};
     const int64_t N = (int64_t)n_fib * npf;
-    sp.P = make_partition(N, N, 2);
+    sp.P = make_partition(N, N, mixed ? R_SL32 : R_SL64, TARGET_BLOCKS_SLOT);
     sp.B = dot_blocks(3 * N);
     const int64_t n = 3 * N;
     size_t b = 0;

@@ -201,10 +201,8 @@ __global__ void check_fiber_kernel(const int32_t* __restrict__ fib, int64_t n, i
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-constexpr int R_SL64 = 2, R_SL32 = 2, R_DL64 = 2, R_DL32 = 2;
-constexpr int64_t TARGET_BLOCKS = 2048;
 
-Partition make_partition(int64_t n_t, int64_t n_s, int R) {
+Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks) {
     Partition p{};
     p.R = R;
     p.n_t = n_t;
@@ -216,8 +214,8 @@ Partition make_partition(int64_t n_t, int64_t n_s, int R) {
         p.n_chunks = 0;
         return p;
     }
-    int64_t ch = (TARGET_BLOCKS + p.n_tblocks - 1) / p.n_tblocks;
-    ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / 4));
+    int64_t ch = (target_blocks + p.n_tblocks - 1) / p.n_tblocks;
+    ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / MIN_TILES_PER_CHUNK));
     ch = std::max<int64_t>(1, std::min<int64_t>(ch, p.n_tiles));
     p.tiles_per_chunk = (int32_t)((p.n_tiles + ch - 1) / ch);
     p.n_chunks = (p.n_tiles + p.tiles_per_chunk - 1) / p.tiles_per_chunk;

@@ -4,6 +4,21 @@
 
 #include "stokes_internal.hpp"
 
+// Unroll depth of the branch-free source loops (tuned on gfx950; overridable
+// at compile time for experiments).
+#ifndef STOKES_UNROLL_SL64
+#define STOKES_UNROLL_SL64 4
+#endif
+#ifndef STOKES_UNROLL_SL32
+#define STOKES_UNROLL_SL32 2
+#endif
+#ifndef STOKES_UNROLL_DL64
+#define STOKES_UNROLL_DL64 2
+#endif
+#ifndef STOKES_UNROLL_DL32
+#define STOKES_UNROLL_DL32 4
+#endif
+
 namespace stokes {
 
 constexpr double PI_D = 3.14159265358979323846264338327950288;
@@ -176,7 +191,7 @@ __device__ __forceinline__ void sl_fp64_wave(const SumArgs& a, int tb, int chunk
             need |= (lo[r] < T.j1) & (hi[r] > T.j0);
         }
         if (__ballot(need) == 0) {
-#pragma unroll 4
+#pragma unroll STOKES_UNROLL_SL64
             for (int j = T.j0; j < T.j1; ++j) {
                 const SrcSL64 s = src[j];
 #pragma unroll
@@ -259,7 +274,7 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
             px[r] = py[r] = pz[r] = 0.0f;
         }
         if (__ballot(need) == 0) {
-#pragma unroll 4
+#pragma unroll STOKES_UNROLL_SL32
             for (int j = T.j0; j < T.j1; ++j) {
                 const SrcSL32 s = src[j];
 #pragma unroll
@@ -372,7 +387,7 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
             need |= (lo[r] < T.j1) & (hi[r] > T.j0);
         }
         if (__ballot(need) == 0) {
-#pragma unroll 2
+#pragma unroll STOKES_UNROLL_DL64
             for (int j = T.j0; j < T.j1; ++j) {
                 const SrcDL64 s = src[j];
 #pragma unroll
@@ -466,7 +481,7 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
             px[r] = py[r] = pz[r] = 0.0f;
         }
         if (__ballot(need) == 0) {
-#pragma unroll 4
+#pragma unroll STOKES_UNROLL_DL32
             for (int j = T.j0; j < T.j1; ++j) {
                 const SrcDL32 s = src[j];
 #pragma unroll
