@@ -36,10 +36,10 @@ NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go 
 # HBM traffic of one sl_mixed_kernel launch on this workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by the
 # factors that make a 256 MiB elementwise copy in the same run read and write
-# 256 MiB (FETCH x 1.99981, WRITE x 0.999998); see
+# 256 MiB (FETCH x 1.99978, WRITE x 1.0); see
 # profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
 # sources with this digest: after any change the field reports null.
-TRAFFIC = {"digest": "e66b77938a5be82a", "bytes": 407746252}
+TRAFFIC = {"digest": "ca2b0c3334cef4dc", "bytes": 407744754}
 KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
                   "paper_1602_05650_amd/csrc/stokes_sums.hip",
                   "paper_1602_05650_amd/csrc/stokes_internal.hpp"]
@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--only", choices=["mixed", "fp64", "both", "none"], default="both")
+    ap.add_argument("--extra", default="c0,c1,c4",
+                    help="other workloads timed after the headline (c0,c1,c4 or none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one elementwise copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -96,6 +98,58 @@ def time_matvecs(S, torch, xyz, forces, fib, flen, eps, mixed, steps, warmup):
     return t1 - t0, ms, launches, first
 
 
+def config_run(S, torch, name, steps, warmup, log_fn):
+    """One step = single layer (+ double layer when the config has a sphere) to all targets.
+    Returns Gpair/s and ms per step for both precisions and the mixed-vs-FP64 error."""
+    from paper_1602_05650_amd import workloads as W
+    c = {"c0": W.config0, "c1": W.config1, "c4": W.config4}[name]()
+    fs = c["fibers"]
+    dev = torch.device("cuda:0")
+    d = lambda a, t=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, t)
+    sph = c.get("sphere")
+    if sph is not None:
+        trg = np.concatenate([fs.xyz, sph.xyz], axis=1)
+        sl_self = np.concatenate([np.arange(fs.n), -np.ones(sph.n, dtype=np.int64)])
+        dl_self = np.concatenate([-np.ones(fs.n, dtype=np.int64), np.arange(sph.n)])
+        n_t = trg.shape[1]
+        pairs_sl, pairs_dl = n_t * fs.n - fs.n, n_t * sph.n - sph.n
+        T, SS, DS = d(trg), d(sl_self, torch.int64), d(dl_self, torch.int64)
+        sx, sn, sw, sq = d(sph.xyz), d(sph.normal), d(sph.weight), d(c["q"])
+    else:
+        n_t, pairs_sl, pairs_dl = fs.n, fs.n * (fs.n - 1), 0
+    X, F, FB, FL = d(fs.xyz), d(c["force"]), d(fs.fiber, torch.int32), d(fs.length)
+    out = torch.empty((3, n_t), dtype=torch.float64, device=dev)
+
+    def step(mixed):
+        if sph is not None:
+            S.sl_eval(X, F, src_fiber=FB, fiber_len=FL, eps=fs.eps, trg_xyz=T, trg_self=SS,
+                      mixed=mixed, out=out)
+            S.dl_eval(sx, sn, sw, sq, trg_xyz=T, trg_self=DS, mixed=mixed, accumulate=True,
+                      out=out)
+        else:
+            S.sl_eval(X, F, src_fiber=FB, fiber_len=FL, eps=fs.eps, mixed=mixed, out=out)
+
+    res = {"targets": n_t, "pairs_per_step": pairs_sl + pairs_dl}
+    u = {}
+    for mixed in (True, False):
+        for _ in range(warmup):
+            step(mixed)
+        torch.cuda.synchronize()
+        u[mixed] = out.cpu().numpy()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(mixed)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        tag = "mixed" if mixed else "fp64"
+        res[tag] = {"ms_per_step": round(dt * 1e3, 4),
+                    "gpair_per_s": round((pairs_sl + pairs_dl) / dt / 1e9, 1)}
+    res["err_mixed_vs_fp64_relmax"] = float(
+        f"{np.abs(u[True] - u[False]).max() / np.abs(u[False]).max():.3e}")
+    log_fn(f"{name}: {res}")
+    return res
+
+
 def serving_run(S, n_req, log_fn):
     from paper_1602_05650_amd import workloads as W
     reqs = [W.serving_request(3, rid) for rid in range(n_req)]
@@ -108,13 +162,17 @@ def serving_run(S, n_req, log_fn):
                            r["iters"], tag=r["rid"])
 
     with S.Session(hbm_budget_bytes=4 << 30, max_slots=64, mixed=True) as sess:
-        # calibration: saturate with the first 24 requests, measure capacity (requests/s)
-        n_cal = min(24, n_req)
+        # warm-up (arena, graph capture), then calibration: a burst of 48 requests drawn
+        # like the stream (other ids) saturates the session; capacity = requests/s
+        for t in [submit(sess, W.serving_request(3, 20000 + i, n_fib=32, iters=20))
+                  for i in range(4)]:
+            sess.wait(t)
+        cal = [W.serving_request(3, 10000 + i) for i in range(48)]
         t0 = time.perf_counter()
-        ts = [submit(sess, r) for r in reqs[:n_cal]]
+        ts = [submit(sess, r) for r in cal]
         for t in ts:
             sess.wait(t)
-        cap = n_cal / (time.perf_counter() - t0)
+        cap = len(cal) / (time.perf_counter() - t0)
         rate = 0.7 * cap
         arrivals = W.serving_stream(3, n_req, rate)
         log_fn(f"serving: capacity {cap:.1f} req/s (calibration), Poisson rate {rate:.1f} req/s")
@@ -283,6 +341,11 @@ def main():
         }
         out["mixed_over_fp64"] = round(f64["sec"] / res[True]["sec"], 3)
         out["err_mixed_vs_fp64_relmax"] = float(f"{np.abs(u32 - u64).max() / np.abs(u64).max():.3e}")
+    extra = [e for e in args.extra.split(",") if e in ("c0", "c1", "c4")]
+    if extra and args.only == "both":
+        out["other_workloads"] = {
+            {"c0": "cloud_512", "c1": "confined_32k", "c4": "confined_524k"}[e]:
+            config_run(S, torch, e, 200 if e == "c0" else 10, 3, log) for e in extra}
     if not args.no_serving:
         try:
             out["serving"] = serving_run(S, args.serving_requests, log)

@@ -22,11 +22,11 @@ constexpr int G_ELEM = 512;   // grid of the elementwise kernels in graph mode
 constexpr int G_SL = 2048;    // grid of the single-layer kernel in graph mode
 constexpr int G_ONE = MAX_SLOTS;
 
-__device__ __forceinline__ int find_slot(const WorkList& wl, int64_t item) {
-    int lo = 0, hi = wl.n - 1;
+__device__ __forceinline__ int find_slot(cptr<WorkList> wl, int64_t item) {
+    int lo = 0, hi = wl->n - 1;
     while (lo < hi) {   // largest s with prefix[s] <= item
         const int mid = (lo + hi + 1) >> 1;
-        if (wl.prefix[mid] <= item) lo = mid; else hi = mid - 1;
+        if (wl->prefix[mid] <= item) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -94,12 +94,12 @@ __device__ void dot_partials(const double* A, int64_t stride, int m, const doubl
 
 // ---- set-up kernels (eager, at admission) ------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_geom(const SlotDesc* D, const StepTables* T) {
-    const WorkList& wl = T->wl[WL_PRE];
-    const int64_t total = wl.prefix[wl.n];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
+    const int64_t total = wl->prefix[wl->n];
     for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int64_t i = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (i < d.N) {
             const int f = (int)(i / d.npf);
             const int kk = (int)(i % d.npf);
@@ -112,11 +112,11 @@ __global__ __launch_bounds__(BLOCK) void k_geom(const SlotDesc* D, const StepTab
 
 // Bounding spheres of the source tiles (after k_geom: reads the fiber ids).
 __global__ __launch_bounds__(BLOCK) void k_tiles(const SlotDesc* D, const StepTables* T) {
-    const WorkList& wl = T->wl[WL_PRE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int64_t t = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int64_t t = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (t < d.sl.n_tiles)
             tile_prep_one((int)t, d.N, d.xyz, d.near_r, d.sl.s32 ? 2.0 * d.eps : 0.0, d.fib,
                           d.n_fib, d.flen, d.tiles);
@@ -126,21 +126,21 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const SlotDesc* D, const StepTa
 // beta = |rhs| partials (WL_DOT), then beta and v_0 (WL_ONE, WL_VEC).
 __global__ __launch_bounds__(BLOCK) void k_init_norm(const SlotDesc* D, const StepTables* T) {
     __shared__ double lds[BLOCK];
-    const WorkList& wl = T->wl[WL_DOT];
-    const int64_t total = wl.prefix[wl.n];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_DOT];
+    const int64_t total = wl->prefix[wl->n];
     for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        dot_partials(d.rhs, 0, 1, d.rhs, 3 * (int64_t)d.N, d.B, (int)(it - wl.prefix[si]), d.normp,
+        const auto& d = as_const(D)[wl->slot[si]];
+        dot_partials(d.rhs, 0, 1, d.rhs, 3 * (int64_t)d.N, d.B, (int)(it - wl->prefix[si]), d.normp,
                      lds);
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_init_beta(const SlotDesc* D, const StepTables* T,
                                                      double* stat) {
-    const WorkList& wl = T->wl[WL_ONE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
-        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
+        const auto& d = as_const(D)[wl->slot[find_slot(wl, it)]];
         if (threadIdx.x == 0) {
             double s = 0.0;
             for (int b = 0; b < d.B; ++b) s += d.normp[b];
@@ -157,11 +157,11 @@ __global__ __launch_bounds__(BLOCK) void k_init_beta(const SlotDesc* D, const St
 }
 
 __global__ __launch_bounds__(BLOCK) void k_init_v0(const SlotDesc* D, const StepTables* T) {
-    const WorkList& wl = T->wl[WL_VEC];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_VEC];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int64_t e = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int64_t e = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (e < 3 * (int64_t)d.N) {
             const double beta = d.g[0];
             d.V[e] = beta > 0.0 ? d.rhs[e] / beta : 0.0;
@@ -172,11 +172,11 @@ __global__ __launch_bounds__(BLOCK) void k_init_v0(const SlotDesc* D, const Step
 // ---- step kernels ------------------------------------------------------------------
 // z = M^{-1} v_j and the packed single-layer sources s = pref * wq * z.
 __global__ __launch_bounds__(BLOCK) void k_pre(const SlotDesc* D, const StepTables* T, int doublet) {
-    const WorkList& wl = T->wl[WL_PRE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int64_t i = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (i >= d.N) continue;
         const int64_t N = d.N;
         const double* v = d.V + (int64_t)d.j * 3 * N;
@@ -192,27 +192,35 @@ __global__ __launch_bounds__(BLOCK) void k_pre(const SlotDesc* D, const StepTabl
 
 template <bool MIXED, bool DOUBLET>
 __global__ __launch_bounds__(BLOCK) void k_sl(const SlotDesc* D, const StepTables* T) {
-    const WorkList& wl = T->wl[WL_SL];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_SL];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int local = (int)(it - wl.prefix[si]);
-        const int tb = local % d.sl.n_tblocks;
-        const int chunk = local / d.sl.n_tblocks;
+        // copy the slot's sum arguments into registers with scalar loads
+        SumArgs a;
+        {
+            static_assert(sizeof(SumArgs) % 8 == 0, "SumArgs is copied in 8-byte words");
+            const cptr<uint64_t> w = (cptr<uint64_t>)&as_const(D)[wl->slot[si]].sl;
+            uint64_t* o = reinterpret_cast<uint64_t*>(&a);
+#pragma unroll
+            for (int q = 0; q < (int)(sizeof(SumArgs) / 8); ++q) o[q] = w[q];
+        }
+        const int local = (int)(it - wl->prefix[si]);
+        const int tb = local % a.n_tblocks;
+        const int chunk = local / a.n_tblocks;
         if (MIXED)
-            sl_mixed_wave<R_SL32, DOUBLET>(d.sl, tb, chunk);
+            sl_mixed_wave<R_SL32, DOUBLET>(a, tb, chunk);
         else
-            sl_fp64_wave<R_SL64, DOUBLET>(d.sl, tb, chunk);
+            sl_fp64_wave<R_SL64, DOUBLET>(a, tb, chunk);
     }
 }
 
 // w = M z + (sum of the chunk partials, in chunk order).
 __global__ __launch_bounds__(BLOCK) void k_red(const SlotDesc* D, const StepTables* T) {
-    const WorkList& wl = T->wl[WL_PRE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int64_t i = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (i >= d.N) continue;
         const int64_t N = d.N;
         double u[3] = {0.0, 0.0, 0.0};
@@ -235,11 +243,11 @@ __global__ __launch_bounds__(BLOCK) void k_red(const SlotDesc* D, const StepTabl
 // which = 2: partials of w.w (norm).
 __global__ __launch_bounds__(BLOCK) void k_dot(const SlotDesc* D, const StepTables* T, int which) {
     __shared__ double lds[BLOCK];
-    const WorkList& wl = T->wl[WL_DOT];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_DOT];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int b = (int)(it - wl.prefix[si]);
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int b = (int)(it - wl->prefix[si]);
         const int64_t n = 3 * (int64_t)d.N;
         if (which == 2)
             dot_partials(d.w, 0, 1, d.w, n, d.B, b, d.normp, lds);
@@ -250,9 +258,9 @@ __global__ __launch_bounds__(BLOCK) void k_dot(const SlotDesc* D, const StepTabl
 
 // h = (sum over blocks of the partials), in block order.  which: 0 -> hA, 1 -> hB.
 __global__ __launch_bounds__(BLOCK) void k_dred(const SlotDesc* D, const StepTables* T, int which) {
-    const WorkList& wl = T->wl[WL_ONE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
-        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
+        const auto& d = as_const(D)[wl->slot[find_slot(wl, it)]];
         double* h = which ? d.hB : d.hA;
         for (int i = threadIdx.x; i <= d.j; i += BLOCK) {
             double s = 0.0;
@@ -264,12 +272,12 @@ __global__ __launch_bounds__(BLOCK) void k_dred(const SlotDesc* D, const StepTab
 
 // w -= sum_i V[i] h[i]  (i ascending), h = hA or hB.
 __global__ __launch_bounds__(BLOCK) void k_axpy(const SlotDesc* D, const StepTables* T, int which) {
-    const WorkList& wl = T->wl[WL_VEC];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_VEC];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
+        const auto& d = as_const(D)[wl->slot[si]];
         const int64_t n = 3 * (int64_t)d.N;
-        const int64_t e = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const int64_t e = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (e >= n) continue;
         const double* h = which ? d.hB : d.hA;
         double acc = 0.0;
@@ -281,9 +289,9 @@ __global__ __launch_bounds__(BLOCK) void k_axpy(const SlotDesc* D, const StepTab
 // Hessenberg column j, previous rotations, new rotation, residual |g_{j+1}|.
 __global__ __launch_bounds__(BLOCK) void k_givens(const SlotDesc* D, const StepTables* T,
                                                   double* stat) {
-    const WorkList& wl = T->wl[WL_ONE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
-        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
+        const auto& d = as_const(D)[wl->slot[find_slot(wl, it)]];
         if (threadIdx.x != 0) continue;
         const int j = d.j;
         double s = 0.0;
@@ -314,12 +322,12 @@ __global__ __launch_bounds__(BLOCK) void k_givens(const SlotDesc* D, const StepT
 // v_{j+1} = w / h_{j+1,j}
 __global__ __launch_bounds__(BLOCK) void k_scale(const SlotDesc* D, const StepTables* T,
                                                  const double* stat) {
-    const WorkList& wl = T->wl[WL_VEC];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_VEC];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
+        const auto& d = as_const(D)[wl->slot[si]];
         const int64_t n = 3 * (int64_t)d.N;
-        const int64_t e = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const int64_t e = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (e >= n) continue;
         const double hn = stat[NSTAT * d.sid];
         d.V[(int64_t)(d.j + 1) * n + e] = hn > 0.0 ? d.w[e] / hn : 0.0;
@@ -329,9 +337,9 @@ __global__ __launch_bounds__(BLOCK) void k_scale(const SlotDesc* D, const StepTa
 // ---- finalisation ----------------------------------------------------------------
 // Back substitution R y = g over the m = d.j iterations done.
 __global__ __launch_bounds__(BLOCK) void k_backsub(const SlotDesc* D, const StepTables* T) {
-    const WorkList& wl = T->wl[WL_ONE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
-        const SlotDesc& d = D[wl.slot[find_slot(wl, it)]];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
+        const auto& d = as_const(D)[wl->slot[find_slot(wl, it)]];
         if (threadIdx.x != 0) continue;
         const int m = d.j;
         const int ld = d.k + 1;
@@ -345,11 +353,11 @@ __global__ __launch_bounds__(BLOCK) void k_backsub(const SlotDesc* D, const Step
 
 // x = M^{-1} (V_m y) at every node.
 __global__ __launch_bounds__(BLOCK) void k_solution(const SlotDesc* D, const StepTables* T) {
-    const WorkList& wl = T->wl[WL_PRE];
-    for (int64_t it = blockIdx.x; it < wl.prefix[wl.n]; it += gridDim.x) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
-        const SlotDesc& d = D[wl.slot[si]];
-        const int64_t i = (it - wl.prefix[si]) * BLOCK + threadIdx.x;
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int64_t i = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (i >= d.N) continue;
         const int64_t N = d.N, n = 3 * N;
         double v[3] = {0.0, 0.0, 0.0};

@@ -21,6 +21,24 @@
 
 namespace stokes {
 
+// Read-only view of device memory in the constant address space.  Used for
+// buffers that no thread writes while the kernel runs (source packs, tiles,
+// descriptor tables): the compiler then turns wave-uniform reads of them into
+// scalar loads even when the kernel also stores to global memory.
+// (The host compilation pass sees plain const pointers: these functions only
+// run on the device.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+#else
+template <class T>
+using cptr = const T*;
+#endif
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)p;
+}
+
 constexpr double PI_D = 3.14159265358979323846264338327950288;
 
 // ---- small device helpers -------------------------------------------------
@@ -178,11 +196,11 @@ __device__ __forceinline__ void sl_fp64_wave(const SumArgs& a, int tb, int chunk
         ux[r] = uy[r] = uz[r] = 0.0;
     }
     unsigned long long ncoin = 0;
-    const SrcSL64* __restrict__ src = static_cast<const SrcSL64*>(a.s64);
+    const cptr<SrcSL64> src = as_const(static_cast<const SrcSL64*>(a.s64));
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
-        const Tile T = a.tiles[t];
+        const Tile T = as_const(a.tiles)[t];
         bool need = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -256,12 +274,12 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
     unsigned long long nnear = 0, ncoin = 0;
-    const SrcSL32* __restrict__ src = static_cast<const SrcSL32*>(a.s32);
+    const cptr<SrcSL32> src = as_const(static_cast<const SrcSL32*>(a.s32));
     const SrcSL64* __restrict__ src64 = static_cast<const SrcSL64*>(a.s64);
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
-        const Tile T = a.tiles[t];
+        const Tile T = as_const(a.tiles)[t];
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
         bool need = false;
 #pragma unroll
@@ -290,7 +308,7 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
             for (int r = 0; r < R; ++r) m[r] = 0u;
             for (int j = T.j0; j < T.j1; ++j) {
                 const SrcSL32 s = src[j];
-                const float tj = a.near_t[j];
+                const float tj = as_const(a.near_t)[j];
                 const uint32_t bit = 1u << (j - T.j0);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -374,11 +392,11 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
         ux[r] = uy[r] = uz[r] = 0.0;
     }
     unsigned long long ncoin = 0;
-    const SrcDL64* __restrict__ src = static_cast<const SrcDL64*>(a.s64);
+    const cptr<SrcDL64> src = as_const(static_cast<const SrcDL64*>(a.s64));
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
-        const Tile T = a.tiles[t];
+        const Tile T = as_const(a.tiles)[t];
         bool need = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -462,13 +480,13 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
     unsigned long long nnear = 0, ncoin = 0;
-    const SrcDL32* __restrict__ src = static_cast<const SrcDL32*>(a.s32);
+    const cptr<SrcDL32> src = as_const(static_cast<const SrcDL32*>(a.s32));
     const SrcDL64* __restrict__ src64 = static_cast<const SrcDL64*>(a.s64);
     const float tn = a.near_t_uniform;
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
-        const Tile T = a.tiles[t];
+        const Tile T = as_const(a.tiles)[t];
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
         bool need = false;
 #pragma unroll
