@@ -59,23 +59,31 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;    // 4 waves per block
 // Targets per lane (register blocking) of each pair kernel, and the number of
 // blocks a launch aims for (many small work items keep all 256 CUs busy to
-// the end; measured on gfx950: R = 1 with ~32k blocks is fastest for both
+// the end; measured on gfx950: R = 1 with ~64k blocks is fastest for both
 // precisions, because occupancy matters more here than reuse of the SGPR
 // source operands).
 constexpr int R_SL64 = 1, R_SL32 = 1, R_DL64 = 1, R_DL32 = 1;
-constexpr int64_t TARGET_BLOCKS = 32768;
+constexpr int64_t TARGET_BLOCKS = 65536;
 // Serving slots share the GPU with other requests, so each uses fewer chunks
 // (less partial-sum memory per request).
 constexpr int64_t TARGET_BLOCKS_SLOT = 4096;
 constexpr int MIN_TILES_PER_CHUNK = 8;
 
-// A tile of TILE consecutive sources with its bounding sphere.
+// A tile of TILE consecutive sources with two bounding volumes: a sphere about
+// the centre of its bounding box, and a capsule (a segment from the first to
+// the last source plus a radius) that is much tighter for a straight fiber.
+// A target that is outside either volume cannot meet an excluded, coincident
+// or near pair in the tile.
 struct __align__(16) Tile {
     double ox, oy, oz;   // FP64 origin: centre of the bounding box
     double reach2;       // FP64 path: a target closer than sqrt(reach2) may coincide with a source
     float reach2_f;      // mixed path: a target closer than this may have a near pair
     int32_t j0, j1;      // sources [j0, j1)
-    int32_t pad;
+    float inv_l2;        // 1/|b|^2 of the capsule axis (0: the axis is a point)
+    float ax, ay, az;    // capsule axis start, relative to the origin
+    float bx, by, bz;    // capsule axis vector
+    float cap2_f;        // mixed path: (capsule radius + near radius)^2, padded
+    float cap2_d;        // FP64 path: (capsule radius)^2, padded
 };
 
 // Single-layer source, premultiplied: s = w f / (8 pi mu), c = (eps L)^2/2, c3 = -3 c.

@@ -31,20 +31,6 @@ __device__ __forceinline__ int find_slot(cptr<WorkList> wl, int64_t item) {
     return lo;
 }
 
-// Deterministic block reduction (fixed tree) of one value per thread; result in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* lds) {
-    const int t = threadIdx.x;
-    lds[t] = v;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (t < s) lds[t] += lds[t + s];
-        __syncthreads();
-    }
-    const double r = lds[0];
-    __syncthreads();
-    return r;
-}
-
 // Clenshaw-Curtis weight of node kk on the p+1 CGL nodes cos(k pi/p) (Waldvogel's
 // closed form): w_k = (c_k/p) (1 - sum_{j=1}^{p/2} b_j cos(2 j k pi/p) / (4 j^2 - 1)).
 __device__ double cc_weight(int kk, int p) {
@@ -77,18 +63,39 @@ __device__ __forceinline__ void apply_local(double kap, double mu, bool inverse,
     fz = a * fz + b * tf * tz;
 }
 
-// Partial dot products of m vectors A[i] (stride) with w over block b's range.
+// Partial dot products of m vectors A[i] (stride) with w over block b's range,
+// eight vectors per pass (w is read once per pass).  Per vector the order of
+// the arithmetic is fixed: each thread's strided partial, then a fixed tree.
+constexpr int DOT_GROUP = 8;
 __device__ void dot_partials(const double* A, int64_t stride, int m, const double* w, int64_t n,
-                             int B, int b, double* out, double* lds) {
+                             int B, int b, double* out, double (*lds)[BLOCK]) {
     const int64_t L = (n + B - 1) / B;
     const int64_t e0 = (int64_t)b * L;
     const int64_t e1 = min(n, e0 + L);
-    for (int i = 0; i < m; ++i) {
-        const double* a = A + (int64_t)i * stride;
-        double s = 0.0;
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) s = fma(a[e], w[e], s);
-        s = block_sum(s, lds);
-        if (threadIdx.x == 0) out[(int64_t)i * B + b] = s;
+    const int t = threadIdx.x;
+    for (int i0 = 0; i0 < m; i0 += DOT_GROUP) {
+        const int g_n = min(DOT_GROUP, m - i0);
+        double s[DOT_GROUP];
+#pragma unroll
+        for (int g = 0; g < DOT_GROUP; ++g) s[g] = 0.0;
+        for (int64_t e = e0 + t; e < e1; e += BLOCK) {
+            const double we = w[e];
+#pragma unroll
+            for (int g = 0; g < DOT_GROUP; ++g)
+                if (g < g_n) s[g] = fma(A[(int64_t)(i0 + g) * stride + e], we, s[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < DOT_GROUP; ++g) lds[g][t] = s[g];
+        __syncthreads();
+        for (int h = BLOCK / 2; h > 0; h >>= 1) {
+            if (t < h) {
+#pragma unroll
+                for (int g = 0; g < DOT_GROUP; ++g) lds[g][t] += lds[g][t + h];
+            }
+            __syncthreads();
+        }
+        if (t < g_n) out[(int64_t)(i0 + t) * B + b] = lds[t][0];
+        __syncthreads();
     }
 }
 
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const SlotDesc* D, const StepTa
 
 // beta = |rhs| partials (WL_DOT), then beta and v_0 (WL_ONE, WL_VEC).
 __global__ __launch_bounds__(BLOCK) void k_init_norm(const SlotDesc* D, const StepTables* T) {
-    __shared__ double lds[BLOCK];
+    __shared__ double lds[DOT_GROUP][BLOCK];
     const cptr<WorkList> wl = &as_const(T)->wl[WL_DOT];
     const int64_t total = wl->prefix[wl->n];
     for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
@@ -242,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_red(const SlotDesc* D, const StepTabl
 // which = 0: partials of V[0..j].w ; which = 1: same (second Gram-Schmidt pass);
 // which = 2: partials of w.w (norm).
 __global__ __launch_bounds__(BLOCK) void k_dot(const SlotDesc* D, const StepTables* T, int which) {
-    __shared__ double lds[BLOCK];
+    __shared__ double lds[DOT_GROUP][BLOCK];
     const cptr<WorkList> wl = &as_const(T)->wl[WL_DOT];
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);

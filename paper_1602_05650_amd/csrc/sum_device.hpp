@@ -57,6 +57,15 @@ __device__ __forceinline__ bool in_range(int j, int lo, int hi) {
     return (unsigned)(j - lo) < (unsigned)(hi - lo);
 }
 
+// Squared distance of a tile-local point from the tile's capsule axis (FP32).
+__device__ __forceinline__ float capsule_d2(const Tile& T, float x, float y, float z) {
+    const float qx = x - T.ax, qy = y - T.ay, qz = z - T.az;
+    float u = fmaf(qx, T.bx, fmaf(qy, T.by, qz * T.bz)) * T.inv_l2;
+    u = fminf(fmaxf(u, 0.0f), 1.0f);
+    const float dx = fmaf(-u, T.bx, qx), dy = fmaf(-u, T.by, qy), dz = fmaf(-u, T.bz, qz);
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
 __device__ __forceinline__ void kahan_add(float& S, float& C, float v) {
     const float y = v - C;
     const float t = S + y;
@@ -201,12 +210,21 @@ __device__ __forceinline__ void sl_fp64_wave(const SumArgs& a, int tb, int chunk
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
-        bool need = false;
+        bool near_s = false, ex = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = X[r] - T.ox, dy = Y[r] - T.oy, dz = Z[r] - T.oz;
-            need |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
-            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+            near_s |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
+            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
+        }
+        bool need = near_s | ex;
+        if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
+            bool near_c = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                near_c |= capsule_d2(T, (float)(X[r] - T.ox), (float)(Y[r] - T.oy),
+                                     (float)(Z[r] - T.oz)) <= T.cap2_d;
+            need = ex | (near_s & near_c);
         }
         if (__ballot(need) == 0) {
 #pragma unroll STOKES_UNROLL_SL64
@@ -253,7 +271,10 @@ template <int R, bool DOUBLET>
 __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chunk) {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
-    if (wbase >= a.n_t) return;
+    const bool wave_active = wbase < a.n_t;   // no early exit: block barriers below
+    // source tile staged in LDS: every operand of the pair arithmetic is a VGPR
+    // (gfx950 issues FP32 VALU ops with an SGPR operand at a lower rate)
+    __shared__ float4 lds[2 * TILE];
 
     double X[R], Y[R], Z[R], nx[R], ny[R], nz[R];
     float Sx[R], Sy[R], Sz[R], Cx[R], Cy[R], Cz[R];
@@ -274,27 +295,42 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
     unsigned long long nnear = 0, ncoin = 0;
-    const cptr<SrcSL32> src = as_const(static_cast<const SrcSL32*>(a.s32));
+    const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcSL64* __restrict__ src64 = static_cast<const SrcSL64*>(a.s64);
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
+        const int nsrc = T.j1 - T.j0;
+        if ((int)threadIdx.x < 2 * nsrc) lds[threadIdx.x] = src4[2 * (int64_t)T.j0 + threadIdx.x];
+        __syncthreads();
+        if (!wave_active) {
+            __syncthreads();
+            continue;
+        }
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
-        bool need = false;
+        bool near_s = false, ex = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             xs[r] = (float)(X[r] - T.ox);
             ys[r] = (float)(Y[r] - T.oy);
             zs[r] = (float)(Z[r] - T.oz);
-            need |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
-            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+            near_s |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
+            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
             px[r] = py[r] = pz[r] = 0.0f;
+        }
+        bool need = near_s | ex;
+        if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
+            bool near_c = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) near_c |= capsule_d2(T, xs[r], ys[r], zs[r]) <= T.cap2_f;
+            need = ex | (near_s & near_c);
         }
         if (__ballot(need) == 0) {
 #pragma unroll STOKES_UNROLL_SL32
-            for (int j = T.j0; j < T.j1; ++j) {
-                const SrcSL32 s = src[j];
+            for (int k = 0; k < nsrc; ++k) {
+                const float4 p0 = lds[2 * k], p1 = lds[2 * k + 1];
+                const SrcSL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
@@ -306,10 +342,12 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
             uint32_t m[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) m[r] = 0u;
-            for (int j = T.j0; j < T.j1; ++j) {
-                const SrcSL32 s = src[j];
+            for (int k = 0; k < nsrc; ++k) {
+                const int j = T.j0 + k;
+                const float4 p0 = lds[2 * k], p1 = lds[2 * k + 1];
+                const SrcSL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
                 const float tj = as_const(a.near_t)[j];
-                const uint32_t bit = 1u << (j - T.j0);
+                const uint32_t bit = 1u << k;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
@@ -347,7 +385,9 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
             kahan_add(Sy[r], Cy[r], py[r]);
             kahan_add(Sz[r], Cz[r], pz[r]);
         }
+        __syncthreads();
     }
+    if (!wave_active) return;
     double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -397,12 +437,21 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
-        bool need = false;
+        bool near_s = false, ex = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = X[r] - T.ox, dy = Y[r] - T.oy, dz = Z[r] - T.oz;
-            need |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
-            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+            near_s |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
+            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
+        }
+        bool need = near_s | ex;
+        if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
+            bool near_c = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                near_c |= capsule_d2(T, (float)(X[r] - T.ox), (float)(Y[r] - T.oy),
+                                     (float)(Z[r] - T.oz)) <= T.cap2_d;
+            need = ex | (near_s & near_c);
         }
         if (__ballot(need) == 0) {
 #pragma unroll STOKES_UNROLL_DL64
@@ -449,7 +498,10 @@ template <int R, bool SUB>
 __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chunk) {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
-    if (wbase >= a.n_t) return;
+    const bool wave_active = wbase < a.n_t;   // no early exit: block barriers below
+    // source tile staged in LDS: every operand of the pair arithmetic is a VGPR
+    // (gfx950 issues FP32 VALU ops with an SGPR operand at a lower rate)
+    __shared__ float4 lds[3 * TILE];
 
     double X[R], Y[R], Z[R], nx[R], ny[R], nz[R], qx[R], qy[R], qz[R];
     float fqx[R], fqy[R], fqz[R];
@@ -480,28 +532,43 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
     unsigned long long nnear = 0, ncoin = 0;
-    const cptr<SrcDL32> src = as_const(static_cast<const SrcDL32*>(a.s32));
+    const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcDL64* __restrict__ src64 = static_cast<const SrcDL64*>(a.s64);
     const float tn = a.near_t_uniform;
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
+        const int nsrc = T.j1 - T.j0;
+        if ((int)threadIdx.x < 3 * nsrc) lds[threadIdx.x] = src4[3 * (int64_t)T.j0 + threadIdx.x];
+        __syncthreads();
+        if (!wave_active) {
+            __syncthreads();
+            continue;
+        }
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
-        bool need = false;
+        bool near_s = false, ex = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             xs[r] = (float)(X[r] - T.ox);
             ys[r] = (float)(Y[r] - T.oy);
             zs[r] = (float)(Z[r] - T.oz);
-            need |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
-            need |= (lo[r] < T.j1) & (hi[r] > T.j0);
+            near_s |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
+            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
             px[r] = py[r] = pz[r] = 0.0f;
+        }
+        bool need = near_s | ex;
+        if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
+            bool near_c = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) near_c |= capsule_d2(T, xs[r], ys[r], zs[r]) <= T.cap2_f;
+            need = ex | (near_s & near_c);
         }
         if (__ballot(need) == 0) {
 #pragma unroll STOKES_UNROLL_DL32
-            for (int j = T.j0; j < T.j1; ++j) {
-                const SrcDL32 s = src[j];
+            for (int k = 0; k < nsrc; ++k) {
+                const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
+                const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
@@ -514,9 +581,11 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
             uint32_t m[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) m[r] = 0u;
-            for (int j = T.j0; j < T.j1; ++j) {
-                const SrcDL32 s = src[j];
-                const uint32_t bit = 1u << (j - T.j0);
+            for (int k = 0; k < nsrc; ++k) {
+                const int j = T.j0 + k;
+                const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
+                const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, 0.f, 0.f, 0.f};
+                const uint32_t bit = 1u << k;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
@@ -553,7 +622,9 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
             kahan_add(Sy[r], Cy[r], py[r]);
             kahan_add(Sz[r], Cz[r], pz[r]);
         }
+        __syncthreads();
     }
+    if (!wave_active) return;
     double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -611,7 +682,33 @@ __device__ __forceinline__ void tile_prep_one(int t, int64_t n_s, const double* 
     T.reach2_f = (float)(rm * rm) * (1.0f + 1e-6f);
     T.j0 = j0;
     T.j1 = j1;
-    T.pad = 0;
+    // capsule: axis from the first to the last source; radius = largest distance
+    // of a source from that segment.  The FP32 test of a target against it
+    // (in tile-local coordinates) gets a margin that covers its rounding.
+    const double a[3] = {sx[j0] - T.ox, sx[n_s + j0] - T.oy, sx[2 * n_s + j0] - T.oz};
+    const double b[3] = {sx[j1 - 1] - sx[j0], sx[n_s + j1 - 1] - sx[n_s + j0],
+                         sx[2 * n_s + j1 - 1] - sx[2 * n_s + j0]};
+    const double l2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    double crad2 = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double q[3] = {sx[j] - T.ox - a[0], sx[n_s + j] - T.oy - a[1],
+                             sx[2 * n_s + j] - T.oz - a[2]};
+        double u = l2 > 0.0 ? (q[0] * b[0] + q[1] * b[1] + q[2] * b[2]) / l2 : 0.0;
+        u = fmin(fmax(u, 0.0), 1.0);
+        const double d[3] = {q[0] - u * b[0], q[1] - u * b[1], q[2] - u * b[2]};
+        crad2 = fmax(crad2, d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+    const double margin = 1e-5 * (rad + 1.0);
+    const double cm = sqrt(crad2) + nr + margin, cd = sqrt(crad2) + margin;
+    T.inv_l2 = l2 > 0.0 ? (float)(1.0 / l2) : 0.0f;
+    T.ax = (float)a[0];
+    T.ay = (float)a[1];
+    T.az = (float)a[2];
+    T.bx = (float)b[0];
+    T.by = (float)b[1];
+    T.bz = (float)b[2];
+    T.cap2_f = (float)(cm * cm) * (1.0f + 1e-6f);
+    T.cap2_d = (float)(cd * cd) * (1.0f + 1e-6f);
     tiles[t] = T;
 }
 
