@@ -36,10 +36,10 @@ NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go 
 # HBM traffic of one sl_mixed_kernel launch on this workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by the
 # factors that make a 256 MiB elementwise copy in the same run read and write
-# 256 MiB (FETCH x 1.99978, WRITE x 1.0); see
+# 256 MiB (FETCH x 1.99976, WRITE x 0.99999); see
 # profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
 # sources with this digest: after any change the field reports null.
-TRAFFIC = {"digest": "ca2b0c3334cef4dc", "bytes": 407744754}
+TRAFFIC = {"digest": "a7247a7e29336183", "bytes": 540353205}
 KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
                   "paper_1602_05650_amd/csrc/stokes_sums.hip",
                   "paper_1602_05650_amd/csrc/stokes_internal.hpp"]
@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=150)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--only", choices=["mixed", "fp64", "both", "none"], default="both")
     ap.add_argument("--extra", default="c0,c1,c4",
                     help="other workloads timed after the headline (c0,c1,c4 or none)")
@@ -99,51 +99,59 @@ def time_matvecs(S, torch, xyz, forces, fib, flen, eps, mixed, steps, warmup):
 
 
 def config_run(S, torch, name, steps, warmup, log_fn):
-    """One step = single layer (+ double layer when the config has a sphere) to all targets.
-    Returns Gpair/s and ms per step for both precisions and the mixed-vs-FP64 error."""
+    """Time the single layer (and, when the config has a sphere, the double layer) to all
+    targets, for both precisions; report Gpair/s per sum and the mixed-vs-FP64 error."""
     from paper_1602_05650_amd import workloads as W
     c = {"c0": W.config0, "c1": W.config1, "c4": W.config4}[name]()
     fs = c["fibers"]
     dev = torch.device("cuda:0")
     d = lambda a, t=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, t)
     sph = c.get("sphere")
+    X, F, FB, FL = d(fs.xyz), d(c["force"]), d(fs.fiber, torch.int32), d(fs.length)
     if sph is not None:
         trg = np.concatenate([fs.xyz, sph.xyz], axis=1)
         sl_self = np.concatenate([np.arange(fs.n), -np.ones(sph.n, dtype=np.int64)])
         dl_self = np.concatenate([-np.ones(fs.n, dtype=np.int64), np.arange(sph.n)])
         n_t = trg.shape[1]
-        pairs_sl, pairs_dl = n_t * fs.n - fs.n, n_t * sph.n - sph.n
         T, SS, DS = d(trg), d(sl_self, torch.int64), d(dl_self, torch.int64)
         sx, sn, sw, sq = d(sph.xyz), d(sph.normal), d(sph.weight), d(c["q"])
+        pairs = {"sl": n_t * fs.n - fs.n, "dl": n_t * sph.n - sph.n}
     else:
-        n_t, pairs_sl, pairs_dl = fs.n, fs.n * (fs.n - 1), 0
-    X, F, FB, FL = d(fs.xyz), d(c["force"]), d(fs.fiber, torch.int32), d(fs.length)
+        n_t = fs.n
+        pairs = {"sl": fs.n * (fs.n - 1)}
     out = torch.empty((3, n_t), dtype=torch.float64, device=dev)
 
-    def step(mixed):
-        if sph is not None:
+    def run_sum(which, mixed):
+        if which == "sl" and sph is not None:
             S.sl_eval(X, F, src_fiber=FB, fiber_len=FL, eps=fs.eps, trg_xyz=T, trg_self=SS,
                       mixed=mixed, out=out)
+        elif which == "sl":
+            S.sl_eval(X, F, src_fiber=FB, fiber_len=FL, eps=fs.eps, mixed=mixed, out=out)
+        else:
             S.dl_eval(sx, sn, sw, sq, trg_xyz=T, trg_self=DS, mixed=mixed, accumulate=True,
                       out=out)
-        else:
-            S.sl_eval(X, F, src_fiber=FB, fiber_len=FL, eps=fs.eps, mixed=mixed, out=out)
 
-    res = {"targets": n_t, "pairs_per_step": pairs_sl + pairs_dl}
+    res = {"targets": n_t, "pairs": pairs}
     u = {}
     for mixed in (True, False):
-        for _ in range(warmup):
-            step(mixed)
-        torch.cuda.synchronize()
-        u[mixed] = out.cpu().numpy()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step(mixed)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
         tag = "mixed" if mixed else "fp64"
-        res[tag] = {"ms_per_step": round(dt * 1e3, 4),
-                    "gpair_per_s": round((pairs_sl + pairs_dl) / dt / 1e9, 1)}
+        res[tag] = {}
+        for which in pairs:
+            for _ in range(warmup):
+                run_sum(which, mixed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                run_sum(which, mixed)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res[tag][which] = {"ms": round(dt * 1e3, 4),
+                               "gpair_per_s": round(pairs[which] / dt / 1e9, 1)}
+        run_sum("sl", mixed)
+        if sph is not None:
+            run_sum("dl", mixed)
+        torch.cuda.synchronize()
+        u[mixed] = out.cpu().numpy()       # SL (+ DL) of one step
     res["err_mixed_vs_fp64_relmax"] = float(
         f"{np.abs(u[True] - u[False]).max() / np.abs(u[False]).max():.3e}")
     log_fn(f"{name}: {res}")

@@ -55,7 +55,6 @@ struct Carve {
 
 // ---- geometry of the kernel sums -----------------------------------------
 constexpr int TILE = 32;      // sources per tile (one 32-node fiber in the benchmark geometries)
-constexpr int WAVE = 64;
 constexpr int BLOCK = 256;    // 4 waves per block
 // Targets per lane (register blocking) of each pair kernel, and the number of
 // blocks a launch aims for (many small work items keep all 256 CUs busy to
@@ -105,35 +104,5 @@ struct Partition {
     int32_t n_tblocks;
 };
 Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks = TARGET_BLOCKS);
-
-// ---- launch entry points used by the solver and the session ---------------
-struct SLProblem {
-    int64_t n_s;
-    const double* sxyz;
-    const double* force;
-    const double* weight;      // may be null
-    const int32_t* sfib;       // may be null
-    int32_t n_fib;
-    const double* flen;        // may be null
-    int64_t n_t;
-    const double* txyz;        // never null here (resolved by the caller)
-    int64_t t_stride;
-    const int2* excl;          // may be null: no exclusion
-    double mu, eps, near_r;
-    bool mixed, doublet, accumulate;
-    double* u;                 // [3][n_t], stride n_t
-};
-
-// Sizes of the scratch needed by sl_launch for a problem.
-size_t sl_scratch_bytes(int64_t n_s, int64_t n_t, bool mixed);
-// Enqueue the single-layer sum; scratch must hold sl_scratch_bytes().
-// counters: null or 3 u64 on device (near pairs, coincident, excluded), accumulated.
-int sl_launch(const SLProblem& p, void* scratch, unsigned long long* counters, hipStream_t st);
-
-// Fiber start/end index per fiber id, then per-target exclusion ranges.
-int fiber_bounds_launch(int64_t n_s, const int32_t* sfib, int32_t n_fib, int2* bounds,
-                        hipStream_t st);
-int excl_same_fiber_launch(int64_t n_t, const int32_t* tfib, const int2* bounds, int32_t n_fib,
-                           int2* excl, hipStream_t st);
 
 }  // namespace stokes

@@ -384,8 +384,10 @@ __global__ __launch_bounds__(BLOCK) void k_solution(const SlotDesc* D, const Ste
 
 // ---- host side ---------------------------------------------------------------------
 
+// Blocks per request for the Gram-Schmidt dot products: about one per 1024
+// vector elements, so mid-size requests also spread over many CUs.
 static int32_t dot_blocks(int64_t n) {
-    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (n + 4095) / 4096));
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (n + 1023) / 1024));
 }
 
 SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed) {

@@ -267,11 +267,6 @@ static SumScratch carve_sum(void* base, int64_t n_s, int64_t n_t, int32_t n_fib,
     return s;
 }
 
-size_t sl_scratch_bytes(int64_t n_s, int64_t n_t, bool mixed) {
-    const Partition p = make_partition(n_t, n_s, mixed ? R_SL32 : R_SL64);
-    return sum_scratch_bytes(n_s, n_t, 0, sizeof(SrcSL64), mixed ? sizeof(SrcSL32) : 0,
-                             p.n_chunks);
-}
 
 // The register blocking R must match the one the partition was made with.
 static void launch_sl_kernel(bool mixed, bool doublet, unsigned grid, const SumArgs& a,
@@ -290,6 +285,36 @@ static void launch_sl_kernel(bool mixed, bool doublet, unsigned grid, const SumA
 }
 
 // Core launcher: exclusion ranges must already be in `excl` (or null).
+// One single-layer problem, with the targets resolved (never null here).
+struct SLProblem {
+    int64_t n_s;
+    const double* sxyz;
+    const double* force;
+    const double* weight;      // may be null
+    const int32_t* sfib;       // may be null
+    int32_t n_fib;
+    const double* flen;        // may be null
+    int64_t n_t;
+    const double* txyz;
+    int64_t t_stride;
+    double mu, eps, near_r;
+    bool mixed, doublet, accumulate;
+    double* u;                 // [3][n_t], stride n_t
+};
+
+// Start/end source index of every fiber (fiber ids non-decreasing).
+static int fiber_bounds_launch(int64_t n_s, const int32_t* sfib, int32_t n_fib, int2* bounds,
+                               hipStream_t st) {
+    if (n_fib > 0)
+        hipLaunchKernelGGL(fill_int2_kernel, dim3(nblk(n_fib)), dim3(256), 0, st, bounds,
+                           (int64_t)n_fib, make_int2(0, 0));
+    if (n_s > 0)
+        hipLaunchKernelGGL(fiber_bounds_kernel, dim3(nblk(n_s)), dim3(256), 0, st, n_s, sfib, n_fib,
+                           bounds);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
 static int sl_core(const SLProblem& p, const Partition& P, const SumScratch& S, const int2* excl,
                    unsigned long long* counters, hipStream_t st) {
     if (P.n_chunks > 0) {
@@ -330,33 +355,8 @@ static int sl_core(const SLProblem& p, const Partition& P, const SumScratch& S, 
     return STOKES_OK;
 }
 
-int sl_launch(const SLProblem& p, void* scratch, unsigned long long* counters, hipStream_t st) {
-    const Partition P = make_partition(p.n_t, p.n_s, p.mixed ? R_SL32 : R_SL64);
-    const SumScratch S = carve_sum(scratch, p.n_s, p.n_t, 0, sizeof(SrcSL64),
-                                   p.mixed ? sizeof(SrcSL32) : 0, P.n_chunks);
-    return sl_core(p, P, S, p.excl, counters, st);
-}
 
-int fiber_bounds_launch(int64_t n_s, const int32_t* sfib, int32_t n_fib, int2* bounds,
-                        hipStream_t st) {
-    if (n_fib > 0)
-        hipLaunchKernelGGL(fill_int2_kernel, dim3(nblk(n_fib)), dim3(256), 0, st, bounds,
-                           (int64_t)n_fib, make_int2(0, 0));
-    if (n_s > 0)
-        hipLaunchKernelGGL(fiber_bounds_kernel, dim3(nblk(n_s)), dim3(256), 0, st, n_s, sfib, n_fib,
-                           bounds);
-    STOKES_HIP(hipGetLastError());
-    return STOKES_OK;
-}
 
-int excl_same_fiber_launch(int64_t n_t, const int32_t* tfib, const int2* bounds, int32_t n_fib,
-                           int2* excl, hipStream_t st) {
-    if (n_t > 0)
-        hipLaunchKernelGGL(excl_fiber_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, tfib, bounds,
-                           n_fib, excl, (unsigned long long*)nullptr);
-    STOKES_HIP(hipGetLastError());
-    return STOKES_OK;
-}
 
 // ---- validation helpers ---------------------------------------------------------
 static bool bad_ptr(const void* p, int64_t n) { return p == nullptr && n > 0; }
@@ -489,7 +489,6 @@ extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double
     p.n_t = n_t;
     p.txyz = same ? src_xyz : trg_xyz;
     p.t_stride = same ? n_src : n_t;
-    p.excl = excl;
     p.mu = mu;
     p.eps = eps;
     p.near_r = near_r;
