@@ -239,11 +239,21 @@ typedef struct stokes_solve_stats {
 /* Create a session (a worker thread, one stream, device slot memory on demand). */
 int stokes_session_create(const stokes_session_cfg* cfg, stokes_session** out);
 /* Copy a request and queue it; returns at once.  E_NOMEM if it can never fit the
- * budget, E_BUSY if the queue is full, E_INVAL for bad sizes. */
+ * budget, E_BUSY if the queue is full, E_INVAL for bad sizes, E_NONFINITE if an
+ * input holds a NaN or Inf. */
 int stokes_session_submit(stokes_session* s, const stokes_solve_req* req, uint64_t* ticket);
-/* Wait for a ticket (timeout_ms < 0: forever).  f_out: NULL or host [3*N]. */
+/* Wait for a ticket (timeout_ms < 0: forever) and collect it: the ticket is
+ * released unless the wait times out.  f_out: NULL or host [3*N].  Only one
+ * thread may wait for a ticket at a time (a second one gets STOKES_E_BUSY). */
 int stokes_session_wait(stokes_session* s, uint64_t ticket, double* f_out,
                         stokes_solve_stats* st, int32_t timeout_ms);
+/* Device bytes a request of this shape takes from a session's budget (flags:
+ * the session's STOKES_PREC_*).  Returns 0 for invalid shapes. */
+int64_t stokes_solve_footprint(int32_t n_fib, int32_t nodes_per_fib, int32_t iters, uint32_t flags);
+/* Test hook for failure handling: the session's next step reports a device
+ * error for every request then in flight (their waits return STOKES_E_DEVICE);
+ * queued requests are not affected and the session keeps serving. */
+int stokes_session_inject_fault(stokes_session* s);
 /* Cancel a queued or running request; its wait returns STOKES_E_CANCELED. */
 int stokes_session_cancel(stokes_session* s, uint64_t ticket);
 /* Stop the worker; pending requests finish with STOKES_E_CANCELED. */

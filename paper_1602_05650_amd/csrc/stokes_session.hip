@@ -11,7 +11,9 @@
 #include <time.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <string>
@@ -97,6 +99,7 @@ struct Request {
     double* host = nullptr;       // pinned: xyz | tan | rhs | flen | result
     ReqState state = QUEUED;
     bool cancel = false;
+    bool claimed = false;         // a thread is inside stokes_session_wait for it
     int slot = -1;
     void* mem = nullptr;
     int j = 0;                    // iterations done
@@ -119,6 +122,7 @@ struct stokes_session {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool stop = false;
+    std::atomic<bool> inject_fault{false};
     int waiters = 0;
     int worker_rc = STOKES_OK;
     uint64_t next_ticket = 1;
@@ -230,6 +234,14 @@ static void worker_main(stokes_session* s) {
                 B.desc(q).j = r->j;
                 iterating.push_back(q);
             }
+            if (s->inject_fault.exchange(false) && !iterating.empty()) {
+                // forced failure of this step: fail the requests in flight, keep serving
+                std::lock_guard<std::mutex> lk(s->mu);
+                set_error("injected step failure");
+                for (int q : iterating) finish(s, slots[q], STOKES_E_DEVICE);
+                iterating.clear();
+                s->cv_done.notify_all();
+            }
             rc = B.step(iterating);
         }
         if (!rc) {
@@ -326,6 +338,12 @@ extern "C" int stokes_session_submit(stokes_session* s, const stokes_solve_req* 
         return fail(STOKES_E_INVAL, "stokes_session_submit: null array");
     const int64_t N = (int64_t)req->n_fib * req->nodes_per_fib;
     if (N >= (int64_t)1 << 30) return fail(STOKES_E_INVAL, "stokes_session_submit: too many nodes");
+    for (int64_t i = 0; i < 3 * N; ++i)
+        if (!std::isfinite(req->xyz[i]) || !std::isfinite(req->tangent[i]) || !std::isfinite(req->rhs[i]))
+            return fail(STOKES_E_NONFINITE, "stokes_session_submit: non-finite input");
+    for (int32_t f = 0; f < req->n_fib; ++f)
+        if (!std::isfinite(req->fiber_len[f]) || !(req->fiber_len[f] > 0.0))
+            return fail(STOKES_E_INVAL, "stokes_session_submit: fiber lengths must be finite and > 0");
     const bool mixed = s->cfg.flags & STOKES_PREC_MIXED;
     const size_t bytes = slot_plan(req->n_fib, req->nodes_per_fib, req->iters, mixed).bytes;
     if (bytes > s->arena.capacity())
@@ -381,6 +399,8 @@ extern "C" int stokes_session_wait(stokes_session* s, uint64_t ticket, double* f
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return fail(STOKES_E_NOTFOUND, "stokes_session_wait: unknown ticket");
     Request* r = it->second;
+    if (r->claimed) return fail(STOKES_E_BUSY, "stokes_session_wait: another thread waits for this ticket");
+    r->claimed = true;
     s->waiters++;
     auto ready = [&] { return r->state == DONE; };
     bool ok = true;
@@ -390,6 +410,7 @@ extern "C" int stokes_session_wait(stokes_session* s, uint64_t ticket, double* f
         ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
     s->waiters--;
     if (!ok) {
+        r->claimed = false;
         s->cv_done.notify_all();
         return fail(STOKES_E_TIMEOUT, "stokes_session_wait: timeout");
     }
@@ -441,4 +462,19 @@ extern "C" int stokes_session_destroy(stokes_session* s) {
     (void)hipStreamDestroy(st);
     (void)hipSetDevice(cur);
     return rc ? rc : STOKES_OK;
+}
+
+extern "C" int64_t stokes_solve_footprint(int32_t n_fib, int32_t nodes_per_fib, int32_t iters,
+                                          uint32_t flags) {
+    if (n_fib < 1 || nodes_per_fib < 2 || nodes_per_fib > 64 || iters < 1 || iters > STOKES_MAX_ITERS)
+        return 0;
+    if ((int64_t)n_fib * nodes_per_fib >= (int64_t)1 << 30) return 0;
+    return (int64_t)slot_plan(n_fib, nodes_per_fib, iters, flags & STOKES_PREC_MIXED).bytes;
+}
+
+extern "C" int stokes_session_inject_fault(stokes_session* s) {
+    if (!s) return fail(STOKES_E_INVAL, "stokes_session_inject_fault: null session");
+    s->inject_fault.store(true);
+    s->cv_work.notify_one();
+    return STOKES_OK;
 }

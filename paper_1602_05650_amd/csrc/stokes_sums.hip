@@ -215,7 +215,9 @@ Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks)
         return p;
     }
     int64_t ch = (target_blocks + p.n_tblocks - 1) / p.n_tblocks;
-    ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / MIN_TILES_PER_CHUNK));
+    // few target blocks (a small, latency-bound problem): down to one tile per chunk
+    const int64_t min_tiles = p.n_tblocks >= 64 ? MIN_TILES_PER_CHUNK : 1;
+    ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / min_tiles));
     ch = std::max<int64_t>(1, std::min<int64_t>(ch, p.n_tiles));
     p.tiles_per_chunk = (int32_t)((p.n_tiles + ch - 1) / ch);
     p.n_chunks = (p.n_tiles + p.tiles_per_chunk - 1) / p.tiles_per_chunk;

@@ -77,6 +77,7 @@ def _load():
         "stokes_session_submit": [P, P, P],
         "stokes_session_wait": [P, ctypes.c_uint64, P, P, I32],
         "stokes_session_cancel": [P, ctypes.c_uint64],
+        "stokes_session_inject_fault": [P],
         "stokes_session_destroy": [P],
         "stokes_release_workspace": [],
         "stokes_version": [],
@@ -87,6 +88,8 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.stokes_solve_footprint.argtypes = [I32, I32, I32, U32]
+    lib.stokes_solve_footprint.restype = ctypes.c_int64
     lib.stokes_status_string.argtypes = [ctypes.c_int]
     lib.stokes_status_string.restype = ctypes.c_char_p
     lib.stokes_last_error.argtypes = []
@@ -252,6 +255,12 @@ def profile_read():
     return ms.value, n.value
 
 
+def solve_footprint(n_fib, nodes_per_fib, iters, mixed=False):
+    """Device bytes a mobility request of this shape takes from a session budget."""
+    return int(_lib.stokes_solve_footprint(int(n_fib), int(nodes_per_fib), int(iters),
+                                           PREC_MIXED if mixed else PREC_FP64))
+
+
 def release_workspace():
     _check(_lib.stokes_release_workspace())
 
@@ -293,11 +302,15 @@ class Session:
         rc = _lib.stokes_session_wait(self._h, ctypes.c_uint64(ticket),
                                       out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
                                       int(timeout_ms))
-        if rc != E_TIMEOUT:
+        if rc not in (E_TIMEOUT, E_BUSY):      # the ticket is still live after these
             self._shapes.pop(ticket, None)
         _check(rc)
         stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
         return out, stats
+
+    def inject_fault(self):
+        """Test hook: the next step fails every request then in flight."""
+        _check(_lib.stokes_session_inject_fault(self._h))
 
     def cancel(self, ticket):
         _check(_lib.stokes_session_cancel(self._h, ctypes.c_uint64(ticket)))

@@ -16,7 +16,7 @@ LIB = os.path.join(ROOT, "paper_1602_05650_amd", "libstokes.so")
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(stokes_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(stokes_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_required_entry_points():
@@ -70,6 +70,17 @@ def test_status_strings_and_validation_without_gpu():
                                    None, None) == S.E_INVAL
     assert L.stokes_session_create(None, None) == S.E_INVAL
     assert L.stokes_session_destroy(None) == S.E_INVAL
+
+
+def test_solve_footprint_without_gpu():
+    from paper_1602_05650_amd import stokes as S
+    small = S.solve_footprint(10, 16, 20)
+    big = S.solve_footprint(2048, 64, 60)
+    assert 0 < small < big
+    assert S.solve_footprint(10, 16, 20, mixed=True) > small        # FP32 packs on top
+    assert S.solve_footprint(0, 16, 20) == 0 and S.solve_footprint(10, 65, 20) == 0
+    # the Krylov basis alone: (k+1) x 3N doubles
+    assert big > 61 * 3 * 2048 * 64 * 8
 
 
 def test_version():

@@ -106,19 +106,94 @@ def test_session_mixed_alone_equals_mix(S):
 def test_session_budget_binds_and_errors(S):
     reqs = [W.serving_request(5, rid, n_fib=n, nodes=32, iters=20)
             for rid, n in enumerate([100, 120, 80, 110])]
-    from paper_1602_05650_amd import stokes as SS
-    # budget just above the largest request: requests run one after another
-    biggest = max(r["fibers"].n for r in reqs)
-    with S.Session(hbm_budget_bytes=64 << 20, max_slots=8) as s:
+    foot = [S.solve_footprint(r["fibers"].n_fib, 32, 20) for r in reqs]
+    # room for the largest request but not for any two: the budget, not the
+    # eight slots, serialises them, in FIFO order
+    budget = max(foot) + min(foot) // 2
+    assert all(a + b > budget for i, a in enumerate(foot) for b in foot[i + 1:])
+    with S.Session(hbm_budget_bytes=budget, max_slots=8) as s:
         ts = [_submit(s, r) for r in reqs]
-        stats = [s.wait(t)[1] for t in ts]
-        assert all(st["status"] == 0 for st in stats)
+        out = [s.wait(t) for t in ts]
+    stats = [st for _, st in out]
+    assert all(st["status"] == 0 for st in stats)
+    for a, b in zip(stats, stats[1:]):
+        assert b["t_admit_ns"] >= a["t_finish_ns"]
+    # the serialised results equal the same requests in a roomy session
+    with S.Session(hbm_budget_bytes=1 << 30, max_slots=8) as s:
+        ts = [_submit(s, r) for r in reqs]
+        roomy = [s.wait(t)[0] for t in ts]
+    for (f, _), g in zip(out, roomy):
+        assert np.array_equal(f, g)
     # over budget: refused at submit
-    with S.Session(hbm_budget_bytes=1 << 20, max_slots=2) as s:
-        with pytest.raises(SS.StokesError) as ei:
+    with S.Session(hbm_budget_bytes=min(foot) - 1, max_slots=2) as s:
+        with pytest.raises(S.StokesError) as ei:
             _submit(s, reqs[0])
-        assert ei.value.code == SS.E_NOMEM
-    assert biggest > 0
+        assert ei.value.code == S.E_NOMEM
+
+
+def test_session_rejects_nonfinite_input(S):
+    req = W.serving_request(8, 0, n_fib=10, nodes=16, iters=10)
+    with S.Session(hbm_budget_bytes=1 << 28, max_slots=2) as s:
+        for field in ("xyz", "tangent", "rhs"):
+            bad = dict(req)
+            fs = req["fibers"]
+            arrs = {"xyz": fs.xyz.copy(), "tangent": fs.tangent.copy(), "rhs": req["rhs"].copy()}
+            arrs[field][1, 17] = np.nan if field != "rhs" else np.inf
+            with pytest.raises(S.StokesError) as ei:
+                s.submit(arrs["xyz"], arrs["tangent"], fs.length, arrs["rhs"],
+                         fs.nodes_per_fiber, fs.eps, req["iters"])
+            assert ei.value.code == S.E_NONFINITE
+            del bad
+        fl = req["fibers"].length.copy()
+        fl[3] = 0.0
+        with pytest.raises(S.StokesError) as ei:
+            s.submit(req["fibers"].xyz, req["fibers"].tangent, fl, req["rhs"],
+                     req["fibers"].nodes_per_fiber, req["fibers"].eps, req["iters"])
+        assert ei.value.code == S.E_INVAL
+        # the session still serves a good request afterwards
+        f, st = s.wait(_submit(s, req))
+        assert st["status"] == 0 and np.all(np.isfinite(f))
+
+
+def test_session_injected_fault_fails_in_flight_only(S):
+    big = W.serving_request(11, 0, n_fib=1500, nodes=32, iters=60)
+    small = W.serving_request(11, 1, n_fib=20, nodes=16, iters=10)
+    with S.Session(hbm_budget_bytes=1 << 31, max_slots=1) as s:
+        ref = s.wait(_submit(s, small))[0]
+        t_big = _submit(s, big)
+        t_small = _submit(s, small)     # queued behind the big one (one slot)
+        time.sleep(0.02)
+        s.inject_fault()
+        with pytest.raises(S.StokesError) as ei:
+            s.wait(t_big)
+        assert ei.value.code == S.E_DEVICE
+        f, st = s.wait(t_small)         # not in flight at the fault: served normally
+        assert st["status"] == 0 and np.array_equal(f, ref)
+        f2, st2 = s.wait(_submit(s, small))
+        assert st2["status"] == 0 and np.array_equal(f2, ref)
+
+
+def test_session_second_waiter_gets_busy(S):
+    big = W.serving_request(12, 0, n_fib=2000, nodes=64, iters=60)
+    with S.Session(hbm_budget_bytes=1 << 32, max_slots=1) as s:
+        t = _submit(s, big)
+        box = {}
+
+        def waiter():
+            box["f"], box["st"] = s.wait(t)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        time.sleep(0.05)
+        busy = None
+        try:
+            s.wait(t, timeout_ms=0)
+        except S.StokesError as e:
+            busy = e.code
+        th.join(timeout=120)
+        assert box["st"]["status"] == 0
+        # the first waiter was still inside wait, or had already taken the result
+        assert busy in (S.E_BUSY, S.E_NOTFOUND)
 
 
 def test_session_cancel_and_destroy_with_pending(S):
