@@ -36,10 +36,10 @@ NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go 
 # HBM traffic of one sl_mixed_kernel launch on this workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by the
 # factors that make a 256 MiB elementwise copy in the same run read and write
-# 256 MiB (FETCH x 1.99976, WRITE x 0.99999); see
+# 256 MiB (FETCH x 1.99977, WRITE x 0.99998); see
 # profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
 # sources with this digest: after any change the field reports null.
-TRAFFIC = {"digest": "a7247a7e29336183", "bytes": 540353205}
+TRAFFIC = {"digest": "a2dba041d59ff552", "bytes": 540350403}
 KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
                   "paper_1602_05650_amd/csrc/stokes_sums.hip",
                   "paper_1602_05650_amd/csrc/stokes_internal.hpp"]

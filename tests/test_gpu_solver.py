@@ -109,8 +109,9 @@ def test_session_budget_binds_and_errors(S):
     foot = [S.solve_footprint(r["fibers"].n_fib, 32, 20) for r in reqs]
     # room for the largest request but not for any two: the budget, not the
     # eight slots, serialises them, in FIFO order
-    budget = max(foot) + min(foot) // 2
-    assert all(a + b > budget for i, a in enumerate(foot) for b in foot[i + 1:])
+    pair_min = min(a + b for i, a in enumerate(foot) for b in foot[i + 1:])
+    budget = (max(foot) + pair_min) // 2
+    assert max(foot) < budget < pair_min
     with S.Session(hbm_budget_bytes=budget, max_slots=8) as s:
         ts = [_submit(s, r) for r in reqs]
         out = [s.wait(t) for t in ts]
