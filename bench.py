@@ -67,6 +67,13 @@ def parse():
     ap.add_argument("--only", choices=["mixed", "fp64", "both", "none"], default="both")
     ap.add_argument("--extra", default="c0,c1,c4",
                     help="other workloads timed after the headline (c0,c1,c4 or none)")
+    ap.add_argument("--step-pairs", type=float, default=0,
+                    help="serving: single-layer pairs one request may take per step "
+                         "(0: library default, < 0: whole matvec per step)")
+    ap.add_argument("--serving-rate", type=float, default=0,
+                    help="serving: fixed Poisson rate in requests/s (0: 0.7 x calibrated capacity)")
+    ap.add_argument("--serving-fp64", action="store_true",
+                    help="serving run with FP64 sums instead of mixed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one elementwise copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -158,7 +165,7 @@ def config_run(S, torch, name, steps, warmup, log_fn):
     return res
 
 
-def serving_run(S, n_req, log_fn):
+def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
     from paper_1602_05650_amd import workloads as W
     reqs = [W.serving_request(3, rid) for rid in range(n_req)]
     pairs = sum(r["iters"] * r["fibers"].n * (r["fibers"].n - r["fibers"].nodes_per_fiber)
@@ -169,7 +176,8 @@ def serving_run(S, n_req, log_fn):
         return sess.submit(fs.xyz, fs.tangent, fs.length, r["rhs"], fs.nodes_per_fiber, fs.eps,
                            r["iters"], tag=r["rid"])
 
-    with S.Session(hbm_budget_bytes=4 << 30, max_slots=64, mixed=True) as sess:
+    with S.Session(hbm_budget_bytes=4 << 30, max_slots=64, mixed=mixed,
+                   step_pairs=int(step_pairs)) as sess:
         # warm-up (arena, graph capture), then calibration: a burst of 48 requests drawn
         # like the stream (other ids) saturates the session; capacity = requests/s
         for t in [submit(sess, W.serving_request(3, 20000 + i, n_fib=32, iters=20))
@@ -181,7 +189,7 @@ def serving_run(S, n_req, log_fn):
         for t in ts:
             sess.wait(t)
         cap = len(cal) / (time.perf_counter() - t0)
-        rate = 0.7 * cap
+        rate = rate if rate > 0 else 0.7 * cap
         arrivals = W.serving_stream(3, n_req, rate)
         log_fn(f"serving: capacity {cap:.1f} req/s (calibration), Poisson rate {rate:.1f} req/s")
         tickets = [None] * n_req
@@ -215,7 +223,10 @@ def serving_run(S, n_req, log_fn):
         "mean_ms": round(float(lat.mean()), 2),
         "throughput_req_per_s": round(n_req / wall, 2),
         "gpair_per_s": round(pairs / wall / 1e9, 1),
-        "precision": "mixed sums, FP64 GMRES", "hbm_budget_gib": 4, "max_slots": 64,
+        "precision": "mixed sums, FP64 GMRES" if mixed else "FP64 sums, FP64 GMRES",
+        "hbm_budget_gib": 4, "max_slots": 64,
+        "step_pairs": ("library default" if step_pairs == 0 else
+                       "whole matvec" if step_pairs < 0 else int(step_pairs)),
         "workload": "Poisson stream; N_f log-uniform [32, 2048] fibers x {16,32,64} nodes; "
                     "20-60 GMRES iterations; same-fiber excluded, Clenshaw-Curtis weights",
     }
@@ -257,7 +268,8 @@ def main():
     from paper_1602_05650_amd import workloads as W
 
     if args.only == "none":          # serving run alone (for profiling it)
-        print(json.dumps({"serving": serving_run(S, args.serving_requests, log)}), flush=True)
+        print(json.dumps({"serving": serving_run(S, args.serving_requests, log, args.step_pairs,
+                                                 not args.serving_fp64, args.serving_rate)}), flush=True)
         return
     t_gen = time.perf_counter()
     c = W.config2()
@@ -356,7 +368,8 @@ def main():
             config_run(S, torch, e, 200 if e == "c0" else 10, 3, log) for e in extra}
     if not args.no_serving:
         try:
-            out["serving"] = serving_run(S, args.serving_requests, log)
+            out["serving"] = serving_run(S, args.serving_requests, log, args.step_pairs,
+                                         not args.serving_fp64, args.serving_rate)
         except Exception as e:  # report, do not hide
             out["serving"] = {"error": repr(e)}
             log("serving run failed:", repr(e))

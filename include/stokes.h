@@ -211,7 +211,14 @@ typedef struct stokes_session_cfg {
     int32_t max_queue;         /* submitted but not admitted requests, >= 1 */
     uint32_t flags;            /* STOKES_PREC_* and STOKES_NO_DOUBLET for every request */
     int32_t device;            /* HIP device ordinal */
+    int64_t step_pairs;        /* pair budget of one request's single-layer work in one
+                                  step: a larger matvec is spread over several steps so
+                                  that small requests in flight keep advancing every
+                                  step (results are unchanged, bit for bit).  0: the
+                                  default (STOKES_STEP_PAIRS_DEFAULT); < 0: no limit. */
 } stokes_session_cfg;
+
+#define STOKES_STEP_PAIRS_DEFAULT 8000000000LL
 
 typedef struct stokes_solve_req {   /* HOST pointers; copied by stokes_session_submit */
     int32_t n_fib;

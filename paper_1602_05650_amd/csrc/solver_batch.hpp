@@ -61,12 +61,15 @@ struct SlotDesc {
     double* partial;
 };
 
-// Work list of one kernel: slots taking part and the prefix sum of their items.
+// Work list of one kernel: slots taking part, the prefix sum of their items and,
+// per slot, the index of its first item (nonzero only when a slot's single-layer
+// sum is split over several steps).
 struct WorkList {
     int32_t n;
     int32_t pad;
     int32_t slot[MAX_SLOTS];
     int64_t prefix[MAX_SLOTS + 1];
+    int64_t base[MAX_SLOTS];
 };
 
 enum WL {
@@ -109,6 +112,17 @@ public:
     int start(const std::vector<int>& slots);
     // One GMRES iteration for every listed slot, then read the status rows back.
     int step(const std::vector<int>& slots);
+    // Part of one GMRES iteration per listed slot: single-layer items
+    // [sl_begin, sl_begin + sl_count) of the slot's current iteration.  The part
+    // with sl_begin == 0 also forms z = M^{-1} v_j and the source pack; the part
+    // that reaches the last item also finishes the iteration (reduction,
+    // Gram-Schmidt, Givens) and only for those slots is the status row fresh.
+    // The items write disjoint partials, so the split does not change a bit.
+    struct Part {
+        int slot;
+        int32_t sl_begin, sl_count;
+    };
+    int step_parts(const std::vector<Part>& parts);
     // Solutions of the listed slots into their x buffers (iterations done in desc.j).
     int finalize(const std::vector<int>& slots);
     const double* status(int s) const { return host_stat_ + NSTAT * s; }
@@ -120,7 +134,9 @@ private:
     int upload();
     int launch_step(bool capture);
     void set_list(WL w, const std::vector<int>& slots);
-    int read_status(const std::vector<int>& slots);
+    void set_sl_list(const std::vector<Part>& parts);
+    int run_step();
+    int read_status();
 
     hipStream_t st_ = nullptr;
     bool mixed_ = false, doublet_ = true, use_graph_ = false;

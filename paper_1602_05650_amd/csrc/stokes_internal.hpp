@@ -103,6 +103,9 @@ struct Partition {
     int32_t n_chunks;
     int32_t n_tblocks;
 };
-Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks = TARGET_BLOCKS);
+// min_tiles_small: least source tiles per chunk when there are fewer than 64
+// target blocks (a problem too small to fill the chip with target blocks alone).
+Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks = TARGET_BLOCKS,
+                         int min_tiles_small = 1);
 
 }  // namespace stokes

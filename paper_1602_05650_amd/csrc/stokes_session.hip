@@ -103,6 +103,8 @@ struct Request {
     int slot = -1;
     void* mem = nullptr;
     int j = 0;                    // iterations done
+    int32_t sl_done = 0;          // single-layer items of iteration j already summed
+    int32_t sl_quota = 0;         // single-layer items per step
     stokes_solve_stats st{};
     double* xyz() { return host; }
     double* tan() { return host + 3 * N; }
@@ -152,6 +154,16 @@ static void finish(stokes_session* s, Request* r, int status) {
         s->arena.release(r->mem);
         r->mem = nullptr;
     }
+}
+
+// Single-layer items a request takes per step: its pair budget over the pairs
+// of one item (target block x source chunk), at least one item.
+static int32_t step_quota(const SlotDesc& d, int64_t step_pairs) {
+    if (step_pairs == 0) step_pairs = STOKES_STEP_PAIRS_DEFAULT;
+    if (step_pairs < 0 || d.n_items_sl <= 0) return std::max<int32_t>(1, d.n_items_sl);
+    const double pairs_per_item = (double)d.N * (double)d.N / d.n_items_sl;
+    const double q = std::floor((double)step_pairs / std::max(1.0, pairs_per_item));
+    return (int32_t)std::max(1.0, std::min<double>(q, d.n_items_sl));
 }
 
 static void worker_main(stokes_session* s) {
@@ -218,6 +230,7 @@ static void worker_main(stokes_session* s) {
         }
         if (!rc) rc = B.start(admitted);
         std::vector<int> iterating, finishing;
+        std::vector<Batch::Part> parts;
         if (!rc) {
             for (int q = 0; q < (int)slots.size(); ++q) {
                 Request* r = slots[q];
@@ -225,6 +238,8 @@ static void worker_main(stokes_session* s) {
                 const bool fresh = std::find(admitted.begin(), admitted.end(), q) != admitted.end();
                 if (fresh) {
                     r->j = 0;
+                    r->sl_done = 0;
+                    r->sl_quota = step_quota(B.desc(q), s->cfg.step_pairs);
                     r->st.residual = B.status(q)[2];
                     if (B.status(q)[3] != 0.0) {   // zero right-hand side
                         finishing.push_back(q);
@@ -242,14 +257,22 @@ static void worker_main(stokes_session* s) {
                 iterating.clear();
                 s->cv_done.notify_all();
             }
-            rc = B.step(iterating);
-        }
-        if (!rc) {
             for (int q : iterating) {
                 Request* r = slots[q];
+                const int32_t n = B.desc(q).n_items_sl;
+                parts.push_back({q, r->sl_done, std::min(r->sl_quota, n - r->sl_done)});
+            }
+            rc = B.step_parts(parts);
+        }
+        if (!rc) {
+            for (const Batch::Part& p : parts) {
+                Request* r = slots[p.slot];
+                r->sl_done += p.sl_count;
+                if (r->sl_done < B.desc(p.slot).n_items_sl) continue;   // matvec not complete
+                r->sl_done = 0;
                 r->j += 1;
-                r->st.residual = B.status(q)[2];
-                if (r->j >= r->k || B.status(q)[3] != 0.0) finishing.push_back(q);
+                r->st.residual = B.status(p.slot)[2];
+                if (r->j >= r->k || B.status(p.slot)[3] != 0.0) finishing.push_back(p.slot);
             }
             for (int q : finishing) B.desc(q).j = slots[q]->j;
             rc = B.finalize(finishing);

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(BLOCK) void k_sl(const SlotDesc* D, const StepTable
 #pragma unroll
             for (int q = 0; q < (int)(sizeof(SumArgs) / 8); ++q) o[q] = w[q];
         }
-        const int local = (int)(it - wl->prefix[si]);
+        const int local = (int)(wl->base[si] + (it - wl->prefix[si]));
         const int tb = local % a.n_tblocks;
         const int chunk = local / a.n_tblocks;
         if (MIXED)
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_sl(const SlotDesc* D, const StepTable
 
 // w = M z + (sum of the chunk partials, in chunk order).
 __global__ __launch_bounds__(BLOCK) void k_red(const SlotDesc* D, const StepTables* T) {
-    const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_RED];
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
         const auto& d = as_const(D)[wl->slot[si]];
@@ -393,7 +393,7 @@ static int32_t dot_blocks(int64_t n) {
 SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed) {
     SlotPlan sp{};
     const int64_t N = (int64_t)n_fib * npf;
-    sp.P = make_partition(N, N, mixed ? R_SL32 : R_SL64, TARGET_BLOCKS_SLOT);
+    sp.P = make_partition(N, N, mixed ? R_SL32 : R_SL64, TARGET_BLOCKS_SLOT, MIN_TILES_PER_CHUNK);
     sp.B = dot_blocks(3 * N);
     const int64_t n = 3 * N;
     size_t b = 0;
@@ -551,7 +551,21 @@ void Batch::set_list(WL w, const std::vector<int>& slots) {
             default: break;
         }
         L.slot[q] = slots[q];
+        L.base[q] = 0;
         L.prefix[q + 1] = L.prefix[q] + items;
+    }
+}
+
+void Batch::set_sl_list(const std::vector<Part>& parts) {
+    WorkList& L = host_tab_->wl[WL_SL];
+    L.n = 0;
+    L.prefix[0] = 0;
+    for (const Part& p : parts) {
+        if (p.sl_count <= 0) continue;
+        L.slot[L.n] = p.slot;
+        L.base[L.n] = p.sl_begin;
+        L.prefix[L.n + 1] = L.prefix[L.n] + p.sl_count;
+        ++L.n;
     }
 }
 
@@ -567,8 +581,7 @@ static unsigned grid_for(const WorkList& L, int cap) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(t, cap));
 }
 
-int Batch::read_status(const std::vector<int>& slots) {
-    (void)slots;
+int Batch::read_status() {
     STOKES_HIP(hipMemcpyAsync(host_stat_, dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS,
                               hipMemcpyDeviceToHost, st_));
     STOKES_HIP(hipStreamSynchronize(st_));
@@ -590,7 +603,7 @@ int Batch::start(const std::vector<int>& slots) {
     hipLaunchKernelGGL(k_init_beta, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_, dev_stat_);
     hipLaunchKernelGGL(k_init_v0, dim3(grid_for(T.wl[WL_VEC], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     STOKES_HIP(hipGetLastError());
-    return read_status(slots);
+    return read_status();
 }
 
 int Batch::launch_step(bool graph_sizes) {
@@ -607,7 +620,7 @@ int Batch::launch_step(bool graph_sizes) {
         else hipLaunchKernelGGL((k_sl<false, false>), dim3(g(WL_SL, G_SL)), b, 0, st_, dev_desc_, dev_tab_);
     }
     if (!graph_sizes) prof_end(st_);
-    hipLaunchKernelGGL(k_red, dim3(g(WL_PRE, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_red, dim3(g(WL_RED, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_);
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_dot, dim3(g(WL_DOT, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, pass);
         hipLaunchKernelGGL(k_dred, dim3(g(WL_ONE, G_ONE)), b, 0, st_, dev_desc_, dev_tab_, pass);
@@ -628,6 +641,29 @@ int Batch::step(const std::vector<int>& slots) {
     set_list(WL_DOT, slots);
     set_list(WL_ONE, slots);
     set_list(WL_VEC, slots);
+    return run_step();
+}
+
+int Batch::step_parts(const std::vector<Part>& parts) {
+    if (parts.empty()) return STOKES_OK;
+    std::vector<int> begin, end;
+    for (const Part& p : parts) {
+        const int32_t n = host_desc_[p.slot].n_items_sl;
+        if (p.sl_begin < 0 || p.sl_count < 0 || p.sl_begin + p.sl_count > n)
+            return fail(STOKES_E_INVAL, "step_parts: single-layer item range out of bounds");
+        if (p.sl_begin == 0) begin.push_back(p.slot);
+        if (p.sl_begin + p.sl_count == n) end.push_back(p.slot);
+    }
+    set_list(WL_PRE, begin);
+    set_sl_list(parts);
+    set_list(WL_RED, end);
+    set_list(WL_DOT, end);
+    set_list(WL_ONE, end);
+    set_list(WL_VEC, end);
+    return run_step();
+}
+
+int Batch::run_step() {
     int rc = upload();
     if (rc) return rc;
     if (use_graph_) {
@@ -648,7 +684,7 @@ int Batch::step(const std::vector<int>& slots) {
     } else {
         if ((rc = launch_step(false))) return rc;
     }
-    return read_status(slots);
+    return read_status();
 }
 
 int Batch::finalize(const std::vector<int>& slots) {

@@ -202,7 +202,8 @@ __global__ void check_fiber_kernel(const int32_t* __restrict__ fib, int64_t n, i
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 
-Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks) {
+Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks,
+                         int min_tiles_small) {
     Partition p{};
     p.R = R;
     p.n_t = n_t;
@@ -215,8 +216,8 @@ Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks)
         return p;
     }
     int64_t ch = (target_blocks + p.n_tblocks - 1) / p.n_tblocks;
-    // few target blocks (a small, latency-bound problem): down to one tile per chunk
-    const int64_t min_tiles = p.n_tblocks >= 64 ? MIN_TILES_PER_CHUNK : 1;
+    // few target blocks (a small, latency-bound problem): shorter chunks
+    const int64_t min_tiles = p.n_tblocks >= 64 ? MIN_TILES_PER_CHUNK : min_tiles_small;
     ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / min_tiles));
     ch = std::max<int64_t>(1, std::min<int64_t>(ch, p.n_tiles));
     p.tiles_per_chunk = (int32_t)((p.n_tiles + ch - 1) / ch);

@@ -43,7 +43,7 @@ class Diag(ctypes.Structure):
 class SessionCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
                 ("max_queue", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("step_pairs", ctypes.c_int64)]
 
 
 class SolveReq(ctypes.Structure):
@@ -273,10 +273,12 @@ class Session:
     """Continuous-batching mobility-solve session (host arrays in, host arrays out)."""
 
     def __init__(self, hbm_budget_bytes=4 << 30, max_slots=64, max_queue=4096, mixed=False,
-                 doublet=True, device=0):
+                 doublet=True, device=0, step_pairs=0):
+        """step_pairs: single-layer pairs one request may take per step (0: the
+        library default, < 0: a whole matvec per step)."""
         cfg = SessionCfg(int(hbm_budget_bytes), int(max_slots), int(max_queue),
                          (PREC_MIXED if mixed else PREC_FP64) | (0 if doublet else NO_DOUBLET),
-                         int(device))
+                         int(device), int(step_pairs))
         self._h = ctypes.c_void_p()
         _check(_lib.stokes_session_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._shapes = {}

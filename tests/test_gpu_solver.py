@@ -103,6 +103,45 @@ def test_session_mixed_alone_equals_mix(S):
         assert np.array_equal(a, m)
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_session_split_matvecs_are_bitwise_unchanged(S, mixed):
+    # a pair budget far below one matvec spreads every single-layer sum over
+    # many steps; the items write disjoint partials, so nothing changes
+    reqs = [W.serving_request(13, rid, n_fib=n, nodes=p, iters=k)
+            for rid, (n, p, k) in enumerate([(300, 32, 12), (20, 16, 15), (90, 64, 10)])]
+    out = {}
+    for sp in (-1, 0, 2_000_000):
+        with S.Session(hbm_budget_bytes=1 << 30, max_slots=4, mixed=mixed, step_pairs=sp) as s:
+            ts = [_submit(s, r) for r in reqs]
+            out[sp] = [s.wait(t) for t in ts]
+    # one work item per step (the 320-node request: 20 items per matvec)
+    with S.Session(hbm_budget_bytes=1 << 30, max_slots=4, mixed=mixed, step_pairs=1) as s:
+        out[1] = [s.wait(_submit(s, reqs[1]))]
+    for sp in (0, 2_000_000, 1):
+        ref = out[-1] if sp != 1 else out[-1][1:2]
+        for (a, sa), (b, sb) in zip(ref, out[sp]):
+            assert np.array_equal(a, b), f"step_pairs={sp} changed a result"
+            assert sa["iters"] == sb["iters"] and sa["residual"] == sb["residual"]
+
+
+def test_session_alone_equals_mix_serving_distribution(S):
+    # 56 requests drawn like the serving stream (sizes 512 to 131k nodes), submitted
+    # in three waves into 64 slots and a 4 GiB budget, against each run alone
+    reqs = [W.serving_request(3, 30000 + rid) for rid in range(56)]
+    with S.Session(hbm_budget_bytes=4 << 30, max_slots=1, mixed=True) as s1:
+        alone = [s1.wait(_submit(s1, r)) for r in reqs]
+    with S.Session(hbm_budget_bytes=4 << 30, max_slots=64, mixed=True) as sm:
+        ts = []
+        for wave in (reqs[:20], reqs[20:40], reqs[40:]):
+            ts += [_submit(sm, r) for r in wave]
+            time.sleep(0.01)
+        mix = [sm.wait(t) for t in ts]
+    for r, (a, sa), (m, sm_) in zip(reqs, alone, mix):
+        assert np.array_equal(a, m), f"request {r['rid']} differs alone vs in the mix"
+        assert sa["iters"] == sm_["iters"] == r["iters"]
+        assert np.all(np.isfinite(a))
+
+
 def test_session_budget_binds_and_errors(S):
     reqs = [W.serving_request(5, rid, n_fib=n, nodes=32, iters=20)
             for rid, n in enumerate([100, 120, 80, 110])]
