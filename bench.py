@@ -39,7 +39,12 @@ NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go 
 # 256 MiB (FETCH x 1.99977, WRITE x 0.99998); see
 # profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
 # sources with this digest: after any change the field reports null.
-TRAFFIC = {"digest": "a2dba041d59ff552", "bytes": 540350403}
+TRAFFIC = {"digest": "59f6b4305be9e990", "bytes": 540349496}
+# VALU flops per pair from rocprofv3 instruction counters of the same kernel sources
+# (64 x (2 FMA + MUL + ADD + TRANS) of the kernel's precision, per dispatch, over the
+# pairs of one launch); see profiles/sl_spindle_262k_valu_counters.md.  Combined with
+# the live kernel time they give the counter-based fraction of peak.
+VALU_FLOPS_PER_PAIR = {"digest": "59f6b4305be9e990", "mixed": 34.70, "fp64": 42.25}
 KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
                   "paper_1602_05650_amd/csrc/stokes_sums.hip",
                   "paper_1602_05650_amd/csrc/stokes_internal.hpp"]
@@ -55,6 +60,13 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
+def counter_fpp(mixed):
+    """Counter-measured VALU flops per pair, or None once the kernel sources changed."""
+    if kernel_digest() != VALU_FLOPS_PER_PAIR["digest"]:
+        return None
+    return VALU_FLOPS_PER_PAIR["mixed" if mixed else "fp64"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +76,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-other", action="store_true",
+                    help="time the oracle on the headline workload only")
     ap.add_argument("--only", choices=["mixed", "fp64", "both", "none"], default="both")
     ap.add_argument("--extra", default="c0,c1,c4",
                     help="other workloads timed after the headline (c0,c1,c4 or none)")
@@ -105,11 +119,21 @@ def time_matvecs(S, torch, xyz, forces, fib, flen, eps, mixed, steps, warmup):
     return t1 - t0, ms, launches, first
 
 
+_CONFIGS = {}
+
+
+def load_config(name):
+    """Seeded workload by short name (generated once per process)."""
+    from paper_1602_05650_amd import workloads as W
+    if name not in _CONFIGS:
+        _CONFIGS[name] = {"c0": W.config0, "c1": W.config1, "c4": W.config4}[name]()
+    return _CONFIGS[name]
+
+
 def config_run(S, torch, name, steps, warmup, log_fn):
     """Time the single layer (and, when the config has a sphere, the double layer) to all
     targets, for both precisions; report Gpair/s per sum and the mixed-vs-FP64 error."""
-    from paper_1602_05650_amd import workloads as W
-    c = {"c0": W.config0, "c1": W.config1, "c4": W.config4}[name]()
+    c = load_config(name)
     fs = c["fibers"]
     dev = torch.device("cuda:0")
     d = lambda a, t=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, t)
@@ -232,27 +256,87 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
     }
 
 
-def cpu_baseline(c, seconds, log_fn):
+def cpu_baseline(c, seconds, log_fn, other=True):
+    """The oracle (plain FP64 double loop, OpenMP over targets) on seeded samples of the
+    headline workload: about 60% of `seconds` on all host threads, 25% on one thread;
+    then, if `other`, the smaller workloads in full and a large one on a sample."""
     import oracle
     oracle.build(force=False)
     fs = c["fibers"]
     nthreads = max(1, min(16, os.cpu_count() or 1))
     from paper_1602_05650_amd import workloads as W
     idx = W.subsample(2, fs.n, 65536)
-    kw = dict(src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps, excl=1, nthreads=nthreads)
-    t0 = time.perf_counter()
-    oracle.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx[:32]], trg_self=idx[:32], **kw)
-    dt = time.perf_counter() - t0
-    n_t = int(min(len(idx), max(64, 32 * seconds / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx[:n_t]], trg_self=idx[:n_t], **kw)
-    dt = time.perf_counter() - t0
+    kw = dict(src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps, excl=1)
+
+    def timed(n_t, threads):
+        t0 = time.perf_counter()
+        oracle.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx[:n_t]], trg_self=idx[:n_t],
+                  nthreads=threads, **kw)
+        return time.perf_counter() - t0
+
+    def sized(threads, budget):
+        n_t = 64 * threads
+        dt = timed(n_t, threads)
+        while dt < 0.5 and n_t < len(idx):       # calibrate on a run of at least 0.5 s
+            n_t = min(len(idx), n_t * 4)
+            dt = timed(n_t, threads)
+        n_t = int(min(len(idx), max(n_t, n_t * budget / max(dt, 1e-6))))
+        return n_t, timed(n_t, threads)
+
+    n_t, dt = sized(nthreads, 0.6 * seconds)
     pairs = n_t * (fs.n - 1)
     log_fn(f"cpu oracle: {n_t} targets x {fs.n} sources in {dt:.2f} s on {nthreads} threads")
-    return {"value": round(pairs / dt / 1e9, 4), "unit": "Gpair/s", "cores": nthreads,
-            "kind": "oracle",
-            "sample": f"{n_t} seeded targets of the spindle workload x all {fs.n} sources, "
-                      f"FP64 brute force, self-pairs excluded ({dt:.1f} s)"}
+    n1, dt1 = sized(1, 0.25 * seconds)
+    log_fn(f"cpu oracle: {n1} targets x {fs.n} sources in {dt1:.2f} s on 1 thread")
+    out = {"value": round(pairs / dt / 1e9, 4), "unit": "Gpair/s", "cores": nthreads,
+           "kind": "oracle",
+           "sample": f"{n_t} seeded targets of the spindle workload x all {fs.n} sources, "
+                     f"FP64 brute force, self-pairs excluded ({dt:.1f} s)",
+           "single_thread": {"value": round(n1 * (fs.n - 1) / dt1 / 1e9, 4), "unit": "Gpair/s",
+                             "cores": 1, "sample": f"{n1} seeded targets ({dt1:.1f} s)"}}
+    if other:
+        out["other_workloads"] = {}
+        for name, label, n_sample in (("c0", "cloud_512", None), ("c1", "confined_32k", None),
+                                      ("c4", "confined_524k", 4096)):
+            out["other_workloads"][label] = cpu_config(load_config(name), n_sample, nthreads)
+            log_fn(f"cpu oracle {label}: {out['other_workloads'][label]}")
+    return out
+
+
+def cpu_config(c, n_sample, nthreads):
+    """Oracle Gpair/s of the single (and double) layer of one workload to all targets, or
+    to n_sample seeded targets of each kind."""
+    import oracle
+    from paper_1602_05650_amd import workloads as W
+    fs = c["fibers"]
+    sph = c.get("sphere")
+    fi = np.arange(fs.n) if n_sample is None else W.subsample(4, fs.n, n_sample)
+    res = {"targets": "all" if n_sample is None else f"{len(fi)} fiber"}
+    t0 = time.perf_counter()
+    oracle.sl(fs.xyz, c["force"], src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps, excl=1,
+              trg_xyz=fs.xyz[:, fi], trg_self=fi, nthreads=nthreads)
+    t_sl = time.perf_counter() - t0
+    pairs_sl = len(fi) * (fs.n - 1)
+    if sph is not None:
+        si = np.arange(sph.n) if n_sample is None else W.subsample(5, sph.n, n_sample)
+        if n_sample is not None:
+            res["targets"] += f" + {len(si)} sphere"
+        t0 = time.perf_counter()
+        oracle.sl(fs.xyz, c["force"], src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps,
+                  excl=1, trg_xyz=sph.xyz[:, si], nthreads=nthreads)
+        oracle.dl(sph.xyz, sph.normal, sph.weight, c["q"], trg_xyz=fs.xyz[:, fi],
+                  subtract=False, nthreads=nthreads)
+        oracle.dl(sph.xyz, sph.normal, sph.weight, c["q"], trg_xyz=sph.xyz[:, si], trg_self=si,
+                  subtract=True, nthreads=nthreads)
+        t_rest = time.perf_counter() - t0
+        pairs_sl += len(si) * fs.n
+        pairs_dl = (len(fi) + len(si)) * sph.n - len(si)
+        res["sl_plus_dl_gpair_per_s"] = round((pairs_sl + pairs_dl) / (t_sl + t_rest) / 1e9, 4)
+        res["seconds"] = round(t_sl + t_rest, 2)
+    else:
+        res["sl_gpair_per_s"] = round(pairs_sl / t_sl / 1e9, 4)
+        res["seconds"] = round(t_sl, 3)
+    return res
 
 
 def main():
@@ -343,6 +427,9 @@ def main():
             "kernel": "sl_mixed_kernel" if head else "sl_fp64_kernel",
             "flops_per_pair": FLOPS_PER_PAIR_SL,
             "kernel_ms": round(k_avg * 1e3, 4),
+            "counter_flops_per_pair": counter_fpp(head),
+            "counter_frac": (round(pairs * counter_fpp(head) / k_avg / 1e12 / peak, 4)
+                             if counter_fpp(head) else None),
             "peak_basis": "published vector peak of the kernel's precision (FP32 for the mixed "
                           "kernel: 256 CUs x 128 FP32 lanes x 2 flops x 2.4 GHz)",
         },
@@ -358,6 +445,9 @@ def main():
             "ms_per_step": round(f64["sec"] / args.steps * 1e3, 3),
             "kernel_ms": round(k64 * 1e3, 4), "achieved_tflops": round(a64, 2),
             "frac_of_fp64_peak": round(a64 / PEAK_FP64, 4),
+            "counter_flops_per_pair": counter_fpp(False),
+            "counter_frac": (round(pairs * counter_fpp(False) / k64 / 1e12 / PEAK_FP64, 4)
+                             if counter_fpp(False) else None),
         }
         out["mixed_over_fp64"] = round(f64["sec"] / res[True]["sec"], 3)
         out["err_mixed_vs_fp64_relmax"] = float(f"{np.abs(u32 - u64).max() / np.abs(u64).max():.3e}")
@@ -374,7 +464,7 @@ def main():
             out["serving"] = {"error": repr(e)}
             log("serving run failed:", repr(e))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, log)
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, log, not args.no_cpu_other)
     print(json.dumps(out), flush=True)
 
 
