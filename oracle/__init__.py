@@ -15,11 +15,17 @@ Contents
     block-Jacobi preconditioner, eq. prec, in their local form).
   * ``clenshaw_curtis``: Clenshaw-Curtis weights on CGL nodes (section
     "Integration over fiber centerlines"), as the interpolatory rule.
+  * ``nonlocal_sbt``: the regularised finite-part self-interaction K_delta of
+    eq. sb-stokes-reg on each fiber, with the Clenshaw-Curtis rule of section
+    "Integration over fiber centerlines" (the s' = s term vanishes: both parts of
+    the integrand tend to (I + X_s X_s) f(s) / (8 pi mu delta) there).
+  * ``fiber_block_solve``: the fiber block-Jacobi preconditioner of section
+    "Linear solver and preconditioner": each fiber's self block M + K_delta is
+    formed column by column and solved with numpy.linalg.solve.
   * ``mobility_apply`` / ``gmres``: the fiber mobility operator
-    A f = M f + u_bar[f] (eq. main-sb-local without the finite-part term, with
-    the complementary flow of eq. complementary-uf: all other fibers) and
-    right-preconditioned GMRES (Saad) with classical Gram-Schmidt applied twice
-    and Givens rotations.
+    A f = M f [+ K_delta f] + u_bar[f] (eq. main-sb-local, with the complementary
+    flow of eq. complementary-uf: all other fibers) and right-preconditioned
+    GMRES (Saad) with classical Gram-Schmidt applied twice and Givens rotations.
 
 Nothing here is blocked, fused or reordered beyond the definitions.
 """
@@ -200,14 +206,95 @@ def fiber_quadrature_weights(fiber, fiber_len, nodes_per_fiber):
 # Fiber mobility operator and GMRES.
 # ---------------------------------------------------------------------------
 
+def fiber_arclength(fiber, fiber_len, nodes_per_fiber):
+    """Arc length s of every node: node k of a fiber sits at alpha_k = cos(k pi / p),
+    s = (L/2)(1 + alpha_k), so node 0 is the plus end s = L."""
+    p = nodes_per_fiber - 1
+    fiber = np.asarray(fiber)
+    kk = np.arange(fiber.shape[0]) % nodes_per_fiber
+    return 0.5 * np.asarray(fiber_len, dtype=np.float64)[fiber] * (1.0 + np.cos(kk * np.pi / p))
+
+
+def nonlocal_sbt(f, xyz, tangent, fiber, fiber_len, nodes_per_fiber, delta, mu=1.0):
+    """K_delta[f] at every node (eq. sb-stokes-reg): over the node's own fiber,
+
+        sum_{k != i} w_k [ |r|/sqrt(|r|^2 + delta^2) G(r) f_k
+                           - (I + t_i t_i) f_i / (8 pi mu sqrt((s_i - s_k)^2 + delta^2)) ],
+
+    r = X_i - X_k, G(r) = (I/|r| + r r/|r|^3)/(8 pi mu), w_k the Clenshaw-Curtis
+    weight times L/2 and s the arc length.  Plain loops over fibers and node pairs."""
+    f = np.asarray(f, dtype=np.float64)
+    X = np.asarray(xyz, dtype=np.float64)
+    t = np.asarray(tangent, dtype=np.float64)
+    fiber = np.asarray(fiber)
+    w = fiber_quadrature_weights(fiber, fiber_len, nodes_per_fiber)
+    s = fiber_arclength(fiber, fiber_len, nodes_per_fiber)
+    c = 1.0 / (8.0 * math.pi * mu)
+    out = np.zeros_like(f)
+    n_fib = int(fiber.max()) + 1 if fiber.size else 0
+    for m in range(n_fib):
+        idx = np.nonzero(fiber == m)[0]
+        for i in idx:
+            ks = idx[idx != i]                                      # the s' = s term is zero
+            ti = t[:, i]
+            proj_fi = f[:, i] + ti * np.dot(ti, f[:, i])           # (I + t_i t_i) f_i
+            r = X[:, i:i + 1] - X[:, ks]                            # (3, n-1)
+            rn = np.sqrt(np.sum(r * r, axis=0))
+            rf = np.sum(r * f[:, ks], axis=0)
+            G_fk = c * (f[:, ks] / rn + r * (rf / rn ** 3))
+            phi = rn / np.sqrt(rn * rn + delta * delta)
+            psi = 1.0 / np.sqrt((s[i] - s[ks]) ** 2 + delta * delta)
+            out[:, i] = np.sum(w[ks] * (phi * G_fk - c * proj_fi[:, None] * psi), axis=1)
+    return out
+
+
+def fiber_blocks(xyz, tangent, fiber, fiber_len, nodes_per_fiber, eps, mu=1.0, delta=None):
+    """Self block M [+ K_delta] of every fiber, as (node indices, 3n x 3n matrix) with
+    row and column index c n + k (component c of the fiber's node k).  Each column is
+    the operator applied to a unit vector of the fiber."""
+    fiber = np.asarray(fiber)
+    blocks = []
+    n_fib = int(fiber.max()) + 1 if fiber.size else 0
+    for m in range(n_fib):
+        idx = np.nonzero(fiber == m)[0]
+        n = idx.size
+        X, t = np.asarray(xyz)[:, idx], np.asarray(tangent)[:, idx]
+        fl = np.asarray(fiber_len, dtype=np.float64)[m: m + 1]
+        fb = np.zeros(n, dtype=np.int64)
+        B = np.empty((3 * n, 3 * n))
+        for col in range(3 * n):
+            e = np.zeros((3, n))
+            e.flat[col] = 1.0
+            Ae = local_sbt(e, t, eps, mu)
+            if delta is not None:
+                Ae = Ae + nonlocal_sbt(e, X, t, fb, fl, nodes_per_fiber, delta, mu)
+            B[:, col] = Ae.ravel()
+        blocks.append((idx, B))
+    return blocks
+
+
+def fiber_block_solve(v, blocks):
+    """Block-Jacobi preconditioner: z with B_m z_m = v_m on every fiber m (Gaussian
+    elimination, numpy.linalg.solve), blocks from ``fiber_blocks``."""
+    v = np.asarray(v, dtype=np.float64)
+    out = np.empty_like(v)
+    for idx, B in blocks:
+        out[:, idx] = np.linalg.solve(B, v[:, idx].ravel()).reshape(3, idx.size)
+    return out
+
+
 def mobility_apply(f, xyz, tangent, fiber, fiber_len, nodes_per_fiber, eps, mu=1.0,
-                   doublet=True, nthreads=1):
-    """A f = M f + u_bar[f]: local SBT term plus the flow of all other fibers
-    (Clenshaw-Curtis-weighted Stokeslet + doublet sum, own fiber excluded)."""
+                   doublet=True, nthreads=1, delta=None):
+    """A f = M f [+ K_delta f] + u_bar[f]: local SBT term, the nonlocal self term when
+    delta is given, and the flow of all other fibers (Clenshaw-Curtis-weighted
+    Stokeslet + doublet sum, own fiber excluded)."""
     w = fiber_quadrature_weights(fiber, fiber_len, nodes_per_fiber)
     u = sl(xyz, f, src_weight=w, src_fiber=fiber, fiber_len=fiber_len, mu=mu, eps=eps,
            excl=EXCL_SAME_FIBER, doublet=doublet, nthreads=nthreads)
-    return local_sbt(f, tangent, eps, mu) + u
+    out = local_sbt(f, tangent, eps, mu) + u
+    if delta is not None:
+        out = out + nonlocal_sbt(f, xyz, tangent, fiber, fiber_len, nodes_per_fiber, delta, mu)
+    return out
 
 
 def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, k: int,
@@ -268,16 +355,26 @@ def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, k: int,
 
 
 def mobility_solve(rhs, xyz, tangent, fiber, fiber_len, nodes_per_fiber, eps, iters, mu=1.0,
-                   doublet=True, nthreads=1):
-    """GMRES on A f = V with the local-SBT (block-Jacobi) right preconditioner."""
+                   doublet=True, nthreads=1, delta=None, precond="local"):
+    """GMRES on A f = V with a right preconditioner: "local" applies M^{-1} node by
+    node, "block" solves each fiber's self block M [+ K_delta].  delta given: the
+    operator includes the nonlocal self term K_delta."""
     shape = np.asarray(rhs).shape
 
     def A(v):
         return mobility_apply(v.reshape(shape), xyz, tangent, fiber, fiber_len, nodes_per_fiber,
-                              eps, mu, doublet, nthreads).ravel()
+                              eps, mu, doublet, nthreads, delta).ravel()
 
-    def Pinv(v):
-        return local_sbt_inv_closed(v.reshape(shape), tangent, eps, mu).ravel()
+    if precond == "block":
+        blocks = fiber_blocks(xyz, tangent, fiber, fiber_len, nodes_per_fiber, eps, mu, delta)
+
+        def Pinv(v):
+            return fiber_block_solve(v.reshape(shape), blocks).ravel()
+    elif precond == "local":
+        def Pinv(v):
+            return local_sbt_inv_closed(v.reshape(shape), tangent, eps, mu).ravel()
+    else:
+        raise ValueError(f"unknown preconditioner {precond!r}")
 
     x, hist, m = gmres(A, np.asarray(rhs).ravel(), iters, Pinv)
     return x.reshape(shape), hist, m
