@@ -79,6 +79,8 @@ extern "C" {
 #define STOKES_ACCUMULATE      16u   /* add into u_out instead of overwriting it */
 #define STOKES_CHECK_INPUTS    32u   /* scan device inputs first (finite values, fiber ids); synchronous */
 #define STOKES_ONSURF_RAW      64u   /* double layer: no singularity subtraction on the surface */
+#define STOKES_NONLOCAL       128u   /* mobility solve: include the nonlocal self term K_delta */
+#define STOKES_PRECOND_BLOCK  256u   /* mobility solve: fiber block-Jacobi preconditioner */
 
 /* Optional counters filled by the *_eval calls (passing one makes the call synchronous). */
 typedef struct stokes_diag {
@@ -175,23 +177,45 @@ int stokes_local_sbt(int64_t n, const double* tangent, const double* f, double e
                      int inverse, double* out, void* stream);
 
 /*
+ * stokes_nonlocal_sbt -- the regularised nonlocal self-interaction of every
+ * fiber (eq. sb-stokes-reg), FP64:
+ *   out_i = sum over the other nodes k of node i's fiber of
+ *           w_k [ |r|/sqrt(|r|^2 + delta^2) G(r) f_k
+ *                 - (I + t_i t_i) f_i / (8 pi mu sqrt((s_i - s_k)^2 + delta^2)) ],
+ *   r = X_i - X_k, G(r) = (I/|r| + r r/|r|^3)/(8 pi mu), w_k the Clenshaw-Curtis
+ *   weight x L/2 (section "Integration over fiber centerlines") and s_k = (L/2)(1 +
+ *   alpha_k) the arc length; the s' = s node contributes nothing (both parts of the
+ *   integrand have the same limit there).
+ * n_fib, nodes_per_fib (2..64), xyz, tangent, f, out [3*N] SoA as for the mobility
+ * solve, fiber_len [n_fib]; delta > 0, mu > 0.  out must not alias f.  Uses the
+ * stream's workspace; asynchronous on stream.
+ */
+int stokes_nonlocal_sbt(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
+                        const double* tangent, const double* fiber_len, const double* f,
+                        double delta, double mu, double* out, void* stream);
+
+/*
  * stokes_mobility_solve -- fiber mobility solve on device pointers.
  *
- * Finds forces f with  M f + u_bar[f] = V  at every fiber node, where M is the
- * local slender-body operator (eq. main-sb-local, without the finite-part
- * term) and u_bar[f] the flow of all OTHER fibers (eq. complementary-uf):
- * the Stokeslet + doublet sum with Clenshaw-Curtis weights x L/2 and the own
- * fiber excluded.  Right-preconditioned GMRES (section "Linear solver and
- * preconditioner") with the local blocks M^{-1} as preconditioner, x0 = 0,
- * classical Gram-Schmidt applied twice, Givens rotations, in FP64; `iters`
- * iterations unless the Krylov space is exhausted (exact breakdown).
+ * Finds forces f with  M f [+ K_delta f] + u_bar[f] = V  at every fiber node,
+ * where M is the local slender-body operator (eq. main-sb-local), K_delta the
+ * nonlocal self term (eq. sb-stokes-reg; with STOKES_NONLOCAL) and u_bar[f] the
+ * flow of all OTHER fibers (eq. complementary-uf): the Stokeslet + doublet sum
+ * with Clenshaw-Curtis weights x L/2 and the own fiber excluded.
+ * Right-preconditioned GMRES (section "Linear solver and preconditioner"),
+ * x0 = 0, classical Gram-Schmidt applied twice, Givens rotations, in FP64;
+ * `iters` iterations unless the Krylov space is exhausted (exact breakdown).
+ * Preconditioner: the local node blocks M^{-1}, or with STOKES_PRECOND_BLOCK
+ * each fiber's self block M [+ K_delta] inverted once (Gauss-Jordan with partial
+ * pivoting, FP64) and applied as a dense product.
  *
  * n_fib, nodes_per_fib   fibers and CGL nodes per fiber (2..64); N = n_fib*nodes_per_fib.
  * xyz, tangent           [3*N] node positions and unit tangents, fiber-contiguous,
  *                        node k of a fiber at alpha_k = cos(k pi/(nodes-1)).
  * fiber_len              [n_fib] lengths.     rhs  [3*N] fiber velocities V.
+ * delta                  regularisation of K_delta (> 0 with STOKES_NONLOCAL, else unused).
  * iters                  1..STOKES_MAX_ITERS.  flags: STOKES_PREC_* for the sums,
- *                        STOKES_NO_DOUBLET.
+ *                        STOKES_NO_DOUBLET, STOKES_NONLOCAL, STOKES_PRECOND_BLOCK.
  * f_out                  [3*N] forces.   resid_out: NULL or host double, the final
  *                        least-squares residual norm.  iters_out: NULL or host int.
  * Synchronous (waits for the stream at the end).
@@ -199,7 +223,7 @@ int stokes_local_sbt(int64_t n, const double* tangent, const double* f, double e
 #define STOKES_MAX_ITERS 128
 int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
                           const double* tangent, const double* fiber_len, const double* rhs,
-                          double eps, double mu, int32_t iters, uint32_t flags,
+                          double eps, double mu, double delta, int32_t iters, uint32_t flags,
                           double* f_out, double* resid_out, int32_t* iters_out, void* stream);
 
 /* ---- serving: continuous batching of mobility solves ------------------- */
@@ -231,6 +255,8 @@ typedef struct stokes_solve_req {   /* HOST pointers; copied by stokes_session_s
     double mu;
     int32_t iters;                  /* GMRES iterations, 1..STOKES_MAX_ITERS */
     uint64_t tag;                   /* returned in the stats */
+    uint32_t flags;                 /* STOKES_NONLOCAL, STOKES_PRECOND_BLOCK (or 0) */
+    double delta;                   /* K_delta regularisation (> 0 with STOKES_NONLOCAL) */
 } stokes_solve_req;
 
 typedef struct stokes_solve_stats {
@@ -255,7 +281,9 @@ int stokes_session_submit(stokes_session* s, const stokes_solve_req* req, uint64
 int stokes_session_wait(stokes_session* s, uint64_t ticket, double* f_out,
                         stokes_solve_stats* st, int32_t timeout_ms);
 /* Device bytes a request of this shape takes from a session's budget (flags:
- * the session's STOKES_PREC_*).  Returns 0 for invalid shapes. */
+ * the session's STOKES_PREC_* and the request's STOKES_PRECOND_BLOCK, whose
+ * inverted fiber blocks take 72 nodes_per_fib^2 bytes per fiber).  Returns 0 for
+ * invalid shapes. */
 int64_t stokes_solve_footprint(int32_t n_fib, int32_t nodes_per_fib, int32_t iters, uint32_t flags);
 /* Test hook for failure handling: the session's next step reports a device
  * error for every request then in flight (their waits return STOKES_E_DEVICE);

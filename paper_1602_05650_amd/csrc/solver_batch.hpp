@@ -32,7 +32,10 @@ struct SlotDesc {
     int32_t n_items_node; // ceil(N / 256)
     int32_t n_items_sl;   // SL work items (target blocks x chunks)
     int32_t sid;          // slot index (row of the status table)
+    uint32_t opts;        // STOKES_NONLOCAL | STOKES_PRECOND_BLOCK
+    int32_t pad0;
     double eps, mu, kappa, pref, near_r;
+    double delta;         // K_delta regularisation
     SumArgs sl;           // single-layer sum over the slot's own nodes
     const double* xyz;    // [3][N]
     const double* tan;    // [3][N]
@@ -40,6 +43,9 @@ struct SlotDesc {
     const double* rhs;    // [3][N]
     int32_t* fib;         // [N]
     double* wq;           // [N] Clenshaw-Curtis weight x L/2
+    double* sarc;         // [N] arc length s = (L/2)(1 + alpha_k)
+    double* binv;         // [n_fib][3 npf][3 npf] inverse self blocks, column-major
+                          // (row and column index c npf + k), or null
     double* V;            // [(k+1)][3N]
     double* z;            // [3][N]  M^{-1} v_j
     double* w;            // [3][N]
@@ -79,6 +85,7 @@ enum WL {
     WL_DOT,      // partial dots of V[0..j] with w         items: B
     WL_ONE,      // one block per slot (reductions, Givens) items: 1
     WL_VEC,      // elementwise over 3N                    items: ceil(3N/256)
+    WL_FIB,      // one block per fiber (block-Jacobi set-up) items: n_fib or 0
     WL_COUNT
 };
 
@@ -94,7 +101,7 @@ struct SlotPlan {
     int32_t B;
     size_t bytes;
 };
-SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed);
+SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed, uint32_t opts);
 
 class Batch {
 public:
@@ -106,9 +113,10 @@ public:
     // Lay a request out in `mem` (slot_plan bytes) and copy its inputs there
     // (hipMemcpyDefault: host inputs must be pinned for the copy to be async).
     int attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, double eps, double mu,
-               double near_r, const double* xyz, const double* tan, const double* flen,
-               const double* rhs);
-    // Geometry set-up, beta = |rhs| and v_0 for newly attached slots.
+               double near_r, uint32_t opts, double delta, const double* xyz,
+               const double* tan, const double* flen, const double* rhs);
+    // Geometry set-up (and the inverted fiber blocks), beta = |rhs| and v_0 for
+    // newly attached slots.
     int start(const std::vector<int>& slots);
     // One GMRES iteration for every listed slot, then read the status rows back.
     int step(const std::vector<int>& slots);

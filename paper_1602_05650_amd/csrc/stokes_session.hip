@@ -93,7 +93,8 @@ struct Request {
     uint64_t ticket = 0;
     int32_t n_fib = 0, npf = 0, k = 0;
     int64_t N = 0;
-    double eps = 0, mu = 0;
+    double eps = 0, mu = 0, delta = 0;
+    uint32_t opts = 0;            // STOKES_NONLOCAL | STOKES_PRECOND_BLOCK
     uint64_t tag = 0;
     size_t bytes = 0;
     double* host = nullptr;       // pinned: xyz | tan | rhs | flen | result
@@ -224,7 +225,8 @@ static void worker_main(stokes_session* s) {
         int rc = STOKES_OK;
         for (int q : admitted) {
             Request* r = slots[q];
-            rc = B.attach(q, r->mem, r->n_fib, r->npf, r->k, r->eps, r->mu, 0.0, r->xyz(), r->tan(),
+            rc = B.attach(q, r->mem, r->n_fib, r->npf, r->k, r->eps, r->mu, 0.0, r->opts, r->delta,
+                          r->xyz(), r->tan(),
                           r->flen(), r->rhs());
             if (rc) break;
         }
@@ -368,7 +370,12 @@ extern "C" int stokes_session_submit(stokes_session* s, const stokes_solve_req* 
         if (!std::isfinite(req->fiber_len[f]) || !(req->fiber_len[f] > 0.0))
             return fail(STOKES_E_INVAL, "stokes_session_submit: fiber lengths must be finite and > 0");
     const bool mixed = s->cfg.flags & STOKES_PREC_MIXED;
-    const size_t bytes = slot_plan(req->n_fib, req->nodes_per_fib, req->iters, mixed).bytes;
+    if (req->flags & ~(STOKES_NONLOCAL | STOKES_PRECOND_BLOCK))
+        return fail(STOKES_E_INVAL, "stokes_session_submit: unknown request flag bits");
+    if ((req->flags & STOKES_NONLOCAL) && (!(req->delta > 0.0) || !std::isfinite(req->delta)))
+        return fail(STOKES_E_INVAL, "stokes_session_submit: delta must be finite and > 0 with STOKES_NONLOCAL");
+    const size_t bytes =
+        slot_plan(req->n_fib, req->nodes_per_fib, req->iters, mixed, req->flags).bytes;
     if (bytes > s->arena.capacity())
         return fail(STOKES_E_NOMEM, "stokes_session_submit: request needs " + std::to_string(bytes) +
                                         " bytes, more than the session budget");
@@ -386,6 +393,8 @@ extern "C" int stokes_session_submit(stokes_session* s, const stokes_solve_req* 
     r->N = N;
     r->eps = req->eps;
     r->mu = req->mu;
+    r->opts = req->flags;
+    r->delta = req->delta;
     r->tag = req->tag;
     r->bytes = bytes;
     const size_t hb = sizeof(double) * (12 * N + r->n_fib);
@@ -492,7 +501,8 @@ extern "C" int64_t stokes_solve_footprint(int32_t n_fib, int32_t nodes_per_fib, 
     if (n_fib < 1 || nodes_per_fib < 2 || nodes_per_fib > 64 || iters < 1 || iters > STOKES_MAX_ITERS)
         return 0;
     if ((int64_t)n_fib * nodes_per_fib >= (int64_t)1 << 30) return 0;
-    return (int64_t)slot_plan(n_fib, nodes_per_fib, iters, flags & STOKES_PREC_MIXED).bytes;
+    return (int64_t)slot_plan(n_fib, nodes_per_fib, iters, flags & STOKES_PREC_MIXED,
+                              flags & STOKES_PRECOND_BLOCK).bytes;
 }
 
 extern "C" int stokes_session_inject_fault(stokes_session* s) {

@@ -1,9 +1,12 @@
 // Fiber mobility solve: right-preconditioned GMRES in FP64 on the device.
 //
-//   A f = M f + u_bar[f] = V           (eq. main-sb-local without the finite-part
-//                                       term; u_bar from all other fibers,
-//                                       eq. complementary-uf)
-//   P = M (the local 3x3 node blocks of the block-Jacobi preconditioner, eq. prec)
+//   A f = M f [+ K_delta f] + u_bar[f] = V    (eq. main-sb-local; K_delta the
+//                                       regularised nonlocal self term of
+//                                       eq. sb-stokes-reg; u_bar from all other
+//                                       fibers, eq. complementary-uf)
+//   P = M (the local 3x3 node blocks) or, block-Jacobi (section "Linear solver
+//       and preconditioner"), each fiber's self block M [+ K_delta], inverted
+//       once per request by Gauss-Jordan elimination
 //   GMRES (Saad) on A P^{-1} y = V from y0 = 0: Arnoldi with classical
 //   Gram-Schmidt applied twice, Givens rotations, x = P^{-1} V_m y.
 //
@@ -63,6 +66,60 @@ __device__ __forceinline__ void apply_local(double kap, double mu, bool inverse,
     fz = a * fz + b * tf * tz;
 }
 
+// K_delta[f] at node i (eq. sb-stokes-reg) over the other nodes of its fiber, with
+// the fiber's quadrature weights wq and arc lengths sarc.  |r|/sqrt(r^2+d^2) G(r) f_k
+// is written (f_k + r (r.f_k)/r^2) / (8 pi mu sqrt(r^2 + d^2)).
+__device__ void nonlocal_at(int64_t i, int64_t N, int npf, const double* xyz, const double* tan,
+                            const double* f, const double* wq, const double* sarc, double delta,
+                            double pref, double& ox, double& oy, double& oz) {
+    const int64_t f0 = (i / npf) * npf;
+    const double xi = xyz[i], yi = xyz[N + i], zi = xyz[2 * N + i];
+    const double si = sarc[i], d2 = delta * delta;
+    double ax = 0.0, ay = 0.0, az = 0.0, dsum = 0.0;
+    for (int k = 0; k < npf; ++k) {
+        const int64_t j = f0 + k;
+        if (j == i) continue;
+        const double rx = xi - xyz[j], ry = yi - xyz[N + j], rz = zi - xyz[2 * N + j];
+        const double fx = f[j], fy = f[N + j], fz = f[2 * N + j];
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        const double a = wq[j] / sqrt(r2 + d2);
+        const double b = a * (rx * fx + ry * fy + rz * fz) / r2;
+        ax += a * fx + b * rx;
+        ay += a * fy + b * ry;
+        az += a * fz + b * rz;
+        const double ds = si - sarc[j];
+        dsum += wq[j] / sqrt(ds * ds + d2);
+    }
+    const double tx = tan[i], ty = tan[N + i], tz = tan[2 * N + i];
+    const double fx = f[i], fy = f[N + i], fz = f[2 * N + i];
+    const double tf = tx * fx + ty * fy + tz * fz;
+    ox = pref * (ax - dsum * (fx + tf * tx));
+    oy = pref * (ay - dsum * (fy + tf * ty));
+    oz = pref * (az - dsum * (fz + tf * tz));
+}
+
+// (B_f^{-1} v) at node i of fiber f: rows c npf + kk of the fiber's inverse block
+// (column-major, m = 3 npf) against the fiber's 3 npf values of v.
+__device__ __forceinline__ void block_apply(const double* binv, int64_t i, int64_t N, int npf,
+                                            const double* v, double& ox, double& oy,
+                                            double& oz) {
+    const int f = (int)(i / npf), kk = (int)(i % npf), m = 3 * npf;
+    const double* A = binv + (int64_t)f * m * m;
+    const int64_t f0 = (int64_t)f * npf;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int col = 0; col < m; ++col) {
+        const int e = col / npf, k = col - e * npf;
+        const double vc = v[(int64_t)e * N + f0 + k];
+        const double* Ac = A + (int64_t)col * m + kk;
+        a0 = fma(Ac[0], vc, a0);
+        a1 = fma(Ac[npf], vc, a1);
+        a2 = fma(Ac[2 * npf], vc, a2);
+    }
+    ox = a0;
+    oy = a1;
+    oz = a2;
+}
+
 // Partial dot products of m vectors A[i] (stride) with w over block b's range,
 // eight vectors per pass (w is read once per pass).  Per vector the order of
 // the arithmetic is fixed: each thread's strided partial, then a fixed tree.
@@ -112,6 +169,7 @@ __global__ __launch_bounds__(BLOCK) void k_geom(const SlotDesc* D, const StepTab
             const int kk = (int)(i % d.npf);
             d.fib[i] = f;
             d.wq[i] = cc_weight(kk, d.npf - 1) * 0.5 * d.flen[f];
+            d.sarc[i] = 0.5 * d.flen[f] * (1.0 + cos(kk * 3.14159265358979323846 / (d.npf - 1)));
             d.excl[i] = make_int2(f * d.npf, f * d.npf + d.npf);
         }
     }
@@ -127,6 +185,110 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const SlotDesc* D, const StepTa
         if (t < d.sl.n_tiles)
             tile_prep_one((int)t, d.N, d.xyz, d.near_r, d.sl.s32 ? 2.0 * d.eps : 0.0, d.fib,
                           d.n_fib, d.flen, d.tiles);
+    }
+}
+
+// Self block M [+ K_delta] of one fiber (after k_geom), inverted in place by
+// Gauss-Jordan elimination with partial pivoting: one workgroup per fiber, the
+// matrix in the slot's binv buffer (column-major, m = 3 npf <= 192).
+__global__ __launch_bounds__(BLOCK) void k_block(const SlotDesc* D, const StepTables* T) {
+    __shared__ double rowp[192], colp[192], rv[BLOCK];
+    __shared__ int ri[BLOCK], perm[192];
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_FIB];
+    const int t = threadIdx.x;
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int f = (int)(it - wl->prefix[si]);
+        const int npf = d.npf, m = 3 * npf;
+        const int64_t N = d.N, f0 = (int64_t)f * npf;
+        double* A = d.binv + (int64_t)f * m * m;
+        const bool nl = d.opts & STOKES_NONLOCAL;
+        const double d2 = d.delta * d.delta;
+        for (int e = t; e < m * m; e += BLOCK) {
+            const int col = e / m, row = e - col * m;
+            const int c = row / npf, i = row - c * npf, ce = col / npf, k = col - ce * npf;
+            const int64_t gi = f0 + i, gk = f0 + k;
+            double v = 0.0;
+            if (i != k) {
+                if (nl) {
+                    const double rx = d.xyz[gi] - d.xyz[gk], ry = d.xyz[N + gi] - d.xyz[N + gk],
+                                 rz = d.xyz[2 * N + gi] - d.xyz[2 * N + gk];
+                    const double r[3] = {rx, ry, rz};
+                    const double r2 = rx * rx + ry * ry + rz * rz;
+                    v = d.pref * d.wq[gk] * ((c == ce ? 1.0 : 0.0) + r[c] * r[ce] / r2) /
+                        sqrt(r2 + d2);
+                }
+            } else {
+                const double tc = d.tan[c * N + gi], te = d.tan[ce * N + gi];
+                const double id = c == ce ? 1.0 : 0.0;
+                v = d.pref * ((d.kappa + 2.0) * id + (d.kappa - 2.0) * tc * te);
+                if (nl) {
+                    double dsum = 0.0;
+                    for (int q = 0; q < npf; ++q) {
+                        if (q == i) continue;
+                        const double ds = d.sarc[gi] - d.sarc[f0 + q];
+                        dsum += d.wq[f0 + q] / sqrt(ds * ds + d2);
+                    }
+                    v -= d.pref * dsum * (id + tc * te);
+                }
+            }
+            A[e] = v;
+        }
+        __syncthreads();
+        for (int p = 0; p < m; ++p) {
+            // pivot: largest |A[r][p]|, r >= p (smallest r on ties)
+            double bv = -1.0;
+            int bi = m;
+            for (int r = p + t; r < m; r += BLOCK) {
+                const double a = fabs(A[(int64_t)p * m + r]);
+                if (a > bv) { bv = a; bi = r; }
+            }
+            rv[t] = bv;
+            ri[t] = bi;
+            __syncthreads();
+            for (int h = BLOCK / 2; h > 0; h >>= 1) {
+                if (t < h && (rv[t + h] > rv[t] || (rv[t + h] == rv[t] && ri[t + h] < ri[t]))) {
+                    rv[t] = rv[t + h];
+                    ri[t] = ri[t + h];
+                }
+                __syncthreads();
+            }
+            const int pr = ri[0] < m ? ri[0] : p;   // (a column of NaN: no row qualifies)
+            if (t == 0) perm[p] = pr;
+            if (pr != p)
+                for (int col = t; col < m; col += BLOCK) {
+                    const double a = A[(int64_t)col * m + p];
+                    A[(int64_t)col * m + p] = A[(int64_t)col * m + pr];
+                    A[(int64_t)col * m + pr] = a;
+                }
+            __syncthreads();
+            const double inv = 1.0 / A[(int64_t)p * m + p];
+            for (int j = t; j < m; j += BLOCK) {
+                rowp[j] = j == p ? inv : A[(int64_t)j * m + p] * inv;
+                colp[j] = A[(int64_t)p * m + j];
+            }
+            __syncthreads();
+            for (int j = t; j < m; j += BLOCK) A[(int64_t)j * m + p] = rowp[j];
+            for (int e = t; e < m * m; e += BLOCK) {
+                const int j = e / m, r = e - j * m;
+                if (r == p) continue;
+                const double a = j == p ? 0.0 : A[e];
+                A[e] = a - colp[r] * rowp[j];
+            }
+            __syncthreads();
+        }
+        // undo the row interchanges on the columns, last first
+        for (int p = m - 1; p >= 0; --p) {
+            const int q = perm[p];
+            if (q != p)
+                for (int r = t; r < m; r += BLOCK) {
+                    const double a = A[(int64_t)p * m + r];
+                    A[(int64_t)p * m + r] = A[(int64_t)q * m + r];
+                    A[(int64_t)q * m + r] = a;
+                }
+            __syncthreads();
+        }
     }
 }
 
@@ -177,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_v0(const SlotDesc* D, const Step
 }
 
 // ---- step kernels ------------------------------------------------------------------
-// z = M^{-1} v_j and the packed single-layer sources s = pref * wq * z.
+// z = P^{-1} v_j and the packed single-layer sources s = pref * wq * z.
 __global__ __launch_bounds__(BLOCK) void k_pre(const SlotDesc* D, const StepTables* T, int doublet) {
     const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
@@ -187,8 +349,15 @@ __global__ __launch_bounds__(BLOCK) void k_pre(const SlotDesc* D, const StepTabl
         if (i >= d.N) continue;
         const int64_t N = d.N;
         const double* v = d.V + (int64_t)d.j * 3 * N;
-        double fx = v[i], fy = v[N + i], fz = v[2 * N + i];
-        apply_local(d.kappa, d.mu, true, d.tan[i], d.tan[N + i], d.tan[2 * N + i], fx, fy, fz);
+        double fx, fy, fz;
+        if (d.opts & STOKES_PRECOND_BLOCK) {
+            block_apply(d.binv, i, N, d.npf, v, fx, fy, fz);
+        } else {
+            fx = v[i];
+            fy = v[N + i];
+            fz = v[2 * N + i];
+            apply_local(d.kappa, d.mu, true, d.tan[i], d.tan[N + i], d.tan[2 * N + i], fx, fy, fz);
+        }
         d.z[i] = fx;
         d.z[N + i] = fy;
         d.z[2 * N + i] = fz;
@@ -240,6 +409,13 @@ __global__ __launch_bounds__(BLOCK) void k_red(const SlotDesc* D, const StepTabl
         }
         double mx = d.z[i], my = d.z[N + i], mz = d.z[2 * N + i];
         apply_local(d.kappa, d.mu, false, d.tan[i], d.tan[N + i], d.tan[2 * N + i], mx, my, mz);
+        if (d.opts & STOKES_NONLOCAL) {
+            double kx, ky, kz;
+            nonlocal_at(i, N, d.npf, d.xyz, d.tan, d.z, d.wq, d.sarc, d.delta, d.pref, kx, ky, kz);
+            mx += kx;
+            my += ky;
+            mz += kz;
+        }
         d.w[i] = mx + u[0];
         d.w[N + i] = my + u[1];
         d.w[2 * N + i] = mz + u[2];
@@ -358,8 +534,8 @@ __global__ __launch_bounds__(BLOCK) void k_backsub(const SlotDesc* D, const Step
     }
 }
 
-// x = M^{-1} (V_m y) at every node.
-__global__ __launch_bounds__(BLOCK) void k_solution(const SlotDesc* D, const StepTables* T) {
+// w = V_m y at every node (w is free once the iterations are done).
+__global__ __launch_bounds__(BLOCK) void k_vy(const SlotDesc* D, const StepTables* T) {
     const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
@@ -375,11 +551,57 @@ __global__ __launch_bounds__(BLOCK) void k_solution(const SlotDesc* D, const Ste
             v[1] = fma(Vl[N + i], yl, v[1]);
             v[2] = fma(Vl[2 * N + i], yl, v[2]);
         }
-        apply_local(d.kappa, d.mu, true, d.tan[i], d.tan[N + i], d.tan[2 * N + i], v[0], v[1], v[2]);
-        d.x[i] = v[0];
-        d.x[N + i] = v[1];
-        d.x[2 * N + i] = v[2];
+        d.w[i] = v[0];
+        d.w[N + i] = v[1];
+        d.w[2 * N + i] = v[2];
     }
+}
+
+// x = P^{-1} w at every node.
+__global__ __launch_bounds__(BLOCK) void k_solution(const SlotDesc* D, const StepTables* T) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_PRE];
+    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
+        const int si = find_slot(wl, it);
+        const auto& d = as_const(D)[wl->slot[si]];
+        const int64_t i = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
+        if (i >= d.N) continue;
+        const int64_t N = d.N;
+        double x0, x1, x2;
+        if (d.opts & STOKES_PRECOND_BLOCK) {
+            block_apply(d.binv, i, N, d.npf, d.w, x0, x1, x2);
+        } else {
+            x0 = d.w[i];
+            x1 = d.w[N + i];
+            x2 = d.w[2 * N + i];
+            apply_local(d.kappa, d.mu, true, d.tan[i], d.tan[N + i], d.tan[2 * N + i], x0, x1, x2);
+        }
+        d.x[i] = x0;
+        d.x[N + i] = x1;
+        d.x[2 * N + i] = x2;
+    }
+}
+
+// ---- the nonlocal self term alone (stokes_nonlocal_sbt) --------------------------
+__global__ __launch_bounds__(BLOCK) void k_fiber_tables(int64_t N, int npf, const double* flen,
+                                                        double* wq, double* sarc) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= N) return;
+    const int f = (int)(i / npf), kk = (int)(i % npf);
+    wq[i] = cc_weight(kk, npf - 1) * 0.5 * flen[f];
+    sarc[i] = 0.5 * flen[f] * (1.0 + cos(kk * 3.14159265358979323846 / (npf - 1)));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_nonlocal_eval(int64_t N, int npf, const double* xyz,
+                                                         const double* tan, const double* f,
+                                                         const double* wq, const double* sarc,
+                                                         double delta, double pref, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= N) return;
+    double kx, ky, kz;
+    nonlocal_at(i, N, npf, xyz, tan, f, wq, sarc, delta, pref, kx, ky, kz);
+    out[i] = kx;
+    out[N + i] = ky;
+    out[2 * N + i] = kz;
 }
 
 // ---- host side ---------------------------------------------------------------------
@@ -390,7 +612,7 @@ static int32_t dot_blocks(int64_t n) {
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (n + 1023) / 1024));
 }
 
-SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed) {
+SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed, uint32_t opts) {
     SlotPlan sp{};
     const int64_t N = (int64_t)n_fib * npf;
     sp.P = make_partition(N, N, mixed ? R_SL32 : R_SL64, TARGET_BLOCKS_SLOT, MIN_TILES_PER_CHUNK);
@@ -404,6 +626,8 @@ SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed) {
     add(n * 8);               // rhs
     add(N * 4);               // fib
     add(N * 8);               // wq
+    add(N * 8);               // sarc
+    add((opts & STOKES_PRECOND_BLOCK) ? (size_t)n_fib * 9 * npf * npf * 8 : 0);  // binv
     add((size_t)(k + 1) * n * 8);  // V
     add(n * 8);               // z
     add(n * 8);               // w
@@ -456,9 +680,9 @@ int Batch::init(hipStream_t st, bool mixed, bool doublet, bool use_graph) {
 }
 
 int Batch::attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, double eps, double mu,
-                  double near_r, const double* xyz, const double* tan, const double* flen,
-                  const double* rhs) {
-    const SlotPlan sp = slot_plan(n_fib, npf, k, mixed_);
+                  double near_r, uint32_t opts, double delta, const double* xyz,
+                  const double* tan, const double* flen, const double* rhs) {
+    const SlotPlan sp = slot_plan(n_fib, npf, k, mixed_, opts);
     const int64_t N = (int64_t)n_fib * npf, n = 3 * N;
     Carve c(mem);
     SlotDesc d{};
@@ -472,6 +696,8 @@ int Batch::attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, doubl
     d.n_items_node = (int32_t)((N + BLOCK - 1) / BLOCK);
     d.n_items_sl = sp.P.n_tblocks * sp.P.n_chunks;
     d.sid = s;
+    d.opts = opts & (STOKES_NONLOCAL | STOKES_PRECOND_BLOCK);
+    d.delta = delta;
     d.eps = eps;
     d.mu = mu;
     d.kappa = -log(eps * eps * M_E);
@@ -487,6 +713,8 @@ int Batch::attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, doubl
     d.rhs = rhs_d;
     d.fib = c.take<int32_t>(N);
     d.wq = c.take<double>(N);
+    d.sarc = c.take<double>(N);
+    d.binv = (opts & STOKES_PRECOND_BLOCK) ? c.take<double>((size_t)n_fib * 9 * npf * npf) : nullptr;
     d.V = c.take<double>((size_t)(k + 1) * n);
     d.z = c.take<double>(n);
     d.w = c.take<double>(n);
@@ -548,6 +776,7 @@ void Batch::set_list(WL w, const std::vector<int>& slots) {
             case WL_DOT: items = d.B; break;
             case WL_ONE: items = 1; break;
             case WL_VEC: items = d.n_items_vec; break;
+            case WL_FIB: items = (d.opts & STOKES_PRECOND_BLOCK) ? d.n_fib : 0; break;
             default: break;
         }
         L.slot[q] = slots[q];
@@ -594,11 +823,14 @@ int Batch::start(const std::vector<int>& slots) {
     set_list(WL_DOT, slots);
     set_list(WL_ONE, slots);
     set_list(WL_VEC, slots);
+    set_list(WL_FIB, slots);
     int rc = upload();
     if (rc) return rc;
     const StepTables& T = *host_tab_;
     hipLaunchKernelGGL(k_geom, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_tiles, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    if (T.wl[WL_FIB].prefix[T.wl[WL_FIB].n] > 0)
+        hipLaunchKernelGGL(k_block, dim3(grid_for(T.wl[WL_FIB], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_init_norm, dim3(grid_for(T.wl[WL_DOT], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_init_beta, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_, dev_stat_);
     hipLaunchKernelGGL(k_init_v0, dim3(grid_for(T.wl[WL_VEC], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
@@ -695,6 +927,7 @@ int Batch::finalize(const std::vector<int>& slots) {
     if (rc) return rc;
     const StepTables& T = *host_tab_;
     hipLaunchKernelGGL(k_backsub, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_vy, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_solution, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
@@ -704,13 +937,44 @@ int Batch::finalize(const std::vector<int>& slots) {
 
 using namespace stokes;
 
+extern "C" int stokes_nonlocal_sbt(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
+                                   const double* tangent, const double* fiber_len, const double* f,
+                                   double delta, double mu, double* out, void* stream) {
+    if (n_fib < 0 || nodes_per_fib < 2 || nodes_per_fib > 64)
+        return fail(STOKES_E_INVAL, "stokes_nonlocal_sbt: need n_fib >= 0 and 2 <= nodes_per_fib <= 64");
+    if (!(mu > 0.0)) return fail(STOKES_E_INVAL, "stokes_nonlocal_sbt: mu must be > 0");
+    if (!(delta > 0.0) || !std::isfinite(delta))
+        return fail(STOKES_E_INVAL, "stokes_nonlocal_sbt: delta must be finite and > 0");
+    const int64_t N = (int64_t)n_fib * nodes_per_fib;
+    if (N >= (int64_t)1 << 30) return fail(STOKES_E_INVAL, "stokes_nonlocal_sbt: too many nodes");
+    if (N == 0) return STOKES_OK;
+    if (!xyz || !tangent || !fiber_len || !f || !out)
+        return fail(STOKES_E_INVAL, "stokes_nonlocal_sbt: null pointer");
+    if (out == f) return fail(STOKES_E_INVAL, "stokes_nonlocal_sbt: out must not alias f");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace* ws = nullptr;
+    int rc = workspace_get(st, (size_t)(2 * N) * sizeof(double), &ws);
+    if (rc) return rc;
+    double* wq = static_cast<double*>(ws->dev);
+    double* sarc = wq + N;
+    const unsigned grid = (unsigned)((N + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_fiber_tables, dim3(grid), dim3(BLOCK), 0, st, N, nodes_per_fib, fiber_len,
+                       wq, sarc);
+    hipLaunchKernelGGL(k_nonlocal_eval, dim3(grid), dim3(BLOCK), 0, st, N, nodes_per_fib, xyz,
+                       tangent, f, wq, sarc, delta, 1.0 / (8.0 * 3.14159265358979323846 * mu), out);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
 extern "C" int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
                                      const double* tangent, const double* fiber_len,
-                                     const double* rhs, double eps, double mu, int32_t iters,
-                                     uint32_t flags, double* f_out, double* resid_out,
-                                     int32_t* iters_out, void* stream) {
-    if (flags & ~(STOKES_PREC_MIXED | STOKES_NO_DOUBLET))
+                                     const double* rhs, double eps, double mu, double delta,
+                                     int32_t iters, uint32_t flags, double* f_out,
+                                     double* resid_out, int32_t* iters_out, void* stream) {
+    if (flags & ~(STOKES_PREC_MIXED | STOKES_NO_DOUBLET | STOKES_NONLOCAL | STOKES_PRECOND_BLOCK))
         return fail(STOKES_E_INVAL, "stokes_mobility_solve: unknown flag bits");
+    if ((flags & STOKES_NONLOCAL) && (!(delta > 0.0) || !std::isfinite(delta)))
+        return fail(STOKES_E_INVAL, "stokes_mobility_solve: delta must be finite and > 0 with STOKES_NONLOCAL");
     if (n_fib < 0 || nodes_per_fib < 2 || nodes_per_fib > 64)
         return fail(STOKES_E_INVAL, "stokes_mobility_solve: need n_fib >= 0 and 2 <= nodes_per_fib <= 64");
     if (iters < 1 || iters > STOKES_MAX_ITERS)
@@ -728,14 +992,15 @@ extern "C" int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool mixed = flags & STOKES_PREC_MIXED;
-    const SlotPlan sp = slot_plan(n_fib, nodes_per_fib, iters, mixed);
+    const uint32_t opts = flags & (STOKES_NONLOCAL | STOKES_PRECOND_BLOCK);
+    const SlotPlan sp = slot_plan(n_fib, nodes_per_fib, iters, mixed, opts);
     Workspace* ws = nullptr;
     int rc = workspace_get(st, sp.bytes, &ws);
     if (rc) return rc;
     Batch b;
     if ((rc = b.init(st, mixed, !(flags & STOKES_NO_DOUBLET), false))) return rc;
-    if ((rc = b.attach(0, ws->dev, n_fib, nodes_per_fib, iters, eps, mu, 0.0, xyz, tangent,
-                       fiber_len, rhs)))
+    if ((rc = b.attach(0, ws->dev, n_fib, nodes_per_fib, iters, eps, mu, 0.0, opts, delta, xyz,
+                       tangent, fiber_len, rhs)))
         return rc;
     std::vector<int> one{0};
     if ((rc = b.start(one))) return rc;

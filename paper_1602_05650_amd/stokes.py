@@ -26,6 +26,8 @@ NO_DOUBLET = 8
 ACCUMULATE = 16
 CHECK_INPUTS = 32
 ONSURF_RAW = 64
+NONLOCAL = 128
+PRECOND_BLOCK = 256
 MAX_ITERS = 128
 
 
@@ -51,7 +53,7 @@ class SolveReq(ctypes.Structure):
                 ("xyz", ctypes.c_void_p), ("tangent", ctypes.c_void_p),
                 ("fiber_len", ctypes.c_void_p), ("rhs", ctypes.c_void_p),
                 ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("iters", ctypes.c_int32),
-                ("tag", ctypes.c_uint64)]
+                ("tag", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("delta", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -72,7 +74,8 @@ def _load():
         "stokes_sl_eval": [I64, P, P, P, P, I32, P, I64, P, P, P, D, D, D, U32, P, P, P],
         "stokes_dl_eval": [I64, P, P, P, P, I64, P, P, D, U32, P, P, P],
         "stokes_local_sbt": [I64, P, P, D, D, ctypes.c_int, P, P],
-        "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, I32, U32, P, P, P, P],
+        "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, D, I32, U32, P, P, P, P],
+        "stokes_nonlocal_sbt": [I32, I32, P, P, P, P, D, D, P, P],
         "stokes_session_create": [P, P],
         "stokes_session_submit": [P, P, P],
         "stokes_session_wait": [P, ctypes.c_uint64, P, P, I32],
@@ -222,9 +225,34 @@ def local_sbt(tangent, f, eps, mu=1.0, inverse=False, out=None, stream=None):
     return out
 
 
+def _solve_opts(delta, precond):
+    if precond not in ("local", "block"):
+        raise ValueError(f"precond must be 'local' or 'block', not {precond!r}")
+    return ((NONLOCAL if delta is not None else 0) | (PRECOND_BLOCK if precond == "block" else 0),
+            0.0 if delta is None else float(delta))
+
+
+def nonlocal_sbt(xyz, tangent, fiber_len, f, nodes_per_fib, delta, mu=1.0, out=None, stream=None):
+    """K_delta[f] (regularised nonlocal slender-body self term) at every node, (3, N) float64."""
+    xyz = _dev(xyz, torch.float64, "xyz")
+    n = xyz.shape[1]
+    _dev(tangent, torch.float64, "tangent", (3, n))
+    _dev(fiber_len, torch.float64, "fiber_len")
+    _dev(f, torch.float64, "f", (3, n))
+    if out is None:
+        out = torch.empty_like(f)
+    _dev(out, torch.float64, "out", (3, n))
+    _check(_lib.stokes_nonlocal_sbt(fiber_len.shape[0], int(nodes_per_fib), _ptr(xyz),
+                                    _ptr(tangent), _ptr(fiber_len), _ptr(f), float(delta),
+                                    float(mu), _ptr(out), _stream(stream)))
+    return out
+
+
 def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1.0, mixed=False,
-                   doublet=True, stream=None):
-    """GMRES mobility solve on device tensors; returns (f, residual, iterations)."""
+                   doublet=True, delta=None, precond="local", stream=None):
+    """GMRES mobility solve on device tensors; returns (f, residual, iterations).
+    delta given: the operator includes the nonlocal self term K_delta; precond "block"
+    uses each fiber's inverted self block instead of the local 3x3 blocks."""
     xyz = _dev(xyz, torch.float64, "xyz")
     n = xyz.shape[1]
     _dev(tangent, torch.float64, "tangent", (3, n))
@@ -234,9 +262,10 @@ def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1
     out = torch.empty_like(rhs)
     res = ctypes.c_double(0.0)
     it = ctypes.c_int32(0)
-    flags = (PREC_MIXED if mixed else PREC_FP64) | (0 if doublet else NO_DOUBLET)
+    opts, dl = _solve_opts(delta, precond)
+    flags = (PREC_MIXED if mixed else PREC_FP64) | (0 if doublet else NO_DOUBLET) | opts
     _check(_lib.stokes_mobility_solve(n_fib, nodes_per_fib, _ptr(xyz), _ptr(tangent),
-                                      _ptr(fiber_len), _ptr(rhs), float(eps), float(mu),
+                                      _ptr(fiber_len), _ptr(rhs), float(eps), float(mu), dl,
                                       int(iters), flags, _ptr(out), ctypes.byref(res),
                                       ctypes.byref(it), _stream(stream)))
     return out, res.value, it.value
@@ -255,10 +284,10 @@ def profile_read():
     return ms.value, n.value
 
 
-def solve_footprint(n_fib, nodes_per_fib, iters, mixed=False):
+def solve_footprint(n_fib, nodes_per_fib, iters, mixed=False, precond="local"):
     """Device bytes a mobility request of this shape takes from a session budget."""
-    return int(_lib.stokes_solve_footprint(int(n_fib), int(nodes_per_fib), int(iters),
-                                           PREC_MIXED if mixed else PREC_FP64))
+    flags = (PREC_MIXED if mixed else PREC_FP64) | (PRECOND_BLOCK if precond == "block" else 0)
+    return int(_lib.stokes_solve_footprint(int(n_fib), int(nodes_per_fib), int(iters), flags))
 
 
 def release_workspace():
@@ -283,13 +312,16 @@ class Session:
         _check(_lib.stokes_session_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._shapes = {}
 
-    def submit(self, xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1.0, tag=0):
+    def submit(self, xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1.0, tag=0,
+               delta=None, precond="local"):
         import numpy as np
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xyz, tangent, fiber_len, rhs)]
         n = arrs[0].shape[1]
+        opts, dl = _solve_opts(delta, precond)
         req = SolveReq(int(arrs[2].shape[0]), int(nodes_per_fib),
                        arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
-                       arrs[3].ctypes.data, float(eps), float(mu), int(iters), int(tag))
+                       arrs[3].ctypes.data, float(eps), float(mu), int(iters), int(tag),
+                       opts, dl)
         t = ctypes.c_uint64(0)
         _check(_lib.stokes_session_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         self._shapes[t.value] = n

@@ -64,10 +64,19 @@ def test_status_strings_and_validation_without_gpu():
                             1.0, 0.01, 0.0, 0, None, None, None) == S.OK
     assert L.stokes_local_sbt(0, None, None, 0.01, 1.0, 0, None, None) == S.OK
     assert L.stokes_local_sbt(3, None, None, 0.01, 1.0, 0, None, None) == S.E_INVAL
-    assert L.stokes_mobility_solve(1, 1, None, None, None, None, 0.01, 1.0, 5, 0, None, None,
-                                   None, None) == S.E_INVAL
-    assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0, 0, None, None,
-                                   None, None) == S.E_INVAL
+    assert L.stokes_mobility_solve(1, 1, None, None, None, None, 0.01, 1.0, 0.0, 5, 0, None,
+                                   None, None, None) == S.E_INVAL
+    assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0.0, 0, 0, None,
+                                   None, None, None) == S.E_INVAL
+    # the nonlocal term needs delta > 0; unknown flag bits are refused
+    assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0.0, 5, S.NONLOCAL,
+                                   None, None, None, None) == S.E_INVAL
+    assert "delta" in S.last_error()
+    assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0.0, 5, 1 << 12,
+                                   None, None, None, None) == S.E_INVAL
+    assert L.stokes_nonlocal_sbt(0, 8, None, None, None, None, 0.01, 1.0, None, None) == S.OK
+    assert L.stokes_nonlocal_sbt(2, 8, None, None, None, None, 0.0, 1.0, None, None) == S.E_INVAL
+    assert L.stokes_nonlocal_sbt(2, 65, None, None, None, None, 0.01, 1.0, None, None) == S.E_INVAL
     assert L.stokes_session_create(None, None) == S.E_INVAL
     assert L.stokes_session_destroy(None) == S.E_INVAL
 
@@ -81,6 +90,8 @@ def test_solve_footprint_without_gpu():
     assert S.solve_footprint(0, 16, 20) == 0 and S.solve_footprint(10, 65, 20) == 0
     # the Krylov basis alone: (k+1) x 3N doubles
     assert big > 61 * 3 * 2048 * 64 * 8
+    # block-Jacobi adds the inverted fiber blocks: (3 npf)^2 doubles per fiber
+    assert S.solve_footprint(10, 16, 20, precond="block") - small >= 10 * 48 * 48 * 8
 
 
 def test_version():
