@@ -78,7 +78,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-other", action="store_true",
                     help="time the oracle on the headline workload only")
-    ap.add_argument("--only", choices=["mixed", "fp64", "both", "none"], default="both")
+    ap.add_argument("--only", choices=["mixed", "fp64", "both", "none", "nonlocal"], default="both",
+                    help="none: serving run alone; nonlocal: the nonlocal-term section alone")
     ap.add_argument("--extra", default="c0,c1,c4",
                     help="other workloads timed after the headline (c0,c1,c4 or none)")
     ap.add_argument("--step-pairs", type=float, default=0,
@@ -256,6 +257,53 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
     }
 
 
+FLOPS_PER_PAIR_NONLOCAL = 36   # K_delta node pair: 3 sub, |r|^2 5, a 3, r.f 5, b 2, 3 x (2 fma) 12, s-term 6
+
+
+def nonlocal_run(S, torch, log_fn, n_fib=2048, nodes=64, iters=20, delta=0.01):
+    """The nonlocal self term and the block-Jacobi preconditioner on the largest serving
+    request shape: K_delta alone (node pairs/s), then one-shot solves with the local
+    operator, with K_delta, and with K_delta and block-Jacobi preconditioning."""
+    from paper_1602_05650_amd import workloads as W
+    req = W.serving_request(3, 40000, n_fib=n_fib, nodes=nodes, iters=iters)
+    fs = req["fibers"]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    X, T, L, V = d(fs.xyz), d(fs.tangent), d(fs.length), d(req["rhs"])
+    out = torch.empty_like(V)
+    n = fs.n
+    pairs = n * (nodes - 1)
+    for _ in range(3):
+        S.nonlocal_sbt(X, T, L, V, nodes, delta, out=out)
+    torch.cuda.synchronize()
+    reps = 50
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S.nonlocal_sbt(X, T, L, V, nodes, delta, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    res = {"workload": f"{n_fib} fibers x {nodes} nodes ({n} points), delta={delta}",
+           "k_delta": {"ms": round(dt * 1e3, 4), "node_pairs": pairs,
+                       "gpair_per_s": round(pairs / dt / 1e9, 2),
+                       "tflops_counted": round(pairs * FLOPS_PER_PAIR_NONLOCAL / dt / 1e12, 2)}}
+    log_fn(f"K_delta: {dt * 1e3:.3f} ms for {pairs} node pairs")
+    sl_pairs = iters * n * (n - nodes)
+    for tag, dl, pre in (("local_operator", None, "local"), ("nonlocal_local_precond", delta, "local"),
+                         ("nonlocal_block_precond", delta, "block")):
+        S.mobility_solve(X, T, L, V, nodes, fs.eps, 2, mixed=True, delta=dl, precond=pre)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f, r, it = S.mobility_solve(X, T, L, V, nodes, fs.eps, iters, mixed=True, delta=dl,
+                                    precond=pre)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        beta = float(torch.linalg.vector_norm(V))
+        res[tag] = {"ms": round(dt * 1e3, 2), "iterations": it,
+                    "relative_residual": float(f"{r / beta:.3e}"),
+                    "sl_gpair_per_s": round(sl_pairs / dt / 1e9, 1)}
+        log_fn(f"solve {tag}: {dt * 1e3:.1f} ms, {it} iterations, residual {r / beta:.2e}")
+    return res
+
+
 def cpu_baseline(c, seconds, log_fn, other=True):
     """The oracle (plain FP64 double loop, OpenMP over targets) on seeded samples of the
     headline workload: about 60% of `seconds` on all host threads, 25% on one thread;
@@ -351,6 +399,9 @@ def main():
     from paper_1602_05650_amd import stokes as S
     from paper_1602_05650_amd import workloads as W
 
+    if args.only == "nonlocal":      # nonlocal-term section alone (for profiling it)
+        print(json.dumps({"nonlocal": nonlocal_run(S, torch, log)}), flush=True)
+        return
     if args.only == "none":          # serving run alone (for profiling it)
         print(json.dumps({"serving": serving_run(S, args.serving_requests, log, args.step_pairs,
                                                  not args.serving_fp64, args.serving_rate)}), flush=True)
@@ -456,6 +507,8 @@ def main():
         out["other_workloads"] = {
             {"c0": "cloud_512", "c1": "confined_32k", "c4": "confined_524k"}[e]:
             config_run(S, torch, e, 200 if e == "c0" else 10, 3, log) for e in extra}
+    if extra and args.only == "both":
+        out["nonlocal"] = nonlocal_run(S, torch, log)
     if not args.no_serving:
         try:
             out["serving"] = serving_run(S, args.serving_requests, log, args.step_pairs,

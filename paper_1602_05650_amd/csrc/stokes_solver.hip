@@ -188,107 +188,174 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const SlotDesc* D, const StepTa
     }
 }
 
-// Self block M [+ K_delta] of one fiber (after k_geom), inverted in place by
-// Gauss-Jordan elimination with partial pivoting: one workgroup per fiber, the
-// matrix in the slot's binv buffer (column-major, m = 3 npf <= 192).
-__global__ __launch_bounds__(BLOCK) void k_block(const SlotDesc* D, const StepTables* T) {
-    __shared__ double rowp[192], colp[192], rv[BLOCK];
-    __shared__ int ri[BLOCK], perm[192];
+// Self block M [+ K_delta] of one fiber (after k_geom), inverted by Gauss-Jordan
+// elimination with partial pivoting.  One workgroup of BLOCK_GJ threads per fiber
+// holds the whole m x m matrix (m = 3 npf <= 192) in registers: thread t owns row
+// r = t % m and the columns c = g + GJ_G jj (g = t / m, jj < GJ_COLS), so every
+// pivot step only exchanges the pivot column and row through LDS.  The inverse is
+// written column-major to the slot's binv buffer (row and column index c npf + k).
+constexpr int BLOCK_GJ = 1024;
+constexpr int GJ_G = 5;                          // column groups: GJ_G * 192 <= BLOCK_GJ
+constexpr int GJ_COLS = (192 + GJ_G - 1) / GJ_G;  // columns per thread
+__global__ __launch_bounds__(BLOCK_GJ) void k_block(const SlotDesc* D, const StepTables* T) {
+    __shared__ double s_col[192], s_row[192], s_swap[2][192], s_wv[BLOCK_GJ / 64];
+    __shared__ int s_wi[BLOCK_GJ / 64], s_perm[192], s_dest[192];
     const cptr<WorkList> wl = &as_const(T)->wl[WL_FIB];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
         const auto& d = as_const(D)[wl->slot[si]];
         const int f = (int)(it - wl->prefix[si]);
         const int npf = d.npf, m = 3 * npf;
         const int64_t N = d.N, f0 = (int64_t)f * npf;
-        double* A = d.binv + (int64_t)f * m * m;
         const bool nl = d.opts & STOKES_NONLOCAL;
         const double d2 = d.delta * d.delta;
-        for (int e = t; e < m * m; e += BLOCK) {
-            const int col = e / m, row = e - col * m;
-            const int c = row / npf, i = row - c * npf, ce = col / npf, k = col - ce * npf;
-            const int64_t gi = f0 + i, gk = f0 + k;
+        const bool act = t < GJ_G * m;
+        const int r = act ? t % m : 0, g = act ? t / m : 0;
+        const int rc = r / npf, ri = r - rc * npf;
+        const int64_t gi = f0 + ri;
+        // this row's node: position, tangent, and the subtracted K_delta coefficient
+        const double xi = d.xyz[gi], yi = d.xyz[N + gi], zi = d.xyz[2 * N + gi];
+        const double rti = d.tan[rc * N + gi];
+        double dsum = 0.0;
+        if (nl)
+            for (int q = 0; q < npf; ++q) {
+                if (q == ri) continue;
+                const double ds = d.sarc[gi] - d.sarc[f0 + q];
+                dsum += d.wq[f0 + q] / sqrt(ds * ds + d2);
+            }
+        double A[GJ_COLS];
+#pragma unroll
+        for (int jj = 0; jj < GJ_COLS; ++jj) {
+            const int c = g + GJ_G * jj;
             double v = 0.0;
-            if (i != k) {
-                if (nl) {
-                    const double rx = d.xyz[gi] - d.xyz[gk], ry = d.xyz[N + gi] - d.xyz[N + gk],
-                                 rz = d.xyz[2 * N + gi] - d.xyz[2 * N + gk];
-                    const double r[3] = {rx, ry, rz};
-                    const double r2 = rx * rx + ry * ry + rz * rz;
-                    v = d.pref * d.wq[gk] * ((c == ce ? 1.0 : 0.0) + r[c] * r[ce] / r2) /
-                        sqrt(r2 + d2);
-                }
-            } else {
-                const double tc = d.tan[c * N + gi], te = d.tan[ce * N + gi];
-                const double id = c == ce ? 1.0 : 0.0;
-                v = d.pref * ((d.kappa + 2.0) * id + (d.kappa - 2.0) * tc * te);
-                if (nl) {
-                    double dsum = 0.0;
-                    for (int q = 0; q < npf; ++q) {
-                        if (q == i) continue;
-                        const double ds = d.sarc[gi] - d.sarc[f0 + q];
-                        dsum += d.wq[f0 + q] / sqrt(ds * ds + d2);
+            if (act && c < m) {
+                const int ce = c / npf, k = c - ce * npf;
+                const double id = rc == ce ? 1.0 : 0.0;
+                if (k != ri) {
+                    if (nl) {
+                        const int64_t gk = f0 + k;
+                        const double rx = xi - d.xyz[gk], ry = yi - d.xyz[N + gk], rz = zi - d.xyz[2 * N + gk];
+                        const double r2 = rx * rx + ry * ry + rz * rz;
+                        const double ra = rc == 0 ? rx : (rc == 1 ? ry : rz);
+                        const double rb = ce == 0 ? rx : (ce == 1 ? ry : rz);
+                        v = d.pref * d.wq[gk] * (id + ra * rb / r2) / sqrt(r2 + d2);
                     }
-                    v -= d.pref * dsum * (id + tc * te);
+                } else {
+                    const double te = d.tan[ce * N + gi];
+                    v = d.pref * ((d.kappa + 2.0) * id + (d.kappa - 2.0) * rti * te);
+                    if (nl) v -= d.pref * dsum * (id + rti * te);
                 }
             }
-            A[e] = v;
+            A[jj] = v;
         }
-        __syncthreads();
         for (int p = 0; p < m; ++p) {
-            // pivot: largest |A[r][p]|, r >= p (smallest r on ties)
+            const int gp = p % GJ_G, jp = p / GJ_G;
+            // pivot: largest |A[r][p]| over rows r >= p (smallest r on ties)
             double bv = -1.0;
             int bi = m;
-            for (int r = p + t; r < m; r += BLOCK) {
-                const double a = fabs(A[(int64_t)p * m + r]);
-                if (a > bv) { bv = a; bi = r; }
+            if (act && g == gp) {
+                double v = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < GJ_COLS; ++jj)
+                    if (jj == jp) v = A[jj];
+                if (r >= p) {
+                    bv = fabs(v);
+                    bi = r;
+                }
             }
-            rv[t] = bv;
-            ri[t] = bi;
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                s_wv[wave] = bv;
+                s_wi[wave] = bi;
+            }
             __syncthreads();
-            for (int h = BLOCK / 2; h > 0; h >>= 1) {
-                if (t < h && (rv[t + h] > rv[t] || (rv[t + h] == rv[t] && ri[t + h] < ri[t]))) {
-                    rv[t] = rv[t + h];
-                    ri[t] = ri[t + h];
+            double pv = s_wv[0];
+            int pr = s_wi[0];
+            for (int w = 1; w < BLOCK_GJ / 64; ++w)
+                if (s_wv[w] > pv || (s_wv[w] == pv && s_wi[w] < pr)) {
+                    pv = s_wv[w];
+                    pr = s_wi[w];
+                }
+            if (pr >= m) pr = p;    // (a column of NaN: no row qualifies)
+            if (t == 0) s_perm[p] = pr;
+            // row interchange p <-> pr through LDS
+            if (pr != p) {
+                if (act && (r == p || r == pr)) {
+#pragma unroll
+                    for (int jj = 0; jj < GJ_COLS; ++jj) {
+                        const int c = g + GJ_G * jj;
+                        if (c < m) s_swap[r == p ? 0 : 1][c] = A[jj];
+                    }
                 }
                 __syncthreads();
-            }
-            const int pr = ri[0] < m ? ri[0] : p;   // (a column of NaN: no row qualifies)
-            if (t == 0) perm[p] = pr;
-            if (pr != p)
-                for (int col = t; col < m; col += BLOCK) {
-                    const double a = A[(int64_t)col * m + p];
-                    A[(int64_t)col * m + p] = A[(int64_t)col * m + pr];
-                    A[(int64_t)col * m + pr] = a;
+                if (act && (r == p || r == pr)) {
+#pragma unroll
+                    for (int jj = 0; jj < GJ_COLS; ++jj) {
+                        const int c = g + GJ_G * jj;
+                        if (c < m) A[jj] = s_swap[r == p ? 1 : 0][c];
+                    }
                 }
-            __syncthreads();
-            const double inv = 1.0 / A[(int64_t)p * m + p];
-            for (int j = t; j < m; j += BLOCK) {
-                rowp[j] = j == p ? inv : A[(int64_t)j * m + p] * inv;
-                colp[j] = A[(int64_t)p * m + j];
+            }
+            // pivot column and (unscaled) pivot row to LDS
+            if (act && g == gp) {
+                double v = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < GJ_COLS; ++jj)
+                    if (jj == jp) v = A[jj];
+                s_col[r] = v;
+            }
+            if (act && r == p) {
+#pragma unroll
+                for (int jj = 0; jj < GJ_COLS; ++jj) {
+                    const int c = g + GJ_G * jj;
+                    if (c < m) s_row[c] = A[jj];
+                }
             }
             __syncthreads();
-            for (int j = t; j < m; j += BLOCK) A[(int64_t)j * m + p] = rowp[j];
-            for (int e = t; e < m * m; e += BLOCK) {
-                const int j = e / m, r = e - j * m;
-                if (r == p) continue;
-                const double a = j == p ? 0.0 : A[e];
-                A[e] = a - colp[r] * rowp[j];
+            const double inv = 1.0 / s_col[p];
+            const double cr = s_col[r];
+            if (act) {
+#pragma unroll
+                for (int jj = 0; jj < GJ_COLS; ++jj) {
+                    const int c = g + GJ_G * jj;
+                    if (c < m) {
+                        const double rp = c == p ? inv : s_row[c] * inv;
+                        A[jj] = r == p ? rp : (c == p ? 0.0 : A[jj]) - cr * rp;
+                    }
+                }
             }
             __syncthreads();
         }
-        // undo the row interchanges on the columns, last first
-        for (int p = m - 1; p >= 0; --p) {
-            const int q = perm[p];
-            if (q != p)
-                for (int r = t; r < m; r += BLOCK) {
-                    const double a = A[(int64_t)p * m + r];
-                    A[(int64_t)p * m + r] = A[(int64_t)q * m + r];
-                    A[(int64_t)q * m + r] = a;
-                }
-            __syncthreads();
+        // undo the row interchanges on the columns (last first): column c of the
+        // inverse is working column s_dest^{-1}(c)
+        if (t == 0) {
+            for (int c = 0; c < m; ++c) s_dest[c] = c;   // s_dest[c]: working column at c
+            for (int p = m - 1; p >= 0; --p) {
+                const int q = s_perm[p];
+                const int a = s_dest[p];
+                s_dest[p] = s_dest[q];
+                s_dest[q] = a;
+            }
+            for (int c = 0; c < m; ++c) s_perm[s_dest[c]] = c;       // working column -> final column
         }
+        __syncthreads();
+        if (act) {
+            double* X = d.binv + (int64_t)f * m * m;
+#pragma unroll
+            for (int jj = 0; jj < GJ_COLS; ++jj) {
+                const int c = g + GJ_G * jj;
+                if (c < m) X[(int64_t)s_perm[c] * m + r] = A[jj];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -830,7 +897,7 @@ int Batch::start(const std::vector<int>& slots) {
     hipLaunchKernelGGL(k_geom, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_tiles, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     if (T.wl[WL_FIB].prefix[T.wl[WL_FIB].n] > 0)
-        hipLaunchKernelGGL(k_block, dim3(grid_for(T.wl[WL_FIB], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+        hipLaunchKernelGGL(k_block, dim3(grid_for(T.wl[WL_FIB], 4096)), dim3(BLOCK_GJ), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_init_norm, dim3(grid_for(T.wl[WL_DOT], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_init_beta, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_, dev_stat_);
     hipLaunchKernelGGL(k_init_v0, dim3(grid_for(T.wl[WL_VEC], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
