@@ -390,3 +390,7 @@ def local_sbt_inv_closed(v, tangent, eps, mu=1.0):
     tv = np.sum(t * v, axis=0)
     par = t * tv[None, :]
     return 8.0 * math.pi * mu * (par / (2.0 * kap) + (v - par) / (kap + 2.0))
+
+
+# Confined rigid particles (second-kind boundary integral mobility problem).
+from .particles import ParticleSystem, particle_solve, stokeslet, rotlet, dl_diagonal  # noqa: E402,F401
