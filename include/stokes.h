@@ -226,6 +226,42 @@ int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xy
                           double eps, double mu, double delta, int32_t iters, uint32_t flags,
                           double* f_out, double* resid_out, int32_t* iters_out, void* stream);
 
+/*
+ * stokes_particle_solve -- mobility of rigid particles in a fixed confining
+ * periphery: the second-kind boundary integral equations of sections "The
+ * contribution from the periphery" and "The contribution from rigid immersed
+ * particles" (eq. main-cortex-density with the rank completion
+ * N[q0](x) = n(x) int n.q0 dS, eq. main-nsb-second-kind, constraints
+ * eq. main-nsb-rgbt and eq. main-nsb-rgbr), Nystrom on the given surface
+ * quadratures with singularity subtraction, external forces and torques
+ * through the Stokeslet and rotlet (eq. oseen, eq. rotlet).  With K the double
+ * layer of stokes_dl_eval (outward normals), the paper's double layer with the
+ * normal into the fluid is +K on the periphery and -K on a particle.  Right-
+ * preconditioned GMRES in FP64 with the diagonal of the self blocks (eq. prec).
+ *
+ * m0, y0, n0, w0     periphery: points, OUTWARD unit normals [3*m0], area weights
+ *                    [m0]; m0 = 0 for an unbounded fluid.
+ * n_part (>= 1), part_offset   HOST array [n_part+1], part_offset[0] = 0: particle p
+ *                    owns points [part_offset[p], part_offset[p+1]) (>= 4 each).
+ * yp, np, wp         particle points, outward normals [3*Mp], weights [Mp],
+ *                    Mp = part_offset[n_part].
+ * centers, force, torque   [3*n_part] (SoA: x of every particle, then y, then z):
+ *                    X_p, F_p, L_p.
+ * mu > 0; near_r: mixed double-layer sums only (see stokes_dl_eval);
+ * iters 1..STOKES_MAX_ITERS; flags: STOKES_PREC_* for the double-layer sums.
+ * U_out, Omega_out   [3*n_part] translational and angular velocities (SoA).
+ * q_out              NULL or [3*(m0+Mp)] densities (periphery points first).
+ * resid_out, iters_out   NULL or host: final least-squares residual, iterations.
+ * All arrays except part_offset are DEVICE pointers.  The call allocates its own
+ * scratch (about (3 iters + 30)(m0 + Mp) doubles) and is synchronous.
+ */
+int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const double* w0,
+                          int32_t n_part, const int64_t* part_offset, const double* yp,
+                          const double* np, const double* wp, const double* centers,
+                          const double* force, const double* torque, double mu, double near_r,
+                          int32_t iters, uint32_t flags, double* U_out, double* Omega_out,
+                          double* q_out, double* resid_out, int32_t* iters_out, void* stream);
+
 /* ---- serving: continuous batching of mobility solves ------------------- */
 typedef struct stokes_session stokes_session;
 

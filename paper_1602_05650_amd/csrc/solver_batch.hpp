@@ -102,6 +102,8 @@ struct SlotPlan {
     size_t bytes;
 };
 SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed, uint32_t opts);
+// Bytes of a generic-vector slot (attach_vector).
+size_t vector_plan_bytes(int64_t n_vec, int32_t k);
 
 class Batch {
 public:
@@ -133,6 +135,19 @@ public:
     int step_parts(const std::vector<Part>& parts);
     // Solutions of the listed slots into their x buffers (iterations done in desc.j).
     int finalize(const std::vector<int>& slots);
+
+    // ---- GMRES for an operator applied by the caller (generic vectors) -------
+    // A slot holding only the Krylov state for vectors of 3 * n_vec entries (three
+    // planes of n_vec); rhs is a device vector copied into the slot.
+    int attach_vector(int s, void* mem, int64_t n_vec, int32_t k, const double* rhs);
+    // beta = |rhs| and v_0.
+    int start_vector(const std::vector<int>& slots);
+    // The caller has written w = A P^{-1} v_j (desc.j) into desc.w: Gram-Schmidt,
+    // Givens rotation and v_{j+1}; then the status rows are read back.
+    int step_ortho(const std::vector<int>& slots);
+    // y from the least-squares problem and w = V_m y (iterations done in desc.j);
+    // the caller forms x = P^{-1} w.
+    int finalize_vector(const std::vector<int>& slots);
     const double* status(int s) const { return host_stat_ + NSTAT * s; }
     SlotDesc& desc(int s) { return host_desc_[s]; }
     hipStream_t stream() const { return st_; }
@@ -141,6 +156,7 @@ public:
 private:
     int upload();
     int launch_step(bool capture);
+    int launch_ortho(bool capture);
     void set_list(WL w, const std::vector<int>& slots);
     void set_sl_list(const std::vector<Part>& parts);
     int run_step();

@@ -1,0 +1,403 @@
+// Rigid particles in a confining periphery: the second-kind boundary integral
+// mobility problem (eq. main-cortex-density with the rank completion N of
+// eq. main-cortex-vel; eq. main-nsb-second-kind with the constraints
+// eq. main-nsb-rgbt and eq. main-nsb-rgbr), Nystrom-discretised on the given
+// surface quadratures, solved by right-preconditioned GMRES with the diagonal
+// Jacobi preconditioner of eq. prec.
+//
+// With K the double-layer sum of stokes_dl_eval (outward normals; -q inside,
+// -q/2 on the surface, 0 outside), the paper's double layer with the normal into
+// the fluid is +K on the periphery and -K on a particle, and the equations are
+//
+//   x on Gamma_0:  -q0/2 + K0_PV[q0] + n(x) int n.q0 dS - sum_p K_p[q_p]   = b(x)
+//   x on P_p:      -q_p/2 + K0[q0] - sum_p' K_p'[q_p'] (own term PV)
+//                  - U_p - Omega_p x (x - X_p)                             = b(x)
+//   (1/|P_p|) int q_p dS - U_p = 0,  (1/|P_p|) int (y - X_p) x q_p dS - Omega_p = 0
+//
+// b(x) = -sum_p [G(x - X_p) F_p + R(x - X_p) L_p]  (eq. oseen, eq. rotlet).
+// Unknowns: three planes of n_tot = M_s + 2 n_p entries,
+// [q on the M_s surface points (periphery first) | U_1..U_np | Omega_1..Omega_np].
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "solver_batch.hpp"
+
+namespace stokes {
+namespace {
+
+constexpr int PB = 256;
+constexpr double PI = 3.14159265358979323846;
+
+// Surfaces: index 0 is the periphery (possibly empty), 1 + p is particle p.  Each
+// surface's points are a contiguous SoA block (three planes of its size) in the
+// block arrays; point i of the concatenated surface list belongs to surface sid[i]
+// and sits at local index i - sstart[sid[i]].
+struct Surfaces {
+    const double* xyz;      // blocks: surface s at 3 * sstart[s], planes of ssize[s]
+    const double* nrm;
+    const double* w;        // [M_s], concatenated
+    const int32_t* sid;     // [M_s]
+    const int64_t* sstart;  // [n_surf]
+    const int64_t* ssize;   // [n_surf]
+};
+
+__device__ __forceinline__ const double* block(const double* a, const Surfaces& S, int s) {
+    return a + 3 * S.sstart[s];
+}
+
+// b = -sum_p [G(x - X_p) F_p + R(x - X_p) L_p] on the surface points, 0 on the U, Omega rows.
+__global__ __launch_bounds__(PB) void k_pt_rhs(int64_t ms, int64_t ntot, const double* T, int32_t np,
+                                               const double* X, const double* F, const double* L,
+                                               double mu, double* b) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= ntot) return;
+    double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+    if (i < ms) {
+        const double x = T[i], y = T[ms + i], z = T[2 * ms + i];
+        for (int p = 0; p < np; ++p) {
+            const double rx = x - X[p], ry = y - X[np + p], rz = z - X[2 * np + p];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double rn = sqrt(r2);
+            const double ri = 1.0 / rn, ri3 = ri / r2;
+            const double fx = F[p], fy = F[np + p], fz = F[2 * np + p];
+            const double lx = L[p], ly = L[np + p], lz = L[2 * np + p];
+            const double rf = (rx * fx + ry * fy + rz * fz) * ri3;
+            u0 += fx * ri + rx * rf + (ly * rz - lz * ry) * ri3;
+            u1 += fy * ri + ry * rf + (lz * rx - lx * rz) * ri3;
+            u2 += fz * ri + rz * rf + (lx * ry - ly * rx) * ri3;
+        }
+        const double c = -1.0 / (8.0 * PI * mu);
+        u0 *= c;
+        u1 *= c;
+        u2 *= c;
+    }
+    b[i] = u0;
+    b[ntot + i] = u1;
+    b[2 * ntot + i] = u2;
+}
+
+// Diagonal of the self-interaction blocks: on the periphery -1 - sum_s w_s K_cc + w n_c^2,
+// on a particle sum_s w_s K_cc over its own points (s != i), -1 on the U, Omega rows.
+__global__ __launch_bounds__(PB) void k_pt_diag(Surfaces S, int64_t ms, int64_t ntot, double* diag) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= ntot) return;
+    double d0 = -1.0, d1 = -1.0, d2 = -1.0;
+    if (i < ms) {
+        const int s = S.sid[i];
+        const int64_t n = S.ssize[s], li = i - S.sstart[s];
+        const double* y = block(S.xyz, S, s);
+        const double* nn = block(S.nrm, S, s);
+        const double* w = S.w + S.sstart[s];
+        const double xi = y[li], yi = y[n + li], zi = y[2 * n + li];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == li) continue;
+            const double dx = xi - y[k], dy = yi - y[n + k], dz = zi - y[2 * n + k];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double dn = dx * nn[k] + dy * nn[n + k] + dz * nn[2 * n + k];
+            const double c = 3.0 / (4.0 * PI) * w[k] * dn / (r2 * r2 * sqrt(r2));
+            a0 += c * dx * dx;
+            a1 += c * dy * dy;
+            a2 += c * dz * dz;
+        }
+        if (s == 0) {
+            const double wi = w[li];
+            d0 = -1.0 - a0 + wi * nn[li] * nn[li];
+            d1 = -1.0 - a1 + wi * nn[n + li] * nn[n + li];
+            d2 = -1.0 - a2 + wi * nn[2 * n + li] * nn[2 * n + li];
+        } else {
+            d0 = a0;
+            d1 = a1;
+            d2 = a2;
+        }
+    }
+    diag[i] = d0;
+    diag[ntot + i] = d1;
+    diag[2 * ntot + i] = d2;
+}
+
+// out = v / d elementwise over 3 n_tot entries.
+__global__ __launch_bounds__(PB) void k_pt_scale(int64_t n3, const double* v, const double* d, double* out) {
+    const int64_t e = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (e < n3) out[e] = v[e] / d[e];
+}
+
+// Surface part of the unknown vector into per-surface SoA blocks (the sources of the
+// double-layer sums).
+__global__ __launch_bounds__(PB) void k_pt_gather(Surfaces S, int64_t ms, int64_t ntot, const double* z,
+                                                  double* qb) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= ms) return;
+    const int s = S.sid[i];
+    const int64_t n = S.ssize[s], li = i - S.sstart[s];
+    double* q = qb + 3 * S.sstart[s];
+    q[li] = z[i];
+    q[n + li] = z[ntot + i];
+    q[2 * n + li] = z[2 * ntot + i];
+}
+
+// One block per surface, fixed order: area (which = 0) or the moments of q (which = 1):
+// periphery red[0] = int n.q0; particle red[8 s + 0..2] = int q, red[8 s + 3..5] =
+// int (y - X) x q.
+__global__ __launch_bounds__(PB) void k_pt_reduce(Surfaces S, const double* qb, const double* X, int32_t np,
+                                                  int which, double* red) {
+    __shared__ double lds[6][PB];
+    const int s = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t n = S.ssize[s];
+    const double* y = block(S.xyz, S, s);
+    const double* nn = block(S.nrm, S, s);
+    const double* q = qb + 3 * S.sstart[s];
+    const double* w = S.w + S.sstart[s];
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double cx = s > 0 ? X[s - 1] : 0.0, cy = s > 0 ? X[np + s - 1] : 0.0,
+                 cz = s > 0 ? X[2 * np + s - 1] : 0.0;
+    for (int64_t k = t; k < n; k += PB) {
+        if (which == 0) {
+            a[0] += w[k];
+        } else if (s == 0) {
+            a[0] += w[k] * (nn[k] * q[k] + nn[n + k] * q[n + k] + nn[2 * n + k] * q[2 * n + k]);
+        } else {
+            const double qx = q[k], qy = q[n + k], qz = q[2 * n + k];
+            const double rx = y[k] - cx, ry = y[n + k] - cy, rz = y[2 * n + k] - cz;
+            a[0] += w[k] * qx;
+            a[1] += w[k] * qy;
+            a[2] += w[k] * qz;
+            a[3] += w[k] * (ry * qz - rz * qy);
+            a[4] += w[k] * (rz * qx - rx * qz);
+            a[5] += w[k] * (rx * qy - ry * qx);
+        }
+    }
+    for (int c = 0; c < 6; ++c) lds[c][t] = a[c];
+    __syncthreads();
+    for (int h = PB / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int c = 0; c < 6; ++c) lds[c][t] += lds[c][t + h];
+        __syncthreads();
+    }
+    if (t < 6) red[8 * s + t] = lds[t][0];
+}
+
+// w = A z from the double-layer sums D0 (periphery sources) and DP (particle
+// sources), the moments red and the areas (area[8 s], as k_pt_reduce lays them out).
+__global__ __launch_bounds__(PB) void k_pt_assemble(Surfaces S, int64_t ms, int64_t ntot, int32_t np,
+                                                    const double* z, const double* D0, const double* DP,
+                                                    const double* red, const double* area,
+                                                    const double* X, double* w) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= ntot) return;
+    double v[3];
+    if (i < ms) {
+        const int s = S.sid[i];
+        for (int c = 0; c < 3; ++c)
+            v[c] = -0.5 * z[c * ntot + i] + D0[c * ms + i] - DP[c * ms + i];
+        const int64_t n = S.ssize[s], li = i - S.sstart[s];
+        if (s == 0) {
+            const double* nn = block(S.nrm, S, 0);
+            for (int c = 0; c < 3; ++c) v[c] += nn[c * n + li] * red[0];
+        } else {
+            const int p = s - 1;
+            const double* y = block(S.xyz, S, s);
+            const double rx = y[li] - X[p], ry = y[n + li] - X[np + p], rz = y[2 * n + li] - X[2 * np + p];
+            const double ux = z[ms + p], uy = z[ntot + ms + p], uz = z[2 * ntot + ms + p];
+            const double ox = z[ms + np + p], oy = z[ntot + ms + np + p], oz = z[2 * ntot + ms + np + p];
+            v[0] -= ux + (oy * rz - oz * ry);
+            v[1] -= uy + (oz * rx - ox * rz);
+            v[2] -= uz + (ox * ry - oy * rx);
+        }
+    } else {
+        const int64_t r = i - ms;
+        const int p = (int)(r < np ? r : r - np);
+        const int off = r < np ? 0 : 3;
+        for (int c = 0; c < 3; ++c)
+            v[c] = red[8 * (1 + p) + off + c] / area[8 * (1 + p)] - z[c * ntot + i];
+    }
+    w[i] = v[0];
+    w[ntot + i] = v[1];
+    w[2 * ntot + i] = v[2];
+}
+
+inline unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + PB - 1) / PB); }
+
+// Device scratch of one solve, freed at the end of the call.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+}  // namespace stokes
+
+using namespace stokes;
+
+extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const double* w0,
+                                     int32_t n_part, const int64_t* part_offset, const double* yp,
+                                     const double* np_, const double* wp, const double* centers,
+                                     const double* force, const double* torque, double mu,
+                                     double near_r, int32_t iters, uint32_t flags, double* U_out,
+                                     double* Omega_out, double* q_out, double* resid_out,
+                                     int32_t* iters_out, void* stream) {
+    if (flags & ~STOKES_PREC_MIXED) return fail(STOKES_E_INVAL, "stokes_particle_solve: unknown flag bits");
+    if (m0 < 0 || n_part < 1 || !part_offset)
+        return fail(STOKES_E_INVAL, "stokes_particle_solve: need m0 >= 0, n_part >= 1 and part_offset");
+    if (iters < 1 || iters > STOKES_MAX_ITERS) return fail(STOKES_E_INVAL, "stokes_particle_solve: iters out of range");
+    if (!(mu > 0.0)) return fail(STOKES_E_INVAL, "stokes_particle_solve: mu must be > 0");
+    if (part_offset[0] != 0) return fail(STOKES_E_INVAL, "stokes_particle_solve: part_offset[0] must be 0");
+    for (int p = 0; p < n_part; ++p)
+        if (part_offset[p + 1] - part_offset[p] < 4)
+            return fail(STOKES_E_INVAL, "stokes_particle_solve: every particle needs >= 4 surface points");
+    const int64_t mp = part_offset[n_part];
+    const int64_t ms = m0 + mp, ntot = ms + 2 * (int64_t)n_part, n3 = 3 * ntot;
+    if (ntot >= ((int64_t)1 << 30)) return fail(STOKES_E_INVAL, "stokes_particle_solve: too many points");
+    if ((m0 > 0 && (!y0 || !n0 || !w0)) || !yp || !np_ || !wp || !centers || !force || !torque ||
+        !U_out || !Omega_out)
+        return fail(STOKES_E_INVAL, "stokes_particle_solve: null pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n_surf = 1 + n_part;
+    const uint32_t sumflags = flags & STOKES_PREC_MIXED;
+
+    // host tables
+    std::vector<int64_t> sstart(n_surf), ssize(n_surf);
+    sstart[0] = 0;
+    ssize[0] = m0;
+    for (int p = 0; p < n_part; ++p) {
+        sstart[1 + p] = m0 + part_offset[p];
+        ssize[1 + p] = part_offset[p + 1] - part_offset[p];
+    }
+    std::vector<int32_t> sid(ms);
+    for (int s = 0; s < n_surf; ++s)
+        for (int64_t k = 0; k < ssize[s]; ++k) sid[sstart[s] + k] = s;
+    // trg_self of each surface's double-layer sum over all surface points
+    std::vector<int64_t> selfs((size_t)n_surf * ms, -1);
+    for (int s = 0; s < n_surf; ++s)
+        for (int64_t k = 0; k < ssize[s]; ++k) selfs[(size_t)s * ms + sstart[s] + k] = k;
+
+    // device scratch
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_T = take(3 * ms * 8), o_bx = take(3 * ms * 8), o_bn = take(3 * ms * 8),
+                 o_bw = take(ms * 8), o_sid = take(ms * 4), o_ss = take(n_surf * 8), o_sz = take(n_surf * 8),
+                 o_self = take((size_t)n_surf * ms * 8), o_qb = take(3 * ms * 8), o_D0 = take(3 * ms * 8),
+                 o_DP = take(3 * ms * 8), o_red = take(8 * n_surf * 8), o_area = take(8 * n_surf * 8),
+                 o_diag = take(n3 * 8), o_rhs = take(n3 * 8), o_slot = take(vector_plan_bytes(ntot, iters));
+    DevBuf buf;
+    STOKES_HIP(hipMalloc(&buf.p, off));
+    char* base = static_cast<char*>(buf.p);
+    double* T = reinterpret_cast<double*>(base + o_T);
+    double* bx = reinterpret_cast<double*>(base + o_bx);
+    double* bn = reinterpret_cast<double*>(base + o_bn);
+    double* bw = reinterpret_cast<double*>(base + o_bw);
+    int32_t* d_sid = reinterpret_cast<int32_t*>(base + o_sid);
+    int64_t* d_ss = reinterpret_cast<int64_t*>(base + o_ss);
+    int64_t* d_sz = reinterpret_cast<int64_t*>(base + o_sz);
+    int64_t* d_self = reinterpret_cast<int64_t*>(base + o_self);
+    double* qb = reinterpret_cast<double*>(base + o_qb);
+    double* D0 = reinterpret_cast<double*>(base + o_D0);
+    double* DP = reinterpret_cast<double*>(base + o_DP);
+    double* red = reinterpret_cast<double*>(base + o_red);
+    double* area = reinterpret_cast<double*>(base + o_area);
+    double* diag = reinterpret_cast<double*>(base + o_diag);
+    double* rhs = reinterpret_cast<double*>(base + o_rhs);
+    void* slot = base + o_slot;
+
+    // geometry: targets T (planes of M_s), per-surface blocks of points and normals
+    for (int c = 0; c < 3; ++c) {
+        if (m0 > 0) {
+            STOKES_HIP(hipMemcpyAsync(T + c * ms, y0 + c * m0, m0 * 8, hipMemcpyDeviceToDevice, st));
+            STOKES_HIP(hipMemcpyAsync(bx + c * m0, y0 + c * m0, m0 * 8, hipMemcpyDeviceToDevice, st));
+            STOKES_HIP(hipMemcpyAsync(bn + c * m0, n0 + c * m0, m0 * 8, hipMemcpyDeviceToDevice, st));
+        }
+        STOKES_HIP(hipMemcpyAsync(T + c * ms + m0, yp + c * mp, mp * 8, hipMemcpyDeviceToDevice, st));
+        for (int p = 0; p < n_part; ++p) {
+            const int64_t sz = ssize[1 + p], o = 3 * sstart[1 + p] + c * sz;
+            STOKES_HIP(hipMemcpyAsync(bx + o, yp + c * mp + part_offset[p], sz * 8, hipMemcpyDeviceToDevice, st));
+            STOKES_HIP(hipMemcpyAsync(bn + o, np_ + c * mp + part_offset[p], sz * 8, hipMemcpyDeviceToDevice, st));
+        }
+    }
+    if (m0 > 0) STOKES_HIP(hipMemcpyAsync(bw, w0, m0 * 8, hipMemcpyDeviceToDevice, st));
+    STOKES_HIP(hipMemcpyAsync(bw + m0, wp, mp * 8, hipMemcpyDeviceToDevice, st));
+    STOKES_HIP(hipMemcpyAsync(d_sid, sid.data(), ms * 4, hipMemcpyHostToDevice, st));
+    STOKES_HIP(hipMemcpyAsync(d_ss, sstart.data(), n_surf * 8, hipMemcpyHostToDevice, st));
+    STOKES_HIP(hipMemcpyAsync(d_sz, ssize.data(), n_surf * 8, hipMemcpyHostToDevice, st));
+    STOKES_HIP(hipMemcpyAsync(d_self, selfs.data(), (size_t)n_surf * ms * 8, hipMemcpyHostToDevice, st));
+    const Surfaces S{bx, bn, bw, d_sid, d_ss, d_sz};
+
+    hipLaunchKernelGGL(k_pt_rhs, dim3(grid1(ntot)), dim3(PB), 0, st, ms, ntot, T, n_part, centers, force,
+                       torque, mu, rhs);
+    hipLaunchKernelGGL(k_pt_diag, dim3(grid1(ntot)), dim3(PB), 0, st, S, ms, ntot, diag);
+    hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, st, S, (const double*)qb, centers, n_part, 0,
+                       area);
+    STOKES_HIP(hipGetLastError());
+
+    // w = A P^{-1} v: z = v / diag, then the operator
+    auto apply = [&](const double* v, double* z, double* w) -> int {
+        hipLaunchKernelGGL(k_pt_scale, dim3(grid1(n3)), dim3(PB), 0, st, n3, v, (const double*)diag, z);
+        hipLaunchKernelGGL(k_pt_gather, dim3(grid1(ms)), dim3(PB), 0, st, S, ms, ntot, (const double*)z, qb);
+        int rc = STOKES_OK;
+        if (m0 > 0) {
+            rc = stokes_dl_eval(m0, bx, bn, bw, qb, ms, T, d_self, near_r, sumflags, D0, st, nullptr);
+        } else {
+            STOKES_HIP(hipMemsetAsync(D0, 0, 3 * ms * 8, st));
+        }
+        if (rc) return rc;
+        for (int p = 0; p < n_part && !rc; ++p) {
+            const int s = 1 + p;
+            rc = stokes_dl_eval(ssize[s], bx + 3 * sstart[s], bn + 3 * sstart[s], bw + sstart[s],
+                                qb + 3 * sstart[s], ms, T, d_self + (size_t)s * ms, near_r,
+                                sumflags | (p > 0 ? STOKES_ACCUMULATE : 0u), DP, st, nullptr);
+        }
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, st, S, (const double*)qb, centers, n_part,
+                           1, red);
+        hipLaunchKernelGGL(k_pt_assemble, dim3(grid1(ntot)), dim3(PB), 0, st, S, ms, ntot, n_part,
+                           (const double*)z, (const double*)D0, (const double*)DP, (const double*)red,
+                           (const double*)area, centers, w);
+        STOKES_HIP(hipGetLastError());
+        return STOKES_OK;
+    };
+
+    Batch b;
+    int rc = b.init(st, false, true, false);
+    if (rc) return rc;
+    if ((rc = b.attach_vector(0, slot, ntot, iters, rhs))) return rc;
+    const std::vector<int> one{0};
+    if ((rc = b.start_vector(one))) return rc;
+    int done = 0;
+    double resid = b.status(0)[2];
+    if (b.status(0)[3] == 0.0) {
+        for (int j = 0; j < iters; ++j) {
+            SlotDesc& d = b.desc(0);
+            d.j = j;
+            if ((rc = apply(d.V + (int64_t)j * n3, d.z, d.w))) return rc;
+            if ((rc = b.step_ortho(one))) return rc;
+            done = j + 1;
+            resid = b.status(0)[2];
+            if (b.status(0)[3] != 0.0) break;   // exact breakdown
+        }
+    }
+    b.desc(0).j = done;
+    if ((rc = b.finalize_vector(one))) return rc;
+    SlotDesc& d = b.desc(0);
+    hipLaunchKernelGGL(k_pt_scale, dim3(grid1(n3)), dim3(PB), 0, st, n3, (const double*)d.w,
+                       (const double*)diag, d.x);
+    STOKES_HIP(hipGetLastError());
+    for (int c = 0; c < 3; ++c) {
+        STOKES_HIP(hipMemcpyAsync(U_out + c * n_part, d.x + c * ntot + ms, n_part * 8, hipMemcpyDeviceToDevice, st));
+        STOKES_HIP(hipMemcpyAsync(Omega_out + c * n_part, d.x + c * ntot + ms + n_part, n_part * 8,
+                                  hipMemcpyDeviceToDevice, st));
+        if (q_out) STOKES_HIP(hipMemcpyAsync(q_out + c * ms, d.x + c * ntot, ms * 8, hipMemcpyDeviceToDevice, st));
+    }
+    STOKES_HIP(hipStreamSynchronize(st));
+    if (resid_out) *resid_out = resid;
+    if (iters_out) *iters_out = done;
+    return STOKES_OK;
+}

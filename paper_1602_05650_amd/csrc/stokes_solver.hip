@@ -679,6 +679,28 @@ static int32_t dot_blocks(int64_t n) {
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (n + 1023) / 1024));
 }
 
+size_t vector_plan_bytes(int64_t n_vec, int32_t k) {
+    const int64_t n = 3 * n_vec;
+    const int32_t B = dot_blocks(n);
+    size_t b = 0;
+    auto add = [&](size_t bytes) { b += Carve::round(bytes) + 256; };
+    add(n * 8);                        // rhs
+    add((size_t)(k + 1) * n * 8);      // V
+    add(n * 8);                        // z
+    add(n * 8);                        // w
+    add(n * 8);                        // x
+    add((size_t)(k + 1) * B * 8);      // dotp
+    add(B * 8);                        // normp
+    add((k + 1) * 8);                  // hA
+    add((k + 1) * 8);                  // hB
+    add((size_t)(k + 1) * k * 8);      // H
+    add(k * 8);                        // cs
+    add(k * 8);                        // sn
+    add((k + 1) * 8);                  // g
+    add(k * 8);                        // y
+    return b + 4096;
+}
+
 SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed, uint32_t opts) {
     SlotPlan sp{};
     const int64_t N = (int64_t)n_fib * npf;
@@ -920,6 +942,13 @@ int Batch::launch_step(bool graph_sizes) {
     }
     if (!graph_sizes) prof_end(st_);
     hipLaunchKernelGGL(k_red, dim3(g(WL_RED, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_);
+    return launch_ortho(graph_sizes);
+}
+
+int Batch::launch_ortho(bool graph_sizes) {
+    const StepTables& T = *host_tab_;
+    auto g = [&](WL w, int cap) { return graph_sizes ? (unsigned)cap : grid_for(T.wl[w], cap); };
+    const dim3 b(BLOCK);
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_dot, dim3(g(WL_DOT, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, pass);
         hipLaunchKernelGGL(k_dred, dim3(g(WL_ONE, G_ONE)), b, 0, st_, dev_desc_, dev_tab_, pass);
@@ -996,6 +1025,82 @@ int Batch::finalize(const std::vector<int>& slots) {
     hipLaunchKernelGGL(k_backsub, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_vy, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     hipLaunchKernelGGL(k_solution, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+int Batch::attach_vector(int s, void* mem, int64_t n_vec, int32_t k, const double* rhs) {
+    const int64_t n = 3 * n_vec;
+    Carve c(mem);
+    SlotDesc d{};
+    d.N = (int32_t)n_vec;
+    d.k = k;
+    d.j = 0;
+    d.B = dot_blocks(n);
+    d.n_items_vec = (int32_t)((n + BLOCK - 1) / BLOCK);
+    d.n_items_node = (int32_t)((n_vec + BLOCK - 1) / BLOCK);
+    d.n_items_sl = 0;
+    d.sid = s;
+    double* rhs_d = c.take<double>(n);
+    d.rhs = rhs_d;
+    d.V = c.take<double>((size_t)(k + 1) * n);
+    d.z = c.take<double>(n);
+    d.w = c.take<double>(n);
+    d.x = c.take<double>(n);
+    d.dotp = c.take<double>((size_t)(k + 1) * d.B);
+    d.normp = c.take<double>(d.B);
+    d.hA = c.take<double>(k + 1);
+    d.hB = c.take<double>(k + 1);
+    d.H = c.take<double>((size_t)(k + 1) * k);
+    d.cs = c.take<double>(k);
+    d.sn = c.take<double>(k);
+    d.g = c.take<double>(k + 1);
+    d.y = c.take<double>(k);
+    if (c.off > vector_plan_bytes(n_vec, k)) return fail(STOKES_E_INVAL, "vector slot layout exceeds its plan");
+    STOKES_HIP(hipMemcpyAsync(rhs_d, rhs, n * 8, hipMemcpyDeviceToDevice, st_));
+    host_desc_[s] = d;
+    return STOKES_OK;
+}
+
+int Batch::start_vector(const std::vector<int>& slots) {
+    if (slots.empty()) return STOKES_OK;
+    set_list(WL_PRE, {});
+    set_list(WL_SL, {});
+    set_list(WL_RED, {});
+    set_list(WL_FIB, {});
+    set_list(WL_DOT, slots);
+    set_list(WL_ONE, slots);
+    set_list(WL_VEC, slots);
+    int rc = upload();
+    if (rc) return rc;
+    const StepTables& T = *host_tab_;
+    hipLaunchKernelGGL(k_init_norm, dim3(grid_for(T.wl[WL_DOT], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_init_beta, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_, dev_stat_);
+    hipLaunchKernelGGL(k_init_v0, dim3(grid_for(T.wl[WL_VEC], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    STOKES_HIP(hipGetLastError());
+    return read_status();
+}
+
+int Batch::step_ortho(const std::vector<int>& slots) {
+    if (slots.empty()) return STOKES_OK;
+    set_list(WL_DOT, slots);
+    set_list(WL_ONE, slots);
+    set_list(WL_VEC, slots);
+    int rc = upload();
+    if (rc) return rc;
+    if ((rc = launch_ortho(false))) return rc;
+    return read_status();
+}
+
+int Batch::finalize_vector(const std::vector<int>& slots) {
+    if (slots.empty()) return STOKES_OK;
+    set_list(WL_PRE, slots);
+    set_list(WL_ONE, slots);
+    int rc = upload();
+    if (rc) return rc;
+    const StepTables& T = *host_tab_;
+    hipLaunchKernelGGL(k_backsub, dim3(grid_for(T.wl[WL_ONE], G_ONE)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
+    hipLaunchKernelGGL(k_vy, dim3(grid_for(T.wl[WL_PRE], 4096)), dim3(BLOCK), 0, st_, dev_desc_, dev_tab_);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }

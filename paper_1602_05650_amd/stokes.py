@@ -76,6 +76,8 @@ def _load():
         "stokes_local_sbt": [I64, P, P, D, D, ctypes.c_int, P, P],
         "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, D, I32, U32, P, P, P, P],
         "stokes_nonlocal_sbt": [I32, I32, P, P, P, P, D, D, P, P],
+        "stokes_particle_solve": [I64, P, P, P, I32, P, P, P, P, P, P, P, D, D, I32, U32, P, P, P,
+                                  P, P, P],
         "stokes_session_create": [P, P],
         "stokes_session_submit": [P, P, P],
         "stokes_session_wait": [P, ctypes.c_uint64, P, P, I32],
@@ -269,6 +271,54 @@ def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1
                                       int(iters), flags, _ptr(out), ctypes.byref(res),
                                       ctypes.byref(it), _stream(stream)))
     return out, res.value, it.value
+
+
+def particle_solve(particles, force, torque, periphery=None, mu=1.0, iters=40, mixed=False,
+                   near_r=0.0, stream=None):
+    """Mobility of rigid particles in a fixed periphery (second-kind boundary integrals).
+
+    particles: list of (xyz (3, M), outward normals (3, M), weights (M,), centre (3,));
+    periphery: (xyz, outward normals, weights) or None for an unbounded fluid;
+    force, torque: (3, n_particles).  Arrays may be numpy or torch (copied to the
+    device).  Returns (U (3, n_p), Omega (3, n_p), q (3, M_s) device tensors,
+    residual, iterations)."""
+    import numpy as np
+    dev = torch.device("cuda", torch.cuda.current_device())
+
+    def d(a):
+        if isinstance(a, torch.Tensor):
+            return a.to(device=dev, dtype=torch.float64).contiguous()
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    def host(a):
+        return a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a, np.float64)
+
+    n_p = len(particles)
+    sizes = [host(pt[0]).shape[1] for pt in particles]
+    offs = (ctypes.c_int64 * (n_p + 1))(*np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+    yp = d(np.concatenate([host(pt[0]) for pt in particles], axis=1))
+    npn = d(np.concatenate([host(pt[1]) for pt in particles], axis=1))
+    wp = d(np.concatenate([host(pt[2]) for pt in particles]))
+    X = d(np.stack([host(pt[3]) for pt in particles], axis=1))
+    F, L = d(force).reshape(3, n_p), d(torque).reshape(3, n_p)
+    if periphery is None:
+        m0, y0, n0, w0 = 0, None, None, None
+    else:
+        y0, n0, w0 = (d(a) for a in periphery)
+        m0 = y0.shape[1]
+    ms = m0 + int(sum(sizes))
+    U = torch.empty((3, n_p), dtype=torch.float64, device=dev)
+    Om = torch.empty_like(U)
+    q = torch.empty((3, ms), dtype=torch.float64, device=dev)
+    res = ctypes.c_double(0.0)
+    it = ctypes.c_int32(0)
+    nz = lambda t: None if t is None else _ptr(t)
+    _check(_lib.stokes_particle_solve(m0, nz(y0), nz(n0), nz(w0), n_p, offs, _ptr(yp), _ptr(npn),
+                                      _ptr(wp), _ptr(X), _ptr(F), _ptr(L), float(mu), float(near_r),
+                                      int(iters), PREC_MIXED if mixed else PREC_FP64, _ptr(U),
+                                      _ptr(Om), _ptr(q), ctypes.byref(res), ctypes.byref(it),
+                                      _stream(stream)))
+    return U, Om, q, res.value, it.value
 
 
 def profile_enable(on=True):

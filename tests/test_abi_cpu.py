@@ -77,6 +77,17 @@ def test_status_strings_and_validation_without_gpu():
     assert L.stokes_nonlocal_sbt(0, 8, None, None, None, None, 0.01, 1.0, None, None) == S.OK
     assert L.stokes_nonlocal_sbt(2, 8, None, None, None, None, 0.0, 1.0, None, None) == S.E_INVAL
     assert L.stokes_nonlocal_sbt(2, 65, None, None, None, None, 0.01, 1.0, None, None) == S.E_INVAL
+    # particle solve: every particle needs >= 4 points, part_offset starts at 0
+    offs = (ctypes.c_int64 * 2)(0, 3)
+    assert L.stokes_particle_solve(0, None, None, None, 1, offs, None, None, None, None, None, None,
+                                   1.0, 0.0, 5, 0, None, None, None, None, None, None) == S.E_INVAL
+    offs = (ctypes.c_int64 * 2)(1, 9)
+    assert L.stokes_particle_solve(0, None, None, None, 1, offs, None, None, None, None, None, None,
+                                   1.0, 0.0, 5, 0, None, None, None, None, None, None) == S.E_INVAL
+    offs = (ctypes.c_int64 * 2)(0, 9)
+    assert L.stokes_particle_solve(0, None, None, None, 1, offs, None, None, None, None, None, None,
+                                   1.0, 0.0, 5, 0, None, None, None, None, None, None) == S.E_INVAL
+    assert "null" in S.last_error()
     assert L.stokes_session_create(None, None) == S.E_INVAL
     assert L.stokes_session_destroy(None) == S.E_INVAL
 

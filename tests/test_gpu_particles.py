@@ -1,0 +1,77 @@
+"""GPU rigid-particle mobility (stokes_particle_solve) against the oracle and the closed
+forms: Stokes drag and rotation of an unbounded sphere, a sphere in a concentric
+sphere (eq. concentric-sphere and the rotating-sphere torque), and an off-centre
+multi-particle configuration element by element."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1602_05650_amd import workloads as W  # noqa: E402
+
+MU = 1.3
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05650_amd import stokes
+    return stokes
+
+
+def sphere(nt, nph, R, c=(0.0, 0.0, 0.0)):
+    s = W.sphere_surface(nt, nph, R)
+    return s.xyz + np.asarray(c, float)[:, None], s.normal, s.weight
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_unbounded_sphere(S):
+    a, X = 0.7, np.array([0.1, -0.2, 0.3])
+    F, L = np.array([[1.0], [0.5], [-2.0]]), np.array([[0.3], [-1.0], [0.7]])
+    U, Om, q, res, it = S.particle_solve([(*sphere(12, 24, a, X), X)], F, L, mu=MU, iters=30)
+    assert rel(U.cpu().numpy()[:, 0], F[:, 0] / (6 * math.pi * MU * a)) <= 1e-10
+    assert rel(Om.cpu().numpy()[:, 0], L[:, 0] / (8 * math.pi * MU * a ** 3)) <= 1e-10
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_concentric_sphere_vs_oracle_and_closed_form(S, oracle_mod, mixed):
+    a, b = 1.0, 2.0
+    per = sphere(24, 48, b)
+    part = (*sphere(12, 24, a), np.zeros(3))
+    F, L = np.array([[0.0], [0.0], [1.0]]), np.array([[0.0], [0.0], [1.0]])
+    U, Om, q, res, it = S.particle_solve([part], F, L, periphery=per, mu=MU, iters=40, mixed=mixed)
+    U, Om, q = U.cpu().numpy(), Om.cpu().numpy(), q.cpu().numpy()
+    sysm = oracle_mod.ParticleSystem(per, [part], MU)
+    Ur, Omr, xr, h, m = oracle_mod.particle_solve(sysm, F, L, 40)
+    tol = 1e-10 if not mixed else 2e-5
+    assert rel(U[2], Ur[2]) <= tol and rel(Om[2], Omr[2]) <= tol
+    assert rel(q, xr[:, : sysm.Ms]) <= (1e-9 if not mixed else 1e-4)
+    lam = a / b
+    gam = 6 * math.pi * MU * a * 4 * (1 - lam ** 5) / (4 - 9 * lam + 10 * lam ** 3 - 9 * lam ** 5 + 4 * lam ** 6)
+    assert abs(U[2, 0] * gam - 1.0) < 6e-4                                  # eq. concentric-sphere
+    assert abs(Om[2, 0] * 8 * math.pi * MU * a ** 3 / (1 - lam ** 3) - 1.0) < 1e-6
+
+
+def test_three_particles_in_periphery_vs_oracle(S, oracle_mod):
+    rng = np.random.default_rng(4)
+    per = sphere(16, 32, 3.0)
+    Xs = [np.array([1.0, 0.2, -0.3]), np.array([-0.9, 0.8, 0.4]), np.array([0.1, -1.2, 0.9])]
+    parts = [(*sphere(8, 16, r, X), X) for r, X in zip((0.5, 0.35, 0.45), Xs)]
+    F = rng.standard_normal((3, 3))
+    L = rng.standard_normal((3, 3))
+    U, Om, q, res, it = S.particle_solve(parts, F, L, periphery=per, mu=MU, iters=25)
+    sysm = oracle_mod.ParticleSystem(per, parts, MU)
+    Ur, Omr, xr, h, m = oracle_mod.particle_solve(sysm, F, L, 25)
+    assert it == m
+    assert rel(U.cpu().numpy(), Ur) <= 1e-10
+    assert rel(Om.cpu().numpy(), Omr) <= 1e-10
+    assert rel(q.cpu().numpy(), xr[:, : sysm.Ms]) <= 1e-9
+    assert abs(res - h[-1]) <= 1e-8 * h[0]
