@@ -78,8 +78,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-other", action="store_true",
                     help="time the oracle on the headline workload only")
-    ap.add_argument("--only", choices=["mixed", "fp64", "both", "none", "nonlocal"], default="both",
-                    help="none: serving run alone; nonlocal: the nonlocal-term section alone")
+    ap.add_argument("--only", choices=["mixed", "fp64", "both", "none", "nonlocal", "particles"],
+                    default="both",
+                    help="none: serving run alone; nonlocal / particles: that section alone")
     ap.add_argument("--extra", default="c0,c1,c4",
                     help="other workloads timed after the headline (c0,c1,c4 or none)")
     ap.add_argument("--step-pairs", type=float, default=0,
@@ -304,6 +305,62 @@ def nonlocal_run(S, torch, log_fn, n_fib=2048, nodes=64, iters=20, delta=0.01):
     return res
 
 
+def particles_run(S, torch, log_fn, iters=30):
+    """Confined rigid spheres (second-kind boundary integrals): the concentric-sphere
+    drag and torque against their closed forms, and a confined suspension of spheres
+    timed per solve."""
+    import math
+    from paper_1602_05650_amd import workloads as W
+    mu = 1.0
+
+    def sph(nt, nph, R, c=(0.0, 0.0, 0.0)):
+        s = W.sphere_surface(nt, nph, R)
+        return s.xyz + np.asarray(c, float)[:, None], s.normal, s.weight
+
+    res = {}
+    a, b = 1.0, 2.0
+    lam = a / b
+    per = sph(48, 96, b)
+    part = (*sph(24, 48, a), np.zeros(3))
+    U, Om, q, r, it = S.particle_solve([part], np.array([[0.0], [0.0], [1.0]]),
+                                       np.array([[0.0], [0.0], [1.0]]), periphery=per, mu=mu,
+                                       iters=iters)
+    gam = 6 * math.pi * mu * a * 4 * (1 - lam ** 5) / (4 - 9 * lam + 10 * lam ** 3 - 9 * lam ** 5 + 4 * lam ** 6)
+    res["concentric"] = {
+        "points": f"periphery 48x96 = 4608 (R = 2), sphere 24x48 = 1152 (a = 1)",
+        "drag_rel_error": float(f"{abs(float(U[2, 0]) * gam - 1.0):.3e}"),
+        "torque_rel_error": float(f"{abs(float(Om[2, 0]) * 8 * math.pi * mu * a ** 3 / (1 - lam ** 3) - 1.0):.3e}"),
+        "iterations": it}
+    # a confined suspension: C1's periphery (64 x 96 on R = 5) and 16 spheres
+    rng = np.random.default_rng(11)
+    centres = []
+    while len(centres) < 16:
+        c = rng.uniform(-3.2, 3.2, 3)
+        if np.linalg.norm(c) < 3.3 and all(np.linalg.norm(c - o) > 1.3 for o in centres):
+            centres.append(c)
+    parts = [(*sph(16, 32, 0.5, c), c) for c in centres]
+    per = sph(64, 96, 5.0)
+    F = rng.standard_normal((3, 16))
+    L = rng.standard_normal((3, 16))
+    ms = 6144 + 16 * 512
+    pairs = ms * ms - ms          # double-layer pairs per operator application
+    for mixed in (False, True):
+        S.particle_solve(parts, F, L, periphery=per, mu=mu, iters=2, mixed=mixed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, Om, q, r, it = S.particle_solve(parts, F, L, periphery=per, mu=mu, iters=iters,
+                                           mixed=mixed)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res["suspension_" + ("mixed" if mixed else "fp64")] = {
+            "points": f"periphery 6144 (R = 5) + 16 spheres x 512 (a = 0.5) = {ms}",
+            "ms": round(dt * 1e3, 2), "iterations": it, "ms_per_iteration": round(dt * 1e3 / it, 3),
+            "residual": float(f"{r:.3e}"),
+            "dl_gpair_per_s": round(pairs * it / dt / 1e9, 1)}
+        log_fn(f"particles {('mixed' if mixed else 'fp64')}: {dt * 1e3:.1f} ms, {it} iterations")
+    return res
+
+
 def cpu_baseline(c, seconds, log_fn, other=True):
     """The oracle (plain FP64 double loop, OpenMP over targets) on seeded samples of the
     headline workload: about 60% of `seconds` on all host threads, 25% on one thread;
@@ -401,6 +458,9 @@ def main():
 
     if args.only == "nonlocal":      # nonlocal-term section alone (for profiling it)
         print(json.dumps({"nonlocal": nonlocal_run(S, torch, log)}), flush=True)
+        return
+    if args.only == "particles":     # rigid-particle section alone (for profiling it)
+        print(json.dumps({"particles": particles_run(S, torch, log)}), flush=True)
         return
     if args.only == "none":          # serving run alone (for profiling it)
         print(json.dumps({"serving": serving_run(S, args.serving_requests, log, args.step_pairs,
@@ -509,6 +569,7 @@ def main():
             config_run(S, torch, e, 200 if e == "c0" else 10, 3, log) for e in extra}
     if extra and args.only == "both":
         out["nonlocal"] = nonlocal_run(S, torch, log)
+        out["particles"] = particles_run(S, torch, log)
     if not args.no_serving:
         try:
             out["serving"] = serving_run(S, args.serving_requests, log, args.step_pairs,

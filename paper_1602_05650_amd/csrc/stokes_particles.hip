@@ -26,7 +26,7 @@
 #include "solver_batch.hpp"
 
 namespace stokes {
-namespace {
+namespace pt {
 
 constexpr int PB = 256;
 constexpr double PI = 3.14159265358979323846;
@@ -230,10 +230,11 @@ struct DevBuf {
     }
 };
 
-}  // namespace
+}  // namespace pt
 }  // namespace stokes
 
 using namespace stokes;
+using namespace stokes::pt;
 
 extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const double* w0,
                                      int32_t n_part, const int64_t* part_offset, const double* yp,
