@@ -262,6 +262,44 @@ int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const 
                           int32_t iters, uint32_t flags, double* U_out, double* Omega_out,
                           double* q_out, double* resid_out, int32_t* iters_out, void* stream);
 
+/* ---- far-field acceleration: barycentric Lagrange treecode ---------------
+ *
+ * The single-layer sum of stokes_sl_eval (Stokeslet + doublet) with the far
+ * field approximated, as the paper does with its fast multipole method (section
+ * "Matrix-vector products and FMM"), here by a kernel-independent treecode
+ * (barycentric Lagrange interpolation at Chebyshev points of the second kind,
+ * the published method of Wang, Krasny and Tlupova, 2020).  A source cluster C
+ * acts on a target batch B (at most 64 targets) through (degree+1)^3 proxy
+ * points when (r_B + r_C) < theta |c_B - c_C| and C holds more sources than
+ * proxies; otherwise its children are visited, and leaves (at most leaf_size
+ * sources) are summed directly with the pair arithmetic of stokes_sl_eval
+ * (mixed: FP32 with FP64 near pairs).  The error against the exact sum is
+ * controlled by degree and theta (about 1e-6 relative at degree 6, theta 0.7).
+ *
+ * stokes_tree_create  builds the trees and interaction lists on the host from
+ *   DEVICE positions src_xyz [3*n_src] and trg_xyz [3*n_trg] (NULL: the targets
+ *   are the sources); degree 1..10, theta in (0, 1), leaf_size >= 1.  The plan
+ *   holds the geometry on the device until stokes_tree_destroy.  Synchronous.
+ * stokes_tree_sl_eval  one sum on a plan: src_force [3*n_src], src_weight
+ *   [n_src] or NULL, src_fiber / fiber_len as in stokes_sl_eval (or both NULL:
+ *   L = 1), mu, eps, near_r; flags STOKES_PREC_*, STOKES_EXCL_SELF_POINT (plans
+ *   built with targets = sources only), STOKES_NO_DOUBLET, STOKES_ACCUMULATE;
+ *   u_out [3*n_trg].  Asynchronous on stream; the plan's buffers are reused, so
+ *   evaluations on one plan must not overlap.
+ * stokes_tree_info     pair counts of one evaluation (targets x proxies and
+ *   targets x direct sources), proxy clusters and target batches.
+ */
+typedef struct stokes_tree stokes_tree;
+int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t n_trg, const double* trg_xyz,
+                       int32_t degree, double theta, int32_t leaf_size, void* stream,
+                       stokes_tree** out);
+int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, const double* src_weight,
+                        const int32_t* src_fiber, const double* fiber_len, double mu, double eps,
+                        double near_r, uint32_t flags, double* u_out, void* stream);
+int stokes_tree_info(const stokes_tree* t, int64_t* proxy_pairs, int64_t* direct_pairs,
+                     int32_t* n_proxy_clusters, int32_t* n_batches);
+int stokes_tree_destroy(stokes_tree* t);
+
 /* ---- serving: continuous batching of mobility solves ------------------- */
 typedef struct stokes_session stokes_session;
 

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 SOURCES = ["stokes_runtime.hip", "stokes_sums.hip", "stokes_solver.hip", "stokes_session.hip",
+           "stokes_tree.hip",
            "stokes_particles.hip"]
 LIB = os.path.join(PKG, "libstokes.so")
 ARCH = os.environ.get("STOKES_OFFLOAD_ARCH", "gfx950")

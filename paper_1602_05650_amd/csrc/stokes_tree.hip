@@ -1,0 +1,772 @@
+// Far-field acceleration of the single-layer sum (the paper evaluates the sums with
+// a fast multipole method, section "Matrix-vector products and FMM"): a
+// kernel-independent treecode with barycentric Lagrange interpolation at
+// Chebyshev points (the published method of Wang, Krasny and Tlupova, 2020),
+// with the direct pair arithmetic as its near field.
+//
+//   Sources: a tree of boxes; every cluster C holds proxy points p_k, the tensor
+//   Chebyshev points (second kind, degree n) of its box, and proxy charges
+//       F_k = sum_{j in C} L_k(y_j) s_j,    D_k = sum_{j in C} L_k(y_j) c_j s_j
+//   (L_k the tensor barycentric Lagrange basis of the box, s_j = w_j f_j /(8 pi mu),
+//   c_j the doublet coefficient).  Targets: batches of at most 64 (median splits).
+//   A batch B takes cluster C through its proxies when (r_B + r_C) < theta |c_B - c_C|
+//   and C has more sources than proxies:
+//       u_i += sum_k [ G(x_i - p_k) F_k + W(x_i - p_k) D_k ]   (8 pi mu G, W unscaled)
+//   otherwise it recurses into C's children or, at a leaf, sums C's sources directly.
+//   The error is controlled by n and theta (measured against the exact sum).
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "stokes_internal.hpp"
+
+namespace stokes {
+namespace tree {
+
+constexpr int TB = 256;        // threads per workgroup (4 waves, one batch per wave)
+constexpr int BATCH = 64;      // targets per batch
+constexpr int MAX_DEG = 10;
+
+struct Cluster {
+    double lo[3], hi[3], c[3], r;
+    int64_t start, count;
+    int32_t first_child, n_child;
+};
+
+struct Batch {
+    double c[3], r;
+    int64_t start;
+    int32_t count;
+};
+
+// Octree-like midpoint splits: every dimension whose extent is at least half the
+// largest is halved, until a cluster holds at most `leaf` points.
+static void build_sources(const std::vector<double>& xyz, int64_t n, std::vector<int64_t>& perm,
+                          std::vector<Cluster>& cl, int leaf) {
+    perm.resize(n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    struct Item { int64_t start, count; int32_t self; };
+    cl.clear();
+    cl.push_back(Cluster{});
+    std::vector<Item> stack{{0, n, 0}};
+    std::vector<int64_t> tmp;
+    while (!stack.empty()) {
+        const Item it = stack.back();
+        stack.pop_back();
+        Cluster& C = cl[it.self];
+        C.start = it.start;
+        C.count = it.count;
+        for (int d = 0; d < 3; ++d) {
+            C.lo[d] = INFINITY;
+            C.hi[d] = -INFINITY;
+        }
+        for (int64_t k = it.start; k < it.start + it.count; ++k)
+            for (int d = 0; d < 3; ++d) {
+                const double v = xyz[d * n + perm[k]];
+                C.lo[d] = std::min(C.lo[d], v);
+                C.hi[d] = std::max(C.hi[d], v);
+            }
+        double emax = 0.0;
+        for (int d = 0; d < 3; ++d) emax = std::max(emax, C.hi[d] - C.lo[d]);
+        double r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            C.c[d] = 0.5 * (C.lo[d] + C.hi[d]);
+            r2 += 0.25 * (C.hi[d] - C.lo[d]) * (C.hi[d] - C.lo[d]);
+        }
+        C.r = std::sqrt(r2);
+        C.first_child = -1;
+        C.n_child = 0;
+        if (it.count <= leaf || emax == 0.0) continue;
+        // split
+        std::vector<std::pair<int64_t, int64_t>> groups{{it.start, it.count}};
+        for (int d = 0; d < 3; ++d) {
+            if (C.hi[d] - C.lo[d] < 0.5 * emax) continue;
+            const double mid = C.c[d];
+            std::vector<std::pair<int64_t, int64_t>> ng;
+            for (auto g : groups) {
+                auto b = perm.begin() + g.first, e = b + g.second;
+                auto m = std::stable_partition(b, e, [&](int64_t q) { return xyz[d * n + q] <= mid; });
+                const int64_t a = m - b;
+                if (a == 0 || a == g.second) {
+                    ng.push_back(g);
+                } else {
+                    ng.push_back({g.first, a});
+                    ng.push_back({g.first + a, g.second - a});
+                }
+            }
+            groups.swap(ng);
+        }
+        if (groups.size() < 2) continue;
+        const int32_t first = (int32_t)cl.size();
+        cl[it.self].first_child = first;
+        cl[it.self].n_child = (int32_t)groups.size();
+        for (size_t g = 0; g < groups.size(); ++g) {
+            cl.push_back(Cluster{});
+            stack.push_back({groups[g].first, groups[g].second, first + (int32_t)g});
+        }
+    }
+}
+
+// Median splits along the longest extent down to at most BATCH targets per batch.
+static void build_batches(const std::vector<double>& xyz, int64_t n, std::vector<int64_t>& perm,
+                          std::vector<Batch>& bt) {
+    perm.resize(n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    bt.clear();
+    std::vector<std::pair<int64_t, int64_t>> stack{{0, n}};
+    while (!stack.empty()) {
+        const auto g = stack.back();
+        stack.pop_back();
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t k = g.first; k < g.first + g.second; ++k)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], xyz[d * n + perm[k]]);
+                hi[d] = std::max(hi[d], xyz[d * n + perm[k]]);
+            }
+        if (g.second <= BATCH) {
+            Batch B{};
+            double r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                B.c[d] = 0.5 * (lo[d] + hi[d]);
+                r2 += 0.25 * (hi[d] - lo[d]) * (hi[d] - lo[d]);
+            }
+            B.r = std::sqrt(r2);
+            B.start = g.first;
+            B.count = (int32_t)g.second;
+            bt.push_back(B);
+            continue;
+        }
+        int dm = 0;
+        for (int d = 1; d < 3; ++d)
+            if (hi[d] - lo[d] > hi[dm] - lo[dm]) dm = d;
+        const int64_t half = g.second / 2;
+        auto b = perm.begin() + g.first;
+        std::nth_element(b, b + half, b + g.second,
+                         [&](int64_t a, int64_t c) { return xyz[dm * n + a] < xyz[dm * n + c]; });
+        stack.push_back({g.first, half});
+        stack.push_back({g.first + half, g.second - half});
+    }
+}
+
+// ---- device kernels -------------------------------------------------------------
+
+struct DevCl {              // what the kernels need of a proxy cluster
+    double lo[3], hi[3];
+    int64_t start, count;
+};
+
+// Sorted source packs: s = pref * w * f, doublet coefficient c = (eps L)^2 / 2 and
+// the mixed path's near threshold t = max(near_r, 2 eps L)^2.
+__global__ __launch_bounds__(TB) void k_tr_src(int64_t ns, const int64_t* sperm, const double* f,
+                                               const double* w, const int32_t* fib, const double* flen,
+                                               double pref, double eps, double near_r, int doublet,
+                                               double* ss, double* sc, float* st) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= ns) return;
+    const int64_t o = sperm[j];
+    const double wj = w ? w[o] : 1.0;
+    const double L = (fib && flen) ? flen[fib[o]] : 1.0;
+    const double a = eps * L;
+    const double k = pref * wj;
+    ss[j] = k * f[o];
+    ss[ns + j] = k * f[ns + o];
+    ss[2 * ns + j] = k * f[2 * ns + o];
+    sc[j] = doublet ? 0.5 * a * a : 0.0;
+    const double tr = fmax(near_r, 2.0 * a);
+    st[j] = (float)(tr * tr);
+}
+
+// Chebyshev points of the second kind, cos(i pi / n), and their barycentric weights.
+__device__ __forceinline__ double cheb_node(int i, int n) { return cos(i * 3.14159265358979323846 / n); }
+__device__ __forceinline__ double cheb_bw(int i, int n) {
+    const double s = (i & 1) ? -1.0 : 1.0;
+    return (i == 0 || i == n) ? 0.5 * s : s;
+}
+
+// Proxy charges of one cluster per workgroup: F_k = sum_j L_k(y_j) s_j and
+// D_k = sum_j L_k(y_j) c_j s_j.  Proxies are taken TB at a time (one per thread);
+// for each pass the 1-D barycentric basis values of 64 sources at a time are
+// staged in LDS.
+__global__ __launch_bounds__(TB) void k_tr_charges(int deg, const DevCl* cls, const double* sxyz,
+                                                   int64_t ns, const double* ss, const double* sc,
+                                                   double* pF, double* pD) {
+    __shared__ double lb[3][64][MAX_DEG + 1];
+    __shared__ double sv[6][64];
+    const int q = blockIdx.x, t = threadIdx.x;
+    const DevCl* Cp = cls + q;            // (the box is indexed per thread: no private copy)
+    const int64_t c_start = Cp->start, c_count = Cp->count;
+    const int n1 = deg + 1, P = n1 * n1 * n1;
+    for (int k0 = 0; k0 < P; k0 += TB) {
+        const int k = k0 + t;
+        const int kx = k / (n1 * n1), ky = (k / n1) % n1, kz = k % n1;
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t j0 = 0; j0 < c_count; j0 += 64) {
+            const int m = (int)min<int64_t>(64, c_count - j0);
+            __syncthreads();
+            if (t < 3 * 64) {
+                const int jj = t / 3, d = t - 3 * jj;
+                if (jj < m) {
+                    const int64_t j = c_start + j0 + jj;
+                    const double lo = Cp->lo[d], ext = Cp->hi[d] - lo;
+                    const double x = 2.0 * (sxyz[d * ns + j] - lo) / ext - 1.0;
+                    int hit = -1;
+                    double den = 0.0;
+                    for (int i = 0; i <= deg; ++i) {
+                        const double dx = x - cheb_node(i, deg);
+                        if (dx == 0.0) hit = i;
+                        den += cheb_bw(i, deg) / (dx == 0.0 ? 1.0 : dx);
+                    }
+                    for (int i = 0; i <= deg; ++i) {
+                        const double dx = x - cheb_node(i, deg);
+                        lb[d][jj][i] = hit >= 0 ? (i == hit ? 1.0 : 0.0) : cheb_bw(i, deg) / dx / den;
+                    }
+                    if (d == 0) {
+                        const double cj = sc[j];
+                        for (int c = 0; c < 3; ++c) {
+                            sv[c][jj] = ss[c * ns + j];
+                            sv[3 + c][jj] = cj * ss[c * ns + j];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (k < P)
+                for (int jj = 0; jj < m; ++jj) {
+                    const double L = lb[0][jj][kx] * lb[1][jj][ky] * lb[2][jj][kz];
+#pragma unroll
+                    for (int b = 0; b < 6; ++b) acc[b] = fma(L, sv[b][jj], acc[b]);
+                }
+        }
+        if (k < P)
+            for (int c = 0; c < 3; ++c) {
+                pF[((int64_t)q * 3 + c) * P + k] = acc[c];
+                pD[((int64_t)q * 3 + c) * P + k] = acc[3 + c];
+            }
+    }
+}
+
+// One wave per target batch.  Lists: proxy clusters px_list[px_off[b] .. px_off[b+1]),
+// direct source ranges dr_*[dr_off[b] .. dr_off[b+1]).
+struct EvalArgs {
+    int64_t ns, nt;
+    const double* sxyz;      // [3][ns] sorted sources
+    const double* ss;        // [3][ns]
+    const double* sc;        // [ns]
+    const float* st;         // [ns]
+    const double* txyz;      // [3][nt] sorted targets
+    const int64_t* tperm;    // [nt]
+    const int64_t* tself;    // [nt] sorted source index of the target, or -1
+    const Batch* bt;
+    int32_t nb;
+    const int32_t* px_off;
+    const int32_t* px_list;
+    const double* px_pos;    // [n_px][3][P]
+    const double* pF;
+    const double* pD;
+    int32_t P;
+    const int32_t* dr_off;
+    const int64_t* dr_start;
+    const int32_t* dr_count;
+    double* out;
+    int accumulate;
+};
+
+__device__ __forceinline__ void kahan(float& s, float& c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// FP64 single-layer pair (Stokeslet + doublet) into (ux, uy, uz).
+__device__ __forceinline__ void pair64(double dx, double dy, double dz, double sx, double sy, double sz,
+                                       double c, double& ux, double& uy, double& uz) {
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double ri = 1.0 / sqrt(r2);
+    const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+    const double ds = dx * sx + dy * sy + dz * sz;
+    const double A = fma(c, ri3, ri);
+    const double B = ds * fma(-3.0 * c, ri5, ri3);
+    ux = fma(A, sx, fma(B, dx, ux));
+    uy = fma(A, sy, fma(B, dy, uy));
+    uz = fma(A, sz, fma(B, dz, uz));
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(64) void k_tr_eval(EvalArgs a) {
+    __shared__ float lf[64][12];
+    __shared__ double ld[64][10];
+    const int b = blockIdx.x, l = threadIdx.x;
+    if (b >= a.nb) return;
+    const Batch B = a.bt[b];
+    const bool act = l < B.count;
+    const int64_t ti = B.start + (act ? l : 0);
+    const double cx = B.c[0], cy = B.c[1], cz = B.c[2];
+    const double x = a.txyz[ti], y = a.txyz[a.nt + ti], z = a.txyz[2 * a.nt + ti];
+    const int64_t self = a.tself ? a.tself[ti] : -1;
+    const float xl = (float)(x - cx), yl = (float)(y - cy), zl = (float)(z - cz);
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+    // far field: proxies
+    for (int e = a.px_off[b]; e < a.px_off[b + 1]; ++e) {
+        const int q = a.px_list[e];
+        const double* pos = a.px_pos + (int64_t)q * 3 * a.P;
+        const double* F = a.pF + (int64_t)q * 3 * a.P;
+        const double* D = a.pD + (int64_t)q * 3 * a.P;
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+        for (int k0 = 0; k0 < a.P; k0 += 64) {
+            const int m = min(64, a.P - k0);
+            __syncthreads();
+            if (l < m) {
+                const int k = k0 + l;
+                if (MIXED) {
+                    lf[l][0] = (float)(pos[k] - cx);
+                    lf[l][1] = (float)(pos[a.P + k] - cy);
+                    lf[l][2] = (float)(pos[2 * a.P + k] - cz);
+                    for (int c = 0; c < 3; ++c) {
+                        lf[l][3 + c] = (float)F[c * a.P + k];
+                        lf[l][6 + c] = (float)D[c * a.P + k];
+                        lf[l][9 + c] = (float)(-3.0 * D[c * a.P + k]);
+                    }
+                } else {
+                    ld[l][0] = pos[k] - cx;
+                    ld[l][1] = pos[a.P + k] - cy;
+                    ld[l][2] = pos[2 * a.P + k] - cz;
+                    for (int c = 0; c < 3; ++c) {
+                        ld[l][3 + c] = F[c * a.P + k];
+                        ld[l][6 + c] = D[c * a.P + k];
+                    }
+                }
+            }
+            __syncthreads();
+            if (MIXED) {
+                for (int k = 0; k < m; ++k) {
+                    const float dx = xl - lf[k][0], dy = yl - lf[k][1], dz = zl - lf[k][2];
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                    const float dF = fmaf(dx, lf[k][3], fmaf(dy, lf[k][4], dz * lf[k][5]));
+                    const float dD = fmaf(dx, lf[k][9], fmaf(dy, lf[k][10], dz * lf[k][11]));
+                    const float g = fmaf(dD, ri5, dF * ri3);
+                    p0 = fmaf(lf[k][3], ri, fmaf(lf[k][6], ri3, fmaf(g, dx, p0)));
+                    p1 = fmaf(lf[k][4], ri, fmaf(lf[k][7], ri3, fmaf(g, dy, p1)));
+                    p2 = fmaf(lf[k][5], ri, fmaf(lf[k][8], ri3, fmaf(g, dz, p2)));
+                }
+            } else {
+                for (int k = 0; k < m; ++k) {
+                    const double dx = (x - cx) - ld[k][0], dy = (y - cy) - ld[k][1], dz = (z - cz) - ld[k][2];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const double ri = 1.0 / sqrt(r2);
+                    const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                    const double dF = dx * ld[k][3] + dy * ld[k][4] + dz * ld[k][5];
+                    const double dD = dx * ld[k][6] + dy * ld[k][7] + dz * ld[k][8];
+                    const double g = dF * ri3 - 3.0 * dD * ri5;
+                    u0 += ld[k][3] * ri + ld[k][6] * ri3 + g * dx;
+                    u1 += ld[k][4] * ri + ld[k][7] * ri3 + g * dy;
+                    u2 += ld[k][5] * ri + ld[k][8] * ri3 + g * dz;
+                }
+            }
+        }
+        if (MIXED) {
+            kahan(S0, C0, p0);
+            kahan(S1, C1, p1);
+            kahan(S2, C2, p2);
+        }
+    }
+    // near field: direct ranges
+    for (int e = a.dr_off[b]; e < a.dr_off[b + 1]; ++e) {
+        const int64_t j0s = a.dr_start[e];
+        const int32_t cnt = a.dr_count[e];
+        for (int32_t k0 = 0; k0 < cnt; k0 += 64) {
+            const int m = min(64, cnt - k0);
+            __syncthreads();
+            if (l < m) {
+                const int64_t j = j0s + k0 + l;
+                if (MIXED) {
+                    lf[l][0] = (float)(a.sxyz[j] - cx);
+                    lf[l][1] = (float)(a.sxyz[a.ns + j] - cy);
+                    lf[l][2] = (float)(a.sxyz[2 * a.ns + j] - cz);
+                    lf[l][3] = (float)a.ss[j];
+                    lf[l][4] = (float)a.ss[a.ns + j];
+                    lf[l][5] = (float)a.ss[2 * a.ns + j];
+                    lf[l][6] = (float)a.sc[j];
+                    lf[l][7] = (float)(-3.0 * a.sc[j]);
+                    lf[l][8] = a.st[j];
+                } else {
+                    ld[l][0] = a.sxyz[j];
+                    ld[l][1] = a.sxyz[a.ns + j];
+                    ld[l][2] = a.sxyz[2 * a.ns + j];
+                    ld[l][3] = a.ss[j];
+                    ld[l][4] = a.ss[a.ns + j];
+                    ld[l][5] = a.ss[2 * a.ns + j];
+                    ld[l][6] = a.sc[j];
+                }
+            }
+            __syncthreads();
+            if (MIXED) {
+                float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+                uint64_t near = 0;
+                for (int k = 0; k < m; ++k) {
+                    const float dx = xl - lf[k][0], dy = yl - lf[k][1], dz = zl - lf[k][2];
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    if (r2 < lf[k][8]) {
+                        near |= 1ull << k;
+                        continue;
+                    }
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                    const float ds = fmaf(dx, lf[k][3], fmaf(dy, lf[k][4], dz * lf[k][5]));
+                    const float A = fmaf(lf[k][6], ri3, ri);
+                    const float Bc = ds * fmaf(lf[k][7], ri5, ri3);
+                    p0 = fmaf(A, lf[k][3], fmaf(Bc, dx, p0));
+                    p1 = fmaf(A, lf[k][4], fmaf(Bc, dy, p1));
+                    p2 = fmaf(A, lf[k][5], fmaf(Bc, dz, p2));
+                }
+                kahan(S0, C0, p0);
+                kahan(S1, C1, p1);
+                kahan(S2, C2, p2);
+                while (near) {
+                    const int k = __builtin_ctzll(near);
+                    near &= near - 1;
+                    const int64_t j = j0s + k0 + k;
+                    if (j == self) continue;
+                    const double dx = x - a.sxyz[j], dy = y - a.sxyz[a.ns + j], dz = z - a.sxyz[2 * a.ns + j];
+                    if (dx == 0.0 && dy == 0.0 && dz == 0.0) continue;   // coincident: skipped
+                    pair64(dx, dy, dz, a.ss[j], a.ss[a.ns + j], a.ss[2 * a.ns + j], a.sc[j], u0, u1, u2);
+                }
+            } else {
+                for (int k = 0; k < m; ++k) {
+                    if (j0s + k0 + k == self) continue;
+                    const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
+                    if (dx == 0.0 && dy == 0.0 && dz == 0.0) continue;
+                    pair64(dx, dy, dz, ld[k][3], ld[k][4], ld[k][5], ld[k][6], u0, u1, u2);
+                }
+            }
+        }
+    }
+    if (!act) return;
+    double r0 = u0, r1 = u1, r2 = u2;
+    if (MIXED) {
+        r0 += (double)S0 - (double)C0;
+        r1 += (double)S1 - (double)C1;
+        r2 += (double)S2 - (double)C2;
+    }
+    const int64_t o = a.tperm[ti];
+    if (a.accumulate) {
+        a.out[o] += r0;
+        a.out[a.nt + o] += r1;
+        a.out[2 * a.nt + o] += r2;
+    } else {
+        a.out[o] = r0;
+        a.out[a.nt + o] = r1;
+        a.out[2 * a.nt + o] = r2;
+    }
+}
+
+}  // namespace tree
+}  // namespace stokes
+
+using namespace stokes;
+using namespace stokes::tree;
+
+struct stokes_tree {
+    int64_t ns = 0, nt = 0;
+    bool same = false;
+    int deg = 0, P = 0;
+    double theta = 0.0;
+    int32_t nb = 0, n_px = 0;
+    int64_t pairs_px = 0, pairs_dir = 0;
+    void* mem = nullptr;
+    // device views into mem
+    double* sxyz = nullptr;
+    int64_t* sperm = nullptr;
+    double* txyz = nullptr;
+    int64_t* tperm = nullptr;
+    int64_t* tself = nullptr;
+    Batch* bt = nullptr;
+    int32_t* px_off = nullptr;
+    int32_t* px_list = nullptr;
+    DevCl* px_cl = nullptr;
+    double* px_pos = nullptr;
+    double* pF = nullptr;
+    double* pD = nullptr;
+    int32_t* dr_off = nullptr;
+    int64_t* dr_start = nullptr;
+    int32_t* dr_count = nullptr;
+    double* ss = nullptr;
+    double* sc = nullptr;
+    float* st = nullptr;
+    ~stokes_tree() {
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t n_trg,
+                                  const double* trg_xyz, int32_t degree, double theta,
+                                  int32_t leaf_size, void* stream, stokes_tree** out) {
+    if (!out) return fail(STOKES_E_INVAL, "stokes_tree_create: null out");
+    *out = nullptr;
+    if (n_src < 1 || !src_xyz) return fail(STOKES_E_INVAL, "stokes_tree_create: need n_src >= 1 and src_xyz");
+    if (degree < 1 || degree > MAX_DEG) return fail(STOKES_E_INVAL, "stokes_tree_create: degree must be 1..10");
+    if (!(theta > 0.0 && theta < 1.0)) return fail(STOKES_E_INVAL, "stokes_tree_create: theta must be in (0, 1)");
+    if (leaf_size < 1) return fail(STOKES_E_INVAL, "stokes_tree_create: leaf_size must be >= 1");
+    const bool same = trg_xyz == nullptr;
+    if (same) n_trg = n_src;
+    if (n_trg < 1) return fail(STOKES_E_INVAL, "stokes_tree_create: need n_trg >= 1");
+    if (n_src >= ((int64_t)1 << 31) || n_trg >= ((int64_t)1 << 31))
+        return fail(STOKES_E_INVAL, "stokes_tree_create: too many points");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<double> hs(3 * n_src), ht;
+    STOKES_HIP(hipMemcpyAsync(hs.data(), src_xyz, 3 * n_src * 8, hipMemcpyDeviceToHost, st));
+    if (!same) {
+        ht.resize(3 * n_trg);
+        STOKES_HIP(hipMemcpyAsync(ht.data(), trg_xyz, 3 * n_trg * 8, hipMemcpyDeviceToHost, st));
+    }
+    STOKES_HIP(hipStreamSynchronize(st));
+    for (double v : hs)
+        if (!std::isfinite(v)) return fail(STOKES_E_NONFINITE, "stokes_tree_create: non-finite source position");
+    for (double v : ht)
+        if (!std::isfinite(v)) return fail(STOKES_E_NONFINITE, "stokes_tree_create: non-finite target position");
+    const std::vector<double>& tx = same ? hs : ht;
+
+    std::vector<int64_t> sperm, tperm;
+    std::vector<Cluster> cl;
+    std::vector<Batch> bt;
+    build_sources(hs, n_src, sperm, cl, leaf_size);
+    build_batches(tx, n_trg, tperm, bt);
+    const int n1 = degree + 1, P = n1 * n1 * n1;
+    // interaction lists
+    std::vector<int32_t> px_off{0}, px_list, dr_off{0}, dr_count, slot_of(cl.size(), -1);
+    std::vector<int64_t> dr_start;
+    std::vector<int32_t> used;
+    int64_t pairs_px = 0, pairs_dir = 0;
+    std::vector<int32_t> stack;
+    for (const Batch& B : bt) {
+        stack.assign(1, 0);
+        while (!stack.empty()) {
+            const int32_t ci = stack.back();
+            stack.pop_back();
+            const Cluster& C = cl[ci];
+            const double dx = B.c[0] - C.c[0], dy = B.c[1] - C.c[1], dz = B.c[2] - C.c[2];
+            const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+            const bool far = B.r + C.r < theta * dist;
+            if (far && C.count > P) {
+                if (slot_of[ci] < 0) {
+                    slot_of[ci] = (int32_t)used.size();
+                    used.push_back(ci);
+                }
+                px_list.push_back(slot_of[ci]);
+                pairs_px += (int64_t)B.count * P;
+            } else if (C.n_child == 0 || far) {
+                if (!dr_start.empty() && dr_off.size() == px_off.size() &&
+                    (int64_t)dr_start.size() > dr_off.back() &&
+                    dr_start.back() + dr_count.back() == C.start && dr_count.back() + C.count < (1 << 30)) {
+                    dr_count.back() += (int32_t)C.count;      // adjacent ranges merge
+                } else {
+                    dr_start.push_back(C.start);
+                    dr_count.push_back((int32_t)C.count);
+                }
+                pairs_dir += (int64_t)B.count * C.count;
+            } else {
+                for (int32_t k = C.n_child - 1; k >= 0; --k) stack.push_back(C.first_child + k);
+            }
+        }
+        px_off.push_back((int32_t)px_list.size());
+        dr_off.push_back((int32_t)dr_start.size());
+    }
+    // proxy clusters: boxes (degenerate extents padded) and Chebyshev points
+    const int32_t n_px = (int32_t)used.size();
+    std::vector<DevCl> pcl(n_px);
+    std::vector<double> ppos((size_t)n_px * 3 * P);
+    for (int32_t q = 0; q < n_px; ++q) {
+        const Cluster& C = cl[used[q]];
+        double emax = 0.0;
+        for (int d = 0; d < 3; ++d) emax = std::max(emax, C.hi[d] - C.lo[d]);
+        for (int d = 0; d < 3; ++d) {
+            double lo = C.lo[d], hi = C.hi[d];
+            const double minext = emax > 0.0 ? 1e-3 * emax : 1.0;   // flat or point-like boxes
+            if (hi - lo < minext) {
+                const double m = 0.5 * (lo + hi);
+                lo = m - 0.5 * minext;
+                hi = m + 0.5 * minext;
+            }
+            pcl[q].lo[d] = lo;
+            pcl[q].hi[d] = hi;
+        }
+        pcl[q].start = C.start;
+        pcl[q].count = C.count;
+        for (int k = 0; k < P; ++k) {
+            const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
+            for (int d = 0; d < 3; ++d) {
+                const double sn = std::cos(idx[d] * 3.14159265358979323846 / degree);
+                ppos[((size_t)q * 3 + d) * P + k] = pcl[q].lo[d] + 0.5 * (sn + 1.0) * (pcl[q].hi[d] - pcl[q].lo[d]);
+            }
+        }
+    }
+    // sorted coordinates, self indices
+    std::vector<double> sx(3 * n_src), txs(3 * n_trg);
+    for (int64_t j = 0; j < n_src; ++j)
+        for (int d = 0; d < 3; ++d) sx[d * n_src + j] = hs[d * n_src + sperm[j]];
+    for (int64_t i = 0; i < n_trg; ++i)
+        for (int d = 0; d < 3; ++d) txs[d * n_trg + i] = tx[d * n_trg + tperm[i]];
+    std::vector<int64_t> tself;
+    if (same) {
+        std::vector<int64_t> inv(n_src);
+        for (int64_t j = 0; j < n_src; ++j) inv[sperm[j]] = j;
+        tself.resize(n_trg);
+        for (int64_t i = 0; i < n_trg; ++i) tself[i] = inv[tperm[i]];
+    }
+
+    // one device allocation
+    auto t = new stokes_tree();
+    t->ns = n_src;
+    t->nt = n_trg;
+    t->same = same;
+    t->deg = degree;
+    t->P = P;
+    t->theta = theta;
+    t->nb = (int32_t)bt.size();
+    t->n_px = n_px;
+    t->pairs_px = pairs_px;
+    t->pairs_dir = pairs_dir;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (std::max<size_t>(bytes, 8) + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_sx = take(sx.size() * 8), o_sp = take(n_src * 8), o_tx = take(txs.size() * 8),
+                 o_tp = take(n_trg * 8), o_ts = take(tself.size() * 8), o_bt = take(bt.size() * sizeof(Batch)),
+                 o_po = take(px_off.size() * 4), o_pl = take(px_list.size() * 4),
+                 o_pc = take((size_t)n_px * sizeof(DevCl)), o_pp = take(ppos.size() * 8),
+                 o_pF = take(ppos.size() * 8), o_pD = take(ppos.size() * 8), o_do = take(dr_off.size() * 4),
+                 o_ds = take(dr_start.size() * 8), o_dc = take(dr_count.size() * 4), o_ss = take(3 * n_src * 8),
+                 o_sc = take(n_src * 8), o_st = take(n_src * 4);
+    hipError_t e = hipMalloc(&t->mem, off);
+    if (e != hipSuccess) {
+        delete t;
+        return hip_fail(e, "hipMalloc(tree)");
+    }
+    char* base = static_cast<char*>(t->mem);
+    t->sxyz = reinterpret_cast<double*>(base + o_sx);
+    t->sperm = reinterpret_cast<int64_t*>(base + o_sp);
+    t->txyz = reinterpret_cast<double*>(base + o_tx);
+    t->tperm = reinterpret_cast<int64_t*>(base + o_tp);
+    t->tself = same ? reinterpret_cast<int64_t*>(base + o_ts) : nullptr;
+    t->bt = reinterpret_cast<Batch*>(base + o_bt);
+    t->px_off = reinterpret_cast<int32_t*>(base + o_po);
+    t->px_list = reinterpret_cast<int32_t*>(base + o_pl);
+    t->px_cl = reinterpret_cast<DevCl*>(base + o_pc);
+    t->px_pos = reinterpret_cast<double*>(base + o_pp);
+    t->pF = reinterpret_cast<double*>(base + o_pF);
+    t->pD = reinterpret_cast<double*>(base + o_pD);
+    t->dr_off = reinterpret_cast<int32_t*>(base + o_do);
+    t->dr_start = reinterpret_cast<int64_t*>(base + o_ds);
+    t->dr_count = reinterpret_cast<int32_t*>(base + o_dc);
+    t->ss = reinterpret_cast<double*>(base + o_ss);
+    t->sc = reinterpret_cast<double*>(base + o_sc);
+    t->st = reinterpret_cast<float*>(base + o_st);
+    auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (!bytes) return STOKES_OK;
+        hipError_t r = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+        return r == hipSuccess ? STOKES_OK : hip_fail(r, "hipMemcpyAsync(tree)");
+    };
+    int rc = STOKES_OK;
+    if (!rc) rc = up(t->sxyz, sx.data(), sx.size() * 8);
+    if (!rc) rc = up(t->sperm, sperm.data(), n_src * 8);
+    if (!rc) rc = up(t->txyz, txs.data(), txs.size() * 8);
+    if (!rc) rc = up(t->tperm, tperm.data(), n_trg * 8);
+    if (!rc && same) rc = up(t->tself, tself.data(), tself.size() * 8);
+    if (!rc) rc = up(t->bt, bt.data(), bt.size() * sizeof(Batch));
+    if (!rc) rc = up(t->px_off, px_off.data(), px_off.size() * 4);
+    if (!rc) rc = up(t->px_list, px_list.data(), px_list.size() * 4);
+    if (!rc) rc = up(t->px_cl, pcl.data(), pcl.size() * sizeof(DevCl));
+    if (!rc) rc = up(t->px_pos, ppos.data(), ppos.size() * 8);
+    if (!rc) rc = up(t->dr_off, dr_off.data(), dr_off.size() * 4);
+    if (!rc) rc = up(t->dr_start, dr_start.data(), dr_start.size() * 8);
+    if (!rc) rc = up(t->dr_count, dr_count.data(), dr_count.size() * 4);
+    if (!rc) {
+        hipError_t r = hipStreamSynchronize(st);
+        if (r != hipSuccess) rc = hip_fail(r, "hipStreamSynchronize(tree)");
+    }
+    if (rc) {
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return STOKES_OK;
+}
+
+extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, const double* src_weight,
+                                   const int32_t* src_fiber, const double* fiber_len, double mu,
+                                   double eps, double near_r, uint32_t flags, double* u_out,
+                                   void* stream) {
+    if (!t) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: null tree");
+    if (flags & ~(STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_NO_DOUBLET | STOKES_ACCUMULATE))
+        return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: unsupported flag bits");
+    if ((flags & STOKES_EXCL_SELF_POINT) && !t->same)
+        return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: self exclusion needs targets = sources");
+    if (!src_force || !u_out) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: null pointer");
+    if ((src_fiber == nullptr) != (fiber_len == nullptr))
+        return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: src_fiber and fiber_len go together");
+    if (!(mu > 0.0)) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: mu must be > 0");
+    if (!(eps > 0.0 && eps < 0.5)) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: eps must be in (0, 0.5)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool mixed = flags & STOKES_PREC_MIXED;
+    const double pref = 1.0 / (8.0 * 3.14159265358979323846 * mu);
+    hipLaunchKernelGGL(k_tr_src, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, t->sperm,
+                       src_force, src_weight, src_fiber, fiber_len, pref, eps, near_r,
+                       (flags & STOKES_NO_DOUBLET) ? 0 : 1, t->ss, t->sc, t->st);
+    if (t->n_px > 0)
+        hipLaunchKernelGGL(k_tr_charges, dim3(t->n_px), dim3(TB), 0, st, t->deg, (const DevCl*)t->px_cl,
+                           (const double*)t->sxyz, t->ns, (const double*)t->ss, (const double*)t->sc, t->pF,
+                           t->pD);
+    EvalArgs a{};
+    a.ns = t->ns;
+    a.nt = t->nt;
+    a.sxyz = t->sxyz;
+    a.ss = t->ss;
+    a.sc = t->sc;
+    a.st = t->st;
+    a.txyz = t->txyz;
+    a.tperm = t->tperm;
+    a.tself = (flags & STOKES_EXCL_SELF_POINT) ? t->tself : nullptr;
+    a.bt = t->bt;
+    a.nb = t->nb;
+    a.px_off = t->px_off;
+    a.px_list = t->px_list;
+    a.px_pos = t->px_pos;
+    a.pF = t->pF;
+    a.pD = t->pD;
+    a.P = t->P;
+    a.dr_off = t->dr_off;
+    a.dr_start = t->dr_start;
+    a.dr_count = t->dr_count;
+    a.out = u_out;
+    a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
+    if (mixed)
+        hipLaunchKernelGGL(k_tr_eval<true>, dim3(t->nb), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_tr_eval<false>, dim3(t->nb), dim3(64), 0, st, a);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+extern "C" int stokes_tree_info(const stokes_tree* t, int64_t* proxy_pairs, int64_t* direct_pairs,
+                                int32_t* n_proxy_clusters, int32_t* n_batches) {
+    if (!t) return fail(STOKES_E_INVAL, "stokes_tree_info: null tree");
+    if (proxy_pairs) *proxy_pairs = t->pairs_px;
+    if (direct_pairs) *direct_pairs = t->pairs_dir;
+    if (n_proxy_clusters) *n_proxy_clusters = t->n_px;
+    if (n_batches) *n_batches = t->nb;
+    return STOKES_OK;
+}
+
+extern "C" int stokes_tree_destroy(stokes_tree* t) {
+    if (!t) return fail(STOKES_E_INVAL, "stokes_tree_destroy: null tree");
+    delete t;
+    return STOKES_OK;
+}

@@ -76,6 +76,10 @@ def _load():
         "stokes_local_sbt": [I64, P, P, D, D, ctypes.c_int, P, P],
         "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, D, I32, U32, P, P, P, P],
         "stokes_nonlocal_sbt": [I32, I32, P, P, P, P, D, D, P, P],
+        "stokes_tree_create": [I64, P, I64, P, I32, D, I32, P, P],
+        "stokes_tree_sl_eval": [P, P, P, P, P, D, D, D, U32, P, P],
+        "stokes_tree_info": [P, P, P, P, P],
+        "stokes_tree_destroy": [P],
         "stokes_particle_solve": [I64, P, P, P, I32, P, P, P, P, P, P, P, D, D, I32, U32, P, P, P,
                                   P, P, P],
         "stokes_session_create": [P, P],
@@ -319,6 +323,61 @@ def particle_solve(particles, force, torque, periphery=None, mu=1.0, iters=40, m
                                       _ptr(Om), _ptr(q), ctypes.byref(res), ctypes.byref(it),
                                       _stream(stream)))
     return U, Om, q, res.value, it.value
+
+
+class Tree:
+    """Treecode plan for the single-layer sum over fixed source and target positions
+    (device tensors); see stokes_tree_create."""
+
+    def __init__(self, src_xyz, trg_xyz=None, degree=6, theta=0.7, leaf_size=128, stream=None):
+        self._src = _dev(src_xyz, torch.float64, "src_xyz")
+        self.n_src = self._src.shape[1]
+        if trg_xyz is not None:
+            trg_xyz = _dev(trg_xyz, torch.float64, "trg_xyz")
+        self.n_trg = self.n_src if trg_xyz is None else trg_xyz.shape[1]
+        self._h = ctypes.c_void_p()
+        _check(_lib.stokes_tree_create(self.n_src, _ptr(self._src), self.n_trg,
+                                       None if trg_xyz is None else _ptr(trg_xyz), int(degree),
+                                       float(theta), int(leaf_size), _stream(stream),
+                                       ctypes.byref(self._h)))
+
+    def sl_eval(self, force, src_fiber=None, fiber_len=None, src_weight=None, mu=1.0, eps=0.01,
+                near_r=0.0, excl_self=True, mixed=False, doublet=True, out=None, accumulate=False,
+                stream=None):
+        _dev(force, torch.float64, "force", (3, self.n_src))
+        if src_fiber is not None:
+            _dev(src_fiber, torch.int32, "src_fiber", (self.n_src,))
+            _dev(fiber_len, torch.float64, "fiber_len")
+        if src_weight is not None:
+            _dev(src_weight, torch.float64, "src_weight", (self.n_src,))
+        if out is None:
+            out = torch.zeros((3, self.n_trg), dtype=torch.float64, device=force.device)
+        flags = ((PREC_MIXED if mixed else PREC_FP64) | (EXCL_SELF_POINT if excl_self else 0)
+                 | (0 if doublet else NO_DOUBLET) | (ACCUMULATE if accumulate else 0))
+        nz = lambda t: None if t is None else _ptr(t)
+        _check(_lib.stokes_tree_sl_eval(self._h, _ptr(force), nz(src_weight), nz(src_fiber),
+                                        nz(fiber_len), float(mu), float(eps), float(near_r), flags,
+                                        _ptr(out), _stream(stream)))
+        return out
+
+    def info(self):
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        c, d = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.stokes_tree_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                     ctypes.byref(d)))
+        return {"proxy_pairs": a.value, "direct_pairs": b.value, "proxy_clusters": c.value,
+                "batches": d.value}
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, None
+            _check(_lib.stokes_tree_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on=True):

@@ -88,6 +88,17 @@ def test_status_strings_and_validation_without_gpu():
     assert L.stokes_particle_solve(0, None, None, None, 1, offs, None, None, None, None, None, None,
                                    1.0, 0.0, 5, 0, None, None, None, None, None, None) == S.E_INVAL
     assert "null" in S.last_error()
+    # treecode plans: parameters are checked before any device work
+    h = ctypes.c_void_p()
+    assert L.stokes_tree_create(0, None, 0, None, 6, 0.7, 128, None, ctypes.byref(h)) == S.E_INVAL
+    assert L.stokes_tree_create(10, ctypes.c_void_p(8), 0, None, 11, 0.7, 128, None,
+                                ctypes.byref(h)) == S.E_INVAL
+    assert L.stokes_tree_create(10, ctypes.c_void_p(8), 0, None, 6, 1.5, 128, None,
+                                ctypes.byref(h)) == S.E_INVAL
+    assert "theta" in S.last_error()
+    assert L.stokes_tree_sl_eval(None, None, None, None, None, 1.0, 0.01, 0.0, 0, None,
+                                 None) == S.E_INVAL
+    assert L.stokes_tree_destroy(None) == S.E_INVAL
     assert L.stokes_session_create(None, None) == S.E_INVAL
     assert L.stokes_session_destroy(None) == S.E_INVAL
 

@@ -1,0 +1,118 @@
+"""GPU treecode (barycentric Lagrange interpolation of the far field) against the
+oracle's exact single-layer sum: the approximation error must stay within the bound
+its parameters give and shrink with the interpolation degree; when every interaction
+is direct the result is the exact sum to rounding."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1602_05650_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05650_amd import stokes
+    return stokes
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.fixture(scope="module")
+def cloud():
+    c = W.config1()
+    fs = c["fibers"]
+    idx = W.subsample(7, fs.n, 1500)
+    return c, fs, idx
+
+
+@pytest.fixture(scope="module")
+def cloud_ref(cloud, oracle_mod):
+    c, fs, idx = cloud
+    return oracle_mod.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx], trg_self=idx, src_fiber=fs.fiber,
+                         fiber_len=fs.length, eps=fs.eps, excl=1, nthreads=16)
+
+
+@pytest.mark.parametrize("degree,theta,mixed,tol", [(6, 0.7, True, 2e-6), (6, 0.7, False, 2e-6),
+                                                    (8, 0.5, False, 2e-8), (4, 0.5, True, 2e-6)])
+def test_tree_accuracy_vs_oracle(S, cloud, cloud_ref, degree, theta, mixed, tol):
+    c, fs, idx = cloud
+    T = S.Tree(dev(fs.xyz), degree=degree, theta=theta, leaf_size=128)
+    u = T.sl_eval(dev(c["force"]), src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length),
+                  eps=fs.eps, mixed=mixed).cpu().numpy()
+    err = relmax(u[:, idx], cloud_ref)
+    info = T.info()
+    print(f"degree {degree} theta {theta} mixed {mixed}: err {err:.2e}, {info}")
+    assert err <= tol
+    assert info["proxy_pairs"] > 0           # the far field is really approximated
+
+
+def test_tree_error_shrinks_with_degree(S, cloud, cloud_ref):
+    c, fs, idx = cloud
+    errs = []
+    for degree in (3, 5, 7):
+        T = S.Tree(dev(fs.xyz), degree=degree, theta=0.6, leaf_size=128)
+        u = T.sl_eval(dev(c["force"]), src_fiber=dev(fs.fiber, torch.int32),
+                      fiber_len=dev(fs.length), eps=fs.eps).cpu().numpy()
+        errs.append(relmax(u[:, idx], cloud_ref))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] < 1e-7
+
+
+def test_tree_all_direct_is_exact(S, oracle_mod):
+    # fewer sources than one leaf: every interaction is direct
+    c = W.config0()
+    fs = c["fibers"]
+    ref = oracle_mod.sl(fs.xyz, c["force"], src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps, excl=1)
+    T = S.Tree(dev(fs.xyz), degree=4, theta=0.5, leaf_size=1024)
+    u = T.sl_eval(dev(c["force"]), src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length),
+                  eps=fs.eps).cpu().numpy()
+    assert T.info()["proxy_pairs"] == 0
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) <= 1e-13
+    um = T.sl_eval(dev(c["force"]), src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length),
+                   eps=fs.eps, mixed=True).cpu().numpy()
+    assert relmax(um, ref) <= 2e-6
+    # a single source and target
+    T1 = S.Tree(dev(fs.xyz[:, :1]), degree=3, theta=0.5, leaf_size=8)
+    assert np.all(T1.sl_eval(dev(c["force"][:, :1])).cpu().numpy() == 0.0)
+
+
+def test_tree_separate_targets_and_accumulate(S, oracle_mod):
+    rng = np.random.default_rng(3)
+    src = rng.uniform(-2, 2, (3, 20000))
+    f = rng.standard_normal((3, 20000))
+    trg = rng.uniform(-3, 3, (3, 3000))
+    ref = oracle_mod.sl(src, f, trg_xyz=trg, eps=0.01, excl=0, nthreads=16)
+    T = S.Tree(dev(src), dev(trg), degree=7, theta=0.6, leaf_size=128)
+    base = dev(np.ones((3, 3000)))
+    u = T.sl_eval(dev(f), eps=0.01, excl_self=False, out=base, accumulate=True).cpu().numpy()
+    assert relmax(u - 1.0, ref) <= 1e-6
+    with pytest.raises(S.StokesError):
+        T.sl_eval(dev(f), eps=0.01, excl_self=True)        # self exclusion needs targets = sources
+
+
+def test_tree_spindle_sampled(S, oracle_mod):
+    c = W.config2()
+    fs = c["fibers"]
+    idx = W.subsample(2, fs.n, 2048)
+    ref = oracle_mod.sl(fs.xyz, c["force"], trg_xyz=fs.xyz[:, idx], trg_self=idx, src_fiber=fs.fiber,
+                        fiber_len=fs.length, eps=fs.eps, excl=1, nthreads=16)
+    T = S.Tree(dev(fs.xyz), degree=6, theta=0.7, leaf_size=128)
+    u = T.sl_eval(dev(c["force"]), src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length),
+                  eps=fs.eps, mixed=True).cpu().numpy()
+    err = relmax(u[:, idx], ref)
+    info = T.info()
+    n = fs.n
+    print(f"spindle: err {err:.2e}, pair work {(info['proxy_pairs'] + info['direct_pairs']) / (n * n):.3f} "
+          f"of direct, {info}")
+    assert err <= 2e-6
