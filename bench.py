@@ -78,9 +78,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-other", action="store_true",
                     help="time the oracle on the headline workload only")
-    ap.add_argument("--only", choices=["mixed", "fp64", "both", "none", "nonlocal", "particles"],
+    ap.add_argument("--only", choices=["mixed", "fp64", "both", "none", "nonlocal", "particles",
+                                       "treecode"],
                     default="both",
-                    help="none: serving run alone; nonlocal / particles: that section alone")
+                    help="none: serving run alone; nonlocal / particles / treecode: that section alone")
     ap.add_argument("--extra", default="c0,c1,c4",
                     help="other workloads timed after the headline (c0,c1,c4 or none)")
     ap.add_argument("--step-pairs", type=float, default=0,
@@ -361,6 +362,46 @@ def particles_run(S, torch, log_fn, iters=30):
     return res
 
 
+def tree_run(S, torch, log_fn, degree=6, theta=0.7, leaf=128, reps=10):
+    """Treecode single-layer sum on the spindle and the large confined fiber set: plan
+    build time, evaluation time (mixed and FP64), interactions per second, and the
+    error against the direct GPU sum on all targets."""
+    from paper_1602_05650_amd import workloads as W
+    res = {"degree": degree, "theta": theta, "leaf_size": leaf}
+    for name, gen in (("spindle_262k", W.config2), ("confined_524k_fibers", W.config4)):
+        c = gen()
+        fs = c["fibers"]
+        d = lambda a, t=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", t)
+        X, F, FB, FL = d(fs.xyz), d(c["force"]), d(fs.fiber, torch.int32), d(fs.length)
+        n = fs.n
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = S.Tree(X, degree=degree, theta=theta, leaf_size=leaf)
+        t_plan = time.perf_counter() - t0
+        info = T.info()
+        out = torch.empty((3, n), dtype=torch.float64, device="cuda")
+        ref = S.sl_eval(X, F, src_fiber=FB, fiber_len=FL, eps=fs.eps)       # direct FP64
+        entry = {"points": n, "plan_s": round(t_plan, 3),
+                 "pair_work_vs_direct": round((info["proxy_pairs"] + info["direct_pairs"]) / (n * (n - 1)), 4),
+                 **info}
+        for mixed in (True, False):
+            T.sl_eval(F, src_fiber=FB, fiber_len=FL, eps=fs.eps, mixed=mixed, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                T.sl_eval(F, src_fiber=FB, fiber_len=FL, eps=fs.eps, mixed=mixed, out=out)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            err = float((out - ref).abs().max() / ref.abs().max())
+            entry["mixed" if mixed else "fp64"] = {
+                "ms": round(dt * 1e3, 3), "interactions_per_s_g": round(n * (n - 1) / dt / 1e9, 1),
+                "err_vs_direct_relmax": float(f"{err:.3e}")}
+            log_fn(f"tree {name} {'mixed' if mixed else 'fp64'}: {dt * 1e3:.2f} ms, err {err:.2e}")
+        T.close()
+        res[name] = entry
+    return res
+
+
 def cpu_baseline(c, seconds, log_fn, other=True):
     """The oracle (plain FP64 double loop, OpenMP over targets) on seeded samples of the
     headline workload: about 60% of `seconds` on all host threads, 25% on one thread;
@@ -458,6 +499,9 @@ def main():
 
     if args.only == "nonlocal":      # nonlocal-term section alone (for profiling it)
         print(json.dumps({"nonlocal": nonlocal_run(S, torch, log)}), flush=True)
+        return
+    if args.only == "treecode":      # treecode section alone (for profiling it)
+        print(json.dumps({"treecode": tree_run(S, torch, log)}), flush=True)
         return
     if args.only == "particles":     # rigid-particle section alone (for profiling it)
         print(json.dumps({"particles": particles_run(S, torch, log)}), flush=True)
@@ -570,6 +614,7 @@ def main():
     if extra and args.only == "both":
         out["nonlocal"] = nonlocal_run(S, torch, log)
         out["particles"] = particles_run(S, torch, log)
+        out["treecode"] = tree_run(S, torch, log)
     if not args.no_serving:
         try:
             out["serving"] = serving_run(S, args.serving_requests, log, args.step_pairs,

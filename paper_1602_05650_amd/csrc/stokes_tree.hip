@@ -186,30 +186,42 @@ __device__ __forceinline__ double cheb_bw(int i, int n) {
     return (i == 0 || i == n) ? 0.5 * s : s;
 }
 
-// Proxy charges of one cluster per workgroup: F_k = sum_j L_k(y_j) s_j and
-// D_k = sum_j L_k(y_j) c_j s_j.  Proxies are taken TB at a time (one per thread);
-// for each pass the 1-D barycentric basis values of 64 sources at a time are
-// staged in LDS.
-__global__ __launch_bounds__(TB) void k_tr_charges(int deg, const DevCl* cls, const double* sxyz,
-                                                   int64_t ns, const double* ss, const double* sc,
-                                                   double* pF, double* pD) {
-    __shared__ double lb[3][64][MAX_DEG + 1];
-    __shared__ double sv[6][64];
-    const int q = blockIdx.x, t = threadIdx.x;
-    const DevCl* Cp = cls + q;            // (the box is indexed per thread: no private copy)
-    const int64_t c_start = Cp->start, c_count = Cp->count;
+// Proxy charges, in two steps.  Each work item is a piece of at most CH_SRC
+// sources of one proxy cluster: it forms the partial charges of that piece for
+// every proxy (one proxy per thread, CB at a time), with the 1-D barycentric basis
+// values of SRC_TILE sources at a time staged in LDS.  Then k_tr_charges_sum adds
+// each cluster's pieces in a fixed order: F_k = sum_j L_k(y_j) s_j,
+// D_k = sum_j L_k(y_j) c_j s_j.
+constexpr int CB = 512;
+constexpr int SRC_TILE = 160;      // 3 * SRC_TILE <= CB threads compute basis values
+constexpr int64_t CH_SRC = 4096;
+struct ChargeItem {
+    int32_t q;                     // proxy slot
+    int32_t count;
+    int64_t start;
+};
+
+__global__ __launch_bounds__(CB) void k_tr_charges(int deg, const DevCl* cls, const ChargeItem* items,
+                                                   const double* sxyz, int64_t ns, const double* ss,
+                                                   const double* sc, double* part) {
+    __shared__ double lb[3][SRC_TILE][MAX_DEG + 1];
+    __shared__ double sv[6][SRC_TILE];
+    const int t = threadIdx.x;
+    const ChargeItem it = items[blockIdx.x];
+    const DevCl* Cp = cls + it.q;            // (the box is indexed per thread: no private copy)
     const int n1 = deg + 1, P = n1 * n1 * n1;
-    for (int k0 = 0; k0 < P; k0 += TB) {
+    double* out = part + (int64_t)blockIdx.x * 6 * P;
+    for (int k0 = 0; k0 < P; k0 += CB) {
         const int k = k0 + t;
         const int kx = k / (n1 * n1), ky = (k / n1) % n1, kz = k % n1;
         double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int64_t j0 = 0; j0 < c_count; j0 += 64) {
-            const int m = (int)min<int64_t>(64, c_count - j0);
+        for (int j0 = 0; j0 < it.count; j0 += SRC_TILE) {
+            const int m = min(SRC_TILE, it.count - j0);
             __syncthreads();
-            if (t < 3 * 64) {
+            if (t < 3 * SRC_TILE) {
                 const int jj = t / 3, d = t - 3 * jj;
                 if (jj < m) {
-                    const int64_t j = c_start + j0 + jj;
+                    const int64_t j = it.start + j0 + jj;
                     const double lo = Cp->lo[d], ext = Cp->hi[d] - lo;
                     const double x = 2.0 * (sxyz[d * ns + j] - lo) / ext - 1.0;
                     int hit = -1;
@@ -241,10 +253,33 @@ __global__ __launch_bounds__(TB) void k_tr_charges(int deg, const DevCl* cls, co
                 }
         }
         if (k < P)
-            for (int c = 0; c < 3; ++c) {
-                pF[((int64_t)q * 3 + c) * P + k] = acc[c];
-                pD[((int64_t)q * 3 + c) * P + k] = acc[3 + c];
-            }
+            for (int b = 0; b < 6; ++b) out[b * P + k] = acc[b];
+    }
+}
+
+// F and D of every proxy cluster: its pieces summed in item order.
+__global__ __launch_bounds__(TB) void k_tr_charges_sum(int P, const int32_t* item_off, const double* part,
+                                                       double* pF, double* pD) {
+    const int q = blockIdx.x;
+    for (int e = threadIdx.x; e < 6 * P; e += TB) {
+        double s = 0.0;
+        for (int i = item_off[q]; i < item_off[q + 1]; ++i) s += part[(int64_t)i * 6 * P + e];
+        const int b = e / P, k = e - b * P;
+        if (b < 3)
+            pF[((int64_t)q * 3 + b) * P + k] = s;
+        else
+            pD[((int64_t)q * 3 + b - 3) * P + k] = s;
+    }
+}
+
+// FP32 charge records for the mixed evaluation, 8 floats per proxy.
+__global__ __launch_bounds__(TB) void k_tr_pack(int P, const double* pF, const double* pD, float4* pk) {
+    const int q = blockIdx.x;
+    for (int k = threadIdx.x; k < P; k += TB) {
+        const double* F = pF + (int64_t)q * 3 * P;
+        const double* D = pD + (int64_t)q * 3 * P;
+        pk[((int64_t)q * P + k) * 2] = make_float4((float)F[k], (float)F[P + k], (float)F[2 * P + k], (float)D[k]);
+        pk[((int64_t)q * P + k) * 2 + 1] = make_float4((float)D[P + k], (float)D[2 * P + k], 0.f, 0.f);
     }
 }
 
@@ -266,6 +301,8 @@ struct EvalArgs {
     const double* px_pos;    // [n_px][3][P]
     const double* pF;
     const double* pD;
+    const float4* pk;        // [n_px][P][2] packed FP32 charges: F0 F1 F2 D0 | D1 D2 0 0
+    const double* p1d;       // [n_px][3][deg+1] 1-D proxy coordinates of each box
     int32_t P;
     const int32_t* dr_off;
     const int64_t* dr_start;
@@ -295,12 +332,69 @@ __device__ __forceinline__ void pair64(double dx, double dy, double dz, double s
     uz = fma(A, sz, fma(B, dz, uz));
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(64) void k_tr_eval(EvalArgs a) {
-    __shared__ float lf[64][12];
-    __shared__ double ld[64][10];
-    const int b = blockIdx.x, l = threadIdx.x;
+// Make the wave's LDS writes visible to all of its lanes (each wave of a workgroup
+// works on its own batch and LDS region, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int EW = 4;   // waves (batches) per workgroup
+// Mixed far field of one proxy cluster for a compile-time degree: the proxies form
+// the tensor grid (X[kx], Y[ky], Z[kz]), so each lane keeps its z offsets and their
+// squares in registers and only the six charges of a proxy come from LDS; the
+// charges are staged one kx slab ((DEG+1)^2 proxies) at a time.
+template <int DEG>
+__device__ __forceinline__ void far_tensor(const EvalArgs& a, int q, int l, float4* slab, double cx, double cy,
+                                           double cz, float xl, float yl, float zl, float& p0, float& p1,
+                                           float& p2) {
+    constexpr int N1 = DEG + 1, PP = N1 * N1 * N1;
+    const double* X1 = a.p1d + (int64_t)q * 3 * N1;
+    float DZ[N1], DZ2[N1];
+#pragma unroll
+    for (int kz = 0; kz < N1; ++kz) {
+        DZ[kz] = zl - (float)(X1[2 * N1 + kz] - cz);
+        DZ2[kz] = DZ[kz] * DZ[kz];
+    }
+    const float4* src = a.pk + (int64_t)q * PP * 2;
+    for (int kx = 0; kx < N1; ++kx) {
+        wave_sync();
+        for (int e = l; e < 2 * N1 * N1; e += 64) slab[e] = src[2 * N1 * N1 * kx + e];
+        wave_sync();
+        const float dx = xl - (float)(X1[kx] - cx);
+        const float dx2 = dx * dx;
+        for (int ky = 0; ky < N1; ++ky) {
+            const float dy = yl - (float)(X1[N1 + ky] - cy);
+            const float rxy = fmaf(dy, dy, dx2);
+#pragma unroll
+            for (int kz = 0; kz < N1; ++kz) {
+                const float4 f = slab[2 * (ky * N1 + kz)];
+                const float4 g4 = slab[2 * (ky * N1 + kz) + 1];
+                const float dz = DZ[kz];
+                const float r2 = rxy + DZ2[kz];
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float ri2 = ri * ri, ri3 = ri * ri2, m3ri5 = -3.0f * (ri3 * ri2);
+                const float dF = fmaf(dx, f.x, fmaf(dy, f.y, dz * f.z));
+                const float dD = fmaf(dx, f.w, fmaf(dy, g4.x, dz * g4.y));
+                const float g = fmaf(dD, m3ri5, dF * ri3);
+                p0 = fmaf(f.x, ri, fmaf(f.w, ri3, fmaf(g, dx, p0)));
+                p1 = fmaf(f.y, ri, fmaf(g4.x, ri3, fmaf(g, dy, p1)));
+                p2 = fmaf(f.z, ri, fmaf(g4.y, ri3, fmaf(g, dz, p2)));
+            }
+        }
+    }
+}
+
+template <bool MIXED, int DEG>
+__global__ __launch_bounds__(64 * EW) void k_tr_eval(EvalArgs a) {
+    __shared__ __align__(16) float lfs[EW][64][12];    // (a DEG <= 8 slab: 8 (DEG+1)^2 <= 768 floats)
+    __shared__ double lds_[EW][64][10];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int b = blockIdx.x * EW + w;
     if (b >= a.nb) return;
+    float (*lf)[12] = lfs[w];
+    double (*ld)[10] = lds_[w];
     const Batch B = a.bt[b];
     const bool act = l < B.count;
     const int64_t ti = B.start + (act ? l : 0);
@@ -313,13 +407,21 @@ __global__ __launch_bounds__(64) void k_tr_eval(EvalArgs a) {
     // far field: proxies
     for (int e = a.px_off[b]; e < a.px_off[b + 1]; ++e) {
         const int q = a.px_list[e];
+        if constexpr (MIXED && DEG > 0) {
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+            far_tensor<DEG>(a, q, l, reinterpret_cast<float4*>(&lf[0][0]), cx, cy, cz, xl, yl, zl, p0, p1, p2);
+            kahan(S0, C0, p0);
+            kahan(S1, C1, p1);
+            kahan(S2, C2, p2);
+            continue;
+        }
         const double* pos = a.px_pos + (int64_t)q * 3 * a.P;
         const double* F = a.pF + (int64_t)q * 3 * a.P;
         const double* D = a.pD + (int64_t)q * 3 * a.P;
         float p0 = 0.f, p1 = 0.f, p2 = 0.f;
         for (int k0 = 0; k0 < a.P; k0 += 64) {
             const int m = min(64, a.P - k0);
-            __syncthreads();
+            wave_sync();
             if (l < m) {
                 const int k = k0 + l;
                 if (MIXED) {
@@ -341,8 +443,9 @@ __global__ __launch_bounds__(64) void k_tr_eval(EvalArgs a) {
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
             if (MIXED) {
+#pragma unroll 8
                 for (int k = 0; k < m; ++k) {
                     const float dx = xl - lf[k][0], dy = yl - lf[k][1], dz = zl - lf[k][2];
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -382,19 +485,15 @@ __global__ __launch_bounds__(64) void k_tr_eval(EvalArgs a) {
         const int32_t cnt = a.dr_count[e];
         for (int32_t k0 = 0; k0 < cnt; k0 += 64) {
             const int m = min(64, cnt - k0);
-            __syncthreads();
+            wave_sync();
             if (l < m) {
                 const int64_t j = j0s + k0 + l;
                 if (MIXED) {
-                    lf[l][0] = (float)(a.sxyz[j] - cx);
-                    lf[l][1] = (float)(a.sxyz[a.ns + j] - cy);
-                    lf[l][2] = (float)(a.sxyz[2 * a.ns + j] - cz);
-                    lf[l][3] = (float)a.ss[j];
-                    lf[l][4] = (float)a.ss[a.ns + j];
-                    lf[l][5] = (float)a.ss[2 * a.ns + j];
-                    lf[l][6] = (float)a.sc[j];
-                    lf[l][7] = (float)(-3.0 * a.sc[j]);
-                    lf[l][8] = a.st[j];
+                    float4* r = reinterpret_cast<float4*>(&lf[0][0]) + 2 * l;
+                    r[0] = make_float4((float)(a.sxyz[j] - cx), (float)(a.sxyz[a.ns + j] - cy),
+                                       (float)(a.sxyz[2 * a.ns + j] - cz), (float)a.sc[j]);
+                    r[1] = make_float4((float)a.ss[j], (float)a.ss[a.ns + j], (float)a.ss[2 * a.ns + j],
+                                       a.st[j]);
                 } else {
                     ld[l][0] = a.sxyz[j];
                     ld[l][1] = a.sxyz[a.ns + j];
@@ -405,25 +504,63 @@ __global__ __launch_bounds__(64) void k_tr_eval(EvalArgs a) {
                     ld[l][6] = a.sc[j];
                 }
             }
-            __syncthreads();
+            wave_sync();
             if (MIXED) {
                 float p0 = 0.f, p1 = 0.f, p2 = 0.f;
                 uint64_t near = 0;
-                for (int k = 0; k < m; ++k) {
-                    const float dx = xl - lf[k][0], dy = yl - lf[k][1], dz = zl - lf[k][2];
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    if (r2 < lf[k][8]) {
-                        near |= 1ull << k;
-                        continue;
+                // can any pair of this chunk be near?  Box of the staged sources (wave
+                // reduction) against the batch's sphere, with the largest threshold.
+                const float4* rec = reinterpret_cast<const float4*>(&lf[0][0]);
+                const float4 own = rec[2 * l], own1 = rec[2 * l + 1];
+                float b0 = l < m ? own.x : INFINITY, b1 = l < m ? own.y : INFINITY,
+                      b2 = l < m ? own.z : INFINITY;
+                float e0 = l < m ? own.x : -INFINITY, e1 = l < m ? own.y : -INFINITY,
+                      e2 = l < m ? own.z : -INFINITY, tm = l < m ? own1.w : 0.f;
+                for (int o = 32; o > 0; o >>= 1) {
+                    b0 = fminf(b0, __shfl_xor(b0, o));
+                    b1 = fminf(b1, __shfl_xor(b1, o));
+                    b2 = fminf(b2, __shfl_xor(b2, o));
+                    e0 = fmaxf(e0, __shfl_xor(e0, o));
+                    e1 = fmaxf(e1, __shfl_xor(e1, o));
+                    e2 = fmaxf(e2, __shfl_xor(e2, o));
+                    tm = fmaxf(tm, __shfl_xor(tm, o));
+                }
+                const float gx = fmaxf(0.f, fmaxf(b0, -e0)), gy = fmaxf(0.f, fmaxf(b1, -e1)),
+                            gz = fmaxf(0.f, fmaxf(b2, -e2));
+                const float gap = sqrtf(gx * gx + gy * gy + gz * gz) - (float)B.r;
+                if (gap > 0.f && gap * gap > 1.01f * tm) {
+#pragma unroll 8
+                    for (int k = 0; k < m; ++k) {
+                        const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
+                        const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float ri = __builtin_amdgcn_rsqf(r2);
+                        const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                        const float ds = fmaf(dx, a1.x, fmaf(dy, a1.y, dz * a1.z));
+                        const float A = fmaf(a0.w, ri3, ri);
+                        const float Bc = ds * fmaf(-3.0f * a0.w, ri5, ri3);
+                        p0 = fmaf(A, a1.x, fmaf(Bc, dx, p0));
+                        p1 = fmaf(A, a1.y, fmaf(Bc, dy, p1));
+                        p2 = fmaf(A, a1.z, fmaf(Bc, dz, p2));
                     }
-                    const float ri = __builtin_amdgcn_rsqf(r2);
-                    const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
-                    const float ds = fmaf(dx, lf[k][3], fmaf(dy, lf[k][4], dz * lf[k][5]));
-                    const float A = fmaf(lf[k][6], ri3, ri);
-                    const float Bc = ds * fmaf(lf[k][7], ri5, ri3);
-                    p0 = fmaf(A, lf[k][3], fmaf(Bc, dx, p0));
-                    p1 = fmaf(A, lf[k][4], fmaf(Bc, dy, p1));
-                    p2 = fmaf(A, lf[k][5], fmaf(Bc, dz, p2));
+                } else {
+                    for (int k = 0; k < m; ++k) {
+                        const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
+                        const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        if (r2 < a1.w) {
+                            near |= 1ull << k;
+                            continue;
+                        }
+                        const float ri = __builtin_amdgcn_rsqf(r2);
+                        const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                        const float ds = fmaf(dx, a1.x, fmaf(dy, a1.y, dz * a1.z));
+                        const float A = fmaf(a0.w, ri3, ri);
+                        const float Bc = ds * fmaf(-3.0f * a0.w, ri5, ri3);
+                        p0 = fmaf(A, a1.x, fmaf(Bc, dx, p0));
+                        p1 = fmaf(A, a1.y, fmaf(Bc, dy, p1));
+                        p2 = fmaf(A, a1.z, fmaf(Bc, dz, p2));
+                    }
                 }
                 kahan(S0, C0, p0);
                 kahan(S1, C1, p1);
@@ -499,6 +636,12 @@ struct stokes_tree {
     double* ss = nullptr;
     double* sc = nullptr;
     float* st = nullptr;
+    float4* pk = nullptr;
+    double* p1d = nullptr;
+    int32_t n_items = 0;
+    ChargeItem* items = nullptr;
+    int32_t* item_off = nullptr;
+    double* part = nullptr;
     ~stokes_tree() {
         if (mem) (void)hipFree(mem);
     }
@@ -606,6 +749,22 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
             }
         }
     }
+    // 1-D proxy coordinates of each box: [q][dim][i] = lo + (1 + cos(i pi / n)) (hi - lo) / 2
+    std::vector<double> p1d((size_t)n_px * 3 * n1);
+    for (int32_t q = 0; q < n_px; ++q)
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i < n1; ++i)
+                p1d[((size_t)q * 3 + d) * n1 + i] =
+                    pcl[q].lo[d] + 0.5 * (std::cos(i * 3.14159265358979323846 / degree) + 1.0) *
+                                       (pcl[q].hi[d] - pcl[q].lo[d]);
+    // charge work items: pieces of at most CH_SRC sources of each proxy cluster
+    std::vector<ChargeItem> items;
+    std::vector<int32_t> item_off{0};
+    for (int32_t q = 0; q < n_px; ++q) {
+        for (int64_t o = 0; o < pcl[q].count; o += CH_SRC)
+            items.push_back(ChargeItem{q, (int32_t)std::min<int64_t>(CH_SRC, pcl[q].count - o), pcl[q].start + o});
+        item_off.push_back((int32_t)items.size());
+    }
     // sorted coordinates, self indices
     std::vector<double> sx(3 * n_src), txs(3 * n_trg);
     for (int64_t j = 0; j < n_src; ++j)
@@ -644,7 +803,9 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
                  o_pc = take((size_t)n_px * sizeof(DevCl)), o_pp = take(ppos.size() * 8),
                  o_pF = take(ppos.size() * 8), o_pD = take(ppos.size() * 8), o_do = take(dr_off.size() * 4),
                  o_ds = take(dr_start.size() * 8), o_dc = take(dr_count.size() * 4), o_ss = take(3 * n_src * 8),
-                 o_sc = take(n_src * 8), o_st = take(n_src * 4);
+                 o_sc = take(n_src * 8), o_st = take(n_src * 4), o_it = take(items.size() * sizeof(ChargeItem)),
+                 o_io = take(item_off.size() * 4), o_pa = take(items.size() * 6 * P * 8),
+                 o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8);
     hipError_t e = hipMalloc(&t->mem, off);
     if (e != hipSuccess) {
         delete t;
@@ -669,6 +830,12 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     t->ss = reinterpret_cast<double*>(base + o_ss);
     t->sc = reinterpret_cast<double*>(base + o_sc);
     t->st = reinterpret_cast<float*>(base + o_st);
+    t->n_items = (int32_t)items.size();
+    t->items = reinterpret_cast<ChargeItem*>(base + o_it);
+    t->item_off = reinterpret_cast<int32_t*>(base + o_io);
+    t->part = reinterpret_cast<double*>(base + o_pa);
+    t->pk = reinterpret_cast<float4*>(base + o_pk);
+    t->p1d = reinterpret_cast<double*>(base + o_p1);
     auto up = [&](void* dst, const void* src, size_t bytes) -> int {
         if (!bytes) return STOKES_OK;
         hipError_t r = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
@@ -688,6 +855,9 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     if (!rc) rc = up(t->dr_off, dr_off.data(), dr_off.size() * 4);
     if (!rc) rc = up(t->dr_start, dr_start.data(), dr_start.size() * 8);
     if (!rc) rc = up(t->dr_count, dr_count.data(), dr_count.size() * 4);
+    if (!rc) rc = up(t->items, items.data(), items.size() * sizeof(ChargeItem));
+    if (!rc) rc = up(t->item_off, item_off.data(), item_off.size() * 4);
+    if (!rc) rc = up(t->p1d, p1d.data(), p1d.size() * 8);
     if (!rc) {
         hipError_t r = hipStreamSynchronize(st);
         if (r != hipSuccess) rc = hip_fail(r, "hipStreamSynchronize(tree)");
@@ -720,10 +890,16 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
     hipLaunchKernelGGL(k_tr_src, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, t->sperm,
                        src_force, src_weight, src_fiber, fiber_len, pref, eps, near_r,
                        (flags & STOKES_NO_DOUBLET) ? 0 : 1, t->ss, t->sc, t->st);
-    if (t->n_px > 0)
-        hipLaunchKernelGGL(k_tr_charges, dim3(t->n_px), dim3(TB), 0, st, t->deg, (const DevCl*)t->px_cl,
-                           (const double*)t->sxyz, t->ns, (const double*)t->ss, (const double*)t->sc, t->pF,
-                           t->pD);
+    if (t->n_px > 0) {
+        hipLaunchKernelGGL(k_tr_charges, dim3(t->n_items), dim3(CB), 0, st, t->deg, (const DevCl*)t->px_cl,
+                           (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns, (const double*)t->ss,
+                           (const double*)t->sc, t->part);
+        hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px), dim3(TB), 0, st, t->P, (const int32_t*)t->item_off,
+                           (const double*)t->part, t->pF, t->pD);
+        if (mixed)
+            hipLaunchKernelGGL(k_tr_pack, dim3(t->n_px), dim3(TB), 0, st, t->P, (const double*)t->pF,
+                               (const double*)t->pD, t->pk);
+    }
     EvalArgs a{};
     a.ns = t->ns;
     a.nt = t->nt;
@@ -741,16 +917,28 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
     a.px_pos = t->px_pos;
     a.pF = t->pF;
     a.pD = t->pD;
+    a.pk = t->pk;
+    a.p1d = t->p1d;
     a.P = t->P;
     a.dr_off = t->dr_off;
     a.dr_start = t->dr_start;
     a.dr_count = t->dr_count;
     a.out = u_out;
     a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
-    if (mixed)
-        hipLaunchKernelGGL(k_tr_eval<true>, dim3(t->nb), dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_tr_eval<false>, dim3(t->nb), dim3(64), 0, st, a);
+    const unsigned grid = (unsigned)((t->nb + EW - 1) / EW);
+    const dim3 blk(64 * EW);
+    if (!mixed) {
+        hipLaunchKernelGGL((k_tr_eval<false, 0>), dim3(grid), blk, 0, st, a);
+    } else {
+        switch (t->deg) {   // the tensor-grid far field for the common degrees
+            case 4: hipLaunchKernelGGL((k_tr_eval<true, 4>), dim3(grid), blk, 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_tr_eval<true, 5>), dim3(grid), blk, 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_tr_eval<true, 6>), dim3(grid), blk, 0, st, a); break;
+            case 7: hipLaunchKernelGGL((k_tr_eval<true, 7>), dim3(grid), blk, 0, st, a); break;
+            case 8: hipLaunchKernelGGL((k_tr_eval<true, 8>), dim3(grid), blk, 0, st, a); break;
+            default: hipLaunchKernelGGL((k_tr_eval<true, 0>), dim3(grid), blk, 0, st, a); break;
+        }
+    }
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }

@@ -44,7 +44,8 @@ def cloud_ref(cloud, oracle_mod):
 
 
 @pytest.mark.parametrize("degree,theta,mixed,tol", [(6, 0.7, True, 2e-6), (6, 0.7, False, 2e-6),
-                                                    (8, 0.5, False, 2e-8), (4, 0.5, True, 2e-6)])
+                                                    (8, 0.5, False, 2e-8), (4, 0.5, True, 2e-6),
+                                                    (7, 0.7, True, 2e-6), (9, 0.6, True, 2e-6)])
 def test_tree_accuracy_vs_oracle(S, cloud, cloud_ref, degree, theta, mixed, tol):
     c, fs, idx = cloud
     T = S.Tree(dev(fs.xyz), degree=degree, theta=theta, leaf_size=128)
