@@ -394,3 +394,6 @@ def local_sbt_inv_closed(v, tangent, eps, mu=1.0):
 
 # Confined rigid particles (second-kind boundary integral mobility problem).
 from .particles import ParticleSystem, particle_solve, stokeslet, rotlet, dl_diagonal  # noqa: E402,F401
+
+# One implicit time step of free elastic fibers.
+from .timestep import FiberStep, cheb_diff, fiber_step  # noqa: E402,F401
