@@ -13,28 +13,42 @@ Unknowns per fiber with n = p + 1 CGL nodes alpha_k = cos(k pi / p) (node 0 is t
 end s = L, alpha = 1): X+ (3 n) and T+ (n).  With
   V[f] = M f (+ K_delta f) + u_bar[f]   (u_bar: the other fibers' Stokeslet + doublet sum
                                           with Clenshaw-Curtis weights x L/2)
-the equations are
+the position equations are those of eq. discrete-update,
 
-  position   X+ / dt - V[f+] = X / dt + V[f_ext]                        (eq. discrete-update)
-  tension    -(D_a V[f+]) . X_a = (D_a V[f_ext]) . X_a                   (eq. main-inextensibility)
+  X+ / dt - V[f+] = X / dt + V[f_ext],   f+ = -E X+_ssss + (T+ X_s)_s,
 
-The tension equation is the inextensibility constraint in the velocity form the paper
-states it in, (V_s . X_s) = 0 with V = (X+ - X) / dt = V[f+ + f_ext]: second order in T,
-which is the order the paper assigns it when it counts boundary conditions.  (Its
-position form (D_a X+) . X_a = X_a . X_a has no T in it, and with the boundary rows
-below that square system is singular: for a straight fiber the tension keeps a
-three-dimensional null space.)  The paper leaves open how the boundary conditions
-enter the collocation system; here by rectangular collocation (Driscoll and Hale, IMA
-J. Numer. Anal. 2016): each position component is collocated at the n - 4 first-kind
-Chebyshev points (the node values interpolated there) and completed by X_ss = 0 and
-X_sss = 0 at both ends; the tension equation is collocated at the n - 2 first-kind
-points and completed by T = 0 at both ends (eq. bc-free).
+and the tension equation is the inextensibility constraint in the velocity form the
+paper states it in (eq. main-inextensibility), t . (V[f+ + f_ext])_s = 0, written as the
+second-order equation for T that the paper takes from Tornberg and Shelley (2004).
+Split V = A f + R[f] into the part that acts node by node, A = alpha I + beta t t (M, and
+with the nonlocal term its subtracted local part -(8 pi mu)^-1 sum_k w_k psi_ik (I + t t)),
+and R (the other fibers' flow and the rest of K_delta, smooth along the fiber).  For
+a curve parametrised by arclength (t . X_ss = 0, t . X_sss = -|X_ss|^2,
+t . X_ssss = -3 X_ss . X_sss), with c = alpha + beta,
+
+  t . (A f)_s = c_s (t . f) + c (t . f)_s - alpha X_ss . f,
+  t . f+      = 3 E X_ss . X+_sss + T_s,
+  (t . f+)_s  = 3 E (X_sss . X+_sss + X_ss . X+_ssss) + T_ss,
+  X_ss . f+   = -E X_ss . X+_ssss + |X_ss|^2 T,
+
+geometry (t, X_ss, X_sss) explicit and X+, T implicit (section "Time discretization").
+The tension equation is then h(X+, T) + t . (R[f+])_s = -t . (V[f_ext])_s with h the
+three terms above: fourth order in X and second in T, as the paper counts them.  (The
+velocity form differentiated as it stands puts D^5 on X+: such a system has
+node-to-node oscillating tension modes.)  The paper leaves open how the boundary
+conditions enter the collocation system; here by rectangular collocation (Driscoll and
+Hale, IMA J. Numer. Anal. 2016): each position component is collocated at the n - 4
+first-kind Chebyshev points (the node values interpolated there) and completed by
+X_ss = 0 and X_sss = 0 at both ends; the tension equation is collocated at the n - 2
+first-kind points and completed by T = 0 at both ends (eq. bc-free).
 
 Row layout of the operator (3 N position rows, then N tension rows, fiber by fiber):
 position rows of a fiber = its n - 4 collocated rows, then X_ss(s=L), X_sss(s=L),
 X_ss(s=0), X_sss(s=0); tension rows = its n - 2 collocated rows, then T(s=L), T(s=0).
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -89,11 +103,11 @@ class FiberStep:
     eps, bending modulus E, step dt, viscosity mu, optional nonlocal term (delta), and
     the source doublet in the other fibers' flow (doublet)."""
 
-    def __init__(self, X, L, npf, eps, E, dt, mu=1.0, delta=None, doublet=True):
+    def __init__(self, X, L, npf, eps, E, dt, mu=1.0, delta=None, doublet=True, nthreads=1):
         self.X = np.asarray(X, dtype=np.float64)
         self.L = np.asarray(L, dtype=np.float64)
         self.npf, self.eps, self.E, self.dt, self.mu = npf, eps, E, dt, mu
-        self.delta, self.doublet = delta, doublet
+        self.delta, self.doublet, self.nthreads = delta, doublet, nthreads
         self.N = self.X.shape[1]
         self.nf = self.N // npf
         assert self.nf * npf == self.N and self.L.size == self.nf and npf >= 6
@@ -102,9 +116,31 @@ class FiberStep:
         self.Da = cheb_diff(p)
         self.P4 = cheb_resample(p, npf - 4)
         self.P2 = cheb_resample(p, npf - 2)
+        self.D2 = self.Da @ self.Da
+        self.D3 = self.D2 @ self.Da
+        self.D4 = self.D3 @ self.Da
         self.Xa = self.per_fiber(self.Da, self.X, 0)
         self.Xs = self.Xa * (2.0 / self.L[self.fib])[None, :]
         self.tangent = self.Xs / np.linalg.norm(self.Xs, axis=0)
+        self.Xss = self.per_fiber(self.D2, self.X, 2)
+        self.Xsss = self.per_fiber(self.D3, self.X, 3)
+        # the node-by-node part A = alpha I + beta t t of V, and c = alpha + beta
+        pref = 1.0 / (8.0 * math.pi * mu)
+        kap = -math.log(eps * eps * math.e)
+        self.alpha = np.full(self.N, pref * (kap + 2.0))
+        self.c = np.full(self.N, pref * 2.0 * kap)
+        if delta is not None:
+            import oracle
+            w = oracle.fiber_quadrature_weights(self.fib, self.L, npf)
+            sa = oracle.fiber_arclength(self.fib, self.L, npf)
+            self.dsum = np.zeros(self.N)
+            for i in range(self.N):
+                ks = np.arange((i // npf) * npf, (i // npf + 1) * npf)
+                ks = ks[ks != i]
+                self.dsum[i] = np.sum(w[ks] / np.sqrt((sa[i] - sa[ks]) ** 2 + delta * delta))
+            self.alpha -= pref * self.dsum
+            self.c -= 2.0 * pref * self.dsum
+        self.c_s = self.per_fiber(self.Da, self.c[None, :], 1)[0]
 
     def per_fiber(self, A, V, scale_pow):
         """Apply the matrix A (rows x n) on each fiber to V (c, N) times (2/L)^scale_pow;
@@ -118,23 +154,59 @@ class FiberStep:
 
     def force(self, Xp, T):
         """f+ = -E D_s^4 X+ + D_s (T+ X_s), with X_s of the current geometry."""
-        D4 = np.linalg.matrix_power(self.Da, 4)
-        return (-self.E * self.per_fiber(D4, Xp, 4)
+        return (-self.E * self.per_fiber(self.D4, Xp, 4)
                 + self.per_fiber(self.Da, T[None, :] * self.Xs, 1))
 
-    def velocity(self, f, others=True):
-        """V[f] = M f (+ K_delta f) (+ the flow of the other fibers at the nodes)."""
+    def smooth_velocity(self, f, others=True):
+        """R[f] = V[f] - A f: the other fibers' flow and K_delta without its subtracted
+        local part."""
         import oracle
-        v = oracle.local_sbt(f, self.tangent, self.eps, self.mu)
+        v = np.zeros_like(f)
         if self.delta is not None:
-            v = v + oracle.nonlocal_sbt(f, self.X, self.tangent, self.fib, self.L, self.npf,
-                                        self.delta, self.mu)
+            t = self.tangent
+            proj = f + t * np.sum(t * f, axis=0)
+            v = (oracle.nonlocal_sbt(f, self.X, t, self.fib, self.L, self.npf, self.delta, self.mu)
+                 + proj * (self.dsum / (8.0 * math.pi * self.mu))[None, :])
         if others:
             w = oracle.fiber_quadrature_weights(self.fib, self.L, self.npf)
             v = v + oracle.sl(self.X, f, src_weight=w, src_fiber=self.fib, fiber_len=self.L,
                               mu=self.mu, eps=self.eps, excl=oracle.EXCL_SAME_FIBER,
-                              doublet=self.doublet)
+                              doublet=self.doublet, nthreads=self.nthreads)
         return v
+
+    def tension_local(self, Xp, T):
+        """h(X+, T): t . (A f+)_s with the arclength identities (module docstring)."""
+        E = self.E
+        x3 = self.per_fiber(self.D3, Xp, 3)
+        x4 = self.per_fiber(self.D4, Xp, 4)
+        Ts = self.per_fiber(self.Da, T[None, :], 1)[0]
+        Tss = self.per_fiber(self.D2, T[None, :], 2)[0]
+        ss3 = np.sum(self.Xss * x3, axis=0)
+        ss4 = np.sum(self.Xss * x4, axis=0)
+        sss3 = np.sum(self.Xsss * x3, axis=0)
+        k2 = np.sum(self.Xss * self.Xss, axis=0)
+        tf = 3.0 * E * ss3 + Ts
+        tf_s = 3.0 * E * (sss3 + ss4) + Tss
+        ssf = -E * ss4 + k2 * T
+        return self.c_s * tf + self.c * tf_s - self.alpha * ssf
+
+    def t_dot_ds(self, v):
+        """t . (v)_s at the nodes (D_s on node values)."""
+        return np.sum(self.tangent * self.per_fiber(self.Da, v, 1), axis=0)
+
+    def local_velocity(self, f):
+        """A f: M f, and with the nonlocal term its subtracted local part
+        -(8 pi mu)^-1 sum_k w_k psi_ik (I + t t) f (eq. main-sb-local, eq. sb-stokes-reg)."""
+        import oracle
+        v = oracle.local_sbt(f, self.tangent, self.eps, self.mu)
+        if self.delta is not None:
+            t = self.tangent
+            v = v - (f + t * np.sum(t * f, axis=0)) * (self.dsum / (8.0 * math.pi * self.mu))[None, :]
+        return v
+
+    def velocity(self, f, others=True):
+        """V[f] = M f (+ K_delta f) (+ the flow of the other fibers at the nodes)."""
+        return self.local_velocity(f) + self.smooth_velocity(f, others)
 
     def _assemble(self, pos_nodes, ten_nodes, bc_pos, bc_ten):
         """Collocate node values and append the boundary rows (row layout: module doc)."""
@@ -155,14 +227,12 @@ class FiberStep:
         Y = np.asarray(Y, dtype=np.float64).ravel()
         Xp = Y[: 3 * self.N].reshape(3, self.N)
         T = Y[3 * self.N:]
-        v = self.velocity(self.force(Xp, T), others)
-        pos = Xp / self.dt - v
-        ten = -np.sum(self.per_fiber(self.Da, v, 0) * self.Xa, axis=0)
-        D2 = self.Da @ self.Da
-        D3 = D2 @ self.Da
+        f = self.force(Xp, T)
+        pos = Xp / self.dt - self.local_velocity(f) - (vr := self.smooth_velocity(f, others))
+        ten = -(self.tension_local(Xp, T) + self.t_dot_ds(vr))
         p = self.npf - 1
-        s2 = self.per_fiber(D2, Xp, 2)
-        s3 = self.per_fiber(D3, Xp, 3)
+        s2 = self.per_fiber(self.D2, Xp, 2)
+        s3 = self.per_fiber(self.D3, Xp, 3)
         bc_pos = np.zeros((3, 4 * self.nf))
         bc_ten = np.zeros(2 * self.nf)
         for m in range(self.nf):
@@ -175,7 +245,7 @@ class FiberStep:
     def rhs(self, fext):
         v = self.velocity(np.asarray(fext, dtype=np.float64))
         pos = self.X / self.dt + v
-        ten = np.sum(self.per_fiber(self.Da, v, 0) * self.Xa, axis=0)
+        ten = self.t_dot_ds(v)
         return self._assemble(pos, ten, np.zeros((3, 4 * self.nf)), np.zeros(2 * self.nf))
 
     def self_blocks(self):
