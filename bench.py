@@ -79,9 +79,10 @@ def parse():
     ap.add_argument("--no-cpu-other", action="store_true",
                     help="time the oracle on the headline workload only")
     ap.add_argument("--only", choices=["mixed", "fp64", "both", "none", "nonlocal", "particles",
-                                       "treecode"],
+                                       "treecode", "fiberstep"],
                     default="both",
-                    help="none: serving run alone; nonlocal / particles / treecode: that section alone")
+                    help="none: serving run alone; nonlocal / particles / treecode / fiberstep: that "
+                         "section alone")
     ap.add_argument("--extra", default="c0,c1,c4",
                     help="other workloads timed after the headline (c0,c1,c4 or none)")
     ap.add_argument("--step-pairs", type=float, default=0,
@@ -362,6 +363,48 @@ def particles_run(S, torch, log_fn, iters=30):
     return res
 
 
+def fiberstep_run(S, torch, log_fn, reps=3, iters=60, tol=1e-5):
+    """One implicit backward-Euler step of a sedimenting suspension of 2048 free bent
+    fibers x 32 nodes (the paper's GMRES study: up to 2048 fibers of 31 points, GMRES
+    tolerance 1e-5, dt = 1e-3 tau_E): time per step, GMRES iterations, and the share of
+    the single-layer pair-sum kernels (the other fibers' flow, once per iteration and
+    once for the right-hand side)."""
+    from paper_1602_05650_amd import workloads as W
+    c = W.config_step()
+    fs = c["fibers"]
+    n, N = fs.nodes_per_fiber, fs.n
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xyz, flen, fext = d(fs.xyz), d(fs.length), d(c["f_ext"])
+    kw = dict(mu=c["mu"], iters=iters, tol=tol, near_r=NEAR_R)
+    pairs = N * (N - n)                     # other-fiber pairs per operator application
+    res = {"workload": f"{fs.n_fib} free bent fibers x {n} CGL nodes = {N} nodes in a ball of "
+                       f"radius 5, L = 1, eps = {c['eps']}, E = {c['E']}, dt = {c['dt']:.4e} "
+                       f"(1e-3 tau_E), sedimenting, GMRES tol {tol}"}
+    for mixed in (False, True):
+        S.fiber_step(xyz, flen, fext, n, c["eps"], c["E"], c["dt"], mixed=mixed, **dict(kw, iters=2))
+        torch.cuda.synchronize()
+        S.profile_read()
+        S.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            X1, T1, r, it = S.fiber_step(xyz, flen, fext, n, c["eps"], c["E"], c["dt"], mixed=mixed, **kw)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        S.profile_enable(False)
+        kms, launches = S.profile_read()
+        tag = "mixed" if mixed else "fp64"
+        res[tag] = {"ms_per_step": round(sec * 1e3, 2), "gmres_iterations": it,
+                    "operator_applications": it + 1,
+                    "pair_sum_ms": round(kms / reps, 2),
+                    "pair_sum_share": round(kms / reps / (sec * 1e3), 3),
+                    "pair_sum_gpair_per_s": round(pairs * (it + 1) / (kms / reps * 1e-3) / 1e9, 1),
+                    "max_displacement": float(f"{float((X1 - xyz).abs().max()):.4e}"),
+                    "max_tension": float(f"{float(T1.abs().max()):.4e}")}
+        log_fn(f"fiber step {tag}: {sec * 1e3:.1f} ms, {it} iterations, pair sums "
+               f"{kms / reps:.1f} ms")
+    return res
+
+
 def tree_run(S, torch, log_fn, degree=6, theta=0.7, leaf=128, reps=10):
     """Treecode single-layer sum on the spindle and the large confined fiber set: plan
     build time, evaluation time (mixed and FP64), interactions per second, and the
@@ -503,6 +546,9 @@ def main():
     if args.only == "treecode":      # treecode section alone (for profiling it)
         print(json.dumps({"treecode": tree_run(S, torch, log)}), flush=True)
         return
+    if args.only == "fiberstep":     # implicit fiber time step alone (for profiling it)
+        print(json.dumps({"fiber_step": fiberstep_run(S, torch, log)}), flush=True)
+        return
     if args.only == "particles":     # rigid-particle section alone (for profiling it)
         print(json.dumps({"particles": particles_run(S, torch, log)}), flush=True)
         return
@@ -615,6 +661,7 @@ def main():
         out["nonlocal"] = nonlocal_run(S, torch, log)
         out["particles"] = particles_run(S, torch, log)
         out["treecode"] = tree_run(S, torch, log)
+        out["fiber_step"] = fiberstep_run(S, torch, log)
     if not args.no_serving:
         try:
             out["serving"] = serving_run(S, args.serving_requests, log, args.step_pairs,

@@ -227,6 +227,51 @@ int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xy
                           double* f_out, double* resid_out, int32_t* iters_out, void* stream);
 
 /*
+ * stokes_fiber_step -- one implicit (backward Euler) time step of free elastic
+ * fibers (section "Time discretization"), fixed lengths, no rigid bodies.
+ *
+ * Finds X+ and the tension T+ with (eq. discrete-update, fiber rows)
+ *   (X+ - X) / dt = V[f+ + f_ext],   f+ = -E X+_ssss + (T+ X_s)_s   (X_s explicit)
+ *   V[f] = M f [+ K_delta f] + u_bar[f]   (eq. main-sb-local, eq. sb-stokes-reg with
+ *          STOKES_NONLOCAL, and the other fibers' flow of eq. complementary-uf, all
+ *          implicit), the inextensibility constraint in the velocity form of
+ *   eq. main-inextensibility, t . (V[f+ + f_ext])_s = 0, taken as a second-order equation
+ *   for T: the node-by-node part A = alpha I + beta t t of V (M, and the subtracted
+ *   local part of K_delta) is differentiated with the arclength identities
+ *   (t . X_ss = 0, t . X_sss = -|X_ss|^2, t . X_ssss = -3 X_ss . X_sss), the rest of V with
+ *   D_s; and the free-end conditions of eq. bc-free (X_ss = X_sss = 0, T = 0 at both ends).
+ * Discretisation: Chebyshev differentiation on the CGL nodes by the coefficient
+ * recursion (section "Fiber representation"); the position equations collocated at
+ * nodes_per_fib - 4 and the tension equation at nodes_per_fib - 2 first-kind
+ * Chebyshev points, completed by the boundary rows (rectangular collocation).
+ * Solved for the increment (X+ - X, T+) by right-preconditioned GMRES in FP64 from
+ * zero, with each fiber's self block (its rows without u_bar: 4 n x 4 n) inverted by
+ * Gauss-Jordan as block-Jacobi preconditioner (section "Linear solver and
+ * preconditioner"); iterations stop after `iters`, at exact breakdown, or when the
+ * least-squares residual is <= tol x |rhs|.
+ *
+ * n_fib, nodes_per_fib   fibers (>= 0) and CGL nodes per fiber (6..48); N = n_fib*nodes.
+ * xyz        [3*N] node positions (x of every node, then y, then z), fiber-contiguous,
+ *            node k of a fiber at alpha_k = cos(k pi/(nodes-1)) (node 0: s = L).
+ * fiber_len  [n_fib] lengths L.    f_ext [3*N] external force density at the nodes.
+ * eps        slenderness in (0, 0.5);  E >= 0 bending modulus;  dt > 0;  mu > 0.
+ * delta      regularisation of K_delta (> 0 with STOKES_NONLOCAL, else unused).
+ * near_r     mixed single-layer sums only (see stokes_sl_eval).
+ * iters      1..STOKES_MAX_ITERS;  tol >= 0 (0: run all iterations).
+ * flags      STOKES_PREC_* for the u_bar sums, STOKES_NO_DOUBLET, STOKES_NONLOCAL.
+ * xyz_out    [3*N] X+ (must not alias xyz or f_ext).   T_out [N] T+ at the nodes.
+ * resid_out, iters_out   NULL or host: final least-squares residual, iterations.
+ * All arrays are DEVICE pointers.  The call allocates its own scratch (about
+ * (16 n + 3 iters + 30) N doubles plus 37 n^2 per fiber of a 512-fiber chunk) and is
+ * synchronous.
+ */
+int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
+                      const double* fiber_len, const double* f_ext, double eps, double E,
+                      double dt, double mu, double delta, double near_r, int32_t iters,
+                      double tol, uint32_t flags, double* xyz_out, double* T_out,
+                      double* resid_out, int32_t* iters_out, void* stream);
+
+/*
  * stokes_particle_solve -- mobility of rigid particles in a fixed confining
  * periphery: the second-kind boundary integral equations of sections "The
  * contribution from the periphery" and "The contribution from rigid immersed

@@ -12,7 +12,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 SOURCES = ["stokes_runtime.hip", "stokes_sums.hip", "stokes_solver.hip", "stokes_session.hip",
            "stokes_tree.hip",
-           "stokes_particles.hip"]
+           "stokes_particles.hip", "stokes_fiberstep.hip"]
 LIB = os.path.join(PKG, "libstokes.so")
 ARCH = os.environ.get("STOKES_OFFLOAD_ARCH", "gfx950")
 

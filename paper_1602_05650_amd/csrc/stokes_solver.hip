@@ -17,6 +17,8 @@
 #include <cmath>
 #include <cstring>
 
+#include "fiber_device.hpp"
+#include "gj_device.hpp"
 #include "solver_batch.hpp"
 
 namespace stokes {
@@ -32,70 +34,6 @@ __device__ __forceinline__ int find_slot(cptr<WorkList> wl, int64_t item) {
         if (wl->prefix[mid] <= item) lo = mid; else hi = mid - 1;
     }
     return lo;
-}
-
-// Clenshaw-Curtis weight of node kk on the p+1 CGL nodes cos(k pi/p) (Waldvogel's
-// closed form): w_k = (c_k/p) (1 - sum_{j=1}^{p/2} b_j cos(2 j k pi/p) / (4 j^2 - 1)).
-__device__ double cc_weight(int kk, int p) {
-    if (p == 1) return 1.0;
-    double s = 0.0;
-    for (int j = 1; j <= p / 2; ++j) {
-        const double b = (2 * j == p) ? 1.0 : 2.0;
-        s += b * cos(2.0 * j * kk * 3.14159265358979323846 / p) / (4.0 * j * j - 1.0);
-    }
-    const double c = (kk == 0 || kk == p) ? 1.0 : 2.0;
-    return c / p * (1.0 - s);
-}
-
-// out = a f + b t (t.f): M (inverse = 0) or M^{-1} (inverse = 1), eq. main-sb-local.
-__device__ __forceinline__ void apply_local(double kap, double mu, bool inverse, double tx,
-                                            double ty, double tz, double& fx, double& fy,
-                                            double& fz) {
-    const double pi8mu = 8.0 * 3.14159265358979323846 * mu;
-    double a, b;
-    if (!inverse) {
-        a = (kap + 2.0) / pi8mu;
-        b = (kap - 2.0) / pi8mu;
-    } else {
-        a = pi8mu / (kap + 2.0);
-        b = pi8mu / (2.0 * kap) - a;
-    }
-    const double tf = tx * fx + ty * fy + tz * fz;
-    fx = a * fx + b * tf * tx;
-    fy = a * fy + b * tf * ty;
-    fz = a * fz + b * tf * tz;
-}
-
-// K_delta[f] at node i (eq. sb-stokes-reg) over the other nodes of its fiber, with
-// the fiber's quadrature weights wq and arc lengths sarc.  |r|/sqrt(r^2+d^2) G(r) f_k
-// is written (f_k + r (r.f_k)/r^2) / (8 pi mu sqrt(r^2 + d^2)).
-__device__ void nonlocal_at(int64_t i, int64_t N, int npf, const double* xyz, const double* tan,
-                            const double* f, const double* wq, const double* sarc, double delta,
-                            double pref, double& ox, double& oy, double& oz) {
-    const int64_t f0 = (i / npf) * npf;
-    const double xi = xyz[i], yi = xyz[N + i], zi = xyz[2 * N + i];
-    const double si = sarc[i], d2 = delta * delta;
-    double ax = 0.0, ay = 0.0, az = 0.0, dsum = 0.0;
-    for (int k = 0; k < npf; ++k) {
-        const int64_t j = f0 + k;
-        if (j == i) continue;
-        const double rx = xi - xyz[j], ry = yi - xyz[N + j], rz = zi - xyz[2 * N + j];
-        const double fx = f[j], fy = f[N + j], fz = f[2 * N + j];
-        const double r2 = rx * rx + ry * ry + rz * rz;
-        const double a = wq[j] / sqrt(r2 + d2);
-        const double b = a * (rx * fx + ry * fy + rz * fz) / r2;
-        ax += a * fx + b * rx;
-        ay += a * fy + b * ry;
-        az += a * fz + b * rz;
-        const double ds = si - sarc[j];
-        dsum += wq[j] / sqrt(ds * ds + d2);
-    }
-    const double tx = tan[i], ty = tan[N + i], tz = tan[2 * N + i];
-    const double fx = f[i], fy = f[N + i], fz = f[2 * N + i];
-    const double tf = tx * fx + ty * fy + tz * fz;
-    ox = pref * (ax - dsum * (fx + tf * tx));
-    oy = pref * (ay - dsum * (fy + tf * ty));
-    oz = pref * (az - dsum * (fz + tf * tz));
 }
 
 // (B_f^{-1} v) at node i of fiber f: rows c npf + kk of the fiber's inverse block
@@ -189,19 +127,13 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const SlotDesc* D, const StepTa
 }
 
 // Self block M [+ K_delta] of one fiber (after k_geom), inverted by Gauss-Jordan
-// elimination with partial pivoting.  One workgroup of BLOCK_GJ threads per fiber
-// holds the whole m x m matrix (m = 3 npf <= 192) in registers: thread t owns row
-// r = t % m and the columns c = g + GJ_G jj (g = t / m, jj < GJ_COLS), so every
-// pivot step only exchanges the pivot column and row through LDS.  The inverse is
-// written column-major to the slot's binv buffer (row and column index c npf + k).
-constexpr int BLOCK_GJ = 1024;
-constexpr int GJ_G = 5;                          // column groups: GJ_G * 192 <= BLOCK_GJ
-constexpr int GJ_COLS = (192 + GJ_G - 1) / GJ_G;  // columns per thread
+// elimination with partial pivoting (gj_device.hpp): one workgroup of BLOCK_GJ
+// threads per fiber holds the m x m matrix (m = 3 npf) in registers.  The inverse
+// is written column-major to the slot's binv buffer (row and column index c npf + k).
 __global__ __launch_bounds__(BLOCK_GJ) void k_block(const SlotDesc* D, const StepTables* T) {
-    __shared__ double s_col[192], s_row[192], s_swap[2][192], s_wv[BLOCK_GJ / 64];
-    __shared__ int s_wi[BLOCK_GJ / 64], s_perm[192], s_dest[192];
+    __shared__ GjLds sh;
     const cptr<WorkList> wl = &as_const(T)->wl[WL_FIB];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x;
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
         const auto& d = as_const(D)[wl->slot[si]];
@@ -211,7 +143,7 @@ __global__ __launch_bounds__(BLOCK_GJ) void k_block(const SlotDesc* D, const Ste
         const bool nl = d.opts & STOKES_NONLOCAL;
         const double d2 = d.delta * d.delta;
         const bool act = t < GJ_G * m;
-        const int r = act ? t % m : 0, g = act ? t / m : 0;
+        const int r = act ? t % m : 0, g = act ? t / m : 0;   // as gj_invert expects
         const int rc = r / npf, ri = r - rc * npf;
         const int64_t gi = f0 + ri;
         // this row's node: position, tangent, and the subtracted K_delta coefficient
@@ -249,112 +181,7 @@ __global__ __launch_bounds__(BLOCK_GJ) void k_block(const SlotDesc* D, const Ste
             }
             A[jj] = v;
         }
-        for (int p = 0; p < m; ++p) {
-            const int gp = p % GJ_G, jp = p / GJ_G;
-            // pivot: largest |A[r][p]| over rows r >= p (smallest r on ties)
-            double bv = -1.0;
-            int bi = m;
-            if (act && g == gp) {
-                double v = 0.0;
-#pragma unroll
-                for (int jj = 0; jj < GJ_COLS; ++jj)
-                    if (jj == jp) v = A[jj];
-                if (r >= p) {
-                    bv = fabs(v);
-                    bi = r;
-                }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(bv, o);
-                const int oi = __shfl_xor(bi, o);
-                if (ov > bv || (ov == bv && oi < bi)) {
-                    bv = ov;
-                    bi = oi;
-                }
-            }
-            if (lane == 0) {
-                s_wv[wave] = bv;
-                s_wi[wave] = bi;
-            }
-            __syncthreads();
-            double pv = s_wv[0];
-            int pr = s_wi[0];
-            for (int w = 1; w < BLOCK_GJ / 64; ++w)
-                if (s_wv[w] > pv || (s_wv[w] == pv && s_wi[w] < pr)) {
-                    pv = s_wv[w];
-                    pr = s_wi[w];
-                }
-            if (pr >= m) pr = p;    // (a column of NaN: no row qualifies)
-            if (t == 0) s_perm[p] = pr;
-            // row interchange p <-> pr through LDS
-            if (pr != p) {
-                if (act && (r == p || r == pr)) {
-#pragma unroll
-                    for (int jj = 0; jj < GJ_COLS; ++jj) {
-                        const int c = g + GJ_G * jj;
-                        if (c < m) s_swap[r == p ? 0 : 1][c] = A[jj];
-                    }
-                }
-                __syncthreads();
-                if (act && (r == p || r == pr)) {
-#pragma unroll
-                    for (int jj = 0; jj < GJ_COLS; ++jj) {
-                        const int c = g + GJ_G * jj;
-                        if (c < m) A[jj] = s_swap[r == p ? 1 : 0][c];
-                    }
-                }
-            }
-            // pivot column and (unscaled) pivot row to LDS
-            if (act && g == gp) {
-                double v = 0.0;
-#pragma unroll
-                for (int jj = 0; jj < GJ_COLS; ++jj)
-                    if (jj == jp) v = A[jj];
-                s_col[r] = v;
-            }
-            if (act && r == p) {
-#pragma unroll
-                for (int jj = 0; jj < GJ_COLS; ++jj) {
-                    const int c = g + GJ_G * jj;
-                    if (c < m) s_row[c] = A[jj];
-                }
-            }
-            __syncthreads();
-            const double inv = 1.0 / s_col[p];
-            const double cr = s_col[r];
-            if (act) {
-#pragma unroll
-                for (int jj = 0; jj < GJ_COLS; ++jj) {
-                    const int c = g + GJ_G * jj;
-                    if (c < m) {
-                        const double rp = c == p ? inv : s_row[c] * inv;
-                        A[jj] = r == p ? rp : (c == p ? 0.0 : A[jj]) - cr * rp;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        // undo the row interchanges on the columns (last first): column c of the
-        // inverse is working column s_dest^{-1}(c)
-        if (t == 0) {
-            for (int c = 0; c < m; ++c) s_dest[c] = c;   // s_dest[c]: working column at c
-            for (int p = m - 1; p >= 0; --p) {
-                const int q = s_perm[p];
-                const int a = s_dest[p];
-                s_dest[p] = s_dest[q];
-                s_dest[q] = a;
-            }
-            for (int c = 0; c < m; ++c) s_perm[s_dest[c]] = c;       // working column -> final column
-        }
-        __syncthreads();
-        if (act) {
-            double* X = d.binv + (int64_t)f * m * m;
-#pragma unroll
-            for (int jj = 0; jj < GJ_COLS; ++jj) {
-                const int c = g + GJ_G * jj;
-                if (c < m) X[(int64_t)s_perm[c] * m + r] = A[jj];
-            }
-        }
+        gj_invert(m, act, r, g, A, sh, d.binv + (int64_t)f * m * m);
         __syncthreads();
     }
 }

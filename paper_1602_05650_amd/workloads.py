@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "FiberSet", "SphereSurface", "cgl_alpha", "uniform_ball", "uniform_sphere_dirs",
     "straight_fibers", "sphere_surface", "config0", "config1", "config2", "config4",
-    "serving_request", "serving_stream", "random_points",
+    "serving_request", "serving_stream", "random_points", "bent_fibers", "config_step",
 ]
 
 
@@ -191,6 +191,69 @@ def random_fibers_in_ball(rng, n_fib, nodes, R_center, L=1.0, eps=0.01, gap=None
     else:
         pts = _resolve_overlaps(nodes_fn, params, resample, gap)
     return _fiberset(pts, params["t"], length, eps)
+
+
+def bent_shape(nodes, L, amp):
+    """Planar centerlines of length L parametrised by arclength, (len(amp), nodes, 2) in
+    their own frames, each centred on its mean node: tangent angle
+    theta(s) = amp (phi(s/L) - 1/2) with phi(u) = u^3 (10 - 15 u + 6 u^2), so
+    theta' = theta'' = 0 at both ends (zero curvature and curvature derivative:
+    compatible with free ends).  Positions are the integrals of (cos theta, sin theta),
+    by 48-point Gauss-Legendre on [0, s_k]."""
+    amp = np.atleast_1d(np.asarray(amp, np.float64))
+    s = (cgl_alpha(nodes - 1) + 1.0) * 0.5 * L
+    gx, gw = np.polynomial.legendre.leggauss(48)
+    q = 0.5 * s[:, None] * (gx[None, :] + 1.0)               # (nodes, 48) points in [0, s_k]
+    u = q / L
+    th = amp[:, None, None] * (u ** 3 * (10.0 - 15.0 * u + 6.0 * u * u) - 0.5)[None]
+    w = (0.5 * s[:, None] * gw[None, :])[None]
+    xy = np.stack([np.sum(w * np.cos(th), axis=2), np.sum(w * np.sin(th), axis=2)], axis=2)
+    return xy - xy.mean(axis=1, keepdims=True)
+
+
+def bent_fibers(rng, n_fib, nodes, R_center, L=1.0, eps=0.01, amp=0.6, gap=None):
+    """Bent planar fibers (bent_shape with amp uniform in [-amp, amp]) with centres
+    uniform in a ball, random orientation of the shape's plane and axis.  gap: minimum
+    node distance between different fibers (None = no rejection).  The FiberSet's
+    tangent is the chord direction (the time step computes its own tangents)."""
+    length = np.full(n_fib, float(L))
+
+    def draw(idx):
+        k = len(idx)
+        t = uniform_sphere_dirs(rng, k)
+        a = uniform_sphere_dirs(rng, k)
+        nrm = np.cross(t, a)
+        nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+        return uniform_ball(rng, k, R_center), t, nrm, rng.uniform(-amp, amp, k)
+
+    params = dict(zip(("c", "t", "n", "amp"), draw(np.arange(n_fib))))
+
+    def nodes_fn(p):
+        xy = bent_shape(nodes, L, p["amp"])
+        return (p["c"][:, None, :] + xy[:, :, :1] * p["t"][:, None, :]
+                + xy[:, :, 1:] * p["n"][:, None, :])
+
+    def resample(p, idx):
+        c, t, nrm, am = draw(idx)
+        p["c"][idx], p["t"][idx], p["n"][idx], p["amp"][idx] = c, t, nrm, am
+
+    pts = nodes_fn(params) if gap is None else _resolve_overlaps(nodes_fn, params, resample, gap)
+    return _fiberset(pts, params["t"], length, eps)
+
+
+def config_step(seed=5, n_fib=2048, nodes=32, R=5.0, L=1.0, eps=0.01, E=1.0, mu=1.0):
+    """One implicit step of a sedimenting suspension of free bent fibers: n_fib fibers
+    x nodes CGL nodes (the paper's GMRES study uses up to 2048 fibers of 31 points),
+    centres in a ball of radius R (gap 0.05 between fibers), uniform force density
+    -E/(32 L^3) e_z plus a seeded random part of the same size, and the step
+    dt = 1e-3 tau_E with tau_E = -8 pi mu L^4 / (E ln(eps^2 e)) (section "Numerical
+    results": stable steps of 0.25e-3 .. 1.3e-3 tau_E)."""
+    g, d, _ = _streams(seed)
+    fs = bent_fibers(g, n_fib, nodes, R - 0.55 * L, L=L, eps=eps, gap=0.05 * L)
+    f0 = E / (32.0 * L ** 3)
+    f_ext = f0 * (d.standard_normal((3, fs.n)) * 0.5 + np.array([[0.0], [0.0], [-1.0]]))
+    tau = -8.0 * math.pi * mu * L ** 4 / (E * math.log(eps * eps * math.e))
+    return {"fibers": fs, "f_ext": f_ext, "E": E, "mu": mu, "eps": eps, "dt": 1e-3 * tau}
 
 
 def sphere_surface(n_theta: int, n_phi: int, R: float, patch=(4, 8)) -> SphereSurface:

@@ -119,3 +119,26 @@ def test_solve_footprint_without_gpu():
 def test_version():
     from paper_1602_05650_amd import stokes as S
     assert S.version() >= 10000
+
+
+def test_fiber_step_validation_without_gpu():
+    from paper_1602_05650_amd import stokes as S
+    L = S._lib
+
+    def call(n_fib=0, npf=16, eps=0.01, E=1.0, dt=1e-3, mu=1.0, delta=0.0, iters=10, tol=0.0, flags=0,
+             ptrs=None):
+        p = ptrs if ptrs is not None else [None] * 5
+        return L.stokes_fiber_step(n_fib, npf, p[0], p[1], p[2], eps, E, dt, mu, delta, 0.0, iters, tol,
+                                   flags, p[3], p[4], None, None, None)
+
+    assert call() == S.OK                                   # no fibers: nothing to do
+    for kw in ({"npf": 5}, {"npf": 49}, {"n_fib": -1}, {"eps": 0.6}, {"E": -1.0}, {"dt": 0.0},
+               {"mu": 0.0}, {"iters": 0}, {"iters": 129}, {"tol": -1.0},
+               {"flags": S.NONLOCAL}, {"flags": S.EXCL_SELF_POINT}, {"dt": float("nan")}):
+        assert call(**kw) == S.E_INVAL, kw
+    assert "stokes_fiber_step" in S.last_error()
+    assert call(n_fib=2) == S.E_INVAL                       # null arrays with fibers
+    assert "null" in S.last_error()
+    fake = ctypes.c_void_p(1)
+    assert call(n_fib=2, ptrs=[fake, fake, fake, fake, fake]) == S.E_INVAL   # X+ aliases X
+    assert "alias" in S.last_error()
