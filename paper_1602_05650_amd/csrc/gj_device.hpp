@@ -26,8 +26,10 @@ struct GjLds {
 // is then not finite).  Every thread of the workgroup must call it.
 // (act, r, g) are the thread's role as set out above: act = t < GJ_G m, r = t % m,
 // g = t / m (both 0 when inactive).
+// ds (LDS or null): the result's column j is multiplied by ds[j] (the inverse of a
+// row-equilibrated matrix D B gives B^-1 = (D B)^-1 D).
 __device__ __forceinline__ void gj_invert(int m, bool act, int r, int g, double (&A)[GJ_COLS], GjLds& s,
-                                          double* X) {
+                                          double* X, const double* ds = nullptr) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int p = 0; p < m; ++p) {
         const int gp = p % GJ_G, jp = p / GJ_G;
@@ -131,7 +133,112 @@ __device__ __forceinline__ void gj_invert(int m, bool act, int r, int g, double 
 #pragma unroll
         for (int jj = 0; jj < GJ_COLS; ++jj) {
             const int c = g + GJ_G * jj;
-            if (c < m) X[(int64_t)s.perm[c] * m + r] = A[jj];
+            if (c < m) X[(int64_t)s.perm[c] * m + r] = ds ? A[jj] * ds[s.perm[c]] : A[jj];
+        }
+    }
+}
+
+}  // namespace stokes
+
+namespace stokes {
+
+// A second layout for blocks of m <= 128 with 256 threads: thread t owns row r = t % m
+// and the contiguous columns g * 64 + jj (g = t / m < 2, jj < 64) when t < 2 m.  A wave
+// then holds one column range for 64 rows, so the pivot row is read from LDS as a
+// broadcast and the pivot column sits at the same register index in the whole wave.
+constexpr int GJ64_T = 256;
+constexpr int GJ64_MAX = 128;
+
+struct Gj64Lds {
+    double col[2][GJ64_MAX], row[2][GJ64_MAX], oh[2][GJ64_MAX];
+    unsigned wk[2][GJ64_T / 64];
+    int perm[GJ64_MAX], dest[GJ64_MAX];
+};
+
+// Same contract as gj_invert: A holds A[r][g * 64 + jj] (zero beyond m); on return X
+// (column-major, m x m) holds the inverse.  Every thread of the workgroup must call it.
+// Partial pivoting without row interchanges: the pivot of column p is the largest
+// |a_rp| over rows not yet used (to a relative 2^-13: the search compares the high
+// 32 bits of |a_rp|), pi(p) records it, and the stored result S gives
+// A^-1[pi^-1(a)][pi(b)] = S[a][b].  The pivot loop has no branches on the column
+// index: rows are padded with zeros to 128 columns, the pivot column is a one-hot
+// vector oh in LDS, a thread's entry in column p is sum_jj A[jj] oh[c], and the update
+// is A <- A ks (1 - oh[c]) - (a_rp / a_pp) row[c] with row carrying 1 at column p (ks = 0
+// and a_rp = -1 on the pivot row).  The LDS vectors alternate between two buffers by
+// the parity of p, so one pivot step needs two barriers.
+// ds as for gj_invert.
+__device__ __forceinline__ void gj_invert64(int m, bool act, int r, int g, double (&A)[64], Gj64Lds& s,
+                                            double* X, const double* ds = nullptr) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t < GJ64_MAX) {
+        s.oh[0][t] = t == 0 ? 1.0 : 0.0;
+        s.oh[1][t] = 0.0;
+    }
+    bool used = false;
+    __syncthreads();
+    for (int p = 0; p < m; ++p) {
+        const int gp = p >> 6, b = p & 1;
+        const double* oh = s.oh[b];
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;   // this thread's entry of column p
+#pragma unroll
+        for (int jj = 0; jj < 64; jj += 4) {
+            q0 = fma(A[jj], oh[g * 64 + jj], q0);
+            q1 = fma(A[jj + 1], oh[g * 64 + jj + 1], q1);
+            q2 = fma(A[jj + 2], oh[g * 64 + jj + 2], q2);
+            q3 = fma(A[jj + 3], oh[g * 64 + jj + 3], q3);
+        }
+        const double pc = (q0 + q1) + (q2 + q3);          // (one term is nonzero)
+        // pivot search key: the high word of |a_rp| with its low 7 bits replaced by
+        // 127 - r (largest |a| to 2^-13, then smallest row); 0 for used rows
+        unsigned key = 0u;
+        if (act && g == gp) {
+            s.col[b][r] = pc;
+            if (!used)
+                key = ((unsigned)(__double_as_longlong(fabs(pc)) >> 32) & 0xFFFFFF80u) | (unsigned)(127 - r);
+        }
+        for (int o = 32; o > 0; o >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, o));
+        if (lane == 0) s.wk[b][wave] = key;
+        __syncthreads();
+        unsigned kb = s.wk[b][0];
+        for (int w = 1; w < GJ64_T / 64; ++w) kb = max(kb, s.wk[b][w]);
+        const int pr = 127 - (int)(kb & 0x7Fu);
+        if (t == 0) {
+            s.perm[p] = pr;
+            double* on = s.oh[b ^ 1];       // next pivot's one-hot (last read at p - 1)
+            if (p >= 1) on[p - 1] = 0.0;
+            if (p + 1 < m) on[p + 1] = 1.0;
+        }
+        const bool piv = act && r == pr;
+        if (piv) {
+#pragma unroll
+            for (int jj = 0; jj < 64; ++jj) {
+                const double o = oh[g * 64 + jj];
+                s.row[b][g * 64 + jj] = fma(A[jj], 1.0 - o, o);
+            }
+            used = true;
+        }
+        __syncthreads();
+        const double inv = 1.0 / s.col[b][pr];
+        const double crinv = (piv ? -1.0 : s.col[b][r]) * inv;
+        const double ks = piv ? 0.0 : 1.0;
+        if (act) {
+#pragma unroll
+            for (int jj = 0; jj < 64; ++jj) {
+                const int c = g * 64 + jj;
+                A[jj] = fma(A[jj], ks * (1.0 - oh[c]), -crinv * s.row[b][c]);
+            }
+        }
+    }
+    __syncthreads();
+    if (t == 0)
+        for (int p = 0; p < m; ++p) s.dest[s.perm[p]] = p;     // pi^-1
+    __syncthreads();
+    if (act) {
+        const int row_out = s.dest[r];
+#pragma unroll
+        for (int jj = 0; jj < 64; ++jj) {
+            const int c = g * 64 + jj;
+            if (c < m) X[(int64_t)s.perm[c] * m + row_out] = ds ? A[jj] * ds[s.perm[c]] : A[jj];
         }
     }
 }

@@ -430,7 +430,176 @@ __global__ __launch_bounds__(BLOCK_GJ) void k_fs_block(Geo g, int f_begin, const
         }
         A[jj] = v;
     }
-    gj_invert(m, act, r, grp, A, sh, binv + (int64_t)f * m * m);
+    // row equilibration (as in k_fs_block64): the largest |entry| of each row over the
+    // GJ_G column groups of its threads
+    __shared__ double rmax[GJ_G][GJ_MAX], rscale[GJ_MAX];
+    double mx = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < GJ_COLS; ++jj) mx = fmax(mx, fabs(A[jj]));
+    if (act) rmax[grp][r] = mx;
+    __syncthreads();
+    if (act) {
+        double rm = 0.0;
+        for (int q = 0; q < GJ_G; ++q) rm = fmax(rm, rmax[q][r]);
+        const double d = rm > 0.0 && rm < INFINITY ? 1.0 / rm : 1.0;
+#pragma unroll
+        for (int jj = 0; jj < GJ_COLS; ++jj) A[jj] *= d;
+        if (grp == 0) rscale[r] = d;
+    }
+    gj_invert(m, act, r, grp, A, sh, binv + (int64_t)f * m * m, rscale);
+}
+
+// Self blocks of fibers with at most 32 nodes (m = 4 n <= 128), one 256-thread workgroup
+// per fiber (gj_invert64).  Without the nonlocal term the entries are formed here from
+// the node data and the tables staged in LDS: the self velocity is node by node, so
+// Vs[(a,k), c] = A_k F[(.,k), c].  With it they come from k_fs_prep's scratch.
+constexpr int NB64 = 32;
+template <bool LOCAL>
+__global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fs_block64(Geo g, int f_begin, const double* scratch,
+                                                       double* binv) {
+    // the tables of phase 1 and the elimination's LDS are never live together
+    union Lds {
+        struct {
+            double d1[NB64 * NB64], d2[NB64 * NB64], d3[NB64 * NB64], d4[NB64 * NB64];
+            double p4t[NB64 * NB64], p2t[NB64 * NB64];               // P4T[k][j], P2T[k][j]
+            double nal[NB64], nbe[NB64], ncc[NB64], ncs[NB64], nk2[NB64];
+            double nt[3][NB64], nxa[3][NB64], nxss[3][NB64], nxsss[3][NB64];
+        } tb;
+        Gj64Lds gj;
+    };
+    __shared__ Lds lds;
+    Gj64Lds& sh = lds.gj;
+    double *d1 = lds.tb.d1, *d2 = lds.tb.d2, *d3 = lds.tb.d3, *d4 = lds.tb.d4, *p4t = lds.tb.p4t,
+           *p2t = lds.tb.p2t, *nal = lds.tb.nal, *nbe = lds.tb.nbe, *ncc = lds.tb.ncc, *ncs = lds.tb.ncs,
+           *nk2 = lds.tb.nk2;
+    double(*nt)[NB64] = lds.tb.nt;
+    double(*nxa)[NB64] = lds.tb.nxa;
+    double(*nxss)[NB64] = lds.tb.nxss;
+    double(*nxsss)[NB64] = lds.tb.nxsss;
+    const int n = g.n, m = 4 * n, n3 = 3 * n, t = threadIdx.x;
+    const int fl = blockIdx.x, f = f_begin + fl;
+    const int64_t N = g.N, f0 = (int64_t)f * n;
+    const double s = 2.0 / g.flen[f], E = g.E;
+    for (int e = t; e < n * n; e += GJ64_T) {
+        d1[e] = g.D1[e];
+        d2[e] = g.D2[e];
+        d3[e] = g.D3[e];
+        d4[e] = g.D4[e];
+        const int k = e / n, j = e - k * n;              // transposed resampling tables
+        if (j < n - 4) p4t[e] = g.P4[j * n + k];
+        if (j < n - 2) p2t[e] = g.P2[j * n + k];
+    }
+    if (t < n) {
+        const int64_t i = f0 + t;
+        nal[t] = g.alpha[i];
+        ncc[t] = g.cc[i];
+        nbe[t] = g.cc[i] - g.alpha[i];
+        ncs[t] = g.cs[i];
+        double k2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            nt[c][t] = g.tan[c * N + i];
+            nxa[c][t] = g.Xa[c * N + i];
+            nxss[c][t] = g.xss[c * N + i];
+            nxsss[c][t] = g.xsss[c * N + i];
+            k2 = fma(g.xss[c * N + i], g.xss[c * N + i], k2);
+        }
+        nk2[t] = k2;
+    }
+    __syncthreads();
+    const double* Vs = scratch + (int64_t)fl * prep_doubles(n) + 9 * n * n;
+    const double* G = Vs + 24 * n * n;
+    const double e4 = -E * s * s * s * s, s2 = s * s, s3 = s2 * s, s4 = s2 * s2;
+    double* Bf = binv + (int64_t)f * m * m;
+    // phase 1: the block, column-major, into its own inverse slot (consecutive threads
+    // take consecutive rows of one column)
+    for (int e = t; e < m * m; e += GJ64_T) {
+        const int c = e / m, r = e - c * m;
+        double v = 0.0;
+        const bool xcol = c < n3;
+        const int ce = xcol ? c / n : 3, kc = xcol ? c - ce * n : c - n3;
+        if (r < n3) {
+            const int a = r / n, j = r - a * n;
+            if (j < n - 4) {
+                if (LOCAL) {
+                    if (xcol) {
+                        for (int k = 0; k < n; ++k) {
+                            const double Ake = (a == ce ? nal[k] : 0.0) + nbe[k] * nt[a][k] * nt[ce][k];
+                            v = fma(p4t[k * n + j] * Ake, d4[k * n + kc], v);
+                        }
+                        v *= -e4;
+                    } else {
+                        const double xa0 = nxa[0][kc], xa1 = nxa[1][kc], xa2 = nxa[2][kc];
+                        const double xaa = a == 0 ? xa0 : (a == 1 ? xa1 : xa2);
+                        for (int k = 0; k < n; ++k) {
+                            const double tx = nt[0][k] * xa0 + nt[1][k] * xa1 + nt[2][k] * xa2;
+                            const double ax = nal[k] * xaa + nbe[k] * nt[a][k] * tx;
+                            v = fma(p4t[k * n + j] * d1[k * n + kc], ax, v);
+                        }
+                        v *= -s2;
+                    }
+                } else {
+                    for (int k = 0; k < n; ++k) v = fma(p4t[k * n + j], -Vs[(int64_t)(a * n + k) * m + c], v);
+                }
+                if (xcol && ce == a) v += p4t[kc * n + j] / g.dt;
+            } else if (xcol && ce == a) {
+                const int b = j - (n - 4);
+                const int node = b < 2 ? 0 : n - 1;
+                v = (b & 1) ? s3 * d3[node * n + kc] : s2 * d2[node * n + kc];
+            }
+        } else {
+            const int j = r - n3;
+            if (j < n - 2) {
+                if (LOCAL) {
+                    if (xcol) {
+                        for (int k = 0; k < n; ++k) {
+                            const double x3 = s3 * d3[k * n + kc], x4 = s4 * d4[k * n + kc];
+                            const double xs2 = nxss[ce][k], xs3 = nxsss[ce][k];
+                            const double h = ncs[k] * 3.0 * E * xs2 * x3 +
+                                             ncc[k] * 3.0 * E * (xs3 * x3 + xs2 * x4) + nal[k] * E * xs2 * x4;
+                            v = fma(p2t[k * n + j], h, v);
+                        }
+                    } else {
+                        for (int k = 0; k < n; ++k) {
+                            const double h = ncs[k] * s * d1[k * n + kc] + ncc[k] * s2 * d2[k * n + kc] -
+                                             (k == kc ? nal[k] * nk2[k] : 0.0);
+                            v = fma(p2t[k * n + j], h, v);
+                        }
+                    }
+                    v = -v;
+                } else {
+                    for (int k = 0; k < n; ++k) v = fma(p2t[k * n + j], -G[(int64_t)k * m + c], v);
+                }
+            } else if (!xcol) {
+                v = kc == (j == n - 2 ? 0 : n - 1) ? 1.0 : 0.0;
+            }
+        }
+        Bf[e] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // phase 2: each thread's row segment into registers, then Gauss-Jordan in place
+    const bool act = t < 2 * m;
+    const int r = act ? t % m : 0, grp = act ? t / m : 0;
+    double A[64], mx = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 64; ++jj) {
+        const int c = grp * 64 + jj;
+        A[jj] = (act && c < m) ? Bf[(int64_t)c * m + r] : 0.0;
+        mx = fmax(mx, fabs(A[jj]));
+    }
+    // row equilibration: the rows span many orders of magnitude (E M D_s^4 against the
+    // boundary and tension rows), which Gauss-Jordan in FP64 does not survive unscaled
+    __shared__ double rmax[2][GJ64_MAX], rscale[GJ64_MAX];
+    if (act) rmax[grp][r] = mx;
+    __syncthreads();   // (also: every load done before any thread writes the inverse)
+    if (act) {
+        const double rm = fmax(rmax[0][r], rmax[1][r]);
+        const double d = rm > 0.0 && rm < INFINITY ? 1.0 / rm : 1.0;
+#pragma unroll
+        for (int jj = 0; jj < 64; ++jj) A[jj] *= d;
+        if (grp == 0) rscale[r] = d;
+    }
+    gj_invert64(m, act, r, grp, A, sh, Bf, rscale);
 }
 
 __global__ __launch_bounds__(EB) void k_fs_finish(int64_t N, const double* X, const double* x,
@@ -571,8 +740,17 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
     STOKES_HIP(hipGetLastError());
     for (int f0 = 0; f0 < n_fib; f0 += chunk) {
         const int nb = std::min(chunk, n_fib - f0);
-        hipLaunchKernelGGL(k_fs_prep, dim3(nb), dim3(FB), 0, st, g, f0, prep);
-        hipLaunchKernelGGL(k_fs_block, dim3(nb), dim3(BLOCK_GJ), 0, st, g, f0, (const double*)prep, binv);
+        if (n <= NB64 && !nonlocal) {
+            hipLaunchKernelGGL(k_fs_block64<true>, dim3(nb), dim3(GJ64_T), 0, st, g, f0, (const double*)prep,
+                               binv);
+        } else {
+            hipLaunchKernelGGL(k_fs_prep, dim3(nb), dim3(FB), 0, st, g, f0, prep);
+            if (n <= NB64)
+                hipLaunchKernelGGL(k_fs_block64<false>, dim3(nb), dim3(GJ64_T), 0, st, g, f0,
+                                   (const double*)prep, binv);
+            else
+                hipLaunchKernelGGL(k_fs_block, dim3(nb), dim3(BLOCK_GJ), 0, st, g, f0, (const double*)prep, binv);
+        }
         STOKES_HIP(hipGetLastError());
     }
     // right-hand side: the rows of f_exp = f_ext - E s^4 D4 X with the current nodes

@@ -119,6 +119,29 @@ def test_straight_fiber_translates_and_beam_mode_decays(S):
     assert np.abs(nv @ Xg.cpu().numpy() - fac * A * phi).max() <= 1e-4 * A
 
 
+@pytest.mark.parametrize("nodes,delta", [(6, None), (16, None), (31, None), (32, None), (32, 0.05),
+                                         (20, 0.05), (40, None), (48, 0.05)])
+def test_single_fiber_block_is_the_inverse(S, oracle_mod, nodes, delta):
+    # one fiber: the block-Jacobi preconditioner is the exact inverse of the operator, so
+    # one GMRES iteration leaves only rounding amplified by the block's conditioning
+    # (~p^8 after row equilibration; a wrong inverse leaves O(1)).  With the nonlocal
+    # term the block's columns carry D4 (entries ~p^8) through a sum over the fiber's
+    # nodes, which costs another ~eps p^8 of accuracy in forming it (a preconditioner
+    # only: the solution is the operator's).  Every block path: built in place for
+    # <= 32 nodes, from the prepared products with the nonlocal term, the wide kernel
+    # above 32.
+    from oracle.timestep import FiberStep
+    fs, f = small_case(21 + nodes, 1, nodes)
+    E, dt = 1.0, 2e-3
+    St = FiberStep(fs.xyz, fs.length, nodes, fs.eps, E, dt, 1.0, delta=delta)
+    beta = np.linalg.norm(St.rhs(f) - St.apply(np.concatenate([fs.xyz.ravel(), np.zeros(nodes)])))
+    X1, T1, res, it = S.fiber_step(dev(fs.xyz), dev(fs.length), dev(f), nodes, fs.eps, E, dt,
+                                   delta=delta, iters=1)
+    bound = min(0.2 if delta else 1e-3, 1e-6 * max(1.0, (nodes / 16) ** 8) * (100.0 if delta else 1.0))
+    print(f"nodes {nodes} delta {delta}: residual after one iteration {res / beta:.2e} (bound {bound:.1e})")
+    assert it == 1 and res / beta <= bound
+
+
 def test_fiber_at_rest_stays(S):
     # a straight fiber without force: the right-hand side is rounding (D4 of a line,
     # ~eps p^8 (2/L)^4 E dt |M| |X| ~ 1e-11 here), the fiber stays where it is and carries
