@@ -150,7 +150,7 @@ constexpr int GJ64_T = 256;
 constexpr int GJ64_MAX = 128;
 
 struct Gj64Lds {
-    double col[2][GJ64_MAX], row[2][GJ64_MAX], oh[2][GJ64_MAX];
+    double col[2][GJ64_MAX], row[2][GJ64_MAX], oh[2][GJ64_MAX], kv[2][GJ64_MAX];
     unsigned wk[2][GJ64_T / 64];
     int perm[GJ64_MAX], dest[GJ64_MAX];
 };
@@ -163,9 +163,9 @@ struct Gj64Lds {
 // A^-1[pi^-1(a)][pi(b)] = S[a][b].  The pivot loop has no branches on the column
 // index: rows are padded with zeros to 128 columns, the pivot column is a one-hot
 // vector oh in LDS, a thread's entry in column p is sum_jj A[jj] oh[c], and the update
-// is A <- A ks (1 - oh[c]) - (a_rp / a_pp) row[c] with row carrying 1 at column p (ks = 0
-// and a_rp = -1 on the pivot row).  The LDS vectors alternate between two buffers by
-// the parity of p, so one pivot step needs two barriers.
+// is A <- A kv[c] - (a_rp / a_pp) row[c] with kv = 1 - oh and row carrying 1 at column p
+// (the pivot row starts from 0 with a_rp = -1).  The LDS vectors alternate between two
+// buffers by the parity of p, so one pivot step needs two barriers.
 // ds as for gj_invert.
 __device__ __forceinline__ void gj_invert64(int m, bool act, int r, int g, double (&A)[64], Gj64Lds& s,
                                             double* X, const double* ds = nullptr) {
@@ -173,6 +173,8 @@ __device__ __forceinline__ void gj_invert64(int m, bool act, int r, int g, doubl
     if (t < GJ64_MAX) {
         s.oh[0][t] = t == 0 ? 1.0 : 0.0;
         s.oh[1][t] = 0.0;
+        s.kv[0][t] = t == 0 ? 0.0 : 1.0;
+        s.kv[1][t] = 1.0;
     }
     bool used = false;
     __syncthreads();
@@ -205,27 +207,35 @@ __device__ __forceinline__ void gj_invert64(int m, bool act, int r, int g, doubl
         if (t == 0) {
             s.perm[p] = pr;
             double* on = s.oh[b ^ 1];       // next pivot's one-hot (last read at p - 1)
-            if (p >= 1) on[p - 1] = 0.0;
-            if (p + 1 < m) on[p + 1] = 1.0;
+            double* kn = s.kv[b ^ 1];
+            if (p >= 1) {
+                on[p - 1] = 0.0;
+                kn[p - 1] = 1.0;
+            }
+            if (p + 1 < m) {
+                on[p + 1] = 1.0;
+                kn[p + 1] = 0.0;
+            }
         }
         const bool piv = act && r == pr;
-        if (piv) {
+        if (piv) {          // publish the pivot row (1 at column p), then start it from 0
 #pragma unroll
             for (int jj = 0; jj < 64; ++jj) {
                 const double o = oh[g * 64 + jj];
                 s.row[b][g * 64 + jj] = fma(A[jj], 1.0 - o, o);
+                A[jj] = 0.0;
             }
             used = true;
         }
         __syncthreads();
         const double inv = 1.0 / s.col[b][pr];
         const double crinv = (piv ? -1.0 : s.col[b][r]) * inv;
-        const double ks = piv ? 0.0 : 1.0;
+        const double* kv = s.kv[b];
         if (act) {
 #pragma unroll
             for (int jj = 0; jj < 64; ++jj) {
                 const int c = g * 64 + jj;
-                A[jj] = fma(A[jj], ks * (1.0 - oh[c]), -crinv * s.row[b][c]);
+                A[jj] = fma(A[jj], kv[c], -crinv * s.row[b][c]);
             }
         }
     }

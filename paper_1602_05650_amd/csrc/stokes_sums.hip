@@ -151,19 +151,35 @@ __global__ void excl_fiber_kernel(int64_t n_t, const int32_t* __restrict__ tfib,
 }
 
 // out = (accumulate ? out : 0) + sum_k partial[k]  (+ jump term), chunk order fixed.
-__global__ void reduce_kernel(int64_t n_t, int32_t n_chunks, const double* __restrict__ partial,
-                              int accumulate, double* out, int64_t out_stride,
-                              const int2* __restrict__ excl, const double* __restrict__ q,
-                              int64_t n_s, double jump) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_t) return;
+// Sum of the chunk partials per target (plus the double layer's jump term).  A
+// workgroup takes 64 targets with four threads each: thread slice sl sums chunks
+// sl, sl + 4, ... in order, and the four slice sums are added in a fixed order, so the
+// result does not depend on the launch.
+constexpr int RED_T = 64, RED_S = 4;
+__global__ __launch_bounds__(RED_T * RED_S) void reduce_kernel(int64_t n_t, int32_t n_chunks,
+                                                              const double* __restrict__ partial,
+                                                              int accumulate, double* out, int64_t out_stride,
+                                                              const int2* __restrict__ excl,
+                                                              const double* __restrict__ q, int64_t n_s,
+                                                              double jump) {
+    __shared__ double part[RED_S - 1][3][RED_T];
+    const int tx = threadIdx.x % RED_T, sl = threadIdx.x / RED_T;
+    const int64_t i = (int64_t)blockIdx.x * RED_T + tx;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < n_chunks; ++k) {
-        const double* p = partial + (int64_t)k * 3 * n_t;
-        v[0] += p[i];
-        v[1] += p[n_t + i];
-        v[2] += p[2 * n_t + i];
+    if (i < n_t) {
+        for (int k = sl; k < n_chunks; k += RED_S) {
+            const double* p = partial + (int64_t)k * 3 * n_t;
+            v[0] += p[i];
+            v[1] += p[n_t + i];
+            v[2] += p[2 * n_t + i];
+        }
     }
+    if (sl > 0)
+        for (int c = 0; c < 3; ++c) part[sl - 1][c][tx] = v[c];
+    __syncthreads();
+    if (sl > 0 || i >= n_t) return;
+    for (int s2 = 0; s2 < RED_S - 1; ++s2)
+        for (int c = 0; c < 3; ++c) v[c] += part[s2][c][tx];
     if (q && excl) {
         const int2 e = excl[i];
         if (e.y > e.x) {
@@ -177,6 +193,8 @@ __global__ void reduce_kernel(int64_t n_t, int32_t n_chunks, const double* __res
         *o = accumulate ? *o + v[c] : v[c];
     }
 }
+
+inline unsigned red_blocks(int64_t n_t) { return (unsigned)((n_t + RED_T - 1) / RED_T); }
 
 __global__ void zero_u64_kernel(unsigned long long* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
@@ -351,7 +369,7 @@ static int sl_core(const SLProblem& p, const Partition& P, const SumScratch& S, 
         prof_end(st);
         STOKES_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(reduce_kernel, dim3(nblk(p.n_t)), dim3(256), 0, st, p.n_t, P.n_chunks,
+    hipLaunchKernelGGL(reduce_kernel, dim3(red_blocks(p.n_t)), dim3(RED_T * RED_S), 0, st, p.n_t, P.n_chunks,
                        S.partial, p.accumulate ? 1 : 0, p.u, p.n_t, (const int2*)nullptr,
                        (const double*)nullptr, (int64_t)0, 0.0);
     STOKES_HIP(hipGetLastError());
@@ -598,7 +616,7 @@ extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double
         launch_dl_kernel(mixed, sub, grid, a, st);
         prof_end(st);
     }
-    hipLaunchKernelGGL(reduce_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, P.n_chunks,
+    hipLaunchKernelGGL(reduce_kernel, dim3(red_blocks(n_t)), dim3(RED_T * RED_S), 0, st, n_t, P.n_chunks,
                        S.partial, (flags & STOKES_ACCUMULATE) ? 1 : 0, u_out, n_t,
                        (const int2*)S.excl, sub ? src_q : (const double*)nullptr, n_src, -0.5);
     STOKES_HIP(hipGetLastError());
