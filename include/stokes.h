@@ -261,9 +261,10 @@ int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xy
  * flags      STOKES_PREC_* for the u_bar sums, STOKES_NO_DOUBLET, STOKES_NONLOCAL.
  * xyz_out    [3*N] X+ (must not alias xyz or f_ext).   T_out [N] T+ at the nodes.
  * resid_out, iters_out   NULL or host: final least-squares residual, iterations.
- * All arrays are DEVICE pointers.  The call allocates its own scratch (about
- * (16 n + 3 iters + 30) N doubles plus 37 n^2 per fiber of a 512-fiber chunk) and is
- * synchronous.
+ * All arrays are DEVICE pointers.  The call is synchronous.  Its device memory, about
+ * (16 n + 3 iters + 30) N doubles plus 37 n^2 per fiber of a 512-fiber chunk, is kept
+ * per (device, stream) for the next call and released by stokes_release_workspace;
+ * calls on one stream must therefore not overlap.
  */
 int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
                       const double* fiber_len, const double* f_ext, double eps, double E,

@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "cheb_tables.hpp"
@@ -174,13 +175,19 @@ __global__ __launch_bounds__(EB) void k_fs_smooth(Geo g, const double* f, double
 // The rows of one fiber per workgroup.  rhs = false: the operator on z with f = F z and
 // vr = R[f].  rhs = true: the right-hand side with f = f_ext - E s^4 D4 X, vr = R[f],
 // fe = f_ext, and the current nodes in the place of z (boundary defects, h(X, 0)).
-__global__ __launch_bounds__(FB) void k_fs_rows(Geo g, const double* z, const double* f, const double* vr,
-                                                const double* fe, bool rhs, double* w) {
-    __shared__ double pk[3][MAX_NPF], hk[MAX_NPF];
-    const int n = g.n, fi = blockIdx.x, t = threadIdx.x;
-    const int64_t N = g.N, f0 = (int64_t)fi * n;
-    const double s = 2.0 / g.flen[fi], E = g.E;
-    if (t < n) {
+constexpr int ROWS_FPB = 4;   // fibers per workgroup of k_fs_rows (64 threads each)
+__global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* z, const double* f,
+                                                           const double* vr, const double* fe, bool rhs,
+                                                           double* w) {
+    __shared__ double pk_all[ROWS_FPB][3][MAX_NPF], hk_all[ROWS_FPB][MAX_NPF];
+    const int n = g.n, fl = threadIdx.x / 64, t = threadIdx.x % 64;
+    const int fi = blockIdx.x * ROWS_FPB + fl;
+    const bool live = fi < g.nf;
+    double(*pk)[MAX_NPF] = pk_all[fl];
+    double* hk = hk_all[fl];
+    const int64_t N = g.N, f0 = (int64_t)(live ? fi : 0) * n;
+    const double s = 2.0 / g.flen[live ? fi : 0], E = g.E;
+    if (live && t < n) {
         const int64_t i = f0 + t;
         const double* d1 = g.D1 + t * n;
         const double* d2 = g.D2 + t * n;
@@ -241,7 +248,8 @@ __global__ __launch_bounds__(FB) void k_fs_rows(Geo g, const double* z, const do
         hk[t] = h;
     }
     __syncthreads();
-    for (int r = t; r < 4 * n; r += FB) {
+    if (!live) return;
+    for (int r = t; r < 4 * n; r += 64) {
         double out = 0.0;
         int64_t dst;
         if (r < 3 * n) {
@@ -612,14 +620,70 @@ __global__ __launch_bounds__(EB) void k_fs_finish(int64_t N, const double* X, co
 
 inline unsigned grid_e(int64_t n) { return (unsigned)((n + EB - 1) / EB); }
 
-struct DevBuf {
+// Device memory of the step, kept per (device, stream) between calls: a call is
+// synchronous, so the next call on the same stream may reuse it.  tab_n records the
+// nodes per fiber whose tables sit at the start of the buffer.
+struct StepBuf {
+    int dev = 0;
+    hipStream_t st = nullptr;
     void* p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
+    size_t bytes = 0;
+    int tab_n = 0;
 };
+static std::mutex g_step_mu;
+static std::vector<StepBuf> g_step_bufs;
+
+static int step_buffer(hipStream_t st, size_t bytes, StepBuf* out) {
+    int dev = 0;
+    STOKES_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_step_mu);
+    for (auto& b : g_step_bufs)
+        if (b.dev == dev && b.st == st) {
+            if (b.bytes < bytes) {
+                STOKES_HIP(hipFree(b.p));
+                b.p = nullptr;
+                b.bytes = 0;
+                b.tab_n = 0;
+                STOKES_HIP(hipMalloc(&b.p, bytes));
+                b.bytes = bytes;
+            }
+            *out = b;
+            return STOKES_OK;
+        }
+    StepBuf b;
+    b.dev = dev;
+    b.st = st;
+    STOKES_HIP(hipMalloc(&b.p, bytes));
+    b.bytes = bytes;
+    g_step_bufs.push_back(b);
+    *out = b;
+    return STOKES_OK;
+}
+
+static void step_tables_loaded(hipStream_t st, int n) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_step_mu);
+    for (auto& b : g_step_bufs)
+        if (b.dev == dev && b.st == st) b.tab_n = n;
+}
 
 }  // namespace fs
+
+// Frees the step buffers (called by stokes_release_workspace after a device sync).
+void fiberstep_release() {
+    std::lock_guard<std::mutex> lk(fs::g_step_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& b : fs::g_step_bufs) {
+        (void)hipSetDevice(b.dev);
+        (void)hipDeviceSynchronize();
+        if (b.p) (void)hipFree(b.p);
+    }
+    (void)hipSetDevice(cur);
+    fs::g_step_bufs.clear();
+}
+
 }  // namespace stokes
 
 using namespace stokes;
@@ -661,8 +725,6 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
     const int m = 4 * n;
     const int64_t n_vec = (4 * N + 2) / 3, nv3 = 3 * n_vec;
     const int chunk = std::min(n_fib, PREP_CHUNK);
-    const cheb::Tables tab = cheb::build(n);
-
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -676,18 +738,21 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
                  o_fib = take(N * 4), o_f = take(3 * N * 8), o_v = take(3 * N * 8), o_rhs = take(nv3 * 8),
                  o_binv = take((size_t)n_fib * m * m * 8), o_prep = take((size_t)chunk * prep_doubles(n) * 8),
                  o_slot = take(vector_plan_bytes(n_vec, iters));
-    DevBuf buf;
-    STOKES_HIP(hipMalloc(&buf.p, off));
+    StepBuf buf;
+    int rc0 = step_buffer(st, off, &buf);
+    if (rc0) return rc0;
     char* base = static_cast<char*>(buf.p);
     auto at = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
     double* dtab = at(o_tab);
-    {
+    if (buf.tab_n != n) {
+        const cheb::Tables tab = cheb::build(n);
         std::vector<double> h;
         h.reserve(4 * n * n + 2 * n * n);
         for (const auto* v : {&tab.D1, &tab.D2, &tab.D3, &tab.D4, &tab.P4, &tab.P2})
             h.insert(h.end(), v->begin(), v->end());
         STOKES_HIP(hipMemcpyAsync(dtab, h.data(), h.size() * 8, hipMemcpyHostToDevice, st));
         STOKES_HIP(hipStreamSynchronize(st));   // h is a pageable host buffer
+        step_tables_loaded(st, n);
     }
     double *Xa = at(o_Xa), *tan = at(o_tan), *wq = at(o_wq), *sarc = at(o_sarc), *fbuf = at(o_f),
            *vbuf = at(o_v), *rhs = at(o_rhs), *binv = at(o_binv), *prep = at(o_prep), *xss = at(o_xss),
@@ -760,7 +825,8 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
     STOKES_HIP(hipGetLastError());
     int rc = smooth_velocity(fbuf, vbuf);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_fs_rows, dim3(n_fib), dim3(FB), 0, st, g, xyz, (const double*)fbuf,
+    const unsigned rows_grid = (unsigned)((n_fib + ROWS_FPB - 1) / ROWS_FPB);
+    hipLaunchKernelGGL(k_fs_rows, dim3(rows_grid), dim3(64 * ROWS_FPB), 0, st, g, xyz, (const double*)fbuf,
                        (const double*)vbuf, f_ext, true, rhs);
     STOKES_HIP(hipGetLastError());
 
@@ -772,8 +838,8 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
         STOKES_HIP(hipGetLastError());
         const int r2 = smooth_velocity(fbuf, vbuf);
         if (r2) return r2;
-        hipLaunchKernelGGL(k_fs_rows, dim3(n_fib), dim3(FB), 0, st, g, (const double*)z, (const double*)fbuf,
-                           (const double*)vbuf, (const double*)nullptr, false, w);
+        hipLaunchKernelGGL(k_fs_rows, dim3(rows_grid), dim3(64 * ROWS_FPB), 0, st, g, (const double*)z,
+                           (const double*)fbuf, (const double*)vbuf, (const double*)nullptr, false, w);
         STOKES_HIP(hipGetLastError());
         return STOKES_OK;
     };

@@ -37,6 +37,8 @@ struct Workspace {
     void* host = nullptr;      // small pinned host buffer for status read-back
 };
 int workspace_get(hipStream_t stream, size_t bytes, Workspace** out);
+// Frees the implicit time step's cached device buffers (stokes_release_workspace).
+void fiberstep_release();
 
 // Bump allocator over a workspace buffer (256-byte aligned slices).
 struct Carve {

@@ -202,6 +202,7 @@ extern "C" int stokes_release_workspace(void) {
         delete ws;
     }
     g_ws.clear();
+    fiberstep_release();
     if (rc) set_error("stokes_release_workspace: device synchronisation failed");
     return rc;
 }

@@ -142,6 +142,24 @@ def test_single_fiber_block_is_the_inverse(S, oracle_mod, nodes, delta):
     assert it == 1 and res / beta <= bound
 
 
+def test_buffers_reused_across_calls(S):
+    # the step keeps its device buffer per stream: calls of other sizes in between, and a
+    # release of every workspace, leave the result of the same input bitwise unchanged
+    fs1, f1 = small_case(31, 4, 16)
+    fs2, f2 = small_case(32, 3, 32)
+
+    def run(fs, f, n):
+        X, T, res, it = S.fiber_step(dev(fs.xyz), dev(fs.length), dev(f), n, fs.eps, 1.0, 2e-3, iters=12)
+        return X.cpu().numpy(), T.cpu().numpy()
+    a = run(fs1, f1, 16)
+    run(fs2, f2, 32)             # larger: the buffer grows, the tables change
+    b = run(fs1, f1, 16)
+    S.release_workspace()
+    c = run(fs1, f1, 16)
+    for u in (b, c):
+        assert np.array_equal(u[0], a[0]) and np.array_equal(u[1], a[1])
+
+
 def test_fiber_at_rest_stays(S):
     # a straight fiber without force: the right-hand side is rounding (D4 of a line,
     # ~eps p^8 (2/L)^4 E dt |M| |X| ~ 1e-11 here), the fiber stays where it is and carries
