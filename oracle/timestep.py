@@ -42,9 +42,15 @@ first-kind Chebyshev points (the node values interpolated there) and completed b
 X_ss = 0 and X_sss = 0 at both ends; the tension equation is collocated at the n - 2
 first-kind points and completed by T = 0 at both ends (eq. bc-free).
 
+A fiber may instead have its minus end (s = 0) clamped to a body at rest: with U = Ω = 0,
+eq. BC2-1 and eq. BC2-2 keep that end's position and tangent (X+ = X, X+_s = X_s there),
+and eq. BC2-T, the tangential component of the same velocity condition, becomes
+t . V[f+ + f_ext] = 0 at the end, with t . f+ written as in the tension equation.
+
 Row layout of the operator (3 N position rows, then N tension rows, fiber by fiber):
 position rows of a fiber = its n - 4 collocated rows, then X_ss(s=L), X_sss(s=L),
-X_ss(s=0), X_sss(s=0); tension rows = its n - 2 collocated rows, then T(s=L), T(s=0).
+X_ss(s=0), X_sss(s=0) (clamped: X+(s=0), X+_s(s=0)); tension rows = its n - 2
+collocated rows, then T(s=L), T(s=0) (clamped: -t . V[f+](s=0)).
 """
 from __future__ import annotations
 
@@ -103,7 +109,8 @@ class FiberStep:
     eps, bending modulus E, step dt, viscosity mu, optional nonlocal term (delta), and
     the source doublet in the other fibers' flow (doublet)."""
 
-    def __init__(self, X, L, npf, eps, E, dt, mu=1.0, delta=None, doublet=True, nthreads=1):
+    def __init__(self, X, L, npf, eps, E, dt, mu=1.0, delta=None, doublet=True, nthreads=1,
+                 clamp=None):
         self.X = np.asarray(X, dtype=np.float64)
         self.L = np.asarray(L, dtype=np.float64)
         self.npf, self.eps, self.E, self.dt, self.mu = npf, eps, E, dt, mu
@@ -112,6 +119,8 @@ class FiberStep:
         self.nf = self.N // npf
         assert self.nf * npf == self.N and self.L.size == self.nf and npf >= 6
         self.fib = np.repeat(np.arange(self.nf), npf)
+        self.clamp = np.zeros(self.nf, bool) if clamp is None else np.asarray(clamp, bool).ravel()
+        assert self.clamp.size == self.nf
         p = npf - 1
         self.Da = cheb_diff(p)
         self.P4 = cheb_resample(p, npf - 4)
@@ -231,22 +240,40 @@ class FiberStep:
         pos = Xp / self.dt - self.local_velocity(f) - (vr := self.smooth_velocity(f, others))
         ten = -(self.tension_local(Xp, T) + self.t_dot_ds(vr))
         p = self.npf - 1
+        s1 = self.per_fiber(self.Da, Xp, 1)
         s2 = self.per_fiber(self.D2, Xp, 2)
         s3 = self.per_fiber(self.D3, Xp, 3)
+        # clamped minus end: t . V[f+] there, with t . f+ = 3 E X_ss . X+_sss + T_s
+        tf = 3.0 * self.E * np.sum(self.Xss * s3, axis=0) + self.per_fiber(self.Da, T[None, :], 1)[0]
+        tv = self.c * tf + np.sum(self.tangent * vr, axis=0)
         bc_pos = np.zeros((3, 4 * self.nf))
         bc_ten = np.zeros(2 * self.nf)
         for m in range(self.nf):
             o = m * self.npf
-            bc_pos[:, 4 * m:4 * m + 4] = np.stack([s2[:, o], s3[:, o], s2[:, o + p], s3[:, o + p]],
-                                                  axis=1)
-            bc_ten[2 * m:2 * m + 2] = [T[o], T[o + p]]
+            if self.clamp[m]:
+                bc_pos[:, 4 * m:4 * m + 4] = np.stack([s2[:, o], s3[:, o], Xp[:, o + p], s1[:, o + p]], axis=1)
+                bc_ten[2 * m:2 * m + 2] = [T[o], -tv[o + p]]
+            else:
+                bc_pos[:, 4 * m:4 * m + 4] = np.stack([s2[:, o], s3[:, o], s2[:, o + p], s3[:, o + p]],
+                                                      axis=1)
+                bc_ten[2 * m:2 * m + 2] = [T[o], T[o + p]]
         return self._assemble(pos, ten, bc_pos, bc_ten)
 
     def rhs(self, fext):
         v = self.velocity(np.asarray(fext, dtype=np.float64))
         pos = self.X / self.dt + v
         ten = self.t_dot_ds(v)
-        return self._assemble(pos, ten, np.zeros((3, 4 * self.nf)), np.zeros(2 * self.nf))
+        bc_pos = np.zeros((3, 4 * self.nf))
+        bc_ten = np.zeros(2 * self.nf)
+        p = self.npf - 1
+        tv = np.sum(self.tangent * v, axis=0)
+        for m in range(self.nf):
+            if self.clamp[m]:     # the end keeps its position and tangent, and no tangential velocity
+                o = m * self.npf
+                bc_pos[:, 4 * m + 2] = self.X[:, o + p]
+                bc_pos[:, 4 * m + 3] = self.Xs[:, o + p]
+                bc_ten[2 * m + 1] = tv[o + p]
+        return self._assemble(pos, ten, bc_pos, bc_ten)
 
     def self_blocks(self):
         """Per fiber, the operator without the other fibers' flow as a 4n x 4n matrix
@@ -255,7 +282,7 @@ class FiberStep:
         blocks = []
         for m in range(self.nf):
             sub = type(self)(self.X[:, m * n:(m + 1) * n], self.L[m:m + 1], n, self.eps, self.E,
-                            self.dt, self.mu, self.delta, self.doublet)
+                             self.dt, self.mu, self.delta, self.doublet, clamp=self.clamp[m:m + 1])
             blocks.append(np.stack([sub.apply(e, others=False) for e in np.eye(4 * n)], axis=1))
         return blocks
 
@@ -276,7 +303,7 @@ class FiberStep:
         return Pinv
 
 
-def fiber_step(X, L, npf, eps, E, dt, fext, iters, mu=1.0, delta=None, doublet=True):
+def fiber_step(X, L, npf, eps, E, dt, fext, iters, mu=1.0, delta=None, doublet=True, clamp=None):
     """One step by right-preconditioned GMRES with the fiber block-Jacobi preconditioner
     (section "Linear solver and preconditioner").  The unknown is the increment
     (X+ - X, T+): the same linear system shifted by the current geometry,
@@ -284,7 +311,7 @@ def fiber_step(X, L, npf, eps, E, dt, fext, iters, mu=1.0, delta=None, doublet=T
     with the coordinates (the operator amplifies node rounding by up to p^10 through the
     tension rows).  Returns (X+ (3, N), T+ (N,), residual history, iterations)."""
     from oracle import gmres
-    S = FiberStep(X, L, npf, eps, E, dt, mu, delta, doublet)
+    S = FiberStep(X, L, npf, eps, E, dt, mu, delta, doublet, clamp=clamp)
     N = S.N
     b = S.rhs(fext) - S.apply(np.concatenate([S.X.ravel(), np.zeros(N)]))
     y, hist, m = gmres(S.apply, b, iters, S.precond(S.self_blocks()))

@@ -10,6 +10,10 @@ mechanics fixes.
   cosh(bL) = 1) relaxes in one backward-Euler step by the factor 1/(1 + dt M_nn E b^4).
 * At small dt the tension of a planar curve solves the arclength-reduced tension
   equation (a two-point problem solved by scipy).
+* A minus end clamped to a body at rest (eq. BC2-1, BC2-2, BC2-T) keeps its position
+  and tangent; a clamped straight fiber under a tangential load does not move and its
+  tension is the load beyond s; clamped-free beam modes (cos(bL) cosh(bL) = -1) relax
+  by 1/(1 + dt M_nn E b^4).
 * The step is consistent (one step against two half steps: local error of order above
   one), changes the length by a small fraction of the motion, and is covariant under rotations; fibers far apart decouple; on several
   fibers the block-preconditioned GMRES reaches the dense solution.
@@ -180,6 +184,58 @@ def test_tension_of_a_planar_curve_at_small_dt(oracle_mod, amp):
     assert np.abs(ref).max() > 0.05
     assert np.abs(T - ref).max() <= 1e-5 * np.abs(ref).max()
     assert np.abs(Xp - X).max() <= 1e-6
+def test_clamped_straight_fiber_holds_a_tangential_load(oracle_mod):
+    # clamped at s = 0, pulled along itself: it cannot move, and the tension carries the
+    # load of the part beyond s, T(s) = int_s^L g (eq. BC2-1, BC2-2, BC2-T with U = Omega = 0)
+    p, L, eps, mu, E, dt = 20, 1.4, 0.02, 0.8, 1.3, 2e-3
+    X, t = straight(p, L, [0.5, -1.0, 0.3], [0.1, 0.0, 0.2])
+    s = 0.5 * L * (1 + cgl(p))
+    g = s ** 2 - 0.3 * s + 0.2
+    G = lambda x: x ** 3 / 3 - 0.15 * x ** 2 + 0.2 * x
+    Xp, T, h, m = oracle_mod.fiber_step(X, np.array([L]), p + 1, eps, E, dt, g[None, :] * t[:, None], 8, mu,
+                                        clamp=[True])
+    ref = G(L) - G(s)
+    assert np.abs(T - ref).max() <= 1e-8 * np.abs(ref).max()
+    assert np.abs(Xp - X).max() <= 1e-10
+
+
+def test_clamped_end_keeps_position_and_tangent(oracle_mod):
+    p, L, eps, mu, E, dt = 24, 1.0, 0.01, 1.0, 0.7, 5e-3
+    X = bent(p, L)
+    fE = np.random.default_rng(2).standard_normal((3, p + 1))
+    Xp, T, h, m = oracle_mod.fiber_step(X, np.array([L]), p + 1, eps, E, dt, fE, 12, mu, clamp=[True])
+    D = oracle_mod.cheb_diff(p)
+    assert np.abs(Xp - X).max() > 1e-4                            # the fiber moves
+    assert np.abs(Xp[:, p] - X[:, p]).max() <= 1e-12              # the clamped node does not
+    assert np.abs((Xp - X) @ D[p]).max() <= 1e-10                 # nor its tangent
+    Xf, _, _, _ = oracle_mod.fiber_step(X, np.array([L]), p + 1, eps, E, dt, fE, 12, mu)
+    assert np.abs(Xf[:, p] - X[:, p]).max() > 1e-4                # free, the same end moves
+
+
+def clamped_mode(bL, x, L):
+    b = bL / L
+    sig = (math.cosh(bL) + math.cos(bL)) / (math.sinh(bL) + math.sin(bL))
+    return np.cosh(b * x) - np.cos(b * x) - sig * (np.sinh(b * x) - np.sin(b * x))
+
+
+@pytest.mark.parametrize("bL", [1.8751040687119611, 4.694091132974175])
+def test_clamped_free_beam_mode_decay(oracle_mod, bL):
+    assert abs(math.cos(bL) * math.cosh(bL) + 1) < 1e-9
+    # (amplitude 1e-5: rounding of this system, ~1e-10 absolute at 32 nodes, stays well
+    # below the bound, and the neglected nonlinear terms are O(A) relative)
+    p, L, eps, mu, E, dt, A = 31, 1.1, 0.01, 0.9, 1.5, 2e-2, 1e-5
+    X0, t = straight(p, L, [0.2, 0.9, 0.4], [0.0, 0.0, 0.0])
+    nv = normal_to(t)
+    s = 0.5 * L * (1 + cgl(p))                                    # s = 0 is the clamped end
+    X = X0 + A * clamped_mode(bL, s, L)[None, :] * nv[:, None]
+    Xp, T, h, m = oracle_mod.fiber_step(X, np.array([L]), p + 1, eps, E, dt, np.zeros((3, p + 1)), 8, mu,
+                                        clamp=[True])
+    _, Mnn = m_coeffs(eps, mu)
+    factor = 1.0 / (1.0 + dt * Mnn * E * (bL / L) ** 4)
+    assert 0.05 < factor < 0.95
+    assert np.abs(nv @ Xp - factor * A * clamped_mode(bL, s, L)).max() <= 1e-3 * A
+
+
 def rot(axis, ang):
     a = np.asarray(axis, float) / np.linalg.norm(axis)
     K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
@@ -258,6 +314,10 @@ TS_MUTANTS = {
     "rhs_position_dropped": ("pos = self.X / self.dt + v", "pos = v"),
     "resample_points": ("(2.0 * np.arange(m) + 1.0) * np.pi / (2.0 * m)", "(2.0 * np.arange(m) + 0.5) * np.pi / (2.0 * m)"),
     "self_not_excluded": ("excl=oracle.EXCL_SAME_FIBER", "excl=0"),
+    "clamp_value_row": ("[s2[:, o], s3[:, o], Xp[:, o + p], s1[:, o + p]]", "[s2[:, o], s3[:, o], Xp[:, o + p - 1], s1[:, o + p]]"),
+    "clamp_tangent_row": ("[s2[:, o], s3[:, o], Xp[:, o + p], s1[:, o + p]]", "[s2[:, o], s3[:, o], Xp[:, o + p], s2[:, o + p]]"),
+    "clamp_tension_sign": ("bc_ten[2 * m:2 * m + 2] = [T[o], -tv[o + p]]", "bc_ten[2 * m:2 * m + 2] = [T[o], tv[o + p]]"),
+    "clamp_tension_local": ("tv = self.c * tf + np.sum(self.tangent * vr, axis=0)", "tv = self.alpha * tf + np.sum(self.tangent * vr, axis=0)"),
     "explicit_dt_velocity": ("pos = Xp / self.dt - self.local_velocity(f)", "pos = Xp / self.dt - 0.5 * self.local_velocity(f)"),
 }
 
