@@ -65,9 +65,12 @@ struct Geo {
     const double* D4;
     const double* P4;     // (n - 4) x n
     const double* P2;     // (n - 2) x n
+    const int32_t* clamp; // [nf] or null: nonzero = minus end clamped to a body at rest
     double E, dt, mu, kappa, pref, delta;
     bool nonlocal;
 };
+
+__device__ __forceinline__ bool clamped(const Geo& g, int f) { return g.clamp && g.clamp[f] != 0; }
 
 __global__ __launch_bounds__(EB) void k_fs_geom(Geo g, double* Xa, double* tan, double* wq,
                                                 double* sarc, int32_t* fib, double* xss, double* xsss,
@@ -179,7 +182,7 @@ constexpr int ROWS_FPB = 4;   // fibers per workgroup of k_fs_rows (64 threads e
 __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* z, const double* f,
                                                            const double* vr, const double* fe, bool rhs,
                                                            double* w) {
-    __shared__ double pk_all[ROWS_FPB][3][MAX_NPF], hk_all[ROWS_FPB][MAX_NPF];
+    __shared__ double pk_all[ROWS_FPB][3][MAX_NPF], hk_all[ROWS_FPB][MAX_NPF], cl_all[ROWS_FPB];
     const int n = g.n, fl = threadIdx.x / 64, t = threadIdx.x % 64;
     const int fi = blockIdx.x * ROWS_FPB + fl;
     const bool live = fi < g.nf;
@@ -227,9 +230,15 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
             const double av = al * f[c * N + i] + be * tv[c] * tfv + vr[c * N + i];   // V[f] at the node
             pk[c][t] = rhs ? av : z[c * N + i] / g.dt - av;
         }
-        double h;
+        double h, tvr = 0.0;
+        for (int c = 0; c < 3; ++c) tvr = fma(tv[c], vr[c * N + i], tvr);
         if (rhs) {   // h(X, 0) + t . D_s (A f_ext) + t . D_s R[f_exp]
             h = g.cs[i] * 3.0 * E * ss3 + g.cc[i] * 3.0 * E * (sss3 + ss4) + al * E * ss4 + tdl + tdv;
+            if (t == n - 1) {   // clamped end: c (t . f_ext + 3 E X_ss . X_sss) + t . R[f_exp]
+                double tfe = 0.0;
+                for (int c = 0; c < 3; ++c) tfe = fma(tv[c], fe[c * N + i], tfe);
+                cl_all[fl] = g.cc[i] * (tfe + 3.0 * E * ss3) + tvr;
+            }
         } else {
             const double* zT = z + 3 * N + f0;
             double Ts = 0.0, Tss = 0.0;
@@ -244,11 +253,13 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
             ssf = -E * ss4 + k2 * zT[t];
             const double tf = 3.0 * E * ss3 + Ts, tf_s = 3.0 * E * (sss3 + ss4) + Tss;
             h = -(g.cs[i] * tf + g.cc[i] * tf_s - al * ssf + tdv);
+            if (t == n - 1) cl_all[fl] = -(g.cc[i] * tf + tvr);   // clamped end: -t . V[f]
         }
         hk[t] = h;
     }
     __syncthreads();
     if (!live) return;
+    const bool clamp = clamped(g, fi);
     for (int r = t; r < 4 * n; r += 64) {
         double out = 0.0;
         int64_t dst;
@@ -261,11 +272,23 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
             } else {
                 const int b = j - (n - 4);                    // X_ss(L), X_sss(L), X_ss(0), X_sss(0)
                 const int node = b < 2 ? 0 : n - 1;
-                const double* dm = ((b & 1) ? g.D3 : g.D2) + node * n;
-                const double sc = (b & 1) ? s * s * s : s * s;
                 const double* u = z + c * N + f0;
-                for (int k = 0; k < n; ++k) out = fma(dm[k], u[k] - u[0], out);
-                out *= rhs ? -sc : sc;
+                if (clamp && b >= 2) {                        // clamped: dX(0), D_s dX(0); rhs 0
+                    if (!rhs) {
+                        if (b == 2) {
+                            out = u[n - 1];
+                        } else {
+                            const double* d1 = g.D1 + (n - 1) * n;
+                            for (int k = 0; k < n; ++k) out = fma(d1[k], u[k] - u[0], out);
+                            out *= s;
+                        }
+                    }
+                } else {
+                    const double* dm = ((b & 1) ? g.D3 : g.D2) + node * n;
+                    const double sc = (b & 1) ? s * s * s : s * s;
+                    for (int k = 0; k < n; ++k) out = fma(dm[k], u[k] - u[0], out);
+                    out *= rhs ? -sc : sc;
+                }
             }
         } else {
             const int j = r - 3 * n;
@@ -273,6 +296,8 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
             if (j < n - 2) {
                 const double* p2 = g.P2 + j * n;
                 for (int k = 0; k < n; ++k) out = fma(p2[k], hk[k], out);
+            } else if (clamp && j == n - 1) {
+                out = cl_all[fl];
             } else if (!rhs) {
                 out = z[3 * N + f0 + (j == n - 2 ? 0 : n - 1)];
             }
@@ -396,6 +421,25 @@ __global__ __launch_bounds__(FB) void k_fs_prep(Geo g, int f_begin, double* scra
     }
 }
 
+// t . V of one unknown at the minus end (node n - 1) of fiber f: c (t . f) with
+// t . f = 3 E X_ss . X_sss (unit increment) or T_s (unit tension), plus the smooth part
+// t . Vm when Vm (the prepared smooth self velocity, 3n x 4n) is given.
+__device__ double clamp_entry(const Geo& g, int f, int c, const double* Vm, double s) {
+    const int n = g.n, m = 4 * n, n3 = 3 * n, p = n - 1;
+    const int64_t N = g.N, i = (int64_t)f * n + p;
+    double tf;
+    if (c < n3) {
+        const int ce = c / n, kc = c - ce * n;
+        tf = 3.0 * g.E * g.xss[ce * N + i] * s * s * s * g.D3[p * n + kc];
+    } else {
+        tf = s * g.D1[p * n + (c - n3)];
+    }
+    double v = g.cc[i] * tf;
+    if (Vm)
+        for (int b = 0; b < 3; ++b) v = fma(g.tan[b * N + i], Vm[(int64_t)(b * n + p) * m + c], v);
+    return v;
+}
+
 // Entries of the self block of each fiber of a chunk (rows as k_fs_rows, columns the
 // unknowns dX_x, dX_y, dX_z, T of the fiber's nodes), inverted into binv.
 __global__ __launch_bounds__(BLOCK_GJ) void k_fs_block(Geo g, int f_begin, const double* scratch,
@@ -403,8 +447,10 @@ __global__ __launch_bounds__(BLOCK_GJ) void k_fs_block(Geo g, int f_begin, const
     __shared__ GjLds sh;
     const int n = g.n, m = 4 * n, n3 = 3 * n, f = f_begin + blockIdx.x, t = threadIdx.x;
     const double* Vs = scratch + (int64_t)blockIdx.x * prep_doubles(n) + 9 * n * n;
+    const double* Vm = Vs + 12 * n * n;
     const double* G = Vs + 24 * n * n;
     const double s = 2.0 / g.flen[f];
+    const bool clamp = clamped(g, f);
     const bool act = t < GJ_G * m;
     const int r = act ? t % m : 0, grp = act ? t / m : 0;
     double A[GJ_COLS];
@@ -424,13 +470,18 @@ __global__ __launch_bounds__(BLOCK_GJ) void k_fs_block(Geo g, int f_begin, const
                 } else if (xcol && ce == a) {
                     const int b = j - (n - 4);
                     const int node = b < 2 ? 0 : n - 1;
-                    v = (b & 1) ? s * s * s * g.D3[node * n + kc] : s * s * g.D2[node * n + kc];
+                    if (clamp && b >= 2)
+                        v = b == 2 ? (kc == n - 1 ? 1.0 : 0.0) : s * g.D1[(n - 1) * n + kc];
+                    else
+                        v = (b & 1) ? s * s * s * g.D3[node * n + kc] : s * s * g.D2[node * n + kc];
                 }
             } else {
                 const int j = r - n3;
                 if (j < n - 2) {
                     const double* p2 = g.P2 + j * n;
                     for (int k = 0; k < n; ++k) v = fma(p2[k], -G[(int64_t)k * m + c], v);
+                } else if (clamp && j == n - 1) {
+                    v = -clamp_entry(g, f, c, Vm, s);
                 } else if (!xcol) {
                     v = kc == (j == n - 2 ? 0 : n - 1) ? 1.0 : 0.0;
                 }
@@ -517,6 +568,7 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const double* Vs = scratch + (int64_t)fl * prep_doubles(n) + 9 * n * n;
     const double* G = Vs + 24 * n * n;
     const double e4 = -E * s * s * s * s, s2 = s * s, s3 = s2 * s, s4 = s2 * s2;
+    const bool clamp = clamped(g, f);
     double* Bf = binv + (int64_t)f * m * m;
     // phase 1: the block, column-major, into its own inverse slot (consecutive threads
     // take consecutive rows of one column)
@@ -552,7 +604,10 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             } else if (xcol && ce == a) {
                 const int b = j - (n - 4);
                 const int node = b < 2 ? 0 : n - 1;
-                v = (b & 1) ? s3 * d3[node * n + kc] : s2 * d2[node * n + kc];
+                if (clamp && b >= 2)
+                    v = b == 2 ? (kc == n - 1 ? 1.0 : 0.0) : s * d1[(n - 1) * n + kc];
+                else
+                    v = (b & 1) ? s3 * d3[node * n + kc] : s2 * d2[node * n + kc];
             }
         } else {
             const int j = r - n3;
@@ -577,6 +632,8 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 } else {
                     for (int k = 0; k < n; ++k) v = fma(p2t[k * n + j], -G[(int64_t)k * m + c], v);
                 }
+            } else if (clamp && j == n - 1) {
+                v = -clamp_entry(g, f, c, LOCAL ? nullptr : Vs + 12 * n * n, s);
             } else if (!xcol) {
                 v = kc == (j == n - 2 ? 0 : n - 1) ? 1.0 : 0.0;
             }
@@ -690,7 +747,8 @@ using namespace stokes;
 using namespace stokes::fs;
 
 extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
-                                 const double* fiber_len, const double* f_ext, double eps, double E,
+                                 const double* fiber_len, const double* f_ext,
+                                 const int32_t* clamp_minus, double eps, double E,
                                  double dt, double mu, double delta, double near_r, int32_t iters,
                                  double tol, uint32_t flags, double* xyz_out, double* T_out,
                                  double* resid_out, int32_t* iters_out, void* stream) {
@@ -766,6 +824,7 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
     g.nf = n_fib;
     g.X = xyz;
     g.flen = fiber_len;
+    g.clamp = clamp_minus;
     g.Xa = Xa;
     g.tan = tan;
     g.wq = wq;

@@ -82,7 +82,7 @@ def _load():
         "stokes_tree_destroy": [P],
         "stokes_particle_solve": [I64, P, P, P, I32, P, P, P, P, P, P, P, D, D, I32, U32, P, P, P,
                                   P, P, P],
-        "stokes_fiber_step": [I32, I32, P, P, P, D, D, D, D, D, D, I32, D, U32, P, P, P, P, P],
+        "stokes_fiber_step": [I32, I32, P, P, P, P, D, D, D, D, D, D, I32, D, U32, P, P, P, P, P],
         "stokes_session_create": [P, P],
         "stokes_session_submit": [P, P, P],
         "stokes_session_wait": [P, ctypes.c_uint64, P, P, I32],
@@ -327,10 +327,12 @@ def particle_solve(particles, force, torque, periphery=None, mu=1.0, iters=40, m
 
 
 def fiber_step(xyz, fiber_len, f_ext, nodes_per_fib, eps, E, dt, mu=1.0, delta=None, iters=40,
-               tol=0.0, mixed=False, doublet=True, near_r=0.0, stream=None):
-    """One implicit (backward Euler) step of free elastic fibers (stokes_fiber_step) on
-    device tensors: xyz, f_ext (3, N), fiber_len (n_fib,).  delta given: the nonlocal
-    self term K_delta is included.  Returns (X+ (3, N), T+ (N,), residual, iterations)."""
+               tol=0.0, mixed=False, doublet=True, near_r=0.0, clamp=None, stream=None):
+    """One implicit (backward Euler) step of elastic fibers (stokes_fiber_step) on device
+    tensors: xyz, f_ext (3, N), fiber_len (n_fib,).  delta given: the nonlocal self term
+    K_delta is included.  clamp: (n_fib,) flags (any array) clamping minus ends to a
+    body at rest; otherwise both ends are free.  Returns (X+ (3, N), T+ (N,), residual,
+    iterations)."""
     xyz = _dev(xyz, torch.float64, "xyz")
     n = xyz.shape[1]
     _dev(fiber_len, torch.float64, "fiber_len")
@@ -338,6 +340,13 @@ def fiber_step(xyz, fiber_len, f_ext, nodes_per_fib, eps, E, dt, mu=1.0, delta=N
     n_fib = fiber_len.shape[0]
     if n_fib * int(nodes_per_fib) != n:
         raise ValueError("fiber_len and nodes_per_fib do not match xyz")
+    cl = None
+    if clamp is not None:
+        import numpy as np
+        host = clamp.detach().cpu().numpy() if isinstance(clamp, torch.Tensor) else np.asarray(clamp)
+        if host.size != n_fib:
+            raise ValueError("clamp must have one flag per fiber")
+        cl = torch.from_numpy((host.ravel() != 0).astype(np.int32)).to(xyz.device)
     out = torch.empty_like(xyz)
     T = torch.empty((n,), dtype=torch.float64, device=xyz.device)
     res = ctypes.c_double(0.0)
@@ -345,7 +354,7 @@ def fiber_step(xyz, fiber_len, f_ext, nodes_per_fib, eps, E, dt, mu=1.0, delta=N
     flags = ((PREC_MIXED if mixed else PREC_FP64) | (0 if doublet else NO_DOUBLET)
              | (NONLOCAL if delta is not None else 0))
     _check(_lib.stokes_fiber_step(n_fib, int(nodes_per_fib), _ptr(xyz), _ptr(fiber_len), _ptr(f_ext),
-                                  float(eps), float(E), float(dt), float(mu),
+                                  None if cl is None else _ptr(cl), float(eps), float(E), float(dt), float(mu),
                                   float(delta) if delta is not None else 0.0, float(near_r), int(iters),
                                   float(tol), flags, _ptr(out), _ptr(T), ctypes.byref(res),
                                   ctypes.byref(it), _stream(stream)))

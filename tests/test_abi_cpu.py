@@ -128,8 +128,8 @@ def test_fiber_step_validation_without_gpu():
     def call(n_fib=0, npf=16, eps=0.01, E=1.0, dt=1e-3, mu=1.0, delta=0.0, iters=10, tol=0.0, flags=0,
              ptrs=None):
         p = ptrs if ptrs is not None else [None] * 5
-        return L.stokes_fiber_step(n_fib, npf, p[0], p[1], p[2], eps, E, dt, mu, delta, 0.0, iters, tol,
-                                   flags, p[3], p[4], None, None, None)
+        return L.stokes_fiber_step(n_fib, npf, p[0], p[1], p[2], None, eps, E, dt, mu, delta, 0.0, iters,
+                                   tol, flags, p[3], p[4], None, None, None)
 
     assert call() == S.OK                                   # no fibers: nothing to do
     for kw in ({"npf": 5}, {"npf": 49}, {"n_fib": -1}, {"eps": 0.6}, {"E": -1.0}, {"dt": 0.0},
