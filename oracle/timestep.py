@@ -42,14 +42,17 @@ first-kind Chebyshev points (the node values interpolated there) and completed b
 X_ss = 0 and X_sss = 0 at both ends; the tension equation is collocated at the n - 2
 first-kind points and completed by T = 0 at both ends (eq. bc-free).
 
-A fiber may instead have its minus end (s = 0) clamped to a body at rest: with U = Ω = 0,
-eq. BC2-1 and eq. BC2-2 keep that end's position and tangent (X+ = X, X+_s = X_s there),
-and eq. BC2-T, the tangential component of the same velocity condition, becomes
-t . V[f+ + f_ext] = 0 at the end, with t . f+ written as in the tension equation.
+A fiber may instead have its minus end (s = 0) attached to a body at rest (U = Ω = 0).
+Clamped: eq. BC2-1 and eq. BC2-2 keep that end's position and tangent (X+ = X,
+X+_s = X_s there).  Hinged: the position is kept and the end is torque free
+(X+ = X, X+_ss = 0).  Either way eq. BC2-T, the tangential component of the velocity
+condition, becomes t . V[f+ + f_ext] = 0 at the end, with t . f+ written as in the
+tension equation.
 
 Row layout of the operator (3 N position rows, then N tension rows, fiber by fiber):
 position rows of a fiber = its n - 4 collocated rows, then X_ss(s=L), X_sss(s=L),
-X_ss(s=0), X_sss(s=0) (clamped: X+(s=0), X+_s(s=0)); tension rows = its n - 2
+X_ss(s=0), X_sss(s=0) (clamped: X+(s=0), X+_s(s=0); hinged: X+(s=0), X+_ss(s=0));
+tension rows = its n - 2
 collocated rows, then T(s=L), T(s=0) (clamped: -t . V[f+](s=0)).
 """
 from __future__ import annotations
@@ -119,8 +122,9 @@ class FiberStep:
         self.nf = self.N // npf
         assert self.nf * npf == self.N and self.L.size == self.nf and npf >= 6
         self.fib = np.repeat(np.arange(self.nf), npf)
-        self.clamp = np.zeros(self.nf, bool) if clamp is None else np.asarray(clamp, bool).ravel()
-        assert self.clamp.size == self.nf
+        # minus-end condition per fiber: 0 free, 1 clamped, 2 hinged (to a body at rest)
+        self.clamp = np.zeros(self.nf, int) if clamp is None else np.asarray(clamp, int).ravel()
+        assert self.clamp.size == self.nf and np.all((self.clamp >= 0) & (self.clamp <= 2))
         p = npf - 1
         self.Da = cheb_diff(p)
         self.P4 = cheb_resample(p, npf - 4)
@@ -251,7 +255,8 @@ class FiberStep:
         for m in range(self.nf):
             o = m * self.npf
             if self.clamp[m]:
-                bc_pos[:, 4 * m:4 * m + 4] = np.stack([s2[:, o], s3[:, o], Xp[:, o + p], s1[:, o + p]], axis=1)
+                second = s1[:, o + p] if self.clamp[m] == 1 else s2[:, o + p]
+                bc_pos[:, 4 * m:4 * m + 4] = np.stack([s2[:, o], s3[:, o], Xp[:, o + p], second], axis=1)
                 bc_ten[2 * m:2 * m + 2] = [T[o], -tv[o + p]]
             else:
                 bc_pos[:, 4 * m:4 * m + 4] = np.stack([s2[:, o], s3[:, o], s2[:, o + p], s3[:, o + p]],
@@ -268,10 +273,11 @@ class FiberStep:
         p = self.npf - 1
         tv = np.sum(self.tangent * v, axis=0)
         for m in range(self.nf):
-            if self.clamp[m]:     # the end keeps its position and tangent, and no tangential velocity
+            if self.clamp[m]:     # the end keeps its position (and tangent), no tangential velocity
                 o = m * self.npf
                 bc_pos[:, 4 * m + 2] = self.X[:, o + p]
-                bc_pos[:, 4 * m + 3] = self.Xs[:, o + p]
+                if self.clamp[m] == 1:
+                    bc_pos[:, 4 * m + 3] = self.Xs[:, o + p]
                 bc_ten[2 * m + 1] = tv[o + p]
         return self._assemble(pos, ten, bc_pos, bc_ten)
 

@@ -236,6 +236,37 @@ def test_clamped_free_beam_mode_decay(oracle_mod, bL):
     assert np.abs(nv @ Xp - factor * A * clamped_mode(bL, s, L)).max() <= 1e-3 * A
 
 
+def hinged_mode(bL, x, L):
+    b = bL / L
+    return math.sin(bL) * np.sinh(b * x) + math.sinh(bL) * np.sin(b * x)
+
+
+def test_hinged_free_beam_mode_decay_and_end(oracle_mod):
+    # hinged at s = 0 to a body at rest: position kept, torque free (X_ss = 0); the
+    # hinged-free modes (tan(bL) = tanh(bL)) relax by 1/(1 + dt M_nn E b^4)
+    bL = 3.926602312047919
+    assert abs(math.tan(bL) - math.tanh(bL)) < 1e-9
+    p, L, eps, mu, E, dt, A = 31, 1.1, 0.01, 0.9, 1.5, 2e-3, 1e-5
+    X0, t = straight(p, L, [0.2, 0.9, 0.4], [0.0, 0.0, 0.0])
+    nv = normal_to(t)
+    s = 0.5 * L * (1 + cgl(p))
+    X = X0 + A * hinged_mode(bL, s, L)[None, :] * nv[:, None]
+    Xp, T, h, m = oracle_mod.fiber_step(X, np.array([L]), p + 1, eps, E, dt, np.zeros((3, p + 1)), 8, mu,
+                                        clamp=[2])
+    _, Mnn = m_coeffs(eps, mu)
+    factor = 1.0 / (1.0 + dt * Mnn * E * (bL / L) ** 4)
+    assert 0.05 < factor < 0.95
+    assert np.abs(nv @ Xp - factor * A * hinged_mode(bL, s, L)).max() <= 1e-3 * A
+    # a bent fiber under a load: the hinged end stays, its curvature vanishes, its tangent turns
+    Xb = bent(24, 1.0)
+    fE = np.random.default_rng(7).standard_normal((3, 25))
+    Xq, _, _, _ = oracle_mod.fiber_step(Xb, np.array([1.0]), 25, eps, E, 5e-3, fE, 12, mu, clamp=[2])
+    D = oracle_mod.cheb_diff(24)
+    assert np.abs(Xq[:, 24] - Xb[:, 24]).max() <= 1e-10
+    assert np.abs(Xq @ (D @ D)[24]).max() <= 1e-8 * np.abs(Xq @ (D @ D)[12]).max() + 1e-10
+    assert np.abs((Xq - Xb) @ D[24]).max() > 1e-4
+
+
 def rot(axis, ang):
     a = np.asarray(axis, float) / np.linalg.norm(axis)
     K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
@@ -314,8 +345,9 @@ TS_MUTANTS = {
     "rhs_position_dropped": ("pos = self.X / self.dt + v", "pos = v"),
     "resample_points": ("(2.0 * np.arange(m) + 1.0) * np.pi / (2.0 * m)", "(2.0 * np.arange(m) + 0.5) * np.pi / (2.0 * m)"),
     "self_not_excluded": ("excl=oracle.EXCL_SAME_FIBER", "excl=0"),
-    "clamp_value_row": ("[s2[:, o], s3[:, o], Xp[:, o + p], s1[:, o + p]]", "[s2[:, o], s3[:, o], Xp[:, o + p - 1], s1[:, o + p]]"),
-    "clamp_tangent_row": ("[s2[:, o], s3[:, o], Xp[:, o + p], s1[:, o + p]]", "[s2[:, o], s3[:, o], Xp[:, o + p], s2[:, o + p]]"),
+    "clamp_value_row": ("[s2[:, o], s3[:, o], Xp[:, o + p], second]", "[s2[:, o], s3[:, o], Xp[:, o + p - 1], second]"),
+    "clamp_tangent_row": ("second = s1[:, o + p] if self.clamp[m] == 1 else s2[:, o + p]", "second = s2[:, o + p] if self.clamp[m] == 1 else s2[:, o + p]"),
+    "hinge_curvature_row": ("second = s1[:, o + p] if self.clamp[m] == 1 else s2[:, o + p]", "second = s1[:, o + p] if self.clamp[m] == 1 else s1[:, o + p]"),
     "clamp_tension_sign": ("bc_ten[2 * m:2 * m + 2] = [T[o], -tv[o + p]]", "bc_ten[2 * m:2 * m + 2] = [T[o], tv[o + p]]"),
     "clamp_tension_local": ("tv = self.c * tf + np.sum(self.tangent * vr, axis=0)", "tv = self.alpha * tf + np.sum(self.tangent * vr, axis=0)"),
     "explicit_dt_velocity": ("pos = Xp / self.dt - self.local_velocity(f)", "pos = Xp / self.dt - 0.5 * self.local_velocity(f)"),
