@@ -254,10 +254,12 @@ int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xy
  * xyz        [3*N] node positions (x of every node, then y, then z), fiber-contiguous,
  *            node k of a fiber at alpha_k = cos(k pi/(nodes-1)) (node 0: s = L).
  * fiber_len  [n_fib] lengths L.    f_ext [3*N] external force density at the nodes.
- * clamp_minus  [n_fib] int32 or NULL: nonzero clamps that fiber's minus end (s = 0,
- *            node nodes-1) to a body at rest (eq. BC2-1, BC2-2 and the tangential
- *            condition of eq. BC2-T with U = Omega = 0): the end keeps its position and
- *            tangent and has no tangential velocity; otherwise both ends are free.
+ * clamp_minus  [n_fib] int32 or NULL: attaches that fiber's minus end (s = 0, node
+ *            nodes-1) to a body at rest (U = Omega = 0).  0: both ends free.  2: hinged,
+ *            the end keeps its position and is torque free (X_ss = 0, the condition
+ *            stated beside eq. BC2-2).  Any other value:
+ *            clamped (eq. BC2-1, BC2-2), the end keeps its position and tangent.  An
+ *            attached end has no tangential velocity (tangential part of eq. BC2-T).
  * eps        slenderness in (0, 0.5);  E >= 0 bending modulus;  dt > 0;  mu > 0.
  * delta      regularisation of K_delta (> 0 with STOKES_NONLOCAL, else unused).
  * near_r     mixed single-layer sums only (see stokes_sl_eval).

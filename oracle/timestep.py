@@ -45,7 +45,7 @@ first-kind points and completed by T = 0 at both ends (eq. bc-free).
 A fiber may instead have its minus end (s = 0) attached to a body at rest (U = Ω = 0).
 Clamped: eq. BC2-1 and eq. BC2-2 keep that end's position and tangent (X+ = X,
 X+_s = X_s there).  Hinged: the position is kept and the end is torque free
-(X+ = X, X+_ss = 0).  Either way eq. BC2-T, the tangential component of the velocity
+(X+ = X, X+_ss = 0, the condition stated beside eq. BC2-2).  Either way eq. BC2-T, the tangential component of the velocity
 condition, becomes t . V[f+ + f_ext] = 0 at the end, with t . f+ written as in the
 tension equation.
 

@@ -65,12 +65,16 @@ struct Geo {
     const double* D4;
     const double* P4;     // (n - 4) x n
     const double* P2;     // (n - 2) x n
-    const int32_t* clamp; // [nf] or null: nonzero = minus end clamped to a body at rest
+    const int32_t* clamp; // [nf] or null: minus end 0 free, 2 hinged, other: clamped (body at rest)
     double E, dt, mu, kappa, pref, delta;
     bool nonlocal;
 };
 
-__device__ __forceinline__ bool clamped(const Geo& g, int f) { return g.clamp && g.clamp[f] != 0; }
+// minus-end condition of fiber f: 0 free, 1 clamped, 2 hinged
+__device__ __forceinline__ int end_kind(const Geo& g, int f) {
+    const int v = g.clamp ? g.clamp[f] : 0;
+    return v == 0 ? 0 : (v == 2 ? 2 : 1);
+}
 
 __global__ __launch_bounds__(EB) void k_fs_geom(Geo g, double* Xa, double* tan, double* wq,
                                                 double* sarc, int32_t* fib, double* xss, double* xsss,
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
         for (int c = 0; c < 3; ++c) tvr = fma(tv[c], vr[c * N + i], tvr);
         if (rhs) {   // h(X, 0) + t . D_s (A f_ext) + t . D_s R[f_exp]
             h = g.cs[i] * 3.0 * E * ss3 + g.cc[i] * 3.0 * E * (sss3 + ss4) + al * E * ss4 + tdl + tdv;
-            if (t == n - 1) {   // clamped end: c (t . f_ext + 3 E X_ss . X_sss) + t . R[f_exp]
+            if (t == n - 1) {   // attached end: c (t . f_ext + 3 E X_ss . X_sss) + t . R[f_exp]
                 double tfe = 0.0;
                 for (int c = 0; c < 3; ++c) tfe = fma(tv[c], fe[c * N + i], tfe);
                 cl_all[fl] = g.cc[i] * (tfe + 3.0 * E * ss3) + tvr;
@@ -253,13 +257,14 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
             ssf = -E * ss4 + k2 * zT[t];
             const double tf = 3.0 * E * ss3 + Ts, tf_s = 3.0 * E * (sss3 + ss4) + Tss;
             h = -(g.cs[i] * tf + g.cc[i] * tf_s - al * ssf + tdv);
-            if (t == n - 1) cl_all[fl] = -(g.cc[i] * tf + tvr);   // clamped end: -t . V[f]
+            if (t == n - 1) cl_all[fl] = -(g.cc[i] * tf + tvr);   // attached end: -t . V[f]
         }
         hk[t] = h;
     }
     __syncthreads();
     if (!live) return;
-    const bool clamp = clamped(g, fi);
+    const int ek = end_kind(g, fi);
+    const bool clamp = ek != 0;
     for (int r = t; r < 4 * n; r += 64) {
         double out = 0.0;
         int64_t dst;
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
                 const int b = j - (n - 4);                    // X_ss(L), X_sss(L), X_ss(0), X_sss(0)
                 const int node = b < 2 ? 0 : n - 1;
                 const double* u = z + c * N + f0;
-                if (clamp && b >= 2) {                        // clamped: dX(0), D_s dX(0); rhs 0
+                if (clamp && (b == 2 || (b == 3 && ek == 1))) {   // dX(0); clamped: D_s dX(0); rhs 0
                     if (!rhs) {
                         if (b == 2) {
                             out = u[n - 1];
@@ -283,9 +288,10 @@ __global__ __launch_bounds__(64 * ROWS_FPB) void k_fs_rows(Geo g, const double* 
                             out *= s;
                         }
                     }
-                } else {
-                    const double* dm = ((b & 1) ? g.D3 : g.D2) + node * n;
-                    const double sc = (b & 1) ? s * s * s : s * s;
+                } else {                                      // hinged b = 3: X_ss(0)
+                    const bool d3 = b == 1 || (b == 3 && ek != 2);
+                    const double* dm = (d3 ? g.D3 : g.D2) + node * n;
+                    const double sc = d3 ? s * s * s : s * s;
                     for (int k = 0; k < n; ++k) out = fma(dm[k], u[k] - u[0], out);
                     out *= rhs ? -sc : sc;
                 }
@@ -450,7 +456,8 @@ __global__ __launch_bounds__(BLOCK_GJ) void k_fs_block(Geo g, int f_begin, const
     const double* Vm = Vs + 12 * n * n;
     const double* G = Vs + 24 * n * n;
     const double s = 2.0 / g.flen[f];
-    const bool clamp = clamped(g, f);
+    const int ek = end_kind(g, f);
+    const bool clamp = ek != 0;
     const bool act = t < GJ_G * m;
     const int r = act ? t % m : 0, grp = act ? t / m : 0;
     double A[GJ_COLS];
@@ -470,10 +477,13 @@ __global__ __launch_bounds__(BLOCK_GJ) void k_fs_block(Geo g, int f_begin, const
                 } else if (xcol && ce == a) {
                     const int b = j - (n - 4);
                     const int node = b < 2 ? 0 : n - 1;
-                    if (clamp && b >= 2)
-                        v = b == 2 ? (kc == n - 1 ? 1.0 : 0.0) : s * g.D1[(n - 1) * n + kc];
+                    if (clamp && b == 2)
+                        v = kc == n - 1 ? 1.0 : 0.0;
+                    else if (ek == 1 && b == 3)
+                        v = s * g.D1[(n - 1) * n + kc];
                     else
-                        v = (b & 1) ? s * s * s * g.D3[node * n + kc] : s * s * g.D2[node * n + kc];
+                        v = (b == 1 || (b == 3 && ek != 2)) ? s * s * s * g.D3[node * n + kc]
+                                                            : s * s * g.D2[node * n + kc];
                 }
             } else {
                 const int j = r - n3;
@@ -568,7 +578,8 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const double* Vs = scratch + (int64_t)fl * prep_doubles(n) + 9 * n * n;
     const double* G = Vs + 24 * n * n;
     const double e4 = -E * s * s * s * s, s2 = s * s, s3 = s2 * s, s4 = s2 * s2;
-    const bool clamp = clamped(g, f);
+    const int ek = end_kind(g, f);
+    const bool clamp = ek != 0;
     double* Bf = binv + (int64_t)f * m * m;
     // phase 1: the block, column-major, into its own inverse slot (consecutive threads
     // take consecutive rows of one column)
@@ -604,10 +615,12 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             } else if (xcol && ce == a) {
                 const int b = j - (n - 4);
                 const int node = b < 2 ? 0 : n - 1;
-                if (clamp && b >= 2)
-                    v = b == 2 ? (kc == n - 1 ? 1.0 : 0.0) : s * d1[(n - 1) * n + kc];
+                if (clamp && b == 2)
+                    v = kc == n - 1 ? 1.0 : 0.0;
+                else if (ek == 1 && b == 3)
+                    v = s * d1[(n - 1) * n + kc];
                 else
-                    v = (b & 1) ? s3 * d3[node * n + kc] : s2 * d2[node * n + kc];
+                    v = (b == 1 || (b == 3 && ek != 2)) ? s3 * d3[node * n + kc] : s2 * d2[node * n + kc];
             }
         } else {
             const int j = r - n3;

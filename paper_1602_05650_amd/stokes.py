@@ -330,8 +330,8 @@ def fiber_step(xyz, fiber_len, f_ext, nodes_per_fib, eps, E, dt, mu=1.0, delta=N
                tol=0.0, mixed=False, doublet=True, near_r=0.0, clamp=None, stream=None):
     """One implicit (backward Euler) step of elastic fibers (stokes_fiber_step) on device
     tensors: xyz, f_ext (3, N), fiber_len (n_fib,).  delta given: the nonlocal self term
-    K_delta is included.  clamp: (n_fib,) flags (any array) clamping minus ends to a
-    body at rest; otherwise both ends are free.  Returns (X+ (3, N), T+ (N,), residual,
+    K_delta is included.  clamp: (n_fib,) minus-end conditions at a body at rest
+    (any array; 0 or False free, 1 or True clamped, 2 hinged).  Returns (X+ (3, N), T+ (N,), residual,
     iterations)."""
     xyz = _dev(xyz, torch.float64, "xyz")
     n = xyz.shape[1]
@@ -346,7 +346,10 @@ def fiber_step(xyz, fiber_len, f_ext, nodes_per_fib, eps, E, dt, mu=1.0, delta=N
         host = clamp.detach().cpu().numpy() if isinstance(clamp, torch.Tensor) else np.asarray(clamp)
         if host.size != n_fib:
             raise ValueError("clamp must have one flag per fiber")
-        cl = torch.from_numpy((host.ravel() != 0).astype(np.int32)).to(xyz.device)
+        host = host.ravel().astype(np.int64)
+        if np.any((host < 0) | (host > 2)):
+            raise ValueError("clamp values must be 0 (free), 1 (clamped) or 2 (hinged)")
+        cl = torch.from_numpy(host.astype(np.int32)).to(xyz.device)
     out = torch.empty_like(xyz)
     T = torch.empty((n,), dtype=torch.float64, device=xyz.device)
     res = ctypes.c_double(0.0)

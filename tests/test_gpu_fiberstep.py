@@ -78,13 +78,14 @@ def test_step_parity_with_oracle(S, oracle_mod, n_fib, nodes, delta, E, dt, seed
 
 @pytest.mark.parametrize("n_fib,nodes,delta,seed", [(4, 16, None, 41), (3, 32, None, 42), (3, 20, 0.05, 43),
                                                  (2, 40, None, 44)])
-def test_clamped_step_parity_with_oracle(S, oracle_mod, n_fib, nodes, delta, seed):
-    # minus ends clamped to a body at rest on some fibers, free on the others (every block
-    # path: built in place, from the prepared products, the wide kernel)
+def test_attached_step_parity_with_oracle(S, oracle_mod, n_fib, nodes, delta, seed):
+    # minus ends clamped (1) or hinged (2) to a body at rest on some fibers, free (0) on
+    # the others (every block path: built in place, from the prepared products, the wide
+    # kernel)
     fs, f = small_case(seed, n_fib, nodes)
-    clamp = np.arange(n_fib) % 2 == 0
+    clamp = (np.arange(n_fib) + 1) % 3
     E, dt, mu, iters = 1.0, 2e-3, 0.9, 30
-    print(f"clamped case n_fib={n_fib} nodes={nodes} delta={delta}", flush=True)
+    print(f"attached case n_fib={n_fib} nodes={nodes} delta={delta} ends={clamp.tolist()}", flush=True)
     Xo, To, h, m = oracle_mod.fiber_step(fs.xyz, fs.length, nodes, fs.eps, E, dt, f, iters, mu,
                                          delta=delta, clamp=clamp)
     Xg, Tg, res, it = S.fiber_step(dev(fs.xyz), dev(fs.length), dev(f), nodes, fs.eps, E, dt, mu=mu,
@@ -96,12 +97,20 @@ def test_clamped_step_parity_with_oracle(S, oracle_mod, n_fib, nodes, delta, see
     tx, tT = tolerances(nodes)
     print(f"  dX err {ex:.2e} (tol {tx:.1e}), T err {eT:.2e}, iters {it}/{m}")
     assert it == m and ex <= tx and eT <= tT
-    for k in np.flatnonzero(clamp):         # the clamped ends stay where they were
+    for k in np.flatnonzero(clamp):         # the attached ends stay where they were
         e = (k + 1) * nodes - 1
         assert np.abs(Xg[:, e] - fs.xyz[:, e]).max() <= 1e-12 * (1 + np.abs(fs.xyz).max())
 
 
-def test_clamped_straight_fiber_holds_a_tangential_load(S):
+def test_end_condition_values_checked(S):
+    fs, f = small_case(3, 2, 16)
+    with pytest.raises(ValueError):
+        S.fiber_step(dev(fs.xyz), dev(fs.length), dev(f), 16, fs.eps, 1.0, 1e-3, clamp=[0, 3])
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_attached_straight_fiber_holds_a_tangential_load(S, kind):
+    # clamped or hinged: a straight fiber stays straight, so both hold the load alike
     n, L, eps, mu, E, dt = 21, 1.4, 0.02, 0.8, 1.3, 2e-3
     a = np.cos(np.arange(n) * np.pi / (n - 1))
     t = np.array([0.5, -1.0, 0.3])
@@ -111,7 +120,7 @@ def test_clamped_straight_fiber_holds_a_tangential_load(S):
     g = s ** 2 - 0.3 * s + 0.2
     G = lambda x: x ** 3 / 3 - 0.15 * x ** 2 + 0.2 * x
     Xg, Tg, res, it = S.fiber_step(dev(X), dev([L]), dev(g[None, :] * t[:, None]), n, eps, E, dt, mu=mu,
-                                   iters=8, clamp=[1])
+                                   iters=8, clamp=[kind])
     ref = G(L) - G(s)
     assert np.abs(Tg.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
     assert np.abs(Xg.cpu().numpy() - X).max() <= 1e-10
@@ -162,8 +171,9 @@ def test_straight_fiber_translates_and_beam_mode_decays(S):
 
 @pytest.mark.parametrize("nodes,delta,clamp", [(6, None, False), (16, None, False), (31, None, False),
                                                (32, None, False), (32, 0.05, False), (20, 0.05, False),
-                                               (40, None, False), (48, 0.05, False), (32, None, True),
-                                               (20, 0.05, True), (40, None, True)])
+                                               (40, None, False), (48, 0.05, False), (32, None, 1),
+                                               (20, 0.05, 1), (40, None, 1), (32, None, 2), (20, 0.05, 2),
+                                               (40, None, 2)])
 def test_single_fiber_block_is_the_inverse(S, oracle_mod, nodes, delta, clamp):
     # one fiber: the block-Jacobi preconditioner is the exact inverse of the operator, so
     # one GMRES iteration leaves only rounding amplified by the block's conditioning
@@ -180,7 +190,7 @@ def test_single_fiber_block_is_the_inverse(S, oracle_mod, nodes, delta, clamp):
     beta = np.linalg.norm(St.rhs(f) - St.apply(np.concatenate([fs.xyz.ravel(), np.zeros(nodes)])))
     X1, T1, res, it = S.fiber_step(dev(fs.xyz), dev(fs.length), dev(f), nodes, fs.eps, E, dt,
                                    delta=delta, iters=1, clamp=[int(clamp)])
-    # (a clamped end puts unit position rows beside the D_s^4 rows: a little worse again)
+    # (an attached end puts unit position rows beside the D_s^4 rows: a little worse again)
     cap = 0.2 if delta else (1e-2 if clamp else 1e-3)
     bound = min(cap, 1e-6 * max(1.0, (nodes / 16) ** 8) * (100.0 if delta else (10.0 if clamp else 1.0)))
     print(f"nodes {nodes} delta {delta} clamp {clamp}: residual after one iteration {res / beta:.2e} "
