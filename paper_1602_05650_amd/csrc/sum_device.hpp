@@ -204,7 +204,7 @@ __device__ __forceinline__ void sl_fp64_wave(const SumArgs& a, int tb, int chunk
         hi[r] = e.y;
         ux[r] = uy[r] = uz[r] = 0.0;
     }
-    unsigned long long ncoin = 0;
+    uint32_t ncoin = 0;
     const cptr<SrcSL64> src = as_const(static_cast<const SrcSL64*>(a.s64));
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
@@ -271,7 +271,7 @@ template <int R, bool DOUBLET>
 __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chunk) {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
-    const bool wave_active = wbase < a.n_t;   // no early exit: block barriers below
+    const bool wave_active = wbase < a.n_t;   // else only the barrier loop below
     // source tile staged in LDS: every operand of the pair arithmetic is a VGPR
     // (gfx950 issues FP32 VALU ops with an SGPR operand at a lower rate)
     __shared__ float4 lds[2 * TILE];
@@ -294,20 +294,26 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
         nx[r] = ny[r] = nz[r] = 0.0;
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
-    unsigned long long nnear = 0, ncoin = 0;
+    uint32_t nnear = 0, ncoin = 0;   // per thread: at most its targets x the chunk's sources
     const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcSL64* __restrict__ src64 = static_cast<const SrcSL64*>(a.s64);
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
+    if (!wave_active) {   // a wave past the targets still stages tiles and meets the barriers
+        for (int t = t0; t < t1; ++t) {
+            const Tile T = as_const(a.tiles)[t];
+            const int nsrc = T.j1 - T.j0;
+            if ((int)threadIdx.x < 2 * nsrc) lds[threadIdx.x] = src4[2 * (int64_t)T.j0 + threadIdx.x];
+            __syncthreads();
+            __syncthreads();
+        }
+        return;
+    }
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
         const int nsrc = T.j1 - T.j0;
         if ((int)threadIdx.x < 2 * nsrc) lds[threadIdx.x] = src4[2 * (int64_t)T.j0 + threadIdx.x];
         __syncthreads();
-        if (!wave_active) {
-            __syncthreads();
-            continue;
-        }
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
         bool near_s = false, ex = false;
 #pragma unroll
@@ -327,8 +333,7 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
             need = ex | (near_s & near_c);
         }
         if (__ballot(need) == 0) {
-#pragma unroll STOKES_UNROLL_SL32
-            for (int k = 0; k < nsrc; ++k) {
+            auto far = [&](int k) {
                 const float4 p0 = lds[2 * k], p1 = lds[2 * k + 1];
                 const SrcSL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
 #pragma unroll
@@ -337,6 +342,13 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     sl_pair32<DOUBLET>(dx, dy, dz, __builtin_amdgcn_rsqf(r2), s, px[r], py[r], pz[r]);
                 }
+            };
+            if (nsrc == TILE) {   // a full tile: LDS addresses are immediate offsets
+#pragma unroll
+                for (int k = 0; k < TILE; ++k) far(k);
+            } else {
+#pragma unroll STOKES_UNROLL_SL32
+                for (int k = 0; k < nsrc; ++k) far(k);
             }
         } else {
             uint32_t m[R];
@@ -387,7 +399,6 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
         }
         __syncthreads();
     }
-    if (!wave_active) return;
     double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -431,7 +442,7 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
         }
         ux[r] = uy[r] = uz[r] = 0.0;
     }
-    unsigned long long ncoin = 0;
+    uint32_t ncoin = 0;
     const cptr<SrcDL64> src = as_const(static_cast<const SrcDL64*>(a.s64));
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
@@ -498,7 +509,7 @@ template <int R, bool SUB>
 __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chunk) {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
-    const bool wave_active = wbase < a.n_t;   // no early exit: block barriers below
+    const bool wave_active = wbase < a.n_t;   // else only the barrier loop below
     // source tile staged in LDS: every operand of the pair arithmetic is a VGPR
     // (gfx950 issues FP32 VALU ops with an SGPR operand at a lower rate)
     __shared__ float4 lds[3 * TILE];
@@ -531,21 +542,27 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         nx[r] = ny[r] = nz[r] = 0.0;
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
-    unsigned long long nnear = 0, ncoin = 0;
+    uint32_t nnear = 0, ncoin = 0;   // per thread: at most its targets x the chunk's sources
     const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcDL64* __restrict__ src64 = static_cast<const SrcDL64*>(a.s64);
     const float tn = a.near_t_uniform;
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
+    if (!wave_active) {   // a wave past the targets still stages tiles and meets the barriers
+        for (int t = t0; t < t1; ++t) {
+            const Tile T = as_const(a.tiles)[t];
+            const int nsrc = T.j1 - T.j0;
+            if ((int)threadIdx.x < 3 * nsrc) lds[threadIdx.x] = src4[3 * (int64_t)T.j0 + threadIdx.x];
+            __syncthreads();
+            __syncthreads();
+        }
+        return;
+    }
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
         const int nsrc = T.j1 - T.j0;
         if ((int)threadIdx.x < 3 * nsrc) lds[threadIdx.x] = src4[3 * (int64_t)T.j0 + threadIdx.x];
         __syncthreads();
-        if (!wave_active) {
-            __syncthreads();
-            continue;
-        }
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
         bool near_s = false, ex = false;
 #pragma unroll
@@ -565,8 +582,7 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
             need = ex | (near_s & near_c);
         }
         if (__ballot(need) == 0) {
-#pragma unroll STOKES_UNROLL_DL32
-            for (int k = 0; k < nsrc; ++k) {
+            auto far = [&](int k) {
                 const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
                 const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -576,6 +592,13 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                     dl_pair32<SUB>(dx, dy, dz, __builtin_amdgcn_rsqf(r2), s, fqx[r], fqy[r], fqz[r],
                                    px[r], py[r], pz[r]);
                 }
+            };
+            if (nsrc == TILE) {   // a full tile: LDS addresses are immediate offsets
+#pragma unroll
+                for (int k = 0; k < TILE; ++k) far(k);
+            } else {
+#pragma unroll STOKES_UNROLL_DL32
+                for (int k = 0; k < nsrc; ++k) far(k);
             }
         } else {
             uint32_t m[R];
@@ -624,7 +647,6 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         }
         __syncthreads();
     }
-    if (!wave_active) return;
     double* out = a.partial + (int64_t)chunk * 3 * a.n_t;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
