@@ -2,6 +2,8 @@
 // batched (serving) kernels.  See stokes_sums.hip for the execution scheme.
 #pragma once
 
+#include <climits>
+
 #include "stokes_internal.hpp"
 
 // Unroll depth of the branch-free source loops (tuned on gfx950; overridable
@@ -163,6 +165,25 @@ __device__ __forceinline__ void wave_count(unsigned long long* ctr, unsigned lon
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, v);
 }
 
+// Union of the lanes' non-empty exclusion ranges [lo, hi) of a wave, wave-uniform (an
+// empty union has x > y).  A tile that misses it needs no exclusion test; one that
+// meets it takes the checked path, which tests every pair.  Call with the whole wave.
+template <int R>
+__device__ __forceinline__ int2 wave_excl_union(const int (&lo)[R], const int (&hi)[R]) {
+    int a = INT_MAX, b = INT_MIN;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (hi[r] > lo[r]) {
+            a = min(a, lo[r]);
+            b = max(b, hi[r]);
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        a = min(a, __shfl_xor(a, off, 64));
+        b = max(b, __shfl_xor(b, off, 64));
+    }
+    return make_int2(__builtin_amdgcn_readfirstlane(a), __builtin_amdgcn_readfirstlane(b));
+}
+
 // ---- kernel arguments -------------------------------------------------------
 struct SumArgs {
     const double* tx;        // target planes: tx[c * t_stride + i]
@@ -206,27 +227,28 @@ __device__ __forceinline__ void sl_fp64_wave(const SumArgs& a, int tb, int chunk
     }
     uint32_t ncoin = 0;
     const cptr<SrcSL64> src = as_const(static_cast<const SrcSL64*>(a.s64));
+    const int2 xu = wave_excl_union<R>(lo, hi);
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
-        bool near_s = false, ex = false;
+        bool near_s = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = X[r] - T.ox, dy = Y[r] - T.oy, dz = Z[r] - T.oz;
             near_s |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
-            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
         }
-        bool need = near_s | ex;
+        // wave-uniform: the union of the lanes' exclusion ranges overlaps the tile
+        bool checked = (xu.x < T.j1) & (xu.y > T.j0);
         if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
             bool near_c = false;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 near_c |= capsule_d2(T, (float)(X[r] - T.ox), (float)(Y[r] - T.oy),
                                      (float)(Z[r] - T.oz)) <= T.cap2_d;
-            need = ex | (near_s & near_c);
+            checked |= __ballot(near_s & near_c) != 0;
         }
-        if (__ballot(need) == 0) {
+        if (!checked) {
 #pragma unroll STOKES_UNROLL_SL64
             for (int j = T.j0; j < T.j1; ++j) {
                 const SrcSL64 s = src[j];
@@ -275,8 +297,13 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
     // source tile staged in LDS: every operand of the pair arithmetic is a VGPR
     // (gfx950 issues FP32 VALU ops with an SGPR operand at a lower rate)
     __shared__ float4 lds[2 * TILE];
+    // FP64 near-pair sums and counts of each thread: touched only on the rare checked
+    // tiles, so they live in the thread's own LDS slots, not in loop-carried registers
+    __shared__ double near_sum[3 * R][BLOCK];
+    __shared__ uint32_t near_cnt[2][BLOCK];
+    const int tid = threadIdx.x;
 
-    double X[R], Y[R], Z[R], nx[R], ny[R], nz[R];
+    double X[R], Y[R], Z[R];
     float Sx[R], Sy[R], Sz[R], Cx[R], Cy[R], Cz[R];
     int lo[R], hi[R];
     bool valid[R];
@@ -291,12 +318,13 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
         const int2 e = a.excl ? a.excl[i] : make_int2(0, 0);
         lo[r] = e.x;
         hi[r] = e.y;
-        nx[r] = ny[r] = nz[r] = 0.0;
+        near_sum[3 * r][tid] = near_sum[3 * r + 1][tid] = near_sum[3 * r + 2][tid] = 0.0;
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
-    uint32_t nnear = 0, ncoin = 0;   // per thread: at most its targets x the chunk's sources
+    near_cnt[0][tid] = near_cnt[1][tid] = 0u;   // at most the thread's targets x the chunk's sources
     const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcSL64* __restrict__ src64 = static_cast<const SrcSL64*>(a.s64);
+    const int2 xu = wave_excl_union<R>(lo, hi);
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     if (!wave_active) {   // a wave past the targets still stages tiles and meets the barriers
@@ -315,24 +343,24 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
         if ((int)threadIdx.x < 2 * nsrc) lds[threadIdx.x] = src4[2 * (int64_t)T.j0 + threadIdx.x];
         __syncthreads();
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
-        bool near_s = false, ex = false;
+        bool near_s = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             xs[r] = (float)(X[r] - T.ox);
             ys[r] = (float)(Y[r] - T.oy);
             zs[r] = (float)(Z[r] - T.oz);
             near_s |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
-            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
             px[r] = py[r] = pz[r] = 0.0f;
         }
-        bool need = near_s | ex;
+        // wave-uniform: the union of the lanes' exclusion ranges overlaps the tile
+        bool checked = (xu.x < T.j1) & (xu.y > T.j0);
         if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
             bool near_c = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) near_c |= capsule_d2(T, xs[r], ys[r], zs[r]) <= T.cap2_f;
-            need = ex | (near_s & near_c);
+            checked |= __ballot(near_s & near_c) != 0;
         }
-        if (__ballot(need) == 0) {
+        if (!checked) {
             auto far = [&](int k) {
                 const float4 p0 = lds[2 * k], p1 = lds[2 * k + 1];
                 const SrcSL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
@@ -371,8 +399,10 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
                 }
             }
             // FP64 recomputation of the masked (near) pairs from the FP64 inputs
+            uint32_t nnear = 0, ncoin = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                double ax = 0.0, ay = 0.0, az = 0.0;
                 uint32_t mm = m[r];
                 while (mm) {
                     const int k = __builtin_ctz(mm);
@@ -387,9 +417,14 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
                         continue;
                     }
                     nnear += valid[r] ? 1 : 0;
-                    sl_pair64<DOUBLET>(dx, dy, dz, rsqrt64(r2), s, nx[r], ny[r], nz[r]);
+                    sl_pair64<DOUBLET>(dx, dy, dz, rsqrt64(r2), s, ax, ay, az);
                 }
+                near_sum[3 * r][tid] += ax;
+                near_sum[3 * r + 1][tid] += ay;
+                near_sum[3 * r + 2][tid] += az;
             }
+            near_cnt[0][tid] += nnear;
+            near_cnt[1][tid] += ncoin;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -404,14 +439,14 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
     for (int r = 0; r < R; ++r) {
         const int64_t i = wbase + lane + 64 * r;
         if (valid[r]) {
-            out[i] = ((double)Sx[r] - (double)Cx[r]) + nx[r];
-            out[a.n_t + i] = ((double)Sy[r] - (double)Cy[r]) + ny[r];
-            out[2 * a.n_t + i] = ((double)Sz[r] - (double)Cz[r]) + nz[r];
+            out[i] = ((double)Sx[r] - (double)Cx[r]) + near_sum[3 * r][tid];
+            out[a.n_t + i] = ((double)Sy[r] - (double)Cy[r]) + near_sum[3 * r + 1][tid];
+            out[2 * a.n_t + i] = ((double)Sz[r] - (double)Cz[r]) + near_sum[3 * r + 2][tid];
         }
     }
     if (a.counters) {
-        wave_count(a.counters + 0, nnear);
-        wave_count(a.counters + 1, ncoin);
+        wave_count(a.counters + 0, near_cnt[0][tid]);
+        wave_count(a.counters + 1, near_cnt[1][tid]);
     }
 }
 
@@ -444,27 +479,28 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
     }
     uint32_t ncoin = 0;
     const cptr<SrcDL64> src = as_const(static_cast<const SrcDL64*>(a.s64));
+    const int2 xu = wave_excl_union<R>(lo, hi);
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
-        bool near_s = false, ex = false;
+        bool near_s = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = X[r] - T.ox, dy = Y[r] - T.oy, dz = Z[r] - T.oz;
             near_s |= fma(dx, dx, fma(dy, dy, dz * dz)) <= T.reach2;
-            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
         }
-        bool need = near_s | ex;
+        // wave-uniform: the union of the lanes' exclusion ranges overlaps the tile
+        bool checked = (xu.x < T.j1) & (xu.y > T.j0);
         if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
             bool near_c = false;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 near_c |= capsule_d2(T, (float)(X[r] - T.ox), (float)(Y[r] - T.oy),
                                      (float)(Z[r] - T.oz)) <= T.cap2_d;
-            need = ex | (near_s & near_c);
+            checked |= __ballot(near_s & near_c) != 0;
         }
-        if (__ballot(need) == 0) {
+        if (!checked) {
 #pragma unroll STOKES_UNROLL_DL64
             for (int j = T.j0; j < T.j1; ++j) {
                 const SrcDL64 s = src[j];
@@ -513,8 +549,13 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
     // source tile staged in LDS: every operand of the pair arithmetic is a VGPR
     // (gfx950 issues FP32 VALU ops with an SGPR operand at a lower rate)
     __shared__ float4 lds[3 * TILE];
+    // FP64 near-pair sums and counts of each thread: touched only on the rare checked
+    // tiles, so they live in the thread's own LDS slots, not in loop-carried registers
+    __shared__ double near_sum[3 * R][BLOCK];
+    __shared__ uint32_t near_cnt[2][BLOCK];
+    const int tid = threadIdx.x;
 
-    double X[R], Y[R], Z[R], nx[R], ny[R], nz[R], qx[R], qy[R], qz[R];
+    double X[R], Y[R], Z[R], qx[R], qy[R], qz[R];
     float fqx[R], fqy[R], fqz[R];
     float Sx[R], Sy[R], Sz[R], Cx[R], Cy[R], Cz[R];
     int lo[R], hi[R];
@@ -539,13 +580,14 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         fqx[r] = (float)qx[r];
         fqy[r] = (float)qy[r];
         fqz[r] = (float)qz[r];
-        nx[r] = ny[r] = nz[r] = 0.0;
+        near_sum[3 * r][tid] = near_sum[3 * r + 1][tid] = near_sum[3 * r + 2][tid] = 0.0;
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
-    uint32_t nnear = 0, ncoin = 0;   // per thread: at most its targets x the chunk's sources
+    near_cnt[0][tid] = near_cnt[1][tid] = 0u;   // at most the thread's targets x the chunk's sources
     const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcDL64* __restrict__ src64 = static_cast<const SrcDL64*>(a.s64);
     const float tn = a.near_t_uniform;
+    const int2 xu = wave_excl_union<R>(lo, hi);
     const int t0 = chunk * a.tiles_per_chunk;
     const int t1 = min(t0 + a.tiles_per_chunk, a.n_tiles);
     if (!wave_active) {   // a wave past the targets still stages tiles and meets the barriers
@@ -564,24 +606,24 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         if ((int)threadIdx.x < 3 * nsrc) lds[threadIdx.x] = src4[3 * (int64_t)T.j0 + threadIdx.x];
         __syncthreads();
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
-        bool near_s = false, ex = false;
+        bool near_s = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             xs[r] = (float)(X[r] - T.ox);
             ys[r] = (float)(Y[r] - T.oy);
             zs[r] = (float)(Z[r] - T.oz);
             near_s |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
-            ex |= (lo[r] < T.j1) & (hi[r] > T.j0);
             px[r] = py[r] = pz[r] = 0.0f;
         }
-        bool need = near_s | ex;
+        // wave-uniform: the union of the lanes' exclusion ranges overlaps the tile
+        bool checked = (xu.x < T.j1) & (xu.y > T.j0);
         if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
             bool near_c = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) near_c |= capsule_d2(T, xs[r], ys[r], zs[r]) <= T.cap2_f;
-            need = ex | (near_s & near_c);
+            checked |= __ballot(near_s & near_c) != 0;
         }
-        if (__ballot(need) == 0) {
+        if (!checked) {
             auto far = [&](int k) {
                 const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
                 const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, 0.f, 0.f, 0.f};
@@ -619,8 +661,10 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                     dl_pair32<SUB>(dx, dy, dz, ri, s, fqx[r], fqy[r], fqz[r], px[r], py[r], pz[r]);
                 }
             }
+            uint32_t nnear = 0, ncoin = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                double ax = 0.0, ay = 0.0, az = 0.0;
                 uint32_t mm = m[r];
                 while (mm) {
                     const int k = __builtin_ctz(mm);
@@ -635,9 +679,14 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                         continue;
                     }
                     nnear += valid[r] ? 1 : 0;
-                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, qx[r], qy[r], qz[r], nx[r], ny[r], nz[r]);
+                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, qx[r], qy[r], qz[r], ax, ay, az);
                 }
+                near_sum[3 * r][tid] += ax;
+                near_sum[3 * r + 1][tid] += ay;
+                near_sum[3 * r + 2][tid] += az;
             }
+            near_cnt[0][tid] += nnear;
+            near_cnt[1][tid] += ncoin;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -652,14 +701,14 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
     for (int r = 0; r < R; ++r) {
         const int64_t i = wbase + lane + 64 * r;
         if (valid[r]) {
-            out[i] = ((double)Sx[r] - (double)Cx[r]) + nx[r];
-            out[a.n_t + i] = ((double)Sy[r] - (double)Cy[r]) + ny[r];
-            out[2 * a.n_t + i] = ((double)Sz[r] - (double)Cz[r]) + nz[r];
+            out[i] = ((double)Sx[r] - (double)Cx[r]) + near_sum[3 * r][tid];
+            out[a.n_t + i] = ((double)Sy[r] - (double)Cy[r]) + near_sum[3 * r + 1][tid];
+            out[2 * a.n_t + i] = ((double)Sz[r] - (double)Cz[r]) + near_sum[3 * r + 2][tid];
         }
     }
     if (a.counters) {
-        wave_count(a.counters + 0, nnear);
-        wave_count(a.counters + 1, ncoin);
+        wave_count(a.counters + 0, near_cnt[0][tid]);
+        wave_count(a.counters + 1, near_cnt[1][tid]);
     }
 }
 
