@@ -270,7 +270,9 @@ int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xy
  * All arrays are DEVICE pointers.  The call is synchronous.  Its device memory, about
  * (16 n + 3 iters + 30) N doubles plus 37 n^2 per fiber of a 512-fiber chunk, is kept
  * per (device, stream) for the next call and released by stokes_release_workspace;
- * calls on one stream must therefore not overlap.
+ * calls on one stream must therefore not overlap.  The preconditioner's blocks are
+ * formed on a side stream that the library creates beside `stream` (one per caller
+ * stream, default priority, released with the buffer) and joined back into `stream`.
  */
 int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
                       const double* fiber_len, const double* f_ext, const int32_t* clamp_minus,

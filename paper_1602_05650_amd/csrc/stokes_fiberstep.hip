@@ -575,8 +575,9 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         nk2[t] = k2;
     }
     __syncthreads();
-    const double* Vs = scratch + (int64_t)fl * prep_doubles(n) + 9 * n * n;
-    const double* G = Vs + 24 * n * n;
+    // (entries formed in place: no scratch, and the launch may cover more fibers than a chunk)
+    const double* Vs = LOCAL ? nullptr : scratch + (int64_t)fl * prep_doubles(n) + 9 * n * n;
+    const double* G = LOCAL ? nullptr : Vs + 24 * n * n;
     const double e4 = -E * s * s * s * s, s2 = s * s, s3 = s2 * s, s4 = s2 * s2;
     const int ek = end_kind(g, f);
     const bool clamp = ek != 0;
@@ -699,6 +700,9 @@ struct StepBuf {
     void* p = nullptr;
     size_t bytes = 0;
     int tab_n = 0;
+    // the block set-up runs on a side stream, beside the right-hand side on st
+    hipStream_t side = nullptr;
+    hipEvent_t ev_geom = nullptr, ev_blk = nullptr;
 };
 static std::mutex g_step_mu;
 static std::vector<StepBuf> g_step_bufs;
@@ -723,12 +727,36 @@ static int step_buffer(hipStream_t st, size_t bytes, StepBuf* out) {
     StepBuf b;
     b.dev = dev;
     b.st = st;
+    STOKES_HIP(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));   // (default priority)
+    STOKES_HIP(hipEventCreateWithFlags(&b.ev_geom, hipEventDisableTiming));
+    STOKES_HIP(hipEventCreateWithFlags(&b.ev_blk, hipEventDisableTiming));
     STOKES_HIP(hipMalloc(&b.p, bytes));
     b.bytes = bytes;
     g_step_bufs.push_back(b);
     *out = b;
     return STOKES_OK;
 }
+
+// Joins the side stream into st: everything launched on sd so far completes before
+// later work on st.  join() at the join point; the destructor joins on early returns
+// too, so that a later call on st never overlaps this call's side work.
+struct SideJoin {
+    hipStream_t st, sd;
+    hipEvent_t ev;
+    bool open = true;
+    int join() {
+        open = false;
+        STOKES_HIP(hipEventRecord(ev, sd));
+        STOKES_HIP(hipStreamWaitEvent(st, ev, 0));
+        return STOKES_OK;
+    }
+    ~SideJoin() {
+        if (open) {
+            (void)hipEventRecord(ev, sd);
+            (void)hipStreamWaitEvent(st, ev, 0);
+        }
+    }
+};
 
 static void step_tables_loaded(hipStream_t st, int n) {
     int dev = 0;
@@ -749,6 +777,9 @@ void fiberstep_release() {
         (void)hipSetDevice(b.dev);
         (void)hipDeviceSynchronize();
         if (b.p) (void)hipFree(b.p);
+        if (b.ev_geom) (void)hipEventDestroy(b.ev_geom);
+        if (b.ev_blk) (void)hipEventDestroy(b.ev_blk);
+        if (b.side) (void)hipStreamDestroy(b.side);
     }
     (void)hipSetDevice(cur);
     fs::g_step_bufs.clear();
@@ -875,18 +906,26 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
                        alpha, ccoef);
     hipLaunchKernelGGL(k_fs_geom2, dim3(grid_e(N)), dim3(EB), 0, st, g, cs);
     STOKES_HIP(hipGetLastError());
+    // the preconditioner's blocks on the side stream, beside the right-hand side (both
+    // need only the geometry; the blocks are latency-bound, the right-hand side's pair
+    // sums are not), joined before the first GMRES iteration
+    const hipStream_t sd = buf.side;
+    STOKES_HIP(hipEventRecord(buf.ev_geom, st));
+    STOKES_HIP(hipStreamWaitEvent(sd, buf.ev_geom, 0));
+    SideJoin sj{st, sd, buf.ev_blk};
+    if (n <= NB64 && !nonlocal) {   // entries formed in place: no scratch, one launch
+        hipLaunchKernelGGL(k_fs_block64<true>, dim3(n_fib), dim3(GJ64_T), 0, sd, g, 0, (const double*)prep, binv);
+        STOKES_HIP(hipGetLastError());
+    } else
     for (int f0 = 0; f0 < n_fib; f0 += chunk) {
         const int nb = std::min(chunk, n_fib - f0);
-        if (n <= NB64 && !nonlocal) {
-            hipLaunchKernelGGL(k_fs_block64<true>, dim3(nb), dim3(GJ64_T), 0, st, g, f0, (const double*)prep,
-                               binv);
-        } else {
-            hipLaunchKernelGGL(k_fs_prep, dim3(nb), dim3(FB), 0, st, g, f0, prep);
+        {
+            hipLaunchKernelGGL(k_fs_prep, dim3(nb), dim3(FB), 0, sd, g, f0, prep);
             if (n <= NB64)
-                hipLaunchKernelGGL(k_fs_block64<false>, dim3(nb), dim3(GJ64_T), 0, st, g, f0,
+                hipLaunchKernelGGL(k_fs_block64<false>, dim3(nb), dim3(GJ64_T), 0, sd, g, f0,
                                    (const double*)prep, binv);
             else
-                hipLaunchKernelGGL(k_fs_block, dim3(nb), dim3(BLOCK_GJ), 0, st, g, f0, (const double*)prep, binv);
+                hipLaunchKernelGGL(k_fs_block, dim3(nb), dim3(BLOCK_GJ), 0, sd, g, f0, (const double*)prep, binv);
         }
         STOKES_HIP(hipGetLastError());
     }
@@ -896,10 +935,12 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
                        fbuf);
     STOKES_HIP(hipGetLastError());
     int rc = smooth_velocity(fbuf, vbuf);
-    if (rc) return rc;
     const unsigned rows_grid = (unsigned)((n_fib + ROWS_FPB - 1) / ROWS_FPB);
-    hipLaunchKernelGGL(k_fs_rows, dim3(rows_grid), dim3(64 * ROWS_FPB), 0, st, g, xyz, (const double*)fbuf,
-                       (const double*)vbuf, f_ext, true, rhs);
+    if (!rc)
+        hipLaunchKernelGGL(k_fs_rows, dim3(rows_grid), dim3(64 * ROWS_FPB), 0, st, g, xyz, (const double*)fbuf,
+                           (const double*)vbuf, f_ext, true, rhs);
+    if (int jr = sj.join()) return jr;
+    if (rc) return rc;
     STOKES_HIP(hipGetLastError());
 
     // w = A B^{-1} v: z = B^{-1} v, f = F z, vr = R[f], w = rows(z, f, vr)
