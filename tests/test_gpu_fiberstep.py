@@ -216,6 +216,34 @@ def test_buffers_reused_across_calls(S):
         assert np.array_equal(u[0], a[0]) and np.array_equal(u[1], a[1])
 
 
+def test_step_on_a_caller_stream_matches_the_default_stream(S):
+    # the blocks are formed on a library side stream forked from and joined back into the
+    # caller's stream: on a stream of the caller's own, also with calls of another size
+    # in between and the caller's stream busy with other work, the result is bitwise the
+    # default stream's
+    import torch
+    fs1, f1 = small_case(33, 5, 24)
+    fs2, f2 = small_case(34, 2, 40)
+    args1 = (dev(fs1.xyz), dev(fs1.length), dev(f1), 24, fs1.eps, 1.0, 2e-3)
+    ref = S.fiber_step(*args1, iters=12)
+    ref = (ref[0].cpu().numpy(), ref[1].cpu().numpy())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())   # (the inputs were copied on the default stream)
+    with torch.cuda.stream(side):
+        busy = torch.randn(2048, 2048, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            busy = busy @ busy.T.contiguous() / 2048.0   # work queued ahead of the step
+        outs = []
+        for _ in range(2):
+            X, T, res, it = S.fiber_step(*args1, iters=12, stream=side)
+            outs.append((X.cpu().numpy(), T.cpu().numpy()))
+            S.fiber_step(dev(fs2.xyz), dev(fs2.length), dev(f2), 40, fs2.eps, 1.0, 2e-3, iters=4,
+                         stream=side)
+    torch.cuda.synchronize()
+    for X, T in outs:
+        assert np.array_equal(X, ref[0]) and np.array_equal(T, ref[1])
+
+
 def test_fiber_at_rest_stays(S):
     # a straight fiber without force: the right-hand side is rounding (D4 of a line,
     # ~eps p^8 (2/L)^4 E dt |M| |X| ~ 1e-11 here), the fiber stays where it is and carries
