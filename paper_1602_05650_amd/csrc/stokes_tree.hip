@@ -340,7 +340,7 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int EW = 4;   // waves (batches) per workgroup
+constexpr int EW = 4;   // waves per workgroup: two batches, each split between two waves
 // Mixed far field of one proxy cluster for a compile-time degree: the proxies form
 // the tensor grid (X[kx], Y[ky], Z[kz]), so each lane keeps its z offsets and their
 // squares in registers and only the six charges of a proxy come from LDS; the
@@ -390,9 +390,19 @@ template <bool MIXED, int DEG>
 __global__ __launch_bounds__(64 * EW) void k_tr_eval(EvalArgs a) {
     __shared__ __align__(16) float lfs[EW][64][12];    // (a DEG <= 8 slab: 8 (DEG+1)^2 <= 768 floats)
     __shared__ double lds_[EW][64][10];
+    __shared__ double comb[EW / 2][3][64];              // the second half's sums of each batch
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int b = blockIdx.x * EW + w;
-    if (b >= a.nb) return;
+    // waves 2k and 2k+1 take the first and second halves of batch b's proxy and direct
+    // lists; the halves are added in that order at the end (deterministic), and the
+    // finer work items let the waves of a SIMD even out.  A wave past the last batch
+    // reads a real batch, does no work and still meets the barrier.
+    const int h = w & 1, b_raw = blockIdx.x * (EW / 2) + (w >> 1);
+    const bool live = b_raw < a.nb;
+    const int b = live ? b_raw : a.nb - 1;
+    const int pa = a.px_off[b], pz = a.px_off[b + 1], pm = pa + (pz - pa + 1) / 2;
+    const int p_lo = !live ? 0 : (h ? pm : pa), p_hi = !live ? 0 : (h ? pz : pm);
+    const int da = a.dr_off[b], dz = a.dr_off[b + 1], dm = da + (dz - da + 1) / 2;
+    const int d_lo = !live ? 0 : (h ? dm : da), d_hi = !live ? 0 : (h ? dz : dm);
     float (*lf)[12] = lfs[w];
     double (*ld)[10] = lds_[w];
     const Batch B = a.bt[b];
@@ -405,7 +415,7 @@ __global__ __launch_bounds__(64 * EW) void k_tr_eval(EvalArgs a) {
     float S0 = 0.f, S1 = 0.f, S2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     double u0 = 0.0, u1 = 0.0, u2 = 0.0;
     // far field: proxies
-    for (int e = a.px_off[b]; e < a.px_off[b + 1]; ++e) {
+    for (int e = p_lo; e < p_hi; ++e) {
         const int q = a.px_list[e];
         if constexpr (MIXED && DEG > 0) {
             float p0 = 0.f, p1 = 0.f, p2 = 0.f;
@@ -480,7 +490,7 @@ __global__ __launch_bounds__(64 * EW) void k_tr_eval(EvalArgs a) {
         }
     }
     // near field: direct ranges
-    for (int e = a.dr_off[b]; e < a.dr_off[b + 1]; ++e) {
+    for (int e = d_lo; e < d_hi; ++e) {
         const int64_t j0s = a.dr_start[e];
         const int32_t cnt = a.dr_count[e];
         for (int32_t k0 = 0; k0 < cnt; k0 += 64) {
@@ -584,13 +594,22 @@ __global__ __launch_bounds__(64 * EW) void k_tr_eval(EvalArgs a) {
             }
         }
     }
-    if (!act) return;
     double r0 = u0, r1 = u1, r2 = u2;
     if (MIXED) {
         r0 += (double)S0 - (double)C0;
         r1 += (double)S1 - (double)C1;
         r2 += (double)S2 - (double)C2;
     }
+    if (h == 1) {
+        comb[w >> 1][0][l] = r0;
+        comb[w >> 1][1][l] = r1;
+        comb[w >> 1][2][l] = r2;
+    }
+    __syncthreads();
+    if (!live || h == 1 || !act) return;
+    r0 += comb[w >> 1][0][l];
+    r1 += comb[w >> 1][1][l];
+    r2 += comb[w >> 1][2][l];
     const int64_t o = a.tperm[ti];
     if (a.accumulate) {
         a.out[o] += r0;
@@ -925,7 +944,7 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
     a.dr_count = t->dr_count;
     a.out = u_out;
     a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
-    const unsigned grid = (unsigned)((t->nb + EW - 1) / EW);
+    const unsigned grid = (unsigned)((t->nb + EW / 2 - 1) / (EW / 2));
     const dim3 blk(64 * EW);
     if (!mixed) {
         hipLaunchKernelGGL((k_tr_eval<false, 0>), dim3(grid), blk, 0, st, a);
