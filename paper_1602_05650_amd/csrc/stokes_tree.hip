@@ -386,8 +386,9 @@ __device__ __forceinline__ void far_tensor(const EvalArgs& a, int q, int l, floa
     }
 }
 
+// (5 waves per SIMD: 96 VGPRs without spills; 6 would spill)
 template <bool MIXED, int DEG>
-__global__ __launch_bounds__(64 * EW) void k_tr_eval(EvalArgs a) {
+__global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) void k_tr_eval(EvalArgs a) {
     __shared__ __align__(16) float lfs[EW][64][12];    // (a DEG <= 8 slab: 8 (DEG+1)^2 <= 768 floats)
     __shared__ double lds_[EW][64][10];
     __shared__ double comb[EW / 2][3][64];              // the second half's sums of each batch
