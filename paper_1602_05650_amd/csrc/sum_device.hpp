@@ -832,8 +832,7 @@ __global__ __launch_bounds__(BLOCK) void sl_fp64_kernel(SumArgs a) {
     sl_fp64_wave<R, DOUBLET>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
 }
 template <int R, bool DOUBLET>
-// (7 waves per SIMD: 72 VGPRs, one value spilled outside the tile loop)
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7))) void sl_mixed_kernel(SumArgs a) {
+__global__ __launch_bounds__(BLOCK) void sl_mixed_kernel(SumArgs a) {
     sl_mixed_wave<R, DOUBLET>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
 }
 template <int R, bool SUB>
@@ -841,8 +840,7 @@ __global__ __launch_bounds__(BLOCK) void dl_fp64_kernel(SumArgs a) {
     dl_fp64_wave<R, SUB>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
 }
 template <int R, bool SUB>
-// (6 waves per SIMD: 80 VGPRs, two values spilled outside the tile loop)
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void dl_mixed_kernel(SumArgs a) {
+__global__ __launch_bounds__(BLOCK) void dl_mixed_kernel(SumArgs a) {
     dl_mixed_wave<R, SUB>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
 }
 
