@@ -39,6 +39,12 @@ struct Workspace {
 int workspace_get(hipStream_t stream, size_t bytes, Workspace** out);
 // Frees the implicit time step's cached device buffers (stokes_release_workspace).
 void fiberstep_release();
+// Double layer over several surfaces in one sum: src_sid gives each source's surface;
+// a target's own density is subtracted only from its own surface's sources (the
+// surface of its self source).  Always with the on-surface subtraction.
+int dl_eval_surfaces(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
+                     const double* src_q, const int32_t* src_sid, int64_t n_trg, const double* trg_xyz,
+                     const int64_t* trg_self, double near_r, uint32_t flags, double* u_out, hipStream_t st);
 
 // Bump allocator over a workspace buffer (256-byte aligned slices).
 struct Carve {

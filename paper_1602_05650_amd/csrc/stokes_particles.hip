@@ -128,7 +128,7 @@ __global__ __launch_bounds__(PB) void k_pt_scale(int64_t n3, const double* v, co
 // Surface part of the unknown vector into per-surface SoA blocks (the sources of the
 // double-layer sums).
 __global__ __launch_bounds__(PB) void k_pt_gather(Surfaces S, int64_t ms, int64_t ntot, const double* z,
-                                                  double* qb) {
+                                                  double* qb, int64_t m0, double* qp) {
     const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
     if (i >= ms) return;
     const int s = S.sid[i];
@@ -137,6 +137,12 @@ __global__ __launch_bounds__(PB) void k_pt_gather(Surfaces S, int64_t ms, int64_
     q[li] = z[i];
     q[n + li] = z[ntot + i];
     q[2 * n + li] = z[2 * ntot + i];
+    if (i >= m0) {   // the particles' densities also as one planar [3][mp] array
+        const int64_t mp = ms - m0, k = i - m0;
+        qp[k] = z[i];
+        qp[mp + k] = z[ntot + i];
+        qp[2 * mp + k] = z[2 * ntot + i];
+    }
 }
 
 // One block per surface, fixed order: area (which = 0) or the moments of q (which = 1):
@@ -277,6 +283,9 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     std::vector<int64_t> selfs((size_t)n_surf * ms, -1);
     for (int s = 0; s < n_surf; ++s)
         for (int64_t k = 0; k < ssize[s]; ++k) selfs[(size_t)s * ms + sstart[s] + k] = k;
+    // trg_self of the particles' one multi-surface sum: particle point i is source i - m0
+    std::vector<int64_t> selfp(ms, -1);
+    for (int64_t i = m0; i < ms; ++i) selfp[i] = i - m0;
 
     // device scratch
     size_t off = 0;
@@ -287,7 +296,8 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     };
     const size_t o_T = take(3 * ms * 8), o_bx = take(3 * ms * 8), o_bn = take(3 * ms * 8),
                  o_bw = take(ms * 8), o_sid = take(ms * 4), o_ss = take(n_surf * 8), o_sz = take(n_surf * 8),
-                 o_self = take((size_t)n_surf * ms * 8), o_qb = take(3 * ms * 8), o_D0 = take(3 * ms * 8),
+                 o_self = take((size_t)n_surf * ms * 8), o_selfp = take(ms * 8), o_qp = take(3 * mp * 8),
+                 o_qb = take(3 * ms * 8), o_D0 = take(3 * ms * 8),
                  o_DP = take(3 * ms * 8), o_red = take(8 * n_surf * 8), o_area = take(8 * n_surf * 8),
                  o_diag = take(n3 * 8), o_rhs = take(n3 * 8), o_slot = take(vector_plan_bytes(ntot, iters));
     DevBuf buf;
@@ -301,6 +311,8 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     int64_t* d_ss = reinterpret_cast<int64_t*>(base + o_ss);
     int64_t* d_sz = reinterpret_cast<int64_t*>(base + o_sz);
     int64_t* d_self = reinterpret_cast<int64_t*>(base + o_self);
+    int64_t* d_selfp = reinterpret_cast<int64_t*>(base + o_selfp);
+    double* qp = reinterpret_cast<double*>(base + o_qp);
     double* qb = reinterpret_cast<double*>(base + o_qb);
     double* D0 = reinterpret_cast<double*>(base + o_D0);
     double* DP = reinterpret_cast<double*>(base + o_DP);
@@ -330,6 +342,7 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     STOKES_HIP(hipMemcpyAsync(d_ss, sstart.data(), n_surf * 8, hipMemcpyHostToDevice, st));
     STOKES_HIP(hipMemcpyAsync(d_sz, ssize.data(), n_surf * 8, hipMemcpyHostToDevice, st));
     STOKES_HIP(hipMemcpyAsync(d_self, selfs.data(), (size_t)n_surf * ms * 8, hipMemcpyHostToDevice, st));
+    STOKES_HIP(hipMemcpyAsync(d_selfp, selfp.data(), ms * 8, hipMemcpyHostToDevice, st));
     const Surfaces S{bx, bn, bw, d_sid, d_ss, d_sz};
 
     hipLaunchKernelGGL(k_pt_rhs, dim3(grid1(ntot)), dim3(PB), 0, st, ms, ntot, T, n_part, centers, force,
@@ -342,7 +355,8 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     // w = A P^{-1} v: z = v / diag, then the operator
     auto apply = [&](const double* v, double* z, double* w) -> int {
         hipLaunchKernelGGL(k_pt_scale, dim3(grid1(n3)), dim3(PB), 0, st, n3, v, (const double*)diag, z);
-        hipLaunchKernelGGL(k_pt_gather, dim3(grid1(ms)), dim3(PB), 0, st, S, ms, ntot, (const double*)z, qb);
+        hipLaunchKernelGGL(k_pt_gather, dim3(grid1(ms)), dim3(PB), 0, st, S, ms, ntot, (const double*)z, qb, m0,
+                           qp);
         int rc = STOKES_OK;
         if (m0 > 0) {
             rc = stokes_dl_eval(m0, bx, bn, bw, qb, ms, T, d_self, near_r, sumflags, D0, st, nullptr);
@@ -350,12 +364,9 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
             STOKES_HIP(hipMemsetAsync(D0, 0, 3 * ms * 8, st));
         }
         if (rc) return rc;
-        for (int p = 0; p < n_part && !rc; ++p) {
-            const int s = 1 + p;
-            rc = stokes_dl_eval(ssize[s], bx + 3 * sstart[s], bn + 3 * sstart[s], bw + sstart[s],
-                                qb + 3 * sstart[s], ms, T, d_self + (size_t)s * ms, near_r,
-                                sumflags | (p > 0 ? STOKES_ACCUMULATE : 0u), DP, st, nullptr);
-        }
+        // all particles in one double-layer sum: each target subtracts its own density
+        // only from its own particle's sources (surface ids d_sid, 1 + p)
+        rc = dl_eval_surfaces(mp, yp, np_, wp, qp, d_sid + m0, ms, T, d_selfp, near_r, sumflags, DP, st);
         if (rc) return rc;
         hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, st, S, (const double*)qb, centers, n_part,
                            1, red);

@@ -65,8 +65,8 @@ __global__ void sl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
 
 __global__ void dl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
                                    const double* __restrict__ nrm, const double* __restrict__ w,
-                                   const double* __restrict__ q, const Tile* __restrict__ tiles,
-                                   SrcDL64* s64, SrcDL32* s32) {
+                                   const double* __restrict__ q, const int32_t* __restrict__ sid,
+                                   const Tile* __restrict__ tiles, SrcDL64* s64, SrcDL32* s32) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_s) return;
     const double k = 3.0 / (4.0 * PI_D) * w[j];
@@ -80,7 +80,8 @@ __global__ void dl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
     s.nx = k * nrm[j];
     s.ny = k * nrm[n_s + j];
     s.nz = k * nrm[2 * n_s + j];
-    s.pad0 = s.pad1 = s.pad2 = 0.0;
+    s.pad0 = sid ? (double)sid[j] : 0.0;   // surface id (multi-surface sums)
+    s.pad1 = s.pad2 = 0.0;
     s64[j] = s;
     if (s32) {
         const Tile& T = tiles[j / TILE];
@@ -94,7 +95,8 @@ __global__ void dl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
         h.nx = (float)s.nx;
         h.ny = (float)s.ny;
         h.nz = (float)s.nz;
-        h.pad0 = h.pad1 = h.pad2 = 0.0f;
+        h.pad0 = (float)s.pad0;
+        h.pad1 = h.pad2 = 0.0f;
         s32[j] = h;
     }
 }
@@ -522,7 +524,15 @@ extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double
     return STOKES_OK;
 }
 
-static void launch_dl_kernel(bool mixed, bool sub, unsigned grid, const SumArgs& a, hipStream_t st) {
+static void launch_dl_kernel(bool mixed, bool sub, bool multi, unsigned grid, const SumArgs& a,
+                             hipStream_t st) {
+    if (multi) {   // (always with the on-surface subtraction)
+        if (mixed)
+            hipLaunchKernelGGL((dl_mixed_kernel<R_DL32, true, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else
+            hipLaunchKernelGGL((dl_fp64_kernel<R_DL64, true, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        return;
+    }
     if (mixed) {
         if (sub)
             hipLaunchKernelGGL((dl_mixed_kernel<R_DL32, true>), dim3(grid), dim3(BLOCK), 0, st, a);
@@ -536,10 +546,10 @@ static void launch_dl_kernel(bool mixed, bool sub, unsigned grid, const SumArgs&
     }
 }
 
-extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double* src_normal,
-                              const double* src_weight, const double* src_q, int64_t n_trg,
-                              const double* trg_xyz, const int64_t* trg_self, double near_r,
-                              uint32_t flags, double* u_out, void* stream, stokes_diag* diag) {
+static int dl_run(int64_t n_src, const double* src_xyz, const double* src_normal,
+                  const double* src_weight, const double* src_q, const int32_t* src_sid, int64_t n_trg,
+                  const double* trg_xyz, const int64_t* trg_self, double near_r, uint32_t flags,
+                  double* u_out, void* stream, stokes_diag* diag) {
     const uint32_t known = STOKES_PREC_MIXED | STOKES_ONSURF_RAW | STOKES_ACCUMULATE |
                            STOKES_CHECK_INPUTS;
     if (flags & ~known) return fail(STOKES_E_INVAL, "stokes_dl_eval: unknown flag bits");
@@ -593,7 +603,7 @@ extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double
                            src_xyz, P.n_tiles, mixed ? nr : 0.0, 0.0, (const int32_t*)nullptr, 0,
                            (const double*)nullptr, S.tiles);
         hipLaunchKernelGGL(dl_src_prep_kernel, dim3(nblk(n_src)), dim3(256), 0, st, n_src, src_xyz,
-                           src_normal, src_weight, src_q, S.tiles, static_cast<SrcDL64*>(S.s64),
+                           src_normal, src_weight, src_q, src_sid, S.tiles, static_cast<SrcDL64*>(S.s64),
                            mixed ? static_cast<SrcDL32*>(S.s32) : nullptr);
         SumArgs a{};
         a.tx = tx;
@@ -613,7 +623,7 @@ extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double
         a.counters = counters;
         const unsigned grid = (unsigned)((int64_t)P.n_tblocks * P.n_chunks);
         prof_begin(st);
-        launch_dl_kernel(mixed, sub, grid, a, st);
+        launch_dl_kernel(mixed, sub, src_sid != nullptr && sub, grid, a, st);
         prof_end(st);
     }
     hipLaunchKernelGGL(reduce_kernel, dim3(red_blocks(n_t)), dim3(RED_T * RED_S), 0, st, n_t, P.n_chunks,
@@ -623,3 +633,23 @@ extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double
     if (diag) return finish_diag(ws, counters, st, n_t, n_src, diag);
     return STOKES_OK;
 }
+
+extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double* src_normal,
+                              const double* src_weight, const double* src_q, int64_t n_trg,
+                              const double* trg_xyz, const int64_t* trg_self, double near_r,
+                              uint32_t flags, double* u_out, void* stream, stokes_diag* diag) {
+    return dl_run(n_src, src_xyz, src_normal, src_weight, src_q, nullptr, n_trg, trg_xyz, trg_self, near_r,
+                  flags, u_out, stream, diag);
+}
+
+namespace stokes {
+// The double layer over several surfaces in one sum (see dl_fp64_wave's MULTI).
+int dl_eval_surfaces(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
+                     const double* src_q, const int32_t* src_sid, int64_t n_trg, const double* trg_xyz,
+                     const int64_t* trg_self, double near_r, uint32_t flags, double* u_out, hipStream_t st) {
+    if (!src_sid || (flags & STOKES_ONSURF_RAW))
+        return fail(STOKES_E_INVAL, "dl_eval_surfaces: needs surface ids and the on-surface subtraction");
+    return dl_run(n_src, src_xyz, src_normal, src_weight, src_q, src_sid, n_trg, trg_xyz, trg_self, near_r,
+                  flags, u_out, st, nullptr);
+}
+}  // namespace stokes

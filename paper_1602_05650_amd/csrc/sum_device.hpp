@@ -451,13 +451,16 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
 }
 
 // ---- double layer, FP64 -----------------------------------------------------
-template <int R, bool SUB>
+// MULTI: the sources are several surfaces, their ids in SrcDL64::pad0; a target's own
+// density (SUB) is subtracted only from the sources of its own surface, the surface
+// of its self source (a target without one takes every source raw).
+template <int R, bool SUB, bool MULTI = false>
 __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk) {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
     if (wbase >= a.n_t) return;
 
-    double X[R], Y[R], Z[R], ux[R], uy[R], uz[R], qx[R], qy[R], qz[R];
+    double X[R], Y[R], Z[R], ux[R], uy[R], uz[R], qx[R], qy[R], qz[R], tsid[R];
     int lo[R], hi[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -470,10 +473,12 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
         lo[r] = e.x;
         hi[r] = e.y;
         qx[r] = qy[r] = qz[r] = 0.0;
+        tsid[r] = -1.0;
         if (SUB && e.y > e.x) {
             qx[r] = a.q[e.x];
             qy[r] = a.q[a.n_s + e.x];
             qz[r] = a.q[2 * a.n_s + e.x];
+            if (MULTI) tsid[r] = static_cast<const SrcDL64*>(a.s64)[e.x].pad0;
         }
         ux[r] = uy[r] = uz[r] = 0.0;
     }
@@ -508,7 +513,9 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
                 for (int r = 0; r < R; ++r) {
                     const double dx = X[r] - s.x, dy = Y[r] - s.y, dz = Z[r] - s.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, qx[r], qy[r], qz[r], ux[r], uy[r], uz[r]);
+                    const bool own = !MULTI || s.pad0 == tsid[r];
+                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, own ? qx[r] : 0.0, own ? qy[r] : 0.0,
+                                   own ? qz[r] : 0.0, ux[r], uy[r], uz[r]);
                 }
             }
         } else {
@@ -522,7 +529,9 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
                     const bool zero = (r2 == 0.0);
                     ncoin += (!ex && zero && (wbase + lane + 64 * r < a.n_t)) ? 1 : 0;
                     const double ri = (ex || zero) ? 0.0 : rsqrt64(zero ? 1.0 : r2);
-                    dl_pair64<SUB>(dx, dy, dz, ri, s, qx[r], qy[r], qz[r], ux[r], uy[r], uz[r]);
+                    const bool own = !MULTI || s.pad0 == tsid[r];
+                    dl_pair64<SUB>(dx, dy, dz, ri, s, own ? qx[r] : 0.0, own ? qy[r] : 0.0, own ? qz[r] : 0.0,
+                                   ux[r], uy[r], uz[r]);
                 }
             }
         }
@@ -541,7 +550,8 @@ __device__ __forceinline__ void dl_fp64_wave(const SumArgs& a, int tb, int chunk
 }
 
 // ---- double layer, mixed FP32 / FP64 -------------------------------------------
-template <int R, bool SUB>
+// MULTI as for dl_fp64_wave (the FP32 pack carries the surface id in pad0 too).
+template <int R, bool SUB, bool MULTI = false>
 __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chunk) {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = ((int64_t)tb * 4 + (threadIdx.x >> 6)) * (64 * R);
@@ -555,7 +565,7 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
     __shared__ uint32_t near_cnt[2][BLOCK];
     const int tid = threadIdx.x;
 
-    double X[R], Y[R], Z[R], qx[R], qy[R], qz[R];
+    double X[R], Y[R], Z[R], qx[R], qy[R], qz[R], tsid[R];
     float fqx[R], fqy[R], fqz[R];
     float Sx[R], Sy[R], Sz[R], Cx[R], Cy[R], Cz[R];
     int lo[R], hi[R];
@@ -572,10 +582,12 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         lo[r] = e.x;
         hi[r] = e.y;
         qx[r] = qy[r] = qz[r] = 0.0;
+        tsid[r] = -1.0;
         if (SUB && e.y > e.x) {
             qx[r] = a.q[e.x];
             qy[r] = a.q[a.n_s + e.x];
             qz[r] = a.q[2 * a.n_s + e.x];
+            if (MULTI) tsid[r] = static_cast<const SrcDL64*>(a.s64)[e.x].pad0;
         }
         fqx[r] = (float)qx[r];
         fqy[r] = (float)qy[r];
@@ -626,12 +638,14 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
         if (!checked) {
             auto far = [&](int k) {
                 const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
-                const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, 0.f, 0.f, 0.f};
+                const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, MULTI ? p2.y : 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    dl_pair32<SUB>(dx, dy, dz, __builtin_amdgcn_rsqf(r2), s, fqx[r], fqy[r], fqz[r],
+                    const bool own = !MULTI || s.pad0 == (float)tsid[r];
+                    dl_pair32<SUB>(dx, dy, dz, __builtin_amdgcn_rsqf(r2), s, own ? fqx[r] : 0.f, own ? fqy[r] : 0.f,
+                                   own ? fqz[r] : 0.f,
                                    px[r], py[r], pz[r]);
                 }
             };
@@ -649,7 +663,7 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
             for (int k = 0; k < nsrc; ++k) {
                 const int j = T.j0 + k;
                 const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
-                const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, 0.f, 0.f, 0.f};
+                const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, MULTI ? p2.y : 0.f, 0.f, 0.f};
                 const uint32_t bit = 1u << k;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -658,7 +672,9 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                     const bool bad = (r2 < tn) | in_range(j, lo[r], hi[r]);
                     m[r] |= bad ? bit : 0u;
                     const float ri = bad ? 0.0f : __builtin_amdgcn_rsqf(r2);
-                    dl_pair32<SUB>(dx, dy, dz, ri, s, fqx[r], fqy[r], fqz[r], px[r], py[r], pz[r]);
+                    const bool own = !MULTI || s.pad0 == (float)tsid[r];
+                    dl_pair32<SUB>(dx, dy, dz, ri, s, own ? fqx[r] : 0.f, own ? fqy[r] : 0.f, own ? fqz[r] : 0.f,
+                                   px[r], py[r], pz[r]);
                 }
             }
             uint32_t nnear = 0, ncoin = 0;
@@ -679,7 +695,9 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                         continue;
                     }
                     nnear += valid[r] ? 1 : 0;
-                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, qx[r], qy[r], qz[r], ax, ay, az);
+                    const bool own = !MULTI || s.pad0 == tsid[r];
+                    dl_pair64<SUB>(dx, dy, dz, rsqrt64(r2), s, own ? qx[r] : 0.0, own ? qy[r] : 0.0,
+                                   own ? qz[r] : 0.0, ax, ay, az);
                 }
                 near_sum[3 * r][tid] += ax;
                 near_sum[3 * r + 1][tid] += ay;
@@ -835,13 +853,13 @@ template <int R, bool DOUBLET>
 __global__ __launch_bounds__(BLOCK) void sl_mixed_kernel(SumArgs a) {
     sl_mixed_wave<R, DOUBLET>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
 }
-template <int R, bool SUB>
+template <int R, bool SUB, bool MULTI = false>
 __global__ __launch_bounds__(BLOCK) void dl_fp64_kernel(SumArgs a) {
-    dl_fp64_wave<R, SUB>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
+    dl_fp64_wave<R, SUB, MULTI>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
 }
-template <int R, bool SUB>
+template <int R, bool SUB, bool MULTI = false>
 __global__ __launch_bounds__(BLOCK) void dl_mixed_kernel(SumArgs a) {
-    dl_mixed_wave<R, SUB>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
+    dl_mixed_wave<R, SUB, MULTI>(a, blockIdx.x % a.n_tblocks, blockIdx.x / a.n_tblocks);
 }
 
 }  // namespace stokes
