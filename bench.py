@@ -39,12 +39,12 @@ NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go 
 # 256 MiB (FETCH x 1.99977, WRITE x 0.99998); see
 # profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
 # sources with this digest: after any change the field reports null.
-TRAFFIC = {"digest": "0c7562d9bd27a595", "bytes": 540416085}
+TRAFFIC = {"digest": "913c7827881be904", "bytes": 540421761}
 # VALU flops per pair from rocprofv3 instruction counters of the same kernel sources
 # (64 x (2 FMA + MUL + ADD + TRANS) of the kernel's precision, per dispatch, over the
 # pairs of one launch); see profiles/sl_spindle_262k_valu_counters.md.  Combined with
 # the live kernel time they give the counter-based fraction of peak.
-VALU_FLOPS_PER_PAIR = {"digest": "0c7562d9bd27a595", "mixed": 34.70, "fp64": 42.25}
+VALU_FLOPS_PER_PAIR = {"digest": "913c7827881be904", "mixed": 34.70, "fp64": 42.25}
 KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
                   "paper_1602_05650_amd/csrc/stokes_sums.hip",
                   "paper_1602_05650_amd/csrc/stokes_internal.hpp"]
