@@ -81,9 +81,12 @@ __global__ __launch_bounds__(PB) void k_pt_rhs(int64_t ms, int64_t ntot, const d
 
 // Diagonal of the self-interaction blocks: on the periphery -1 - sum_s w_s K_cc + w n_c^2,
 // on a particle sum_s w_s K_cc over its own points (s != i), -1 on the U, Omega rows.
-__global__ __launch_bounds__(PB) void k_pt_diag(Surfaces S, int64_t ms, int64_t ntot, double* diag) {
-    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (i >= ntot) return;
+// One wave per row: lane l sums the points k = l, l + 64, ... of the row's surface, and
+// the 64 partial sums are combined by a fixed butterfly (the periphery's rows each
+// cover all its points; a thread per row would leave the chip nearly idle).
+__global__ __launch_bounds__(64) void k_pt_diag(Surfaces S, int64_t ms, int64_t ntot, double* diag) {
+    const int64_t i = blockIdx.x;
+    const int l = threadIdx.x;
     double d0 = -1.0, d1 = -1.0, d2 = -1.0;
     if (i < ms) {
         const int s = S.sid[i];
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(PB) void k_pt_diag(Surfaces S, int64_t ms, int64_t 
         const double* w = S.w + S.sstart[s];
         const double xi = y[li], yi = y[n + li], zi = y[2 * n + li];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int64_t k = 0; k < n; ++k) {
+        for (int64_t k = l; k < n; k += 64) {
             if (k == li) continue;
             const double dx = xi - y[k], dy = yi - y[n + k], dz = zi - y[2 * n + k];
             const double r2 = dx * dx + dy * dy + dz * dz;
@@ -102,6 +105,11 @@ __global__ __launch_bounds__(PB) void k_pt_diag(Surfaces S, int64_t ms, int64_t 
             a0 += c * dx * dx;
             a1 += c * dy * dy;
             a2 += c * dz * dz;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            a1 += __shfl_xor(a1, o, 64);
+            a2 += __shfl_xor(a2, o, 64);
         }
         if (s == 0) {
             const double wi = w[li];
@@ -114,9 +122,11 @@ __global__ __launch_bounds__(PB) void k_pt_diag(Surfaces S, int64_t ms, int64_t 
             d2 = a2;
         }
     }
-    diag[i] = d0;
-    diag[ntot + i] = d1;
-    diag[2 * ntot + i] = d2;
+    if (l == 0) {
+        diag[i] = d0;
+        diag[ntot + i] = d1;
+        diag[2 * ntot + i] = d2;
+    }
 }
 
 // out = v / d elementwise over 3 n_tot entries.
@@ -347,7 +357,7 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
 
     hipLaunchKernelGGL(k_pt_rhs, dim3(grid1(ntot)), dim3(PB), 0, st, ms, ntot, T, n_part, centers, force,
                        torque, mu, rhs);
-    hipLaunchKernelGGL(k_pt_diag, dim3(grid1(ntot)), dim3(PB), 0, st, S, ms, ntot, diag);
+    hipLaunchKernelGGL(k_pt_diag, dim3((unsigned)ntot), dim3(64), 0, st, S, ms, ntot, diag);
     hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, st, S, (const double*)qb, centers, n_part, 0,
                        area);
     STOKES_HIP(hipGetLastError());
