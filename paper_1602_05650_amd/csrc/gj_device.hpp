@@ -55,6 +55,7 @@ __device__ __forceinline__ void reg_set(double (&A)[NC], int j, double v) {
     default: break;
     }
 }
+#undef STOKES_REG_CASES
 
 struct GjLds {
     double col[2][GJ_MAX], row[2][GJ_MAX], inv[2];
