@@ -101,3 +101,25 @@ def test_three_particles_in_periphery_mixed_vs_oracle(S, oracle_mod):
     assert rel(U.cpu().numpy(), Ur) <= 2e-6
     assert rel(Om.cpu().numpy(), Omr) <= 2e-6
     assert rel(q.cpu().numpy(), xr[:, : sysm.Ms]) <= 2e-6
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_ragged_particles_share_tiles(S, oracle_mod, mixed):
+    # particles of 91, 66 and 135 points: in the one double-layer sum over all particles,
+    # 32-source tiles straddle two particles, so the same-surface test runs per pair
+    rng = np.random.default_rng(9)
+    per = sphere(14, 28, 3.0)
+    Xs = [np.array([0.9, 0.3, -0.2]), np.array([-1.0, 0.7, 0.5]), np.array([0.2, -1.1, 0.8])]
+    shapes = [(7, 13), (6, 11), (9, 15)]
+    parts = [(*sphere(a, b, r, X), X) for (a, b), r, X in zip(shapes, (0.5, 0.35, 0.45), Xs)]
+    assert [p[0].shape[1] for p in parts] == [91, 66, 135]
+    F = rng.standard_normal((3, 3))
+    L = rng.standard_normal((3, 3))
+    U, Om, q, res, it = S.particle_solve(parts, F, L, periphery=per, mu=MU, iters=25, mixed=mixed)
+    sysm = oracle_mod.ParticleSystem(per, parts, MU)
+    Ur, Omr, xr, h, m = oracle_mod.particle_solve(sysm, F, L, 25)
+    tol = 1e-10 if not mixed else 2e-6
+    assert it == m
+    assert rel(U.cpu().numpy(), Ur) <= tol
+    assert rel(Om.cpu().numpy(), Omr) <= tol
+    assert rel(q.cpu().numpy(), xr[:, : sysm.Ms]) <= 10 * tol
