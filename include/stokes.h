@@ -337,9 +337,11 @@ int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const 
  *   holds the geometry on the device until stokes_tree_destroy.  Synchronous.
  * stokes_tree_sl_eval  one sum on a plan: src_force [3*n_src], src_weight
  *   [n_src] or NULL, src_fiber / fiber_len as in stokes_sl_eval (or both NULL:
- *   L = 1), mu, eps, near_r; flags STOKES_PREC_*, STOKES_EXCL_SELF_POINT (plans
- *   built with targets = sources only), STOKES_NO_DOUBLET, STOKES_ACCUMULATE;
- *   u_out [3*n_trg].  Asynchronous on stream; the plan's buffers are reused, so
+ *   L = 1), mu, eps, near_r; flags STOKES_PREC_*, STOKES_EXCL_SELF_POINT or
+ *   STOKES_EXCL_SAME_FIBER (one of the two; plans built with targets = sources
+ *   only; the fiber mode needs src_fiber, non-decreasing as in stokes_sl_eval, and
+ *   subtracts exactly the own-fiber sources that the far field took through
+ *   proxies), STOKES_NO_DOUBLET, STOKES_ACCUMULATE; u_out [3*n_trg].  Asynchronous on stream; the plan's buffers are reused, so
  *   evaluations on one plan must not overlap.
  * stokes_tree_info     pair counts of one evaluation (targets x proxies and
  *   targets x direct sources), proxy clusters and target batches.

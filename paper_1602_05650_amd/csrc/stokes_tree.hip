@@ -163,10 +163,11 @@ struct DevCl {              // what the kernels need of a proxy cluster
 __global__ __launch_bounds__(TB) void k_tr_src(int64_t ns, const int64_t* sperm, const double* f,
                                                const double* w, const int32_t* fib, const double* flen,
                                                double pref, double eps, double near_r, int doublet,
-                                               double* ss, double* sc, float* st) {
+                                               double* ss, double* sc, float* st, int32_t* sfid) {
     const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (j >= ns) return;
     const int64_t o = sperm[j];
+    if (sfid) sfid[j] = fib[o];
     const double wj = w ? w[o] : 1.0;
     const double L = (fib && flen) ? flen[fib[o]] : 1.0;
     const double a = eps * L;
@@ -177,6 +178,25 @@ __global__ __launch_bounds__(TB) void k_tr_src(int64_t ns, const int64_t* sperm,
     sc[j] = doublet ? 0.5 * a * a : 0.0;
     const double tr = fmax(near_r, 2.0 * a);
     st[j] = (float)(tr * tr);
+}
+
+// Source index range [x, y) of the fiber of every source o (fiber ids non-decreasing,
+// so the range is found by two binary searches; indices stay in [0, ns] whatever the ids).
+__global__ __launch_bounds__(TB) void k_tr_frange(int64_t ns, const int32_t* fib, int2* fr) {
+    const int64_t o = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (o >= ns) return;
+    const int32_t f = fib[o];
+    int64_t lo = 0, hi = o;            // first index in [0, o] with id >= f
+    while (lo < hi) {
+        const int64_t m = (lo + hi) >> 1;
+        if (fib[m] < f) lo = m + 1; else hi = m;
+    }
+    int64_t lo2 = o + 1, hi2 = ns;     // first index in [o + 1, ns) with id > f
+    while (lo2 < hi2) {
+        const int64_t m = (lo2 + hi2) >> 1;
+        if (fib[m] <= f) lo2 = m + 1; else hi2 = m;
+    }
+    fr[o] = make_int2((int)lo, (int)lo2);
 }
 
 // Chebyshev points of the second kind, cos(i pi / n), and their barycentric weights.
@@ -309,6 +329,11 @@ struct EvalArgs {
     const int32_t* dr_count;
     double* out;
     int accumulate;
+    // same-fiber exclusion (targets = sources)
+    const int32_t* sfib;     // [ns] fiber id of each source, original order
+    const int32_t* sfid;     // [ns] fiber id of each sorted source
+    const int2* frange;      // [ns] source range of each source's fiber, original order
+    const int32_t* sinv;     // [ns] sorted index of each original source
 };
 
 __device__ __forceinline__ void kahan(float& s, float& c, float x) {
@@ -387,8 +412,15 @@ __device__ __forceinline__ void far_tensor(const EvalArgs& a, int q, int l, floa
 }
 
 // (5 waves per SIMD: 96 VGPRs without spills; 6 would spill)
-template <bool MIXED, int DEG>
-__global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) void k_tr_eval(EvalArgs a) {
+// EXF: same-fiber exclusion (targets = sources).  The near field skips every source of
+// the target's fiber; the target's own-fiber sources that the batch took through proxy
+// clusters (those in none of its direct ranges, which are sorted by start and disjoint)
+// are subtracted as exact FP64 pairs, so that what remains of them is the
+// interpolation error of their share of the proxy charges.  Such sources are at least
+// (1 - theta) |c_B - c_C| from the target, so the subtraction is never singular.
+// (the EXF variant, 4 waves: its extra state would spill at 96 VGPRs)
+template <bool MIXED, int DEG, bool EXF = false>
+__global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4 : 5))) void k_tr_eval(EvalArgs a) {
     __shared__ __align__(16) float lfs[EW][64][12];    // (a DEG <= 8 slab: 8 (DEG+1)^2 <= 768 floats)
     __shared__ double lds_[EW][64][10];
     __shared__ double comb[EW / 2][3][64];              // the second half's sums of each batch
@@ -412,6 +444,9 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) vo
     const double cx = B.c[0], cy = B.c[1], cz = B.c[2];
     const double x = a.txyz[ti], y = a.txyz[a.nt + ti], z = a.txyz[2 * a.nt + ti];
     const int64_t self = a.tself ? a.tself[ti] : -1;
+    const int64_t o_exf = EXF ? a.tperm[ti] : 0;
+    const int32_t tf = EXF ? a.sfib[o_exf] : 0;   // the target's fiber
+    const int* fidl = reinterpret_cast<const int*>(&lf[0][0]) + 8 * 64;   // after the 64 source records
     const float xl = (float)(x - cx), yl = (float)(y - cy), zl = (float)(z - cz);
     float S0 = 0.f, S1 = 0.f, S2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     double u0 = 0.0, u1 = 0.0, u2 = 0.0;
@@ -505,6 +540,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) vo
                                        (float)(a.sxyz[2 * a.ns + j] - cz), (float)a.sc[j]);
                     r[1] = make_float4((float)a.ss[j], (float)a.ss[a.ns + j], (float)a.ss[2 * a.ns + j],
                                        a.st[j]);
+                    if (EXF) reinterpret_cast<int*>(&lf[0][0])[8 * 64 + l] = a.sfid[j];
                 } else {
                     ld[l][0] = a.sxyz[j];
                     ld[l][1] = a.sxyz[a.ns + j];
@@ -513,6 +549,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) vo
                     ld[l][4] = a.ss[a.ns + j];
                     ld[l][5] = a.ss[2 * a.ns + j];
                     ld[l][6] = a.sc[j];
+                    if (EXF) ld[l][7] = (double)a.sfid[j];
                 }
             }
             wave_sync();
@@ -542,6 +579,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) vo
                 if (gap > 0.f && gap * gap > 1.01f * tm) {
 #pragma unroll 8
                     for (int k = 0; k < m; ++k) {
+                        if (EXF && fidl[k] == tf) continue;
                         const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
                         const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -556,6 +594,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) vo
                     }
                 } else {
                     for (int k = 0; k < m; ++k) {
+                        if (EXF && fidl[k] == tf) continue;
                         const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
                         const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -588,10 +627,32 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) vo
             } else {
                 for (int k = 0; k < m; ++k) {
                     if (j0s + k0 + k == self) continue;
+                    if (EXF && ld[k][7] == (double)tf) continue;
                     const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
                     if (dx == 0.0 && dy == 0.0 && dz == 0.0) continue;
                     pair64(dx, dy, dz, ld[k][3], ld[k][4], ld[k][5], ld[k][6], u0, u1, u2);
                 }
+            }
+        }
+    }
+    if constexpr (EXF) {
+        if (live && act) {
+            const int2 fr = a.frange[o_exf];
+            for (int jo = fr.x + h; jo < fr.y; jo += 2) {     // the two waves take alternate sources
+                const int64_t js = a.sinv[jo];
+                int lo = da, hi = dz;                         // first direct range starting after js
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.dr_start[mid] <= js) lo = mid + 1; else hi = mid;
+                }
+                if (lo > da && js < a.dr_start[lo - 1] + a.dr_count[lo - 1]) continue;   // masked above
+                const double ex = x - a.sxyz[js], ey = y - a.sxyz[a.ns + js], ez = z - a.sxyz[2 * a.ns + js];
+                if (ex == 0.0 && ey == 0.0 && ez == 0.0) continue;
+                double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+                pair64(ex, ey, ez, a.ss[js], a.ss[a.ns + js], a.ss[2 * a.ns + js], a.sc[js], v0, v1, v2);
+                u0 -= v0;
+                u1 -= v1;
+                u2 -= v2;
             }
         }
     }
@@ -611,7 +672,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(5))) vo
     r0 += comb[w >> 1][0][l];
     r1 += comb[w >> 1][1][l];
     r2 += comb[w >> 1][2][l];
-    const int64_t o = a.tperm[ti];
+    const int64_t o = EXF ? o_exf : a.tperm[ti];
     if (a.accumulate) {
         a.out[o] += r0;
         a.out[a.nt + o] += r1;
@@ -658,6 +719,9 @@ struct stokes_tree {
     float* st = nullptr;
     float4* pk = nullptr;
     double* p1d = nullptr;
+    int32_t* sinv = nullptr;      // targets = sources only: sorted index of each source,
+    int32_t* sfid = nullptr;      // fiber id of each sorted source and
+    int2* frange = nullptr;       // the source range of each source's fiber (filled per evaluation)
     int32_t n_items = 0;
     ChargeItem* items = nullptr;
     int32_t* item_off = nullptr;
@@ -792,11 +856,12 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     for (int64_t i = 0; i < n_trg; ++i)
         for (int d = 0; d < 3; ++d) txs[d * n_trg + i] = tx[d * n_trg + tperm[i]];
     std::vector<int64_t> tself;
+    std::vector<int32_t> sinv;
     if (same) {
-        std::vector<int64_t> inv(n_src);
-        for (int64_t j = 0; j < n_src; ++j) inv[sperm[j]] = j;
+        sinv.resize(n_src);
+        for (int64_t j = 0; j < n_src; ++j) sinv[sperm[j]] = (int32_t)j;
         tself.resize(n_trg);
-        for (int64_t i = 0; i < n_trg; ++i) tself[i] = inv[tperm[i]];
+        for (int64_t i = 0; i < n_trg; ++i) tself[i] = sinv[tperm[i]];
     }
 
     // one device allocation
@@ -825,7 +890,8 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
                  o_ds = take(dr_start.size() * 8), o_dc = take(dr_count.size() * 4), o_ss = take(3 * n_src * 8),
                  o_sc = take(n_src * 8), o_st = take(n_src * 4), o_it = take(items.size() * sizeof(ChargeItem)),
                  o_io = take(item_off.size() * 4), o_pa = take(items.size() * 6 * P * 8),
-                 o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8);
+                 o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8),
+                 o_si = take(sinv.size() * 4), o_sf = take(sinv.size() * 4), o_fr = take(sinv.size() * 8);
     hipError_t e = hipMalloc(&t->mem, off);
     if (e != hipSuccess) {
         delete t;
@@ -856,6 +922,11 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     t->part = reinterpret_cast<double*>(base + o_pa);
     t->pk = reinterpret_cast<float4*>(base + o_pk);
     t->p1d = reinterpret_cast<double*>(base + o_p1);
+    if (same) {
+        t->sinv = reinterpret_cast<int32_t*>(base + o_si);
+        t->sfid = reinterpret_cast<int32_t*>(base + o_sf);
+        t->frange = reinterpret_cast<int2*>(base + o_fr);
+    }
     auto up = [&](void* dst, const void* src, size_t bytes) -> int {
         if (!bytes) return STOKES_OK;
         hipError_t r = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
@@ -867,6 +938,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     if (!rc) rc = up(t->txyz, txs.data(), txs.size() * 8);
     if (!rc) rc = up(t->tperm, tperm.data(), n_trg * 8);
     if (!rc && same) rc = up(t->tself, tself.data(), tself.size() * 8);
+    if (!rc && same) rc = up(t->sinv, sinv.data(), sinv.size() * 4);
     if (!rc) rc = up(t->bt, bt.data(), bt.size() * sizeof(Batch));
     if (!rc) rc = up(t->px_off, px_off.data(), px_off.size() * 4);
     if (!rc) rc = up(t->px_list, px_list.data(), px_list.size() * 4);
@@ -890,18 +962,39 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     return STOKES_OK;
 }
 
+template <bool EXF>
+static void launch_eval(bool mixed, int deg, unsigned grid, dim3 blk, hipStream_t st, const EvalArgs& a) {
+    if (!mixed) {
+        hipLaunchKernelGGL((k_tr_eval<false, 0, EXF>), dim3(grid), blk, 0, st, a);
+        return;
+    }
+    switch (deg) {   // the tensor-grid far field for the common degrees
+        case 4: hipLaunchKernelGGL((k_tr_eval<true, 4, EXF>), dim3(grid), blk, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_tr_eval<true, 5, EXF>), dim3(grid), blk, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_tr_eval<true, 6, EXF>), dim3(grid), blk, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_tr_eval<true, 7, EXF>), dim3(grid), blk, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_tr_eval<true, 8, EXF>), dim3(grid), blk, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_tr_eval<true, 0, EXF>), dim3(grid), blk, 0, st, a); break;
+    }
+}
+
 extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, const double* src_weight,
                                    const int32_t* src_fiber, const double* fiber_len, double mu,
                                    double eps, double near_r, uint32_t flags, double* u_out,
                                    void* stream) {
     if (!t) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: null tree");
-    if (flags & ~(STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_NO_DOUBLET | STOKES_ACCUMULATE))
+    if (flags & ~(STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_EXCL_SAME_FIBER | STOKES_NO_DOUBLET |
+                  STOKES_ACCUMULATE))
         return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: unsupported flag bits");
-    if ((flags & STOKES_EXCL_SELF_POINT) && !t->same)
-        return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: self exclusion needs targets = sources");
+    const bool exf = flags & STOKES_EXCL_SAME_FIBER;
+    if (exf && (flags & STOKES_EXCL_SELF_POINT))
+        return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: choose one exclusion mode");
+    if ((flags & (STOKES_EXCL_SELF_POINT | STOKES_EXCL_SAME_FIBER)) && !t->same)
+        return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: exclusion needs targets = sources");
     if (!src_force || !u_out) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: null pointer");
     if ((src_fiber == nullptr) != (fiber_len == nullptr))
         return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: src_fiber and fiber_len go together");
+    if (exf && !src_fiber) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: same-fiber exclusion needs src_fiber");
     if (!(mu > 0.0)) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: mu must be > 0");
     if (!(eps > 0.0 && eps < 0.5)) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: eps must be in (0, 0.5)");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -909,7 +1002,10 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
     const double pref = 1.0 / (8.0 * 3.14159265358979323846 * mu);
     hipLaunchKernelGGL(k_tr_src, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, t->sperm,
                        src_force, src_weight, src_fiber, fiber_len, pref, eps, near_r,
-                       (flags & STOKES_NO_DOUBLET) ? 0 : 1, t->ss, t->sc, t->st);
+                       (flags & STOKES_NO_DOUBLET) ? 0 : 1, t->ss, t->sc, t->st, exf ? t->sfid : nullptr);
+    if (exf)
+        hipLaunchKernelGGL(k_tr_frange, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, src_fiber,
+                           t->frange);
     if (t->n_px > 0) {
         hipLaunchKernelGGL(k_tr_charges, dim3(t->n_items), dim3(CB), 0, st, t->deg, (const DevCl*)t->px_cl,
                            (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns, (const double*)t->ss,
@@ -945,20 +1041,16 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
     a.dr_count = t->dr_count;
     a.out = u_out;
     a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
+    a.sfib = src_fiber;
+    a.sfid = t->sfid;
+    a.frange = t->frange;
+    a.sinv = t->sinv;
     const unsigned grid = (unsigned)((t->nb + EW / 2 - 1) / (EW / 2));
     const dim3 blk(64 * EW);
-    if (!mixed) {
-        hipLaunchKernelGGL((k_tr_eval<false, 0>), dim3(grid), blk, 0, st, a);
-    } else {
-        switch (t->deg) {   // the tensor-grid far field for the common degrees
-            case 4: hipLaunchKernelGGL((k_tr_eval<true, 4>), dim3(grid), blk, 0, st, a); break;
-            case 5: hipLaunchKernelGGL((k_tr_eval<true, 5>), dim3(grid), blk, 0, st, a); break;
-            case 6: hipLaunchKernelGGL((k_tr_eval<true, 6>), dim3(grid), blk, 0, st, a); break;
-            case 7: hipLaunchKernelGGL((k_tr_eval<true, 7>), dim3(grid), blk, 0, st, a); break;
-            case 8: hipLaunchKernelGGL((k_tr_eval<true, 8>), dim3(grid), blk, 0, st, a); break;
-            default: hipLaunchKernelGGL((k_tr_eval<true, 0>), dim3(grid), blk, 0, st, a); break;
-        }
-    }
+    if (exf)
+        launch_eval<true>(mixed, t->deg, grid, blk, st, a);
+    else
+        launch_eval<false>(mixed, t->deg, grid, blk, st, a);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }

@@ -382,7 +382,9 @@ class Tree:
 
     def sl_eval(self, force, src_fiber=None, fiber_len=None, src_weight=None, mu=1.0, eps=0.01,
                 near_r=0.0, excl_self=True, mixed=False, doublet=True, out=None, accumulate=False,
-                stream=None):
+                stream=None, excl_fiber=False):
+        """excl_fiber: skip every source of the target's fiber (plans with targets = sources;
+        needs src_fiber) instead of only the target's own point."""
         _dev(force, torch.float64, "force", (3, self.n_src))
         if src_fiber is not None:
             _dev(src_fiber, torch.int32, "src_fiber", (self.n_src,))
@@ -391,7 +393,8 @@ class Tree:
             _dev(src_weight, torch.float64, "src_weight", (self.n_src,))
         if out is None:
             out = torch.zeros((3, self.n_trg), dtype=torch.float64, device=force.device)
-        flags = ((PREC_MIXED if mixed else PREC_FP64) | (EXCL_SELF_POINT if excl_self else 0)
+        excl = EXCL_SAME_FIBER if excl_fiber else (EXCL_SELF_POINT if excl_self else 0)
+        flags = ((PREC_MIXED if mixed else PREC_FP64) | excl
                  | (0 if doublet else NO_DOUBLET) | (ACCUMULATE if accumulate else 0))
         nz = lambda t: None if t is None else _ptr(t)
         _check(_lib.stokes_tree_sl_eval(self._h, _ptr(force), nz(src_weight), nz(src_fiber),

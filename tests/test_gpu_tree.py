@@ -117,3 +117,47 @@ def test_tree_spindle_sampled(S, oracle_mod):
     print(f"spindle: err {err:.2e}, pair work {(info['proxy_pairs'] + info['direct_pairs']) / (n * n):.3f} "
           f"of direct, {info}")
     assert err <= 2e-6
+
+
+@pytest.fixture(scope="module")
+def long_fibers():
+    # 96 straight fibers of length 5 (128 nodes each) with centres in a ball of radius
+    # 2.5: a fiber spans several source clusters, so the far parts of a target's own
+    # fiber reach it through proxy clusters (67605 target / own-fiber-source pairs on the
+    # plan below; left in, they would change the result by 1.3e-3 of max |u|)
+    g = np.random.default_rng(11)
+    fs = W.random_fibers_in_ball(g, 96, 128, 2.5, L=5.0, eps=0.01, gap=None)
+    f = np.random.default_rng(12).standard_normal((3, fs.n))
+    return fs, f
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_tree_same_fiber_exclusion_vs_oracle(S, oracle_mod, long_fibers, mixed):
+    fs, f = long_fibers
+    ref = oracle_mod.sl(fs.xyz, f, src_fiber=fs.fiber, fiber_len=fs.length, eps=fs.eps, excl=2, nthreads=16)
+    kw = dict(src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length), eps=fs.eps, mixed=mixed)
+    T = S.Tree(dev(fs.xyz), degree=7, theta=0.6, leaf_size=64)
+    u = T.sl_eval(dev(f), excl_fiber=True, **kw).cpu().numpy()
+    err = relmax(u, ref)
+    print(f"same-fiber exclusion, mixed {mixed}: err {err:.2e}, {T.info()}")
+    assert T.info()["proxy_pairs"] > 0
+    assert err <= 2e-6
+    # every interaction direct: the masked near field alone is the exact sum
+    T1 = S.Tree(dev(fs.xyz), degree=4, theta=0.5, leaf_size=1 << 20)
+    u1 = T1.sl_eval(dev(f), excl_fiber=True, **kw).cpu().numpy()
+    assert T1.info()["proxy_pairs"] == 0
+    if mixed:
+        assert relmax(u1, ref) <= 2e-6
+    else:
+        assert np.linalg.norm(u1 - ref) / np.linalg.norm(ref) <= 1e-13
+
+
+def test_tree_same_fiber_exclusion_arguments(S, long_fibers):
+    fs, f = long_fibers
+    T = S.Tree(dev(fs.xyz), degree=4, theta=0.6, leaf_size=64)
+    with pytest.raises(S.StokesError):
+        T.sl_eval(dev(f), excl_fiber=True)                    # needs the fiber ids
+    Tt = S.Tree(dev(fs.xyz), dev(fs.xyz[:, :100]), degree=4, theta=0.6, leaf_size=64)
+    with pytest.raises(S.StokesError):
+        Tt.sl_eval(dev(f), src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length),
+                   excl_fiber=True)                           # targets = sources only
