@@ -210,8 +210,9 @@ __device__ __forceinline__ double cheb_bw(int i, int n) {
 // sources of one proxy cluster: it forms the partial charges of that piece for
 // every proxy (one proxy per thread, CB at a time), with the 1-D barycentric basis
 // values of SRC_TILE sources at a time staged in LDS.  Then k_tr_charges_sum adds
-// each cluster's pieces in a fixed order: F_k = sum_j L_k(y_j) s_j,
-// D_k = sum_j L_k(y_j) c_j s_j.
+// each cluster's pieces in a fixed order.  Single layer (6 per proxy):
+// F_k = sum_j L_k(y_j) s_j, D_k = sum_j L_k(y_j) c_j s_j.  Double layer (12):
+// M_k = sum_j L_k(y_j) q_j (w_j n_j)^T (row-major 3 x 3), N_k = sum_j L_k(y_j) w_j n_j.
 constexpr int CB = 512;
 constexpr int SRC_TILE = 160;      // 3 * SRC_TILE <= CB threads compute basis values
 constexpr int64_t CH_SRC = 4096;
@@ -221,20 +222,26 @@ struct ChargeItem {
     int64_t start;
 };
 
+// ss: [3][ns] sorted s_j (single layer) or w_j n_j (double layer); aux: [ns] c_j or
+// [3][ns] q_j.
+template <bool DL>
 __global__ __launch_bounds__(CB) void k_tr_charges(int deg, const DevCl* cls, const ChargeItem* items,
                                                    const double* sxyz, int64_t ns, const double* ss,
-                                                   const double* sc, double* part) {
+                                                   const double* aux, double* part) {
+    constexpr int NC = DL ? 12 : 6;
     __shared__ double lb[3][SRC_TILE][MAX_DEG + 1];
-    __shared__ double sv[6][SRC_TILE];
+    __shared__ double sv[NC][SRC_TILE];
     const int t = threadIdx.x;
     const ChargeItem it = items[blockIdx.x];
     const DevCl* Cp = cls + it.q;            // (the box is indexed per thread: no private copy)
     const int n1 = deg + 1, P = n1 * n1 * n1;
-    double* out = part + (int64_t)blockIdx.x * 6 * P;
+    double* out = part + (int64_t)blockIdx.x * NC * P;
     for (int k0 = 0; k0 < P; k0 += CB) {
         const int k = k0 + t;
         const int kx = k / (n1 * n1), ky = (k / n1) % n1, kz = k % n1;
-        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double acc[NC];
+#pragma unroll
+        for (int b = 0; b < NC; ++b) acc[b] = 0.0;
         for (int j0 = 0; j0 < it.count; j0 += SRC_TILE) {
             const int m = min(SRC_TILE, it.count - j0);
             __syncthreads();
@@ -255,12 +262,17 @@ __global__ __launch_bounds__(CB) void k_tr_charges(int deg, const DevCl* cls, co
                         const double dx = x - cheb_node(i, deg);
                         lb[d][jj][i] = hit >= 0 ? (i == hit ? 1.0 : 0.0) : cheb_bw(i, deg) / dx / den;
                     }
-                    if (d == 0) {
-                        const double cj = sc[j];
+                    if (d == 0 && !DL) {
+                        const double cj = aux[j];
                         for (int c = 0; c < 3; ++c) {
                             sv[c][jj] = ss[c * ns + j];
                             sv[3 + c][jj] = cj * ss[c * ns + j];
                         }
+                    }
+                    if (d == 0 && DL) {
+                        for (int r = 0; r < 3; ++r)
+                            for (int c = 0; c < 3; ++c) sv[3 * r + c][jj] = aux[r * ns + j] * ss[c * ns + j];
+                        for (int c = 0; c < 3; ++c) sv[9 + c][jj] = ss[c * ns + j];
                     }
                 }
             }
@@ -269,26 +281,27 @@ __global__ __launch_bounds__(CB) void k_tr_charges(int deg, const DevCl* cls, co
                 for (int jj = 0; jj < m; ++jj) {
                     const double L = lb[0][jj][kx] * lb[1][jj][ky] * lb[2][jj][kz];
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) acc[b] = fma(L, sv[b][jj], acc[b]);
+                    for (int b = 0; b < NC; ++b) acc[b] = fma(L, sv[b][jj], acc[b]);
                 }
         }
         if (k < P)
-            for (int b = 0; b < 6; ++b) out[b * P + k] = acc[b];
+            for (int b = 0; b < NC; ++b) out[b * P + k] = acc[b];
     }
 }
 
-// F and D of every proxy cluster: its pieces summed in item order.
+// The NC charges of every proxy cluster: its pieces summed in item order.  The first
+// NA components go to pA ([n_px][NA][P]: F, or M), the others to pB (D, or N).
 __global__ __launch_bounds__(TB) void k_tr_charges_sum(int P, const int32_t* item_off, const double* part,
-                                                       double* pF, double* pD) {
+                                                       double* pA, double* pB, int NC, int NA) {
     const int q = blockIdx.x;
-    for (int e = threadIdx.x; e < 6 * P; e += TB) {
+    for (int e = threadIdx.x; e < NC * P; e += TB) {
         double s = 0.0;
-        for (int i = item_off[q]; i < item_off[q + 1]; ++i) s += part[(int64_t)i * 6 * P + e];
+        for (int i = item_off[q]; i < item_off[q + 1]; ++i) s += part[(int64_t)i * NC * P + e];
         const int b = e / P, k = e - b * P;
-        if (b < 3)
-            pF[((int64_t)q * 3 + b) * P + k] = s;
+        if (b < NA)
+            pA[((int64_t)q * NA + b) * P + k] = s;
         else
-            pD[((int64_t)q * 3 + b - 3) * P + k] = s;
+            pB[((int64_t)q * (NC - NA) + b - NA) * P + k] = s;
     }
 }
 
@@ -684,6 +697,168 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
     }
 }
 
+// ---- double layer ---------------------------------------------------------------
+// u_i = (3 / (4 pi)) sum_{s != self} (d . (q_s - q0))(d . w_s n_s) d / |d|^5 - q0 / 2
+// (d = x_i - y_s; q0 = q_self on the surface with subtraction, else 0 and no -q0/2).
+// On a proxy p_k the sum over its cluster's sources becomes
+// (d^T M_k d - (d . q0)(d . N_k)) d / |d|^5, d = x_i - p_k.
+
+// Sorted double-layer sources: wn = w n, q.
+__global__ __launch_bounds__(TB) void k_tr_dlsrc(int64_t ns, const int64_t* sperm, const double* n,
+                                                 const double* w, const double* q, double* wn, double* sq) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= ns) return;
+    const int64_t o = sperm[j];
+    const double wj = w[o];
+    for (int c = 0; c < 3; ++c) {
+        wn[c * ns + j] = wj * n[c * ns + o];
+        sq[c * ns + j] = q[c * ns + o];
+    }
+}
+
+struct DlArgs {
+    int64_t ns, nt;
+    const double* sxyz;      // [3][ns] sorted sources
+    const double* wn;        // [3][ns] w n
+    const double* sq;        // [3][ns] q
+    const double* txyz;      // [3][nt] sorted targets
+    const int64_t* tperm;
+    const int64_t* tself;    // [nt] sorted source index of the target, or null (off the surface)
+    const Batch* bt;
+    int32_t nb;
+    const int32_t* px_off;
+    const int32_t* px_list;
+    const double* px_pos;    // [n_px][3][P]
+    const double* pM;        // [n_px][9][P]
+    const double* pN;        // [n_px][3][P]
+    int32_t P;
+    const int32_t* dr_off;
+    const int64_t* dr_start;
+    const int32_t* dr_count;
+    double* out;
+    int accumulate, subtract;
+};
+
+// FP64.  Waves 2k and 2k+1 take the halves of batch b's proxy and direct lists, as in
+// k_tr_eval, and the halves are added in that order.
+__global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
+    __shared__ double lds_[EW][64][15];
+    __shared__ double comb[EW / 2][3][64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int h = w & 1, b_raw = blockIdx.x * (EW / 2) + (w >> 1);
+    const bool live = b_raw < a.nb;
+    const int b = live ? b_raw : a.nb - 1;
+    const int pa = a.px_off[b], pz = a.px_off[b + 1], pm = pa + (pz - pa + 1) / 2;
+    const int p_lo = !live ? 0 : (h ? pm : pa), p_hi = !live ? 0 : (h ? pz : pm);
+    const int da = a.dr_off[b], dz = a.dr_off[b + 1], dm = da + (dz - da + 1) / 2;
+    const int d_lo = !live ? 0 : (h ? dm : da), d_hi = !live ? 0 : (h ? dz : dm);
+    double (*ld)[15] = lds_[w];
+    const Batch B = a.bt[b];
+    const bool act = l < B.count;
+    const int64_t ti = B.start + (act ? l : 0);
+    const double cx = B.c[0], cy = B.c[1], cz = B.c[2];
+    const double x = a.txyz[ti], y = a.txyz[a.nt + ti], z = a.txyz[2 * a.nt + ti];
+    const double xl = x - cx, yl = y - cy, zl = z - cz;
+    const int64_t self = a.tself ? a.tself[ti] : -1;
+    const bool sub = a.subtract && self >= 0;
+    const double q0x = sub ? a.sq[self] : 0.0, q0y = sub ? a.sq[a.ns + self] : 0.0,
+                 q0z = sub ? a.sq[2 * a.ns + self] : 0.0;
+    double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+    // far field: proxies
+    for (int e = p_lo; e < p_hi; ++e) {
+        const int q = a.px_list[e];
+        const double* pos = a.px_pos + (int64_t)q * 3 * a.P;
+        const double* M = a.pM + (int64_t)q * 9 * a.P;
+        const double* N = a.pN + (int64_t)q * 3 * a.P;
+        for (int k0 = 0; k0 < a.P; k0 += 64) {
+            const int m = min(64, a.P - k0);
+            wave_sync();
+            if (l < m) {
+                const int k = k0 + l;
+                ld[l][0] = pos[k] - cx;
+                ld[l][1] = pos[a.P + k] - cy;
+                ld[l][2] = pos[2 * a.P + k] - cz;
+                for (int c = 0; c < 9; ++c) ld[l][3 + c] = M[c * a.P + k];
+                for (int c = 0; c < 3; ++c) ld[l][12 + c] = N[c * a.P + k];
+            }
+            wave_sync();
+            for (int k = 0; k < m; ++k) {
+                const double dx = xl - ld[k][0], dy = yl - ld[k][1], dz = zl - ld[k][2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double ri = 1.0 / sqrt(r2);
+                const double ri2 = ri * ri, ri5 = ri2 * ri2 * ri;
+                const double m0 = ld[k][3] * dx + ld[k][4] * dy + ld[k][5] * dz;
+                const double m1 = ld[k][6] * dx + ld[k][7] * dy + ld[k][8] * dz;
+                const double m2 = ld[k][9] * dx + ld[k][10] * dy + ld[k][11] * dz;
+                const double dMd = dx * m0 + dy * m1 + dz * m2;
+                const double dN = dx * ld[k][12] + dy * ld[k][13] + dz * ld[k][14];
+                const double dq0 = dx * q0x + dy * q0y + dz * q0z;
+                const double kk = (dMd - dq0 * dN) * ri5;
+                u0 += kk * dx;
+                u1 += kk * dy;
+                u2 += kk * dz;
+            }
+        }
+    }
+    // near field: direct ranges
+    for (int e = d_lo; e < d_hi; ++e) {
+        const int64_t j0s = a.dr_start[e];
+        const int32_t cnt = a.dr_count[e];
+        for (int32_t k0 = 0; k0 < cnt; k0 += 64) {
+            const int m = min(64, cnt - k0);
+            wave_sync();
+            if (l < m) {
+                const int64_t j = j0s + k0 + l;
+                for (int c = 0; c < 3; ++c) {
+                    ld[l][c] = a.sxyz[c * a.ns + j];
+                    ld[l][3 + c] = a.wn[c * a.ns + j];
+                    ld[l][6 + c] = a.sq[c * a.ns + j];
+                }
+            }
+            wave_sync();
+            for (int k = 0; k < m; ++k) {
+                if (j0s + k0 + k == self) continue;
+                const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0) continue;                            // coincident: skipped
+                const double r = sqrt(r2), r5 = r2 * r2 * r;
+                const double dq = dx * (ld[k][6] - q0x) + dy * (ld[k][7] - q0y) + dz * (ld[k][8] - q0z);
+                const double dn = dx * ld[k][3] + dy * ld[k][4] + dz * ld[k][5];
+                const double kk = dq * dn / r5;
+                u0 += kk * dx;
+                u1 += kk * dy;
+                u2 += kk * dz;
+            }
+        }
+    }
+    if (h == 1) {
+        comb[w >> 1][0][l] = u0;
+        comb[w >> 1][1][l] = u1;
+        comb[w >> 1][2][l] = u2;
+    }
+    __syncthreads();
+    if (!live || h == 1 || !act) return;
+    const double pref = 3.0 / (4.0 * 3.14159265358979323846);
+    double r0 = pref * (u0 + comb[w >> 1][0][l]);
+    double r1 = pref * (u1 + comb[w >> 1][1][l]);
+    double r2 = pref * (u2 + comb[w >> 1][2][l]);
+    if (sub) {
+        r0 -= 0.5 * q0x;
+        r1 -= 0.5 * q0y;
+        r2 -= 0.5 * q0z;
+    }
+    const int64_t o = a.tperm[ti];
+    if (a.accumulate) {
+        a.out[o] += r0;
+        a.out[a.nt + o] += r1;
+        a.out[2 * a.nt + o] += r2;
+    } else {
+        a.out[o] = r0;
+        a.out[a.nt + o] = r1;
+        a.out[2 * a.nt + o] = r2;
+    }
+}
+
 }  // namespace tree
 }  // namespace stokes
 
@@ -711,12 +886,15 @@ struct stokes_tree {
     double* px_pos = nullptr;
     double* pF = nullptr;
     double* pD = nullptr;
+    double* pM = nullptr;
+    double* pN = nullptr;
     int32_t* dr_off = nullptr;
     int64_t* dr_start = nullptr;
     int32_t* dr_count = nullptr;
     double* ss = nullptr;
     double* sc = nullptr;
     float* st = nullptr;
+    double* sq = nullptr;         // [3][ns] sorted double-layer density
     float4* pk = nullptr;
     double* p1d = nullptr;
     int32_t* sinv = nullptr;      // targets = sources only: sorted index of each source,
@@ -886,10 +1064,11 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
                  o_tp = take(n_trg * 8), o_ts = take(tself.size() * 8), o_bt = take(bt.size() * sizeof(Batch)),
                  o_po = take(px_off.size() * 4), o_pl = take(px_list.size() * 4),
                  o_pc = take((size_t)n_px * sizeof(DevCl)), o_pp = take(ppos.size() * 8),
-                 o_pF = take(ppos.size() * 8), o_pD = take(ppos.size() * 8), o_do = take(dr_off.size() * 4),
+                 o_pF = take(ppos.size() * 4 * 8), o_do = take(dr_off.size() * 4),
                  o_ds = take(dr_start.size() * 8), o_dc = take(dr_count.size() * 4), o_ss = take(3 * n_src * 8),
                  o_sc = take(n_src * 8), o_st = take(n_src * 4), o_it = take(items.size() * sizeof(ChargeItem)),
-                 o_io = take(item_off.size() * 4), o_pa = take(items.size() * 6 * P * 8),
+                 o_io = take(item_off.size() * 4), o_pa = take(items.size() * 12 * P * 8),
+                 o_sq = take(3 * n_src * 8),
                  o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8),
                  o_si = take(sinv.size() * 4), o_sf = take(sinv.size() * 4), o_fr = take(sinv.size() * 8);
     hipError_t e = hipMalloc(&t->mem, off);
@@ -909,7 +1088,12 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     t->px_cl = reinterpret_cast<DevCl*>(base + o_pc);
     t->px_pos = reinterpret_cast<double*>(base + o_pp);
     t->pF = reinterpret_cast<double*>(base + o_pF);
-    t->pD = reinterpret_cast<double*>(base + o_pD);
+    // proxy charges, 12 P doubles per cluster: single layer F [n_px][3][P] then
+    // D [n_px][3][P]; double layer M [n_px][9][P] then N [n_px][3][P]
+    t->pD = t->pF + ppos.size();
+    t->pM = t->pF;
+    t->pN = t->pF + 3 * ppos.size();
+    t->sq = reinterpret_cast<double*>(base + o_sq);
     t->dr_off = reinterpret_cast<int32_t*>(base + o_do);
     t->dr_start = reinterpret_cast<int64_t*>(base + o_ds);
     t->dr_count = reinterpret_cast<int32_t*>(base + o_dc);
@@ -1007,11 +1191,11 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
         hipLaunchKernelGGL(k_tr_frange, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, src_fiber,
                            t->frange);
     if (t->n_px > 0) {
-        hipLaunchKernelGGL(k_tr_charges, dim3(t->n_items), dim3(CB), 0, st, t->deg, (const DevCl*)t->px_cl,
-                           (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns, (const double*)t->ss,
-                           (const double*)t->sc, t->part);
+        hipLaunchKernelGGL(k_tr_charges<false>, dim3(t->n_items), dim3(CB), 0, st, t->deg,
+                           (const DevCl*)t->px_cl, (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns,
+                           (const double*)t->ss, (const double*)t->sc, t->part);
         hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px), dim3(TB), 0, st, t->P, (const int32_t*)t->item_off,
-                           (const double*)t->part, t->pF, t->pD);
+                           (const double*)t->part, t->pF, t->pD, 6, 3);
         if (mixed)
             hipLaunchKernelGGL(k_tr_pack, dim3(t->n_px), dim3(TB), 0, st, t->P, (const double*)t->pF,
                                (const double*)t->pD, t->pk);
@@ -1051,6 +1235,54 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
         launch_eval<true>(mixed, t->deg, grid, blk, st, a);
     else
         launch_eval<false>(mixed, t->deg, grid, blk, st, a);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, const double* src_weight,
+                                   const double* src_q, uint32_t flags, double* u_out, void* stream) {
+    if (!t) return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: null tree");
+    if (flags & STOKES_PREC_MIXED)
+        return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: the double layer is evaluated in FP64 only");
+    if (flags & ~(STOKES_ONSURF_RAW | STOKES_ACCUMULATE))
+        return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: unsupported flag bits");
+    if (!src_normal || !src_weight || !src_q || !u_out)
+        return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: null pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_tr_dlsrc, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, t->sperm,
+                       src_normal, src_weight, src_q, t->ss, t->sq);
+    if (t->n_px > 0) {
+        hipLaunchKernelGGL(k_tr_charges<true>, dim3(t->n_items), dim3(CB), 0, st, t->deg,
+                           (const DevCl*)t->px_cl, (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns,
+                           (const double*)t->ss, (const double*)t->sq, t->part);
+        hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px), dim3(TB), 0, st, t->P, (const int32_t*)t->item_off,
+                           (const double*)t->part, t->pM, t->pN, 12, 9);
+    }
+    DlArgs a{};
+    a.ns = t->ns;
+    a.nt = t->nt;
+    a.sxyz = t->sxyz;
+    a.wn = t->ss;
+    a.sq = t->sq;
+    a.txyz = t->txyz;
+    a.tperm = t->tperm;
+    a.tself = t->same ? t->tself : nullptr;
+    a.bt = t->bt;
+    a.nb = t->nb;
+    a.px_off = t->px_off;
+    a.px_list = t->px_list;
+    a.px_pos = t->px_pos;
+    a.pM = t->pM;
+    a.pN = t->pN;
+    a.P = t->P;
+    a.dr_off = t->dr_off;
+    a.dr_start = t->dr_start;
+    a.dr_count = t->dr_count;
+    a.out = u_out;
+    a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
+    a.subtract = (flags & STOKES_ONSURF_RAW) ? 0 : 1;
+    const unsigned grid = (unsigned)((t->nb + EW / 2 - 1) / (EW / 2));
+    hipLaunchKernelGGL(k_tr_dl_eval, dim3(grid), dim3(64 * EW), 0, st, a);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }

@@ -78,6 +78,7 @@ def _load():
         "stokes_nonlocal_sbt": [I32, I32, P, P, P, P, D, D, P, P],
         "stokes_tree_create": [I64, P, I64, P, I32, D, I32, P, P],
         "stokes_tree_sl_eval": [P, P, P, P, P, D, D, D, U32, P, P],
+        "stokes_tree_dl_eval": [P, P, P, P, U32, P, P],
         "stokes_tree_info": [P, P, P, P, P],
         "stokes_tree_destroy": [P],
         "stokes_particle_solve": [I64, P, P, P, I32, P, P, P, P, P, P, P, D, D, I32, U32, P, P, P,
@@ -400,6 +401,19 @@ class Tree:
         _check(_lib.stokes_tree_sl_eval(self._h, _ptr(force), nz(src_weight), nz(src_fiber),
                                         nz(fiber_len), float(mu), float(eps), float(near_r), flags,
                                         _ptr(out), _stream(stream)))
+        return out
+
+    def dl_eval(self, normal, weight, q, raw=False, out=None, accumulate=False, stream=None):
+        """Double-layer sum of dl_eval on this plan, FP64.  Plans built with targets =
+        sources take the singularity subtraction unless raw."""
+        _dev(normal, torch.float64, "normal", (3, self.n_src))
+        _dev(weight, torch.float64, "weight", (self.n_src,))
+        _dev(q, torch.float64, "q", (3, self.n_src))
+        if out is None:
+            out = torch.zeros((3, self.n_trg), dtype=torch.float64, device=q.device)
+        flags = (ONSURF_RAW if raw else 0) | (ACCUMULATE if accumulate else 0)
+        _check(_lib.stokes_tree_dl_eval(self._h, _ptr(normal), _ptr(weight), _ptr(q), flags, _ptr(out),
+                                        _stream(stream)))
         return out
 
     def info(self):

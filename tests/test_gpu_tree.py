@@ -161,3 +161,89 @@ def test_tree_same_fiber_exclusion_arguments(S, long_fibers):
     with pytest.raises(S.StokesError):
         Tt.sl_eval(dev(f), src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length),
                    excl_fiber=True)                           # targets = sources only
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    # a sphere of radius 5 with 128 x 192 quadrature points (24576), random density; the
+    # oracle's sums at 1500 sampled surface points, with and without the subtraction
+    sph = W.sphere_surface(128, 192, 5.0)
+    q = np.random.default_rng(4).standard_normal((3, sph.n))
+    return sph, q
+
+
+@pytest.fixture(scope="module")
+def sphere_ref(oracle_mod, sphere):
+    sph, q = sphere
+    idx = W.subsample(9, sph.n, 1500)
+    return idx, {raw: oracle_mod.dl(sph.xyz, sph.normal, sph.weight, q, trg_xyz=sph.xyz[:, idx], trg_self=idx,
+                                    subtract=not raw, nthreads=16) for raw in (False, True)}
+
+
+# The stresslet's interpolation error is far larger than the Stokeslet's at the same
+# degree and theta (on the surface, the d.n factor nearly cancels for neighbouring
+# points in the exact kernel but not in the interpolated one), so these plans use
+# higher degrees than the single-layer ones.
+@pytest.mark.parametrize("degree,theta,tol", [(8, 0.5, 2e-7), (9, 0.5, 4e-8)])
+def test_tree_double_layer_vs_oracle(S, sphere, sphere_ref, degree, theta, tol):
+    sph, q = sphere
+    idx, ref = sphere_ref
+    T = S.Tree(dev(sph.xyz), degree=degree, theta=theta, leaf_size=64)
+    assert T.info()["proxy_pairs"] > 0
+    for raw in (False, True):
+        u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), raw=raw).cpu().numpy()
+        err = relmax(u[:, idx], ref[raw])
+        print(f"double layer, degree {degree} theta {theta} raw {raw}: err {err:.2e}, {T.info()}")
+        assert err <= tol
+
+
+def test_tree_double_layer_error_shrinks_with_degree(S, sphere, sphere_ref):
+    sph, q = sphere
+    idx, ref = sphere_ref
+    errs = []
+    for degree, theta in ((6, 0.7), (7, 0.6), (8, 0.5)):
+        T = S.Tree(dev(sph.xyz), degree=degree, theta=theta, leaf_size=64)
+        u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q)).cpu().numpy()
+        errs.append(relmax(u[:, idx], ref[False]))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] < 2e-7
+
+
+def test_tree_double_layer_all_direct_is_exact(S, oracle_mod):
+    c = W.config1()
+    sph, q = c["sphere"], c["q"]
+    ref = oracle_mod.dl(sph.xyz, sph.normal, sph.weight, q, nthreads=16)
+    T = S.Tree(dev(sph.xyz), degree=4, theta=0.5, leaf_size=1 << 20)
+    u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q)).cpu().numpy()
+    assert T.info()["proxy_pairs"] == 0
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) <= 1e-13
+
+
+def test_tree_double_layer_constant_density(S, sphere):
+    # q constant: with the subtraction every pair term is zero (a proxy's M_k is
+    # q N_k^T to rounding), so u = -q/2 at every surface point
+    sph, _ = sphere
+    q = np.tile(np.array([[0.3], [-1.1], [0.7]]), (1, sph.n))
+    T = S.Tree(dev(sph.xyz), degree=6, theta=0.7, leaf_size=64)
+    u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q)).cpu().numpy()
+    assert T.info()["proxy_pairs"] > 0
+    assert np.abs(u + 0.5 * q).max() <= 1e-12
+
+
+def test_tree_double_layer_off_surface_and_accumulate(S, oracle_mod, sphere):
+    sph, q = sphere
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal((3, 4000))
+    d /= np.linalg.norm(d, axis=0)
+    trg = d * rng.uniform(0.5, 9.0, 4000)              # inside and outside the sphere
+    ref = oracle_mod.dl(sph.xyz, sph.normal, sph.weight, q, trg_xyz=trg, nthreads=16)
+    T = S.Tree(dev(sph.xyz), dev(trg), degree=7, theta=0.6, leaf_size=64)
+    base = dev(np.ones((3, 4000)))
+    u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), out=base, accumulate=True).cpu().numpy()
+    err = relmax(u - 1.0, ref)
+    print(f"double layer off the surface: err {err:.2e}, {T.info()}")
+    assert err <= 2e-8
+    assert T.info()["proxy_pairs"] > 0
+    with pytest.raises(S.StokesError):                  # FP64 only
+        S._check(S._lib.stokes_tree_dl_eval(T._h, S._ptr(dev(sph.normal)), S._ptr(dev(sph.weight)),
+                                            S._ptr(dev(q)), S.PREC_MIXED, S._ptr(base), None))
