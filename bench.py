@@ -407,8 +407,9 @@ def fiberstep_run(S, torch, log_fn, reps=3, iters=60, tol=1e-5):
 
 def tree_run(S, torch, log_fn, degree=6, theta=0.7, leaf=128, reps=10):
     """Treecode single-layer sum on the spindle and the large confined fiber set: plan
-    build time, evaluation time (mixed and FP64), interactions per second, and the
-    error against the direct GPU sum on all targets."""
+    build time, evaluation time (mixed and FP64; mixed with same-fiber exclusion),
+    interactions per second, and the error against the direct GPU sum on all targets;
+    then the double layer on a sphere."""
     from paper_1602_05650_amd import workloads as W
     res = {"degree": degree, "theta": theta, "leaf_size": leaf}
     for name, gen in (("spindle_262k", W.config2), ("confined_524k_fibers", W.config4)):
@@ -440,9 +441,58 @@ def tree_run(S, torch, log_fn, degree=6, theta=0.7, leaf=128, reps=10):
                 "ms": round(dt * 1e3, 3), "interactions_per_s_g": round(n * (n - 1) / dt / 1e9, 1),
                 "err_vs_direct_relmax": float(f"{err:.3e}")}
             log_fn(f"tree {name} {'mixed' if mixed else 'fp64'}: {dt * 1e3:.2f} ms, err {err:.2e}")
+        # same-fiber exclusion, mixed, against the direct FP64 sum with the same exclusion
+        ref = S.sl_eval(X, F, src_fiber=FB, fiber_len=FL, eps=fs.eps, excl="fiber")
+        kw = dict(src_fiber=FB, fiber_len=FL, eps=fs.eps, mixed=True, excl_fiber=True, out=out)
+        T.sl_eval(F, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            T.sl_eval(F, **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        err = float((out - ref).abs().max() / ref.abs().max())
+        entry["mixed_excl_fiber"] = {"ms": round(dt * 1e3, 3), "err_vs_direct_relmax": float(f"{err:.3e}")}
+        log_fn(f"tree {name} mixed, same-fiber exclusion: {dt * 1e3:.2f} ms, err {err:.2e}")
         T.close()
         res[name] = entry
+    res["double_layer_sphere_393k"] = tree_dl_run(S, torch, log_fn)
     return res
+
+
+def tree_dl_run(S, torch, log_fn, degree=8, theta=0.5, leaf=64, reps=5):
+    """Treecode double-layer sum (FP64) on a sphere of radius 5 with 512 x 768 quadrature
+    points and random density, beside the direct FP64 sum: times and the error."""
+    from paper_1602_05650_amd import workloads as W
+    sph = W.sphere_surface(512, 768, 5.0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", torch.float64)
+    X, N, Wt = d(sph.xyz), d(sph.normal), d(sph.weight)
+    Q = d(np.random.default_rng(4).standard_normal((3, sph.n)))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    ref = S.dl_eval(X, N, Wt, Q)
+    t_direct = timed(lambda: S.dl_eval(X, N, Wt, Q, out=ref))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = S.Tree(X, degree=degree, theta=theta, leaf_size=leaf)
+    t_plan = time.perf_counter() - t0
+    out = torch.empty_like(ref)
+    t_tree = timed(lambda: T.dl_eval(N, Wt, Q, out=out))
+    err = float((out - ref).abs().max() / ref.abs().max())
+    entry = {"points": sph.n, "degree": degree, "theta": theta, "leaf_size": leaf, "plan_s": round(t_plan, 3),
+             **T.info(), "tree_ms": round(t_tree * 1e3, 3), "direct_fp64_ms": round(t_direct * 1e3, 3),
+             "err_vs_direct_relmax": float(f"{err:.3e}")}
+    T.close()
+    log_fn(f"tree double layer {sph.n}: {t_tree * 1e3:.2f} ms vs direct {t_direct * 1e3:.2f} ms, err {err:.2e}")
+    return entry
 
 
 def cpu_baseline(c, seconds, log_fn, other=True):
