@@ -356,11 +356,19 @@ __device__ __forceinline__ void kahan(float& s, float& c, float x) {
     s = t;
 }
 
+// 1/sqrt(x) in FP64 for x > 0: the hardware estimate y, then one third-order Newton
+// step y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2.
+__device__ __forceinline__ double rsq64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // FP64 single-layer pair (Stokeslet + doublet) into (ux, uy, uz).
 __device__ __forceinline__ void pair64(double dx, double dy, double dz, double sx, double sy, double sz,
                                        double c, double& ux, double& uy, double& uz) {
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double ri = 1.0 / sqrt(r2);
+    const double ri = rsq64(r2);
     const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
     const double ds = dx * sx + dy * sy + dz * sz;
     const double A = fma(c, ri3, ri);
@@ -521,7 +529,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
                 for (int k = 0; k < m; ++k) {
                     const double dx = (x - cx) - ld[k][0], dy = (y - cy) - ld[k][1], dz = (z - cz) - ld[k][2];
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    const double ri = 1.0 / sqrt(r2);
+                    const double ri = rsq64(r2);
                     const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
                     const double dF = dx * ld[k][3] + dy * ld[k][4] + dz * ld[k][5];
                     const double dD = dx * ld[k][6] + dy * ld[k][7] + dz * ld[k][8];
@@ -785,7 +793,7 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
             for (int k = 0; k < m; ++k) {
                 const double dx = xl - ld[k][0], dy = yl - ld[k][1], dz = zl - ld[k][2];
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const double ri = 1.0 / sqrt(r2);
+                const double ri = rsq64(r2);
                 const double ri2 = ri * ri, ri5 = ri2 * ri2 * ri;
                 const double m0 = ld[k][3] * dx + ld[k][4] * dy + ld[k][5] * dz;
                 const double m1 = ld[k][6] * dx + ld[k][7] * dy + ld[k][8] * dz;
@@ -821,10 +829,10 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
                 const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 == 0.0) continue;                            // coincident: skipped
-                const double r = sqrt(r2), r5 = r2 * r2 * r;
+                const double ri = rsq64(r2), ri2 = ri * ri;
                 const double dq = dx * (ld[k][6] - q0x) + dy * (ld[k][7] - q0y) + dz * (ld[k][8] - q0z);
                 const double dn = dx * ld[k][3] + dy * ld[k][4] + dz * ld[k][5];
-                const double kk = dq * dn / r5;
+                const double kk = dq * dn * (ri2 * ri2 * ri);
                 u0 += kk * dx;
                 u1 += kk * dy;
                 u2 += kk * dz;
