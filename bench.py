@@ -461,8 +461,9 @@ def tree_run(S, torch, log_fn, degree=6, theta=0.7, leaf=128, reps=10):
 
 
 def tree_dl_run(S, torch, log_fn, degree=8, theta=0.5, leaf=64, reps=5):
-    """Treecode double-layer sum (FP64) on a sphere of radius 5 with 512 x 768 quadrature
-    points and random density, beside the direct FP64 sum: times and the error."""
+    """Treecode double-layer sum on a sphere of radius 5 with 512 x 768 quadrature points
+    and random density, beside the direct sum: times (FP64 and mixed) and the errors
+    against the direct FP64 sum."""
     from paper_1602_05650_amd import workloads as W
     sph = W.sphere_surface(512, 768, 5.0)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", torch.float64)
@@ -487,11 +488,21 @@ def tree_dl_run(S, torch, log_fn, degree=8, theta=0.5, leaf=64, reps=5):
     out = torch.empty_like(ref)
     t_tree = timed(lambda: T.dl_eval(N, Wt, Q, out=out))
     err = float((out - ref).abs().max() / ref.abs().max())
+    t_tree_m = timed(lambda: T.dl_eval(N, Wt, Q, out=out, mixed=True, near_r=0.4))
+    err_m = float((out - ref).abs().max() / ref.abs().max())
+    out_d = torch.empty_like(ref)
+    t_direct_m = timed(lambda: S.dl_eval(X, N, Wt, Q, mixed=True, near_r=0.4, out=out_d))
+    err_dm = float((out_d - ref).abs().max() / ref.abs().max())
     entry = {"points": sph.n, "degree": degree, "theta": theta, "leaf_size": leaf, "plan_s": round(t_plan, 3),
              **T.info(), "tree_ms": round(t_tree * 1e3, 3), "direct_fp64_ms": round(t_direct * 1e3, 3),
-             "err_vs_direct_relmax": float(f"{err:.3e}")}
+             "err_vs_direct_relmax": float(f"{err:.3e}"), "tree_mixed_ms": round(t_tree_m * 1e3, 3),
+             "direct_mixed_ms": round(t_direct_m * 1e3, 3), "mixed_near_r": 0.4,
+             "mixed_err_vs_direct_relmax": float(f"{err_m:.3e}"),
+             "direct_mixed_err_vs_direct_relmax": float(f"{err_dm:.3e}")}
     T.close()
-    log_fn(f"tree double layer {sph.n}: {t_tree * 1e3:.2f} ms vs direct {t_direct * 1e3:.2f} ms, err {err:.2e}")
+    log_fn(f"tree double layer {sph.n}: {t_tree * 1e3:.2f} ms vs direct {t_direct * 1e3:.2f} ms, err {err:.2e}; "
+           f"mixed {t_tree_m * 1e3:.2f} ms (err {err_m:.2e}) vs direct mixed {t_direct_m * 1e3:.2f} ms "
+           f"(err {err_dm:.2e})")
     return entry
 
 

@@ -343,10 +343,12 @@ int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const 
  *   subtracts exactly the own-fiber sources that the far field took through
  *   proxies), STOKES_NO_DOUBLET, STOKES_ACCUMULATE; u_out [3*n_trg].  Asynchronous on stream; the plan's buffers are reused, so
  *   evaluations on one plan must not overlap.
- * stokes_tree_dl_eval  the double-layer sum of stokes_dl_eval on a plan, in FP64:
+ * stokes_tree_dl_eval  the double-layer sum of stokes_dl_eval on a plan:
  *   src_normal [3*n_src] outward unit normals, src_weight [n_src] area weights,
- *   src_q [3*n_src] density (all required); flags STOKES_ONSURF_RAW,
- *   STOKES_ACCUMULATE (STOKES_PREC_MIXED is rejected); u_out [3*n_trg].  A proxy
+ *   src_q [3*n_src] density (all required); near_r as in stokes_dl_eval (mixed
+ *   only: direct pairs closer than near_r in FP64; <= 0 selects 0.02); flags
+ *   STOKES_PREC_* (mixed: FP32 proxies and direct pairs), STOKES_ONSURF_RAW,
+ *   STOKES_ACCUMULATE; u_out [3*n_trg].  A proxy
  *   carries the charges M_k = sum L_k(y_j) q_j (w_j n_j)^T and
  *   N_k = sum L_k(y_j) w_j n_j, so that the singularity subtraction (q_j - q_i)
  *   of a surface target i carries over to the far field.  Plans built with
@@ -364,7 +366,8 @@ int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, const double* s
                         const int32_t* src_fiber, const double* fiber_len, double mu, double eps,
                         double near_r, uint32_t flags, double* u_out, void* stream);
 int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, const double* src_weight,
-                        const double* src_q, uint32_t flags, double* u_out, void* stream);
+                        const double* src_q, double near_r, uint32_t flags, double* u_out,
+                        void* stream);
 int stokes_tree_info(const stokes_tree* t, int64_t* proxy_pairs, int64_t* direct_pairs,
                      int32_t* n_proxy_clusters, int32_t* n_batches);
 int stokes_tree_destroy(stokes_tree* t);

@@ -745,12 +745,18 @@ struct DlArgs {
     const int32_t* dr_count;
     double* out;
     int accumulate, subtract;
+    float near2;             // mixed: FP64 below this squared distance
 };
 
-// FP64.  Waves 2k and 2k+1 take the halves of batch b's proxy and direct lists, as in
-// k_tr_eval, and the halves are added in that order.
+// Waves 2k and 2k+1 take the halves of batch b's proxy and direct lists, as in
+// k_tr_eval, and the halves are added in that order.  MIXED: proxies and direct pairs in
+// FP32 relative to the batch centre, each cluster's or chunk's sum added with Kahan
+// compensation; direct pairs closer than near_r (and the self point) are taken in FP64
+// from the sorted sources.
+template <bool MIXED>
 __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
     __shared__ double lds_[EW][64][15];
+    __shared__ float lfs[EW][64][16];
     __shared__ double comb[EW / 2][3][64];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int h = w & 1, b_raw = blockIdx.x * (EW / 2) + (w >> 1);
@@ -772,12 +778,53 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
     const double q0x = sub ? a.sq[self] : 0.0, q0y = sub ? a.sq[a.ns + self] : 0.0,
                  q0z = sub ? a.sq[2 * a.ns + self] : 0.0;
     double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+    float (*lf)[16] = lfs[w];
+    const float fxl = (float)xl, fyl = (float)yl, fzl = (float)zl;
+    const float fq0x = (float)q0x, fq0y = (float)q0y, fq0z = (float)q0z;
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     // far field: proxies
     for (int e = p_lo; e < p_hi; ++e) {
         const int q = a.px_list[e];
         const double* pos = a.px_pos + (int64_t)q * 3 * a.P;
         const double* M = a.pM + (int64_t)q * 9 * a.P;
         const double* N = a.pN + (int64_t)q * 3 * a.P;
+        if constexpr (MIXED) {
+            for (int k0 = 0; k0 < a.P; k0 += 64) {     // Kahan step per 64 proxies
+                const int m = min(64, a.P - k0);
+                float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+                wave_sync();
+                if (l < m) {
+                    const int k = k0 + l;
+                    lf[l][0] = (float)(pos[k] - cx);
+                    lf[l][1] = (float)(pos[a.P + k] - cy);
+                    lf[l][2] = (float)(pos[2 * a.P + k] - cz);
+                    for (int c = 0; c < 9; ++c) lf[l][3 + c] = (float)M[c * a.P + k];
+                    for (int c = 0; c < 3; ++c) lf[l][12 + c] = (float)N[c * a.P + k];
+                }
+                wave_sync();
+#pragma unroll 4
+                for (int k = 0; k < m; ++k) {
+                    const float dx = fxl - lf[k][0], dy = fyl - lf[k][1], dz = fzl - lf[k][2];
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float ri2 = ri * ri;
+                    const float m0 = fmaf(lf[k][3], dx, fmaf(lf[k][4], dy, lf[k][5] * dz));
+                    const float m1 = fmaf(lf[k][6], dx, fmaf(lf[k][7], dy, lf[k][8] * dz));
+                    const float m2 = fmaf(lf[k][9], dx, fmaf(lf[k][10], dy, lf[k][11] * dz));
+                    const float dMd = fmaf(dx, m0, fmaf(dy, m1, dz * m2));
+                    const float dN = fmaf(dx, lf[k][12], fmaf(dy, lf[k][13], dz * lf[k][14]));
+                    const float dq0 = fmaf(dx, fq0x, fmaf(dy, fq0y, dz * fq0z));
+                    const float kk = fmaf(-dq0, dN, dMd) * (ri2 * ri2 * ri);
+                    p0 = fmaf(kk, dx, p0);
+                    p1 = fmaf(kk, dy, p1);
+                    p2 = fmaf(kk, dz, p2);
+                }
+                kahan(S0, C0, p0);
+                kahan(S1, C1, p1);
+                kahan(S2, C2, p2);
+            }
+            continue;
+        }
         for (int k0 = 0; k0 < a.P; k0 += 64) {
             const int m = min(64, a.P - k0);
             wave_sync();
@@ -814,6 +861,60 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
         const int32_t cnt = a.dr_count[e];
         for (int32_t k0 = 0; k0 < cnt; k0 += 64) {
             const int m = min(64, cnt - k0);
+            if constexpr (MIXED) {
+                wave_sync();
+                if (l < m) {
+                    const int64_t j = j0s + k0 + l;
+                    lf[l][0] = (float)(a.sxyz[j] - cx);
+                    lf[l][1] = (float)(a.sxyz[a.ns + j] - cy);
+                    lf[l][2] = (float)(a.sxyz[2 * a.ns + j] - cz);
+                    for (int c = 0; c < 3; ++c) {
+                        lf[l][3 + c] = (float)a.wn[c * a.ns + j];
+                        lf[l][6 + c] = (float)a.sq[c * a.ns + j];
+                    }
+                }
+                wave_sync();
+                float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+                uint64_t near = 0;
+#pragma unroll 4
+                for (int k = 0; k < m; ++k) {
+                    const float dx = fxl - lf[k][0], dy = fyl - lf[k][1], dz = fzl - lf[k][2];
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    if (r2 < a.near2) {                 // includes the self point
+                        near |= 1ull << k;
+                        continue;
+                    }
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float ri2 = ri * ri;
+                    const float dq = fmaf(dx, lf[k][6] - fq0x, fmaf(dy, lf[k][7] - fq0y, dz * (lf[k][8] - fq0z)));
+                    const float dn = fmaf(dx, lf[k][3], fmaf(dy, lf[k][4], dz * lf[k][5]));
+                    const float kk = dq * dn * (ri2 * ri2 * ri);
+                    p0 = fmaf(kk, dx, p0);
+                    p1 = fmaf(kk, dy, p1);
+                    p2 = fmaf(kk, dz, p2);
+                }
+                kahan(S0, C0, p0);
+                kahan(S1, C1, p1);
+                kahan(S2, C2, p2);
+                while (near) {
+                    const int k = __builtin_ctzll(near);
+                    near &= near - 1;
+                    const int64_t j = j0s + k0 + k;
+                    if (j == self) continue;
+                    const double dx = x - a.sxyz[j], dy = y - a.sxyz[a.ns + j], dz = z - a.sxyz[2 * a.ns + j];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 == 0.0) continue;                    // coincident: skipped
+                    const double ri = rsq64(r2), ri2 = ri * ri;
+                    const double dq = dx * (a.sq[j] - q0x) + dy * (a.sq[a.ns + j] - q0y) +
+                                      dz * (a.sq[2 * a.ns + j] - q0z);
+                    const double dn = dx * a.wn[j] + dy * a.wn[a.ns + j] + dz * a.wn[2 * a.ns + j];
+                    const double kk = dq * dn * (ri2 * ri2 * ri);
+                    u0 += kk * dx;
+                    u1 += kk * dy;
+                    u2 += kk * dz;
+                }
+                continue;
+            }
             wave_sync();
             if (l < m) {
                 const int64_t j = j0s + k0 + l;
@@ -838,6 +939,11 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
                 u2 += kk * dz;
             }
         }
+    }
+    if (MIXED) {
+        u0 += (double)S0 - (double)C0;
+        u1 += (double)S1 - (double)C1;
+        u2 += (double)S2 - (double)C2;
     }
     if (h == 1) {
         comb[w >> 1][0][l] = u0;
@@ -1248,11 +1354,11 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
 }
 
 extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, const double* src_weight,
-                                   const double* src_q, uint32_t flags, double* u_out, void* stream) {
+                                   const double* src_q, double near_r, uint32_t flags, double* u_out,
+                                   void* stream) {
     if (!t) return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: null tree");
-    if (flags & STOKES_PREC_MIXED)
-        return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: the double layer is evaluated in FP64 only");
-    if (flags & ~(STOKES_ONSURF_RAW | STOKES_ACCUMULATE))
+    if (!std::isfinite(near_r)) return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: near_r not finite");
+    if (flags & ~(STOKES_PREC_MIXED | STOKES_ONSURF_RAW | STOKES_ACCUMULATE))
         return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: unsupported flag bits");
     if (!src_normal || !src_weight || !src_q || !u_out)
         return fail(STOKES_E_INVAL, "stokes_tree_dl_eval: null pointer");
@@ -1289,8 +1395,13 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
     a.out = u_out;
     a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
     a.subtract = (flags & STOKES_ONSURF_RAW) ? 0 : 1;
+    const double nr = near_r > 0.0 ? near_r : 0.02;
+    a.near2 = (float)(nr * nr);
     const unsigned grid = (unsigned)((t->nb + EW / 2 - 1) / (EW / 2));
-    hipLaunchKernelGGL(k_tr_dl_eval, dim3(grid), dim3(64 * EW), 0, st, a);
+    if (flags & STOKES_PREC_MIXED)
+        hipLaunchKernelGGL(k_tr_dl_eval<true>, dim3(grid), dim3(64 * EW), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_tr_dl_eval<false>, dim3(grid), dim3(64 * EW), 0, st, a);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }

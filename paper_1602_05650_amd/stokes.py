@@ -78,7 +78,7 @@ def _load():
         "stokes_nonlocal_sbt": [I32, I32, P, P, P, P, D, D, P, P],
         "stokes_tree_create": [I64, P, I64, P, I32, D, I32, P, P],
         "stokes_tree_sl_eval": [P, P, P, P, P, D, D, D, U32, P, P],
-        "stokes_tree_dl_eval": [P, P, P, P, U32, P, P],
+        "stokes_tree_dl_eval": [P, P, P, P, D, U32, P, P],
         "stokes_tree_info": [P, P, P, P, P],
         "stokes_tree_destroy": [P],
         "stokes_particle_solve": [I64, P, P, P, I32, P, P, P, P, P, P, P, D, D, I32, U32, P, P, P,
@@ -403,17 +403,20 @@ class Tree:
                                         _ptr(out), _stream(stream)))
         return out
 
-    def dl_eval(self, normal, weight, q, raw=False, out=None, accumulate=False, stream=None):
-        """Double-layer sum of dl_eval on this plan, FP64.  Plans built with targets =
+    def dl_eval(self, normal, weight, q, raw=False, out=None, accumulate=False, stream=None, mixed=False,
+                near_r=0.0):
+        """Double-layer sum of dl_eval on this plan (FP64, or mixed: FP32 pairs with FP64
+        pairs closer than near_r, <= 0 selecting 0.02).  Plans built with targets =
         sources take the singularity subtraction unless raw."""
         _dev(normal, torch.float64, "normal", (3, self.n_src))
         _dev(weight, torch.float64, "weight", (self.n_src,))
         _dev(q, torch.float64, "q", (3, self.n_src))
         if out is None:
             out = torch.zeros((3, self.n_trg), dtype=torch.float64, device=q.device)
-        flags = (ONSURF_RAW if raw else 0) | (ACCUMULATE if accumulate else 0)
-        _check(_lib.stokes_tree_dl_eval(self._h, _ptr(normal), _ptr(weight), _ptr(q), flags, _ptr(out),
-                                        _stream(stream)))
+        flags = ((PREC_MIXED if mixed else PREC_FP64) | (ONSURF_RAW if raw else 0)
+                 | (ACCUMULATE if accumulate else 0))
+        _check(_lib.stokes_tree_dl_eval(self._h, _ptr(normal), _ptr(weight), _ptr(q), float(near_r), flags,
+                                        _ptr(out), _stream(stream)))
         return out
 
     def info(self):

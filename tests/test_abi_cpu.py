@@ -98,7 +98,7 @@ def test_status_strings_and_validation_without_gpu():
     assert "theta" in S.last_error()
     assert L.stokes_tree_sl_eval(None, None, None, None, None, 1.0, 0.01, 0.0, 0, None,
                                  None) == S.E_INVAL
-    assert L.stokes_tree_dl_eval(None, None, None, None, 0, None, None) == S.E_INVAL
+    assert L.stokes_tree_dl_eval(None, None, None, None, 0.0, 0, None, None) == S.E_INVAL
     assert L.stokes_tree_destroy(None) == S.E_INVAL
     assert L.stokes_session_create(None, None) == S.E_INVAL
     assert L.stokes_session_destroy(None) == S.E_INVAL

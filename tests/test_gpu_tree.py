@@ -183,17 +183,20 @@ def sphere_ref(oracle_mod, sphere):
 # The stresslet's interpolation error is far larger than the Stokeslet's at the same
 # degree and theta (on the surface, the d.n factor nearly cancels for neighbouring
 # points in the exact kernel but not in the interpolated one), so these plans use
-# higher degrees than the single-layer ones.
-@pytest.mark.parametrize("degree,theta,tol", [(8, 0.5, 2e-7), (9, 0.5, 4e-8)])
-def test_tree_double_layer_vs_oracle(S, sphere, sphere_ref, degree, theta, tol):
+# higher degrees than the single-layer ones.  Mixed: FP64 below a near radius of 0.4;
+# the bound is that of FP32 stresslet pairs on a random density (the direct mixed sum
+# gives 2.7e-6 on this sphere at the same radius, the treecode 3.0e-6 on all targets).
+@pytest.mark.parametrize("degree,theta,mixed,tol", [(8, 0.5, False, 2e-7), (9, 0.5, False, 4e-8),
+                                                    (8, 0.5, True, 1e-5), (9, 0.5, True, 1e-5)])
+def test_tree_double_layer_vs_oracle(S, sphere, sphere_ref, degree, theta, mixed, tol):
     sph, q = sphere
     idx, ref = sphere_ref
     T = S.Tree(dev(sph.xyz), degree=degree, theta=theta, leaf_size=64)
     assert T.info()["proxy_pairs"] > 0
     for raw in (False, True):
-        u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), raw=raw).cpu().numpy()
+        u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), raw=raw, mixed=mixed, near_r=0.4).cpu().numpy()
         err = relmax(u[:, idx], ref[raw])
-        print(f"double layer, degree {degree} theta {theta} raw {raw}: err {err:.2e}, {T.info()}")
+        print(f"double layer, degree {degree} theta {theta} mixed {mixed} raw {raw}: err {err:.2e}, {T.info()}")
         assert err <= tol
 
 
@@ -244,6 +247,7 @@ def test_tree_double_layer_off_surface_and_accumulate(S, oracle_mod, sphere):
     print(f"double layer off the surface: err {err:.2e}, {T.info()}")
     assert err <= 2e-8
     assert T.info()["proxy_pairs"] > 0
-    with pytest.raises(S.StokesError):                  # FP64 only
-        S._check(S._lib.stokes_tree_dl_eval(T._h, S._ptr(dev(sph.normal)), S._ptr(dev(sph.weight)),
-                                            S._ptr(dev(q)), S.PREC_MIXED, S._ptr(base), None))
+    um = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), mixed=True, near_r=0.4).cpu().numpy()
+    err = relmax(um, ref)
+    print(f"double layer off the surface, mixed: err {err:.2e}")
+    assert err <= 1e-5
