@@ -133,6 +133,11 @@ public:
         int32_t sl_begin, sl_count;
     };
     int step_parts(const std::vector<Part>& parts);
+    // step_parts without reading the status rows back: the step is only enqueued.
+    // copy_status_async then enqueues the copy of the status rows into `dst` (pinned
+    // host memory of MAX_SLOTS * NSTAT doubles), valid once the stream reaches it.
+    int step_parts_nowait(const std::vector<Part>& parts);
+    int copy_status_async(double* dst);
     // Solutions of the listed slots into their x buffers (iterations done in desc.j).
     int finalize(const std::vector<int>& slots);
 
@@ -145,6 +150,8 @@ public:
     // The caller has written w = A P^{-1} v_j (desc.j) into desc.w: Gram-Schmidt,
     // Givens rotation and v_{j+1}; then the status rows are read back.
     int step_ortho(const std::vector<int>& slots);
+    // step_ortho without reading the status rows back (see copy_status_async).
+    int step_ortho_nowait(const std::vector<int>& slots);
     // y from the least-squares problem and w = V_m y (iterations done in desc.j);
     // the caller forms x = P^{-1} w.
     int finalize_vector(const std::vector<int>& slots);
@@ -162,12 +169,27 @@ private:
     int run_step();
     int read_status();
 
+    int set_step_lists(const std::vector<Part>& parts);
+    int launch_or_replay();
+
     hipStream_t st_ = nullptr;
     bool mixed_ = false, doublet_ = true, use_graph_ = false;
-    SlotDesc* host_desc_ = nullptr;   // pinned [MAX_SLOTS]
+    SlotDesc* host_desc_ = nullptr;   // [MAX_SLOTS], the host's current tables
     SlotDesc* dev_desc_ = nullptr;
-    StepTables* host_tab_ = nullptr;  // pinned
+    StepTables* host_tab_ = nullptr;
     StepTables* dev_tab_ = nullptr;
+    // Uploads go through a ring of pinned snapshots of the tables, so the host may
+    // change its tables for the next step while a copy of the last ones is in flight;
+    // a stage is reused once the event recorded after its copy has completed.
+    static constexpr int NSTAGE = 8;
+    struct Stage {
+        SlotDesc* desc = nullptr;
+        StepTables* tab = nullptr;
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    };
+    Stage stage_[NSTAGE];
+    int next_stage_ = 0;
     double* host_stat_ = nullptr;     // pinned [MAX_SLOTS * NSTAT]
     double* dev_stat_ = nullptr;
     hipGraph_t graph_ = nullptr;

@@ -7,6 +7,7 @@
 
 #include <string>
 
+#include "host_logic.hpp"
 #include "stokes.h"
 
 namespace stokes {
@@ -46,35 +47,41 @@ int dl_eval_surfaces(int64_t n_src, const double* src_xyz, const double* src_nor
                      const double* src_q, const int32_t* src_sid, int64_t n_trg, const double* trg_xyz,
                      const int64_t* trg_self, double near_r, uint32_t flags, double* u_out, hipStream_t st);
 
-// Bump allocator over a workspace buffer (256-byte aligned slices).
-struct Carve {
-    char* base;
-    size_t off = 0;
-    explicit Carve(void* b) : base(static_cast<char*>(b)) {}
-    template <class T>
-    T* take(size_t n) {
-        off = (off + 255) & ~size_t(255);
-        T* p = reinterpret_cast<T*>(base + off);
-        off += n * sizeof(T);
-        return p;
-    }
-    static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
-};
+struct Tile;
+struct SrcDL64;
+struct SrcDL32;
 
-// ---- geometry of the kernel sums -----------------------------------------
-constexpr int TILE = 32;      // sources per tile (one 32-node fiber in the benchmark geometries)
-constexpr int BLOCK = 256;    // 4 waves per block
-// Targets per lane (register blocking) of each pair kernel, and the number of
-// blocks a launch aims for (many small work items keep all 256 CUs busy to
-// the end; measured on gfx950: R = 1 with ~64k blocks is fastest for both
-// precisions, because occupancy matters more here than reuse of the SGPR
-// source operands).
-constexpr int R_SL64 = 1, R_SL32 = 1, R_DL64 = 1, R_DL32 = 1;
-constexpr int64_t TARGET_BLOCKS = 65536;
-// Serving slots share the GPU with other requests, so each uses fewer chunks
-// (less partial-sum memory per request).
-constexpr int64_t TARGET_BLOCKS_SLOT = 4096;
-constexpr int MIN_TILES_PER_CHUNK = 8;
+// A double-layer sum on a fixed geometry (sources, normals, weights, surface ids,
+// targets and their self indices), evaluated for many densities: the tiles, the
+// source packs and the exclusion ranges are made once, and an evaluation re-packs
+// only the density.  The geometry arrays (device) must stay alive and unchanged
+// while the plan is used; the plan owns its own device memory.  Each evaluation
+// gives the result of dl_eval_surfaces (src_sid given) or of stokes_dl_eval (src_sid
+// null, with the same near radius and flags), bit for bit.
+class DLPlan {
+public:
+    DLPlan() = default;
+    ~DLPlan();
+    DLPlan(const DLPlan&) = delete;
+    DLPlan& operator=(const DLPlan&) = delete;
+    int init(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
+             const int32_t* src_sid, int64_t n_trg, const double* trg_xyz, const int64_t* trg_self,
+             double near_r, uint32_t flags, hipStream_t st);
+    int eval(const double* src_q, double* u_out, bool accumulate, hipStream_t st);
+
+private:
+    void* mem_ = nullptr;
+    bool mixed_ = false, sub_ = true, multi_ = false;
+    int64_t n_s_ = 0, n_t_ = 0;
+    const double* txyz_ = nullptr;
+    float near2_ = 0.0f;
+    Partition P_{};
+    Tile* tiles_ = nullptr;
+    SrcDL64* s64_ = nullptr;
+    SrcDL32* s32_ = nullptr;
+    int2* excl_ = nullptr;
+    double* partial_ = nullptr;
+};
 
 // A tile of TILE consecutive sources with two bounding volumes: a sphere about
 // the centre of its bounding box, and a capsule (a segment from the first to
@@ -85,11 +92,12 @@ struct __align__(16) Tile {
     double ox, oy, oz;   // FP64 origin: centre of the bounding box
     double reach2;       // FP64 path: a target closer than sqrt(reach2) may coincide with a source
     float reach2_f;      // mixed path: a target closer than this may have a near pair
+                         // (double layer: or lie in the tile's tangent band)
     int32_t j0, j1;      // sources [j0, j1)
     float inv_l2;        // 1/|b|^2 of the capsule axis (0: the axis is a point)
     float ax, ay, az;    // capsule axis start, relative to the origin
     float bx, by, bz;    // capsule axis vector
-    float cap2_f;        // mixed path: (capsule radius + near radius)^2, padded
+    float cap2_f;        // mixed path: (capsule radius + near radius [or band])^2, padded
     float cap2_d;        // FP64 path: (capsule radius)^2, padded
 };
 
@@ -100,20 +108,5 @@ struct __align__(32) SrcSL32 { float x, y, z, c, sx, sy, sz, c3; };
 // Double-layer source: n' = (3/(4 pi)) w n.
 struct __align__(32) SrcDL64 { double x, y, z, qx, qy, qz, nx, ny, nz, pad0, pad1, pad2; };
 struct __align__(16) SrcDL32 { float x, y, z, qx, qy, qz, nx, ny, nz, pad0, pad1, pad2; };
-
-// Work partition of one sum: targets in waves of 64*R, sources in chunks of
-// whole tiles.  Depends only on the problem sizes (bitwise reproducibility).
-struct Partition {
-    int R;
-    int64_t n_t;
-    int32_t n_tiles;
-    int32_t tiles_per_chunk;
-    int32_t n_chunks;
-    int32_t n_tblocks;
-};
-// min_tiles_small: least source tiles per chunk when there are fewer than 64
-// target blocks (a problem too small to fill the chip with target blocks alone).
-Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks = TARGET_BLOCKS,
-                         int min_tiles_small = 1);
 
 }  // namespace stokes

@@ -362,22 +362,28 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
                        area);
     STOKES_HIP(hipGetLastError());
 
+    // The two double-layer sums of the operator on the fixed geometry: the periphery
+    // onto every point, and all particles in one sum in which each target subtracts its
+    // own density only from its own particle's sources (surface ids d_sid, 1 + p).
+    // Their tiles, packs and exclusion ranges are made once here; an iteration re-packs
+    // only the density.
+    DLPlan plan0, planP;
+    if (m0 > 0) {
+        int rc = plan0.init(m0, bx, bn, bw, nullptr, ms, T, d_self, near_r, sumflags, st);
+        if (rc) return rc;
+    } else {
+        STOKES_HIP(hipMemsetAsync(D0, 0, 3 * ms * 8, st));
+    }
+    if (int rc = planP.init(mp, yp, np_, wp, d_sid + m0, ms, T, d_selfp, near_r, sumflags, st)) return rc;
+
     // w = A P^{-1} v: z = v / diag, then the operator
     auto apply = [&](const double* v, double* z, double* w) -> int {
         hipLaunchKernelGGL(k_pt_scale, dim3(grid1(n3)), dim3(PB), 0, st, n3, v, (const double*)diag, z);
         hipLaunchKernelGGL(k_pt_gather, dim3(grid1(ms)), dim3(PB), 0, st, S, ms, ntot, (const double*)z, qb, m0,
                            qp);
         int rc = STOKES_OK;
-        if (m0 > 0) {
-            rc = stokes_dl_eval(m0, bx, bn, bw, qb, ms, T, d_self, near_r, sumflags, D0, st, nullptr);
-        } else {
-            STOKES_HIP(hipMemsetAsync(D0, 0, 3 * ms * 8, st));
-        }
-        if (rc) return rc;
-        // all particles in one double-layer sum: each target subtracts its own density
-        // only from its own particle's sources (surface ids d_sid, 1 + p)
-        rc = dl_eval_surfaces(mp, yp, np_, wp, qp, d_sid + m0, ms, T, d_selfp, near_r, sumflags, DP, st);
-        if (rc) return rc;
+        if (m0 > 0 && (rc = plan0.eval(qb, D0, false, st))) return rc;
+        if ((rc = planP.eval(qp, DP, false, st))) return rc;
         hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, st, S, (const double*)qb, centers, n_part,
                            1, red);
         hipLaunchKernelGGL(k_pt_assemble, dim3(grid1(ntot)), dim3(PB), 0, st, S, ms, ntot, n_part,
@@ -396,15 +402,54 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     int done = 0;
     double resid = b.status(0)[2];
     if (b.status(0)[3] == 0.0) {
-        for (int j = 0; j < iters; ++j) {
-            SlotDesc& d = b.desc(0);
-            d.j = j;
-            if ((rc = apply(d.V + (int64_t)j * n3, d.z, d.w))) return rc;
-            if ((rc = b.step_ortho(one))) return rc;
-            done = j + 1;
-            resid = b.status(0)[2];
-            if (b.status(0)[3] != 0.0) break;   // exact breakdown
+        // The host does not wait for each iteration: iteration j is enqueued before the
+        // status of iteration j - 1 is read (two pinned status rows, one event each).  An
+        // exact breakdown is therefore seen one iteration late; the extra iteration then
+        // writes only Krylov entries beyond the ones the solution uses (x = 0 input).
+        double* hst = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        auto cleanup = [&]() {
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (hst) (void)hipHostFree(hst);
+        };
+        hipError_t e = hipHostMalloc((void**)&hst, 2 * sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "particle solve: status buffers");
         }
+        bool broke = false;
+        for (int j = 0; j <= iters && !broke; ++j) {
+            if (j < iters) {
+                SlotDesc& d = b.desc(0);
+                d.j = j;
+                if (!rc) rc = apply(d.V + (int64_t)j * n3, d.z, d.w);
+                if (!rc) rc = b.step_ortho_nowait(one);
+                if (!rc) rc = b.copy_status_async(hst + (j & 1) * NSTAT * MAX_SLOTS);
+                if (!rc) {
+                    e = hipEventRecord(ev[j & 1], st);
+                    if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+                }
+            }
+            if (j > 0 && !rc) {   // the previous iteration's status
+                e = hipEventSynchronize(ev[(j - 1) & 1]);
+                if (e != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
+                if (!rc) {
+                    const double* row = hst + ((j - 1) & 1) * NSTAT * MAX_SLOTS;
+                    done = j;
+                    resid = row[2];
+                    broke = row[3] != 0.0;   // exact breakdown at iteration j - 1
+                }
+            }
+            if (rc) break;
+        }
+        if (!rc) {
+            e = hipStreamSynchronize(st);   // a late breakdown's extra iteration is done
+            if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+        }
+        cleanup();
+        if (rc) return rc;
     }
     b.desc(0).j = done;
     if ((rc = b.finalize_vector(one))) return rc;

@@ -33,58 +33,29 @@ static int64_t now_ns() {
     return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
 }
 
-// First-fit allocator over one device allocation (offsets are 256-aligned).
+// One device allocation, placed by the first-fit RangeAllocator (host_logic.hpp).
 class Arena {
 public:
     int init(size_t bytes) {
         bytes = bytes & ~size_t(255);
         STOKES_HIP(hipMalloc(&base_, bytes));
-        size_ = bytes;
-        free_[0] = bytes;
+        ranges_.reset(bytes);
         return STOKES_OK;
     }
     ~Arena() {
         if (base_) (void)hipFree(base_);
     }
     void* alloc(size_t bytes) {
-        bytes = (bytes + 255) & ~size_t(255);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const size_t off = it->first, len = it->second;
-                free_.erase(it);
-                if (len > bytes) free_[off + bytes] = len - bytes;
-                used_[off] = bytes;
-                return static_cast<char*>(base_) + off;
-            }
-        }
-        return nullptr;
+        const size_t off = ranges_.alloc(bytes);
+        return off == SIZE_MAX ? nullptr : static_cast<char*>(base_) + off;
     }
-    void release(void* p) {
-        const size_t off = static_cast<char*>(p) - static_cast<char*>(base_);
-        auto u = used_.find(off);
-        if (u == used_.end()) return;
-        size_t len = u->second;
-        used_.erase(u);
-        auto nx = free_.lower_bound(off);   // first free block after the released one
-        if (nx != free_.end() && nx->first == off + len) {
-            len += nx->second;
-            nx = free_.erase(nx);
-        }
-        if (nx != free_.begin()) {
-            auto pv = std::prev(nx);
-            if (pv->first + pv->second == off) {
-                pv->second += len;
-                return;
-            }
-        }
-        free_[off] = len;
-    }
-    size_t capacity() const { return size_; }
+    void release(void* p) { ranges_.release(static_cast<char*>(p) - static_cast<char*>(base_)); }
+    bool fits(size_t bytes) const { return ranges_.fits(bytes); }
+    size_t capacity() const { return ranges_.capacity(); }
 
 private:
     void* base_ = nullptr;
-    size_t size_ = 0;
-    std::map<size_t, size_t> free_, used_;
+    RangeAllocator ranges_;
 };
 
 enum ReqState { QUEUED, RUNNING, DONE };
@@ -103,7 +74,8 @@ struct Request {
     bool claimed = false;         // a thread is inside stokes_session_wait for it
     int slot = -1;
     void* mem = nullptr;
-    int j = 0;                    // iterations done
+    int j = 0;                    // iterations enqueued (complete once their step is)
+    bool final_queued = false;    // the solution and its copy to the host are enqueued
     int32_t sl_done = 0;          // single-layer items of iteration j already summed
     int32_t sl_quota = 0;         // single-layer items per step
     stokes_solve_stats st{};
@@ -121,6 +93,10 @@ struct stokes_session {
     hipStream_t st = nullptr;
     stokes::Batch batch;
     stokes::Arena arena;
+    // Status rows of the last two enqueued steps (pinned) and the event after each
+    // step's work: the worker enqueues step t before it reads step t-1's status.
+    double* stat_buf[2] = {nullptr, nullptr};
+    hipEvent_t stat_ev[2] = {nullptr, nullptr};
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -167,16 +143,116 @@ static int32_t step_quota(const SlotDesc& d, int64_t step_pairs) {
     return (int32_t)std::max(1.0, std::min<double>(q, d.n_items_sl));
 }
 
+// A step on the stream whose status the worker has not read yet.
+struct Pending {
+    bool valid = false;
+    int buf = 0;                                // stat_buf / stat_ev index
+    std::vector<std::pair<int, int>> done;      // (slot, iteration the step completed)
+    std::vector<int> final_slots;               // slots whose solution copy the event covers
+};
+
+// Would the FIFO head be admitted now (a free slot and room in the arena)?  Lock held.
+static bool admissible(stokes_session* s) {
+    if (s->queue.empty()) return false;
+    bool slot = false;
+    for (Request* r : s->slot_req) slot |= (r == nullptr);
+    return slot && s->arena.fits(s->queue.front()->bytes);
+}
+
+// Wait for a pending step and take in its status: residuals, exact breakdowns (the
+// request's solution is formed from the iterations before the breakdown; the extra
+// iteration a lagging host enqueued for it touches only entries beyond them), and the
+// requests whose solution copy the step's event covers.  `next` is the step enqueued
+// after it (a broken-down request is taken out of its finishing list).
+static int complete_pending(stokes_session* s, Pending& P, Pending* next) {
+    if (!P.valid) return STOKES_OK;
+    P.valid = false;
+    STOKES_HIP(hipEventSynchronize(s->stat_ev[P.buf]));
+    const double* st = s->stat_buf[P.buf];
+    Batch& B = s->batch;
+    std::vector<int> broken;
+    for (const auto& dq : P.done) {
+        const int q = dq.first;
+        Request* r = s->slot_req[q];
+        if (!r) continue;
+        r->st.residual = st[NSTAT * q + 2];
+        if (st[NSTAT * q + 3] != 0.0 && std::find(P.final_slots.begin(), P.final_slots.end(), q) ==
+                                            P.final_slots.end()) {
+            r->j = dq.second + 1;
+            broken.push_back(q);
+        }
+    }
+    if (!broken.empty()) {   // rare: finish them now, synchronously
+        for (int q : broken) B.desc(q).j = s->slot_req[q]->j;
+        if (int rc = B.finalize(broken)) return rc;
+        for (int q : broken) {
+            Request* r = s->slot_req[q];
+            STOKES_HIP(hipMemcpyAsync(r->result(), B.desc(q).x, 3 * r->N * sizeof(double), hipMemcpyDeviceToHost,
+                                      s->st));
+            if (next) next->final_slots.erase(std::remove(next->final_slots.begin(), next->final_slots.end(), q),
+                                              next->final_slots.end());
+        }
+        STOKES_HIP(hipStreamSynchronize(s->st));
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int q : P.final_slots)
+        if (s->slot_req[q]) finish(s, s->slot_req[q], STOKES_OK);
+    for (int q : broken)
+        if (s->slot_req[q]) finish(s, s->slot_req[q], STOKES_OK);
+    if (!P.final_slots.empty() || !broken.empty()) s->cv_done.notify_all();
+    return STOKES_OK;
+}
+
+// Fail every request (device error): the session stops admitting.  Lock held.
+static void fail_all(stokes_session* s, int rc) {
+    s->worker_rc = rc;
+    for (Request*& r : s->slot_req)
+        if (r) finish(s, r, rc);
+    for (Request* r : s->queue) finish(s, r, rc);
+    s->queue.clear();
+    s->stop = true;
+    s->cv_done.notify_all();
+}
+
 static void worker_main(stokes_session* s) {
     (void)hipSetDevice(s->cfg.device);
     Batch& B = s->batch;
     std::vector<Request*>& slots = s->slot_req;
+    Pending pend;
+    int next_buf = 0;
     for (;;) {
-        std::vector<int> admitted;
+        // Admissions, cancellations of running requests, fault injection and stopping
+        // need an empty pipeline (memory of a finished request is reused only after its
+        // last step): drain the pending step first when one of them is due.
+        bool drain = false;
         {
+            std::lock_guard<std::mutex> lk(s->mu);
+            bool retired = false;
+            for (auto it = s->queue.begin(); it != s->queue.end();) {
+                if ((*it)->cancel) {
+                    finish(s, *it, STOKES_E_CANCELED);
+                    it = s->queue.erase(it);
+                    retired = true;
+                } else {
+                    ++it;
+                }
+            }
+            if (retired) s->cv_done.notify_all();
+            bool running_cancel = false;
+            for (Request* r : slots) running_cancel |= (r && r->cancel);
+            drain = pend.valid && (s->stop || running_cancel || s->inject_fault.load() || admissible(s));
+        }
+        if (drain) {
+            if (int rc = complete_pending(s, pend, nullptr)) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                fail_all(s, rc);
+                return;
+            }
+        }
+        std::vector<int> admitted;
+        if (!pend.valid) {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
-                // retire cancelled requests (queued or in flight)
                 for (auto it = s->queue.begin(); it != s->queue.end();) {
                     if ((*it)->cancel) {
                         finish(s, *it, STOKES_E_CANCELED);
@@ -188,6 +264,17 @@ static void worker_main(stokes_session* s) {
                 for (Request*& r : slots)
                     if (r && r->cancel) finish(s, r, STOKES_E_CANCELED);
                 if (s->stop) break;
+                if (s->inject_fault.exchange(false)) {
+                    // forced failure of this step: fail the requests in flight, keep serving
+                    bool any = false;
+                    for (Request* r : slots) any |= (r != nullptr);
+                    if (any) {
+                        set_error("injected step failure");
+                        for (Request*& r : slots)
+                            if (r) finish(s, r, STOKES_E_DEVICE);
+                        s->cv_done.notify_all();
+                    }
+                }
                 // FIFO admission by slot and device-memory footprint
                 while (!s->queue.empty()) {
                     Request* r = s->queue.front();
@@ -221,90 +308,92 @@ static void worker_main(stokes_session* s) {
             }
             s->cv_done.notify_all();
         }
-        // set-up of the newly admitted requests (device only; lock released)
+        // set-up of the newly admitted requests (the pipeline is empty; lock released)
         int rc = STOKES_OK;
         for (int q : admitted) {
             Request* r = slots[q];
-            rc = B.attach(q, r->mem, r->n_fib, r->npf, r->k, r->eps, r->mu, 0.0, r->opts, r->delta,
-                          r->xyz(), r->tan(),
-                          r->flen(), r->rhs());
+            rc = B.attach(q, r->mem, r->n_fib, r->npf, r->k, r->eps, r->mu, 0.0, r->opts, r->delta, r->xyz(),
+                          r->tan(), r->flen(), r->rhs());
             if (rc) break;
         }
-        if (!rc) rc = B.start(admitted);
-        std::vector<int> iterating, finishing;
+        if (!rc) rc = B.start(admitted);   // synchronous: reads beta and the breakdown flag
+        Pending cur;
+        cur.buf = next_buf;
         std::vector<Batch::Part> parts;
+        std::vector<int> zero_rhs;
         if (!rc) {
             for (int q = 0; q < (int)slots.size(); ++q) {
                 Request* r = slots[q];
-                if (!r) continue;
-                const bool fresh = std::find(admitted.begin(), admitted.end(), q) != admitted.end();
-                if (fresh) {
+                if (!r || r->final_queued) continue;
+                if (std::find(admitted.begin(), admitted.end(), q) != admitted.end()) {
                     r->j = 0;
                     r->sl_done = 0;
                     r->sl_quota = step_quota(B.desc(q), s->cfg.step_pairs);
                     r->st.residual = B.status(q)[2];
-                    if (B.status(q)[3] != 0.0) {   // zero right-hand side
-                        finishing.push_back(q);
+                    if (B.status(q)[3] != 0.0) {   // zero right-hand side: x = 0
+                        zero_rhs.push_back(q);
                         continue;
                     }
                 }
                 B.desc(q).j = r->j;
-                iterating.push_back(q);
-            }
-            if (s->inject_fault.exchange(false) && !iterating.empty()) {
-                // forced failure of this step: fail the requests in flight, keep serving
-                std::lock_guard<std::mutex> lk(s->mu);
-                set_error("injected step failure");
-                for (int q : iterating) finish(s, slots[q], STOKES_E_DEVICE);
-                iterating.clear();
-                s->cv_done.notify_all();
-            }
-            for (int q : iterating) {
-                Request* r = slots[q];
                 const int32_t n = B.desc(q).n_items_sl;
                 parts.push_back({q, r->sl_done, std::min(r->sl_quota, n - r->sl_done)});
             }
-            rc = B.step_parts(parts);
+            if (parts.empty() && zero_rhs.empty()) {
+                // nothing left to step (every request in a slot has its solution queued):
+                // take in the pending step and go back to waiting for work
+                rc = complete_pending(s, pend, nullptr);
+                if (rc) {
+                    (void)hipStreamSynchronize(s->st);
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    fail_all(s, rc);
+                    return;
+                }
+                continue;
+            }
+            rc = B.step_parts_nowait(parts);
         }
+        if (!rc && !parts.empty()) rc = B.copy_status_async(s->stat_buf[cur.buf]);
         if (!rc) {
+            std::vector<int> finishing = zero_rhs;
             for (const Batch::Part& p : parts) {
                 Request* r = slots[p.slot];
                 r->sl_done += p.sl_count;
                 if (r->sl_done < B.desc(p.slot).n_items_sl) continue;   // matvec not complete
                 r->sl_done = 0;
+                cur.done.push_back({p.slot, r->j});
                 r->j += 1;
-                r->st.residual = B.status(p.slot)[2];
-                if (r->j >= r->k || B.status(p.slot)[3] != 0.0) finishing.push_back(p.slot);
+                if (r->j >= r->k) finishing.push_back(p.slot);
             }
-            for (int q : finishing) B.desc(q).j = slots[q]->j;
-            rc = B.finalize(finishing);
-        }
-        if (!rc) {
             for (int q : finishing) {
+                B.desc(q).j = slots[q]->j;
+                slots[q]->final_queued = true;
+            }
+            rc = B.finalize(finishing);
+            for (int q : finishing) {
+                if (rc) break;
                 Request* r = slots[q];
                 hipError_t e = hipMemcpyAsync(r->result(), B.desc(q).x, 3 * r->N * sizeof(double),
                                               hipMemcpyDeviceToHost, s->st);
-                if (e != hipSuccess) { rc = hip_fail(e, "hipMemcpyAsync(result)"); break; }
+                if (e != hipSuccess) rc = hip_fail(e, "hipMemcpyAsync(result)");
             }
-            if (!rc && !finishing.empty()) {
-                hipError_t e = hipStreamSynchronize(s->st);
-                if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
-            }
+            cur.final_slots = finishing;
         }
-        std::lock_guard<std::mutex> lk(s->mu);
+        if (!rc) {
+            hipError_t e = hipEventRecord(s->stat_ev[cur.buf], s->st);
+            if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+        }
+        cur.valid = true;
+        // the previous step's status, read while this one runs
+        if (!rc) rc = complete_pending(s, pend, &cur);
         if (rc) {
-            // a device error fails every request in flight; the session stops admitting
-            s->worker_rc = rc;
-            for (Request*& r : slots)
-                if (r) finish(s, r, rc);
-            for (Request* r : s->queue) finish(s, r, rc);
-            s->queue.clear();
-            s->stop = true;
-            s->cv_done.notify_all();
+            (void)hipStreamSynchronize(s->st);
+            std::lock_guard<std::mutex> lk(s->mu);
+            fail_all(s, rc);
             return;
         }
-        for (int q : finishing) finish(s, slots[q], STOKES_OK);
-        if (!finishing.empty()) s->cv_done.notify_all();
+        pend = cur;
+        next_buf ^= 1;
     }
 }
 
@@ -335,12 +424,21 @@ extern "C" int stokes_session_create(const stokes_session_cfg* cfg, stokes_sessi
     if (e != hipSuccess) rc = hip_fail(e, "hipStreamCreateWithFlags");
     if (!rc) rc = s->batch.init(s->st, cfg->flags & STOKES_PREC_MIXED,
                                 !(cfg->flags & STOKES_NO_DOUBLET), true);
+    for (int b = 0; b < 2 && !rc; ++b) {
+        e = hipHostMalloc((void**)&s->stat_buf[b], sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stat_ev[b], hipEventDisableTiming);
+        if (e != hipSuccess) rc = hip_fail(e, "stokes_session_create: status buffers");
+    }
     if (!rc) {
         rc = s->arena.init((size_t)cfg->hbm_budget_bytes);
         if (rc) rc = fail(STOKES_E_NOMEM, std::string("stokes_session_create: HBM arena: ") + stokes_last_error());
     }
     (void)hipSetDevice(cur);
     if (rc) {
+        for (int b = 0; b < 2; ++b) {
+            if (s->stat_ev[b]) (void)hipEventDestroy(s->stat_ev[b]);
+            if (s->stat_buf[b]) (void)hipHostFree(s->stat_buf[b]);
+        }
         if (s->st) (void)hipStreamDestroy(s->st);
         delete s;
         return rc;
@@ -490,6 +588,10 @@ extern "C" int stokes_session_destroy(stokes_session* s) {
     (void)hipStreamSynchronize(s->st);
     const int rc = s->worker_rc;
     hipStream_t st = s->st;
+    for (int b = 0; b < 2; ++b) {
+        if (s->stat_ev[b]) (void)hipEventDestroy(s->stat_ev[b]);
+        if (s->stat_buf[b]) (void)hipHostFree(s->stat_buf[b]);
+    }
     delete s;   // batch and arena free their device memory
     (void)hipStreamDestroy(st);
     (void)hipSetDevice(cur);

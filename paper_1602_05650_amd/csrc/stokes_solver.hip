@@ -576,6 +576,11 @@ Batch::~Batch() {
     if (host_desc_) (void)hipHostFree(host_desc_);
     if (host_tab_) (void)hipHostFree(host_tab_);
     if (host_stat_) (void)hipHostFree(host_stat_);
+    for (Stage& g : stage_) {
+        if (g.ev) (void)hipEventDestroy(g.ev);
+        if (g.desc) (void)hipHostFree(g.desc);
+        if (g.tab) (void)hipHostFree(g.tab);
+    }
 }
 
 int Batch::init(hipStream_t st, bool mixed, bool doublet, bool use_graph) {
@@ -586,6 +591,11 @@ int Batch::init(hipStream_t st, bool mixed, bool doublet, bool use_graph) {
     STOKES_HIP(hipHostMalloc((void**)&host_desc_, sizeof(SlotDesc) * MAX_SLOTS, hipHostMallocDefault));
     STOKES_HIP(hipHostMalloc((void**)&host_tab_, sizeof(StepTables), hipHostMallocDefault));
     STOKES_HIP(hipHostMalloc((void**)&host_stat_, sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault));
+    for (Stage& g : stage_) {
+        STOKES_HIP(hipHostMalloc((void**)&g.desc, sizeof(SlotDesc) * MAX_SLOTS, hipHostMallocDefault));
+        STOKES_HIP(hipHostMalloc((void**)&g.tab, sizeof(StepTables), hipHostMallocDefault));
+        STOKES_HIP(hipEventCreateWithFlags(&g.ev, hipEventDisableTiming));
+    }
     STOKES_HIP(hipMalloc((void**)&dev_desc_, sizeof(SlotDesc) * MAX_SLOTS));
     STOKES_HIP(hipMalloc((void**)&dev_tab_, sizeof(StepTables)));
     STOKES_HIP(hipMalloc((void**)&dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS));
@@ -715,9 +725,15 @@ void Batch::set_sl_list(const std::vector<Part>& parts) {
 }
 
 int Batch::upload() {
-    STOKES_HIP(hipMemcpyAsync(dev_desc_, host_desc_, sizeof(SlotDesc) * MAX_SLOTS,
-                              hipMemcpyHostToDevice, st_));
-    STOKES_HIP(hipMemcpyAsync(dev_tab_, host_tab_, sizeof(StepTables), hipMemcpyHostToDevice, st_));
+    Stage& g = stage_[next_stage_];
+    next_stage_ = (next_stage_ + 1) % NSTAGE;
+    if (g.used) STOKES_HIP(hipEventSynchronize(g.ev));   // its last copy has been read
+    memcpy(g.desc, host_desc_, sizeof(SlotDesc) * MAX_SLOTS);
+    memcpy(g.tab, host_tab_, sizeof(StepTables));
+    STOKES_HIP(hipMemcpyAsync(dev_desc_, g.desc, sizeof(SlotDesc) * MAX_SLOTS, hipMemcpyHostToDevice, st_));
+    STOKES_HIP(hipMemcpyAsync(dev_tab_, g.tab, sizeof(StepTables), hipMemcpyHostToDevice, st_));
+    STOKES_HIP(hipEventRecord(g.ev, st_));
+    g.used = true;
     return STOKES_OK;
 }
 
@@ -726,6 +742,10 @@ static unsigned grid_for(const WorkList& L, int cap) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(t, cap));
 }
 
+int Batch::copy_status_async(double* dst) {
+    STOKES_HIP(hipMemcpyAsync(dst, dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS, hipMemcpyDeviceToHost, st_));
+    return STOKES_OK;
+}
 int Batch::read_status() {
     STOKES_HIP(hipMemcpyAsync(host_stat_, dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS,
                               hipMemcpyDeviceToHost, st_));
@@ -799,8 +819,7 @@ int Batch::step(const std::vector<int>& slots) {
     return run_step();
 }
 
-int Batch::step_parts(const std::vector<Part>& parts) {
-    if (parts.empty()) return STOKES_OK;
+int Batch::set_step_lists(const std::vector<Part>& parts) {
     std::vector<int> begin, end;
     for (const Part& p : parts) {
         const int32_t n = host_desc_[p.slot].n_items_sl;
@@ -815,10 +834,27 @@ int Batch::step_parts(const std::vector<Part>& parts) {
     set_list(WL_DOT, end);
     set_list(WL_ONE, end);
     set_list(WL_VEC, end);
+    return STOKES_OK;
+}
+
+int Batch::step_parts(const std::vector<Part>& parts) {
+    if (parts.empty()) return STOKES_OK;
+    if (int rc = set_step_lists(parts)) return rc;
     return run_step();
 }
 
+int Batch::step_parts_nowait(const std::vector<Part>& parts) {
+    if (parts.empty()) return STOKES_OK;
+    if (int rc = set_step_lists(parts)) return rc;
+    return launch_or_replay();
+}
+
 int Batch::run_step() {
+    if (int rc = launch_or_replay()) return rc;
+    return read_status();
+}
+
+int Batch::launch_or_replay() {
     int rc = upload();
     if (rc) return rc;
     if (use_graph_) {
@@ -839,7 +875,7 @@ int Batch::run_step() {
     } else {
         if ((rc = launch_step(false))) return rc;
     }
-    return read_status();
+    return STOKES_OK;
 }
 
 int Batch::finalize(const std::vector<int>& slots) {
@@ -910,13 +946,18 @@ int Batch::start_vector(const std::vector<int>& slots) {
 
 int Batch::step_ortho(const std::vector<int>& slots) {
     if (slots.empty()) return STOKES_OK;
+    if (int rc = step_ortho_nowait(slots)) return rc;
+    return read_status();
+}
+
+int Batch::step_ortho_nowait(const std::vector<int>& slots) {
+    if (slots.empty()) return STOKES_OK;
     set_list(WL_DOT, slots);
     set_list(WL_ONE, slots);
     set_list(WL_VEC, slots);
     int rc = upload();
     if (rc) return rc;
-    if ((rc = launch_ortho(false))) return rc;
-    return read_status();
+    return launch_ortho(false);
 }
 
 int Batch::finalize_vector(const std::vector<int>& slots) {

@@ -51,6 +51,19 @@ __global__ void tile_prep_kernel(int64_t n_s, const double* __restrict__ sx, int
     if (t < n_tiles) tile_prep_one(t, n_s, sx, near_r, near_fac, sfib, n_fib, flen, tiles);
 }
 
+// Double-layer tiles of the mixed path: the reach covers the larger of the near
+// radius and the tile's tangent band (dl_band_radius), so that a target within the
+// band takes the checked loop, which forms d and d.n' in FP64.
+__global__ void dl_tile_prep_kernel(int64_t n_s, const double* __restrict__ sx,
+                                    const double* __restrict__ nrm, int32_t n_tiles, double near_r,
+                                    Tile* tiles) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t j0 = (int64_t)t * TILE, j1 = std::min<int64_t>(j0 + TILE, n_s);
+    tile_prep_one(t, n_s, sx, fmax(near_r, dl_band_radius(j0, j1, n_s, sx, nrm)), 0.0, nullptr, 0,
+                  nullptr, tiles);
+}
+
 __global__ void sl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
                                    const double* __restrict__ f, const double* __restrict__ w,
                                    const int32_t* __restrict__ sfib, int32_t n_fib,
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(RED_T * RED_S) void reduce_kernel(int64_t n_t, int3
                                                               int accumulate, double* out, int64_t out_stride,
                                                               const int2* __restrict__ excl,
                                                               const double* __restrict__ q, int64_t n_s,
-                                                              double jump) {
+                                                              double jump, int round_q = 0) {
     __shared__ double part[RED_S - 1][3][RED_T];
     const int tx = threadIdx.x % RED_T, sl = threadIdx.x / RED_T;
     const int64_t i = (int64_t)blockIdx.x * RED_T + tx;
@@ -185,9 +198,13 @@ __global__ __launch_bounds__(RED_T * RED_S) void reduce_kernel(int64_t n_t, int3
     if (q && excl) {
         const int2 e = excl[i];
         if (e.y > e.x) {
-            v[0] += jump * q[e.x];
-            v[1] += jump * q[n_s + e.x];
-            v[2] += jump * q[2 * n_s + e.x];
+            // round_q: the sum subtracted fl32(q_self) (dl_mixed_wave), so the jump takes it too
+            double qs[3] = {q[e.x], q[n_s + e.x], q[2 * n_s + e.x]};
+            if (round_q)
+                for (int c = 0; c < 3; ++c) qs[c] = (double)(float)qs[c];
+            v[0] += jump * qs[0];
+            v[1] += jump * qs[1];
+            v[2] += jump * qs[2];
         }
     }
     for (int c = 0; c < 3; ++c) {
@@ -222,29 +239,6 @@ __global__ void check_fiber_kernel(const int32_t* __restrict__ fib, int64_t n, i
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 
-Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks,
-                         int min_tiles_small) {
-    Partition p{};
-    p.R = R;
-    p.n_t = n_t;
-    p.n_tiles = (int32_t)((n_s + TILE - 1) / TILE);
-    const int64_t waves = (n_t + 64 * R - 1) / (64 * R);
-    p.n_tblocks = (int32_t)((waves + 3) / 4);
-    if (p.n_tiles == 0 || n_t == 0) {
-        p.tiles_per_chunk = 1;
-        p.n_chunks = 0;
-        return p;
-    }
-    int64_t ch = (target_blocks + p.n_tblocks - 1) / p.n_tblocks;
-    // few target blocks (a small, latency-bound problem): shorter chunks
-    const int64_t min_tiles = p.n_tblocks >= 64 ? MIN_TILES_PER_CHUNK : min_tiles_small;
-    ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / min_tiles));
-    ch = std::max<int64_t>(1, std::min<int64_t>(ch, p.n_tiles));
-    p.tiles_per_chunk = (int32_t)((p.n_tiles + ch - 1) / ch);
-    p.n_chunks = (p.n_tiles + p.tiles_per_chunk - 1) / p.tiles_per_chunk;
-    return p;
-}
-
 // Scratch layout of one sum (both layers use the same carve order).
 struct SumScratch {
     Tile* tiles;
@@ -260,36 +254,36 @@ struct SumScratch {
 
 static size_t sum_scratch_bytes(int64_t n_s, int64_t n_t, int32_t n_fib, size_t s64b, size_t s32b,
                                 int32_t n_chunks) {
-    const int64_t n_tiles = (n_s + TILE - 1) / TILE;
-    size_t b = 0;
-    b += Carve::round(n_tiles * sizeof(Tile)) + 256;
-    b += Carve::round(n_s * s64b) + 256;
-    b += Carve::round(n_s * s32b) + 256;
-    b += Carve::round(n_s * sizeof(float)) + 256;
-    b += Carve::round(n_t * sizeof(int2)) + 256;
-    b += Carve::round((size_t)std::max<int32_t>(n_fib, 1) * sizeof(int2)) + 256;
-    b += Carve::round((size_t)n_chunks * 3 * n_t * sizeof(double)) + 256;
-    b += 512;
-    return b;
+    return sum_layout(n_s, n_t, n_fib, sizeof(Tile), s64b, s32b, n_chunks).bytes;
 }
 
 static SumScratch carve_sum(void* base, int64_t n_s, int64_t n_t, int32_t n_fib, size_t s64b,
                             size_t s32b, int32_t n_chunks) {
-    Carve c(base);
+    const SumLayout L = sum_layout(n_s, n_t, n_fib, sizeof(Tile), s64b, s32b, n_chunks);
+    char* b = static_cast<char*>(base);
     SumScratch s;
-    const int64_t n_tiles = (n_s + TILE - 1) / TILE;
-    s.tiles = c.take<Tile>(n_tiles);
-    s.s64 = c.take<char>(n_s * s64b);
-    s.s32 = s32b ? c.take<char>(n_s * s32b) : nullptr;
-    s.near_t = c.take<float>(n_s);
-    s.excl = c.take<int2>(n_t);
-    s.fbounds = c.take<int2>(std::max<int32_t>(n_fib, 1));
-    s.partial = c.take<double>((size_t)n_chunks * 3 * n_t);
-    s.counters = c.take<unsigned long long>(4);
-    s.flag = c.take<int>(4);
+    s.tiles = reinterpret_cast<Tile*>(b + L.tiles);
+    s.s64 = b + L.s64;
+    s.s32 = s32b ? b + L.s32 : nullptr;
+    s.near_t = reinterpret_cast<float*>(b + L.near_t);
+    s.excl = reinterpret_cast<int2*>(b + L.excl);
+    s.fbounds = reinterpret_cast<int2*>(b + L.fbounds);
+    s.partial = reinterpret_cast<double*>(b + L.partial);
+    s.counters = reinterpret_cast<unsigned long long*>(b + L.counters);
+    s.flag = reinterpret_cast<int*>(b + L.flag);
     return s;
 }
 
+// The launch of a pair kernel has P.grid() workgroups; workgroup g writes chunk
+// g / n_tblocks of the partials, which hold P.n_chunks rows of 3 n_t.  Checked on the
+// host before every launch (a grid that outgrew its partial buffer would write past it).
+static int check_grid(const Partition& P, unsigned grid, int64_t n_t) {
+    if ((int64_t)grid != P.grid() || P.n_t != n_t || P.grid() > INT32_MAX ||
+        (int64_t)P.n_chunks * P.tiles_per_chunk < P.n_tiles ||
+        (P.n_chunks > 0 && (int64_t)(P.n_chunks - 1) * P.tiles_per_chunk >= P.n_tiles))
+        return fail(STOKES_E_INVAL, "internal: launch grid does not match the sum's partition");
+    return STOKES_OK;
+}
 
 // The register blocking R must match the one the partition was made with.
 static void launch_sl_kernel(bool mixed, bool doublet, unsigned grid, const SumArgs& a,
@@ -366,6 +360,7 @@ static int sl_core(const SLProblem& p, const Partition& P, const SumScratch& S, 
         a.partial = S.partial;
         a.counters = counters;
         const unsigned grid = (unsigned)((int64_t)P.n_tblocks * P.n_chunks);
+        if (int rc = check_grid(P, grid, p.n_t)) return rc;
         prof_begin(st);
         launch_sl_kernel(p.mixed, p.doublet, grid, a, st);
         prof_end(st);
@@ -599,9 +594,13 @@ static int dl_run(int64_t n_src, const double* src_xyz, const double* src_normal
     const double* tx = same ? src_xyz : trg_xyz;
     const int64_t ts = same ? n_src : n_t;
     if (P.n_chunks > 0) {
-        hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, n_src,
-                           src_xyz, P.n_tiles, mixed ? nr : 0.0, 0.0, (const int32_t*)nullptr, 0,
-                           (const double*)nullptr, S.tiles);
+        if (mixed)
+            hipLaunchKernelGGL(dl_tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, n_src,
+                               src_xyz, src_normal, P.n_tiles, nr, S.tiles);
+        else
+            hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, n_src,
+                               src_xyz, P.n_tiles, 0.0, 0.0, (const int32_t*)nullptr, 0,
+                               (const double*)nullptr, S.tiles);
         hipLaunchKernelGGL(dl_src_prep_kernel, dim3(nblk(n_src)), dim3(256), 0, st, n_src, src_xyz,
                            src_normal, src_weight, src_q, src_sid, S.tiles, static_cast<SrcDL64*>(S.s64),
                            mixed ? static_cast<SrcDL32*>(S.s32) : nullptr);
@@ -622,13 +621,15 @@ static int dl_run(int64_t n_src, const double* src_xyz, const double* src_normal
         a.partial = S.partial;
         a.counters = counters;
         const unsigned grid = (unsigned)((int64_t)P.n_tblocks * P.n_chunks);
+        if ((rc = check_grid(P, grid, n_t))) return rc;
         prof_begin(st);
         launch_dl_kernel(mixed, sub, src_sid != nullptr && sub, grid, a, st);
         prof_end(st);
     }
     hipLaunchKernelGGL(reduce_kernel, dim3(red_blocks(n_t)), dim3(RED_T * RED_S), 0, st, n_t, P.n_chunks,
                        S.partial, (flags & STOKES_ACCUMULATE) ? 1 : 0, u_out, n_t,
-                       (const int2*)S.excl, sub ? src_q : (const double*)nullptr, n_src, -0.5);
+                       (const int2*)S.excl, sub ? src_q : (const double*)nullptr, n_src, -0.5,
+                       mixed ? 1 : 0);
     STOKES_HIP(hipGetLastError());
     if (diag) return finish_diag(ws, counters, st, n_t, n_src, diag);
     return STOKES_OK;
@@ -643,6 +644,106 @@ extern "C" int stokes_dl_eval(int64_t n_src, const double* src_xyz, const double
 }
 
 namespace stokes {
+
+// Density of the double-layer packs: the only part of a plan's sources that changes
+// between evaluations on a fixed geometry.
+__global__ void dl_q_pack_kernel(int64_t n_s, const double* __restrict__ q, SrcDL64* s64, SrcDL32* s32) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_s) return;
+    const double qx = q[j], qy = q[n_s + j], qz = q[2 * n_s + j];
+    s64[j].qx = qx;
+    s64[j].qy = qy;
+    s64[j].qz = qz;
+    if (s32) {
+        s32[j].qx = (float)qx;
+        s32[j].qy = (float)qy;
+        s32[j].qz = (float)qz;
+    }
+}
+
+DLPlan::~DLPlan() {
+    if (mem_) (void)hipFree(mem_);
+}
+
+int DLPlan::init(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
+                 const int32_t* src_sid, int64_t n_trg, const double* trg_xyz, const int64_t* trg_self,
+                 double near_r, uint32_t flags, hipStream_t st) {
+    if (mem_) return fail(STOKES_E_INVAL, "DLPlan::init: plan already made");
+    const uint32_t known = STOKES_PREC_MIXED | STOKES_ONSURF_RAW;
+    if (flags & ~known) return fail(STOKES_E_INVAL, "DLPlan::init: unknown flag bits");
+    if (n_src < 1 || n_trg < 1 || !src_xyz || !src_normal || !src_weight || !trg_xyz)
+        return fail(STOKES_E_INVAL, "DLPlan::init: empty or null geometry");
+    if (n_src >= (int64_t)1 << 31 || n_trg >= (int64_t)1 << 31)
+        return fail(STOKES_E_INVAL, "DLPlan::init: more than 2^31-1 sources or targets");
+    if (src_sid && (flags & STOKES_ONSURF_RAW))
+        return fail(STOKES_E_INVAL, "DLPlan::init: surface ids need the on-surface subtraction");
+    mixed_ = flags & STOKES_PREC_MIXED;
+    sub_ = !(flags & STOKES_ONSURF_RAW);
+    multi_ = src_sid != nullptr;
+    n_s_ = n_src;
+    n_t_ = n_trg;
+    txyz_ = trg_xyz;
+    const double nr = near_r > 0.0 ? near_r : 0.02;
+    near2_ = (float)(nr * nr);
+    P_ = make_partition(n_t_, n_s_, mixed_ ? R_DL32 : R_DL64);
+    const SumLayout L = sum_layout(n_s_, n_t_, 0, sizeof(Tile), sizeof(SrcDL64), mixed_ ? sizeof(SrcDL32) : 0,
+                                   P_.n_chunks);
+    STOKES_HIP(hipMalloc(&mem_, L.bytes));
+    char* b = static_cast<char*>(mem_);
+    tiles_ = reinterpret_cast<Tile*>(b + L.tiles);
+    s64_ = reinterpret_cast<SrcDL64*>(b + L.s64);
+    s32_ = mixed_ ? reinterpret_cast<SrcDL32*>(b + L.s32) : nullptr;
+    excl_ = reinterpret_cast<int2*>(b + L.excl);
+    partial_ = reinterpret_cast<double*>(b + L.partial);
+    hipLaunchKernelGGL(excl_self_kernel, dim3(nblk(n_t_)), dim3(256), 0, st, n_t_, trg_self, 0, n_s_, excl_,
+                       (unsigned long long*)nullptr);
+    if (mixed_)
+        hipLaunchKernelGGL(dl_tile_prep_kernel, dim3(nblk(P_.n_tiles, 64)), dim3(64), 0, st, n_s_, src_xyz,
+                           src_normal, P_.n_tiles, nr, tiles_);
+    else
+        hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P_.n_tiles, 64)), dim3(64), 0, st, n_s_, src_xyz, P_.n_tiles,
+                           0.0, 0.0, (const int32_t*)nullptr, 0, (const double*)nullptr, tiles_);
+    // positions, weighted normals and surface ids now; the density per evaluation (a
+    // zero density until then: the pack kernel reads q, so pass the normals as a stand-in
+    // and overwrite them in every evaluation)
+    hipLaunchKernelGGL(dl_src_prep_kernel, dim3(nblk(n_s_)), dim3(256), 0, st, n_s_, src_xyz, src_normal,
+                       src_weight, src_normal, src_sid, (const Tile*)tiles_, s64_, s32_);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+int DLPlan::eval(const double* src_q, double* u_out, bool accumulate, hipStream_t st) {
+    if (!mem_) return fail(STOKES_E_INVAL, "DLPlan::eval: no plan");
+    if (!src_q || !u_out) return fail(STOKES_E_INVAL, "DLPlan::eval: null pointer");
+    hipLaunchKernelGGL(dl_q_pack_kernel, dim3(nblk(n_s_)), dim3(256), 0, st, n_s_, src_q, s64_, s32_);
+    SumArgs a{};
+    a.tx = txyz_;
+    a.t_stride = n_t_;
+    a.n_t = n_t_;
+    a.excl = excl_;
+    a.tiles = tiles_;
+    a.n_tiles = P_.n_tiles;
+    a.tiles_per_chunk = P_.tiles_per_chunk;
+    a.n_tblocks = P_.n_tblocks;
+    a.s64 = s64_;
+    a.s32 = s32_;
+    a.near_t_uniform = near2_;
+    a.q = src_q;
+    a.n_s = n_s_;
+    a.partial = partial_;
+    a.counters = nullptr;
+    const unsigned grid = (unsigned)P_.grid();
+    if (int rc = check_grid(P_, grid, n_t_)) return rc;
+    prof_begin(st);
+    launch_dl_kernel(mixed_, sub_, multi_, grid, a, st);
+    prof_end(st);
+    hipLaunchKernelGGL(reduce_kernel, dim3(red_blocks(n_t_)), dim3(RED_T * RED_S), 0, st, n_t_, P_.n_chunks,
+                       (const double*)partial_, accumulate ? 1 : 0, u_out, n_t_, (const int2*)excl_,
+                       sub_ ? src_q : (const double*)nullptr, n_s_, -0.5, mixed_ ? 1 : 0);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
 // The double layer over several surfaces in one sum (see dl_fp64_wave's MULTI).
 int dl_eval_surfaces(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
                      const double* src_q, const int32_t* src_sid, int64_t n_trg, const double* trg_xyz,

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <vector>
 
+#include "pair_math.hpp"
 #include "stokes_internal.hpp"
 
 namespace stokes {
@@ -356,19 +357,12 @@ __device__ __forceinline__ void kahan(float& s, float& c, float x) {
     s = t;
 }
 
-// 1/sqrt(x) in FP64 for x > 0: the hardware estimate y, then one third-order Newton
-// step y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2.
-__device__ __forceinline__ double rsq64(double x) {
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-(x * y), y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
-}
 
 // FP64 single-layer pair (Stokeslet + doublet) into (ux, uy, uz).
 __device__ __forceinline__ void pair64(double dx, double dy, double dz, double sx, double sy, double sz,
                                        double c, double& ux, double& uy, double& uz) {
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double ri = rsq64(r2);
+    const double ri = rsqrt64(r2);
     const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
     const double ds = dx * sx + dy * sy + dz * sz;
     const double A = fma(c, ri3, ri);
@@ -529,7 +523,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
                 for (int k = 0; k < m; ++k) {
                     const double dx = (x - cx) - ld[k][0], dy = (y - cy) - ld[k][1], dz = (z - cz) - ld[k][2];
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    const double ri = rsq64(r2);
+                    const double ri = rsqrt64(r2);
                     const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
                     const double dF = dx * ld[k][3] + dy * ld[k][4] + dz * ld[k][5];
                     const double dD = dx * ld[k][6] + dy * ld[k][7] + dz * ld[k][8];
@@ -724,6 +718,18 @@ __global__ __launch_bounds__(TB) void k_tr_dlsrc(int64_t ns, const int64_t* sper
     }
 }
 
+// Mixed double layer: per sorted source, the squared radius below which its direct pairs
+// are taken in FP64: the larger of the near radius and the tangent band of the source's
+// run of 32 sorted sources (dl_band_radius; the sort keeps a run spatially compact).
+__global__ __launch_bounds__(TB) void k_tr_dlband(int64_t ns, const double* __restrict__ sxyz,
+                                                  const double* __restrict__ wn, double near_r, float* st) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= ns) return;
+    const int64_t j0 = j & ~(int64_t)31, j1 = j0 + 32 < ns ? j0 + 32 : ns;
+    const double r = fmax(near_r, dl_band_radius<false>(j0, j1, ns, sxyz, wn));
+    st[j] = (float)(r * r);
+}
+
 struct DlArgs {
     int64_t ns, nt;
     const double* sxyz;      // [3][ns] sorted sources
@@ -745,14 +751,17 @@ struct DlArgs {
     const int32_t* dr_count;
     double* out;
     int accumulate, subtract;
-    float near2;             // mixed: FP64 below this squared distance
+    const float* near2;      // mixed: [ns] FP64 below this squared distance (k_tr_dlband)
 };
 
 // Waves 2k and 2k+1 take the halves of batch b's proxy and direct lists, as in
 // k_tr_eval, and the halves are added in that order.  MIXED: proxies and direct pairs in
 // FP32 relative to the batch centre, each cluster's or chunk's sum added with Kahan
-// compensation; direct pairs closer than near_r (and the self point) are taken in FP64
-// from the sorted sources.
+// compensation; direct pairs closer than the source's near2 (the near radius or the
+// tangent band, and the self point) are taken in FP64 from the sorted sources.  The
+// subtracted self density is rounded to FP32 once and used as such everywhere (FP32
+// pairs and proxies, FP64 pairs, jump term), so that its constant part cancels against
+// the jump up to the discrete identity's defect.
 template <bool MIXED>
 __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
     __shared__ double lds_[EW][64][15];
@@ -775,8 +784,13 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
     const double xl = x - cx, yl = y - cy, zl = z - cz;
     const int64_t self = a.tself ? a.tself[ti] : -1;
     const bool sub = a.subtract && self >= 0;
-    const double q0x = sub ? a.sq[self] : 0.0, q0y = sub ? a.sq[a.ns + self] : 0.0,
-                 q0z = sub ? a.sq[2 * a.ns + self] : 0.0;
+    double q0x = sub ? a.sq[self] : 0.0, q0y = sub ? a.sq[a.ns + self] : 0.0,
+           q0z = sub ? a.sq[2 * a.ns + self] : 0.0;
+    if (MIXED) {
+        q0x = (double)(float)q0x;
+        q0y = (double)(float)q0y;
+        q0z = (double)(float)q0z;
+    }
     double u0 = 0.0, u1 = 0.0, u2 = 0.0;
     float (*lf)[16] = lfs[w];
     const float fxl = (float)xl, fyl = (float)yl, fzl = (float)zl;
@@ -807,14 +821,13 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
                     const float dx = fxl - lf[k][0], dy = fyl - lf[k][1], dz = fzl - lf[k][2];
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const float ri = __builtin_amdgcn_rsqf(r2);
-                    const float ri2 = ri * ri;
                     const float m0 = fmaf(lf[k][3], dx, fmaf(lf[k][4], dy, lf[k][5] * dz));
                     const float m1 = fmaf(lf[k][6], dx, fmaf(lf[k][7], dy, lf[k][8] * dz));
                     const float m2 = fmaf(lf[k][9], dx, fmaf(lf[k][10], dy, lf[k][11] * dz));
                     const float dMd = fmaf(dx, m0, fmaf(dy, m1, dz * m2));
                     const float dN = fmaf(dx, lf[k][12], fmaf(dy, lf[k][13], dz * lf[k][14]));
                     const float dq0 = fmaf(dx, fq0x, fmaf(dy, fq0y, dz * fq0z));
-                    const float kk = fmaf(-dq0, dN, dMd) * (ri2 * ri2 * ri);
+                    const float kk = fmaf(-dq0, dN, dMd) * rinv5_f32(r2, ri);
                     p0 = fmaf(kk, dx, p0);
                     p1 = fmaf(kk, dy, p1);
                     p2 = fmaf(kk, dz, p2);
@@ -840,7 +853,7 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
             for (int k = 0; k < m; ++k) {
                 const double dx = xl - ld[k][0], dy = yl - ld[k][1], dz = zl - ld[k][2];
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const double ri = rsq64(r2);
+                const double ri = rsqrt64(r2);
                 const double ri2 = ri * ri, ri5 = ri2 * ri2 * ri;
                 const double m0 = ld[k][3] * dx + ld[k][4] * dy + ld[k][5] * dz;
                 const double m1 = ld[k][6] * dx + ld[k][7] * dy + ld[k][8] * dz;
@@ -872,6 +885,7 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
                         lf[l][3 + c] = (float)a.wn[c * a.ns + j];
                         lf[l][6 + c] = (float)a.sq[c * a.ns + j];
                     }
+                    lf[l][9] = a.near2[j];
                 }
                 wave_sync();
                 float p0 = 0.f, p1 = 0.f, p2 = 0.f;
@@ -880,15 +894,14 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
                 for (int k = 0; k < m; ++k) {
                     const float dx = fxl - lf[k][0], dy = fyl - lf[k][1], dz = fzl - lf[k][2];
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    if (r2 < a.near2) {                 // includes the self point
+                    if (r2 < lf[k][9]) {                // includes the self point
                         near |= 1ull << k;
                         continue;
                     }
                     const float ri = __builtin_amdgcn_rsqf(r2);
-                    const float ri2 = ri * ri;
                     const float dq = fmaf(dx, lf[k][6] - fq0x, fmaf(dy, lf[k][7] - fq0y, dz * (lf[k][8] - fq0z)));
                     const float dn = fmaf(dx, lf[k][3], fmaf(dy, lf[k][4], dz * lf[k][5]));
-                    const float kk = dq * dn * (ri2 * ri2 * ri);
+                    const float kk = dq * dn * rinv5_f32(r2, ri);
                     p0 = fmaf(kk, dx, p0);
                     p1 = fmaf(kk, dy, p1);
                     p2 = fmaf(kk, dz, p2);
@@ -904,7 +917,7 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
                     const double dx = x - a.sxyz[j], dy = y - a.sxyz[a.ns + j], dz = z - a.sxyz[2 * a.ns + j];
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 == 0.0) continue;                    // coincident: skipped
-                    const double ri = rsq64(r2), ri2 = ri * ri;
+                    const double ri = rsqrt64(r2), ri2 = ri * ri;
                     const double dq = dx * (a.sq[j] - q0x) + dy * (a.sq[a.ns + j] - q0y) +
                                       dz * (a.sq[2 * a.ns + j] - q0z);
                     const double dn = dx * a.wn[j] + dy * a.wn[a.ns + j] + dz * a.wn[2 * a.ns + j];
@@ -930,7 +943,7 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
                 const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 == 0.0) continue;                            // coincident: skipped
-                const double ri = rsq64(r2), ri2 = ri * ri;
+                const double ri = rsqrt64(r2), ri2 = ri * ri;
                 const double dq = dx * (ld[k][6] - q0x) + dy * (ld[k][7] - q0y) + dz * (ld[k][8] - q0z);
                 const double dn = dx * ld[k][3] + dy * ld[k][4] + dz * ld[k][5];
                 const double kk = dq * dn * (ri2 * ri2 * ri);
@@ -1396,7 +1409,10 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
     a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
     a.subtract = (flags & STOKES_ONSURF_RAW) ? 0 : 1;
     const double nr = near_r > 0.0 ? near_r : 0.02;
-    a.near2 = (float)(nr * nr);
+    if (flags & STOKES_PREC_MIXED)
+        hipLaunchKernelGGL(k_tr_dlband, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns,
+                           (const double*)t->sxyz, (const double*)t->ss, nr, t->st);
+    a.near2 = t->st;
     const unsigned grid = (unsigned)((t->nb + EW / 2 - 1) / (EW / 2));
     if (flags & STOKES_PREC_MIXED)
         hipLaunchKernelGGL(k_tr_dl_eval<true>, dim3(grid), dim3(64 * EW), 0, st, a);

@@ -4,6 +4,7 @@
 
 #include <climits>
 
+#include "pair_math.hpp"
 #include "stokes_internal.hpp"
 
 // Unroll depth of the branch-free source loops (tuned on gfx950; overridable
@@ -44,16 +45,6 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
 constexpr double PI_D = 3.14159265358979323846264338327950288;
 
 // ---- small device helpers -------------------------------------------------
-
-// 1/sqrt(x) to full FP64 accuracy: hardware estimate plus one third-order
-// Newton-Raphson correction y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
-__device__ __forceinline__ double rsqrt64(double x) {
-    const double y = __builtin_amdgcn_rsq(x);
-    const double h = x * y;
-    const double e = fma(-h, y, 1.0);
-    const double p = fma(e, 0.375, 0.5);
-    return fma(y * e, p, y);
-}
 
 __device__ __forceinline__ bool in_range(int j, int lo, int hi) {
     return (unsigned)(j - lo) < (unsigned)(hi - lo);
@@ -142,21 +133,27 @@ __device__ __forceinline__ void dl_pair64(double dx, double dy, double dz, doubl
     uz = fma(e, dz, uz);
 }
 
+// FP32 pair with d.n' given (dl_pair32 forms it from the FP32 operands).
 template <bool SUB>
-__device__ __forceinline__ void dl_pair32(float dx, float dy, float dz, float ri, const SrcDL32& s,
-                                          float q0x, float q0y, float q0z, float& ux, float& uy,
-                                          float& uz) {
+__device__ __forceinline__ void dl_pair32_dn(float dx, float dy, float dz, float dn, float r2, float ri,
+                                             const SrcDL32& s, float q0x, float q0y, float q0z,
+                                             float& ux, float& uy, float& uz) {
     const float qx = SUB ? s.qx - q0x : s.qx;
     const float qy = SUB ? s.qy - q0y : s.qy;
     const float qz = SUB ? s.qz - q0z : s.qz;
     const float dq = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
-    const float dn = fmaf(dx, s.nx, fmaf(dy, s.ny, dz * s.nz));
-    const float ri2 = ri * ri;
-    const float ri5 = ri2 * ri2 * ri;
-    const float e = dq * dn * ri5;
+    const float e = dq * dn * rinv5_f32(r2, ri);
     ux = fmaf(e, dx, ux);
     uy = fmaf(e, dy, uy);
     uz = fmaf(e, dz, uz);
+}
+
+template <bool SUB>
+__device__ __forceinline__ void dl_pair32(float dx, float dy, float dz, float r2, float ri, const SrcDL32& s,
+                                          float q0x, float q0y, float q0z, float& ux, float& uy,
+                                          float& uz) {
+    const float dn = fmaf(dx, s.nx, fmaf(dy, s.ny, dz * s.nz));
+    dl_pair32_dn<SUB>(dx, dy, dz, dn, r2, ri, s, q0x, q0y, q0z, ux, uy, uz);
 }
 
 __device__ __forceinline__ void wave_count(unsigned long long* ctr, unsigned long long v) {
@@ -589,15 +586,23 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
             qz[r] = a.q[2 * a.n_s + e.x];
             if (MULTI) tsid[r] = static_cast<const SrcDL64*>(a.s64)[e.x].pad0;
         }
+        // The subtracted self density is rounded to FP32 once, and that value is used by
+        // the FP32 pairs, the FP64 near pairs and the jump term (reduce_kernel) alike:
+        // the constant part of q then cancels against the jump up to the discrete
+        // identity's defect, instead of leaving half the rounding of q_self behind.
         fqx[r] = (float)qx[r];
         fqy[r] = (float)qy[r];
         fqz[r] = (float)qz[r];
+        qx[r] = (double)fqx[r];
+        qy[r] = (double)fqy[r];
+        qz[r] = (double)fqz[r];
         near_sum[3 * r][tid] = near_sum[3 * r + 1][tid] = near_sum[3 * r + 2][tid] = 0.0;
         Sx[r] = Sy[r] = Sz[r] = Cx[r] = Cy[r] = Cz[r] = 0.0f;
     }
     near_cnt[0][tid] = near_cnt[1][tid] = 0u;   // at most the thread's targets x the chunk's sources
     const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcDL64* __restrict__ src64 = static_cast<const SrcDL64*>(a.s64);
+    const cptr<SrcDL64> srcc64 = as_const(src64);
     const float tn = a.near_t_uniform;
     const int2 xu = wave_excl_union<R>(lo, hi);
     const int t0 = chunk * a.tiles_per_chunk;
@@ -644,7 +649,7 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                     const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const bool own = !MULTI || s.pad0 == (float)tsid[r];
-                    dl_pair32<SUB>(dx, dy, dz, __builtin_amdgcn_rsqf(r2), s, own ? fqx[r] : 0.f, own ? fqy[r] : 0.f,
+                    dl_pair32<SUB>(dx, dy, dz, r2, __builtin_amdgcn_rsqf(r2), s, own ? fqx[r] : 0.f, own ? fqy[r] : 0.f,
                                    own ? fqz[r] : 0.f,
                                    px[r], py[r], pz[r]);
                 }
@@ -657,6 +662,11 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                 for (int k = 0; k < nsrc; ++k) far(k);
             }
         } else {
+            // Tiles within the tangent band of the target (dl_band_radius): d and d.n'
+            // are formed in FP64 and rounded once.  For a target on or near the surface,
+            // d is nearly tangent and d.n' ~ |d|^2 / (2 R_curv); its FP32 evaluation from
+            // tile-local coordinates loses ~ eps32 2 R_curv / |d| of it, the largest
+            // rounding error of the mixed sum.
             uint32_t m[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) m[r] = 0u;
@@ -664,17 +674,20 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                 const int j = T.j0 + k;
                 const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
                 const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, MULTI ? p2.y : 0.f, 0.f, 0.f};
+                const SrcDL64 s8 = srcc64[j];   // wave-uniform: scalar loads
                 const uint32_t bit = 1u << k;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const float dx = xs[r] - s.x, dy = ys[r] - s.y, dz = zs[r] - s.z;
+                    const double Dx = X[r] - s8.x, Dy = Y[r] - s8.y, Dz = Z[r] - s8.z;
+                    const float dx = (float)Dx, dy = (float)Dy, dz = (float)Dz;
+                    const float dn = (float)fma(Dx, s8.nx, fma(Dy, s8.ny, Dz * s8.nz));
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const bool bad = (r2 < tn) | in_range(j, lo[r], hi[r]);
                     m[r] |= bad ? bit : 0u;
                     const float ri = bad ? 0.0f : __builtin_amdgcn_rsqf(r2);
                     const bool own = !MULTI || s.pad0 == (float)tsid[r];
-                    dl_pair32<SUB>(dx, dy, dz, ri, s, own ? fqx[r] : 0.f, own ? fqy[r] : 0.f, own ? fqz[r] : 0.f,
-                                   px[r], py[r], pz[r]);
+                    dl_pair32_dn<SUB>(dx, dy, dz, dn, r2, ri, s, own ? fqx[r] : 0.f, own ? fqy[r] : 0.f,
+                                      own ? fqz[r] : 0.f, px[r], py[r], pz[r]);
                 }
             }
             uint32_t nnear = 0, ncoin = 0;

@@ -103,6 +103,28 @@ def test_session_mixed_alone_equals_mix(S):
         assert np.array_equal(a, m)
 
 
+def test_session_mixed_matches_oracle_and_one_shot(S, oracle_mod):
+    """Mixed sums in a session: against the oracle's FP64 GMRES (the solve carries the
+    sums' 2e-6 error times the operator's conditioning, as the one-shot mixed solve),
+    and bitwise equal to the one-shot mixed solve, which runs the same kernels on the
+    same partition."""
+    reqs = [W.serving_request(4, 100 + rid, n_fib=n, nodes=p, iters=k)
+            for rid, (n, p, k) in enumerate([(60, 32, 30), (35, 16, 24), (20, 64, 26)])]
+    with S.Session(hbm_budget_bytes=1 << 30, max_slots=4, mixed=True) as s4:
+        ts = [_submit(s4, r) for r in reqs]
+        out = [s4.wait(t) for t in ts]
+    for r, (f, st) in zip(reqs, out):
+        ref, _, _ = _oracle_solve(oracle_mod, r)
+        err = rel(f, ref)
+        print(f"mixed session request {r['rid']}: rel err {err:.3e} after {st['iters']} iterations")
+        assert st["status"] == 0
+        assert err <= 1e-5
+        fs = r["fibers"]
+        g, _, _ = S.mobility_solve(dev(fs.xyz), dev(fs.tangent), dev(fs.length), dev(r["rhs"]),
+                                   fs.nodes_per_fiber, fs.eps, r["iters"], mixed=True)
+        assert np.array_equal(g.cpu().numpy(), f), f"request {r['rid']}: session != one-shot"
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_session_split_matvecs_are_bitwise_unchanged(S, mixed):
     # a pair budget far below one matvec spreads every single-layer sum over

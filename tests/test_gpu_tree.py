@@ -183,20 +183,23 @@ def sphere_ref(oracle_mod, sphere):
 # The stresslet's interpolation error is far larger than the Stokeslet's at the same
 # degree and theta (on the surface, the d.n factor nearly cancels for neighbouring
 # points in the exact kernel but not in the interpolated one), so these plans use
-# higher degrees than the single-layer ones.  Mixed: FP64 below a near radius of 0.4;
-# the bound is that of FP32 stresslet pairs on a random density (the direct mixed sum
-# gives 2.7e-6 on this sphere at the same radius, the treecode 3.0e-6 on all targets).
-@pytest.mark.parametrize("degree,theta,mixed,tol", [(8, 0.5, False, 2e-7), (9, 0.5, False, 4e-8),
-                                                    (8, 0.5, True, 1e-5), (9, 0.5, True, 1e-5)])
-def test_tree_double_layer_vs_oracle(S, sphere, sphere_ref, degree, theta, mixed, tol):
+# higher degrees than the single-layer ones.  Mixed (FP32 proxies and direct pairs,
+# FP64 within the near radius or the tangent band): the tree's own FP64 error plus the
+# mixed bound 2e-6, at the default near radius (0: 0.02) and at a wider one.
+@pytest.mark.parametrize("degree,theta,mixed,tol,near_r", [
+    (8, 0.5, False, 2e-7, 0.0), (9, 0.5, False, 4e-8, 0.0),
+    (8, 0.5, True, 2e-7 + 2e-6, 0.0), (9, 0.5, True, 4e-8 + 2e-6, 0.0), (8, 0.5, True, 2e-7 + 2e-6, 0.4)])
+def test_tree_double_layer_vs_oracle(S, sphere, sphere_ref, degree, theta, mixed, tol, near_r):
     sph, q = sphere
     idx, ref = sphere_ref
     T = S.Tree(dev(sph.xyz), degree=degree, theta=theta, leaf_size=64)
     assert T.info()["proxy_pairs"] > 0
     for raw in (False, True):
-        u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), raw=raw, mixed=mixed, near_r=0.4).cpu().numpy()
+        u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), raw=raw, mixed=mixed,
+                      near_r=near_r).cpu().numpy()
         err = relmax(u[:, idx], ref[raw])
-        print(f"double layer, degree {degree} theta {theta} mixed {mixed} raw {raw}: err {err:.2e}, {T.info()}")
+        print(f"double layer, degree {degree} theta {theta} mixed {mixed} near_r {near_r} raw {raw}: "
+              f"err {err:.2e}, {T.info()}")
         assert err <= tol
 
 
@@ -224,13 +227,38 @@ def test_tree_double_layer_all_direct_is_exact(S, oracle_mod):
 
 def test_tree_double_layer_constant_density(S, sphere):
     # q constant: with the subtraction every pair term is zero (a proxy's M_k is
-    # q N_k^T to rounding), so u = -q/2 at every surface point
+    # q N_k^T to rounding), so u = -q/2 at every surface point.  Mixed: the far field
+    # forms d^T M d - (d.q0)(d.N) in FP32, two nearly equal terms; the direct pairs'
+    # q_s - q0 is exactly zero (both rounded once).
     sph, _ = sphere
     q = np.tile(np.array([[0.3], [-1.1], [0.7]]), (1, sph.n))
     T = S.Tree(dev(sph.xyz), degree=6, theta=0.7, leaf_size=64)
     u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q)).cpu().numpy()
     assert T.info()["proxy_pairs"] > 0
     assert np.abs(u + 0.5 * q).max() <= 1e-12
+    um = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), mixed=True).cpu().numpy()
+    err = relmax(um, -0.5 * q)
+    print(f"constant density, mixed: {err:.2e}")
+    assert err <= 2e-6
+
+
+def test_tree_double_layer_constant_density_off_surface_mixed(S, sphere):
+    # -q inside, 0 outside (identity of the double layer); mixed, against |q|
+    sph, _ = sphere
+    q0 = np.array([0.3, -1.1, 0.7])
+    q = np.tile(q0[:, None], (1, sph.n))
+    rng = np.random.default_rng(6)
+    d = rng.standard_normal((3, 3000))
+    d /= np.linalg.norm(d, axis=0)
+    r = np.concatenate([rng.uniform(0.5, 4.0, 1500), rng.uniform(6.0, 9.0, 1500)])
+    trg = d * r
+    T = S.Tree(dev(sph.xyz), dev(trg), degree=7, theta=0.6, leaf_size=64)
+    for mixed in (False, True):
+        u = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), mixed=mixed).cpu().numpy()
+        want = np.where(r < 5.0, -1.0, 0.0)[None, :] * q0[:, None]
+        err = np.abs(u - want).max() / np.abs(q0).max()
+        print(f"constant density off the surface, mixed {mixed}: {err:.2e}")
+        assert err <= (2e-8 if not mixed else 2e-6)
 
 
 def test_tree_double_layer_off_surface_and_accumulate(S, oracle_mod, sphere):
@@ -247,7 +275,7 @@ def test_tree_double_layer_off_surface_and_accumulate(S, oracle_mod, sphere):
     print(f"double layer off the surface: err {err:.2e}, {T.info()}")
     assert err <= 2e-8
     assert T.info()["proxy_pairs"] > 0
-    um = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), mixed=True, near_r=0.4).cpu().numpy()
+    um = T.dl_eval(dev(sph.normal), dev(sph.weight), dev(q), mixed=True).cpu().numpy()
     err = relmax(um, ref)
     print(f"double layer off the surface, mixed: err {err:.2e}")
-    assert err <= 1e-5
+    assert err <= 2e-8 + 2e-6
