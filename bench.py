@@ -74,12 +74,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=150)
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-other", action="store_true",
                     help="time the oracle on the headline workload only")
     ap.add_argument("--only", choices=["mixed", "fp64", "both", "none", "nonlocal", "particles",
-                                       "treecode", "fiberstep"],
+                                       "treecode", "fiberstep", "serving_cpu", "far", "workloads"],
                     default="both",
                     help="none: serving run alone; nonlocal / particles / treecode / fiberstep: that "
                          "section alone")
@@ -194,6 +194,9 @@ def config_run(S, torch, name, steps, warmup, log_fn):
 
 
 def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
+    """One Poisson stream of n_req mobility-solve requests through a session (64 slots,
+    4 GiB), at `rate` requests/s or, when 0, at 0.7 x the capacity a calibration burst
+    measures.  Latency is submit -> result, as the session's own clock records it."""
     from paper_1602_05650_amd import workloads as W
     reqs = [W.serving_request(3, rid) for rid in range(n_req)]
     pairs = sum(r["iters"] * r["fibers"].n * (r["fibers"].n - r["fibers"].nodes_per_fiber)
@@ -219,9 +222,9 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
         cap = len(cal) / (time.perf_counter() - t0)
         rate = rate if rate > 0 else 0.7 * cap
         arrivals = W.serving_stream(3, n_req, rate)
-        log_fn(f"serving: capacity {cap:.1f} req/s (calibration), Poisson rate {rate:.1f} req/s")
+        log_fn(f"serving ({'mixed' if mixed else 'fp64'}): capacity {cap:.1f} req/s (calibration), "
+               f"Poisson rate {rate:.1f} req/s, {n_req} requests")
         tickets = [None] * n_req
-        t_sub = [0.0] * n_req
 
         def producer():
             start = time.perf_counter()
@@ -229,7 +232,6 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
                 dt = arrivals[i] - (time.perf_counter() - start)
                 if dt > 0:
                     time.sleep(dt)
-                t_sub[i] = time.monotonic_ns()
                 tickets[i] = submit(sess, r)
 
         th = threading.Thread(target=producer)
@@ -241,6 +243,8 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
                 time.sleep(0.0005)
             _, st = sess.wait(tickets[i])
             lat.append((st["t_finish_ns"] - st["t_submit_ns"]) * 1e-6)
+            if (i + 1) % 500 == 0:
+                log_fn(f"serving: {i + 1}/{n_req} requests done")
         th.join()
         wall = time.perf_counter() - t_start
     lat = np.array(lat)
@@ -258,6 +262,37 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
         "workload": "Poisson stream; N_f log-uniform [32, 2048] fibers x {16,32,64} nodes; "
                     "20-60 GMRES iterations; same-fiber excluded, Clenshaw-Curtis weights",
     }
+
+
+def serving_cpu(n_req, n_sample, log_fn):
+    """The oracle on n_sample seeded requests of the serving stream: one GMRES iteration
+    of each (operator application, Gram-Schmidt, Givens) timed on all host threads, and
+    the time of the request's whole iteration budget extrapolated from it."""
+    import oracle
+    from paper_1602_05650_amd import workloads as W
+    oracle.build(force=False)
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    ids = W.subsample(33, n_req, n_sample)
+    t_meas, t_extrap, pairs = 0.0, 0.0, 0
+    for rid in ids:
+        r = W.serving_request(3, int(rid))
+        fs = r["fibers"]
+        t0 = time.perf_counter()
+        oracle.mobility_solve(r["rhs"], fs.xyz, fs.tangent, fs.fiber, fs.length, fs.nodes_per_fiber,
+                              fs.eps, 1, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        t_meas += dt
+        t_extrap += dt * r["iters"]
+        pairs += r["iters"] * fs.n * (fs.n - fs.nodes_per_fiber)
+    out = {"kind": "oracle", "cores": nthreads, "requests": [int(i) for i in ids],
+           "measured_s": round(t_meas, 2),
+           "extrapolated_s_per_request": round(t_extrap / len(ids), 2),
+           "extrapolated_gpair_per_s": round(pairs / t_extrap / 1e9, 4),
+           "sample": f"{len(ids)} seeded requests of the stream, one GMRES iteration each "
+                     "(measured); their whole iteration budgets extrapolated as iterations x "
+                     "that time"}
+    log_fn(f"serving cpu oracle: {out}")
+    return out
 
 
 FLOPS_PER_PAIR_NONLOCAL = 36   # K_delta node pair: 3 sub, |r|^2 5, a 3, r.f 5, b 2, 3 x (2 fma) 12, s-term 6
@@ -402,6 +437,51 @@ def fiberstep_run(S, torch, log_fn, reps=3, iters=60, tol=1e-5):
                     "max_tension": float(f"{float(T1.abs().max()):.4e}")}
         log_fn(f"fiber step {tag}: {sec * 1e3:.1f} ms, {it} iterations, pair sums "
                f"{kms / reps:.1f} ms")
+    return res
+
+
+def far_run(S, torch, log_fn, degree=6, theta=0.7, reps=3):
+    """The solvers' u_bar sums through a treecode plan (one per call) against the direct
+    sums: the 2048 x 32 implicit step (GMRES to 1e-5) and the largest serving request
+    shape (2048 fibers x 64 nodes, 60 GMRES iterations) as a one-shot mobility solve;
+    mixed sums; time, iterations and the result's difference from the direct one."""
+    from paper_1602_05650_amd import workloads as W
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    far = (degree, theta)
+    res = {"tree": {"degree": degree, "theta": theta}}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    c = W.config_step()
+    fs = c["fibers"]
+    n = fs.nodes_per_fiber
+    a = (d(fs.xyz), d(fs.length), d(c["f_ext"]), n, c["eps"], c["E"], c["dt"])
+    kw = dict(mu=c["mu"], iters=60, tol=1e-5, mixed=True)
+    t_dir, (X0, _, _, i0) = timed(lambda: S.fiber_step(*a, **kw))
+    t_far, (X1, _, _, i1) = timed(lambda: S.fiber_step(*a, far=far, **kw))
+    dX0, dX1 = X0 - a[0], X1 - a[0]
+    res["fiber_step_2048x32"] = {
+        "direct_ms": round(t_dir * 1e3, 2), "tree_ms": round(t_far * 1e3, 2),
+        "iterations": [i0, i1],
+        "dX_rel_diff": float(f"{float((dX1 - dX0).abs().max() / dX0.abs().max()):.3e}")}
+    log_fn(f"far field, fiber step: direct {t_dir * 1e3:.1f} ms, tree {t_far * 1e3:.1f} ms")
+    req = W.serving_request(3, 40000, n_fib=2048, nodes=64, iters=60)
+    fs = req["fibers"]
+    b = (d(fs.xyz), d(fs.tangent), d(fs.length), d(req["rhs"]), fs.nodes_per_fiber, fs.eps, 60)
+    t_dir, (f0, r0, j0) = timed(lambda: S.mobility_solve(*b, mixed=True))
+    t_far, (f1, r1, j1) = timed(lambda: S.mobility_solve(*b, mixed=True, far=far))
+    res["mobility_solve_2048x64_60it"] = {
+        "direct_ms": round(t_dir * 1e3, 2), "tree_ms": round(t_far * 1e3, 2),
+        "iterations": [j0, j1],
+        "f_rel_diff": float(f"{float(torch.linalg.vector_norm(f1 - f0) / torch.linalg.vector_norm(f0)):.3e}")}
+    log_fn(f"far field, mobility solve: direct {t_dir * 1e3:.1f} ms, tree {t_far * 1e3:.1f} ms")
     return res
 
 
@@ -610,12 +690,23 @@ def main():
     if args.only == "fiberstep":     # implicit fiber time step alone (for profiling it)
         print(json.dumps({"fiber_step": fiberstep_run(S, torch, log)}), flush=True)
         return
+    if args.only == "workloads":     # the --extra workloads alone (for profiling them)
+        names = [e for e in args.extra.split(",") if e in ("c0", "c1", "c4")]
+        print(json.dumps({"other_workloads": {e: config_run(S, torch, e, 200 if e == "c0" else 10, 3, log)
+                                              for e in names}}), flush=True)
+        return
+    if args.only == "far":           # the solvers with the treecode far field
+        print(json.dumps({"far_field_in_solvers": far_run(S, torch, log)}), flush=True)
+        return
     if args.only == "particles":     # rigid-particle section alone (for profiling it)
         print(json.dumps({"particles": particles_run(S, torch, log)}), flush=True)
         return
     if args.only == "none":          # serving run alone (for profiling it)
         print(json.dumps({"serving": serving_run(S, args.serving_requests, log, args.step_pairs,
                                                  not args.serving_fp64, args.serving_rate)}), flush=True)
+        return
+    if args.only == "serving_cpu":   # the oracle's serving leg alone
+        print(json.dumps({"serving_cpu": serving_cpu(args.serving_requests, 10, log)}), flush=True)
         return
     t_gen = time.perf_counter()
     c = W.config2()
@@ -723,13 +814,19 @@ def main():
         out["particles"] = particles_run(S, torch, log)
         out["treecode"] = tree_run(S, torch, log)
         out["fiber_step"] = fiberstep_run(S, torch, log)
+        out["far_field_in_solvers"] = far_run(S, torch, log)
     if not args.no_serving:
-        try:
-            out["serving"] = serving_run(S, args.serving_requests, log, args.step_pairs,
-                                         not args.serving_fp64, args.serving_rate)
-        except Exception as e:  # report, do not hide
-            out["serving"] = {"error": repr(e)}
-            log("serving run failed:", repr(e))
+        out["serving"] = {}
+        for mixed in (True, False):
+            tag = "mixed" if mixed else "fp64"
+            try:
+                out["serving"][tag] = serving_run(S, args.serving_requests, log, args.step_pairs,
+                                                  mixed, args.serving_rate)
+            except Exception as e:  # report, do not hide
+                out["serving"][tag] = {"error": repr(e)}
+                log(f"serving run ({tag}) failed:", repr(e))
+        if not args.no_cpu:
+            out["serving"]["cpu_oracle"] = serving_cpu(args.serving_requests, 10, log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, log, not args.no_cpu_other)
     print(json.dumps(out), flush=True)

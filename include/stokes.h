@@ -195,6 +195,21 @@ int stokes_nonlocal_sbt(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
                         double delta, double mu, double* out, void* stream);
 
 /*
+ * stokes_far -- far field of the u_bar sums of stokes_mobility_solve and
+ * stokes_fiber_step through the treecode of stokes_tree_* (section "Matrix-vector
+ * products and FMM": the paper evaluates these sums with a fast summation at every
+ * GMRES iteration).  A plan is built once per call from the fiber nodes (targets =
+ * sources, same-fiber exclusion); every iteration's sum then runs on it.  Its error
+ * against the direct sum is set by degree and theta as for stokes_tree_create.
+ * Pass NULL for the direct sums.
+ */
+typedef struct stokes_far {
+    int32_t degree;      /* 1..10 */
+    double theta;        /* (0, 1) */
+    int32_t leaf_size;   /* >= 1; <= 0 selects 128 */
+} stokes_far;
+
+/*
  * stokes_mobility_solve -- fiber mobility solve on device pointers.
  *
  * Finds forces f with  M f [+ K_delta f] + u_bar[f] = V  at every fiber node,
@@ -218,13 +233,15 @@ int stokes_nonlocal_sbt(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
  *                        STOKES_NO_DOUBLET, STOKES_NONLOCAL, STOKES_PRECOND_BLOCK.
  * f_out                  [3*N] forces.   resid_out: NULL or host double, the final
  *                        least-squares residual norm.  iters_out: NULL or host int.
+ * far                    NULL (direct u_bar sums) or the treecode's parameters.
  * Synchronous (waits for the stream at the end).
  */
 #define STOKES_MAX_ITERS 128
 int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
                           const double* tangent, const double* fiber_len, const double* rhs,
                           double eps, double mu, double delta, int32_t iters, uint32_t flags,
-                          double* f_out, double* resid_out, int32_t* iters_out, void* stream);
+                          double* f_out, double* resid_out, int32_t* iters_out,
+                          const stokes_far* far, void* stream);
 
 /*
  * stokes_fiber_step -- one implicit (backward Euler) time step of free elastic
@@ -265,6 +282,7 @@ int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const double* xy
  * near_r     mixed single-layer sums only (see stokes_sl_eval).
  * iters      1..STOKES_MAX_ITERS;  tol >= 0 (0: run all iterations).
  * flags      STOKES_PREC_* for the u_bar sums, STOKES_NO_DOUBLET, STOKES_NONLOCAL.
+ * far        NULL (direct u_bar sums) or the treecode's parameters (stokes_far).
  * xyz_out    [3*N] X+ (must not alias xyz or f_ext).   T_out [N] T+ at the nodes.
  * resid_out, iters_out   NULL or host: final least-squares residual, iterations.
  * All arrays are DEVICE pointers.  The call is synchronous.  Its device memory, about
@@ -279,7 +297,8 @@ int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
                       double eps, double E,
                       double dt, double mu, double delta, double near_r, int32_t iters,
                       double tol, uint32_t flags, double* xyz_out, double* T_out,
-                      double* resid_out, int32_t* iters_out, void* stream);
+                      double* resid_out, int32_t* iters_out, const stokes_far* far,
+                      void* stream);
 
 /*
  * stokes_particle_solve -- mobility of rigid particles in a fixed confining
@@ -336,8 +355,11 @@ int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const 
  *   are the sources); degree 1..10, theta in (0, 1), leaf_size >= 1.  The plan
  *   holds the geometry on the device until stokes_tree_destroy.  Synchronous.
  * stokes_tree_sl_eval  one sum on a plan: src_force [3*n_src], src_weight
- *   [n_src] or NULL, src_fiber / fiber_len as in stokes_sl_eval (or both NULL:
- *   L = 1), mu, eps, near_r; flags STOKES_PREC_*, STOKES_EXCL_SELF_POINT or
+ *   [n_src] or NULL, src_fiber / n_fib / fiber_len as in stokes_sl_eval (or
+ *   src_fiber and fiber_len both NULL: L = 1; an id outside [0, n_fib) takes L = 1),
+ *   mu, eps, near_r; flags STOKES_CHECK_INPUTS (the scan of stokes_sl_eval:
+ *   finite forces, weights and lengths, ids in range and non-decreasing;
+ *   synchronous), STOKES_PREC_*, STOKES_EXCL_SELF_POINT or
  *   STOKES_EXCL_SAME_FIBER (one of the two; plans built with targets = sources
  *   only; the fiber mode needs src_fiber, non-decreasing as in stokes_sl_eval, and
  *   subtracts exactly the own-fiber sources that the far field took through
@@ -363,8 +385,8 @@ int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t n_trg, cons
                        int32_t degree, double theta, int32_t leaf_size, void* stream,
                        stokes_tree** out);
 int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, const double* src_weight,
-                        const int32_t* src_fiber, const double* fiber_len, double mu, double eps,
-                        double near_r, uint32_t flags, double* u_out, void* stream);
+                        const int32_t* src_fiber, int32_t n_fib, const double* fiber_len, double mu,
+                        double eps, double near_r, uint32_t flags, double* u_out, void* stream);
 int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, const double* src_weight,
                         const double* src_q, double near_r, uint32_t flags, double* u_out,
                         void* stream);

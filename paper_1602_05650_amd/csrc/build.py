@@ -30,7 +30,8 @@ def build(verbose=False, extra=()):
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-fno-fast-math", "-Wall", "-Wno-unused-function",
-           "-I", os.path.join(ROOT, "include"), *extra, *srcs, "-o", tmp, "-lpthread"]
+           "-I", os.path.join(ROOT, "include"), *extra, *srcs, "-o", tmp, "-lpthread",
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

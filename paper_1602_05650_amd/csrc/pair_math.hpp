@@ -78,4 +78,28 @@ __device__ __forceinline__ double dl_band_radius(int64_t j0, int64_t j1, int64_t
     return k2 > 0.0 ? fmin(BAND_CURV / sqrt(k2), BAND_MAX) : BAND_MAX;
 }
 
+// dl_band_radius<true> of the run [j0, j1) by the 32 lanes of a half-wave (lane l takes
+// point j0 + l against the first and the middle point): the same chords, the same max.
+__device__ __forceinline__ double dl_band_radius_half(int l, int64_t j0, int64_t j1, int64_t ld,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ n) {
+    const int64_t jm = (j0 + j1) / 2;
+    const int64_t k = j0 + l;
+    double k2 = 0.0;
+    if (k < j1) {
+        for (int64_t j = j0; j <= jm; j += (jm - j0 > 0 ? jm - j0 : 1)) {
+            double dy2 = 0.0, dn2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double dy = x[c * ld + j] - x[c * ld + k];
+                const double dn = n[c * ld + j] - n[c * ld + k];
+                dy2 += dy * dy;
+                dn2 += dn * dn;
+            }
+            if (dy2 > 0.0) k2 = fmax(k2, dn2 / dy2);
+        }
+    }
+    for (int off = 16; off > 0; off >>= 1) k2 = fmax(k2, __shfl_xor(k2, off, 32));
+    return k2 > 0.0 ? fmin(BAND_CURV / sqrt(k2), BAND_MAX) : BAND_MAX;
+}
+
 }  // namespace stokes

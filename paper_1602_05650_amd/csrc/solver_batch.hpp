@@ -133,6 +133,18 @@ public:
         int32_t sl_begin, sl_count;
     };
     int step_parts(const std::vector<Part>& parts);
+    // One GMRES iteration of slots attached with OPT_FAR: z = M^{-1} v_j, then `sl(slot)`
+    // writes each slot's single-layer sum (3 x N, the own fiber excluded) into its
+    // partial row 0, then the reduction, Gram-Schmidt and Givens; status read back.
+    template <class F>
+    int step_external(const std::vector<int>& slots, F&& sl) {
+        if (slots.empty()) return STOKES_OK;
+        if (int rc = launch_pre(slots)) return rc;
+        for (int q : slots)
+            if (int rc = sl(q)) return rc;
+        if (int rc = launch_red_ortho(slots)) return rc;
+        return read_status();
+    }
     // step_parts without reading the status rows back: the step is only enqueued.
     // copy_status_async then enqueues the copy of the status rows into `dst` (pinned
     // host memory of MAX_SLOTS * NSTAT doubles), valid once the stream reaches it.
@@ -170,6 +182,8 @@ private:
     int read_status();
 
     int set_step_lists(const std::vector<Part>& parts);
+    int launch_pre(const std::vector<int>& slots);
+    int launch_red_ortho(const std::vector<int>& slots);
     int launch_or_replay();
 
     hipStream_t st_ = nullptr;

@@ -795,9 +795,11 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
                                  const int32_t* clamp_minus, double eps, double E,
                                  double dt, double mu, double delta, double near_r, int32_t iters,
                                  double tol, uint32_t flags, double* xyz_out, double* T_out,
-                                 double* resid_out, int32_t* iters_out, void* stream) {
+                                 double* resid_out, int32_t* iters_out, const stokes_far* far,
+                                 void* stream) {
     const char* who = "stokes_fiber_step: ";
     const int n = nodes_per_fib;
+    if (int rc = check_far(far, "stokes_fiber_step")) return rc;
     if (n_fib < 0 || n < 6 || n > MAX_NPF)
         return fail(STOKES_E_INVAL, std::string(who) + "need n_fib >= 0 and 6 <= nodes_per_fib <= " +
                                         std::to_string(MAX_NPF));
@@ -818,6 +820,7 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
     if (resid_out) *resid_out = 0.0;
     if (iters_out) *iters_out = 0;
     if (N == 0) return STOKES_OK;
+    Range range("stokes_fiber_step");
     if (!xyz || !fiber_len || !f_ext || !xyz_out || !T_out)
         return fail(STOKES_E_INVAL, std::string(who) + "null pointer");
     if (xyz_out == xyz || xyz_out == f_ext)
@@ -894,10 +897,17 @@ extern "C" int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const dou
 
     const uint32_t sumflags = (flags & (STOKES_PREC_MIXED | STOKES_NO_DOUBLET)) | STOKES_EXCL_SAME_FIBER |
                               STOKES_ACCUMULATE;
+    // the other fibers' flow through a treecode plan of this step's nodes, if asked for
+    FarPlan fp;
+    if (far) {
+        if (int rc = fp.make(N, xyz, *far, st)) return rc;
+    }
     // vr = R[f]: the smooth part of K_delta f, then the other fibers' flow added in
     auto smooth_velocity = [&](const double* f, double* vr) -> int {
         hipLaunchKernelGGL(k_fs_smooth, dim3(grid_e(N)), dim3(EB), 0, st, g, f, vr);
         STOKES_HIP(hipGetLastError());
+        if (far)
+            return stokes_tree_sl_eval(fp.t, f, wq, fib, n_fib, fiber_len, mu, eps, near_r, sumflags, vr, st);
         return stokes_sl_eval(N, xyz, f, wq, fib, n_fib, fiber_len, N, xyz, nullptr, fib, mu, eps, near_r,
                               sumflags, vr, st, nullptr);
     };

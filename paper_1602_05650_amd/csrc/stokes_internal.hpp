@@ -7,6 +7,8 @@
 
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "host_logic.hpp"
 #include "stokes.h"
 
@@ -22,6 +24,16 @@ int hip_fail(hipError_t e, const char* what);
         hipError_t e_ = (call);                            \
         if (e_ != hipSuccess) return hip_fail(e_, #call);  \
     } while (0)
+
+// ---- named ranges for the profiler's marker trace (roctx) -------------------
+// One range per solver call or serving step, so a trace shows where each one's
+// kernels begin and end; without a profiler attached a push or pop costs a call.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 // ---- kernel timing for measurement (stokes_profile_enable) -----------------
 // prof_begin/prof_end bracket one launch of a main pair-sum kernel with HIP
@@ -46,6 +58,37 @@ void fiberstep_release();
 int dl_eval_surfaces(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
                      const double* src_q, const int32_t* src_sid, int64_t n_trg, const double* trg_xyz,
                      const int64_t* trg_self, double near_r, uint32_t flags, double* u_out, hipStream_t st);
+
+// The input scan of STOKES_CHECK_INPUTS for a single-layer sum's sources (synchronous on
+// st): forces and weights finite, fiber ids in [0, n_fib) and non-decreasing, lengths
+// finite.  E_NONFINITE or E_INVAL with `who` in the message; the workspace of st is used.
+int scan_sl_inputs(hipStream_t st, const char* who, int64_t n_s, const double* force, const double* weight,
+                   const int32_t* fib, int32_t n_fib, const double* flen);
+
+// Slot option (beside STOKES_NONLOCAL and STOKES_PRECOND_BLOCK): the slot's single-layer
+// sum is evaluated by the caller (a treecode) into partial row 0 instead of by k_sl.
+constexpr uint32_t OPT_FAR = 1u << 20;
+
+// Parameters of the solvers' treecode far field: degree 1..10, theta in (0, 1).
+inline int check_far(const stokes_far* far, const char* who) {
+    if (far && (far->degree < 1 || far->degree > 10 || !(far->theta > 0.0 && far->theta < 1.0)))
+        return fail(STOKES_E_INVAL, std::string(who) + ": stokes_far needs degree 1..10 and theta in (0, 1)");
+    return STOKES_OK;
+}
+
+// A treecode plan over fiber nodes (targets = sources) for the u_bar sums of the
+// solvers; destroyed with the object.
+struct FarPlan {
+    stokes_tree* t = nullptr;
+    FarPlan() = default;
+    FarPlan(const FarPlan&) = delete;
+    FarPlan& operator=(const FarPlan&) = delete;
+    ~FarPlan() {
+        if (t) (void)stokes_tree_destroy(t);
+    }
+    // Validates `far` and builds the plan (synchronous on st).
+    int make(int64_t n, const double* xyz, const stokes_far& far, hipStream_t st);
+};
 
 struct Tile;
 struct SrcDL64;
@@ -92,13 +135,14 @@ struct __align__(16) Tile {
     double ox, oy, oz;   // FP64 origin: centre of the bounding box
     double reach2;       // FP64 path: a target closer than sqrt(reach2) may coincide with a source
     float reach2_f;      // mixed path: a target closer than this may have a near pair
-                         // (double layer: or lie in the tile's tangent band)
     int32_t j0, j1;      // sources [j0, j1)
     float inv_l2;        // 1/|b|^2 of the capsule axis (0: the axis is a point)
     float ax, ay, az;    // capsule axis start, relative to the origin
     float bx, by, bz;    // capsule axis vector
-    float cap2_f;        // mixed path: (capsule radius + near radius [or band])^2, padded
+    float cap2_f;        // mixed path: (capsule radius + near radius)^2, padded
     float cap2_d;        // FP64 path: (capsule radius)^2, padded
+    float band2_f;       // mixed double layer: a target closer than this lies in the
+                         // tile's tangent band (dl_band_radius); 0 otherwise
 };
 
 // Single-layer source, premultiplied: s = w f / (8 pi mu), c = (eps L)^2/2, c3 = -3 c.

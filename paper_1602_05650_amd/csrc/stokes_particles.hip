@@ -276,6 +276,7 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
         return fail(STOKES_E_INVAL, "stokes_particle_solve: null pointer");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int n_surf = 1 + n_part;
+    Range range("stokes_particle_solve");
     const uint32_t sumflags = flags & STOKES_PREC_MIXED;
 
     // host tables

@@ -309,6 +309,7 @@ static void worker_main(stokes_session* s) {
             s->cv_done.notify_all();
         }
         // set-up of the newly admitted requests (the pipeline is empty; lock released)
+        Range range("stokes_session step");
         int rc = STOKES_OK;
         for (int q : admitted) {
             Request* r = slots[q];

@@ -255,8 +255,9 @@ __global__ __launch_bounds__(BLOCK) void k_pre(const SlotDesc* D, const StepTabl
         d.z[i] = fx;
         d.z[N + i] = fy;
         d.z[2 * N + i] = fz;
-        sl_src_prep_one(i, N, d.xyz, d.z, d.wq, d.fib, d.n_fib, d.flen, d.pref, d.eps, doublet,
-                        d.near_r, d.tiles, d.s64, d.s32, d.near_t);
+        if (!(d.opts & OPT_FAR))   // a far slot's sum is the treecode's
+            sl_src_prep_one(i, N, d.xyz, d.z, d.wq, d.fib, d.n_fib, d.flen, d.pref, d.eps, doublet,
+                            d.near_r, d.tiles, d.s64, d.s32, d.near_t);
     }
 }
 
@@ -620,9 +621,9 @@ int Batch::attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, doubl
     d.B = sp.B;
     d.n_items_vec = (int32_t)((n + BLOCK - 1) / BLOCK);
     d.n_items_node = (int32_t)((N + BLOCK - 1) / BLOCK);
-    d.n_items_sl = sp.P.n_tblocks * sp.P.n_chunks;
+    d.n_items_sl = sp.P.n_tblocks * ((opts & OPT_FAR) ? 1 : sp.P.n_chunks);   // far: k_red sums one row
     d.sid = s;
-    d.opts = opts & (STOKES_NONLOCAL | STOKES_PRECOND_BLOCK);
+    d.opts = opts & (STOKES_NONLOCAL | STOKES_PRECOND_BLOCK | OPT_FAR);
     d.delta = delta;
     d.eps = eps;
     d.mu = mu;
@@ -806,6 +807,26 @@ int Batch::launch_ortho(bool graph_sizes) {
     hipLaunchKernelGGL(k_scale, dim3(g(WL_VEC, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, (const double*)dev_stat_);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
+}
+
+int Batch::launch_pre(const std::vector<int>& slots) {
+    set_list(WL_PRE, slots);
+    if (int rc = upload()) return rc;
+    hipLaunchKernelGGL(k_pre, dim3(grid_for(host_tab_->wl[WL_PRE], G_ELEM)), dim3(BLOCK), 0, st_, dev_desc_,
+                       dev_tab_, doublet_ ? 1 : 0);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
+int Batch::launch_red_ortho(const std::vector<int>& slots) {
+    set_list(WL_RED, slots);
+    set_list(WL_DOT, slots);
+    set_list(WL_ONE, slots);
+    set_list(WL_VEC, slots);
+    if (int rc = upload()) return rc;
+    hipLaunchKernelGGL(k_red, dim3(grid_for(host_tab_->wl[WL_RED], G_ELEM)), dim3(BLOCK), 0, st_, dev_desc_,
+                       dev_tab_);
+    return launch_ortho(false);
 }
 
 int Batch::step(const std::vector<int>& slots) {
@@ -1010,9 +1031,11 @@ extern "C" int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const
                                      const double* tangent, const double* fiber_len,
                                      const double* rhs, double eps, double mu, double delta,
                                      int32_t iters, uint32_t flags, double* f_out,
-                                     double* resid_out, int32_t* iters_out, void* stream) {
+                                     double* resid_out, int32_t* iters_out, const stokes_far* far,
+                                     void* stream) {
     if (flags & ~(STOKES_PREC_MIXED | STOKES_NO_DOUBLET | STOKES_NONLOCAL | STOKES_PRECOND_BLOCK))
         return fail(STOKES_E_INVAL, "stokes_mobility_solve: unknown flag bits");
+    if (int rc = check_far(far, "stokes_mobility_solve")) return rc;
     if ((flags & STOKES_NONLOCAL) && (!(delta > 0.0) || !std::isfinite(delta)))
         return fail(STOKES_E_INVAL, "stokes_mobility_solve: delta must be finite and > 0 with STOKES_NONLOCAL");
     if (n_fib < 0 || nodes_per_fib < 2 || nodes_per_fib > 64)
@@ -1030,6 +1053,7 @@ extern "C" int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const
         if (iters_out) *iters_out = 0;
         return STOKES_OK;
     }
+    Range range("stokes_mobility_solve");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool mixed = flags & STOKES_PREC_MIXED;
     const uint32_t opts = flags & (STOKES_NONLOCAL | STOKES_PRECOND_BLOCK);
@@ -1037,19 +1061,27 @@ extern "C" int stokes_mobility_solve(int32_t n_fib, int32_t nodes_per_fib, const
     Workspace* ws = nullptr;
     int rc = workspace_get(st, sp.bytes, &ws);
     if (rc) return rc;
+    FarPlan fp;
+    if (far && (rc = fp.make(N, xyz, *far, st))) return rc;
     Batch b;
     if ((rc = b.init(st, mixed, !(flags & STOKES_NO_DOUBLET), false))) return rc;
-    if ((rc = b.attach(0, ws->dev, n_fib, nodes_per_fib, iters, eps, mu, 0.0, opts, delta, xyz,
-                       tangent, fiber_len, rhs)))
+    if ((rc = b.attach(0, ws->dev, n_fib, nodes_per_fib, iters, eps, mu, 0.0, far ? opts | OPT_FAR : opts, delta,
+                       xyz, tangent, fiber_len, rhs)))
         return rc;
     std::vector<int> one{0};
     if ((rc = b.start(one))) return rc;
+    // the treecode's u_bar: Clenshaw-Curtis weights x L/2 and the fiber ids of the slot
+    const uint32_t tflags = (flags & (STOKES_PREC_MIXED | STOKES_NO_DOUBLET)) | STOKES_EXCL_SAME_FIBER;
+    auto far_sum = [&](int q) {
+        const SlotDesc& d = b.desc(q);
+        return stokes_tree_sl_eval(fp.t, d.z, d.wq, d.fib, d.n_fib, d.flen, mu, eps, 0.0, tflags, d.partial, st);
+    };
     int done = 0;
     double resid = b.status(0)[2];
     if (b.status(0)[3] == 0.0) {
         for (int j = 0; j < iters; ++j) {
             b.desc(0).j = j;
-            if ((rc = b.step(one))) return rc;
+            if ((rc = far ? b.step_external(one, far_sum) : b.step(one))) return rc;
             done = j + 1;
             resid = b.status(0)[2];
             if (b.status(0)[3] != 0.0) break;   // exact breakdown

@@ -33,6 +33,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "stokes_internal.hpp"
 #include "sum_device.hpp"
@@ -41,27 +43,21 @@ namespace stokes {
 
 // ---- preparation kernels -------------------------------------------------------
 
-// Bounding sphere of each tile.  near_r_tile: extra reach for the mixed path
-// (largest near radius of the tile's sources); per-source near radius is
-// max(near_r, near_fac * L_fiber) when flen/sfib are given.
-__global__ void tile_prep_kernel(int64_t n_s, const double* __restrict__ sx, int32_t n_tiles,
-                                 double near_r, double near_fac, const int32_t* __restrict__ sfib,
-                                 int32_t n_fib, const double* __restrict__ flen, Tile* tiles) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n_tiles) tile_prep_one(t, n_s, sx, near_r, near_fac, sfib, n_fib, flen, tiles);
+// Bounding volumes of each tile, 32 lanes per tile (tile_prep_half).  near_r: extra
+// reach for the mixed path; the per-source near radius is max(near_r, near_fac *
+// L_fiber) when flen/sfib are given.  band < 0 (mixed double layer): each tile's
+// tangent band from the normals nrm.  Launch with TILE_PREP_BLOCK threads per block.
+constexpr int TILE_PREP_BLOCK = 256;
+__global__ __launch_bounds__(TILE_PREP_BLOCK) void tile_prep_kernel(
+        int64_t n_s, const double* __restrict__ sx, int32_t n_tiles, double near_r, double near_fac,
+        const int32_t* __restrict__ sfib, int32_t n_fib, const double* __restrict__ flen, Tile* tiles,
+        double band, const double* __restrict__ nrm) {
+    const int t = (blockIdx.x * TILE_PREP_BLOCK + threadIdx.x) / 32;
+    if (t < n_tiles)   // whole half-waves: n_tiles bounds them together
+        tile_prep_half(t, threadIdx.x & 31, n_s, sx, near_r, near_fac, sfib, n_fib, flen, tiles, band, nrm);
 }
-
-// Double-layer tiles of the mixed path: the reach covers the larger of the near
-// radius and the tile's tangent band (dl_band_radius), so that a target within the
-// band takes the checked loop, which forms d and d.n' in FP64.
-__global__ void dl_tile_prep_kernel(int64_t n_s, const double* __restrict__ sx,
-                                    const double* __restrict__ nrm, int32_t n_tiles, double near_r,
-                                    Tile* tiles) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tiles) return;
-    const int64_t j0 = (int64_t)t * TILE, j1 = std::min<int64_t>(j0 + TILE, n_s);
-    tile_prep_one(t, n_s, sx, fmax(near_r, dl_band_radius(j0, j1, n_s, sx, nrm)), 0.0, nullptr, 0,
-                  nullptr, tiles);
+static inline unsigned tile_prep_blocks(int64_t n_tiles) {
+    return (unsigned)((n_tiles * 32 + TILE_PREP_BLOCK - 1) / TILE_PREP_BLOCK);
 }
 
 __global__ void sl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
@@ -336,9 +332,10 @@ static int sl_core(const SLProblem& p, const Partition& P, const SumScratch& S, 
                    unsigned long long* counters, hipStream_t st) {
     if (P.n_chunks > 0) {
         const double pref = 1.0 / (8.0 * PI_D * p.mu);
-        hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, p.n_s,
-                           p.sxyz, P.n_tiles, p.mixed ? std::max(p.near_r, 0.0) : 0.0,
-                           p.mixed ? 2.0 * p.eps : 0.0, p.sfib, p.n_fib, p.flen, S.tiles);
+        hipLaunchKernelGGL(tile_prep_kernel, dim3(tile_prep_blocks(P.n_tiles)), dim3(TILE_PREP_BLOCK), 0, st,
+                           p.n_s, p.sxyz, P.n_tiles, p.mixed ? std::max(p.near_r, 0.0) : 0.0,
+                           p.mixed ? 2.0 * p.eps : 0.0, p.sfib, p.n_fib, p.flen, S.tiles, 0.0,
+                           (const double*)nullptr);
         hipLaunchKernelGGL(sl_src_prep_kernel, dim3(nblk(p.n_s)), dim3(256), 0, st, p.n_s, p.sxyz,
                            p.force, p.weight, p.sfib, p.n_fib, p.flen, pref, p.eps,
                            p.doublet ? 1 : 0, std::max(p.near_r, 0.0), S.tiles,
@@ -402,6 +399,25 @@ static int read_flag(Workspace* ws, int* flag, hipStream_t st, int* out) {
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
+int scan_sl_inputs(hipStream_t st, const char* who, int64_t n_s, const double* force, const double* weight,
+                   const int32_t* fib, int32_t n_fib, const double* flen) {
+    Workspace* ws = nullptr;
+    if (int rc = workspace_get(st, 256, &ws)) return rc;
+    int* flag = static_cast<int*>(ws->dev);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, flag);
+    Check c{flag, st};
+    c.finite(force, 3 * n_s);
+    c.finite(weight, n_s);
+    c.finite(flen, fib ? n_fib : 0);
+    c.fiber(fib, n_s, n_fib);
+    STOKES_HIP(hipGetLastError());
+    int f = 0;
+    if (int rc = read_flag(ws, flag, st, &f)) return rc;
+    if (f & 2) return fail(STOKES_E_INVAL, std::string(who) + ": fiber ids out of range or decreasing");
+    if (f & 1) return fail(STOKES_E_NONFINITE, std::string(who) + ": non-finite input");
+    return STOKES_OK;
+}
+
 static int finish_diag(Workspace* ws, unsigned long long* counters, hipStream_t st, int64_t n_t,
                        int64_t n_s, stokes_diag* diag) {
     STOKES_HIP(hipMemcpyAsync(ws->host, counters, 3 * sizeof(unsigned long long),
@@ -418,12 +434,12 @@ static int finish_diag(Workspace* ws, unsigned long long* counters, hipStream_t 
 
 using namespace stokes;
 
-extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double* src_force,
-                              const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
-                              const double* fiber_len, int64_t n_trg, const double* trg_xyz,
-                              const int64_t* trg_self, const int32_t* trg_fiber, double mu,
-                              double eps, double near_r, uint32_t flags, double* u_out,
-                              void* stream, stokes_diag* diag) {
+static int sl_run(int64_t n_src, const double* src_xyz, const double* src_force,
+                  const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
+                  const double* fiber_len, int64_t n_trg, const double* trg_xyz,
+                  const int64_t* trg_self, const int32_t* trg_fiber, double mu,
+                  double eps, double near_r, uint32_t flags, double* u_out,
+                  void* stream, stokes_diag* diag) {
     const uint32_t known = STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_EXCL_SAME_FIBER |
                            STOKES_NO_DOUBLET | STOKES_ACCUMULATE | STOKES_CHECK_INPUTS;
     if (flags & ~known) return fail(STOKES_E_INVAL, "stokes_sl_eval: unknown flag bits");
@@ -458,12 +474,16 @@ extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double
     const bool mixed = flags & STOKES_PREC_MIXED;
     const Partition P = make_partition(n_t, n_src, mixed ? R_SL32 : R_SL64);
     const int32_t nf = src_fiber ? n_fib : 0;
+    const size_t s32b = mixed ? sizeof(SrcSL32) : 0;
     Workspace* ws = nullptr;
-    int rc = workspace_get(st, sum_scratch_bytes(n_src, n_t, nf, sizeof(SrcSL64),
-                                                 mixed ? sizeof(SrcSL32) : 0, P.n_chunks), &ws);
-    if (rc) return rc;
-    const SumScratch S = carve_sum(ws->dev, n_src, n_t, nf, sizeof(SrcSL64),
-                                   mixed ? sizeof(SrcSL32) : 0, P.n_chunks);
+    void* base = nullptr;
+    int rc = STOKES_OK;
+    {
+        rc = workspace_get(st, sum_scratch_bytes(n_src, n_t, nf, sizeof(SrcSL64), s32b, P.n_chunks), &ws);
+        if (rc) return rc;
+        base = ws->dev;
+    }
+    const SumScratch S = carve_sum(base, n_src, n_t, nf, sizeof(SrcSL64), s32b, P.n_chunks);
     if (flags & STOKES_CHECK_INPUTS) {
         hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, S.flag);
         Check c{S.flag, st};
@@ -517,6 +537,16 @@ extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double
     if ((rc = sl_core(p, P, S, excl, counters, st))) return rc;
     if (diag) return finish_diag(ws, counters, st, n_t, n_src, diag);
     return STOKES_OK;
+}
+
+extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double* src_force,
+                              const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
+                              const double* fiber_len, int64_t n_trg, const double* trg_xyz,
+                              const int64_t* trg_self, const int32_t* trg_fiber, double mu,
+                              double eps, double near_r, uint32_t flags, double* u_out,
+                              void* stream, stokes_diag* diag) {
+    return sl_run(n_src, src_xyz, src_force, src_weight, src_fiber, n_fib, fiber_len, n_trg, trg_xyz, trg_self,
+                  trg_fiber, mu, eps, near_r, flags, u_out, stream, diag);
 }
 
 static void launch_dl_kernel(bool mixed, bool sub, bool multi, unsigned grid, const SumArgs& a,
@@ -594,13 +624,9 @@ static int dl_run(int64_t n_src, const double* src_xyz, const double* src_normal
     const double* tx = same ? src_xyz : trg_xyz;
     const int64_t ts = same ? n_src : n_t;
     if (P.n_chunks > 0) {
-        if (mixed)
-            hipLaunchKernelGGL(dl_tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, n_src,
-                               src_xyz, src_normal, P.n_tiles, nr, S.tiles);
-        else
-            hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P.n_tiles, 64)), dim3(64), 0, st, n_src,
-                               src_xyz, P.n_tiles, 0.0, 0.0, (const int32_t*)nullptr, 0,
-                               (const double*)nullptr, S.tiles);
+        hipLaunchKernelGGL(tile_prep_kernel, dim3(tile_prep_blocks(P.n_tiles)), dim3(TILE_PREP_BLOCK), 0, st,
+                           n_src, src_xyz, P.n_tiles, mixed ? nr : 0.0, 0.0, (const int32_t*)nullptr, 0,
+                           (const double*)nullptr, S.tiles, mixed ? -1.0 : 0.0, src_normal);
         hipLaunchKernelGGL(dl_src_prep_kernel, dim3(nblk(n_src)), dim3(256), 0, st, n_src, src_xyz,
                            src_normal, src_weight, src_q, src_sid, S.tiles, static_cast<SrcDL64*>(S.s64),
                            mixed ? static_cast<SrcDL32*>(S.s32) : nullptr);
@@ -697,12 +723,9 @@ int DLPlan::init(int64_t n_src, const double* src_xyz, const double* src_normal,
     partial_ = reinterpret_cast<double*>(b + L.partial);
     hipLaunchKernelGGL(excl_self_kernel, dim3(nblk(n_t_)), dim3(256), 0, st, n_t_, trg_self, 0, n_s_, excl_,
                        (unsigned long long*)nullptr);
-    if (mixed_)
-        hipLaunchKernelGGL(dl_tile_prep_kernel, dim3(nblk(P_.n_tiles, 64)), dim3(64), 0, st, n_s_, src_xyz,
-                           src_normal, P_.n_tiles, nr, tiles_);
-    else
-        hipLaunchKernelGGL(tile_prep_kernel, dim3(nblk(P_.n_tiles, 64)), dim3(64), 0, st, n_s_, src_xyz, P_.n_tiles,
-                           0.0, 0.0, (const int32_t*)nullptr, 0, (const double*)nullptr, tiles_);
+    hipLaunchKernelGGL(tile_prep_kernel, dim3(tile_prep_blocks(P_.n_tiles)), dim3(TILE_PREP_BLOCK), 0, st, n_s_,
+                       src_xyz, P_.n_tiles, mixed_ ? nr : 0.0, 0.0, (const int32_t*)nullptr, 0,
+                       (const double*)nullptr, tiles_, mixed_ ? -1.0 : 0.0, src_normal);
     // positions, weighted normals and surface ids now; the density per evaluation (a
     // zero density until then: the pack kernel reads q, so pass the normals as a stand-in
     // and overwrite them in every evaluation)

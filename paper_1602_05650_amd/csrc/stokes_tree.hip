@@ -162,15 +162,17 @@ struct DevCl {              // what the kernels need of a proxy cluster
 // Sorted source packs: s = pref * w * f, doublet coefficient c = (eps L)^2 / 2 and
 // the mixed path's near threshold t = max(near_r, 2 eps L)^2.
 __global__ __launch_bounds__(TB) void k_tr_src(int64_t ns, const int64_t* sperm, const double* f,
-                                               const double* w, const int32_t* fib, const double* flen,
-                                               double pref, double eps, double near_r, int doublet,
-                                               double* ss, double* sc, float* st, int32_t* sfid) {
+                                               const double* w, const int32_t* fib, int32_t n_fib,
+                                               const double* flen, double pref, double eps, double near_r,
+                                               int doublet, double* ss, double* sc, float* st, int32_t* sfid) {
     const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (j >= ns) return;
     const int64_t o = sperm[j];
     if (sfid) sfid[j] = fib[o];
     const double wj = w ? w[o] : 1.0;
-    const double L = (fib && flen) ? flen[fib[o]] : 1.0;
+    // an id outside [0, n_fib) reads no length (L = 1), as in the direct sums
+    const int32_t fo = fib ? fib[o] : -1;
+    const double L = (flen && fo >= 0 && fo < n_fib) ? flen[fo] : 1.0;
     const double a = eps * L;
     const double k = pref * wj;
     ss[j] = k * f[o];
@@ -1290,13 +1292,15 @@ static void launch_eval(bool mixed, int deg, unsigned grid, dim3 blk, hipStream_
 }
 
 extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, const double* src_weight,
-                                   const int32_t* src_fiber, const double* fiber_len, double mu,
-                                   double eps, double near_r, uint32_t flags, double* u_out,
+                                   const int32_t* src_fiber, int32_t n_fib, const double* fiber_len,
+                                   double mu, double eps, double near_r, uint32_t flags, double* u_out,
                                    void* stream) {
     if (!t) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: null tree");
     if (flags & ~(STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_EXCL_SAME_FIBER | STOKES_NO_DOUBLET |
-                  STOKES_ACCUMULATE))
+                  STOKES_ACCUMULATE | STOKES_CHECK_INPUTS))
         return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: unsupported flag bits");
+    if (src_fiber && n_fib < 1) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: src_fiber needs n_fib >= 1");
+    if (!std::isfinite(near_r)) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: near_r not finite");
     const bool exf = flags & STOKES_EXCL_SAME_FIBER;
     if (exf && (flags & STOKES_EXCL_SELF_POINT))
         return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: choose one exclusion mode");
@@ -1309,10 +1313,15 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
     if (!(mu > 0.0)) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: mu must be > 0");
     if (!(eps > 0.0 && eps < 0.5)) return fail(STOKES_E_INVAL, "stokes_tree_sl_eval: eps must be in (0, 0.5)");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (flags & STOKES_CHECK_INPUTS) {   // the direct sums' scan (synchronous)
+        if (int rc = scan_sl_inputs(st, "stokes_tree_sl_eval", t->ns, src_force, src_weight, src_fiber, n_fib,
+                                    fiber_len))
+            return rc;
+    }
     const bool mixed = flags & STOKES_PREC_MIXED;
     const double pref = 1.0 / (8.0 * 3.14159265358979323846 * mu);
     hipLaunchKernelGGL(k_tr_src, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, t->sperm,
-                       src_force, src_weight, src_fiber, fiber_len, pref, eps, near_r,
+                       src_force, src_weight, src_fiber, src_fiber ? n_fib : 0, fiber_len, pref, eps, near_r,
                        (flags & STOKES_NO_DOUBLET) ? 0 : 1, t->ss, t->sc, t->st, exf ? t->sfid : nullptr);
     if (exf)
         hipLaunchKernelGGL(k_tr_frange, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, src_fiber,
@@ -1421,6 +1430,15 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }
+
+namespace stokes {
+int FarPlan::make(int64_t n, const double* xyz, const stokes_far& far, hipStream_t st) {
+    if (far.degree < 1 || far.degree > tree::MAX_DEG || !(far.theta > 0.0 && far.theta < 1.0))
+        return fail(STOKES_E_INVAL, "stokes_far: degree must be 1..10 and theta in (0, 1)");
+    return stokes_tree_create(n, xyz, 0, nullptr, far.degree, far.theta, far.leaf_size > 0 ? far.leaf_size : 128,
+                              st, &t);
+}
+}  // namespace stokes
 
 extern "C" int stokes_tree_info(const stokes_tree* t, int64_t* proxy_pairs, int64_t* direct_pairs,
                                 int32_t* n_proxy_clusters, int32_t* n_batches) {

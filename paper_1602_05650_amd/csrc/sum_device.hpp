@@ -556,6 +556,9 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
     // source tile staged in LDS: every operand of the pair arithmetic is a VGPR
     // (gfx950 issues FP32 VALU ops with an SGPR operand at a lower rate)
     __shared__ float4 lds[3 * TILE];
+    // the tile's FP64 positions and weighted normals (x, y | z, - | n'x, n'y | n'z, -) for
+    // the loops that form d and d.n' in FP64; staged with the FP32 pack every tile
+    __shared__ double2 lds64[4 * TILE];
     // FP64 near-pair sums and counts of each thread: touched only on the rare checked
     // tiles, so they live in the thread's own LDS slots, not in loop-carried registers
     __shared__ double near_sum[3 * R][BLOCK];
@@ -602,7 +605,17 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
     near_cnt[0][tid] = near_cnt[1][tid] = 0u;   // at most the thread's targets x the chunk's sources
     const cptr<float4> src4 = as_const(static_cast<const float4*>(a.s32));
     const SrcDL64* __restrict__ src64 = static_cast<const SrcDL64*>(a.s64);
-    const cptr<SrcDL64> srcc64 = as_const(src64);
+    // double2 words 0, 1, 3, 4 of a 6-word SrcDL64: (x, y), (z, qx), (nx, ny), (nz, pad0)
+    const cptr<double2> src2 = as_const(static_cast<const double2*>(a.s64));
+    auto stage = [&](const Tile& T, int nsrc) {
+        const int th = threadIdx.x;
+        if (th < 3 * nsrc) lds[th] = src4[3 * (int64_t)T.j0 + th];
+        const int u = th - 128;
+        if (u >= 0 && u < 4 * nsrc) {
+            const int k = u >> 2, w = u & 3;
+            lds64[u] = src2[6 * ((int64_t)T.j0 + k) + (w < 2 ? w : w + 1)];
+        }
+    };
     const float tn = a.near_t_uniform;
     const int2 xu = wave_excl_union<R>(lo, hi);
     const int t0 = chunk * a.tiles_per_chunk;
@@ -610,8 +623,7 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
     if (!wave_active) {   // a wave past the targets still stages tiles and meets the barriers
         for (int t = t0; t < t1; ++t) {
             const Tile T = as_const(a.tiles)[t];
-            const int nsrc = T.j1 - T.j0;
-            if ((int)threadIdx.x < 3 * nsrc) lds[threadIdx.x] = src4[3 * (int64_t)T.j0 + threadIdx.x];
+            stage(T, T.j1 - T.j0);
             __syncthreads();
             __syncthreads();
         }
@@ -620,27 +632,58 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
         const int nsrc = T.j1 - T.j0;
-        if ((int)threadIdx.x < 3 * nsrc) lds[threadIdx.x] = src4[3 * (int64_t)T.j0 + threadIdx.x];
+        stage(T, nsrc);
         __syncthreads();
         float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
-        bool near_s = false;
+        bool near_s = false, band_s = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             xs[r] = (float)(X[r] - T.ox);
             ys[r] = (float)(Y[r] - T.oy);
             zs[r] = (float)(Z[r] - T.oz);
-            near_s |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
+            const float d2 = fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r]));
+            near_s |= d2 <= T.reach2_f;
+            band_s |= d2 <= T.band2_f;   // in the tile's tangent band
             px[r] = py[r] = pz[r] = 0.0f;
         }
         // wave-uniform: the union of the lanes' exclusion ranges overlaps the tile
         bool checked = (xu.x < T.j1) & (xu.y > T.j0);
-        if (__ballot(near_s) != 0) {   // refine the sphere test with the capsule
+        const bool band = __ballot(band_s) != 0;
+        if (!checked && __ballot(near_s) != 0) {   // refine the sphere test with the capsule
             bool near_c = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) near_c |= capsule_d2(T, xs[r], ys[r], zs[r]) <= T.cap2_f;
             checked |= __ballot(near_s & near_c) != 0;
         }
-        if (!checked) {
+        // FP64 d and d.n' (rounded once) for a pair of the tile, from the staged FP64 data.
+        // Used in the tangent band, where d is nearly tangent to the surface and
+        // d.n' ~ |d|^2 / (2 R_curv): from tile-local FP32 coordinates it would lose
+        // ~ eps32 2 R_curv / |d| of itself, the largest rounding error of the mixed sum.
+        auto d64 = [&](int k, int r, float& dx, float& dy, float& dz, float& dn) {
+            const double2 a0 = lds64[4 * k], a1 = lds64[4 * k + 1], a2 = lds64[4 * k + 2], a3 = lds64[4 * k + 3];
+            const double Dx = X[r] - a0.x, Dy = Y[r] - a0.y, Dz = Z[r] - a1.x;
+            dx = (float)Dx;
+            dy = (float)Dy;
+            dz = (float)Dz;
+            dn = (float)fma(Dx, a2.x, fma(Dy, a2.y, Dz * a3.x));
+        };
+        if (!checked && band) {   // no near or excluded pair: the band loop, without masks
+            auto bpair = [&](int k) {
+                const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
+                const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, MULTI ? p2.y : 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float dx, dy, dz, dn;
+                    d64(k, r, dx, dy, dz, dn);
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const bool own = !MULTI || s.pad0 == (float)tsid[r];
+                    dl_pair32_dn<SUB>(dx, dy, dz, dn, r2, __builtin_amdgcn_rsqf(r2), s, own ? fqx[r] : 0.f,
+                                      own ? fqy[r] : 0.f, own ? fqz[r] : 0.f, px[r], py[r], pz[r]);
+                }
+            };
+#pragma unroll 2
+            for (int k = 0; k < nsrc; ++k) bpair(k);
+        } else if (!checked) {
             auto far = [&](int k) {
                 const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
                 const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, MULTI ? p2.y : 0.f, 0.f, 0.f};
@@ -662,11 +705,7 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                 for (int k = 0; k < nsrc; ++k) far(k);
             }
         } else {
-            // Tiles within the tangent band of the target (dl_band_radius): d and d.n'
-            // are formed in FP64 and rounded once.  For a target on or near the surface,
-            // d is nearly tangent and d.n' ~ |d|^2 / (2 R_curv); its FP32 evaluation from
-            // tile-local coordinates loses ~ eps32 2 R_curv / |d| of it, the largest
-            // rounding error of the mixed sum.
+            // checked loop: d and d.n' in FP64 as in the band loop; near and excluded pairs masked
             uint32_t m[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) m[r] = 0u;
@@ -674,13 +713,11 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
                 const int j = T.j0 + k;
                 const float4 p0 = lds[3 * k], p1 = lds[3 * k + 1], p2 = lds[3 * k + 2];
                 const SrcDL32 s = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, MULTI ? p2.y : 0.f, 0.f, 0.f};
-                const SrcDL64 s8 = srcc64[j];   // wave-uniform: scalar loads
                 const uint32_t bit = 1u << k;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const double Dx = X[r] - s8.x, Dy = Y[r] - s8.y, Dz = Z[r] - s8.z;
-                    const float dx = (float)Dx, dy = (float)Dy, dz = (float)Dz;
-                    const float dn = (float)fma(Dx, s8.nx, fma(Dy, s8.ny, Dz * s8.nz));
+                    float dx, dy, dz, dn;
+                    d64(k, r, dx, dy, dz, dn);
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const bool bad = (r2 < tn) | in_range(j, lo[r], hi[r]);
                     m[r] |= bad ? bit : 0u;
@@ -748,7 +785,8 @@ __device__ __forceinline__ void dl_mixed_wave(const SumArgs& a, int tb, int chun
 __device__ __forceinline__ void tile_prep_one(int t, int64_t n_s, const double* __restrict__ sx,
                                               double near_r, double near_fac,
                                               const int32_t* __restrict__ sfib, int32_t n_fib,
-                                              const double* __restrict__ flen, Tile* tiles) {
+                                              const double* __restrict__ flen, Tile* tiles,
+                                              double band = 0.0) {
     const int j0 = t * TILE;
     const int j1 = (int)min((int64_t)j0 + TILE, n_s);
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -811,7 +849,94 @@ __device__ __forceinline__ void tile_prep_one(int t, int64_t n_s, const double* 
     T.bz = (float)b[2];
     T.cap2_f = (float)(cm * cm) * (1.0f + 1e-6f);
     T.cap2_d = (float)(cd * cd) * (1.0f + 1e-6f);
+    const double bm = (rad + band) * (1.0 + 1e-5) + 1e-30;
+    T.band2_f = band > 0.0 ? (float)(bm * bm) * (1.0f + 1e-6f) : 0.0f;
     tiles[t] = T;
+}
+
+// Reductions over the 32 lanes of a half-wave (xor butterflies stay inside it).
+__device__ __forceinline__ double half_min(double v) {
+    for (int off = 16; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 32));
+    return v;
+}
+__device__ __forceinline__ double half_max(double v) {
+    for (int off = 16; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 32));
+    return v;
+}
+
+// tile_prep_one by the 32 lanes of a half-wave, lane l taking source t * TILE + l: the
+// same Tile (every quantity is a per-source expression of tile_prep_one followed by a
+// min or max, which do not depend on the order), in five butterflies instead of three
+// passes over the sources by one thread.  band < 0: the double layer's tangent band,
+// dl_band_radius of the tile's sources with normals nrm.  Call with whole half-waves.
+__device__ __forceinline__ void tile_prep_half(int t, int l, int64_t n_s, const double* __restrict__ sx,
+                                               double near_r, double near_fac,
+                                               const int32_t* __restrict__ sfib, int32_t n_fib,
+                                               const double* __restrict__ flen, Tile* tiles, double band,
+                                               const double* __restrict__ nrm) {
+    const int j0 = t * TILE;
+    const int j1 = (int)min((int64_t)j0 + TILE, n_s);
+    const int m = j1 - j0;
+    const bool act = l < m;
+    const int j = act ? j0 + l : j0;
+    const double x = sx[j], y = sx[n_s + j], z = sx[2 * n_s + j];
+    double lo[3], hi[3];
+    lo[0] = half_min(act ? x : INFINITY);
+    lo[1] = half_min(act ? y : INFINITY);
+    lo[2] = half_min(act ? z : INFINITY);
+    hi[0] = half_max(act ? x : -INFINITY);
+    hi[1] = half_max(act ? y : -INFINITY);
+    hi[2] = half_max(act ? z : -INFINITY);
+    double nr = near_r;
+    if (near_fac > 0.0) {
+        double L = 1.0;
+        if (flen) {
+            int f = sfib ? sfib[j] : 0;
+            if (f >= 0 && f < (sfib ? n_fib : 1)) L = flen[f];
+        }
+        nr = fmax(nr, half_max(act ? near_fac * L : -INFINITY));
+    }
+    Tile T;
+    T.ox = 0.5 * (lo[0] + hi[0]);
+    T.oy = 0.5 * (lo[1] + hi[1]);
+    T.oz = 0.5 * (lo[2] + hi[2]);
+    {
+        const double dx = x - T.ox, dy = y - T.oy, dz = z - T.oz;
+        const double rad2 = half_max(act ? dx * dx + dy * dy + dz * dz : 0.0);
+        const double rad = sqrt(rad2);
+        const double r64 = rad * (1.0 + 1e-9) + 1e-300;
+        T.reach2 = r64 * r64;
+        const double rm = (rad + nr) * (1.0 + 1e-5) + 1e-30;
+        T.reach2_f = (float)(rm * rm) * (1.0f + 1e-6f);
+        // capsule: axis from the first to the last source (lanes 0 and m - 1)
+        const double x0 = __shfl(x, 0, 32), y0 = __shfl(y, 0, 32), z0 = __shfl(z, 0, 32);
+        const double xe = __shfl(x, m - 1, 32), ye = __shfl(y, m - 1, 32), ze = __shfl(z, m - 1, 32);
+        const double a[3] = {x0 - T.ox, y0 - T.oy, z0 - T.oz};
+        const double b[3] = {xe - x0, ye - y0, ze - z0};
+        const double l2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+        const double q[3] = {x - T.ox - a[0], y - T.oy - a[1], z - T.oz - a[2]};
+        double u = l2 > 0.0 ? (q[0] * b[0] + q[1] * b[1] + q[2] * b[2]) / l2 : 0.0;
+        u = fmin(fmax(u, 0.0), 1.0);
+        const double d[3] = {q[0] - u * b[0], q[1] - u * b[1], q[2] - u * b[2]};
+        const double crad2 = half_max(act ? d[0] * d[0] + d[1] * d[1] + d[2] * d[2] : 0.0);
+        const double margin = 1e-5 * (rad + 1.0);
+        const double cm = sqrt(crad2) + nr + margin, cd = sqrt(crad2) + margin;
+        T.inv_l2 = l2 > 0.0 ? (float)(1.0 / l2) : 0.0f;
+        T.ax = (float)a[0];
+        T.ay = (float)a[1];
+        T.az = (float)a[2];
+        T.bx = (float)b[0];
+        T.by = (float)b[1];
+        T.bz = (float)b[2];
+        T.cap2_f = (float)(cm * cm) * (1.0f + 1e-6f);
+        T.cap2_d = (float)(cd * cd) * (1.0f + 1e-6f);
+        if (band < 0.0) band = dl_band_radius_half(l, j0, j1, n_s, sx, nrm);
+        const double bm = (rad + band) * (1.0 + 1e-5) + 1e-30;
+        T.band2_f = band > 0.0 ? (float)(bm * bm) * (1.0f + 1e-6f) : 0.0f;
+    }
+    T.j0 = j0;
+    T.j1 = j1;
+    if (l == 0) tiles[t] = T;
 }
 
 __device__ __forceinline__ void sl_src_prep_one(int64_t j, int64_t n_s, const double* __restrict__ sx,

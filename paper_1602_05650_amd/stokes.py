@@ -56,6 +56,20 @@ class SolveReq(ctypes.Structure):
                 ("tag", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("delta", ctypes.c_double)]
 
 
+class Far(ctypes.Structure):
+    """stokes_far: the treecode's parameters for the u_bar sums of the solvers."""
+    _fields_ = [("degree", ctypes.c_int32), ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int32)]
+
+
+def _far(far):
+    """None, or (degree, theta[, leaf_size]) -> a Far by reference."""
+    if far is None:
+        return None
+    deg, theta = far[0], far[1]
+    leaf = far[2] if len(far) > 2 else 0
+    return ctypes.byref(Far(int(deg), float(theta), int(leaf)))
+
+
 class SolveStats(ctypes.Structure):
     _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
                 ("t_finish_ns", ctypes.c_int64), ("iters", ctypes.c_int32),
@@ -74,16 +88,16 @@ def _load():
         "stokes_sl_eval": [I64, P, P, P, P, I32, P, I64, P, P, P, D, D, D, U32, P, P, P],
         "stokes_dl_eval": [I64, P, P, P, P, I64, P, P, D, U32, P, P, P],
         "stokes_local_sbt": [I64, P, P, D, D, ctypes.c_int, P, P],
-        "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, D, I32, U32, P, P, P, P],
+        "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, D, I32, U32, P, P, P, P, P],
         "stokes_nonlocal_sbt": [I32, I32, P, P, P, P, D, D, P, P],
         "stokes_tree_create": [I64, P, I64, P, I32, D, I32, P, P],
-        "stokes_tree_sl_eval": [P, P, P, P, P, D, D, D, U32, P, P],
+        "stokes_tree_sl_eval": [P, P, P, P, I32, P, D, D, D, U32, P, P],
         "stokes_tree_dl_eval": [P, P, P, P, D, U32, P, P],
         "stokes_tree_info": [P, P, P, P, P],
         "stokes_tree_destroy": [P],
         "stokes_particle_solve": [I64, P, P, P, I32, P, P, P, P, P, P, P, D, D, I32, U32, P, P, P,
                                   P, P, P],
-        "stokes_fiber_step": [I32, I32, P, P, P, P, D, D, D, D, D, D, I32, D, U32, P, P, P, P, P],
+        "stokes_fiber_step": [I32, I32, P, P, P, P, D, D, D, D, D, D, I32, D, U32, P, P, P, P, P, P],
         "stokes_session_create": [P, P],
         "stokes_session_submit": [P, P, P],
         "stokes_session_wait": [P, ctypes.c_uint64, P, P, I32],
@@ -257,10 +271,11 @@ def nonlocal_sbt(xyz, tangent, fiber_len, f, nodes_per_fib, delta, mu=1.0, out=N
 
 
 def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1.0, mixed=False,
-                   doublet=True, delta=None, precond="local", stream=None):
+                   doublet=True, delta=None, precond="local", far=None, stream=None):
     """GMRES mobility solve on device tensors; returns (f, residual, iterations).
     delta given: the operator includes the nonlocal self term K_delta; precond "block"
-    uses each fiber's inverted self block instead of the local 3x3 blocks."""
+    uses each fiber's inverted self block instead of the local 3x3 blocks; far =
+    (degree, theta[, leaf_size]): the other fibers' flow through a treecode plan."""
     xyz = _dev(xyz, torch.float64, "xyz")
     n = xyz.shape[1]
     _dev(tangent, torch.float64, "tangent", (3, n))
@@ -275,7 +290,7 @@ def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1
     _check(_lib.stokes_mobility_solve(n_fib, nodes_per_fib, _ptr(xyz), _ptr(tangent),
                                       _ptr(fiber_len), _ptr(rhs), float(eps), float(mu), dl,
                                       int(iters), flags, _ptr(out), ctypes.byref(res),
-                                      ctypes.byref(it), _stream(stream)))
+                                      ctypes.byref(it), _far(far), _stream(stream)))
     return out, res.value, it.value
 
 
@@ -328,12 +343,13 @@ def particle_solve(particles, force, torque, periphery=None, mu=1.0, iters=40, m
 
 
 def fiber_step(xyz, fiber_len, f_ext, nodes_per_fib, eps, E, dt, mu=1.0, delta=None, iters=40,
-               tol=0.0, mixed=False, doublet=True, near_r=0.0, clamp=None, stream=None):
+               tol=0.0, mixed=False, doublet=True, near_r=0.0, clamp=None, far=None, stream=None):
     """One implicit (backward Euler) step of elastic fibers (stokes_fiber_step) on device
     tensors: xyz, f_ext (3, N), fiber_len (n_fib,).  delta given: the nonlocal self term
     K_delta is included.  clamp: (n_fib,) minus-end conditions at a body at rest
-    (any array; 0 or False free, 1 or True clamped, 2 hinged).  Returns (X+ (3, N), T+ (N,), residual,
-    iterations)."""
+    (any array; 0 or False free, 1 or True clamped, 2 hinged).  far = (degree, theta[,
+    leaf_size]): the other fibers' flow through a treecode plan of the step's nodes.
+    Returns (X+ (3, N), T+ (N,), residual, iterations)."""
     xyz = _dev(xyz, torch.float64, "xyz")
     n = xyz.shape[1]
     _dev(fiber_len, torch.float64, "fiber_len")
@@ -361,7 +377,7 @@ def fiber_step(xyz, fiber_len, f_ext, nodes_per_fib, eps, E, dt, mu=1.0, delta=N
                                   None if cl is None else _ptr(cl), float(eps), float(E), float(dt), float(mu),
                                   float(delta) if delta is not None else 0.0, float(near_r), int(iters),
                                   float(tol), flags, _ptr(out), _ptr(T), ctypes.byref(res),
-                                  ctypes.byref(it), _stream(stream)))
+                                  ctypes.byref(it), _far(far), _stream(stream)))
     return out, T, res.value, it.value
 
 
@@ -383,9 +399,10 @@ class Tree:
 
     def sl_eval(self, force, src_fiber=None, fiber_len=None, src_weight=None, mu=1.0, eps=0.01,
                 near_r=0.0, excl_self=True, mixed=False, doublet=True, out=None, accumulate=False,
-                stream=None, excl_fiber=False):
+                stream=None, excl_fiber=False, check_inputs=False):
         """excl_fiber: skip every source of the target's fiber (plans with targets = sources;
-        needs src_fiber) instead of only the target's own point."""
+        needs src_fiber) instead of only the target's own point.  check_inputs: the input
+        scan of sl_eval (synchronous)."""
         _dev(force, torch.float64, "force", (3, self.n_src))
         if src_fiber is not None:
             _dev(src_fiber, torch.int32, "src_fiber", (self.n_src,))
@@ -396,9 +413,11 @@ class Tree:
             out = torch.zeros((3, self.n_trg), dtype=torch.float64, device=force.device)
         excl = EXCL_SAME_FIBER if excl_fiber else (EXCL_SELF_POINT if excl_self else 0)
         flags = ((PREC_MIXED if mixed else PREC_FP64) | excl
-                 | (0 if doublet else NO_DOUBLET) | (ACCUMULATE if accumulate else 0))
+                 | (0 if doublet else NO_DOUBLET) | (ACCUMULATE if accumulate else 0)
+                 | (CHECK_INPUTS if check_inputs else 0))
         nz = lambda t: None if t is None else _ptr(t)
-        _check(_lib.stokes_tree_sl_eval(self._h, _ptr(force), nz(src_weight), nz(src_fiber),
+        n_fib = 0 if fiber_len is None else fiber_len.shape[0]
+        _check(_lib.stokes_tree_sl_eval(self._h, _ptr(force), nz(src_weight), nz(src_fiber), n_fib,
                                         nz(fiber_len), float(mu), float(eps), float(near_r), flags,
                                         _ptr(out), _stream(stream)))
         return out

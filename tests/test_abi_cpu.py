@@ -65,15 +65,23 @@ def test_status_strings_and_validation_without_gpu():
     assert L.stokes_local_sbt(0, None, None, 0.01, 1.0, 0, None, None) == S.OK
     assert L.stokes_local_sbt(3, None, None, 0.01, 1.0, 0, None, None) == S.E_INVAL
     assert L.stokes_mobility_solve(1, 1, None, None, None, None, 0.01, 1.0, 0.0, 5, 0, None,
-                                   None, None, None) == S.E_INVAL
+                                   None, None, None, None) == S.E_INVAL
     assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0.0, 0, 0, None,
-                                   None, None, None) == S.E_INVAL
+                                   None, None, None, None) == S.E_INVAL
     # the nonlocal term needs delta > 0; unknown flag bits are refused
     assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0.0, 5, S.NONLOCAL,
-                                   None, None, None, None) == S.E_INVAL
+                                   None, None, None, None, None) == S.E_INVAL
     assert "delta" in S.last_error()
     assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0.0, 5, 1 << 12,
-                                   None, None, None, None) == S.E_INVAL
+                                   None, None, None, None, None) == S.E_INVAL
+    # treecode far field: degree 1..10, theta in (0, 1), checked before any device work
+    for deg, th in ((0, 0.5), (11, 0.5), (6, 0.0), (6, 1.0)):
+        far = ctypes.byref(S.Far(deg, th, 0))
+        assert L.stokes_mobility_solve(1, 8, None, None, None, None, 0.01, 1.0, 0.0, 5, 0,
+                                       None, None, None, far, None) == S.E_INVAL
+        assert "stokes_far" in S.last_error()
+        assert L.stokes_fiber_step(0, 16, None, None, None, None, 0.01, 1.0, 1e-3, 1.0, 0.0, 0.0, 10,
+                                   0.0, 0, None, None, None, None, far, None) == S.E_INVAL
     assert L.stokes_nonlocal_sbt(0, 8, None, None, None, None, 0.01, 1.0, None, None) == S.OK
     assert L.stokes_nonlocal_sbt(2, 8, None, None, None, None, 0.0, 1.0, None, None) == S.E_INVAL
     assert L.stokes_nonlocal_sbt(2, 65, None, None, None, None, 0.01, 1.0, None, None) == S.E_INVAL
@@ -96,7 +104,7 @@ def test_status_strings_and_validation_without_gpu():
     assert L.stokes_tree_create(10, ctypes.c_void_p(8), 0, None, 6, 1.5, 128, None,
                                 ctypes.byref(h)) == S.E_INVAL
     assert "theta" in S.last_error()
-    assert L.stokes_tree_sl_eval(None, None, None, None, None, 1.0, 0.01, 0.0, 0, None,
+    assert L.stokes_tree_sl_eval(None, None, None, None, 0, None, 1.0, 0.01, 0.0, 0, None,
                                  None) == S.E_INVAL
     assert L.stokes_tree_dl_eval(None, None, None, None, 0.0, 0, None, None) == S.E_INVAL
     assert L.stokes_tree_destroy(None) == S.E_INVAL
@@ -130,7 +138,7 @@ def test_fiber_step_validation_without_gpu():
              ptrs=None):
         p = ptrs if ptrs is not None else [None] * 5
         return L.stokes_fiber_step(n_fib, npf, p[0], p[1], p[2], None, eps, E, dt, mu, delta, 0.0, iters,
-                                   tol, flags, p[3], p[4], None, None, None)
+                                   tol, flags, p[3], p[4], None, None, None, None)
 
     assert call() == S.OK                                   # no fibers: nothing to do
     for kw in ({"npf": 5}, {"npf": 49}, {"n_fib": -1}, {"eps": 0.6}, {"E": -1.0}, {"dt": 0.0},

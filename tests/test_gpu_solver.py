@@ -307,3 +307,38 @@ def test_session_timeout(S):
         assert ei.value.code == SS.E_TIMEOUT
         f, st = s.wait(t)
         assert st["status"] == 0 and np.all(np.isfinite(f))
+
+
+@pytest.mark.parametrize("far,mixed,tol", [((8, 0.5), False, 1e-7), ((6, 0.7), True, 2e-5)])
+def test_mobility_solve_treecode_far_field_vs_oracle(S, oracle_mod, far, mixed, tol):
+    """The other fibers' flow through a treecode plan (the paper's fast summation per
+    GMRES matvec) against the oracle's direct FP64 solve: the tree's error on the sum,
+    carried through the solve."""
+    req = W.serving_request(9, 4000, n_fib=400, nodes=16, iters=25)
+    fs = req["fibers"]
+    ref, hist, m = _oracle_solve(oracle_mod, req)
+    args = (dev(fs.xyz), dev(fs.tangent), dev(fs.length), dev(req["rhs"]), fs.nodes_per_fiber, fs.eps,
+            25)
+    f_dir, _, _ = S.mobility_solve(*args, mixed=mixed)
+    f_far, res, it = S.mobility_solve(*args, mixed=mixed, far=far)
+    e_far, e_dir = rel(f_far.cpu().numpy(), ref), rel(f_dir.cpu().numpy(), ref)
+    print(f"treecode far field {far} mixed={mixed}: solve vs oracle {e_far:.3e} (direct {e_dir:.3e}), "
+          f"{it} iterations")
+    assert it == m
+    assert e_far <= tol
+    assert e_far > 0.0      # the far field really went through the tree (not bitwise the direct sum)
+
+
+def test_fiber_step_treecode_far_field(S, oracle_mod):
+    """One implicit step with the other fibers' flow through a treecode plan against the
+    same step with direct sums (degree 8, theta 0.5: the tree's sum error is ~1e-9)."""
+    c = W.config_step(n_fib=300, nodes=16, R=4.0)
+    fs = c["fibers"]
+    a = (dev(fs.xyz), dev(fs.length), dev(c["f_ext"]), fs.nodes_per_fiber, c["eps"], c["E"], c["dt"])
+    X0, T0, r0, i0 = S.fiber_step(*a, iters=40, tol=1e-10)
+    X1, T1, r1, i1 = S.fiber_step(*a, iters=40, tol=1e-10, far=(8, 0.5))
+    x = fs.xyz
+    dX0, dX1 = X0.cpu().numpy() - x, X1.cpu().numpy() - x
+    e = np.abs(dX1 - dX0).max() / np.abs(dX0).max()
+    print(f"fiber step, treecode far field vs direct: dX {e:.3e}, iterations {i0} / {i1}")
+    assert e <= 1e-6
