@@ -131,6 +131,30 @@ int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double* src_force
                    double* u_out, void* stream, stokes_diag* diag);
 
 /*
+ * stokes_sl_eval_noalloc -- stokes_sl_eval for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same sum, arguments and layouts, on the same stream rules, but its
+ * scratch (tiles, source packs, exclusion ranges, chunk partials) is a static array
+ * of 64 MiB per GPU in the library's device code, held until the process ends, and
+ * the call allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *   - The caller passes every input and the output, as for stokes_sl_eval.
+ *   - No diagnostics argument; STOKES_CHECK_INPUTS is rejected (E_INVAL).
+ *   - A problem whose scratch does not fit 64 MiB even with one source chunk is
+ *     rejected with E_INVAL (about 5e5 sources and targets together); larger ones
+ *     fit with fewer source chunks than stokes_sl_eval takes, so the reduction order
+ *     and the last bits of the result can differ from it (within the precision's bound).
+ *   - Every call on one GPU uses that GPU's one array and it keeps the last call's
+ *     contents: calls that overlap on one GPU (other streams or threads) race.
+ */
+int stokes_sl_eval_noalloc(int64_t n_src, const double* src_xyz, const double* src_force,
+                           const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
+                           const double* fiber_len,
+                           int64_t n_trg, const double* trg_xyz, const int64_t* trg_self,
+                           const int32_t* trg_fiber,
+                           double mu, double eps, double near_r, uint32_t flags,
+                           double* u_out, void* stream);
+
+/*
  * stokes_dl_eval -- double-layer (stresslet) sum over surface quadrature points.
  *
  *   u_i = (3/(4 pi)) sum_{s != self(i)} w_s (d . qt_s)(d . n_s) d / |d|^5,   d = x_i - y_s

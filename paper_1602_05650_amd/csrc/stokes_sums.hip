@@ -434,14 +434,45 @@ static int finish_diag(Workspace* ws, unsigned long long* counters, hipStream_t 
 
 using namespace stokes;
 
+// Scratch of the entry point that allocates nothing (stokes_sl_eval_noalloc): one
+// array per GPU, in the library's device code object, held until the process ends.
+// Host code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is not a device address on the host).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device, resolved once per device.
+static int noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static void* addr[64] = {};
+    int dev = 0;
+    STOKES_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(STOKES_E_INVAL, "stokes_sl_eval_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(STOKES_E_DEVICE, "stokes_sl_eval_noalloc: no device address for the scratch array");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return STOKES_OK;
+}
+
+// fixed: the call's scratch is `fixed` (fixed_cap bytes) instead of the library's
+// workspace, and nothing is allocated; the partition then takes fewer source chunks
+// when the standard one's partials do not fit (the reduction order, and so the last
+// bits of the result, follow the partition).
 static int sl_run(int64_t n_src, const double* src_xyz, const double* src_force,
                   const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
                   const double* fiber_len, int64_t n_trg, const double* trg_xyz,
                   const int64_t* trg_self, const int32_t* trg_fiber, double mu,
                   double eps, double near_r, uint32_t flags, double* u_out,
-                  void* stream, stokes_diag* diag) {
-    const uint32_t known = STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_EXCL_SAME_FIBER |
-                           STOKES_NO_DOUBLET | STOKES_ACCUMULATE | STOKES_CHECK_INPUTS;
+                  void* stream, stokes_diag* diag, bool noalloc) {
+    uint32_t known = STOKES_PREC_MIXED | STOKES_EXCL_SELF_POINT | STOKES_EXCL_SAME_FIBER |
+                     STOKES_NO_DOUBLET | STOKES_ACCUMULATE | STOKES_CHECK_INPUTS;
+    if (noalloc) known &= ~(uint32_t)STOKES_CHECK_INPUTS;   // its read-back needs a host buffer
     if (flags & ~known) return fail(STOKES_E_INVAL, "stokes_sl_eval: unknown flag bits");
     const bool self_mode = flags & STOKES_EXCL_SELF_POINT;
     const bool fiber_mode = flags & STOKES_EXCL_SAME_FIBER;
@@ -472,13 +503,39 @@ static int sl_run(int64_t n_src, const double* src_xyz, const double* src_force,
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool mixed = flags & STOKES_PREC_MIXED;
-    const Partition P = make_partition(n_t, n_src, mixed ? R_SL32 : R_SL64);
+    Partition P = make_partition(n_t, n_src, mixed ? R_SL32 : R_SL64);
     const int32_t nf = src_fiber ? n_fib : 0;
     const size_t s32b = mixed ? sizeof(SrcSL32) : 0;
     Workspace* ws = nullptr;
     void* base = nullptr;
     int rc = STOKES_OK;
-    {
+    if (noalloc) {
+        // the most source chunks (up to the standard partition's) whose partials fit
+        auto bytes = [&](const Partition& Q) {
+            return sum_scratch_bytes(n_src, n_t, nf, sizeof(SrcSL64), s32b, Q.n_chunks);
+        };
+        if (bytes(P) > NOALLOC_SCRATCH_BYTES) {
+            int64_t lo = P.n_tblocks, hi = (int64_t)P.n_tblocks * std::max(P.n_chunks, 1);
+            Partition best = make_partition(n_t, n_src, P.R, lo);
+            if (bytes(best) > NOALLOC_SCRATCH_BYTES)
+                return fail(STOKES_E_INVAL, "stokes_sl_eval_noalloc: " + std::to_string(n_src) + " sources and " +
+                                                std::to_string(n_t) + " targets need more than the " +
+                                                std::to_string(NOALLOC_SCRATCH_BYTES >> 20) +
+                                                " MiB static scratch");
+            while (lo < hi) {   // largest target_blocks that still fits
+                const int64_t mid = lo + (hi - lo + 1) / 2;
+                const Partition Q = make_partition(n_t, n_src, P.R, mid);
+                if (bytes(Q) <= NOALLOC_SCRATCH_BYTES) {
+                    lo = mid;
+                    best = Q;
+                } else {
+                    hi = mid - 1;
+                }
+            }
+            P = best;
+        }
+        if ((rc = noalloc_scratch(&base))) return rc;
+    } else {
         rc = workspace_get(st, sum_scratch_bytes(n_src, n_t, nf, sizeof(SrcSL64), s32b, P.n_chunks), &ws);
         if (rc) return rc;
         base = ws->dev;
@@ -546,7 +603,17 @@ extern "C" int stokes_sl_eval(int64_t n_src, const double* src_xyz, const double
                               double eps, double near_r, uint32_t flags, double* u_out,
                               void* stream, stokes_diag* diag) {
     return sl_run(n_src, src_xyz, src_force, src_weight, src_fiber, n_fib, fiber_len, n_trg, trg_xyz, trg_self,
-                  trg_fiber, mu, eps, near_r, flags, u_out, stream, diag);
+                  trg_fiber, mu, eps, near_r, flags, u_out, stream, diag, false);
+}
+
+extern "C" int stokes_sl_eval_noalloc(int64_t n_src, const double* src_xyz, const double* src_force,
+                                      const double* src_weight, const int32_t* src_fiber, int32_t n_fib,
+                                      const double* fiber_len, int64_t n_trg, const double* trg_xyz,
+                                      const int64_t* trg_self, const int32_t* trg_fiber, double mu,
+                                      double eps, double near_r, uint32_t flags, double* u_out,
+                                      void* stream) {
+    return sl_run(n_src, src_xyz, src_force, src_weight, src_fiber, n_fib, fiber_len, n_trg, trg_xyz, trg_self,
+                  trg_fiber, mu, eps, near_r, flags, u_out, stream, nullptr, true);
 }
 
 static void launch_dl_kernel(bool mixed, bool sub, bool multi, unsigned grid, const SumArgs& a,

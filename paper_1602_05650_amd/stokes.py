@@ -86,6 +86,7 @@ def _load():
                            ctypes.c_double)
     sig = {
         "stokes_sl_eval": [I64, P, P, P, P, I32, P, I64, P, P, P, D, D, D, U32, P, P, P],
+        "stokes_sl_eval_noalloc": [I64, P, P, P, P, I32, P, I64, P, P, P, D, D, D, U32, P, P],
         "stokes_dl_eval": [I64, P, P, P, P, I64, P, P, D, U32, P, P, P],
         "stokes_local_sbt": [I64, P, P, D, D, ctypes.c_int, P, P],
         "stokes_mobility_solve": [I32, I32, P, P, P, P, D, D, D, I32, U32, P, P, P, P, P],
@@ -203,6 +204,47 @@ def sl_eval(src_xyz, src_force, *, src_weight=None, src_fiber=None, fiber_len=No
                              ctypes.byref(d) if d is not None else None)
     _check(rc)
     return (out, d) if diag else out
+
+
+def sl_eval_noalloc(src_xyz, src_force, *, src_weight=None, src_fiber=None, fiber_len=None,
+                    n_fib=None, trg_xyz=None, trg_self=None, trg_fiber=None, mu=1.0, eps=0.01,
+                    near_r=0.0, mixed=False, excl="self", doublet=True, accumulate=False, out=None,
+                    stream=None):
+    """sl_eval through the entry point that allocates nothing (the library's static
+    per-GPU scratch; no diagnostics, no input scan).  `out` (3, n_trg) float64 on the
+    device is allocated here when not given, as for sl_eval."""
+    src_xyz = _dev(src_xyz, torch.float64, "src_xyz")
+    ns = src_xyz.shape[1]
+    _dev(src_force, torch.float64, "src_force", (3, ns))
+    _dev(src_weight, torch.float64, "src_weight", (ns,))
+    _dev(src_fiber, torch.int32, "src_fiber", (ns,))
+    _dev(fiber_len, torch.float64, "fiber_len")
+    _dev(trg_xyz, torch.float64, "trg_xyz")
+    nt = ns if trg_xyz is None else trg_xyz.shape[1]
+    _dev(trg_self, torch.int64, "trg_self", (nt,))
+    _dev(trg_fiber, torch.int32, "trg_fiber", (nt,))
+    if out is None:
+        out = (torch.zeros if accumulate else torch.empty)((3, nt), dtype=torch.float64,
+                                                           device=src_xyz.device)
+    _dev(out, torch.float64, "out", (3, nt))
+    if nt == 0:
+        return out
+    flags = PREC_MIXED if mixed else PREC_FP64
+    flags |= {"self": EXCL_SELF_POINT, "fiber": EXCL_SAME_FIBER, None: 0, "none": 0}[excl]
+    flags |= 0 if doublet else NO_DOUBLET
+    flags |= ACCUMULATE if accumulate else 0
+    if src_fiber is None:
+        n_fib = 0
+    elif fiber_len is not None:
+        n_fib = fiber_len.shape[0]
+    elif n_fib is None:
+        raise ValueError("src_fiber given: pass fiber_len or n_fib")
+    rc = _lib.stokes_sl_eval_noalloc(ns, _ptr(src_xyz), _ptr(src_force), _ptr(src_weight),
+                                     _ptr(src_fiber), n_fib, _ptr(fiber_len), nt, _ptr(trg_xyz),
+                                     _ptr(trg_self), _ptr(trg_fiber), float(mu), float(eps),
+                                     float(near_r), flags, _ptr(out), _stream(stream))
+    _check(rc)
+    return out
 
 
 def dl_eval(src_xyz, src_normal, src_weight, src_q, *, trg_xyz=None, trg_self=None,

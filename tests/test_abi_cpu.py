@@ -82,6 +82,12 @@ def test_status_strings_and_validation_without_gpu():
         assert "stokes_far" in S.last_error()
         assert L.stokes_fiber_step(0, 16, None, None, None, None, 0.01, 1.0, 1e-3, 1.0, 0.0, 0.0, 10,
                                    0.0, 0, None, None, None, None, far, None) == S.E_INVAL
+    # the entry point that allocates nothing: no input scan, and the size limit
+    assert L.stokes_sl_eval_noalloc(0, None, None, None, None, 0, None, 0, ctypes.c_void_p(8), None, None,
+                                    1.0, 0.01, 0.0, 0, None, None) == S.OK
+    assert L.stokes_sl_eval_noalloc(2, ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, 0, None, 0,
+                                    None, None, None, 1.0, 0.01, 0.0, S.CHECK_INPUTS, ctypes.c_void_p(8),
+                                    None) == S.E_INVAL
     assert L.stokes_nonlocal_sbt(0, 8, None, None, None, None, 0.01, 1.0, None, None) == S.OK
     assert L.stokes_nonlocal_sbt(2, 8, None, None, None, None, 0.0, 1.0, None, None) == S.E_INVAL
     assert L.stokes_nonlocal_sbt(2, 65, None, None, None, None, 0.01, 1.0, None, None) == S.E_INVAL
