@@ -39,15 +39,17 @@ NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go 
 # 256 MiB (FETCH x 1.99977, WRITE x 0.99998); see
 # profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
 # sources with this digest: after any change the field reports null.
-TRAFFIC = {"digest": "913c7827881be904", "bytes": 540421761}
+TRAFFIC = {"digest": "0d3dafbe9a89fb1d", "bytes": 542510427}
 # VALU flops per pair from rocprofv3 instruction counters of the same kernel sources
 # (64 x (2 FMA + MUL + ADD + TRANS) of the kernel's precision, per dispatch, over the
 # pairs of one launch); see profiles/sl_spindle_262k_valu_counters.md.  Combined with
 # the live kernel time they give the counter-based fraction of peak.
-VALU_FLOPS_PER_PAIR = {"digest": "913c7827881be904", "mixed": 34.70, "fp64": 42.25}
+VALU_FLOPS_PER_PAIR = {"digest": "0d3dafbe9a89fb1d", "mixed": 34.70, "fp64": 42.25}
 KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
                   "paper_1602_05650_amd/csrc/stokes_sums.hip",
-                  "paper_1602_05650_amd/csrc/stokes_internal.hpp"]
+                  "paper_1602_05650_amd/csrc/stokes_internal.hpp",
+                  "paper_1602_05650_amd/csrc/host_logic.hpp",
+                  "paper_1602_05650_amd/csrc/pair_math.hpp"]
 
 
 def kernel_digest():
@@ -172,8 +174,15 @@ def config_run(S, torch, name, steps, warmup, log_fn):
         tag = "mixed" if mixed else "fp64"
         res[tag] = {}
         for which in pairs:
-            for _ in range(warmup):
+            # warm up for at least 0.25 s of this sum (the clock ramps up after the host
+            # has generated the workload), then time `steps` calls
+            tw = time.perf_counter()
+            k = 0
+            while k < warmup or time.perf_counter() - tw < 0.25:
                 run_sum(which, mixed)
+                k += 1
+                if k % 8 == 0:
+                    torch.cuda.synchronize()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):
@@ -219,7 +228,9 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
         ts = [submit(sess, r) for r in cal]
         for t in ts:
             sess.wait(t)
-        cap = len(cal) / (time.perf_counter() - t0)
+        t_cal = time.perf_counter() - t0
+        cap = len(cal) / t_cal
+        cal_pairs = sum(r["iters"] * r["fibers"].n * (r["fibers"].n - r["fibers"].nodes_per_fiber) for r in cal)
         rate = rate if rate > 0 else 0.7 * cap
         arrivals = W.serving_stream(3, n_req, rate)
         log_fn(f"serving ({'mixed' if mixed else 'fp64'}): capacity {cap:.1f} req/s (calibration), "
@@ -250,6 +261,7 @@ def serving_run(S, n_req, log_fn, step_pairs=0, mixed=True, rate=0.0):
     lat = np.array(lat)
     return {
         "requests": n_req, "rate_req_per_s": round(rate, 2), "capacity_req_per_s": round(cap, 2),
+        "capacity_gpair_per_s": round(cal_pairs / t_cal / 1e9, 1),
         "p50_ms": round(float(np.percentile(lat, 50)), 2),
         "p99_ms": round(float(np.percentile(lat, 99)), 2),
         "mean_ms": round(float(lat.mean()), 2),
