@@ -81,6 +81,8 @@ extern "C" {
 #define STOKES_ONSURF_RAW      64u   /* double layer: no singularity subtraction on the surface */
 #define STOKES_NONLOCAL       128u   /* mobility solve: include the nonlocal self term K_delta */
 #define STOKES_PRECOND_BLOCK  256u   /* mobility solve: fiber block-Jacobi preconditioner */
+#define STOKES_EAGER          512u   /* particle solve: launch each iteration's kernels one by one
+                                        instead of replaying a captured HIP graph (same result) */
 
 /* Optional counters filled by the *_eval calls (passing one makes the call synchronous). */
 typedef struct stokes_diag {
@@ -346,7 +348,9 @@ int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
  * centers, force, torque   [3*n_part] (SoA: x of every particle, then y, then z):
  *                    X_p, F_p, L_p.
  * mu > 0; near_r: mixed double-layer sums only (see stokes_dl_eval);
- * iters 1..STOKES_MAX_ITERS; flags: STOKES_PREC_* for the double-layer sums.
+ * iters 1..STOKES_MAX_ITERS; flags: STOKES_PREC_* for the double-layer sums;
+ * STOKES_EAGER launches each iteration's kernels one by one instead of replaying the
+ * iteration captured once into a HIP graph (the default; the results are the same).
  * U_out, Omega_out   [3*n_part] translational and angular velocities (SoA).
  * q_out              NULL or [3*(m0+Mp)] densities (periphery points first).
  * resid_out, iters_out   NULL or host: final least-squares residual, iterations.

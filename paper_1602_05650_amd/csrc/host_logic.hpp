@@ -28,6 +28,7 @@ constexpr int64_t TARGET_BLOCKS = 65536;
 // (less partial-sum memory per request).
 constexpr int64_t TARGET_BLOCKS_SLOT = 4096;
 constexpr int MIN_TILES_PER_CHUNK = 8;
+constexpr int64_t SMALL_GRID = 4096;
 
 // Bump allocator over a workspace buffer (256-byte aligned slices).
 struct Carve {
@@ -73,6 +74,10 @@ inline Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_
         p.n_chunks = 0;
         return p;
     }
+    // few target blocks (a small problem): aim at SMALL_GRID workgroups, enough to fill
+    // the chip, rather than target_blocks, which would cut the sources into one-tile
+    // chunks and write a partial row per tile
+    if (p.n_tblocks < 64) target_blocks = std::min<int64_t>(target_blocks, SMALL_GRID);
     int64_t ch = (target_blocks + p.n_tblocks - 1) / p.n_tblocks;
     // few target blocks (a small, latency-bound problem): shorter chunks
     const int64_t min_tiles = p.n_tblocks >= 64 ? MIN_TILES_PER_CHUNK : min_tiles_small;

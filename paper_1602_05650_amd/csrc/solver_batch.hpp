@@ -164,6 +164,15 @@ public:
     int step_ortho(const std::vector<int>& slots);
     // step_ortho without reading the status rows back (see copy_status_async).
     int step_ortho_nowait(const std::vector<int>& slots);
+    // For an iteration captured once into a HIP graph and replayed: ortho_lists sets and
+    // uploads the Gram-Schmidt work lists of `slots` (fixed afterwards);
+    // launch_ortho_fixed enqueues Gram-Schmidt, Givens and v_{j+1} on those lists on
+    // stream s (the capturing stream), then advances each slot's iteration counter j on
+    // the device, so a replay needs no upload.  dev_desc() is the device descriptor table (kernels of the caller read
+    // the iteration's v_j through it).
+    int ortho_lists(const std::vector<int>& slots);
+    int launch_ortho_fixed(const std::vector<int>& slots, hipStream_t s);
+    const SlotDesc* dev_desc() const { return dev_desc_; }
     // y from the least-squares problem and w = V_m y (iterations done in desc.j);
     // the caller forms x = P^{-1} w.
     int finalize_vector(const std::vector<int>& slots);

@@ -110,7 +110,8 @@ public:
     int init(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
              const int32_t* src_sid, int64_t n_trg, const double* trg_xyz, const int64_t* trg_self,
              double near_r, uint32_t flags, hipStream_t st);
-    int eval(const double* src_q, double* u_out, bool accumulate, hipStream_t st);
+    // in_capture: the launch is being captured into a graph (no profiling events)
+    int eval(const double* src_q, double* u_out, bool accumulate, hipStream_t st, bool in_capture = false);
 
 private:
     void* mem_ = nullptr;

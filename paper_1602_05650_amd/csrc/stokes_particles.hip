@@ -135,6 +135,14 @@ __global__ __launch_bounds__(PB) void k_pt_scale(int64_t n3, const double* v, co
     if (e < n3) out[e] = v[e] / d[e];
 }
 
+// z = v_j / diag with v_j = V + j n3 of the slot, j read from the device descriptor
+// (the iteration of a replayed graph advances it on the device).
+__global__ __launch_bounds__(PB) void k_pt_scale_vj(int64_t n3, const SlotDesc* D, int slot, const double* d,
+                                                    double* out) {
+    const int64_t e = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (e < n3) out[e] = D[slot].V[(int64_t)D[slot].j * n3 + e] / d[e];
+}
+
 // Surface part of the unknown vector into per-surface SoA blocks (the sources of the
 // double-layer sums).
 __global__ __launch_bounds__(PB) void k_pt_gather(Surfaces S, int64_t ms, int64_t ntot, const double* z,
@@ -246,6 +254,19 @@ struct DevBuf {
     }
 };
 
+// A captured graph, its executable and the stream it was captured on, destroyed with
+// the object.
+struct GraphGuard {
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphGuard() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 }  // namespace pt
 }  // namespace stokes
 
@@ -259,7 +280,9 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
                                      double near_r, int32_t iters, uint32_t flags, double* U_out,
                                      double* Omega_out, double* q_out, double* resid_out,
                                      int32_t* iters_out, void* stream) {
-    if (flags & ~STOKES_PREC_MIXED) return fail(STOKES_E_INVAL, "stokes_particle_solve: unknown flag bits");
+    if (flags & ~(STOKES_PREC_MIXED | STOKES_EAGER))
+        return fail(STOKES_E_INVAL, "stokes_particle_solve: unknown flag bits");
+    const bool graph = !(flags & STOKES_EAGER);
     if (m0 < 0 || n_part < 1 || !part_offset)
         return fail(STOKES_E_INVAL, "stokes_particle_solve: need m0 >= 0, n_part >= 1 and part_offset");
     if (iters < 1 || iters > STOKES_MAX_ITERS) return fail(STOKES_E_INVAL, "stokes_particle_solve: iters out of range");
@@ -377,24 +400,29 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     }
     if (int rc = planP.init(mp, yp, np_, wp, d_sid + m0, ms, T, d_selfp, near_r, sumflags, st)) return rc;
 
-    // w = A P^{-1} v: z = v / diag, then the operator
-    auto apply = [&](const double* v, double* z, double* w) -> int {
-        hipLaunchKernelGGL(k_pt_scale, dim3(grid1(n3)), dim3(PB), 0, st, n3, v, (const double*)diag, z);
-        hipLaunchKernelGGL(k_pt_gather, dim3(grid1(ms)), dim3(PB), 0, st, S, ms, ntot, (const double*)z, qb, m0,
+    // w = A P^{-1} v on stream s: z = v / diag (v given, or v_j of slot 0 read on the
+    // device when v is null: the captured iteration), then the operator
+    Batch b;
+    auto apply = [&](const double* v, double* z, double* w, hipStream_t s) -> int {
+        if (v)
+            hipLaunchKernelGGL(k_pt_scale, dim3(grid1(n3)), dim3(PB), 0, s, n3, v, (const double*)diag, z);
+        else
+            hipLaunchKernelGGL(k_pt_scale_vj, dim3(grid1(n3)), dim3(PB), 0, s, n3, b.dev_desc(), 0,
+                               (const double*)diag, z);
+        hipLaunchKernelGGL(k_pt_gather, dim3(grid1(ms)), dim3(PB), 0, s, S, ms, ntot, (const double*)z, qb, m0,
                            qp);
         int rc = STOKES_OK;
-        if (m0 > 0 && (rc = plan0.eval(qb, D0, false, st))) return rc;
-        if ((rc = planP.eval(qp, DP, false, st))) return rc;
-        hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, st, S, (const double*)qb, centers, n_part,
+        if (m0 > 0 && (rc = plan0.eval(qb, D0, false, s, v == nullptr))) return rc;
+        if ((rc = planP.eval(qp, DP, false, s, v == nullptr))) return rc;
+        hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, s, S, (const double*)qb, centers, n_part,
                            1, red);
-        hipLaunchKernelGGL(k_pt_assemble, dim3(grid1(ntot)), dim3(PB), 0, st, S, ms, ntot, n_part,
+        hipLaunchKernelGGL(k_pt_assemble, dim3(grid1(ntot)), dim3(PB), 0, s, S, ms, ntot, n_part,
                            (const double*)z, (const double*)D0, (const double*)DP, (const double*)red,
                            (const double*)area, centers, w);
         STOKES_HIP(hipGetLastError());
         return STOKES_OK;
     };
 
-    Batch b;
     int rc = b.init(st, false, true, false);
     if (rc) return rc;
     if ((rc = b.attach_vector(0, slot, ntot, iters, rhs))) return rc;
@@ -402,6 +430,27 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     if ((rc = b.start_vector(one))) return rc;
     int done = 0;
     double resid = b.status(0)[2];
+    // The iteration -- operator and Gram-Schmidt, about twenty small kernels -- is
+    // captured once into a HIP graph and replayed (no memset nodes; v_j and the
+    // iteration counter are read on the device), so the host launches one graph per
+    // iteration instead of twenty kernels whose launch gaps exceeded their run time.
+    // The capture runs on a stream of its own (the caller's may be the null stream, which
+    // cannot capture); it only records, and the graph is replayed on the caller's stream.
+    GraphGuard gg;
+    if (graph && b.status(0)[3] == 0.0) {
+        b.desc(0).j = 0;
+        if ((rc = b.ortho_lists(one))) return rc;
+        STOKES_HIP(hipStreamCreateWithFlags(&gg.cap, hipStreamNonBlocking));   // (default priority)
+        STOKES_HIP(hipStreamBeginCapture(gg.cap, hipStreamCaptureModeThreadLocal));
+        rc = apply(nullptr, b.desc(0).z, b.desc(0).w, gg.cap);
+        if (!rc) rc = b.launch_ortho_fixed(one, gg.cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(gg.cap, &gr);
+        gg.graph = gr;
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        STOKES_HIP(hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0));
+    }
     if (b.status(0)[3] == 0.0) {
         // The host does not wait for each iteration: iteration j is enqueued before the
         // status of iteration j - 1 is read (two pinned status rows, one event each).  An
@@ -423,10 +472,15 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
         bool broke = false;
         for (int j = 0; j <= iters && !broke; ++j) {
             if (j < iters) {
-                SlotDesc& d = b.desc(0);
-                d.j = j;
-                if (!rc) rc = apply(d.V + (int64_t)j * n3, d.z, d.w);
-                if (!rc) rc = b.step_ortho_nowait(one);
+                if (graph) {   // the replay computes iteration j (its counter is on the device)
+                    const hipError_t ge = hipGraphLaunch(gg.exec, st);
+                    if (ge != hipSuccess) rc = hip_fail(ge, "hipGraphLaunch");
+                } else {
+                    SlotDesc& d = b.desc(0);
+                    d.j = j;
+                    if (!rc) rc = apply(d.V + (int64_t)j * n3, d.z, d.w, st);
+                    if (!rc) rc = b.step_ortho_nowait(one);
+                }
                 if (!rc) rc = b.copy_status_async(hst + (j & 1) * NSTAT * MAX_SLOTS);
                 if (!rc) {
                     e = hipEventRecord(ev[j & 1], st);

@@ -981,6 +981,33 @@ int Batch::step_ortho_nowait(const std::vector<int>& slots) {
     return launch_ortho(false);
 }
 
+// j += 1 for the listed slots (one thread): the next replay of a captured iteration
+// computes the next Krylov vector.
+__global__ void k_advance(SlotDesc* D, const StepTables* T) {
+    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        for (int q = 0; q < wl->n; ++q) D[wl->slot[q]].j += 1;
+}
+
+int Batch::ortho_lists(const std::vector<int>& slots) {
+    set_list(WL_DOT, slots);
+    set_list(WL_ONE, slots);
+    set_list(WL_VEC, slots);
+    return upload();
+}
+
+int Batch::launch_ortho_fixed(const std::vector<int>& slots, hipStream_t s) {
+    if (slots.empty()) return STOKES_OK;
+    const hipStream_t own = st_;
+    st_ = s;
+    const int rc = launch_ortho(false);
+    st_ = own;
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, dev_desc_, dev_tab_);
+    STOKES_HIP(hipGetLastError());
+    return STOKES_OK;
+}
+
 int Batch::finalize_vector(const std::vector<int>& slots) {
     if (slots.empty()) return STOKES_OK;
     set_list(WL_PRE, slots);

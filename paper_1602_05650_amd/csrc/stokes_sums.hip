@@ -802,7 +802,7 @@ int DLPlan::init(int64_t n_src, const double* src_xyz, const double* src_normal,
     return STOKES_OK;
 }
 
-int DLPlan::eval(const double* src_q, double* u_out, bool accumulate, hipStream_t st) {
+int DLPlan::eval(const double* src_q, double* u_out, bool accumulate, hipStream_t st, bool in_capture) {
     if (!mem_) return fail(STOKES_E_INVAL, "DLPlan::eval: no plan");
     if (!src_q || !u_out) return fail(STOKES_E_INVAL, "DLPlan::eval: null pointer");
     hipLaunchKernelGGL(dl_q_pack_kernel, dim3(nblk(n_s_)), dim3(256), 0, st, n_s_, src_q, s64_, s32_);
@@ -824,9 +824,9 @@ int DLPlan::eval(const double* src_q, double* u_out, bool accumulate, hipStream_
     a.counters = nullptr;
     const unsigned grid = (unsigned)P_.grid();
     if (int rc = check_grid(P_, grid, n_t_)) return rc;
-    prof_begin(st);
+    if (!in_capture) prof_begin(st);
     launch_dl_kernel(mixed_, sub_, multi_, grid, a, st);
-    prof_end(st);
+    if (!in_capture) prof_end(st);
     hipLaunchKernelGGL(reduce_kernel, dim3(red_blocks(n_t_)), dim3(RED_T * RED_S), 0, st, n_t_, P_.n_chunks,
                        (const double*)partial_, accumulate ? 1 : 0, u_out, n_t_, (const int2*)excl_,
                        sub_ ? src_q : (const double*)nullptr, n_s_, -0.5, mixed_ ? 1 : 0);

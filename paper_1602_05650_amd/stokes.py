@@ -28,6 +28,7 @@ CHECK_INPUTS = 32
 ONSURF_RAW = 64
 NONLOCAL = 128
 PRECOND_BLOCK = 256
+EAGER = 512
 MAX_ITERS = 128
 
 
@@ -337,13 +338,14 @@ def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1
 
 
 def particle_solve(particles, force, torque, periphery=None, mu=1.0, iters=40, mixed=False,
-                   near_r=0.0, stream=None):
+                   near_r=0.0, eager=False, stream=None):
     """Mobility of rigid particles in a fixed periphery (second-kind boundary integrals).
 
     particles: list of (xyz (3, M), outward normals (3, M), weights (M,), centre (3,));
     periphery: (xyz, outward normals, weights) or None for an unbounded fluid;
     force, torque: (3, n_particles).  Arrays may be numpy or torch (copied to the
-    device).  Returns (U (3, n_p), Omega (3, n_p), q (3, M_s) device tensors,
+    device).  eager: launch each iteration's kernels one by one instead of replaying a
+    captured graph.  Returns (U (3, n_p), Omega (3, n_p), q (3, M_s) device tensors,
     residual, iterations)."""
     import numpy as np
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -378,7 +380,8 @@ def particle_solve(particles, force, torque, periphery=None, mu=1.0, iters=40, m
     nz = lambda t: None if t is None else _ptr(t)
     _check(_lib.stokes_particle_solve(m0, nz(y0), nz(n0), nz(w0), n_p, offs, _ptr(yp), _ptr(npn),
                                       _ptr(wp), _ptr(X), _ptr(F), _ptr(L), float(mu), float(near_r),
-                                      int(iters), PREC_MIXED if mixed else PREC_FP64, _ptr(U),
+                                      int(iters), (PREC_MIXED if mixed else PREC_FP64) | (EAGER if eager else 0),
+                                      _ptr(U),
                                       _ptr(Om), _ptr(q), ctypes.byref(res), ctypes.byref(it),
                                       _stream(stream)))
     return U, Om, q, res.value, it.value

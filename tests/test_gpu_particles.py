@@ -123,3 +123,25 @@ def test_ragged_particles_share_tiles(S, oracle_mod, mixed):
     assert rel(U.cpu().numpy(), Ur) <= tol
     assert rel(Om.cpu().numpy(), Omr) <= tol
     assert rel(q.cpu().numpy(), xr[:, : sysm.Ms]) <= 10 * tol
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_graph_replays_equal_eager_launches(S, mixed):
+    """The iteration replayed from a captured graph (the default) against the same
+    kernels launched one by one: bitwise the same solution, residual and iteration
+    count; the eager solve runs between two graph solves (eager work and
+    synchronisations between replays of separate graphs)."""
+    rng = np.random.default_rng(12)
+    per = sphere(16, 32, 3.0)
+    Xs = [np.array([0.9, 0.1, -0.2]), np.array([-1.0, 0.6, 0.5]), np.array([0.0, -1.1, 1.0])]
+    parts = [(*sphere(8, 16, r, X), X) for r, X in zip((0.45, 0.4, 0.5), Xs)]
+    F, L = rng.standard_normal((3, 3)), rng.standard_normal((3, 3))
+    out = []
+    for eager in (False, True, False):
+        U, Om, q, res, it = S.particle_solve(parts, F, L, periphery=per, mu=MU, iters=20, mixed=mixed,
+                                             eager=eager)
+        out.append((U.cpu().numpy(), Om.cpu().numpy(), q.cpu().numpy(), res, it))
+    for k in (0, 2):
+        for a, b in zip(out[k][:3], out[1][:3]):
+            assert np.array_equal(a, b)
+        assert out[k][3] == out[1][3] and out[k][4] == out[1][4] == 20
