@@ -354,10 +354,11 @@ def nonlocal_run(S, torch, log_fn, n_fib=2048, nodes=64, iters=20, delta=0.01):
     return res
 
 
-def particles_run(S, torch, log_fn, iters=30):
+def particles_run(S, torch, log_fn, iters=30, reps=5):
     """Confined rigid spheres (second-kind boundary integrals): the concentric-sphere
     drag and torque against their closed forms, and a confined suspension of spheres
-    timed per solve."""
+    timed per whole solve (set-up, iterations, solution; median of `reps` solves on
+    device-resident inputs)."""
     import math
     from paper_1602_05650_amd import workloads as W
     mu = 1.0
@@ -393,20 +394,28 @@ def particles_run(S, torch, log_fn, iters=30):
     L = rng.standard_normal((3, 16))
     ms = 6144 + 16 * 512
     pairs = ms * ms - ms          # double-layer pairs per operator application
+    # the geometry, forces and torques resident on the device before the timed solves
+    geom = S.ParticleGeometry(parts, per)
+    Fd = torch.from_numpy(F).cuda()
+    Ld = torch.from_numpy(L).cuda()
     for mixed in (False, True):
-        S.particle_solve(parts, F, L, periphery=per, mu=mu, iters=2, mixed=mixed)
+        S.particle_solve(geom, Fd, Ld, mu=mu, iters=2, mixed=mixed)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        U, Om, q, r, it = S.particle_solve(parts, F, L, periphery=per, mu=mu, iters=iters,
-                                           mixed=mixed)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            U, Om, q, r, it = S.particle_solve(geom, Fd, Ld, mu=mu, iters=iters, mixed=mixed)
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - t0)
+        dt = float(np.median(dts))
         res["suspension_" + ("mixed" if mixed else "fp64")] = {
             "points": f"periphery 6144 (R = 5) + 16 spheres x 512 (a = 0.5) = {ms}",
-            "ms": round(dt * 1e3, 2), "iterations": it, "ms_per_iteration": round(dt * 1e3 / it, 3),
+            "ms": round(dt * 1e3, 2), "ms_min": round(min(dts) * 1e3, 2), "solves": reps,
+            "iterations": it, "ms_per_iteration": round(dt * 1e3 / it, 3),
             "residual": float(f"{r:.3e}"),
             "dl_gpair_per_s": round(pairs * it / dt / 1e9, 1)}
-        log_fn(f"particles {('mixed' if mixed else 'fp64')}: {dt * 1e3:.1f} ms, {it} iterations")
+        log_fn(f"particles {('mixed' if mixed else 'fp64')}: {dt * 1e3:.1f} ms (median of {reps}), "
+               f"{it} iterations")
     return res
 
 

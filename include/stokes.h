@@ -502,7 +502,9 @@ int stokes_profile_read(double* ms, int64_t* launches);
 /* ---- misc --------------------------------------------------------------- */
 const char* stokes_status_string(int status);
 const char* stokes_last_error(void);
-/* Free every scratch workspace of the calling process (waits for the device). */
+/* Free every scratch workspace of the calling process (waits for the device), and the
+ * pinned tables and events that finished solves leave for the next solve on their
+ * device.  Not to be called while another thread's call into the library runs. */
 int stokes_release_workspace(void);
 /* Library version: major*10000 + minor*100 + patch. */
 int stokes_version(void);

@@ -28,7 +28,7 @@ constexpr int64_t TARGET_BLOCKS = 65536;
 // (less partial-sum memory per request).
 constexpr int64_t TARGET_BLOCKS_SLOT = 4096;
 constexpr int MIN_TILES_PER_CHUNK = 8;
-constexpr int64_t SMALL_GRID = 4096;
+constexpr int64_t SMALL_GRID = 8192;
 
 // Bump allocator over a workspace buffer (256-byte aligned slices).
 struct Carve {

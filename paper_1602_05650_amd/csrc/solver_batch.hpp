@@ -105,6 +105,13 @@ SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed, uint32_t o
 // Bytes of a generic-vector slot (attach_vector).
 size_t vector_plan_bytes(int64_t n_vec, int32_t k);
 
+// The fixed-size resources of a Batch: pinned host tables, the upload ring, two lagged
+// status rows, events and the device tables.  Made once and kept per device in a free
+// list (batch_res_acquire / batch_res_release): a later Batch takes them back instead
+// of making some twenty pinned allocations again.
+struct BatchRes;
+constexpr int UPLOAD_RING = 8;   // pinned table snapshots of a Batch's upload ring
+
 class Batch {
 public:
     Batch() = default;
@@ -147,9 +154,10 @@ public:
     }
     // step_parts without reading the status rows back: the step is only enqueued.
     // copy_status_async then enqueues the copy of the status rows into `dst` (pinned
-    // host memory of MAX_SLOTS * NSTAT doubles), valid once the stream reaches it.
+    // host memory of MAX_SLOTS * NSTAT doubles), valid once the stream reaches it; on
+    // stream s (a capturing stream), or on the Batch's stream when s is null.
     int step_parts_nowait(const std::vector<Part>& parts);
-    int copy_status_async(double* dst);
+    int copy_status_async(double* dst, hipStream_t s = nullptr);
     // Solutions of the listed slots into their x buffers (iterations done in desc.j).
     int finalize(const std::vector<int>& slots);
 
@@ -177,6 +185,10 @@ public:
     // the caller forms x = P^{-1} w.
     int finalize_vector(const std::vector<int>& slots);
     const double* status(int s) const { return host_stat_ + NSTAT * s; }
+    // Two pinned status rows ([MAX_SLOTS * NSTAT] each) and an event per row, for a
+    // caller that reads the status of iteration j - 1 while iteration j runs.
+    double* lag_row(int k);
+    hipEvent_t lag_event(int k);
     SlotDesc& desc(int s) { return host_desc_[s]; }
     hipStream_t stream() const { return st_; }
     bool mixed() const { return mixed_; }
@@ -184,7 +196,7 @@ public:
 private:
     int upload();
     int launch_step(bool capture);
-    int launch_ortho(bool capture);
+    int launch_ortho(bool capture, bool advance = false);
     void set_list(WL w, const std::vector<int>& slots);
     void set_sl_list(const std::vector<Part>& parts);
     int run_step();
@@ -204,7 +216,7 @@ private:
     // Uploads go through a ring of pinned snapshots of the tables, so the host may
     // change its tables for the next step while a copy of the last ones is in flight;
     // a stage is reused once the event recorded after its copy has completed.
-    static constexpr int NSTAGE = 8;
+    static constexpr int NSTAGE = UPLOAD_RING;
     struct Stage {
         SlotDesc* desc = nullptr;
         StepTables* tab = nullptr;
@@ -217,6 +229,7 @@ private:
     double* dev_stat_ = nullptr;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t exec_ = nullptr;
+    BatchRes* res_ = nullptr;
 };
 
 }  // namespace stokes

@@ -52,6 +52,9 @@ struct Workspace {
 int workspace_get(hipStream_t stream, size_t bytes, Workspace** out);
 // Frees the implicit time step's cached device buffers (stokes_release_workspace).
 void fiberstep_release();
+// Frees the pinned tables, events and device tables that finished batched solves keep
+// for the next one (stokes_release_workspace).
+void batch_res_drain();
 // Double layer over several surfaces in one sum: src_sid gives each source's surface;
 // a target's own density is subtracted only from its own surface's sources (the
 // surface of its self source).  Always with the on-surface subtraction.

@@ -129,46 +129,104 @@ __global__ __launch_bounds__(64) void k_pt_diag(Surfaces S, int64_t ms, int64_t 
     }
 }
 
+// The solve's geometry from the caller's arrays, one thread per surface point i: points
+// T and normals NS as planes of M_s (periphery first, then the particles in order), the
+// per-surface blocks bx, bn of Surfaces, the weights bw, surface ids sid (0 the
+// periphery, 1 + p particle p) and self indices (i).  po = part_offset (strictly
+// increasing: every particle has at least four points).
+__global__ __launch_bounds__(PB) void k_pt_geometry(int64_t m0, const double* y0, const double* n0,
+                                                    const double* w0, int64_t mp, const double* yp,
+                                                    const double* np_, const double* wp, int32_t n_part,
+                                                    const int64_t* po, double* T, double* NS, double* bx,
+                                                    double* bn, double* bw, int32_t* sid, int64_t* self) {
+    const int64_t ms = m0 + mp;
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= ms) return;
+    const double *y, *nn;
+    int64_t ns, k, li, n, start;
+    int s;
+    double w;
+    if (i < m0) {
+        s = 0;
+        y = y0;
+        nn = n0;
+        ns = m0;
+        k = li = i;
+        n = m0;
+        start = 0;
+        w = w0[i];
+    } else {
+        k = i - m0;
+        int lo = 0, hi = n_part;   // po[lo] <= k < po[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (po[mid] <= k)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        s = 1 + lo;
+        y = yp;
+        nn = np_;
+        ns = mp;
+        li = k - po[lo];
+        n = po[lo + 1] - po[lo];
+        start = m0 + po[lo];
+        w = wp[k];
+    }
+    for (int c = 0; c < 3; ++c) {
+        const double yc = y[c * ns + k], nc = nn[c * ns + k];
+        T[c * ms + i] = yc;
+        NS[c * ms + i] = nc;
+        bx[3 * start + c * n + li] = yc;
+        bn[3 * start + c * n + li] = nc;
+    }
+    bw[i] = w;
+    sid[i] = s;
+    self[i] = i;
+}
+
 // out = v / d elementwise over 3 n_tot entries.
 __global__ __launch_bounds__(PB) void k_pt_scale(int64_t n3, const double* v, const double* d, double* out) {
     const int64_t e = (int64_t)blockIdx.x * PB + threadIdx.x;
     if (e < n3) out[e] = v[e] / d[e];
 }
 
-// z = v_j / diag with v_j = V + j n3 of the slot, j read from the device descriptor
-// (the iteration of a replayed graph advances it on the device).
-__global__ __launch_bounds__(PB) void k_pt_scale_vj(int64_t n3, const SlotDesc* D, int slot, const double* d,
-                                                    double* out) {
-    const int64_t e = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (e < n3) out[e] = D[slot].V[(int64_t)D[slot].j * n3 + e] / d[e];
-}
-
-// Surface part of the unknown vector into per-surface SoA blocks (the sources of the
-// double-layer sums).
-__global__ __launch_bounds__(PB) void k_pt_gather(Surfaces S, int64_t ms, int64_t ntot, const double* z,
-                                                  double* qb, int64_t m0, double* qp) {
+// z = v / diag over the 3 n_tot entries (v given, or v_j = V + j 3 n_tot of the slot
+// with j read from the device descriptor when v is null: a replayed iteration advances
+// it on the device), and the surface part of z twice: into per-surface SoA blocks qb
+// (the moments' input) and, as planes of M_s, into the density of the one
+// double-layer sum over all surfaces, with the sign of each surface's term in the
+// operator: +q0 on the periphery, -q_p on a particle.
+__global__ __launch_bounds__(PB) void k_pt_scale_gather(Surfaces S, int64_t ms, int64_t ntot, const double* v,
+                                                        const SlotDesc* D, int slot, const double* diag,
+                                                        double* z, double* qb, double* qt) {
     const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= ntot) return;
+    if (!v) v = D[slot].V + (int64_t)D[slot].j * 3 * ntot;
+    double zc[3];
+    for (int c = 0; c < 3; ++c) {
+        zc[c] = v[c * ntot + i] / diag[c * ntot + i];
+        z[c * ntot + i] = zc[c];
+    }
     if (i >= ms) return;
     const int s = S.sid[i];
     const int64_t n = S.ssize[s], li = i - S.sstart[s];
     double* q = qb + 3 * S.sstart[s];
-    q[li] = z[i];
-    q[n + li] = z[ntot + i];
-    q[2 * n + li] = z[2 * ntot + i];
-    if (i >= m0) {   // the particles' densities also as one planar [3][mp] array
-        const int64_t mp = ms - m0, k = i - m0;
-        qp[k] = z[i];
-        qp[mp + k] = z[ntot + i];
-        qp[2 * mp + k] = z[2 * ntot + i];
+    const double sg = s == 0 ? 1.0 : -1.0;
+    for (int c = 0; c < 3; ++c) {
+        q[c * n + li] = zc[c];
+        qt[c * ms + i] = sg * zc[c];
     }
 }
 
-// One block per surface, fixed order: area (which = 0) or the moments of q (which = 1):
-// periphery red[0] = int n.q0; particle red[8 s + 0..2] = int q, red[8 s + 3..5] =
-// int (y - X) x q.
-__global__ __launch_bounds__(PB) void k_pt_reduce(Surfaces S, const double* qb, const double* X, int32_t np,
+// One block of PR threads per surface, fixed order: area (which = 0) or the moments of
+// q (which = 1): periphery red[0] = int n.q0; particle red[8 s + 0..2] = int q,
+// red[8 s + 3..5] = int (y - X) x q.
+constexpr int PR = 1024;
+__global__ __launch_bounds__(PR) void k_pt_reduce(Surfaces S, const double* qb, const double* X, int32_t np,
                                                   int which, double* red) {
-    __shared__ double lds[6][PB];
+    __shared__ double lds[6][PR];
     const int s = blockIdx.x;
     const int t = threadIdx.x;
     const int64_t n = S.ssize[s];
@@ -179,7 +237,7 @@ __global__ __launch_bounds__(PB) void k_pt_reduce(Surfaces S, const double* qb, 
     double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double cx = s > 0 ? X[s - 1] : 0.0, cy = s > 0 ? X[np + s - 1] : 0.0,
                  cz = s > 0 ? X[2 * np + s - 1] : 0.0;
-    for (int64_t k = t; k < n; k += PB) {
+    for (int64_t k = t; k < n; k += PR) {
         if (which == 0) {
             a[0] += w[k];
         } else if (s == 0) {
@@ -197,7 +255,7 @@ __global__ __launch_bounds__(PB) void k_pt_reduce(Surfaces S, const double* qb, 
     }
     for (int c = 0; c < 6; ++c) lds[c][t] = a[c];
     __syncthreads();
-    for (int h = PB / 2; h > 0; h >>= 1) {
+    for (int h = PR / 2; h > 0; h >>= 1) {
         if (t < h)
             for (int c = 0; c < 6; ++c) lds[c][t] += lds[c][t + h];
         __syncthreads();
@@ -205,19 +263,19 @@ __global__ __launch_bounds__(PB) void k_pt_reduce(Surfaces S, const double* qb, 
     if (t < 6) red[8 * s + t] = lds[t][0];
 }
 
-// w = A z from the double-layer sums D0 (periphery sources) and DP (particle
-// sources), the moments red and the areas (area[8 s], as k_pt_reduce lays them out).
+// w = A z from the double-layer sum Dq = K0[q0] - sum_p K_p[q_p] at every surface point
+// (each surface's own term in principal value), the moments red and the areas
+// (area[8 s], as k_pt_reduce lays them out).
 __global__ __launch_bounds__(PB) void k_pt_assemble(Surfaces S, int64_t ms, int64_t ntot, int32_t np,
-                                                    const double* z, const double* D0, const double* DP,
-                                                    const double* red, const double* area,
-                                                    const double* X, double* w) {
+                                                    const double* z, const double* Dq, const double* red,
+                                                    const double* area, const double* X, double* w) {
     const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
     if (i >= ntot) return;
     double v[3];
     if (i < ms) {
         const int s = S.sid[i];
         for (int c = 0; c < 3; ++c)
-            v[c] = -0.5 * z[c * ntot + i] + D0[c * ms + i] - DP[c * ms + i];
+            v[c] = -0.5 * z[c * ntot + i] + Dq[c * ms + i];
         const int64_t n = S.ssize[s], li = i - S.sstart[s];
         if (s == 0) {
             const double* nn = block(S.nrm, S, 0);
@@ -254,15 +312,17 @@ struct DevBuf {
     }
 };
 
-// A captured graph, its executable and the stream it was captured on, destroyed with
-// the object.
+// Two captured graphs, their executables and the stream they were captured on,
+// destroyed with the object.
 struct GraphGuard {
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     ~GraphGuard() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int p = 0; p < 2; ++p) {
+            if (exec[p]) (void)hipGraphExecDestroy(exec[p]);
+            if (graph[p]) (void)hipGraphDestroy(graph[p]);
+        }
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -302,24 +362,15 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     Range range("stokes_particle_solve");
     const uint32_t sumflags = flags & STOKES_PREC_MIXED;
 
-    // host tables
-    std::vector<int64_t> sstart(n_surf), ssize(n_surf);
-    sstart[0] = 0;
-    ssize[0] = m0;
+    // host table: surface starts and sizes (Surfaces), then part_offset
+    std::vector<int64_t> tab(2 * (size_t)n_surf + n_part + 1);
+    tab[0] = 0;
+    tab[n_surf] = m0;
     for (int p = 0; p < n_part; ++p) {
-        sstart[1 + p] = m0 + part_offset[p];
-        ssize[1 + p] = part_offset[p + 1] - part_offset[p];
+        tab[1 + p] = m0 + part_offset[p];
+        tab[n_surf + 1 + p] = part_offset[p + 1] - part_offset[p];
     }
-    std::vector<int32_t> sid(ms);
-    for (int s = 0; s < n_surf; ++s)
-        for (int64_t k = 0; k < ssize[s]; ++k) sid[sstart[s] + k] = s;
-    // trg_self of each surface's double-layer sum over all surface points
-    std::vector<int64_t> selfs((size_t)n_surf * ms, -1);
-    for (int s = 0; s < n_surf; ++s)
-        for (int64_t k = 0; k < ssize[s]; ++k) selfs[(size_t)s * ms + sstart[s] + k] = k;
-    // trg_self of the particles' one multi-surface sum: particle point i is source i - m0
-    std::vector<int64_t> selfp(ms, -1);
-    for (int64_t i = m0; i < ms; ++i) selfp[i] = i - m0;
+    for (int p = 0; p <= n_part; ++p) tab[2 * n_surf + p] = part_offset[p];
 
     // device scratch
     size_t off = 0;
@@ -328,97 +379,67 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
         off += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const size_t o_T = take(3 * ms * 8), o_bx = take(3 * ms * 8), o_bn = take(3 * ms * 8),
-                 o_bw = take(ms * 8), o_sid = take(ms * 4), o_ss = take(n_surf * 8), o_sz = take(n_surf * 8),
-                 o_self = take((size_t)n_surf * ms * 8), o_selfp = take(ms * 8), o_qp = take(3 * mp * 8),
-                 o_qb = take(3 * ms * 8), o_D0 = take(3 * ms * 8),
-                 o_DP = take(3 * ms * 8), o_red = take(8 * n_surf * 8), o_area = take(8 * n_surf * 8),
+    const size_t o_T = take(3 * ms * 8), o_N = take(3 * ms * 8), o_bx = take(3 * ms * 8),
+                 o_bn = take(3 * ms * 8), o_bw = take(ms * 8), o_sid = take(ms * 4), o_tab = take(tab.size() * 8),
+                 o_self = take(ms * 8), o_qt = take(3 * ms * 8), o_qb = take(3 * ms * 8),
+                 o_Dq = take(3 * ms * 8), o_red = take(8 * n_surf * 8), o_area = take(8 * n_surf * 8),
                  o_diag = take(n3 * 8), o_rhs = take(n3 * 8), o_slot = take(vector_plan_bytes(ntot, iters));
     DevBuf buf;
     STOKES_HIP(hipMalloc(&buf.p, off));
     char* base = static_cast<char*>(buf.p);
     double* T = reinterpret_cast<double*>(base + o_T);
+    double* NS = reinterpret_cast<double*>(base + o_N);
     double* bx = reinterpret_cast<double*>(base + o_bx);
     double* bn = reinterpret_cast<double*>(base + o_bn);
     double* bw = reinterpret_cast<double*>(base + o_bw);
     int32_t* d_sid = reinterpret_cast<int32_t*>(base + o_sid);
-    int64_t* d_ss = reinterpret_cast<int64_t*>(base + o_ss);
-    int64_t* d_sz = reinterpret_cast<int64_t*>(base + o_sz);
+    int64_t* d_tab = reinterpret_cast<int64_t*>(base + o_tab);
+    int64_t* d_ss = d_tab;
+    int64_t* d_sz = d_tab + n_surf;
+    const int64_t* d_po = d_tab + 2 * n_surf;
     int64_t* d_self = reinterpret_cast<int64_t*>(base + o_self);
-    int64_t* d_selfp = reinterpret_cast<int64_t*>(base + o_selfp);
-    double* qp = reinterpret_cast<double*>(base + o_qp);
+    double* qt = reinterpret_cast<double*>(base + o_qt);
     double* qb = reinterpret_cast<double*>(base + o_qb);
-    double* D0 = reinterpret_cast<double*>(base + o_D0);
-    double* DP = reinterpret_cast<double*>(base + o_DP);
+    double* Dq = reinterpret_cast<double*>(base + o_Dq);
     double* red = reinterpret_cast<double*>(base + o_red);
     double* area = reinterpret_cast<double*>(base + o_area);
     double* diag = reinterpret_cast<double*>(base + o_diag);
     double* rhs = reinterpret_cast<double*>(base + o_rhs);
     void* slot = base + o_slot;
 
-    // geometry: targets T (planes of M_s), per-surface blocks of points and normals
-    for (int c = 0; c < 3; ++c) {
-        if (m0 > 0) {
-            STOKES_HIP(hipMemcpyAsync(T + c * ms, y0 + c * m0, m0 * 8, hipMemcpyDeviceToDevice, st));
-            STOKES_HIP(hipMemcpyAsync(bx + c * m0, y0 + c * m0, m0 * 8, hipMemcpyDeviceToDevice, st));
-            STOKES_HIP(hipMemcpyAsync(bn + c * m0, n0 + c * m0, m0 * 8, hipMemcpyDeviceToDevice, st));
-        }
-        STOKES_HIP(hipMemcpyAsync(T + c * ms + m0, yp + c * mp, mp * 8, hipMemcpyDeviceToDevice, st));
-        for (int p = 0; p < n_part; ++p) {
-            const int64_t sz = ssize[1 + p], o = 3 * sstart[1 + p] + c * sz;
-            STOKES_HIP(hipMemcpyAsync(bx + o, yp + c * mp + part_offset[p], sz * 8, hipMemcpyDeviceToDevice, st));
-            STOKES_HIP(hipMemcpyAsync(bn + o, np_ + c * mp + part_offset[p], sz * 8, hipMemcpyDeviceToDevice, st));
-        }
-    }
-    if (m0 > 0) STOKES_HIP(hipMemcpyAsync(bw, w0, m0 * 8, hipMemcpyDeviceToDevice, st));
-    STOKES_HIP(hipMemcpyAsync(bw + m0, wp, mp * 8, hipMemcpyDeviceToDevice, st));
-    STOKES_HIP(hipMemcpyAsync(d_sid, sid.data(), ms * 4, hipMemcpyHostToDevice, st));
-    STOKES_HIP(hipMemcpyAsync(d_ss, sstart.data(), n_surf * 8, hipMemcpyHostToDevice, st));
-    STOKES_HIP(hipMemcpyAsync(d_sz, ssize.data(), n_surf * 8, hipMemcpyHostToDevice, st));
-    STOKES_HIP(hipMemcpyAsync(d_self, selfs.data(), (size_t)n_surf * ms * 8, hipMemcpyHostToDevice, st));
-    STOKES_HIP(hipMemcpyAsync(d_selfp, selfp.data(), ms * 8, hipMemcpyHostToDevice, st));
+    STOKES_HIP(hipMemcpyAsync(d_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_pt_geometry, dim3(grid1(ms)), dim3(PB), 0, st, m0, y0, n0, w0, mp, yp, np_, wp, n_part,
+                       d_po, T, NS, bx, bn, bw, d_sid, d_self);
     const Surfaces S{bx, bn, bw, d_sid, d_ss, d_sz};
 
     hipLaunchKernelGGL(k_pt_rhs, dim3(grid1(ntot)), dim3(PB), 0, st, ms, ntot, T, n_part, centers, force,
                        torque, mu, rhs);
     hipLaunchKernelGGL(k_pt_diag, dim3((unsigned)ntot), dim3(64), 0, st, S, ms, ntot, diag);
-    hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, st, S, (const double*)qb, centers, n_part, 0,
+    hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PR), 0, st, S, (const double*)qb, centers, n_part, 0,
                        area);
     STOKES_HIP(hipGetLastError());
 
-    // The two double-layer sums of the operator on the fixed geometry: the periphery
-    // onto every point, and all particles in one sum in which each target subtracts its
-    // own density only from its own particle's sources (surface ids d_sid, 1 + p).
-    // Their tiles, packs and exclusion ranges are made once here; an iteration re-packs
-    // only the density.
-    DLPlan plan0, planP;
-    if (m0 > 0) {
-        int rc = plan0.init(m0, bx, bn, bw, nullptr, ms, T, d_self, near_r, sumflags, st);
-        if (rc) return rc;
-    } else {
-        STOKES_HIP(hipMemsetAsync(D0, 0, 3 * ms * 8, st));
-    }
-    if (int rc = planP.init(mp, yp, np_, wp, d_sid + m0, ms, T, d_selfp, near_r, sumflags, st)) return rc;
+    // The double layers of the operator, K0[q0] - sum_p K_p[q_p] at every surface point,
+    // as one sum over all surfaces with the density +q0 on the periphery and -q_p on the
+    // particles: each target subtracts its own density (the principal value) only from
+    // the sources of its own surface (surface ids d_sid: 0 the periphery, 1 + p the
+    // particles) and sums the other surfaces raw.  Tiles, packs and exclusion ranges are
+    // made once here; an iteration re-packs only the density.
+    DLPlan plan;
+    if (int rc = plan.init(ms, T, NS, bw, d_sid, ms, T, d_self, near_r, sumflags, st)) return rc;
 
     // w = A P^{-1} v on stream s: z = v / diag (v given, or v_j of slot 0 read on the
     // device when v is null: the captured iteration), then the operator
     Batch b;
     auto apply = [&](const double* v, double* z, double* w, hipStream_t s) -> int {
-        if (v)
-            hipLaunchKernelGGL(k_pt_scale, dim3(grid1(n3)), dim3(PB), 0, s, n3, v, (const double*)diag, z);
-        else
-            hipLaunchKernelGGL(k_pt_scale_vj, dim3(grid1(n3)), dim3(PB), 0, s, n3, b.dev_desc(), 0,
-                               (const double*)diag, z);
-        hipLaunchKernelGGL(k_pt_gather, dim3(grid1(ms)), dim3(PB), 0, s, S, ms, ntot, (const double*)z, qb, m0,
-                           qp);
-        int rc = STOKES_OK;
-        if (m0 > 0 && (rc = plan0.eval(qb, D0, false, s, v == nullptr))) return rc;
-        if ((rc = planP.eval(qp, DP, false, s, v == nullptr))) return rc;
-        hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PB), 0, s, S, (const double*)qb, centers, n_part,
+        hipLaunchKernelGGL(k_pt_scale_gather, dim3(grid1(ntot)), dim3(PB), 0, s, S, ms, ntot, v,
+                           (const SlotDesc*)b.dev_desc(), 0, (const double*)diag, z, qb, qt);
+        if (int rc = plan.eval(qt, Dq, false, s, v == nullptr)) return rc;
+        hipLaunchKernelGGL(k_pt_reduce, dim3(n_surf), dim3(PR), 0, s, S, (const double*)qb, centers, n_part,
                            1, red);
         hipLaunchKernelGGL(k_pt_assemble, dim3(grid1(ntot)), dim3(PB), 0, s, S, ms, ntot, n_part,
-                           (const double*)z, (const double*)D0, (const double*)DP, (const double*)red,
-                           (const double*)area, centers, w);
+                           (const double*)z, (const double*)Dq, (const double*)red, (const double*)area,
+                           centers, w);
         STOKES_HIP(hipGetLastError());
         return STOKES_OK;
     };
@@ -430,68 +451,61 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
     if ((rc = b.start_vector(one))) return rc;
     int done = 0;
     double resid = b.status(0)[2];
-    // The iteration -- operator and Gram-Schmidt, about twenty small kernels -- is
-    // captured once into a HIP graph and replayed (no memset nodes; v_j and the
-    // iteration counter are read on the device), so the host launches one graph per
-    // iteration instead of twenty kernels whose launch gaps exceeded their run time.
+    // The iteration -- operator, Gram-Schmidt and the copy of the status row, eleven
+    // kernels and a copy -- is captured into a HIP graph and replayed (no memset nodes;
+    // v_j and the iteration counter are read on the device, and the last Gram-Schmidt
+    // kernel advances the counter), so the host launches one graph per iteration instead
+    // of twelve operations whose launch gaps were longer than most of their run times.
+    // Two graphs, one per status row, alternate (iteration j copies into row j mod 2).
     // The capture runs on a stream of its own (the caller's may be the null stream, which
-    // cannot capture); it only records, and the graph is replayed on the caller's stream.
+    // cannot capture); it only records, and the graphs are replayed on the caller's stream.
     GraphGuard gg;
     if (graph && b.status(0)[3] == 0.0) {
         b.desc(0).j = 0;
         if ((rc = b.ortho_lists(one))) return rc;
         STOKES_HIP(hipStreamCreateWithFlags(&gg.cap, hipStreamNonBlocking));   // (default priority)
-        STOKES_HIP(hipStreamBeginCapture(gg.cap, hipStreamCaptureModeThreadLocal));
-        rc = apply(nullptr, b.desc(0).z, b.desc(0).w, gg.cap);
-        if (!rc) rc = b.launch_ortho_fixed(one, gg.cap);
-        hipGraph_t gr = nullptr;
-        const hipError_t e = hipStreamEndCapture(gg.cap, &gr);
-        gg.graph = gr;
-        if (rc) return rc;
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        STOKES_HIP(hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0));
+        for (int p = 0; p < 2; ++p) {
+            STOKES_HIP(hipStreamBeginCapture(gg.cap, hipStreamCaptureModeThreadLocal));
+            rc = apply(nullptr, b.desc(0).z, b.desc(0).w, gg.cap);
+            if (!rc) rc = b.launch_ortho_fixed(one, gg.cap);
+            if (!rc) rc = b.copy_status_async(b.lag_row(p), gg.cap);
+            hipGraph_t gr = nullptr;
+            const hipError_t e = hipStreamEndCapture(gg.cap, &gr);
+            gg.graph[p] = gr;
+            if (rc) return rc;
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            STOKES_HIP(hipGraphInstantiate(&gg.exec[p], gg.graph[p], nullptr, nullptr, 0));
+        }
     }
     if (b.status(0)[3] == 0.0) {
         // The host does not wait for each iteration: iteration j is enqueued before the
         // status of iteration j - 1 is read (two pinned status rows, one event each).  An
         // exact breakdown is therefore seen one iteration late; the extra iteration then
         // writes only Krylov entries beyond the ones the solution uses (x = 0 input).
-        double* hst = nullptr;
-        hipEvent_t ev[2] = {nullptr, nullptr};
-        auto cleanup = [&]() {
-            for (hipEvent_t e : ev)
-                if (e) (void)hipEventDestroy(e);
-            if (hst) (void)hipHostFree(hst);
-        };
-        hipError_t e = hipHostMalloc((void**)&hst, 2 * sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault);
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
-        if (e != hipSuccess) {
-            cleanup();
-            return hip_fail(e, "particle solve: status buffers");
-        }
+        hipError_t e = hipSuccess;
         bool broke = false;
         for (int j = 0; j <= iters && !broke; ++j) {
             if (j < iters) {
                 if (graph) {   // the replay computes iteration j (its counter is on the device)
-                    const hipError_t ge = hipGraphLaunch(gg.exec, st);
+                    const hipError_t ge = hipGraphLaunch(gg.exec[j & 1], st);
                     if (ge != hipSuccess) rc = hip_fail(ge, "hipGraphLaunch");
                 } else {
                     SlotDesc& d = b.desc(0);
                     d.j = j;
                     if (!rc) rc = apply(d.V + (int64_t)j * n3, d.z, d.w, st);
                     if (!rc) rc = b.step_ortho_nowait(one);
+                    if (!rc) rc = b.copy_status_async(b.lag_row(j));
                 }
-                if (!rc) rc = b.copy_status_async(hst + (j & 1) * NSTAT * MAX_SLOTS);
                 if (!rc) {
-                    e = hipEventRecord(ev[j & 1], st);
+                    e = hipEventRecord(b.lag_event(j), st);
                     if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord");
                 }
             }
             if (j > 0 && !rc) {   // the previous iteration's status
-                e = hipEventSynchronize(ev[(j - 1) & 1]);
+                e = hipEventSynchronize(b.lag_event(j - 1));
                 if (e != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
                 if (!rc) {
-                    const double* row = hst + ((j - 1) & 1) * NSTAT * MAX_SLOTS;
+                    const double* row = b.lag_row(j - 1);
                     done = j;
                     resid = row[2];
                     broke = row[3] != 0.0;   // exact breakdown at iteration j - 1
@@ -503,7 +517,6 @@ extern "C" int stokes_particle_solve(int64_t m0, const double* y0, const double*
             e = hipStreamSynchronize(st);   // a late breakdown's extra iteration is done
             if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
         }
-        cleanup();
         if (rc) return rc;
     }
     b.desc(0).j = done;

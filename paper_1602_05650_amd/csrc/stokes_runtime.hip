@@ -203,6 +203,7 @@ extern "C" int stokes_release_workspace(void) {
     }
     g_ws.clear();
     fiberstep_release();
+    batch_res_drain();
     if (rc) set_error("stokes_release_workspace: device synchronisation failed");
     return rc;
 }

@@ -16,6 +16,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
+#include <vector>
 
 #include "fiber_device.hpp"
 #include "gj_device.hpp"
@@ -58,40 +61,45 @@ __device__ __forceinline__ void block_apply(const double* binv, int64_t i, int64
     oz = a2;
 }
 
-// Partial dot products of m vectors A[i] (stride) with w over block b's range,
-// eight vectors per pass (w is read once per pass).  Per vector the order of
-// the arithmetic is fixed: each thread's strided partial, then a fixed tree.
+// Partial dot products of m vectors A[i] (stride) with w.  A slot's dot work items are
+// B element blocks times dot_groups(k) groups of DOT_GROUP vectors: item `item` covers
+// block b = item % B of the elements and vectors [i0, i0 + DOT_GROUP) with
+// i0 = DOT_GROUP (item / B), so the groups of one iteration run in parallel (a group
+// at or past m has nothing to do).  Per vector the order of the arithmetic is fixed:
+// each thread's strided partial over block b, then a fixed tree.
 constexpr int DOT_GROUP = 8;
+__host__ __device__ inline int dot_groups(int k) { return (k + DOT_GROUP) / DOT_GROUP; }   // covers m <= k + 1
 __device__ void dot_partials(const double* A, int64_t stride, int m, const double* w, int64_t n,
-                             int B, int b, double* out, double (*lds)[BLOCK]) {
+                             int B, int item, double* out, double (*lds)[BLOCK]) {
+    const int b = item % B;
+    const int i0 = (item / B) * DOT_GROUP;
+    if (i0 >= m) return;   // block-uniform
     const int64_t L = (n + B - 1) / B;
     const int64_t e0 = (int64_t)b * L;
     const int64_t e1 = min(n, e0 + L);
     const int t = threadIdx.x;
-    for (int i0 = 0; i0 < m; i0 += DOT_GROUP) {
-        const int g_n = min(DOT_GROUP, m - i0);
-        double s[DOT_GROUP];
+    const int g_n = min(DOT_GROUP, m - i0);
+    double s[DOT_GROUP];
 #pragma unroll
-        for (int g = 0; g < DOT_GROUP; ++g) s[g] = 0.0;
-        for (int64_t e = e0 + t; e < e1; e += BLOCK) {
-            const double we = w[e];
+    for (int g = 0; g < DOT_GROUP; ++g) s[g] = 0.0;
+    for (int64_t e = e0 + t; e < e1; e += BLOCK) {
+        const double we = w[e];
 #pragma unroll
-            for (int g = 0; g < DOT_GROUP; ++g)
-                if (g < g_n) s[g] = fma(A[(int64_t)(i0 + g) * stride + e], we, s[g]);
+        for (int g = 0; g < DOT_GROUP; ++g)
+            if (g < g_n) s[g] = fma(A[(int64_t)(i0 + g) * stride + e], we, s[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < DOT_GROUP; ++g) lds[g][t] = s[g];
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+        if (t < h) {
+#pragma unroll
+            for (int g = 0; g < DOT_GROUP; ++g) lds[g][t] += lds[g][t + h];
         }
-#pragma unroll
-        for (int g = 0; g < DOT_GROUP; ++g) lds[g][t] = s[g];
-        __syncthreads();
-        for (int h = BLOCK / 2; h > 0; h >>= 1) {
-            if (t < h) {
-#pragma unroll
-                for (int g = 0; g < DOT_GROUP; ++g) lds[g][t] += lds[g][t + h];
-            }
-            __syncthreads();
-        }
-        if (t < g_n) out[(int64_t)(i0 + t) * B + b] = lds[t][0];
         __syncthreads();
     }
+    if (t < g_n) out[(int64_t)(i0 + t) * B + b] = lds[t][0];
+    __syncthreads();
 }
 
 // ---- set-up kernels (eager, at admission) ------------------------------------
@@ -334,81 +342,136 @@ __global__ __launch_bounds__(BLOCK) void k_dot(const SlotDesc* D, const StepTabl
     }
 }
 
-// h = (sum over blocks of the partials), in block order.  which: 0 -> hA, 1 -> hB.
-__global__ __launch_bounds__(BLOCK) void k_dred(const SlotDesc* D, const StepTables* T, int which) {
-    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
-    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
-        const auto& d = as_const(D)[wl->slot[find_slot(wl, it)]];
-        double* h = which ? d.hB : d.hA;
-        for (int i = threadIdx.x; i <= d.j; i += BLOCK) {
-            double s = 0.0;
-            for (int b = 0; b < d.B; ++b) s += d.dotp[(int64_t)i * d.B + b];
-            h[i] = s;
+// hs[i] = the sum over b < B of p[i B + b], for i < m, by the whole block: tpr threads
+// per row (8, 16 or 32: more when there are fewer rows; thread t takes row i0 + t / tpr
+// and the partials b = t % tpr, t % tpr + tpr, ... in order, four loads ahead), then a
+// fixed butterfly over the tpr threads, which leaves the same value in each of them.
+// The caller synchronises before reading hs.
+__device__ void block_sum_rows(const double* p, int B, int m, double* hs) {
+    const int tpr = m > 16 ? 8 : (m > 8 ? 16 : 32);
+    const int r = threadIdx.x / tpr, q = threadIdx.x % tpr;
+    for (int i0 = 0; i0 < m; i0 += BLOCK / tpr) {
+        const int i = i0 + r;
+        double s = 0.0;
+        if (i < m) {
+            const double* pr = p + (int64_t)i * B;
+            int b = q;
+            for (; b + 3 * tpr < B; b += 4 * tpr) {
+                const double a0 = pr[b], a1 = pr[b + tpr], a2 = pr[b + 2 * tpr], a3 = pr[b + 3 * tpr];
+                s += a0;
+                s += a1;
+                s += a2;
+                s += a3;
+            }
+            for (; b < B; b += tpr) s += pr[b];
         }
+        for (int o = tpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (i < m && q == 0) hs[i] = s;
     }
 }
 
-// w -= sum_i V[i] h[i]  (i ascending), h = hA or hB.
+// w -= sum_i V[i] h[i] (i ascending) with h[i] = the sum of the B block partials of
+// dotp row i (every block forms h for its slot in LDS; the block that takes the slot's
+// first item also stores it, which: 0 -> hA, 1 -> hB, for the Hessenberg column).
 __global__ __launch_bounds__(BLOCK) void k_axpy(const SlotDesc* D, const StepTables* T, int which) {
+    __shared__ double hs[STOKES_MAX_ITERS + 1];
     const cptr<WorkList> wl = &as_const(T)->wl[WL_VEC];
+    int cur = -1;
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
         const auto& d = as_const(D)[wl->slot[si]];
+        if (si != cur) {   // block-uniform
+            __syncthreads();
+            block_sum_rows(d.dotp, d.B, d.j + 1, hs);
+            __syncthreads();
+            if (it == wl->prefix[si]) {
+                double* h = which ? d.hB : d.hA;
+                for (int i = threadIdx.x; i <= d.j; i += BLOCK) h[i] = hs[i];
+            }
+            cur = si;
+        }
         const int64_t n = 3 * (int64_t)d.N;
         const int64_t e = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (e >= n) continue;
-        const double* h = which ? d.hB : d.hA;
         double acc = 0.0;
-        for (int i = 0; i <= d.j; ++i) acc = fma(d.V[(int64_t)i * n + e], h[i], acc);
+        for (int i = 0; i <= d.j; ++i) acc = fma(d.V[(int64_t)i * n + e], hs[i], acc);
         d.w[e] = d.w[e] - acc;
     }
 }
 
-// Hessenberg column j, previous rotations, new rotation, residual |g_{j+1}|.
-__global__ __launch_bounds__(BLOCK) void k_givens(const SlotDesc* D, const StepTables* T,
-                                                  double* stat) {
-    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
-    for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
-        const auto& d = as_const(D)[wl->slot[find_slot(wl, it)]];
-        if (threadIdx.x != 0) continue;
-        const int j = d.j;
-        double s = 0.0;
-        for (int b = 0; b < d.B; ++b) s += d.normp[b];
-        const double hn = sqrt(s);
-        double* col = d.H + (int64_t)j * (d.k + 1);
-        for (int i = 0; i <= j; ++i) col[i] = d.hA[i] + d.hB[i];
-        col[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-            const double a = col[i], c = col[i + 1];
-            col[i] = d.cs[i] * a + d.sn[i] * c;
-            col[i + 1] = -d.sn[i] * a + d.cs[i] * c;
-        }
-        const double den = hypot(col[j], col[j + 1]);
-        d.cs[j] = col[j] / den;
-        d.sn[j] = col[j + 1] / den;
-        col[j] = den;
-        col[j + 1] = 0.0;
-        d.g[j + 1] = -d.sn[j] * d.g[j];
-        d.g[j] = d.cs[j] * d.g[j];
-        double* st = stat + NSTAT * d.sid;
-        st[0] = hn;
-        st[2] = fabs(d.g[j + 1]);
-        st[3] = hn == 0.0 ? 1.0 : 0.0;
-    }
-}
-
-// v_{j+1} = w / h_{j+1,j}
-__global__ __launch_bounds__(BLOCK) void k_scale(const SlotDesc* D, const StepTables* T,
-                                                 const double* stat) {
+// v_{j+1} = w / h_{j+1,j} with h_{j+1,j} = |w| = sqrt(the sum of the B block partials of
+// w.w), 0 after a breakdown (h_{j+1,j} = 0).  The block that takes the slot's first item
+// also does the Givens step on LDS copies: Hessenberg column j (hA + hB, then
+// h_{j+1,j}), the previous rotations in order, the new rotation, the residual |g_{j+1}|
+// and the status row.  With `arrive` (a replayed iteration), the last block to finish
+// advances each listed slot's iteration counter j, once every block has read it: each
+// block counts itself in after a fence, and the one that brings the count to the grid
+// size resets the count and writes the counters.
+__global__ __launch_bounds__(BLOCK) void k_scale_givens(SlotDesc* D, const StepTables* T, double* stat,
+                                                        unsigned* arrive) {
+    __shared__ double hn_s;
+    __shared__ double col[STOKES_MAX_ITERS + 2], cs[STOKES_MAX_ITERS + 1], sn[STOKES_MAX_ITERS + 1];
     const cptr<WorkList> wl = &as_const(T)->wl[WL_VEC];
+    int cur = -1;
+    double hn = 0.0;
     for (int64_t it = blockIdx.x; it < wl->prefix[wl->n]; it += gridDim.x) {
         const int si = find_slot(wl, it);
         const auto& d = as_const(D)[wl->slot[si]];
+        if (si != cur) {   // block-uniform
+            const bool first = it == wl->prefix[si];
+            const int j = d.j;
+            __syncthreads();
+            block_sum_rows(d.normp, d.B, 1, &hn_s);
+            if (first)
+                for (int i = threadIdx.x; i <= j; i += BLOCK) {
+                    col[i] = d.hA[i] + d.hB[i];
+                    if (i < j) {
+                        cs[i] = d.cs[i];
+                        sn[i] = d.sn[i];
+                    }
+                }
+            __syncthreads();
+            hn = sqrt(hn_s);
+            cur = si;
+            if (first) {
+                if (threadIdx.x == 0) {
+                    col[j + 1] = hn;
+                    for (int i = 0; i < j; ++i) {
+                        const double a = col[i], c = col[i + 1];
+                        col[i] = cs[i] * a + sn[i] * c;
+                        col[i + 1] = -sn[i] * a + cs[i] * c;
+                    }
+                    const double den = hypot(col[j], col[j + 1]);
+                    d.cs[j] = col[j] / den;
+                    d.sn[j] = col[j + 1] / den;
+                    col[j] = den;
+                    col[j + 1] = 0.0;
+                    d.g[j + 1] = -d.sn[j] * d.g[j];
+                    d.g[j] = d.cs[j] * d.g[j];
+                    double* st = stat + NSTAT * d.sid;
+                    st[0] = hn;
+                    st[2] = fabs(d.g[j + 1]);
+                    st[3] = hn == 0.0 ? 1.0 : 0.0;
+                }
+                __syncthreads();
+                double* H = d.H + (int64_t)j * (d.k + 1);
+                for (int i = threadIdx.x; i <= j + 1; i += BLOCK) H[i] = col[i];
+            }
+        }
         const int64_t n = 3 * (int64_t)d.N;
         const int64_t e = (it - wl->prefix[si]) * BLOCK + threadIdx.x;
         if (e >= n) continue;
-        const double hn = stat[NSTAT * d.sid];
         d.V[(int64_t)(d.j + 1) * n + e] = hn > 0.0 ? d.w[e] / hn : 0.0;
+    }
+    if (!arrive) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(arrive, 1u) == gridDim.x - 1) {
+            for (int q = 0; q < wl->n; ++q) D[wl->slot[q]].j += 1;
+            *arrive = 0u;
+            __threadfence();
+        }
     }
 }
 
@@ -501,10 +564,11 @@ __global__ __launch_bounds__(BLOCK) void k_nonlocal_eval(int64_t N, int npf, con
 
 // ---- host side ---------------------------------------------------------------------
 
-// Blocks per request for the Gram-Schmidt dot products: about one per 1024
-// vector elements, so mid-size requests also spread over many CUs.
+// Element blocks per request for the Gram-Schmidt dot products: about one per 256
+// vector elements (a thread per element and vector group), at most 256, so that
+// mid-size requests also spread over many CUs.
 static int32_t dot_blocks(int64_t n) {
-    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (n + 1023) / 1024));
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (n + 255) / 256));
 }
 
 size_t vector_plan_bytes(int64_t n_vec, int32_t k) {
@@ -568,43 +632,137 @@ SlotPlan slot_plan(int32_t n_fib, int32_t npf, int32_t k, bool mixed, uint32_t o
     return sp;
 }
 
+struct BatchRes {
+    int dev = -1;
+    SlotDesc* host_desc = nullptr;
+    StepTables* host_tab = nullptr;
+    double* host_stat = nullptr;
+    double* lag = nullptr;   // [2][MAX_SLOTS * NSTAT]
+    hipEvent_t lag_ev[2] = {nullptr, nullptr};
+    SlotDesc* stage_desc[UPLOAD_RING] = {};
+    StepTables* stage_tab[UPLOAD_RING] = {};
+    hipEvent_t stage_ev[UPLOAD_RING] = {};
+    SlotDesc* dev_desc = nullptr;
+    StepTables* dev_tab = nullptr;
+    double* dev_stat = nullptr;
+    unsigned* dev_arrive = nullptr;   // k_scale_givens' block count (zero between launches)
+    ~BatchRes() {
+        for (int k = 0; k < UPLOAD_RING; ++k) {
+            if (stage_ev[k]) (void)hipEventDestroy(stage_ev[k]);
+            if (stage_desc[k]) (void)hipHostFree(stage_desc[k]);
+            if (stage_tab[k]) (void)hipHostFree(stage_tab[k]);
+        }
+        for (hipEvent_t e : lag_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (dev_desc) (void)hipFree(dev_desc);
+        if (dev_tab) (void)hipFree(dev_tab);
+        if (dev_stat) (void)hipFree(dev_stat);
+        if (dev_arrive) (void)hipFree(dev_arrive);
+        if (host_desc) (void)hipHostFree(host_desc);
+        if (host_tab) (void)hipHostFree(host_tab);
+        if (host_stat) (void)hipHostFree(host_stat);
+        if (lag) (void)hipHostFree(lag);
+    }
+};
+
+static std::mutex g_res_mu;
+static std::vector<BatchRes*> g_res_free;   // kept until the process ends
+
+static int batch_res_acquire(BatchRes** out) {
+    int dev = 0;
+    STOKES_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        for (size_t i = 0; i < g_res_free.size(); ++i)
+            if (g_res_free[i]->dev == dev) {
+                *out = g_res_free[i];
+                g_res_free.erase(g_res_free.begin() + (std::ptrdiff_t)i);
+                return STOKES_OK;
+            }
+    }
+    std::unique_ptr<BatchRes> r(new BatchRes());
+    r->dev = dev;
+    STOKES_HIP(hipHostMalloc((void**)&r->host_desc, sizeof(SlotDesc) * MAX_SLOTS, hipHostMallocDefault));
+    STOKES_HIP(hipHostMalloc((void**)&r->host_tab, sizeof(StepTables), hipHostMallocDefault));
+    STOKES_HIP(hipHostMalloc((void**)&r->host_stat, sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault));
+    STOKES_HIP(hipHostMalloc((void**)&r->lag, 2 * sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault));
+    for (int k = 0; k < 2; ++k) STOKES_HIP(hipEventCreateWithFlags(&r->lag_ev[k], hipEventDisableTiming));
+    for (int k = 0; k < UPLOAD_RING; ++k) {
+        STOKES_HIP(hipHostMalloc((void**)&r->stage_desc[k], sizeof(SlotDesc) * MAX_SLOTS, hipHostMallocDefault));
+        STOKES_HIP(hipHostMalloc((void**)&r->stage_tab[k], sizeof(StepTables), hipHostMallocDefault));
+        STOKES_HIP(hipEventCreateWithFlags(&r->stage_ev[k], hipEventDisableTiming));
+    }
+    STOKES_HIP(hipMalloc((void**)&r->dev_desc, sizeof(SlotDesc) * MAX_SLOTS));
+    STOKES_HIP(hipMalloc((void**)&r->dev_tab, sizeof(StepTables)));
+    STOKES_HIP(hipMalloc((void**)&r->dev_stat, sizeof(double) * NSTAT * MAX_SLOTS));
+    STOKES_HIP(hipMalloc((void**)&r->dev_arrive, sizeof(unsigned)));
+    STOKES_HIP(hipMemset(r->dev_arrive, 0, sizeof(unsigned)));
+    *out = r.release();
+    return STOKES_OK;
+}
+
+// Back to the free list once nothing queued on the Batch's stream still reads them;
+// freed instead if that wait fails.
+static void batch_res_release(BatchRes* r, hipStream_t st) {
+    if (!r) return;
+    if (hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        delete r;
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    g_res_free.push_back(r);
+}
+
+void batch_res_drain() {
+    std::vector<BatchRes*> all;
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        all.swap(g_res_free);
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (BatchRes* r : all) {
+        (void)hipSetDevice(r->dev);
+        delete r;
+    }
+    (void)hipSetDevice(cur);
+}
+
 Batch::~Batch() {
     if (exec_) (void)hipGraphExecDestroy(exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
-    if (dev_desc_) (void)hipFree(dev_desc_);
-    if (dev_tab_) (void)hipFree(dev_tab_);
-    if (dev_stat_) (void)hipFree(dev_stat_);
-    if (host_desc_) (void)hipHostFree(host_desc_);
-    if (host_tab_) (void)hipHostFree(host_tab_);
-    if (host_stat_) (void)hipHostFree(host_stat_);
-    for (Stage& g : stage_) {
-        if (g.ev) (void)hipEventDestroy(g.ev);
-        if (g.desc) (void)hipHostFree(g.desc);
-        if (g.tab) (void)hipHostFree(g.tab);
-    }
+    batch_res_release(res_, st_);
 }
 
 int Batch::init(hipStream_t st, bool mixed, bool doublet, bool use_graph) {
+    if (res_) return fail(STOKES_E_INVAL, "Batch::init: already initialised");
     st_ = st;
     mixed_ = mixed;
     doublet_ = doublet;
     use_graph_ = use_graph;
-    STOKES_HIP(hipHostMalloc((void**)&host_desc_, sizeof(SlotDesc) * MAX_SLOTS, hipHostMallocDefault));
-    STOKES_HIP(hipHostMalloc((void**)&host_tab_, sizeof(StepTables), hipHostMallocDefault));
-    STOKES_HIP(hipHostMalloc((void**)&host_stat_, sizeof(double) * NSTAT * MAX_SLOTS, hipHostMallocDefault));
-    for (Stage& g : stage_) {
-        STOKES_HIP(hipHostMalloc((void**)&g.desc, sizeof(SlotDesc) * MAX_SLOTS, hipHostMallocDefault));
-        STOKES_HIP(hipHostMalloc((void**)&g.tab, sizeof(StepTables), hipHostMallocDefault));
-        STOKES_HIP(hipEventCreateWithFlags(&g.ev, hipEventDisableTiming));
+    if (int rc = batch_res_acquire(&res_)) return rc;
+    host_desc_ = res_->host_desc;
+    host_tab_ = res_->host_tab;
+    host_stat_ = res_->host_stat;
+    dev_desc_ = res_->dev_desc;
+    dev_tab_ = res_->dev_tab;
+    dev_stat_ = res_->dev_stat;
+    for (int k = 0; k < NSTAGE; ++k) {
+        stage_[k].desc = res_->stage_desc[k];
+        stage_[k].tab = res_->stage_tab[k];
+        stage_[k].ev = res_->stage_ev[k];
+        stage_[k].used = false;
     }
-    STOKES_HIP(hipMalloc((void**)&dev_desc_, sizeof(SlotDesc) * MAX_SLOTS));
-    STOKES_HIP(hipMalloc((void**)&dev_tab_, sizeof(StepTables)));
-    STOKES_HIP(hipMalloc((void**)&dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS));
+    next_stage_ = 0;
     memset(host_desc_, 0, sizeof(SlotDesc) * MAX_SLOTS);
     memset(host_tab_, 0, sizeof(StepTables));
     memset(host_stat_, 0, sizeof(double) * NSTAT * MAX_SLOTS);
     return STOKES_OK;
 }
+
+double* Batch::lag_row(int k) { return res_->lag + (size_t)(k & 1) * NSTAT * MAX_SLOTS; }
+hipEvent_t Batch::lag_event(int k) { return res_->lag_ev[k & 1]; }
 
 int Batch::attach(int s, void* mem, int32_t n_fib, int32_t npf, int32_t k, double eps, double mu,
                   double near_r, uint32_t opts, double delta, const double* xyz,
@@ -700,7 +858,7 @@ void Batch::set_list(WL w, const std::vector<int>& slots) {
             case WL_PRE: items = d.n_items_node; break;   // >= tiles / BLOCK as well
             case WL_SL: items = d.n_items_sl; break;
             case WL_RED: items = d.n_items_node; break;
-            case WL_DOT: items = d.B; break;
+            case WL_DOT: items = (int64_t)d.B * dot_groups(d.k); break;
             case WL_ONE: items = 1; break;
             case WL_VEC: items = d.n_items_vec; break;
             case WL_FIB: items = (d.opts & STOKES_PRECOND_BLOCK) ? d.n_fib : 0; break;
@@ -743,8 +901,9 @@ static unsigned grid_for(const WorkList& L, int cap) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(t, cap));
 }
 
-int Batch::copy_status_async(double* dst) {
-    STOKES_HIP(hipMemcpyAsync(dst, dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS, hipMemcpyDeviceToHost, st_));
+int Batch::copy_status_async(double* dst, hipStream_t s) {
+    STOKES_HIP(hipMemcpyAsync(dst, dev_stat_, sizeof(double) * NSTAT * MAX_SLOTS, hipMemcpyDeviceToHost,
+                              s ? s : st_));
     return STOKES_OK;
 }
 int Batch::read_status() {
@@ -793,18 +952,17 @@ int Batch::launch_step(bool graph_sizes) {
     return launch_ortho(graph_sizes);
 }
 
-int Batch::launch_ortho(bool graph_sizes) {
+int Batch::launch_ortho(bool graph_sizes, bool advance) {
     const StepTables& T = *host_tab_;
     auto g = [&](WL w, int cap) { return graph_sizes ? (unsigned)cap : grid_for(T.wl[w], cap); };
     const dim3 b(BLOCK);
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_dot, dim3(g(WL_DOT, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, pass);
-        hipLaunchKernelGGL(k_dred, dim3(g(WL_ONE, G_ONE)), b, 0, st_, dev_desc_, dev_tab_, pass);
         hipLaunchKernelGGL(k_axpy, dim3(g(WL_VEC, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, pass);
     }
     hipLaunchKernelGGL(k_dot, dim3(g(WL_DOT, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, 2);
-    hipLaunchKernelGGL(k_givens, dim3(g(WL_ONE, G_ONE)), b, 0, st_, dev_desc_, dev_tab_, dev_stat_);
-    hipLaunchKernelGGL(k_scale, dim3(g(WL_VEC, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, (const double*)dev_stat_);
+    hipLaunchKernelGGL(k_scale_givens, dim3(g(WL_VEC, G_ELEM)), b, 0, st_, dev_desc_, dev_tab_, dev_stat_,
+                       advance ? res_->dev_arrive : (unsigned*)nullptr);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }
@@ -981,14 +1139,6 @@ int Batch::step_ortho_nowait(const std::vector<int>& slots) {
     return launch_ortho(false);
 }
 
-// j += 1 for the listed slots (one thread): the next replay of a captured iteration
-// computes the next Krylov vector.
-__global__ void k_advance(SlotDesc* D, const StepTables* T) {
-    const cptr<WorkList> wl = &as_const(T)->wl[WL_ONE];
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        for (int q = 0; q < wl->n; ++q) D[wl->slot[q]].j += 1;
-}
-
 int Batch::ortho_lists(const std::vector<int>& slots) {
     set_list(WL_DOT, slots);
     set_list(WL_ONE, slots);
@@ -1000,12 +1150,9 @@ int Batch::launch_ortho_fixed(const std::vector<int>& slots, hipStream_t s) {
     if (slots.empty()) return STOKES_OK;
     const hipStream_t own = st_;
     st_ = s;
-    const int rc = launch_ortho(false);
+    const int rc = launch_ortho(false, true);
     st_ = own;
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, dev_desc_, dev_tab_);
-    STOKES_HIP(hipGetLastError());
-    return STOKES_OK;
+    return rc;
 }
 
 int Batch::finalize_vector(const std::vector<int>& slots) {

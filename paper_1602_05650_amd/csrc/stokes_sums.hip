@@ -163,10 +163,11 @@ __global__ void excl_fiber_kernel(int64_t n_t, const int32_t* __restrict__ tfib,
 
 // out = (accumulate ? out : 0) + sum_k partial[k]  (+ jump term), chunk order fixed.
 // Sum of the chunk partials per target (plus the double layer's jump term).  A
-// workgroup takes 64 targets with four threads each: thread slice sl sums chunks
-// sl, sl + 4, ... in order, and the four slice sums are added in a fixed order, so the
-// result does not depend on the launch.
-constexpr int RED_T = 64, RED_S = 4;
+// workgroup takes 64 targets with eight threads each: thread slice sl sums chunks
+// sl, sl + 8, ... in order (four chunks' loads issued before their adds, so that a
+// thread has twelve loads in flight), and the eight slice sums are added in a fixed
+// order, so the result does not depend on the launch.
+constexpr int RED_T = 64, RED_S = 8;
 __global__ __launch_bounds__(RED_T * RED_S) void reduce_kernel(int64_t n_t, int32_t n_chunks,
                                                               const double* __restrict__ partial,
                                                               int accumulate, double* out, int64_t out_stride,
@@ -178,7 +179,21 @@ __global__ __launch_bounds__(RED_T * RED_S) void reduce_kernel(int64_t n_t, int3
     const int64_t i = (int64_t)blockIdx.x * RED_T + tx;
     double v[3] = {0.0, 0.0, 0.0};
     if (i < n_t) {
-        for (int k = sl; k < n_chunks; k += RED_S) {
+        int k = sl;
+        for (; k + 3 * RED_S < n_chunks; k += 4 * RED_S) {
+            double a[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double* p = partial + (int64_t)(k + u * RED_S) * 3 * n_t;
+                a[u][0] = p[i];
+                a[u][1] = p[n_t + i];
+                a[u][2] = p[2 * n_t + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                for (int c = 0; c < 3; ++c) v[c] += a[u][c];
+        }
+        for (; k < n_chunks; k += RED_S) {
             const double* p = partial + (int64_t)k * 3 * n_t;
             v[0] += p[i];
             v[1] += p[n_t + i];

@@ -337,52 +337,76 @@ def mobility_solve(xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1
     return out, res.value, it.value
 
 
+class ParticleGeometry:
+    """The surfaces of a particle solve packed on the device once: the particles'
+    points, outward normals and weights concatenated as planes (particle p at
+    offsets[p]..offsets[p + 1]), their centres, and the periphery's arrays (or none).
+
+    particles: list of (xyz (3, M), outward normals (3, M), weights (M,), centre (3,));
+    periphery: (xyz, outward normals, weights) or None for an unbounded fluid.  Arrays
+    may be numpy or torch."""
+
+    def __init__(self, particles, periphery=None):
+        import numpy as np
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def d(a):
+            if isinstance(a, torch.Tensor):
+                return a.to(device=dev, dtype=torch.float64).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+        def host(a):
+            return a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a, np.float64)
+
+        self.device = dev
+        self.n_part = len(particles)
+        sizes = [host(pt[0]).shape[1] for pt in particles]
+        self.offsets = (ctypes.c_int64 * (self.n_part + 1))(
+            *np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+        self.yp = d(np.concatenate([host(pt[0]) for pt in particles], axis=1))
+        self.np = d(np.concatenate([host(pt[1]) for pt in particles], axis=1))
+        self.wp = d(np.concatenate([host(pt[2]) for pt in particles]))
+        self.centres = d(np.stack([host(pt[3]) for pt in particles], axis=1))
+        if periphery is None:
+            self.m0, self.y0, self.n0, self.w0 = 0, None, None, None
+        else:
+            self.y0, self.n0, self.w0 = (d(a) for a in periphery)
+            self.m0 = self.y0.shape[1]
+        self.ms = self.m0 + int(sum(sizes))
+
+
 def particle_solve(particles, force, torque, periphery=None, mu=1.0, iters=40, mixed=False,
                    near_r=0.0, eager=False, stream=None):
     """Mobility of rigid particles in a fixed periphery (second-kind boundary integrals).
 
-    particles: list of (xyz (3, M), outward normals (3, M), weights (M,), centre (3,));
-    periphery: (xyz, outward normals, weights) or None for an unbounded fluid;
-    force, torque: (3, n_particles).  Arrays may be numpy or torch (copied to the
-    device).  eager: launch each iteration's kernels one by one instead of replaying a
-    captured graph.  Returns (U (3, n_p), Omega (3, n_p), q (3, M_s) device tensors,
-    residual, iterations)."""
+    particles: a ParticleGeometry, or the list it is made from (with periphery:
+    (xyz, outward normals, weights) or None for an unbounded fluid; ignored with a
+    ParticleGeometry); force, torque: (3, n_particles), numpy or torch (copied to the
+    device unless they are float64 device tensors already).  eager: launch each
+    iteration's kernels one by one instead of replaying a captured graph.  Returns
+    (U (3, n_p), Omega (3, n_p), q (3, M_s) device tensors, residual, iterations)."""
     import numpy as np
-    dev = torch.device("cuda", torch.cuda.current_device())
+    g = particles if isinstance(particles, ParticleGeometry) else ParticleGeometry(particles, periphery)
+    dev = g.device
 
     def d(a):
         if isinstance(a, torch.Tensor):
             return a.to(device=dev, dtype=torch.float64).contiguous()
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
 
-    def host(a):
-        return a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a, np.float64)
-
-    n_p = len(particles)
-    sizes = [host(pt[0]).shape[1] for pt in particles]
-    offs = (ctypes.c_int64 * (n_p + 1))(*np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
-    yp = d(np.concatenate([host(pt[0]) for pt in particles], axis=1))
-    npn = d(np.concatenate([host(pt[1]) for pt in particles], axis=1))
-    wp = d(np.concatenate([host(pt[2]) for pt in particles]))
-    X = d(np.stack([host(pt[3]) for pt in particles], axis=1))
+    n_p = g.n_part
     F, L = d(force).reshape(3, n_p), d(torque).reshape(3, n_p)
-    if periphery is None:
-        m0, y0, n0, w0 = 0, None, None, None
-    else:
-        y0, n0, w0 = (d(a) for a in periphery)
-        m0 = y0.shape[1]
-    ms = m0 + int(sum(sizes))
     U = torch.empty((3, n_p), dtype=torch.float64, device=dev)
     Om = torch.empty_like(U)
-    q = torch.empty((3, ms), dtype=torch.float64, device=dev)
+    q = torch.empty((3, g.ms), dtype=torch.float64, device=dev)
     res = ctypes.c_double(0.0)
     it = ctypes.c_int32(0)
     nz = lambda t: None if t is None else _ptr(t)
-    _check(_lib.stokes_particle_solve(m0, nz(y0), nz(n0), nz(w0), n_p, offs, _ptr(yp), _ptr(npn),
-                                      _ptr(wp), _ptr(X), _ptr(F), _ptr(L), float(mu), float(near_r),
-                                      int(iters), (PREC_MIXED if mixed else PREC_FP64) | (EAGER if eager else 0),
-                                      _ptr(U),
-                                      _ptr(Om), _ptr(q), ctypes.byref(res), ctypes.byref(it),
+    _check(_lib.stokes_particle_solve(g.m0, nz(g.y0), nz(g.n0), nz(g.w0), n_p, g.offsets, _ptr(g.yp),
+                                      _ptr(g.np), _ptr(g.wp), _ptr(g.centres), _ptr(F), _ptr(L), float(mu),
+                                      float(near_r), int(iters),
+                                      (PREC_MIXED if mixed else PREC_FP64) | (EAGER if eager else 0),
+                                      _ptr(U), _ptr(Om), _ptr(q), ctypes.byref(res), ctypes.byref(it),
                                       _stream(stream)))
     return U, Om, q, res.value, it.value
 
