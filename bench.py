@@ -29,6 +29,7 @@ import numpy as np
 
 METRIC = "Gpair-interactions/s and %VALU peak (mixed vs FP64); p50/p99 solve latency"
 FLOPS_PER_PAIR_SL = 34       # Stokeslet + doublet, counted (add/sub/mul 1, FMA 2, rsqrt 1)
+FLOPS_PER_PAIR_DL = 33       # stresslet with the on-surface subtraction, counted the same way
 PEAK_FP32 = 157.3            # TFLOP/s: published FP32 vector peak, 256 CU x 128 lanes x 2 x 2.4 GHz
 PEAK_FP64 = 78.6             # TFLOP/s: published FP64 vector peak
 NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go FP64
@@ -138,7 +139,10 @@ def load_config(name):
 
 def config_run(S, torch, name, steps, warmup, log_fn):
     """Time the single layer (and, when the config has a sphere, the double layer) to all
-    targets, for both precisions; report Gpair/s per sum and the mixed-vs-FP64 error."""
+    targets, for both precisions; report per sum the whole call (set-up, pair kernel,
+    chunk reduction) and the pair kernel alone, in Gpair/s and as a fraction of the
+    vector peak of the kernel's precision at the counted flops per pair, and the
+    mixed-vs-FP64 error."""
     c = load_config(name)
     fs = c["fibers"]
     dev = torch.device("cuda:0")
@@ -189,8 +193,24 @@ def config_run(S, torch, name, steps, warmup, log_fn):
                 run_sum(which, mixed)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / steps
+            # the pair kernel alone (the library's HIP events around each launch), in a
+            # second timed pass so that the events do not touch the whole-call time
+            S.profile_enable(True)
+            S.profile_read()
+            for _ in range(steps):
+                run_sum(which, mixed)
+            torch.cuda.synchronize()
+            kms, nk = S.profile_read()
+            S.profile_enable(False)
+            kt = kms / max(nk, 1) / 1e3
+            fpp = FLOPS_PER_PAIR_SL if which == "sl" else FLOPS_PER_PAIR_DL
+            peak = PEAK_FP32 if mixed else PEAK_FP64
             res[tag][which] = {"ms": round(dt * 1e3, 4),
-                               "gpair_per_s": round(pairs[which] / dt / 1e9, 1)}
+                               "gpair_per_s": round(pairs[which] / dt / 1e9, 1),
+                               "frac_of_peak": round(pairs[which] * fpp / dt / 1e12 / peak, 3),
+                               "kernel_ms": round(kt * 1e3, 4),
+                               "kernel_gpair_per_s": round(pairs[which] / kt / 1e9, 1),
+                               "kernel_frac_of_peak": round(pairs[which] * fpp / kt / 1e12 / peak, 3)}
         run_sum("sl", mixed)
         if sph is not None:
             run_sum("dl", mixed)

@@ -28,6 +28,8 @@ constexpr int64_t TARGET_BLOCKS = 65536;
 // (less partial-sum memory per request).
 constexpr int64_t TARGET_BLOCKS_SLOT = 4096;
 constexpr int MIN_TILES_PER_CHUNK = 8;
+// The double layer's (a pair costs more than a single-layer pair, so shorter chunks).
+constexpr int MIN_TILES_PER_CHUNK_DL = 4;
 constexpr int64_t SMALL_GRID = 8192;
 
 // Bump allocator over a workspace buffer (256-byte aligned slices).
@@ -60,9 +62,10 @@ struct Partition {
 };
 
 // min_tiles_small: least source tiles per chunk when there are fewer than 64
-// target blocks (a problem too small to fill the chip with target blocks alone).
+// target blocks (a problem too small to fill the chip with target blocks alone);
+// min_tiles_large: the same with 64 target blocks or more.
 inline Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_blocks = TARGET_BLOCKS,
-                                int min_tiles_small = 1) {
+                                int min_tiles_small = 1, int min_tiles_large = MIN_TILES_PER_CHUNK) {
     Partition p{};
     p.R = R;
     p.n_t = n_t;
@@ -80,7 +83,7 @@ inline Partition make_partition(int64_t n_t, int64_t n_s, int R, int64_t target_
     if (p.n_tblocks < 64) target_blocks = std::min<int64_t>(target_blocks, SMALL_GRID);
     int64_t ch = (target_blocks + p.n_tblocks - 1) / p.n_tblocks;
     // few target blocks (a small, latency-bound problem): shorter chunks
-    const int64_t min_tiles = p.n_tblocks >= 64 ? MIN_TILES_PER_CHUNK : min_tiles_small;
+    const int64_t min_tiles = p.n_tblocks >= 64 ? min_tiles_large : min_tiles_small;
     ch = std::min<int64_t>(ch, std::max<int64_t>(1, p.n_tiles / min_tiles));
     ch = std::max<int64_t>(1, std::min<int64_t>(ch, p.n_tiles));
     p.tiles_per_chunk = (int32_t)((p.n_tiles + ch - 1) / ch);

@@ -43,88 +43,80 @@ namespace stokes {
 
 // ---- preparation kernels -------------------------------------------------------
 
-// Bounding volumes of each tile, 32 lanes per tile (tile_prep_half).  near_r: extra
-// reach for the mixed path; the per-source near radius is max(near_r, near_fac *
-// L_fiber) when flen/sfib are given.  band < 0 (mixed double layer): each tile's
-// tangent band from the normals nrm.  Launch with TILE_PREP_BLOCK threads per block.
+// Tile bounds take 32 lanes per tile (tile_prep_half), TILE_PREP_BLOCK threads per block.
+// near_r: extra reach for the mixed path; the per-source near radius is max(near_r,
+// near_fac * L_fiber) when flen/sfib are given.  band < 0 (mixed double layer): each
+// tile's tangent band from the normals nrm.
 constexpr int TILE_PREP_BLOCK = 256;
-__global__ __launch_bounds__(TILE_PREP_BLOCK) void tile_prep_kernel(
-        int64_t n_s, const double* __restrict__ sx, int32_t n_tiles, double near_r, double near_fac,
-        const int32_t* __restrict__ sfib, int32_t n_fib, const double* __restrict__ flen, Tile* tiles,
-        double band, const double* __restrict__ nrm) {
-    const int t = (blockIdx.x * TILE_PREP_BLOCK + threadIdx.x) / 32;
-    if (t < n_tiles)   // whole half-waves: n_tiles bounds them together
-        tile_prep_half(t, threadIdx.x & 31, n_s, sx, near_r, near_fac, sfib, n_fib, flen, tiles, band, nrm);
-}
 static inline unsigned tile_prep_blocks(int64_t n_tiles) {
     return (unsigned)((n_tiles * 32 + TILE_PREP_BLOCK - 1) / TILE_PREP_BLOCK);
 }
 
-__global__ void sl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
-                                   const double* __restrict__ f, const double* __restrict__ w,
-                                   const int32_t* __restrict__ sfib, int32_t n_fib,
-                                   const double* __restrict__ flen, double pref, double eps,
-                                   int doublet, double near_r, const Tile* __restrict__ tiles,
-                                   SrcSL64* s64, SrcSL32* s32, float* near_t) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n_s)
-        sl_src_prep_one(j, n_s, sx, f, w, sfib, n_fib, flen, pref, eps, doublet, near_r, tiles,
-                        s64, s32, near_t);
-}
+// The set-up of a sum in one launch.  Blocks below tile_blocks take whole tiles, a
+// half-wave each: tile_prep_half, then lane l packs the tile's source t TILE + l
+// against the tile's FP64 origin (single layer, or double layer when DL).  The other
+// blocks write the self-exclusion range of target i (n_t = 0: none).
+struct PrepArgs {
+    int64_t n_s;
+    const double* sx;
+    int32_t n_tiles;
+    unsigned tile_blocks;
+    double near_r, near_fac, band;       // tile_prep_half
+    const int32_t* sfib;
+    int32_t n_fib;
+    const double* flen;
+    const double* nrm;                   // double layer: normals (also the band's)
+    Tile* tiles;
+    const double* f;                     // single layer: forces; double layer: density
+    const double* w;
+    double pref, eps, src_near_r;        // single layer
+    int doublet;
+    const int32_t* sid;                  // double layer: surface ids or null
+    void* s64;
+    void* s32;
+    float* near_t;
+    int64_t n_t;                         // self exclusion
+    const int64_t* tself;
+    int identity;
+    int2* excl;
+    unsigned long long* counters;
+};
 
-__global__ void dl_src_prep_kernel(int64_t n_s, const double* __restrict__ sx,
-                                   const double* __restrict__ nrm, const double* __restrict__ w,
-                                   const double* __restrict__ q, const int32_t* __restrict__ sid,
-                                   const Tile* __restrict__ tiles, SrcDL64* s64, SrcDL32* s32) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_s) return;
-    const double k = 3.0 / (4.0 * PI_D) * w[j];
-    SrcDL64 s;
-    s.x = sx[j];
-    s.y = sx[n_s + j];
-    s.z = sx[2 * n_s + j];
-    s.qx = q[j];
-    s.qy = q[n_s + j];
-    s.qz = q[2 * n_s + j];
-    s.nx = k * nrm[j];
-    s.ny = k * nrm[n_s + j];
-    s.nz = k * nrm[2 * n_s + j];
-    s.pad0 = sid ? (double)sid[j] : 0.0;   // surface id (multi-surface sums)
-    s.pad1 = s.pad2 = 0.0;
-    s64[j] = s;
-    if (s32) {
-        const Tile& T = tiles[j / TILE];
-        SrcDL32 h;
-        h.x = (float)(s.x - T.ox);
-        h.y = (float)(s.y - T.oy);
-        h.z = (float)(s.z - T.oz);
-        h.qx = (float)s.qx;
-        h.qy = (float)s.qy;
-        h.qz = (float)s.qz;
-        h.nx = (float)s.nx;
-        h.ny = (float)s.ny;
-        h.nz = (float)s.nz;
-        h.pad0 = (float)s.pad0;
-        h.pad1 = h.pad2 = 0.0f;
-        s32[j] = h;
+template <bool DL>
+__global__ __launch_bounds__(TILE_PREP_BLOCK) void prep_kernel(PrepArgs p) {
+    if (blockIdx.x < p.tile_blocks) {
+        const int t = (int)((blockIdx.x * TILE_PREP_BLOCK + threadIdx.x) / 32);
+        const int l = threadIdx.x & 31;
+        if (t >= p.n_tiles) return;   // whole half-waves
+        const Tile T = tile_prep_half(t, l, p.n_s, p.sx, p.near_r, p.near_fac, p.sfib, p.n_fib, p.flen,
+                                      p.tiles, p.band, p.nrm);
+        const int64_t j = (int64_t)t * TILE + l;
+        if (j >= p.n_s) return;
+        if (DL)
+            dl_src_pack(j, p.n_s, p.sx, p.nrm, p.w, p.f, p.sid, T.ox, T.oy, T.oz, static_cast<SrcDL64*>(p.s64),
+                        static_cast<SrcDL32*>(p.s32));
+        else
+            sl_src_pack(j, p.n_s, p.sx, p.f, p.w, p.sfib, p.n_fib, p.flen, p.pref, p.eps, p.doublet,
+                        p.src_near_r, T.ox, T.oy, T.oz, static_cast<SrcSL64*>(p.s64),
+                        static_cast<SrcSL32*>(p.s32), p.near_t);
+        return;
     }
-}
-
-// Excluded range of a target from a self index (self-pair or on-surface point).
-__global__ void excl_self_kernel(int64_t n_t, const int64_t* __restrict__ tself, int identity,
-                                 int64_t n_s, int2* excl, unsigned long long* counters) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)(blockIdx.x - p.tile_blocks) * TILE_PREP_BLOCK + threadIdx.x;
     unsigned long long cnt = 0;
-    if (i < n_t) {
-        int64_t s = tself ? tself[i] : (identity ? i : -1);
+    if (i < p.n_t) {
+        const int64_t s = p.tself ? p.tself[i] : (p.identity ? i : -1);
         int2 e = make_int2(0, 0);
-        if (s >= 0 && s < n_s) {
+        if (s >= 0 && s < p.n_s) {
             e = make_int2((int)s, (int)s + 1);
             cnt = 1;
         }
-        excl[i] = e;
+        p.excl[i] = e;
     }
-    if (counters) wave_count(counters + 2, cnt);
+    if (p.counters) wave_count(p.counters + 2, cnt);
+}
+
+static unsigned prep_grid(const PrepArgs& p) {
+    return p.tile_blocks + (unsigned)((p.n_t + TILE_PREP_BLOCK - 1) / TILE_PREP_BLOCK);
 }
 
 __global__ void fill_int2_kernel(int2* p, int64_t n, int2 v) {
@@ -343,19 +335,41 @@ static int fiber_bounds_launch(int64_t n_s, const int32_t* sfib, int32_t n_fib, 
     return STOKES_OK;
 }
 
+// self_excl: the exclusion ranges come from self indices (tself, or the identity) and
+// are written by the set-up launch; otherwise excl was made before (or is null).
 static int sl_core(const SLProblem& p, const Partition& P, const SumScratch& S, const int2* excl,
-                   unsigned long long* counters, hipStream_t st) {
+                   bool self_excl, const int64_t* tself, int identity, unsigned long long* counters,
+                   hipStream_t st) {
     if (P.n_chunks > 0) {
-        const double pref = 1.0 / (8.0 * PI_D * p.mu);
-        hipLaunchKernelGGL(tile_prep_kernel, dim3(tile_prep_blocks(P.n_tiles)), dim3(TILE_PREP_BLOCK), 0, st,
-                           p.n_s, p.sxyz, P.n_tiles, p.mixed ? std::max(p.near_r, 0.0) : 0.0,
-                           p.mixed ? 2.0 * p.eps : 0.0, p.sfib, p.n_fib, p.flen, S.tiles, 0.0,
-                           (const double*)nullptr);
-        hipLaunchKernelGGL(sl_src_prep_kernel, dim3(nblk(p.n_s)), dim3(256), 0, st, p.n_s, p.sxyz,
-                           p.force, p.weight, p.sfib, p.n_fib, p.flen, pref, p.eps,
-                           p.doublet ? 1 : 0, std::max(p.near_r, 0.0), S.tiles,
-                           static_cast<SrcSL64*>(S.s64),
-                           p.mixed ? static_cast<SrcSL32*>(S.s32) : nullptr, S.near_t);
+        PrepArgs q{};
+        q.n_s = p.n_s;
+        q.sx = p.sxyz;
+        q.n_tiles = P.n_tiles;
+        q.tile_blocks = tile_prep_blocks(P.n_tiles);
+        q.near_r = p.mixed ? std::max(p.near_r, 0.0) : 0.0;
+        q.near_fac = p.mixed ? 2.0 * p.eps : 0.0;
+        q.band = 0.0;
+        q.sfib = p.sfib;
+        q.n_fib = p.n_fib;
+        q.flen = p.flen;
+        q.tiles = S.tiles;
+        q.f = p.force;
+        q.w = p.weight;
+        q.pref = 1.0 / (8.0 * PI_D * p.mu);
+        q.eps = p.eps;
+        q.src_near_r = std::max(p.near_r, 0.0);
+        q.doublet = p.doublet ? 1 : 0;
+        q.s64 = S.s64;
+        q.s32 = p.mixed ? S.s32 : nullptr;
+        q.near_t = S.near_t;
+        if (self_excl) {
+            q.n_t = p.n_t;
+            q.tself = tself;
+            q.identity = identity;
+            q.excl = S.excl;
+            q.counters = counters;
+        }
+        hipLaunchKernelGGL(prep_kernel<false>, dim3(prep_grid(q)), dim3(TILE_PREP_BLOCK), 0, st, q);
         SumArgs a{};
         a.tx = p.txyz;
         a.t_stride = p.t_stride;
@@ -574,12 +588,9 @@ static int sl_run(int64_t n_src, const double* src_xyz, const double* src_force,
     unsigned long long* counters = diag ? S.counters : nullptr;
     if (counters) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, counters, 4);
     const int2* excl = nullptr;
-    if (self_mode) {
-        if (trg_self || same) {
-            hipLaunchKernelGGL(excl_self_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, trg_self,
-                               same ? 1 : 0, n_src, S.excl, counters);
-            excl = S.excl;
-        }
+    const bool self_excl = self_mode && (trg_self || same);   // made in sl_core's set-up launch
+    if (self_excl) {
+        excl = S.excl;
     } else if (fiber_mode && n_src > 0) {
         if ((rc = fiber_bounds_launch(n_src, src_fiber, n_fib, S.fbounds, st))) return rc;
         const int32_t* tf = trg_fiber ? trg_fiber : src_fiber;
@@ -606,7 +617,7 @@ static int sl_run(int64_t n_src, const double* src_xyz, const double* src_force,
     p.doublet = !(flags & STOKES_NO_DOUBLET);
     p.accumulate = flags & STOKES_ACCUMULATE;
     p.u = u_out;
-    if ((rc = sl_core(p, P, S, excl, counters, st))) return rc;
+    if ((rc = sl_core(p, P, S, excl, self_excl, trg_self, same ? 1 : 0, counters, st))) return rc;
     if (diag) return finish_diag(ws, counters, st, n_t, n_src, diag);
     return STOKES_OK;
 }
@@ -679,7 +690,7 @@ static int dl_run(int64_t n_src, const double* src_xyz, const double* src_normal
     const bool mixed = flags & STOKES_PREC_MIXED;
     const bool sub = !(flags & STOKES_ONSURF_RAW);
     const double nr = near_r > 0.0 ? near_r : 0.02;
-    const Partition P = make_partition(n_t, n_src, mixed ? R_DL32 : R_DL64);
+    const Partition P = make_partition(n_t, n_src, mixed ? R_DL32 : R_DL64, TARGET_BLOCKS, 1, MIN_TILES_PER_CHUNK_DL);
     Workspace* ws = nullptr;
     int rc = workspace_get(st, sum_scratch_bytes(n_src, n_t, 0, sizeof(SrcDL64),
                                                  mixed ? sizeof(SrcDL32) : 0, P.n_chunks), &ws);
@@ -701,17 +712,31 @@ static int dl_run(int64_t n_src, const double* src_xyz, const double* src_normal
     }
     unsigned long long* counters = diag ? S.counters : nullptr;
     if (counters) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, counters, 4);
-    hipLaunchKernelGGL(excl_self_kernel, dim3(nblk(n_t)), dim3(256), 0, st, n_t, trg_self,
-                       same ? 1 : 0, n_src, S.excl, counters);
     const double* tx = same ? src_xyz : trg_xyz;
     const int64_t ts = same ? n_src : n_t;
+    // tiles, packs and exclusion ranges in one launch (tiles only when there are sources)
+    PrepArgs q{};
+    q.n_s = n_src;
+    q.sx = src_xyz;
+    q.n_tiles = P.n_chunks > 0 ? P.n_tiles : 0;
+    q.tile_blocks = P.n_chunks > 0 ? tile_prep_blocks(P.n_tiles) : 0;
+    q.near_r = mixed ? nr : 0.0;
+    q.near_fac = 0.0;
+    q.band = mixed ? -1.0 : 0.0;
+    q.nrm = src_normal;
+    q.tiles = S.tiles;
+    q.f = src_q;
+    q.w = src_weight;
+    q.sid = src_sid;
+    q.s64 = S.s64;
+    q.s32 = mixed ? S.s32 : nullptr;
+    q.n_t = n_t;
+    q.tself = trg_self;
+    q.identity = same ? 1 : 0;
+    q.excl = S.excl;
+    q.counters = counters;
+    hipLaunchKernelGGL(prep_kernel<true>, dim3(prep_grid(q)), dim3(TILE_PREP_BLOCK), 0, st, q);
     if (P.n_chunks > 0) {
-        hipLaunchKernelGGL(tile_prep_kernel, dim3(tile_prep_blocks(P.n_tiles)), dim3(TILE_PREP_BLOCK), 0, st,
-                           n_src, src_xyz, P.n_tiles, mixed ? nr : 0.0, 0.0, (const int32_t*)nullptr, 0,
-                           (const double*)nullptr, S.tiles, mixed ? -1.0 : 0.0, src_normal);
-        hipLaunchKernelGGL(dl_src_prep_kernel, dim3(nblk(n_src)), dim3(256), 0, st, n_src, src_xyz,
-                           src_normal, src_weight, src_q, src_sid, S.tiles, static_cast<SrcDL64*>(S.s64),
-                           mixed ? static_cast<SrcDL32*>(S.s32) : nullptr);
         SumArgs a{};
         a.tx = tx;
         a.t_stride = ts;
@@ -793,7 +818,7 @@ int DLPlan::init(int64_t n_src, const double* src_xyz, const double* src_normal,
     txyz_ = trg_xyz;
     const double nr = near_r > 0.0 ? near_r : 0.02;
     near2_ = (float)(nr * nr);
-    P_ = make_partition(n_t_, n_s_, mixed_ ? R_DL32 : R_DL64);
+    P_ = make_partition(n_t_, n_s_, mixed_ ? R_DL32 : R_DL64, TARGET_BLOCKS, 1, MIN_TILES_PER_CHUNK_DL);
     const SumLayout L = sum_layout(n_s_, n_t_, 0, sizeof(Tile), sizeof(SrcDL64), mixed_ ? sizeof(SrcDL32) : 0,
                                    P_.n_chunks);
     STOKES_HIP(hipMalloc(&mem_, L.bytes));
@@ -803,16 +828,29 @@ int DLPlan::init(int64_t n_src, const double* src_xyz, const double* src_normal,
     s32_ = mixed_ ? reinterpret_cast<SrcDL32*>(b + L.s32) : nullptr;
     excl_ = reinterpret_cast<int2*>(b + L.excl);
     partial_ = reinterpret_cast<double*>(b + L.partial);
-    hipLaunchKernelGGL(excl_self_kernel, dim3(nblk(n_t_)), dim3(256), 0, st, n_t_, trg_self, 0, n_s_, excl_,
-                       (unsigned long long*)nullptr);
-    hipLaunchKernelGGL(tile_prep_kernel, dim3(tile_prep_blocks(P_.n_tiles)), dim3(TILE_PREP_BLOCK), 0, st, n_s_,
-                       src_xyz, P_.n_tiles, mixed_ ? nr : 0.0, 0.0, (const int32_t*)nullptr, 0,
-                       (const double*)nullptr, tiles_, mixed_ ? -1.0 : 0.0, src_normal);
-    // positions, weighted normals and surface ids now; the density per evaluation (a
-    // zero density until then: the pack kernel reads q, so pass the normals as a stand-in
-    // and overwrite them in every evaluation)
-    hipLaunchKernelGGL(dl_src_prep_kernel, dim3(nblk(n_s_)), dim3(256), 0, st, n_s_, src_xyz, src_normal,
-                       src_weight, src_normal, src_sid, (const Tile*)tiles_, s64_, s32_);
+    // tiles, exclusion ranges, and positions, weighted normals and surface ids now; the
+    // density per evaluation (the pack reads a density, so the normals stand in for it
+    // until every evaluation overwrites them)
+    PrepArgs q{};
+    q.n_s = n_s_;
+    q.sx = src_xyz;
+    q.n_tiles = P_.n_tiles;
+    q.tile_blocks = tile_prep_blocks(P_.n_tiles);
+    q.near_r = mixed_ ? nr : 0.0;
+    q.near_fac = 0.0;
+    q.band = mixed_ ? -1.0 : 0.0;
+    q.nrm = src_normal;
+    q.tiles = tiles_;
+    q.f = src_normal;
+    q.w = src_weight;
+    q.sid = src_sid;
+    q.s64 = s64_;
+    q.s32 = s32_;
+    q.n_t = n_t_;
+    q.tself = trg_self;
+    q.identity = 0;
+    q.excl = excl_;
+    hipLaunchKernelGGL(prep_kernel<true>, dim3(prep_grid(q)), dim3(TILE_PREP_BLOCK), 0, st, q);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }

@@ -868,8 +868,9 @@ __device__ __forceinline__ double half_max(double v) {
 // same Tile (every quantity is a per-source expression of tile_prep_one followed by a
 // min or max, which do not depend on the order), in five butterflies instead of three
 // passes over the sources by one thread.  band < 0: the double layer's tangent band,
-// dl_band_radius of the tile's sources with normals nrm.  Call with whole half-waves.
-__device__ __forceinline__ void tile_prep_half(int t, int l, int64_t n_s, const double* __restrict__ sx,
+// dl_band_radius of the tile's sources with normals nrm.  Call with whole half-waves;
+// every lane returns the tile.
+__device__ __forceinline__ Tile tile_prep_half(int t, int l, int64_t n_s, const double* __restrict__ sx,
                                                double near_r, double near_fac,
                                                const int32_t* __restrict__ sfib, int32_t n_fib,
                                                const double* __restrict__ flen, Tile* tiles, double band,
@@ -937,16 +938,18 @@ __device__ __forceinline__ void tile_prep_half(int t, int l, int64_t n_s, const 
     T.j0 = j0;
     T.j1 = j1;
     if (l == 0) tiles[t] = T;
+    return T;   // the same in every lane of the half-wave
 }
 
-__device__ __forceinline__ void sl_src_prep_one(int64_t j, int64_t n_s, const double* __restrict__ sx,
-                                                const double* __restrict__ f,
-                                                const double* __restrict__ w,
-                                                const int32_t* __restrict__ sfib, int32_t n_fib,
-                                                const double* __restrict__ flen, double pref,
-                                                double eps, int doublet, double near_r,
-                                                const Tile* __restrict__ tiles, SrcSL64* s64,
-                                                SrcSL32* s32, float* near_t) {
+// Single-layer source j packed: s = pref w f, c = (eps L)^2 / 2 (0 without the
+// doublet); the FP32 pack holds its position relative to its tile's FP64 origin
+// (ox, oy, oz) and its near threshold.
+__device__ __forceinline__ void sl_src_pack(int64_t j, int64_t n_s, const double* __restrict__ sx,
+                                            const double* __restrict__ f, const double* __restrict__ w,
+                                            const int32_t* __restrict__ sfib, int32_t n_fib,
+                                            const double* __restrict__ flen, double pref, double eps,
+                                            int doublet, double near_r, double ox, double oy, double oz,
+                                            SrcSL64* s64, SrcSL32* s32, float* near_t) {
     double L = 1.0;
     if (flen) {
         const int fb = sfib ? sfib[j] : 0;
@@ -966,11 +969,10 @@ __device__ __forceinline__ void sl_src_prep_one(int64_t j, int64_t n_s, const do
     s.sz = pref * wj * f[2 * n_s + j];
     s64[j] = s;
     if (s32) {
-        const Tile& T = tiles[j / TILE];
         SrcSL32 h;
-        h.x = (float)(s.x - T.ox);
-        h.y = (float)(s.y - T.oy);
-        h.z = (float)(s.z - T.oz);
+        h.x = (float)(s.x - ox);
+        h.y = (float)(s.y - oy);
+        h.z = (float)(s.z - oz);
         h.c = (float)c;
         h.c3 = (float)(-3.0 * c);
         h.sx = (float)s.sx;
@@ -979,6 +981,63 @@ __device__ __forceinline__ void sl_src_prep_one(int64_t j, int64_t n_s, const do
         s32[j] = h;
         const double nr = fmax(near_r, 2.0 * a);
         near_t[j] = (float)(nr * nr);
+    }
+}
+
+// sl_src_pack with the origin read from the tile table (tiles made earlier).
+__device__ __forceinline__ void sl_src_prep_one(int64_t j, int64_t n_s, const double* __restrict__ sx,
+                                                const double* __restrict__ f,
+                                                const double* __restrict__ w,
+                                                const int32_t* __restrict__ sfib, int32_t n_fib,
+                                                const double* __restrict__ flen, double pref,
+                                                double eps, int doublet, double near_r,
+                                                const Tile* __restrict__ tiles, SrcSL64* s64,
+                                                SrcSL32* s32, float* near_t) {
+    double ox = 0.0, oy = 0.0, oz = 0.0;
+    if (s32) {
+        const Tile& T = tiles[j / TILE];
+        ox = T.ox;
+        oy = T.oy;
+        oz = T.oz;
+    }
+    sl_src_pack(j, n_s, sx, f, w, sfib, n_fib, flen, pref, eps, doublet, near_r, ox, oy, oz, s64, s32, near_t);
+}
+
+// Double-layer source j packed: position, density q, weighted normal (3/(4 pi)) w n and
+// the surface id (multi-surface sums; 0 otherwise); the FP32 pack holds its position
+// relative to its tile's FP64 origin (ox, oy, oz).
+__device__ __forceinline__ void dl_src_pack(int64_t j, int64_t n_s, const double* __restrict__ sx,
+                                            const double* __restrict__ nrm, const double* __restrict__ w,
+                                            const double* __restrict__ q, const int32_t* __restrict__ sid,
+                                            double ox, double oy, double oz, SrcDL64* s64, SrcDL32* s32) {
+    const double k = 3.0 / (4.0 * PI_D) * w[j];
+    SrcDL64 s;
+    s.x = sx[j];
+    s.y = sx[n_s + j];
+    s.z = sx[2 * n_s + j];
+    s.qx = q[j];
+    s.qy = q[n_s + j];
+    s.qz = q[2 * n_s + j];
+    s.nx = k * nrm[j];
+    s.ny = k * nrm[n_s + j];
+    s.nz = k * nrm[2 * n_s + j];
+    s.pad0 = sid ? (double)sid[j] : 0.0;
+    s.pad1 = s.pad2 = 0.0;
+    s64[j] = s;
+    if (s32) {
+        SrcDL32 h;
+        h.x = (float)(s.x - ox);
+        h.y = (float)(s.y - oy);
+        h.z = (float)(s.z - oz);
+        h.qx = (float)s.qx;
+        h.qy = (float)s.qy;
+        h.qz = (float)s.qz;
+        h.nx = (float)s.nx;
+        h.ny = (float)s.ny;
+        h.nz = (float)s.nz;
+        h.pad0 = (float)s.pad0;
+        h.pad1 = h.pad2 = 0.0f;
+        s32[j] = h;
     }
 }
 
