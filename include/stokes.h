@@ -453,6 +453,14 @@ typedef struct stokes_solve_req {   /* HOST pointers; copied by stokes_session_s
     uint64_t tag;                   /* returned in the stats */
     uint32_t flags;                 /* STOKES_NONLOCAL, STOKES_PRECOND_BLOCK (or 0) */
     double delta;                   /* K_delta regularisation (> 0 with STOKES_NONLOCAL) */
+    const stokes_far* far;          /* NULL (direct u_bar sums) or the treecode's parameters
+                                       for this request's u_bar sums (copied at submit).  Its
+                                       tree plan is built at admission from the request's
+                                       nodes and held outside the HBM budget until the
+                                       request finishes; the request then advances one
+                                       iteration per step with launches of its own after the
+                                       step's graph (paper section 3, "Matrix-vector products
+                                       and FMM"). */
 } stokes_solve_req;
 
 typedef struct stokes_solve_stats {

@@ -152,6 +152,16 @@ public:
         if (int rc = launch_red_ortho(slots)) return rc;
         return read_status();
     }
+    // step_external without reading the status rows back: only enqueued (after whatever
+    // the stream holds, e.g. the graph of the other slots' step).
+    template <class F>
+    int step_external_nowait(const std::vector<int>& slots, F&& sl) {
+        if (slots.empty()) return STOKES_OK;
+        if (int rc = launch_pre(slots)) return rc;
+        for (int q : slots)
+            if (int rc = sl(q)) return rc;
+        return launch_red_ortho(slots);
+    }
     // step_parts without reading the status rows back: the step is only enqueued.
     // copy_status_async then enqueues the copy of the status rows into `dst` (pinned
     // host memory of MAX_SLOTS * NSTAT doubles), valid once the stream reaches it; on

@@ -55,12 +55,6 @@ void fiberstep_release();
 // Frees the pinned tables, events and device tables that finished batched solves keep
 // for the next one (stokes_release_workspace).
 void batch_res_drain();
-// Double layer over several surfaces in one sum: src_sid gives each source's surface;
-// a target's own density is subtracted only from its own surface's sources (the
-// surface of its self source).  Always with the on-surface subtraction.
-int dl_eval_surfaces(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
-                     const double* src_q, const int32_t* src_sid, int64_t n_trg, const double* trg_xyz,
-                     const int64_t* trg_self, double near_r, uint32_t flags, double* u_out, hipStream_t st);
 
 // The input scan of STOKES_CHECK_INPUTS for a single-layer sum's sources (synchronous on
 // st): forces and weights finite, fiber ids in [0, n_fib) and non-decreasing, lengths
@@ -101,9 +95,11 @@ struct SrcDL32;
 // targets and their self indices), evaluated for many densities: the tiles, the
 // source packs and the exclusion ranges are made once, and an evaluation re-packs
 // only the density.  The geometry arrays (device) must stay alive and unchanged
-// while the plan is used; the plan owns its own device memory.  Each evaluation
-// gives the result of dl_eval_surfaces (src_sid given) or of stokes_dl_eval (src_sid
-// null, with the same near radius and flags), bit for bit.
+// while the plan is used; the plan owns its own device memory.  With surface ids
+// (src_sid) the sources are several surfaces, and a target's own density is subtracted
+// only from the sources of its own surface, the surface of its self source (always with
+// the on-surface subtraction; the MULTI kernels).  Without, an evaluation gives the
+// result of stokes_dl_eval with the same near radius and flags, bit for bit.
 class DLPlan {
 public:
     DLPlan() = default;

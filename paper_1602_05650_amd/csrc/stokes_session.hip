@@ -4,7 +4,9 @@
 // loop it (1) retires cancelled requests, (2) admits queued requests in FIFO
 // order while a slot is free and the request's device footprint fits the
 // session's HBM arena, (3) runs one GMRES iteration for every request in
-// flight with a single replay of the captured step graph, and (4) finalises
+// flight with a single replay of the captured step graph (requests whose u_bar
+// goes through a treecode plan run their iteration with launches of their own right
+// after it), and (4) finalises
 // the requests that used their iteration budget (or broke down), copies their
 // solutions to host memory and frees their slots.  Requests therefore join
 // and leave the batch between steps while the others keep iterating.
@@ -66,6 +68,9 @@ struct Request {
     int64_t N = 0;
     double eps = 0, mu = 0, delta = 0;
     uint32_t opts = 0;            // STOKES_NONLOCAL | STOKES_PRECOND_BLOCK
+    bool far = false;             // u_bar through a treecode plan (farp), built at admission
+    stokes_far farp{};
+    FarPlan* fplan = nullptr;
     uint64_t tag = 0;
     size_t bytes = 0;
     double* host = nullptr;       // pinned: xyz | tan | rhs | flen | result
@@ -114,6 +119,7 @@ namespace stokes {
 
 static void free_request(Request* r) {
     if (r->host) (void)hipHostFree(r->host);
+    delete r->fplan;
     delete r;
 }
 
@@ -131,6 +137,8 @@ static void finish(stokes_session* s, Request* r, int status) {
         s->arena.release(r->mem);
         r->mem = nullptr;
     }
+    delete r->fplan;   // no step still reads it: see the callers
+    r->fplan = nullptr;
 }
 
 // Single-layer items a request takes per step: its pair budget over the pairs
@@ -313,14 +321,19 @@ static void worker_main(stokes_session* s) {
         int rc = STOKES_OK;
         for (int q : admitted) {
             Request* r = slots[q];
-            rc = B.attach(q, r->mem, r->n_fib, r->npf, r->k, r->eps, r->mu, 0.0, r->opts, r->delta, r->xyz(),
-                          r->tan(), r->flen(), r->rhs());
+            rc = B.attach(q, r->mem, r->n_fib, r->npf, r->k, r->eps, r->mu, 0.0, r->far ? r->opts | OPT_FAR : r->opts,
+                          r->delta, r->xyz(), r->tan(), r->flen(), r->rhs());
+            if (!rc && r->far) {   // the tree plan of the request's nodes (synchronous)
+                r->fplan = new FarPlan();
+                rc = r->fplan->make(r->N, B.desc(q).xyz, r->farp, s->st);
+            }
             if (rc) break;
         }
         if (!rc) rc = B.start(admitted);   // synchronous: reads beta and the breakdown flag
         Pending cur;
         cur.buf = next_buf;
         std::vector<Batch::Part> parts;
+        std::vector<int> far_slots;   // treecode requests: a whole iteration each step
         std::vector<int> zero_rhs;
         if (!rc) {
             for (int q = 0; q < (int)slots.size(); ++q) {
@@ -337,10 +350,14 @@ static void worker_main(stokes_session* s) {
                     }
                 }
                 B.desc(q).j = r->j;
+                if (r->far) {
+                    far_slots.push_back(q);
+                    continue;
+                }
                 const int32_t n = B.desc(q).n_items_sl;
                 parts.push_back({q, r->sl_done, std::min(r->sl_quota, n - r->sl_done)});
             }
-            if (parts.empty() && zero_rhs.empty()) {
+            if (parts.empty() && far_slots.empty() && zero_rhs.empty()) {
                 // nothing left to step (every request in a slot has its solution queued):
                 // take in the pending step and go back to waiting for work
                 rc = complete_pending(s, pend, nullptr);
@@ -353,10 +370,27 @@ static void worker_main(stokes_session* s) {
                 continue;
             }
             rc = B.step_parts_nowait(parts);
+            // the treecode requests' iteration after the step's graph, on the same stream:
+            // z = M^{-1} v_j, u_bar through the tree into partial row 0, reduction,
+            // Gram-Schmidt and Givens (the own fiber excluded, as in the direct sum)
+            const uint32_t tflags = (s->cfg.flags & (STOKES_PREC_MIXED | STOKES_NO_DOUBLET)) | STOKES_EXCL_SAME_FIBER;
+            auto far_sum = [&](int q) {
+                const SlotDesc& d = B.desc(q);
+                const Request* r = slots[q];
+                return stokes_tree_sl_eval(r->fplan->t, d.z, d.wq, d.fib, d.n_fib, d.flen, r->mu, r->eps, 0.0,
+                                           tflags, d.partial, s->st);
+            };
+            if (!rc) rc = B.step_external_nowait(far_slots, far_sum);
         }
-        if (!rc && !parts.empty()) rc = B.copy_status_async(s->stat_buf[cur.buf]);
+        if (!rc && (!parts.empty() || !far_slots.empty())) rc = B.copy_status_async(s->stat_buf[cur.buf]);
         if (!rc) {
             std::vector<int> finishing = zero_rhs;
+            for (int q : far_slots) {
+                Request* r = slots[q];
+                cur.done.push_back({q, r->j});
+                r->j += 1;
+                if (r->j >= r->k) finishing.push_back(q);
+            }
             for (const Batch::Part& p : parts) {
                 Request* r = slots[p.slot];
                 r->sl_done += p.sl_count;
@@ -473,6 +507,7 @@ extern "C" int stokes_session_submit(stokes_session* s, const stokes_solve_req* 
         return fail(STOKES_E_INVAL, "stokes_session_submit: unknown request flag bits");
     if ((req->flags & STOKES_NONLOCAL) && (!(req->delta > 0.0) || !std::isfinite(req->delta)))
         return fail(STOKES_E_INVAL, "stokes_session_submit: delta must be finite and > 0 with STOKES_NONLOCAL");
+    if (int rc = check_far(req->far, "stokes_session_submit")) return rc;
     const size_t bytes =
         slot_plan(req->n_fib, req->nodes_per_fib, req->iters, mixed, req->flags).bytes;
     if (bytes > s->arena.capacity())
@@ -494,6 +529,10 @@ extern "C" int stokes_session_submit(stokes_session* s, const stokes_solve_req* 
     r->mu = req->mu;
     r->opts = req->flags;
     r->delta = req->delta;
+    if (req->far) {
+        r->far = true;
+        r->farp = *req->far;
+    }
     r->tag = req->tag;
     r->bytes = bytes;
     const size_t hb = sizeof(double) * (12 * N + r->n_fib);

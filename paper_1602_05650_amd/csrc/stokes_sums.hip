@@ -887,13 +887,4 @@ int DLPlan::eval(const double* src_q, double* u_out, bool accumulate, hipStream_
     return STOKES_OK;
 }
 
-// The double layer over several surfaces in one sum (see dl_fp64_wave's MULTI).
-int dl_eval_surfaces(int64_t n_src, const double* src_xyz, const double* src_normal, const double* src_weight,
-                     const double* src_q, const int32_t* src_sid, int64_t n_trg, const double* trg_xyz,
-                     const int64_t* trg_self, double near_r, uint32_t flags, double* u_out, hipStream_t st) {
-    if (!src_sid || (flags & STOKES_ONSURF_RAW))
-        return fail(STOKES_E_INVAL, "dl_eval_surfaces: needs surface ids and the on-surface subtraction");
-    return dl_run(n_src, src_xyz, src_normal, src_weight, src_q, src_sid, n_trg, trg_xyz, trg_self, near_r,
-                  flags, u_out, st, nullptr);
-}
 }  // namespace stokes

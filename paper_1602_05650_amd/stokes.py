@@ -54,7 +54,8 @@ class SolveReq(ctypes.Structure):
                 ("xyz", ctypes.c_void_p), ("tangent", ctypes.c_void_p),
                 ("fiber_len", ctypes.c_void_p), ("rhs", ctypes.c_void_p),
                 ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("iters", ctypes.c_int32),
-                ("tag", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("delta", ctypes.c_double)]
+                ("tag", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("delta", ctypes.c_double),
+                ("far", ctypes.c_void_p)]
 
 
 class Far(ctypes.Structure):
@@ -569,15 +570,20 @@ class Session:
         self._shapes = {}
 
     def submit(self, xyz, tangent, fiber_len, rhs, nodes_per_fib, eps, iters, mu=1.0, tag=0,
-               delta=None, precond="local"):
+               delta=None, precond="local", far=None):
+        """far = (degree, theta[, leaf_size]): the request's u_bar sums through a treecode
+        plan of its nodes (built at admission)."""
         import numpy as np
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xyz, tangent, fiber_len, rhs)]
         n = arrs[0].shape[1]
         opts, dl = _solve_opts(delta, precond)
+        farp = None
+        if far is not None:
+            farp = Far(int(far[0]), float(far[1]), int(far[2]) if len(far) > 2 else 0)
         req = SolveReq(int(arrs[2].shape[0]), int(nodes_per_fib),
                        arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
                        arrs[3].ctypes.data, float(eps), float(mu), int(iters), int(tag),
-                       opts, dl)
+                       opts, dl, ctypes.addressof(farp) if farp is not None else None)
         t = ctypes.c_uint64(0)
         _check(_lib.stokes_session_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         self._shapes[t.value] = n
