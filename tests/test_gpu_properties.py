@@ -133,3 +133,68 @@ def test_source_permutation_invariance(S, fibers, surface):
     up = S.dl_eval(dev(sph.xyz[:, pm]), dev(sph.normal[:, pm]), dev(sph.weight[pm]), dev(q[:, pm]),
                    trg_xyz=dev(trg), trg_self=dev(tself_p.astype(np.int64), torch.int64)).cpu().numpy()
     assert rel(up, u) <= 1e-13
+
+
+@pytest.mark.parametrize("mixed,tol", [(False, 1e-12), (True, 4e-6)])
+def test_single_layer_reciprocity_at_scale(S, mixed, tol):
+    """Reciprocity of the discrete operator (G and W symmetric and even in d; one fiber
+    length, so one doublet coefficient) on the confined workload's 32,768 fiber points,
+    self-pairs excluded: <g, A f> = <A g, f>.  Each sum's max-norm error e|A f|_inf
+    bounds the difference by e (|g|_1 |A f|_inf + |f|_1 |A g|_inf)."""
+    c = W.config1()
+    fs = c["fibers"]
+    assert np.all(fs.length == fs.length[0])
+    rng = np.random.default_rng(41)
+    f = rng.standard_normal((3, fs.n))
+    g = rng.standard_normal((3, fs.n))
+    Af, Ag = _sl(S, fs, f, mixed=mixed), _sl(S, fs, g, mixed=mixed)
+    lhs, rhs = np.sum(g * Af), np.sum(Ag * f)
+    bound = np.abs(g).sum() * np.abs(Af).max() + np.abs(f).sum() * np.abs(Ag).max()
+    assert abs(lhs - rhs) <= tol * bound
+
+
+def _divergence(field, x, h):
+    """Central-difference divergence at the columns of x, and its scale (the sum of the
+    |du_c/dx_c|), from one evaluation at the six shifted copies of x."""
+    n = x.shape[1]
+    pts = []
+    for c in range(3):
+        e = np.zeros((3, 1))
+        e[c] = h
+        pts += [x + e, x - e]
+    u = field(np.concatenate(pts, axis=1))
+    div, scale = np.zeros(n), np.zeros(n)
+    for c in range(3):
+        d = (u[c, (2 * c) * n:(2 * c + 1) * n] - u[c, (2 * c + 1) * n:(2 * c + 2) * n]) / (2 * h)
+        div += d
+        scale += np.abs(d)
+    return div, scale
+
+
+def test_divergence_free_at_scale(S):
+    """The single layer of the confined workload's 32,768 fiber points (all within
+    radius 4.92) and the double layer of its 6,144-point sphere (radius 5) are
+    divergence free away from their sources: at 96 points on spheres of radius 7 and 2.5
+    (FP64; central differences with h = 1e-3 are O((h / distance)^2), below 1e-6 here,
+    while a wrong sign or factor in either term leaves a divergence of the scale's order)."""
+    c = W.config1()
+    fs, sph = c["fibers"], c["sphere"]
+    rng = np.random.default_rng(43)
+    f = rng.standard_normal((3, fs.n))
+    q = rng.standard_normal((3, sph.n))
+
+    def on_sphere(n, r):
+        v = rng.standard_normal((3, n))
+        return r * v / np.linalg.norm(v, axis=0)
+
+    x_out = on_sphere(96, 7.0)
+    sl = lambda y: S.sl_eval(dev(fs.xyz), dev(f), src_fiber=dev(fs.fiber, torch.int32),
+                             fiber_len=dev(fs.length), eps=fs.eps, trg_xyz=dev(y), excl="none").cpu().numpy()
+    div, scale = _divergence(sl, x_out, 1e-3)
+    assert np.all(scale > 0) and np.all(np.abs(div) < 1e-5 * scale)
+    for r in (2.5, 7.5):
+        x = on_sphere(96, r)
+        dl = lambda y: S.dl_eval(dev(sph.xyz), dev(sph.normal), dev(sph.weight), dev(q),
+                                 trg_xyz=dev(y)).cpu().numpy()
+        div, scale = _divergence(dl, x, 1e-3)
+        assert np.all(scale > 0) and np.all(np.abs(div) < 1e-5 * scale)
