@@ -468,16 +468,18 @@ extern "C" int stokes_session_create(const stokes_session_cfg* cfg, stokes_sessi
         rc = s->arena.init((size_t)cfg->hbm_budget_bytes);
         if (rc) rc = fail(STOKES_E_NOMEM, std::string("stokes_session_create: HBM arena: ") + stokes_last_error());
     }
-    (void)hipSetDevice(cur);
     if (rc) {
         for (int b = 0; b < 2; ++b) {
             if (s->stat_ev[b]) (void)hipEventDestroy(s->stat_ev[b]);
             if (s->stat_buf[b]) (void)hipHostFree(s->stat_buf[b]);
         }
-        if (s->st) (void)hipStreamDestroy(s->st);
-        delete s;
+        hipStream_t st = s->st;
+        delete s;   // the batch waits for its stream before it releases its tables
+        if (st) (void)hipStreamDestroy(st);
+        (void)hipSetDevice(cur);
         return rc;
     }
+    (void)hipSetDevice(cur);
     s->worker = std::thread(worker_main, s);
     *out = s;
     return STOKES_OK;
