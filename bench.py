@@ -37,15 +37,15 @@ NEAR_R = 0.0                 # mixed path: pairs closer than two fiber radii go 
 # HBM traffic of one sl_mixed_kernel launch on this workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by the
 # factors that make a 256 MiB elementwise copy in the same run read and write
-# 256 MiB (FETCH x 1.99977, WRITE x 0.99999); see
+# 256 MiB (FETCH x 1.99977, WRITE x 1.00000); see
 # profiles/sl_mixed_spindle_262k_traffic.md.  Valid only for the kernel
 # sources with this digest: after any change the field reports null.
-TRAFFIC = {"digest": "1312510fda54f5df", "bytes": 542515900}
+TRAFFIC = {"digest": "fae4a9cbbb27fd32", "bytes": 542521081}
 # VALU flops per pair from rocprofv3 instruction counters of the same kernel sources
 # (64 x (2 FMA + MUL + ADD + TRANS) of the kernel's precision, per dispatch, over the
 # pairs of one launch); see profiles/sl_spindle_262k_valu_counters.md.  Combined with
 # the live kernel time they give the counter-based fraction of peak.
-VALU_FLOPS_PER_PAIR = {"digest": "1312510fda54f5df", "mixed": 34.70, "fp64": 42.25}
+VALU_FLOPS_PER_PAIR = {"digest": "fae4a9cbbb27fd32", "mixed": 34.51, "fp64": 42.25}
 KERNEL_SOURCES = ["paper_1602_05650_amd/csrc/sum_device.hpp",
                   "paper_1602_05650_amd/csrc/stokes_sums.hip",
                   "paper_1602_05650_amd/csrc/stokes_internal.hpp",

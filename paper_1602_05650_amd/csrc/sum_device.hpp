@@ -334,12 +334,17 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
         }
         return;
     }
+    // FP32 partial of two consecutive tiles, added to the Kahan pair after every second
+    // tile and after the chunk's last
+    float px[R], py[R], pz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
     for (int t = t0; t < t1; ++t) {
         const Tile T = as_const(a.tiles)[t];
         const int nsrc = T.j1 - T.j0;
         if ((int)threadIdx.x < 2 * nsrc) lds[threadIdx.x] = src4[2 * (int64_t)T.j0 + threadIdx.x];
         __syncthreads();
-        float xs[R], ys[R], zs[R], px[R], py[R], pz[R];
+        float xs[R], ys[R], zs[R];
         bool near_s = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -347,7 +352,6 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
             ys[r] = (float)(Y[r] - T.oy);
             zs[r] = (float)(Z[r] - T.oz);
             near_s |= fmaf(xs[r], xs[r], fmaf(ys[r], ys[r], zs[r] * zs[r])) <= T.reach2_f;
-            px[r] = py[r] = pz[r] = 0.0f;
         }
         // wave-uniform: the union of the lanes' exclusion ranges overlaps the tile
         bool checked = (xu.x < T.j1) & (xu.y > T.j0);
@@ -423,11 +427,14 @@ __device__ __forceinline__ void sl_mixed_wave(const SumArgs& a, int tb, int chun
             near_cnt[0][tid] += nnear;
             near_cnt[1][tid] += ncoin;
         }
+        if (((t - t0) & 1) || t == t1 - 1) {   // wave-uniform
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            kahan_add(Sx[r], Cx[r], px[r]);
-            kahan_add(Sy[r], Cy[r], py[r]);
-            kahan_add(Sz[r], Cz[r], pz[r]);
+            for (int r = 0; r < R; ++r) {
+                kahan_add(Sx[r], Cx[r], px[r]);
+                kahan_add(Sy[r], Cy[r], py[r]);
+                kahan_add(Sz[r], Cz[r], pz[r]);
+                px[r] = py[r] = pz[r] = 0.0f;
+            }
         }
         __syncthreads();
     }
