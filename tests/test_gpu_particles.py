@@ -51,9 +51,12 @@ def test_concentric_sphere_vs_oracle_and_closed_form(S, oracle_mod, mixed):
     U, Om, q = U.cpu().numpy(), Om.cpu().numpy(), q.cpu().numpy()
     sysm = oracle_mod.ParticleSystem(per, [part], MU)
     Ur, Omr, xr, h, m = oracle_mod.particle_solve(sysm, F, L, 40)
-    tol = 1e-10 if not mixed else 2e-5
+    print(f"concentric mixed={mixed}: U {rel(U[2], Ur[2]):.2e}, Omega {rel(Om[2], Omr[2]):.2e}, "
+          f"q {rel(q, xr[:, : sysm.Ms]):.2e}")
+    # mixed: the sums' 2e-6 bound (measured: U 1e-8, Omega 1e-9, q 1.3e-7)
+    tol = 1e-10 if not mixed else 2e-6
     assert rel(U[2], Ur[2]) <= tol and rel(Om[2], Omr[2]) <= tol
-    assert rel(q, xr[:, : sysm.Ms]) <= (1e-9 if not mixed else 1e-4)
+    assert rel(q, xr[:, : sysm.Ms]) <= (1e-9 if not mixed else 2e-6)
     lam = a / b
     gam = 6 * math.pi * MU * a * 4 * (1 - lam ** 5) / (4 - 9 * lam + 10 * lam ** 3 - 9 * lam ** 5 + 4 * lam ** 6)
     assert abs(U[2, 0] * gam - 1.0) < 6e-4                                  # eq. concentric-sphere
