@@ -350,12 +350,16 @@ int stokes_fiber_step(int32_t n_fib, int32_t nodes_per_fib, const double* xyz,
  * mu > 0; near_r: mixed double-layer sums only (see stokes_dl_eval);
  * iters 1..STOKES_MAX_ITERS; flags: STOKES_PREC_* for the double-layer sums;
  * STOKES_EAGER launches each iteration's kernels one by one instead of replaying the
- * iteration captured once into a HIP graph (the default; the results are the same).
+ * iteration captured into HIP graphs (the default; the results are the same, bit for
+ * bit).  The capture runs on a stream the call creates (the caller's may be the null
+ * stream) and the replays on `stream`.  The double layers of all surfaces are one sum
+ * over all points (each surface's own term in principal value).
  * U_out, Omega_out   [3*n_part] translational and angular velocities (SoA).
  * q_out              NULL or [3*(m0+Mp)] densities (periphery points first).
  * resid_out, iters_out   NULL or host: final least-squares residual, iterations.
  * All arrays except part_offset are DEVICE pointers.  The call allocates its own
- * scratch (about (3 iters + 30)(m0 + Mp) doubles) and is synchronous.
+ * scratch (about (3 iters + 30)(m0 + Mp) doubles) and is synchronous.  Errors:
+ * E_INVAL (sizes, pointers, flags), E_NOMEM, E_DEVICE.
  */
 int stokes_particle_solve(int64_t m0, const double* y0, const double* n0, const double* w0,
                           int32_t n_part, const int64_t* part_offset, const double* yp,
