@@ -290,6 +290,44 @@ def test_accumulate_and_empty(S, oracle_mod):
     assert e.shape == (3, 0)
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_dl_ragged_single_and_empty(S, oracle_mod, mixed):
+    """The double layer on a ragged surface (91 points: two full tiles and one of 27),
+    on a single source, with no sources (zeros, and accumulate leaves the output as it
+    was) and with no targets, against the oracle."""
+    rng = np.random.default_rng(29)
+    tol = FP64_TOL if not mixed else MIXED_TOL
+    err = rel_l2 if not mixed else rel_max
+    sph = W.sphere_surface(7, 13, 1.1)
+    assert sph.n == 91
+    q = rng.standard_normal((3, sph.n))
+    trg = np.concatenate([sph.xyz, W.uniform_ball(rng, 45, 1.6).T], axis=1)
+    tself = np.concatenate([np.arange(sph.n), -np.ones(45, dtype=np.int64)])
+    args = (dev(sph.xyz), dev(sph.normal), dev(sph.weight), dev(q))
+    for sub in (True, False):
+        ref = oracle_mod.dl(sph.xyz, sph.normal, sph.weight, q, trg_xyz=trg, trg_self=tself, subtract=sub)
+        u = host(S.dl_eval(*args, trg_xyz=dev(trg), trg_self=dev(tself, torch.int64), subtract=sub,
+                           mixed=mixed))
+        assert err(u, ref) <= tol
+    # one source, off-surface targets
+    one = (sph.xyz[:, :1], sph.normal[:, :1], sph.weight[:1], q[:, :1])
+    x = W.uniform_ball(rng, 40, 1.6).T
+    ref = oracle_mod.dl(*one, trg_xyz=x)
+    u = host(S.dl_eval(*(dev(a) for a in one), trg_xyz=dev(x), mixed=mixed))
+    assert err(u, ref) <= tol
+    # no sources: zeros, and accumulate leaves the output unchanged
+    none = (np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0), np.zeros((3, 0)))
+    z = host(S.dl_eval(*(dev(a) for a in none), trg_xyz=dev(x), mixed=mixed))
+    assert z.shape == (3, 40) and np.all(z == 0)
+    base = rng.standard_normal((3, 40))
+    out = dev(base)
+    S.dl_eval(*(dev(a) for a in none), trg_xyz=dev(x), mixed=mixed, accumulate=True, out=out)
+    assert np.array_equal(host(out), base)
+    # no targets
+    e = S.dl_eval(*args, trg_xyz=dev(np.zeros((3, 0))), mixed=mixed)
+    assert e.shape == (3, 0)
+
+
 def test_check_inputs_nonfinite_leaves_output_untouched(S):
     g = _random_fibers(6, 64)
     f = g["f"].copy()
