@@ -113,6 +113,9 @@ struct stokes_session {
     std::deque<stokes::Request*> queue;
     std::map<uint64_t, stokes::Request*> reqs;
     std::vector<stokes::Request*> slot_req;
+    // tree plans of finished requests, freed by the worker outside the lock (freeing
+    // device memory waits for the device)
+    std::vector<stokes::FarPlan*> dead_plans;
 };
 
 namespace stokes {
@@ -137,8 +140,18 @@ static void finish(stokes_session* s, Request* r, int status) {
         s->arena.release(r->mem);
         r->mem = nullptr;
     }
-    delete r->fplan;   // no step still reads it: see the callers
+    if (r->fplan) s->dead_plans.push_back(r->fplan);   // no step still reads it: see the callers
     r->fplan = nullptr;
+}
+
+// Free the tree plans of finished requests (lock not held).
+static void free_dead_plans(stokes_session* s) {
+    std::vector<FarPlan*> dead;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        dead.swap(s->dead_plans);
+    }
+    for (FarPlan* p : dead) delete p;
 }
 
 // Single-layer items a request takes per step: its pair budget over the pairs
@@ -229,6 +242,7 @@ static void worker_main(stokes_session* s) {
     Pending pend;
     int next_buf = 0;
     for (;;) {
+        free_dead_plans(s);
         // Admissions, cancellations of running requests, fault injection and stopping
         // need an empty pipeline (memory of a finished request is reused only after its
         // last step): drain the pending step first when one of them is due.
@@ -624,6 +638,7 @@ extern "C" int stokes_session_destroy(stokes_session* s) {
         for (auto& kv : s->reqs) free_request(kv.second);
         s->reqs.clear();
     }
+    free_dead_plans(s);
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(s->cfg.device);
