@@ -442,7 +442,7 @@ typedef struct stokes_session_cfg {
                                   default (STOKES_STEP_PAIRS_DEFAULT); < 0: no limit. */
 } stokes_session_cfg;
 
-#define STOKES_STEP_PAIRS_DEFAULT 8000000000LL
+#define STOKES_STEP_PAIRS_DEFAULT 4000000000LL
 
 typedef struct stokes_solve_req {   /* HOST pointers; copied by stokes_session_submit */
     int32_t n_fib;
