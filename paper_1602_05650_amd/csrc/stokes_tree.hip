@@ -23,134 +23,16 @@
 
 #include "pair_math.hpp"
 #include "stokes_internal.hpp"
+#include "tree_build.hpp"
 
 namespace stokes {
 namespace tree {
 
 constexpr int TB = 256;        // threads per workgroup (4 waves, one batch per wave)
-constexpr int BATCH = 64;      // targets per batch
 constexpr int MAX_DEG = 10;
 
-struct Cluster {
-    double lo[3], hi[3], c[3], r;
-    int64_t start, count;
-    int32_t first_child, n_child;
-};
-
-struct Batch {
-    double c[3], r;
-    int64_t start;
-    int32_t count;
-};
-
-// Octree-like midpoint splits: every dimension whose extent is at least half the
-// largest is halved, until a cluster holds at most `leaf` points.
-static void build_sources(const std::vector<double>& xyz, int64_t n, std::vector<int64_t>& perm,
-                          std::vector<Cluster>& cl, int leaf) {
-    perm.resize(n);
-    for (int64_t i = 0; i < n; ++i) perm[i] = i;
-    struct Item { int64_t start, count; int32_t self; };
-    cl.clear();
-    cl.push_back(Cluster{});
-    std::vector<Item> stack{{0, n, 0}};
-    std::vector<int64_t> tmp;
-    while (!stack.empty()) {
-        const Item it = stack.back();
-        stack.pop_back();
-        Cluster& C = cl[it.self];
-        C.start = it.start;
-        C.count = it.count;
-        for (int d = 0; d < 3; ++d) {
-            C.lo[d] = INFINITY;
-            C.hi[d] = -INFINITY;
-        }
-        for (int64_t k = it.start; k < it.start + it.count; ++k)
-            for (int d = 0; d < 3; ++d) {
-                const double v = xyz[d * n + perm[k]];
-                C.lo[d] = std::min(C.lo[d], v);
-                C.hi[d] = std::max(C.hi[d], v);
-            }
-        double emax = 0.0;
-        for (int d = 0; d < 3; ++d) emax = std::max(emax, C.hi[d] - C.lo[d]);
-        double r2 = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            C.c[d] = 0.5 * (C.lo[d] + C.hi[d]);
-            r2 += 0.25 * (C.hi[d] - C.lo[d]) * (C.hi[d] - C.lo[d]);
-        }
-        C.r = std::sqrt(r2);
-        C.first_child = -1;
-        C.n_child = 0;
-        if (it.count <= leaf || emax == 0.0) continue;
-        // split
-        std::vector<std::pair<int64_t, int64_t>> groups{{it.start, it.count}};
-        for (int d = 0; d < 3; ++d) {
-            if (C.hi[d] - C.lo[d] < 0.5 * emax) continue;
-            const double mid = C.c[d];
-            std::vector<std::pair<int64_t, int64_t>> ng;
-            for (auto g : groups) {
-                auto b = perm.begin() + g.first, e = b + g.second;
-                auto m = std::stable_partition(b, e, [&](int64_t q) { return xyz[d * n + q] <= mid; });
-                const int64_t a = m - b;
-                if (a == 0 || a == g.second) {
-                    ng.push_back(g);
-                } else {
-                    ng.push_back({g.first, a});
-                    ng.push_back({g.first + a, g.second - a});
-                }
-            }
-            groups.swap(ng);
-        }
-        if (groups.size() < 2) continue;
-        const int32_t first = (int32_t)cl.size();
-        cl[it.self].first_child = first;
-        cl[it.self].n_child = (int32_t)groups.size();
-        for (size_t g = 0; g < groups.size(); ++g) {
-            cl.push_back(Cluster{});
-            stack.push_back({groups[g].first, groups[g].second, first + (int32_t)g});
-        }
-    }
-}
-
-// Median splits along the longest extent down to at most BATCH targets per batch.
-static void build_batches(const std::vector<double>& xyz, int64_t n, std::vector<int64_t>& perm,
-                          std::vector<Batch>& bt) {
-    perm.resize(n);
-    for (int64_t i = 0; i < n; ++i) perm[i] = i;
-    bt.clear();
-    std::vector<std::pair<int64_t, int64_t>> stack{{0, n}};
-    while (!stack.empty()) {
-        const auto g = stack.back();
-        stack.pop_back();
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int64_t k = g.first; k < g.first + g.second; ++k)
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = std::min(lo[d], xyz[d * n + perm[k]]);
-                hi[d] = std::max(hi[d], xyz[d * n + perm[k]]);
-            }
-        if (g.second <= BATCH) {
-            Batch B{};
-            double r2 = 0.0;
-            for (int d = 0; d < 3; ++d) {
-                B.c[d] = 0.5 * (lo[d] + hi[d]);
-                r2 += 0.25 * (hi[d] - lo[d]) * (hi[d] - lo[d]);
-            }
-            B.r = std::sqrt(r2);
-            B.start = g.first;
-            B.count = (int32_t)g.second;
-            bt.push_back(B);
-            continue;
-        }
-        int dm = 0;
-        for (int d = 1; d < 3; ++d)
-            if (hi[d] - lo[d] > hi[dm] - lo[dm]) dm = d;
-        const int64_t half = g.second / 2;
-        auto b = perm.begin() + g.first;
-        std::nth_element(b, b + half, b + g.second,
-                         [&](int64_t a, int64_t c) { return xyz[dm * n + a] < xyz[dm * n + c]; });
-        stack.push_back({g.first, half});
-        stack.push_back({g.first + half, g.second - half});
-    }
-}
+// The host-side construction (clusters, batches, interaction lists) is in
+// tree_build.hpp.
 
 // ---- device kernels -------------------------------------------------------------
 
@@ -1069,49 +951,21 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     std::vector<int64_t> sperm, tperm;
     std::vector<Cluster> cl;
     std::vector<Batch> bt;
-    build_sources(hs, n_src, sperm, cl, leaf_size);
-    build_batches(tx, n_trg, tperm, bt);
+    build_sources(hs, n_src, sperm, cl, leaf_size, plan_threads(n_src));
+    build_batches(tx, n_trg, tperm, bt, plan_threads(n_trg));
     const int n1 = degree + 1, P = n1 * n1 * n1;
-    // interaction lists
-    std::vector<int32_t> px_off{0}, px_list, dr_off{0}, dr_count, slot_of(cl.size(), -1);
-    std::vector<int64_t> dr_start;
-    std::vector<int32_t> used;
-    int64_t pairs_px = 0, pairs_dir = 0;
-    std::vector<int32_t> stack;
-    for (const Batch& B : bt) {
-        stack.assign(1, 0);
-        while (!stack.empty()) {
-            const int32_t ci = stack.back();
-            stack.pop_back();
-            const Cluster& C = cl[ci];
-            const double dx = B.c[0] - C.c[0], dy = B.c[1] - C.c[1], dz = B.c[2] - C.c[2];
-            const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
-            const bool far = B.r + C.r < theta * dist;
-            if (far && C.count > P) {
-                if (slot_of[ci] < 0) {
-                    slot_of[ci] = (int32_t)used.size();
-                    used.push_back(ci);
-                }
-                px_list.push_back(slot_of[ci]);
-                pairs_px += (int64_t)B.count * P;
-            } else if (C.n_child == 0 || far) {
-                if (!dr_start.empty() && dr_off.size() == px_off.size() &&
-                    (int64_t)dr_start.size() > dr_off.back() &&
-                    dr_start.back() + dr_count.back() == C.start && dr_count.back() + C.count < (1 << 30)) {
-                    dr_count.back() += (int32_t)C.count;      // adjacent ranges merge
-                } else {
-                    dr_start.push_back(C.start);
-                    dr_count.push_back((int32_t)C.count);
-                }
-                pairs_dir += (int64_t)B.count * C.count;
-            } else {
-                for (int32_t k = C.n_child - 1; k >= 0; --k) stack.push_back(C.first_child + k);
-            }
-        }
-        px_off.push_back((int32_t)px_list.size());
-        dr_off.push_back((int32_t)dr_start.size());
-    }
+    Lists lists;
+    build_lists(bt, cl, theta, P, lists, plan_threads(n_trg));
+    const std::vector<int32_t>& px_off = lists.px_off;
+    const std::vector<int32_t>& px_list = lists.px_list;
+    const std::vector<int32_t>& used = lists.used;
+    const std::vector<int32_t>& dr_off = lists.dr_off;
+    const std::vector<int64_t>& dr_start = lists.dr_start;
+    const std::vector<int32_t>& dr_count = lists.dr_count;
+    const int64_t pairs_px = lists.pairs_px, pairs_dir = lists.pairs_dir;
     // proxy clusters: boxes (degenerate extents padded) and Chebyshev points
+    std::vector<double> cheb(n1);   // cos(i pi / n), the second-kind points on [-1, 1]
+    for (int i = 0; i < n1; ++i) cheb[i] = std::cos(i * 3.14159265358979323846 / degree);
     const int32_t n_px = (int32_t)used.size();
     std::vector<DevCl> pcl(n_px);
     std::vector<double> ppos((size_t)n_px * 3 * P);
@@ -1134,10 +988,9 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
         pcl[q].count = C.count;
         for (int k = 0; k < P; ++k) {
             const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
-            for (int d = 0; d < 3; ++d) {
-                const double sn = std::cos(idx[d] * 3.14159265358979323846 / degree);
-                ppos[((size_t)q * 3 + d) * P + k] = pcl[q].lo[d] + 0.5 * (sn + 1.0) * (pcl[q].hi[d] - pcl[q].lo[d]);
-            }
+            for (int d = 0; d < 3; ++d)
+                ppos[((size_t)q * 3 + d) * P + k] =
+                    pcl[q].lo[d] + 0.5 * (cheb[idx[d]] + 1.0) * (pcl[q].hi[d] - pcl[q].lo[d]);
         }
     }
     // 1-D proxy coordinates of each box: [q][dim][i] = lo + (1 + cos(i pi / n)) (hi - lo) / 2
@@ -1146,8 +999,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
         for (int d = 0; d < 3; ++d)
             for (int i = 0; i < n1; ++i)
                 p1d[((size_t)q * 3 + d) * n1 + i] =
-                    pcl[q].lo[d] + 0.5 * (std::cos(i * 3.14159265358979323846 / degree) + 1.0) *
-                                       (pcl[q].hi[d] - pcl[q].lo[d]);
+                    pcl[q].lo[d] + 0.5 * (cheb[i] + 1.0) * (pcl[q].hi[d] - pcl[q].lo[d]);
     // charge work items: pieces of at most CH_SRC sources of each proxy cluster
     std::vector<ChargeItem> items;
     std::vector<int32_t> item_off{0};
