@@ -101,6 +101,7 @@ __device__ __forceinline__ double cheb_bw(int i, int n) {
 constexpr int CB = 512;
 constexpr int SRC_TILE = 160;      // 3 * SRC_TILE <= CB threads compute basis values
 constexpr int64_t CH_SRC = 4096;
+constexpr int64_t CHARGE_ITEMS = 1024;   // aim for the number of pieces (4 per CU)
 struct ChargeItem {
     int32_t q;                     // proxy slot
     int32_t count;
@@ -179,7 +180,8 @@ __global__ __launch_bounds__(CB) void k_tr_charges(int deg, const DevCl* cls, co
 __global__ __launch_bounds__(TB) void k_tr_charges_sum(int P, const int32_t* item_off, const double* part,
                                                        double* pA, double* pB, int NC, int NA) {
     const int q = blockIdx.x;
-    for (int e = threadIdx.x; e < NC * P; e += TB) {
+    const int e = blockIdx.y * TB + threadIdx.x;   // one charge per thread
+    if (e < NC * P) {
         double s = 0.0;
         for (int i = item_off[q]; i < item_off[q + 1]; ++i) s += part[(int64_t)i * NC * P + e];
         const int b = e / P, k = e - b * P;
@@ -201,8 +203,10 @@ __global__ __launch_bounds__(TB) void k_tr_pack(int P, const double* pF, const d
     }
 }
 
-// One wave per target batch.  Lists: proxy clusters px_list[px_off[b] .. px_off[b+1]),
-// direct source ranges dr_*[dr_off[b] .. dr_off[b+1]).
+// One wave per (target batch, work part).  Lists: proxy clusters
+// px_list[px_off[b] .. px_off[b+1]), direct source ranges dr_*[dr_off[b] .. dr_off[b+1]).
+// A batch's entry sequence is its proxy list followed by its direct ranges; part h
+// takes entries [cut[b][h], cut[b][h+1]) of it.
 struct EvalArgs {
     int64_t ns, nt;
     const double* sxyz;      // [3][ns] sorted sources
@@ -225,8 +229,9 @@ struct EvalArgs {
     const int32_t* dr_off;
     const int64_t* dr_start;
     const int32_t* dr_count;
-    double* out;
-    int accumulate;
+    int32_t S, SM;           // work parts per batch, of the SM the plan's cuts are made for
+    const int32_t* cut;      // [nb][SM + 1] part boundaries in each batch's entry sequence
+    double* psum;            // [S][3][nt] part sums, sorted target order
     // same-fiber exclusion (targets = sources)
     const int32_t* sfib;     // [ns] fiber id of each source, original order
     const int32_t* sfid;     // [ns] fiber id of each sorted source
@@ -264,7 +269,61 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int EW = 4;   // waves per workgroup: two batches, each split between two waves
+constexpr int EW = 4;   // waves per workgroup, each on its own (batch, part) item
+
+// Work parts per batch for the mixed evaluation: at least 4, and more for small plans,
+// up to 16, until the launch has about EVAL_WAVES waves (16 per SIMD of the 1,024).
+// The FP64 evaluation, whose pairs cost about twice as much, takes twice as many
+// (at most 16): the plan cuts the batches for that number, and the mixed evaluation
+// uses every other cut.  (Measured on fiber sets of 32,768 to 524,288 points, degree
+// 6, theta 0.7, against 2, 4, 8 and 16 parts for both.)
+constexpr int64_t EVAL_WAVES = 16384;
+constexpr int32_t RANGE_MOST = 512;   // sources per direct-range entry, at most
+inline int eval_parts_mixed(int64_t nb) {
+    int s = 4;
+    while (s < 16 && s * nb < EVAL_WAVES) s *= 2;
+    return s;
+}
+inline int eval_parts_fp64(int64_t nb) { return std::min(16, 2 * eval_parts_mixed(nb)); }
+
+// The entry range [p_lo, p_hi) of the proxy list and [d_lo, d_hi) of the direct list
+// that part h of batch b takes.
+struct PartRange {
+    int p_lo, p_hi, d_lo, d_hi;
+};
+__device__ __forceinline__ PartRange part_range(const int32_t* px_off, const int32_t* dr_off, const int32_t* cut,
+                                                int S, int SM, int b, int h) {
+    const int pa = px_off[b], np = px_off[b + 1] - pa, da = dr_off[b], k = SM / S;
+    const int c0 = cut[(int64_t)b * (SM + 1) + h * k], c1 = cut[(int64_t)b * (SM + 1) + (h + 1) * k];
+    return PartRange{pa + min(c0, np), pa + min(c1, np), da + max(c0 - np, 0), da + max(c1 - np, 0)};
+}
+
+// Sum of each target's part sums, in part order, scaled and written (or added) in the
+// caller's order.  Double layer: minus half the subtracted self density (rounded to
+// FP32 first on the mixed path) where q0_self is given.
+__global__ __launch_bounds__(TB) void k_tr_combine(int64_t nt, int S, const double* __restrict__ psum,
+                                                   const int64_t* __restrict__ tperm, double scale, double* out,
+                                                   int accumulate, const int64_t* q0_self, const double* sq,
+                                                   int64_t ns, int round_q0) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nt) return;
+    const int64_t o = tperm[i];
+    const int64_t self = q0_self ? q0_self[i] : -1;
+    for (int c = 0; c < 3; ++c) {
+        double r = psum[c * nt + i];
+        for (int h = 1; h < S; ++h) r += psum[((int64_t)h * 3 + c) * nt + i];
+        r *= scale;
+        if (self >= 0) {
+            double q0 = sq[c * ns + self];
+            if (round_q0) q0 = (double)(float)q0;
+            r -= 0.5 * q0;
+        }
+        if (accumulate)
+            out[c * nt + o] += r;
+        else
+            out[c * nt + o] = r;
+    }
+}
 // Mixed far field of one proxy cluster for a compile-time degree: the proxies form
 // the tensor grid (X[kx], Y[ky], Z[kz]), so each lane keeps its z offsets and their
 // squares in registers and only the six charges of a proxy come from LDS; the
@@ -322,19 +381,17 @@ template <bool MIXED, int DEG, bool EXF = false>
 __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4 : 5))) void k_tr_eval(EvalArgs a) {
     __shared__ __align__(16) float lfs[EW][64][12];    // (a DEG <= 8 slab: 8 (DEG+1)^2 <= 768 floats)
     __shared__ double lds_[EW][64][10];
-    __shared__ double comb[EW / 2][3][64];              // the second half's sums of each batch
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    // waves 2k and 2k+1 take the first and second halves of batch b's proxy and direct
-    // lists; the halves are added in that order at the end (deterministic), and the
-    // finer work items let the waves of a SIMD even out.  A wave past the last batch
-    // reads a real batch, does no work and still meets the barrier.
-    const int h = w & 1, b_raw = blockIdx.x * (EW / 2) + (w >> 1);
-    const bool live = b_raw < a.nb;
-    const int b = live ? b_raw : a.nb - 1;
-    const int pa = a.px_off[b], pz = a.px_off[b + 1], pm = pa + (pz - pa + 1) / 2;
-    const int p_lo = !live ? 0 : (h ? pm : pa), p_hi = !live ? 0 : (h ? pz : pm);
-    const int da = a.dr_off[b], dz = a.dr_off[b + 1], dm = da + (dz - da + 1) / 2;
-    const int d_lo = !live ? 0 : (h ? dm : da), d_hi = !live ? 0 : (h ? dz : dm);
+    // wave (b, h) takes part h of batch b's entries; the parts' sums are added in part
+    // order by k_tr_combine (deterministic).  The parts are cut at about equal pair
+    // counts, and small plans take more of them, so that the launch fills the chip and
+    // the waves of a SIMD even out.  Only wave-level synchronisation follows, so a wave
+    // past the last item leaves at once.
+    const int64_t gw = (int64_t)blockIdx.x * EW + w;
+    const int b = (int)(gw / a.S), h = (int)(gw - (int64_t)b * a.S);
+    if (b >= a.nb) return;
+    const PartRange pr = part_range(a.px_off, a.dr_off, a.cut, a.S, a.SM, b, h);
+    const int p_lo = pr.p_lo, p_hi = pr.p_hi, d_lo = pr.d_lo, d_hi = pr.d_hi;
     float (*lf)[12] = lfs[w];
     double (*ld)[10] = lds_[w];
     const Batch B = a.bt[b];
@@ -535,9 +592,10 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
         }
     }
     if constexpr (EXF) {
-        if (live && act) {
+        if (act) {
+            const int da = a.dr_off[b], dz = a.dr_off[b + 1];   // all of the batch's direct ranges
             const int2 fr = a.frange[o_exf];
-            for (int jo = fr.x + h; jo < fr.y; jo += 2) {     // the two waves take alternate sources
+            for (int jo = fr.x + h; jo < fr.y; jo += a.S) {   // the parts take every S-th source
                 const int64_t js = a.sinv[jo];
                 int lo = da, hi = dz;                         // first direct range starting after js
                 while (lo < hi) {
@@ -561,26 +619,11 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
         r1 += (double)S1 - (double)C1;
         r2 += (double)S2 - (double)C2;
     }
-    if (h == 1) {
-        comb[w >> 1][0][l] = r0;
-        comb[w >> 1][1][l] = r1;
-        comb[w >> 1][2][l] = r2;
-    }
-    __syncthreads();
-    if (!live || h == 1 || !act) return;
-    r0 += comb[w >> 1][0][l];
-    r1 += comb[w >> 1][1][l];
-    r2 += comb[w >> 1][2][l];
-    const int64_t o = EXF ? o_exf : a.tperm[ti];
-    if (a.accumulate) {
-        a.out[o] += r0;
-        a.out[a.nt + o] += r1;
-        a.out[2 * a.nt + o] += r2;
-    } else {
-        a.out[o] = r0;
-        a.out[a.nt + o] = r1;
-        a.out[2 * a.nt + o] = r2;
-    }
+    if (!act) return;
+    double* ps = a.psum + (int64_t)h * 3 * a.nt;
+    ps[ti] = r0;
+    ps[a.nt + ti] = r1;
+    ps[2 * a.nt + ti] = r2;
 }
 
 // ---- double layer ---------------------------------------------------------------
@@ -633,13 +676,15 @@ struct DlArgs {
     const int32_t* dr_off;
     const int64_t* dr_start;
     const int32_t* dr_count;
-    double* out;
-    int accumulate, subtract;
+    int32_t S, SM;           // as in EvalArgs
+    const int32_t* cut;
+    double* psum;
+    int subtract;
     const float* near2;      // mixed: [ns] FP64 below this squared distance (k_tr_dlband)
 };
 
-// Waves 2k and 2k+1 take the halves of batch b's proxy and direct lists, as in
-// k_tr_eval, and the halves are added in that order.  MIXED: proxies and direct pairs in
+// Wave (b, h) takes part h of batch b's proxy and direct lists, as in k_tr_eval; the
+// parts' sums are added in part order, scaled and completed by k_tr_combine.  MIXED: proxies and direct pairs in
 // FP32 relative to the batch centre, each cluster's or chunk's sum added with Kahan
 // compensation; direct pairs closer than the source's near2 (the near radius or the
 // tangent band, and the self point) are taken in FP64 from the sorted sources.  The
@@ -650,15 +695,12 @@ template <bool MIXED>
 __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
     __shared__ double lds_[EW][64][15];
     __shared__ float lfs[EW][64][16];
-    __shared__ double comb[EW / 2][3][64];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int h = w & 1, b_raw = blockIdx.x * (EW / 2) + (w >> 1);
-    const bool live = b_raw < a.nb;
-    const int b = live ? b_raw : a.nb - 1;
-    const int pa = a.px_off[b], pz = a.px_off[b + 1], pm = pa + (pz - pa + 1) / 2;
-    const int p_lo = !live ? 0 : (h ? pm : pa), p_hi = !live ? 0 : (h ? pz : pm);
-    const int da = a.dr_off[b], dz = a.dr_off[b + 1], dm = da + (dz - da + 1) / 2;
-    const int d_lo = !live ? 0 : (h ? dm : da), d_hi = !live ? 0 : (h ? dz : dm);
+    const int64_t gw = (int64_t)blockIdx.x * EW + w;
+    const int b = (int)(gw / a.S), h = (int)(gw - (int64_t)b * a.S);
+    if (b >= a.nb) return;
+    const PartRange pr = part_range(a.px_off, a.dr_off, a.cut, a.S, a.SM, b, h);
+    const int p_lo = pr.p_lo, p_hi = pr.p_hi, d_lo = pr.d_lo, d_hi = pr.d_hi;
     double (*ld)[15] = lds_[w];
     const Batch B = a.bt[b];
     const bool act = l < B.count;
@@ -842,32 +884,11 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
         u1 += (double)S1 - (double)C1;
         u2 += (double)S2 - (double)C2;
     }
-    if (h == 1) {
-        comb[w >> 1][0][l] = u0;
-        comb[w >> 1][1][l] = u1;
-        comb[w >> 1][2][l] = u2;
-    }
-    __syncthreads();
-    if (!live || h == 1 || !act) return;
-    const double pref = 3.0 / (4.0 * 3.14159265358979323846);
-    double r0 = pref * (u0 + comb[w >> 1][0][l]);
-    double r1 = pref * (u1 + comb[w >> 1][1][l]);
-    double r2 = pref * (u2 + comb[w >> 1][2][l]);
-    if (sub) {
-        r0 -= 0.5 * q0x;
-        r1 -= 0.5 * q0y;
-        r2 -= 0.5 * q0z;
-    }
-    const int64_t o = a.tperm[ti];
-    if (a.accumulate) {
-        a.out[o] += r0;
-        a.out[a.nt + o] += r1;
-        a.out[2 * a.nt + o] += r2;
-    } else {
-        a.out[o] = r0;
-        a.out[a.nt + o] = r1;
-        a.out[2 * a.nt + o] = r2;
-    }
+    if (!act) return;
+    double* ps = a.psum + (int64_t)h * 3 * a.nt;
+    ps[ti] = u0;
+    ps[a.nt + ti] = u1;
+    ps[2 * a.nt + ti] = u2;
 }
 
 }  // namespace tree
@@ -915,6 +936,9 @@ struct stokes_tree {
     ChargeItem* items = nullptr;
     int32_t* item_off = nullptr;
     double* part = nullptr;
+    int32_t S_mix = 4, S = 8;     // evaluation work parts per batch: mixed, FP64 (the cuts' own)
+    int32_t* cut = nullptr;       // [nb][S + 1]
+    double* psum = nullptr;       // [S][3][nt]
     ~stokes_tree() {
         if (mem) (void)hipFree(mem);
     }
@@ -956,6 +980,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     const int n1 = degree + 1, P = n1 * n1 * n1;
     Lists lists;
     build_lists(bt, cl, theta, P, lists, plan_threads(n_trg));
+    split_ranges(lists, RANGE_MOST);
     const std::vector<int32_t>& px_off = lists.px_off;
     const std::vector<int32_t>& px_list = lists.px_list;
     const std::vector<int32_t>& used = lists.used;
@@ -1000,13 +1025,39 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
             for (int i = 0; i < n1; ++i)
                 p1d[((size_t)q * 3 + d) * n1 + i] =
                     pcl[q].lo[d] + 0.5 * (cheb[i] + 1.0) * (pcl[q].hi[d] - pcl[q].lo[d]);
-    // charge work items: pieces of at most CH_SRC sources of each proxy cluster
+    // charge work items: pieces of each proxy cluster's sources, about CHARGE_ITEMS of
+    // them in all (whole LDS tiles, at most CH_SRC sources)
+    int64_t px_src = 0;
+    for (int32_t q = 0; q < n_px; ++q) px_src += pcl[q].count;
+    const int64_t ch = std::min<int64_t>(
+        CH_SRC, std::max<int64_t>(1, (px_src + CHARGE_ITEMS * SRC_TILE - 1) / (CHARGE_ITEMS * SRC_TILE)) * SRC_TILE);
     std::vector<ChargeItem> items;
     std::vector<int32_t> item_off{0};
     for (int32_t q = 0; q < n_px; ++q) {
-        for (int64_t o = 0; o < pcl[q].count; o += CH_SRC)
-            items.push_back(ChargeItem{q, (int32_t)std::min<int64_t>(CH_SRC, pcl[q].count - o), pcl[q].start + o});
+        for (int64_t o = 0; o < pcl[q].count; o += ch)
+            items.push_back(ChargeItem{q, (int32_t)std::min<int64_t>(ch, pcl[q].count - o), pcl[q].start + o});
         item_off.push_back((int32_t)items.size());
+    }
+    // evaluation work parts: S per batch, cut at about equal pair counts (a proxy
+    // cluster counts P pairs per target, a direct range its sources)
+    const int64_t nb = (int64_t)bt.size();
+    const int S = eval_parts_fp64(nb);
+    std::vector<int32_t> cut((size_t)nb * (S + 1));
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t pa = px_off[b], np = px_off[b + 1] - pa, da = dr_off[b], nd = dr_off[b + 1] - da;
+        auto cost = [&](int32_t e) -> int64_t { return e < np ? P : dr_count[da + e - np]; };
+        int64_t total = 0;
+        for (int32_t e = 0; e < np + nd; ++e) total += cost(e);
+        int32_t* cb = &cut[(size_t)b * (S + 1)];
+        cb[0] = 0;
+        cb[S] = np + nd;
+        int32_t e = 0;
+        int64_t acc = 0;
+        for (int h = 1; h < S; ++h) {   // first entry whose midpoint lies past h / S of the cost
+            const int64_t goal = total * h / S;
+            while (e < np + nd && 2 * acc + cost(e) <= 2 * goal) acc += cost(e++);
+            cb[h] = e;
+        }
     }
     // sorted coordinates, self indices
     std::vector<double> sx(3 * n_src), txs(3 * n_trg);
@@ -1051,7 +1102,8 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
                  o_io = take(item_off.size() * 4), o_pa = take(items.size() * 12 * P * 8),
                  o_sq = take(3 * n_src * 8),
                  o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8),
-                 o_si = take(sinv.size() * 4), o_sf = take(sinv.size() * 4), o_fr = take(sinv.size() * 8);
+                 o_si = take(sinv.size() * 4), o_sf = take(sinv.size() * 4), o_fr = take(sinv.size() * 8),
+                 o_cu = take(cut.size() * 4), o_ps = take((size_t)S * 3 * n_trg * 8);
     hipError_t e = hipMalloc(&t->mem, off);
     if (e != hipSuccess) {
         delete t;
@@ -1087,6 +1139,10 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     t->part = reinterpret_cast<double*>(base + o_pa);
     t->pk = reinterpret_cast<float4*>(base + o_pk);
     t->p1d = reinterpret_cast<double*>(base + o_p1);
+    t->S = S;
+    t->S_mix = eval_parts_mixed(nb);
+    t->cut = reinterpret_cast<int32_t*>(base + o_cu);
+    t->psum = reinterpret_cast<double*>(base + o_ps);
     if (same) {
         t->sinv = reinterpret_cast<int32_t*>(base + o_si);
         t->sfid = reinterpret_cast<int32_t*>(base + o_sf);
@@ -1115,6 +1171,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     if (!rc) rc = up(t->items, items.data(), items.size() * sizeof(ChargeItem));
     if (!rc) rc = up(t->item_off, item_off.data(), item_off.size() * 4);
     if (!rc) rc = up(t->p1d, p1d.data(), p1d.size() * 8);
+    if (!rc) rc = up(t->cut, cut.data(), cut.size() * 4);
     if (!rc) {
         hipError_t r = hipStreamSynchronize(st);
         if (r != hipSuccess) rc = hip_fail(r, "hipStreamSynchronize(tree)");
@@ -1182,8 +1239,8 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
         hipLaunchKernelGGL(k_tr_charges<false>, dim3(t->n_items), dim3(CB), 0, st, t->deg,
                            (const DevCl*)t->px_cl, (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns,
                            (const double*)t->ss, (const double*)t->sc, t->part);
-        hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px), dim3(TB), 0, st, t->P, (const int32_t*)t->item_off,
-                           (const double*)t->part, t->pF, t->pD, 6, 3);
+        hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px, (6 * t->P + TB - 1) / TB), dim3(TB), 0, st, t->P,
+                           (const int32_t*)t->item_off, (const double*)t->part, t->pF, t->pD, 6, 3);
         if (mixed)
             hipLaunchKernelGGL(k_tr_pack, dim3(t->n_px), dim3(TB), 0, st, t->P, (const double*)t->pF,
                                (const double*)t->pD, t->pk);
@@ -1211,18 +1268,24 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
     a.dr_off = t->dr_off;
     a.dr_start = t->dr_start;
     a.dr_count = t->dr_count;
-    a.out = u_out;
-    a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
+    a.S = mixed ? t->S_mix : t->S;
+    a.SM = t->S;
+    a.cut = t->cut;
+    a.psum = t->psum;
     a.sfib = src_fiber;
     a.sfid = t->sfid;
     a.frange = t->frange;
     a.sinv = t->sinv;
-    const unsigned grid = (unsigned)((t->nb + EW / 2 - 1) / (EW / 2));
+    const unsigned grid = (unsigned)(((int64_t)t->nb * a.S + EW - 1) / EW);
     const dim3 blk(64 * EW);
     if (exf)
         launch_eval<true>(mixed, t->deg, grid, blk, st, a);
     else
         launch_eval<false>(mixed, t->deg, grid, blk, st, a);
+    hipLaunchKernelGGL(k_tr_combine, dim3((unsigned)((t->nt + TB - 1) / TB)), dim3(TB), 0, st, t->nt, a.S,
+                       (const double*)t->psum, (const int64_t*)t->tperm, 1.0, u_out,
+                       (flags & STOKES_ACCUMULATE) ? 1 : 0, (const int64_t*)nullptr, (const double*)nullptr,
+                       t->ns, 0);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }
@@ -1243,8 +1306,8 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
         hipLaunchKernelGGL(k_tr_charges<true>, dim3(t->n_items), dim3(CB), 0, st, t->deg,
                            (const DevCl*)t->px_cl, (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns,
                            (const double*)t->ss, (const double*)t->sq, t->part);
-        hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px), dim3(TB), 0, st, t->P, (const int32_t*)t->item_off,
-                           (const double*)t->part, t->pM, t->pN, 12, 9);
+        hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px, (12 * t->P + TB - 1) / TB), dim3(TB), 0, st, t->P,
+                           (const int32_t*)t->item_off, (const double*)t->part, t->pM, t->pN, 12, 9);
     }
     DlArgs a{};
     a.ns = t->ns;
@@ -1266,19 +1329,27 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
     a.dr_off = t->dr_off;
     a.dr_start = t->dr_start;
     a.dr_count = t->dr_count;
-    a.out = u_out;
-    a.accumulate = (flags & STOKES_ACCUMULATE) ? 1 : 0;
+    a.S = (flags & STOKES_PREC_MIXED) ? t->S_mix : t->S;
+    a.SM = t->S;
+    a.cut = t->cut;
+    a.psum = t->psum;
     a.subtract = (flags & STOKES_ONSURF_RAW) ? 0 : 1;
     const double nr = near_r > 0.0 ? near_r : 0.02;
     if (flags & STOKES_PREC_MIXED)
         hipLaunchKernelGGL(k_tr_dlband, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns,
                            (const double*)t->sxyz, (const double*)t->ss, nr, t->st);
     a.near2 = t->st;
-    const unsigned grid = (unsigned)((t->nb + EW / 2 - 1) / (EW / 2));
+    const unsigned grid = (unsigned)(((int64_t)t->nb * a.S + EW - 1) / EW);
     if (flags & STOKES_PREC_MIXED)
         hipLaunchKernelGGL(k_tr_dl_eval<true>, dim3(grid), dim3(64 * EW), 0, st, a);
     else
         hipLaunchKernelGGL(k_tr_dl_eval<false>, dim3(grid), dim3(64 * EW), 0, st, a);
+    const double pref = 3.0 / (4.0 * 3.14159265358979323846);
+    hipLaunchKernelGGL(k_tr_combine, dim3((unsigned)((t->nt + TB - 1) / TB)), dim3(TB), 0, st, t->nt, a.S,
+                       (const double*)t->psum, (const int64_t*)t->tperm, pref, u_out,
+                       (flags & STOKES_ACCUMULATE) ? 1 : 0,
+                       (const int64_t*)(t->same && a.subtract ? t->tself : nullptr), (const double*)t->sq, t->ns,
+                       (flags & STOKES_PREC_MIXED) ? 1 : 0);
     STOKES_HIP(hipGetLastError());
     return STOKES_OK;
 }

@@ -414,6 +414,26 @@ inline void build_lists(const std::vector<Batch>& bt, const std::vector<Cluster>
     }
 }
 
+// Direct ranges longer than `most` sources cut into pieces of `most` (the last piece
+// shorter), so that a batch's entries can be shared out evenly between the waves that
+// evaluate it (merged neighbouring leaves can make one range hold a large part of a
+// batch's direct work).  The pieces stay in order, sorted by start and disjoint.
+inline void split_ranges(Lists& L, int32_t most) {
+    std::vector<int32_t> off{0}, count;
+    std::vector<int64_t> start;
+    for (size_t b = 0; b + 1 < L.dr_off.size(); ++b) {
+        for (int32_t e = L.dr_off[b]; e < L.dr_off[b + 1]; ++e)
+            for (int32_t o = 0; o < L.dr_count[e]; o += most) {
+                start.push_back(L.dr_start[e] + o);
+                count.push_back(std::min(most, L.dr_count[e] - o));
+            }
+        off.push_back((int32_t)start.size());
+    }
+    L.dr_off.swap(off);
+    L.dr_start.swap(start);
+    L.dr_count.swap(count);
+}
+
 // Threads for a plan over n points: one per 4,096 points, at most the host's cores
 // and 16 (measured on 65,536 points: 16 threads 5.3 ms, 4 threads 5.7 ms).
 inline int plan_threads(int64_t n) {

@@ -245,6 +245,29 @@ static void check_case(const std::vector<double>& xyz, int64_t n, int leaf, int 
             CHECK(ok && next == n);
         }
     }
+    // pieces of at most `most` sources: in order, covering each batch's ranges exactly
+    for (int32_t most : {1, 64, 1000}) {
+        Lists s = r;
+        split_ranges(s, most);
+        CHECK(s.dr_off.size() == r.dr_off.size());
+        CHECK(s.px_off == r.px_off && s.px_list == r.px_list);
+        for (size_t b = 0; b + 1 < r.dr_off.size() && b + 1 < s.dr_off.size(); ++b) {
+            int32_t k = s.dr_off[b];
+            bool ok = true;
+            for (int32_t e = r.dr_off[b]; e < r.dr_off[b + 1]; ++e) {
+                int64_t at = r.dr_start[e];
+                while (at < r.dr_start[e] + r.dr_count[e]) {
+                    ok &= k < s.dr_off[b + 1] && s.dr_start[k] == at && s.dr_count[k] >= 1 &&
+                          s.dr_count[k] <= most;
+                    if (!ok) break;
+                    at += s.dr_count[k++];
+                }
+                ok &= at == r.dr_start[e] + r.dr_count[e];
+                if (!ok) break;
+            }
+            CHECK(ok && k == s.dr_off[b + 1]);
+        }
+    }
 }
 
 int main() {
