@@ -1038,27 +1038,10 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
             items.push_back(ChargeItem{q, (int32_t)std::min<int64_t>(ch, pcl[q].count - o), pcl[q].start + o});
         item_off.push_back((int32_t)items.size());
     }
-    // evaluation work parts: S per batch, cut at about equal pair counts (a proxy
-    // cluster counts P pairs per target, a direct range its sources)
+    // evaluation work parts: S per batch, cut at about equal pair counts
     const int64_t nb = (int64_t)bt.size();
     const int S = eval_parts_fp64(nb);
-    std::vector<int32_t> cut((size_t)nb * (S + 1));
-    for (int64_t b = 0; b < nb; ++b) {
-        const int32_t pa = px_off[b], np = px_off[b + 1] - pa, da = dr_off[b], nd = dr_off[b + 1] - da;
-        auto cost = [&](int32_t e) -> int64_t { return e < np ? P : dr_count[da + e - np]; };
-        int64_t total = 0;
-        for (int32_t e = 0; e < np + nd; ++e) total += cost(e);
-        int32_t* cb = &cut[(size_t)b * (S + 1)];
-        cb[0] = 0;
-        cb[S] = np + nd;
-        int32_t e = 0;
-        int64_t acc = 0;
-        for (int h = 1; h < S; ++h) {   // first entry whose midpoint lies past h / S of the cost
-            const int64_t goal = total * h / S;
-            while (e < np + nd && 2 * acc + cost(e) <= 2 * goal) acc += cost(e++);
-            cb[h] = e;
-        }
-    }
+    const std::vector<int32_t> cut = part_cuts(lists, P, S);
     // sorted coordinates, self indices
     std::vector<double> sx(3 * n_src), txs(3 * n_trg);
     for (int64_t j = 0; j < n_src; ++j)

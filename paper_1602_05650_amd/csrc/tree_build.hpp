@@ -434,6 +434,34 @@ inline void split_ranges(Lists& L, int32_t most) {
     L.dr_count.swap(count);
 }
 
+// Work parts of the batches' evaluation: each batch's entries (its proxy clusters, then
+// its direct ranges) cut into S parts of about equal pair counts, a proxy cluster
+// counting P pairs per target and a direct range its sources.  Part h of batch b takes
+// entries [cut[b (S + 1) + h], cut[b (S + 1) + h + 1]).  Cut h is the first entry whose
+// midpoint lies past h / S of the batch's cost, so a part costs at most 1 / S of it plus
+// one entry, and the cuts for S / 2 parts are every other one of these.
+inline std::vector<int32_t> part_cuts(const Lists& L, int P, int S) {
+    const size_t nb = L.px_off.size() - 1;
+    std::vector<int32_t> cut(nb * (S + 1));
+    for (size_t b = 0; b < nb; ++b) {
+        const int32_t pa = L.px_off[b], np = L.px_off[b + 1] - pa, da = L.dr_off[b], nd = L.dr_off[b + 1] - da;
+        auto cost = [&](int32_t e) -> int64_t { return e < np ? P : L.dr_count[da + e - np]; };
+        int64_t total = 0;
+        for (int32_t e = 0; e < np + nd; ++e) total += cost(e);
+        int32_t* cb = &cut[b * (S + 1)];
+        cb[0] = 0;
+        cb[S] = np + nd;
+        int32_t e = 0;
+        int64_t acc = 0;
+        for (int h = 1; h < S; ++h) {
+            const int64_t goal = total * h / S;
+            while (e < np + nd && 2 * acc + cost(e) <= 2 * goal) acc += cost(e++);
+            cb[h] = e;
+        }
+    }
+    return cut;
+}
+
 // Threads for a plan over n points: one per 4,096 points, at most the host's cores
 // and 16 (measured on 65,536 points: 16 threads 5.3 ms, 4 threads 5.7 ms).
 inline int plan_threads(int64_t n) {

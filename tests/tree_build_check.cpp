@@ -245,6 +245,41 @@ static void check_case(const std::vector<double>& xyz, int64_t n, int leaf, int 
             CHECK(ok && next == n);
         }
     }
+    // work parts: cuts from 0 to the entry count, non-decreasing, each part within one
+    // entry of 1 / S of the batch's cost, and the cuts for S / 2 every other one
+    {
+        Lists s = r;
+        split_ranges(s, 512);
+        const int nb = (int)s.px_off.size() - 1;
+        std::vector<std::vector<int32_t>> cuts;
+        for (int S : {1, 2, 4, 8, 16}) cuts.push_back(part_cuts(s, P, S));
+        for (int si = 0; si < 5; ++si) {
+            const int S = 1 << si;
+            const std::vector<int32_t>& c = cuts[si];
+            CHECK((int)c.size() == nb * (S + 1));
+            bool ok = true;
+            for (int b = 0; b < nb && ok; ++b) {
+                const int32_t np = s.px_off[b + 1] - s.px_off[b], nd = s.dr_off[b + 1] - s.dr_off[b];
+                auto cost = [&](int32_t e) -> int64_t { return e < np ? P : s.dr_count[s.dr_off[b] + e - np]; };
+                int64_t total = 0, most = 0;
+                for (int32_t e = 0; e < np + nd; ++e) {
+                    total += cost(e);
+                    most = std::max(most, cost(e));
+                }
+                const int32_t* cb = &c[(size_t)b * (S + 1)];
+                ok &= cb[0] == 0 && cb[S] == np + nd;
+                for (int h = 0; h < S && ok; ++h) {
+                    ok &= cb[h] <= cb[h + 1];
+                    int64_t part = 0;
+                    for (int32_t e = cb[h]; e < cb[h + 1]; ++e) part += cost(e);
+                    ok &= part <= total / S + most + 1;
+                }
+                if (si > 0)
+                    for (int h = 0; h <= S / 2 && ok; ++h) ok &= cuts[si - 1][(size_t)b * (S / 2 + 1) + h] == cb[2 * h];
+            }
+            CHECK(ok);
+        }
+    }
     // pieces of at most `most` sources: in order, covering each batch's ranges exactly
     for (int32_t most : {1, 64, 1000}) {
         Lists s = r;
