@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "pair_math.hpp"
@@ -481,6 +482,22 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
             kahan(S2, C2, p2);
         }
     }
+    // EXF: the distinct fibers of the wave's targets (after the far field, whose slabs
+    // share this LDS), so that a chunk of direct sources none of which lies on one of
+    // them skips the per-pair fiber test
+    int* fset = reinterpret_cast<int*>(&lf[0][0]) + 9 * 64;   // after the records and their fiber ids
+    int n_fset = 0;
+    if constexpr (EXF) {
+        wave_sync();
+        uint64_t rem = __ballot(act);
+        while (rem) {   // each round takes one fiber and retires every lane on it
+            const int f = __shfl(tf, __builtin_ctzll(rem));
+            if (l == 0) fset[n_fset] = f;
+            rem &= ~__ballot(tf == f);
+            ++n_fset;
+        }
+        wave_sync();
+    }
     // near field: direct ranges
     for (int e = d_lo; e < d_hi; ++e) {
         const int64_t j0s = a.dr_start[e];
@@ -488,8 +505,13 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
         for (int32_t k0 = 0; k0 < cnt; k0 += 64) {
             const int m = min(64, cnt - k0);
             wave_sync();
+            bool onf = false;   // EXF: this lane's source lies on one of the targets' fibers
             if (l < m) {
                 const int64_t j = j0s + k0 + l;
+                if (EXF) {
+                    const int fj = a.sfid[j];
+                    for (int i = 0; i < n_fset; ++i) onf |= fset[i] == fj;
+                }
                 if (MIXED) {
                     float4* r = reinterpret_cast<float4*>(&lf[0][0]) + 2 * l;
                     r[0] = make_float4((float)(a.sxyz[j] - cx), (float)(a.sxyz[a.ns + j] - cy),
@@ -509,6 +531,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
                 }
             }
             wave_sync();
+            const bool fchk = EXF && __ballot(onf) != 0;   // wave-uniform
             if (MIXED) {
                 float p0 = 0.f, p1 = 0.f, p2 = 0.f;
                 uint64_t near = 0;
@@ -533,24 +556,33 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
                             gz = fmaxf(0.f, fmaxf(b2, -e2));
                 const float gap = sqrtf(gx * gx + gy * gy + gz * gz) - (float)B.r;
                 if (gap > 0.f && gap * gap > 1.01f * tm) {
+                    // no pair can be near: the branch-free loop, with the fiber test only
+                    // where a source of the chunk lies on a target's fiber
+                    auto far_pairs = [&](auto fib) {
 #pragma unroll 8
-                    for (int k = 0; k < m; ++k) {
-                        if (EXF && fidl[k] == tf) continue;
-                        const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
-                        const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
-                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        const float ri = __builtin_amdgcn_rsqf(r2);
-                        const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
-                        const float ds = fmaf(dx, a1.x, fmaf(dy, a1.y, dz * a1.z));
-                        const float A = fmaf(a0.w, ri3, ri);
-                        const float Bc = ds * fmaf(-3.0f * a0.w, ri5, ri3);
-                        p0 = fmaf(A, a1.x, fmaf(Bc, dx, p0));
-                        p1 = fmaf(A, a1.y, fmaf(Bc, dy, p1));
-                        p2 = fmaf(A, a1.z, fmaf(Bc, dz, p2));
-                    }
+                        for (int k = 0; k < m; ++k) {
+                            if constexpr (decltype(fib)::value)
+                                if (fidl[k] == tf) continue;
+                            const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
+                            const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                            const float ri = __builtin_amdgcn_rsqf(r2);
+                            const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                            const float ds = fmaf(dx, a1.x, fmaf(dy, a1.y, dz * a1.z));
+                            const float A = fmaf(a0.w, ri3, ri);
+                            const float Bc = ds * fmaf(-3.0f * a0.w, ri5, ri3);
+                            p0 = fmaf(A, a1.x, fmaf(Bc, dx, p0));
+                            p1 = fmaf(A, a1.y, fmaf(Bc, dy, p1));
+                            p2 = fmaf(A, a1.z, fmaf(Bc, dz, p2));
+                        }
+                    };
+                    if (fchk)
+                        far_pairs(std::true_type{});
+                    else
+                        far_pairs(std::false_type{});
                 } else {
                     for (int k = 0; k < m; ++k) {
-                        if (EXF && fidl[k] == tf) continue;
+                        if (fchk && fidl[k] == tf) continue;
                         const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
                         const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -583,7 +615,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
             } else {
                 for (int k = 0; k < m; ++k) {
                     if (j0s + k0 + k == self) continue;
-                    if (EXF && ld[k][7] == (double)tf) continue;
+                    if (fchk && ld[k][7] == (double)tf) continue;
                     const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
                     if (dx == 0.0 && dy == 0.0 && dz == 0.0) continue;
                     pair64(dx, dy, dz, ld[k][3], ld[k][4], ld[k][5], ld[k][6], u0, u1, u2);
