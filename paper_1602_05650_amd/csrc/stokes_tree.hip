@@ -85,8 +85,8 @@ __global__ __launch_bounds__(TB) void k_tr_frange(int64_t ns, const int32_t* fib
     fr[o] = make_int2((int)lo, (int)lo2);
 }
 
-// Chebyshev points of the second kind, cos(i pi / n), and their barycentric weights.
-__device__ __forceinline__ double cheb_node(int i, int n) { return cos(i * 3.14159265358979323846 / n); }
+// Barycentric weights of the Chebyshev points of the second kind, cos(i pi / n)
+// (the points themselves come from the plan's table, the values the proxies use).
 __device__ __forceinline__ double cheb_bw(int i, int n) {
     const double s = (i & 1) ? -1.0 : 1.0;
     return (i == 0 || i == n) ? 0.5 * s : s;
@@ -94,13 +94,18 @@ __device__ __forceinline__ double cheb_bw(int i, int n) {
 
 // Proxy charges, in two steps.  Each work item is a piece of at most CH_SRC
 // sources of one proxy cluster: it forms the partial charges of that piece for
-// every proxy (one proxy per thread, CB at a time), with the 1-D barycentric basis
-// values of SRC_TILE sources at a time staged in LDS.  Then k_tr_charges_sum adds
-// each cluster's pieces in a fixed order.  Single layer (6 per proxy):
-// F_k = sum_j L_k(y_j) s_j, D_k = sum_j L_k(y_j) c_j s_j.  Double layer (12):
-// M_k = sum_j L_k(y_j) q_j (w_j n_j)^T (row-major 3 x 3), N_k = sum_j L_k(y_j) w_j n_j.
-constexpr int CB = 512;
-constexpr int SRC_TILE = 160;      // 3 * SRC_TILE <= CB threads compute basis values
+// every proxy, with the 1-D barycentric basis values of SRC_TILE sources at a time
+// staged in LDS.  Then k_tr_charges_sum adds each cluster's pieces in a fixed order.
+// Single layer (6 per proxy): F_k = sum_j L_k(y_j) s_j, D_k = sum_j L_k(y_j) c_j s_j.
+// Double layer (12): M_k = sum_j L_k(y_j) q_j (w_j n_j)^T (row-major 3 x 3),
+// N_k = sum_j L_k(y_j) w_j n_j.
+// A thread owns one (ky, kz) pair of the tensor grid and a group of CG charge
+// components for every kx: per source it forms L_y L_z s_b once per component and
+// adds L_x[kx] times it for each kx, so each LDS value feeds several FMAs.  The block
+// has at least (deg + 1)^2 NC / CG threads (charges_block).
+constexpr int CB = 512;            // most threads per block (degree 10, double layer: 484)
+constexpr int SRC_TILE = 64;
+constexpr int CG = 3;              // charge components per thread
 constexpr int64_t CH_SRC = 4096;
 constexpr int64_t CHARGE_ITEMS = 1024;   // aim for the number of pieces (4 per CU)
 struct ChargeItem {
@@ -108,72 +113,92 @@ struct ChargeItem {
     int32_t count;
     int64_t start;
 };
+inline unsigned charges_block(int deg, int nc) {
+    const int tasks = (deg + 1) * (deg + 1) * (nc / CG);
+    return (unsigned)((tasks + 63) / 64 * 64);
+}
 
 // ss: [3][ns] sorted s_j (single layer) or w_j n_j (double layer); aux: [ns] c_j or
-// [3][ns] q_j.
+// [3][ns] q_j; xc: the deg + 1 Chebyshev points.
 template <bool DL>
 __global__ __launch_bounds__(CB) void k_tr_charges(int deg, const DevCl* cls, const ChargeItem* items,
                                                    const double* sxyz, int64_t ns, const double* ss,
-                                                   const double* aux, double* part) {
+                                                   const double* aux, const double* xc, double* part) {
     constexpr int NC = DL ? 12 : 6;
     __shared__ double lb[3][SRC_TILE][MAX_DEG + 1];
     __shared__ double sv[NC][SRC_TILE];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
     const ChargeItem it = items[blockIdx.x];
     const DevCl* Cp = cls + it.q;            // (the box is indexed per thread: no private copy)
-    const int n1 = deg + 1, P = n1 * n1 * n1;
-    double* out = part + (int64_t)blockIdx.x * NC * P;
-    for (int k0 = 0; k0 < P; k0 += CB) {
-        const int k = k0 + t;
-        const int kx = k / (n1 * n1), ky = (k / n1) % n1, kz = k % n1;
-        double acc[NC];
+    const int n1 = deg + 1, n2 = n1 * n1, P = n2 * n1;
+    const bool has = t < n2 * (NC / CG);
+    const int g = t / n2, yz = t - g * n2, ky = yz / n1, kz = yz - ky * n1;
+    double acc[MAX_DEG + 1][CG];
 #pragma unroll
-        for (int b = 0; b < NC; ++b) acc[b] = 0.0;
-        for (int j0 = 0; j0 < it.count; j0 += SRC_TILE) {
-            const int m = min(SRC_TILE, it.count - j0);
-            __syncthreads();
-            if (t < 3 * SRC_TILE) {
-                const int jj = t / 3, d = t - 3 * jj;
-                if (jj < m) {
-                    const int64_t j = it.start + j0 + jj;
-                    const double lo = Cp->lo[d], ext = Cp->hi[d] - lo;
-                    const double x = 2.0 * (sxyz[d * ns + j] - lo) / ext - 1.0;
-                    int hit = -1;
-                    double den = 0.0;
-                    for (int i = 0; i <= deg; ++i) {
-                        const double dx = x - cheb_node(i, deg);
-                        if (dx == 0.0) hit = i;
-                        den += cheb_bw(i, deg) / (dx == 0.0 ? 1.0 : dx);
-                    }
-                    for (int i = 0; i <= deg; ++i) {
-                        const double dx = x - cheb_node(i, deg);
-                        lb[d][jj][i] = hit >= 0 ? (i == hit ? 1.0 : 0.0) : cheb_bw(i, deg) / dx / den;
-                    }
-                    if (d == 0 && !DL) {
-                        const double cj = aux[j];
-                        for (int c = 0; c < 3; ++c) {
-                            sv[c][jj] = ss[c * ns + j];
-                            sv[3 + c][jj] = cj * ss[c * ns + j];
-                        }
-                    }
-                    if (d == 0 && DL) {
-                        for (int r = 0; r < 3; ++r)
-                            for (int c = 0; c < 3; ++c) sv[3 * r + c][jj] = aux[r * ns + j] * ss[c * ns + j];
-                        for (int c = 0; c < 3; ++c) sv[9 + c][jj] = ss[c * ns + j];
-                    }
+    for (int kx = 0; kx <= MAX_DEG; ++kx)
+#pragma unroll
+        for (int b = 0; b < CG; ++b) acc[kx][b] = 0.0;
+    for (int j0 = 0; j0 < it.count; j0 += SRC_TILE) {
+        const int m = min(SRC_TILE, it.count - j0);
+        __syncthreads();
+        for (int e = t; e < 3 * m; e += nt) {     // basis values of source jj along dimension d
+            const int jj = e / 3, d = e - 3 * jj;
+            const int64_t j = it.start + j0 + jj;
+            const double lo = Cp->lo[d], ext = Cp->hi[d] - lo;
+            const double x = 2.0 * (sxyz[d * ns + j] - lo) / ext - 1.0;
+            double w[MAX_DEG + 1];
+            int hit = -1;
+            double den = 0.0;
+#pragma unroll
+            for (int i = 0; i <= MAX_DEG; ++i) {
+                w[i] = 0.0;
+                if (i <= deg) {
+                    const double dx = x - xc[i];
+                    if (dx == 0.0) hit = i;
+                    w[i] = cheb_bw(i, deg) / (dx == 0.0 ? 1.0 : dx);
+                    den += w[i];
                 }
             }
-            __syncthreads();
-            if (k < P)
-                for (int jj = 0; jj < m; ++jj) {
-                    const double L = lb[0][jj][kx] * lb[1][jj][ky] * lb[2][jj][kz];
+            const double rden = 1.0 / den;
 #pragma unroll
-                    for (int b = 0; b < NC; ++b) acc[b] = fma(L, sv[b][jj], acc[b]);
+            for (int i = 0; i <= MAX_DEG; ++i)
+                if (i <= deg) lb[d][jj][i] = hit >= 0 ? (i == hit ? 1.0 : 0.0) : w[i] * rden;
+            if (d == 0 && !DL) {
+                const double cj = aux[j];
+                for (int c = 0; c < 3; ++c) {
+                    sv[c][jj] = ss[c * ns + j];
+                    sv[3 + c][jj] = cj * ss[c * ns + j];
                 }
+            }
+            if (d == 0 && DL) {
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) sv[3 * r + c][jj] = aux[r * ns + j] * ss[c * ns + j];
+                for (int c = 0; c < 3; ++c) sv[9 + c][jj] = ss[c * ns + j];
+            }
         }
-        if (k < P)
-            for (int b = 0; b < NC; ++b) out[b * P + k] = acc[b];
+        __syncthreads();
+        if (has)
+            for (int jj = 0; jj < m; ++jj) {
+                const double yzv = lb[1][jj][ky] * lb[2][jj][kz];
+                double tv[CG];
+#pragma unroll
+                for (int b = 0; b < CG; ++b) tv[b] = yzv * sv[g * CG + b][jj];
+#pragma unroll
+                for (int kx = 0; kx <= MAX_DEG; ++kx)
+                    if (kx <= deg) {
+                        const double lx = lb[0][jj][kx];
+#pragma unroll
+                        for (int b = 0; b < CG; ++b) acc[kx][b] = fma(lx, tv[b], acc[kx][b]);
+                    }
+            }
     }
+    if (!has) return;
+    double* out = part + (int64_t)blockIdx.x * NC * P;
+#pragma unroll
+    for (int kx = 0; kx <= MAX_DEG; ++kx)
+        if (kx <= deg)
+#pragma unroll
+            for (int b = 0; b < CG; ++b) out[(int64_t)(g * CG + b) * P + kx * n2 + yz] = acc[kx][b];
 }
 
 // The NC charges of every proxy cluster: its pieces summed in item order.  The first
@@ -971,6 +996,7 @@ struct stokes_tree {
     int32_t S_mix = 4, S = 8;     // evaluation work parts per batch: mixed, FP64 (the cuts' own)
     int32_t* cut = nullptr;       // [nb][S + 1]
     double* psum = nullptr;       // [S][3][nt]
+    double* xc = nullptr;         // [deg + 1] Chebyshev points cos(i pi / deg)
     ~stokes_tree() {
         if (mem) (void)hipFree(mem);
     }
@@ -1118,7 +1144,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
                  o_sq = take(3 * n_src * 8),
                  o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8),
                  o_si = take(sinv.size() * 4), o_sf = take(sinv.size() * 4), o_fr = take(sinv.size() * 8),
-                 o_cu = take(cut.size() * 4), o_ps = take((size_t)S * 3 * n_trg * 8);
+                 o_cu = take(cut.size() * 4), o_ps = take((size_t)S * 3 * n_trg * 8), o_xc = take(cheb.size() * 8);
     hipError_t e = hipMalloc(&t->mem, off);
     if (e != hipSuccess) {
         delete t;
@@ -1158,6 +1184,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     t->S_mix = eval_parts_mixed(nb);
     t->cut = reinterpret_cast<int32_t*>(base + o_cu);
     t->psum = reinterpret_cast<double*>(base + o_ps);
+    t->xc = reinterpret_cast<double*>(base + o_xc);
     if (same) {
         t->sinv = reinterpret_cast<int32_t*>(base + o_si);
         t->sfid = reinterpret_cast<int32_t*>(base + o_sf);
@@ -1187,6 +1214,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     if (!rc) rc = up(t->item_off, item_off.data(), item_off.size() * 4);
     if (!rc) rc = up(t->p1d, p1d.data(), p1d.size() * 8);
     if (!rc) rc = up(t->cut, cut.data(), cut.size() * 4);
+    if (!rc) rc = up(t->xc, cheb.data(), cheb.size() * 8);
     if (!rc) {
         hipError_t r = hipStreamSynchronize(st);
         if (r != hipSuccess) rc = hip_fail(r, "hipStreamSynchronize(tree)");
@@ -1251,9 +1279,9 @@ extern "C" int stokes_tree_sl_eval(stokes_tree* t, const double* src_force, cons
         hipLaunchKernelGGL(k_tr_frange, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, src_fiber,
                            t->frange);
     if (t->n_px > 0) {
-        hipLaunchKernelGGL(k_tr_charges<false>, dim3(t->n_items), dim3(CB), 0, st, t->deg,
+        hipLaunchKernelGGL(k_tr_charges<false>, dim3(t->n_items), dim3(charges_block(t->deg, 6)), 0, st, t->deg,
                            (const DevCl*)t->px_cl, (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns,
-                           (const double*)t->ss, (const double*)t->sc, t->part);
+                           (const double*)t->ss, (const double*)t->sc, (const double*)t->xc, t->part);
         hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px, (6 * t->P + TB - 1) / TB), dim3(TB), 0, st, t->P,
                            (const int32_t*)t->item_off, (const double*)t->part, t->pF, t->pD, 6, 3);
         if (mixed)
@@ -1318,9 +1346,9 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
     hipLaunchKernelGGL(k_tr_dlsrc, dim3((unsigned)((t->ns + TB - 1) / TB)), dim3(TB), 0, st, t->ns, t->sperm,
                        src_normal, src_weight, src_q, t->ss, t->sq);
     if (t->n_px > 0) {
-        hipLaunchKernelGGL(k_tr_charges<true>, dim3(t->n_items), dim3(CB), 0, st, t->deg,
+        hipLaunchKernelGGL(k_tr_charges<true>, dim3(t->n_items), dim3(charges_block(t->deg, 12)), 0, st, t->deg,
                            (const DevCl*)t->px_cl, (const ChargeItem*)t->items, (const double*)t->sxyz, t->ns,
-                           (const double*)t->ss, (const double*)t->sq, t->part);
+                           (const double*)t->ss, (const double*)t->sq, (const double*)t->xc, t->part);
         hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px, (12 * t->P + TB - 1) / TB), dim3(TB), 0, st, t->P,
                            (const int32_t*)t->item_off, (const double*)t->part, t->pM, t->pN, 12, 9);
     }
