@@ -42,6 +42,26 @@ struct DevCl {              // what the kernels need of a proxy cluster
     int64_t start, count;
 };
 
+// Sorted copies of a plan's points (the permutation made on the host: perm[j] is the
+// input index of sorted point j) and, for plans with targets = sources, the sorted index
+// of every source (inv) and of every target's own source (tself, after inv).
+__global__ __launch_bounds__(TB) void k_tr_sort_src(int64_t ns, const double* xyz, const int64_t* perm, double* out,
+                                                    int32_t* inv) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= ns) return;
+    const int64_t o = perm[j];
+    for (int c = 0; c < 3; ++c) out[c * ns + j] = xyz[c * ns + o];
+    if (inv) inv[o] = (int32_t)j;
+}
+__global__ __launch_bounds__(TB) void k_tr_sort_trg(int64_t nt, const double* xyz, const int64_t* perm, double* out,
+                                                    const int32_t* inv, int64_t* tself) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nt) return;
+    const int64_t o = perm[i];
+    for (int c = 0; c < 3; ++c) out[c * nt + i] = xyz[c * nt + o];
+    if (tself) tself[i] = inv[o];
+}
+
 // Sorted source packs: s = pref * w * f, doublet coefficient c = (eps L)^2 / 2 and
 // the mixed path's near threshold t = max(near_r, 2 eps L)^2.
 __global__ __launch_bounds__(TB) void k_tr_src(int64_t ns, const int64_t* sperm, const double* f,
@@ -1100,20 +1120,8 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     const int64_t nb = (int64_t)bt.size();
     const int S = eval_parts_fp64(nb);
     const std::vector<int32_t> cut = part_cuts(lists, P, S);
-    // sorted coordinates, self indices
-    std::vector<double> sx(3 * n_src), txs(3 * n_trg);
-    for (int64_t j = 0; j < n_src; ++j)
-        for (int d = 0; d < 3; ++d) sx[d * n_src + j] = hs[d * n_src + sperm[j]];
-    for (int64_t i = 0; i < n_trg; ++i)
-        for (int d = 0; d < 3; ++d) txs[d * n_trg + i] = tx[d * n_trg + tperm[i]];
-    std::vector<int64_t> tself;
-    std::vector<int32_t> sinv;
-    if (same) {
-        sinv.resize(n_src);
-        for (int64_t j = 0; j < n_src; ++j) sinv[sperm[j]] = (int32_t)j;
-        tself.resize(n_trg);
-        for (int64_t i = 0; i < n_trg; ++i) tself[i] = sinv[tperm[i]];
-    }
+    // (the sorted coordinates and the self indices are made on the device, k_tr_sort_*)
+    const size_t n_inv = same ? (size_t)n_src : 0, n_self = same ? (size_t)n_trg : 0;
 
     // one device allocation
     auto t = new stokes_tree();
@@ -1133,8 +1141,8 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
         off += (std::max<size_t>(bytes, 8) + 255) & ~size_t(255);
         return o;
     };
-    const size_t o_sx = take(sx.size() * 8), o_sp = take(n_src * 8), o_tx = take(txs.size() * 8),
-                 o_tp = take(n_trg * 8), o_ts = take(tself.size() * 8), o_bt = take(bt.size() * sizeof(Batch)),
+    const size_t o_sx = take(3 * n_src * 8), o_sp = take(n_src * 8), o_tx = take(3 * n_trg * 8),
+                 o_tp = take(n_trg * 8), o_ts = take(n_self * 8), o_bt = take(bt.size() * sizeof(Batch)),
                  o_po = take(px_off.size() * 4), o_pl = take(px_list.size() * 4),
                  o_pc = take((size_t)n_px * sizeof(DevCl)), o_pp = take(ppos.size() * 8),
                  o_pF = take(ppos.size() * 4 * 8), o_do = take(dr_off.size() * 4),
@@ -1143,7 +1151,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
                  o_io = take(item_off.size() * 4), o_pa = take(items.size() * 12 * P * 8),
                  o_sq = take(3 * n_src * 8),
                  o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8),
-                 o_si = take(sinv.size() * 4), o_sf = take(sinv.size() * 4), o_fr = take(sinv.size() * 8),
+                 o_si = take(n_inv * 4), o_sf = take(n_inv * 4), o_fr = take(n_inv * 8),
                  o_cu = take(cut.size() * 4), o_ps = take((size_t)S * 3 * n_trg * 8), o_xc = take(cheb.size() * 8);
     hipError_t e = hipMalloc(&t->mem, off);
     if (e != hipSuccess) {
@@ -1196,12 +1204,17 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
         return r == hipSuccess ? STOKES_OK : hip_fail(r, "hipMemcpyAsync(tree)");
     };
     int rc = STOKES_OK;
-    if (!rc) rc = up(t->sxyz, sx.data(), sx.size() * 8);
     if (!rc) rc = up(t->sperm, sperm.data(), n_src * 8);
-    if (!rc) rc = up(t->txyz, txs.data(), txs.size() * 8);
     if (!rc) rc = up(t->tperm, tperm.data(), n_trg * 8);
-    if (!rc && same) rc = up(t->tself, tself.data(), tself.size() * 8);
-    if (!rc && same) rc = up(t->sinv, sinv.data(), sinv.size() * 4);
+    if (!rc) {   // sorted coordinates; the inverse source permutation before the self indices
+        hipLaunchKernelGGL(k_tr_sort_src, dim3((unsigned)((n_src + TB - 1) / TB)), dim3(TB), 0, st, n_src, src_xyz,
+                           (const int64_t*)t->sperm, t->sxyz, t->sinv);
+        hipLaunchKernelGGL(k_tr_sort_trg, dim3((unsigned)((n_trg + TB - 1) / TB)), dim3(TB), 0, st, n_trg,
+                           same ? src_xyz : trg_xyz, (const int64_t*)t->tperm, t->txyz, (const int32_t*)t->sinv,
+                           t->tself);
+        const hipError_t r = hipGetLastError();
+        if (r != hipSuccess) rc = hip_fail(r, "tree sort kernels");
+    }
     if (!rc) rc = up(t->bt, bt.data(), bt.size() * sizeof(Batch));
     if (!rc) rc = up(t->px_off, px_off.data(), px_off.size() * 4);
     if (!rc) rc = up(t->px_list, px_list.data(), px_list.size() * 4);
