@@ -279,3 +279,29 @@ def test_tree_double_layer_off_surface_and_accumulate(S, oracle_mod, sphere):
     err = relmax(um, ref)
     print(f"double layer off the surface, mixed: err {err:.2e}")
     assert err <= 2e-8 + 2e-6
+
+
+def test_tree_evaluations_are_deterministic(S, long_fibers, sphere):
+    """The evaluation's work parts (several waves per target batch) are added in a
+    fixed order, and a plan is the same whatever the host's thread count: a second
+    evaluation on the plan, and an evaluation on a second plan of the same points,
+    give bitwise the same result (single layer with either exclusion, both
+    precisions; the mixed double layer)."""
+    fs, f = long_fibers
+    kw = dict(src_fiber=dev(fs.fiber, torch.int32), fiber_len=dev(fs.length), eps=fs.eps)
+    X, F = dev(fs.xyz), dev(f)
+    T1 = S.Tree(X, degree=6, theta=0.7, leaf_size=64)
+    T2 = S.Tree(X, degree=6, theta=0.7, leaf_size=64)
+    assert T1.info() == T2.info()
+    for mixed in (False, True):
+        for excl_fiber in (False, True):
+            a = T1.sl_eval(F, mixed=mixed, excl_fiber=excl_fiber, **kw).cpu().numpy()
+            b = T1.sl_eval(F, mixed=mixed, excl_fiber=excl_fiber, **kw).cpu().numpy()
+            c = T2.sl_eval(F, mixed=mixed, excl_fiber=excl_fiber, **kw).cpu().numpy()
+            assert np.array_equal(a, b) and np.array_equal(a, c), (mixed, excl_fiber)
+    sph, q = sphere
+    D1 = S.Tree(dev(sph.xyz), degree=8, theta=0.5, leaf_size=64)
+    args = (dev(sph.normal), dev(sph.weight), dev(q))
+    a = D1.dl_eval(*args, mixed=True).cpu().numpy()
+    b = D1.dl_eval(*args, mixed=True).cpu().numpy()
+    assert np.array_equal(a, b)
