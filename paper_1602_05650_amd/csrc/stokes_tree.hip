@@ -249,6 +249,19 @@ __global__ __launch_bounds__(TB) void k_tr_pack(int P, const double* pF, const d
     }
 }
 
+// FP32 charge records of the mixed double layer, 12 floats per proxy.
+__global__ __launch_bounds__(TB) void k_tr_pack_dl(int P, const double* pM, const double* pN, float4* pk) {
+    const int q = blockIdx.x;
+    for (int k = threadIdx.x; k < P; k += TB) {
+        const double* M = pM + (int64_t)q * 9 * P;
+        const double* N = pN + (int64_t)q * 3 * P;
+        float4* o = pk + ((int64_t)q * P + k) * 3;
+        o[0] = make_float4((float)M[k], (float)M[P + k], (float)M[2 * P + k], (float)M[3 * P + k]);
+        o[1] = make_float4((float)M[4 * P + k], (float)M[5 * P + k], (float)M[6 * P + k], (float)M[7 * P + k]);
+        o[2] = make_float4((float)M[8 * P + k], (float)N[k], (float)N[P + k], (float)N[2 * P + k]);
+    }
+}
+
 // One wave per (target batch, work part).  Lists: proxy clusters
 // px_list[px_off[b] .. px_off[b+1]), direct source ranges dr_*[dr_off[b] .. dr_off[b+1]).
 // A batch's entry sequence is its proxy list followed by its direct ranges; part h
@@ -749,6 +762,8 @@ struct DlArgs {
     const double* px_pos;    // [n_px][3][P]
     const double* pM;        // [n_px][9][P]
     const double* pN;        // [n_px][3][P]
+    const float4* pk;        // mixed: [n_px][P][3] FP32 charges M0..M3 | M4..M7 | M8 N0 N1 N2
+    const double* p1d;       // [n_px][3][deg+1] 1-D proxy coordinates of each box
     int32_t P;
     const int32_t* dr_off;
     const int64_t* dr_start;
@@ -760,6 +775,60 @@ struct DlArgs {
     const float* near2;      // mixed: [ns] FP64 below this squared distance (k_tr_dlband)
 };
 
+// Mixed double-layer far field of one proxy cluster for a compile-time degree, on the
+// tensor grid as far_tensor: the lane keeps its z offsets and their squares in
+// registers, the twelve FP32 charges of a proxy come from LDS one kx slab at a time,
+// and the slab's sum takes one Kahan step.
+template <int DEG>
+__device__ __forceinline__ void far_tensor_dl(const DlArgs& a, int q, int l, float4* slab, double cx, double cy,
+                                              double cz, float xl, float yl, float zl, float fq0x, float fq0y,
+                                              float fq0z, float& S0, float& S1, float& S2, float& C0, float& C1,
+                                              float& C2) {
+    constexpr int N1 = DEG + 1, N2 = N1 * N1;
+    const double* X1 = a.p1d + (int64_t)q * 3 * N1;
+    float DZ[N1], DZ2[N1];
+#pragma unroll
+    for (int kz = 0; kz < N1; ++kz) {
+        DZ[kz] = zl - (float)(X1[2 * N1 + kz] - cz);
+        DZ2[kz] = DZ[kz] * DZ[kz];
+    }
+    const float4* src = a.pk + (int64_t)q * N2 * N1 * 3;
+    for (int kx = 0; kx < N1; ++kx) {
+        wave_sync();
+        for (int e = l; e < 3 * N2; e += 64) slab[e] = src[3 * N2 * kx + e];
+        wave_sync();
+        const float dx = xl - (float)(X1[kx] - cx);
+        const float dx2 = dx * dx;
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+        for (int ky = 0; ky < N1; ++ky) {
+            const float dy = yl - (float)(X1[N1 + ky] - cy);
+            const float rxy = fmaf(dy, dy, dx2);
+            const float qxy = fmaf(dx, fq0x, dy * fq0y);
+#pragma unroll
+            for (int kz = 0; kz < N1; ++kz) {
+                const float4 f0 = slab[3 * (ky * N1 + kz)], f1 = slab[3 * (ky * N1 + kz) + 1],
+                             f2 = slab[3 * (ky * N1 + kz) + 2];
+                const float dz = DZ[kz];
+                const float r2 = rxy + DZ2[kz];
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float m0 = fmaf(f0.x, dx, fmaf(f0.y, dy, f0.z * dz));
+                const float m1 = fmaf(f0.w, dx, fmaf(f1.x, dy, f1.y * dz));
+                const float m2 = fmaf(f1.z, dx, fmaf(f1.w, dy, f2.x * dz));
+                const float dMd = fmaf(dx, m0, fmaf(dy, m1, dz * m2));
+                const float dN = fmaf(dx, f2.y, fmaf(dy, f2.z, dz * f2.w));
+                const float dq0 = fmaf(dz, fq0z, qxy);
+                const float kk = fmaf(-dq0, dN, dMd) * rinv5_f32(r2, ri);
+                p0 = fmaf(kk, dx, p0);
+                p1 = fmaf(kk, dy, p1);
+                p2 = fmaf(kk, dz, p2);
+            }
+        }
+        kahan(S0, C0, p0);
+        kahan(S1, C1, p1);
+        kahan(S2, C2, p2);
+    }
+}
+
 // Wave (b, h) takes part h of batch b's proxy and direct lists, as in k_tr_eval; the
 // parts' sums are added in part order, scaled and completed by k_tr_combine.  MIXED: proxies and direct pairs in
 // FP32 relative to the batch centre, each cluster's or chunk's sum added with Kahan
@@ -768,8 +837,8 @@ struct DlArgs {
 // subtracted self density is rounded to FP32 once and used as such everywhere (FP32
 // pairs and proxies, FP64 pairs, jump term), so that its constant part cancels against
 // the jump up to the discrete identity's defect.
-template <bool MIXED>
-__global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
+template <bool MIXED, int DEG = 0>
+__global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(MIXED && DEG > 0 ? 4 : 1))) void k_tr_dl_eval(DlArgs a) {
     __shared__ double lds_[EW][64][15];
     __shared__ float lfs[EW][64][16];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -805,6 +874,11 @@ __global__ __launch_bounds__(64 * EW) void k_tr_dl_eval(DlArgs a) {
         const double* pos = a.px_pos + (int64_t)q * 3 * a.P;
         const double* M = a.pM + (int64_t)q * 9 * a.P;
         const double* N = a.pN + (int64_t)q * 3 * a.P;
+        if constexpr (MIXED && DEG > 0) {
+            far_tensor_dl<DEG>(a, q, l, reinterpret_cast<float4*>(&lf[0][0]), cx, cy, cz, fxl, fyl, fzl, fq0x, fq0y,
+                               fq0z, S0, S1, S2, C0, C1, C2);
+            continue;
+        }
         if constexpr (MIXED) {
             for (int k0 = 0; k0 < a.P; k0 += 64) {     // Kahan step per 64 proxies
                 const int m = min(64, a.P - k0);
@@ -1150,7 +1224,7 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
                  o_sc = take(n_src * 8), o_st = take(n_src * 4), o_it = take(items.size() * sizeof(ChargeItem)),
                  o_io = take(item_off.size() * 4), o_pa = take(items.size() * 12 * P * 8),
                  o_sq = take(3 * n_src * 8),
-                 o_pk = take((size_t)n_px * P * 32), o_p1 = take(p1d.size() * 8),
+                 o_pk = take((size_t)n_px * P * 48), o_p1 = take(p1d.size() * 8),
                  o_si = take(n_inv * 4), o_sf = take(n_inv * 4), o_fr = take(n_inv * 8),
                  o_cu = take(cut.size() * 4), o_ps = take((size_t)S * 3 * n_trg * 8), o_xc = take(cheb.size() * 8);
     hipError_t e = hipMalloc(&t->mem, off);
@@ -1364,6 +1438,9 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
                            (const double*)t->ss, (const double*)t->sq, (const double*)t->xc, t->part);
         hipLaunchKernelGGL(k_tr_charges_sum, dim3(t->n_px, (12 * t->P + TB - 1) / TB), dim3(TB), 0, st, t->P,
                            (const int32_t*)t->item_off, (const double*)t->part, t->pM, t->pN, 12, 9);
+        if (flags & STOKES_PREC_MIXED)
+            hipLaunchKernelGGL(k_tr_pack_dl, dim3(t->n_px), dim3(TB), 0, st, t->P, (const double*)t->pM,
+                               (const double*)t->pN, t->pk);
     }
     DlArgs a{};
     a.ns = t->ns;
@@ -1381,6 +1458,8 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
     a.px_pos = t->px_pos;
     a.pM = t->pM;
     a.pN = t->pN;
+    a.pk = t->pk;
+    a.p1d = t->p1d;
     a.P = t->P;
     a.dr_off = t->dr_off;
     a.dr_start = t->dr_start;
@@ -1396,10 +1475,18 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
                            (const double*)t->sxyz, (const double*)t->ss, nr, t->st);
     a.near2 = t->st;
     const unsigned grid = (unsigned)(((int64_t)t->nb * a.S + EW - 1) / EW);
-    if (flags & STOKES_PREC_MIXED)
-        hipLaunchKernelGGL(k_tr_dl_eval<true>, dim3(grid), dim3(64 * EW), 0, st, a);
-    else
+    if (!(flags & STOKES_PREC_MIXED)) {
         hipLaunchKernelGGL(k_tr_dl_eval<false>, dim3(grid), dim3(64 * EW), 0, st, a);
+    } else {
+        switch (t->deg) {   // the tensor-grid far field for the common degrees
+            case 4: hipLaunchKernelGGL((k_tr_dl_eval<true, 4>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_tr_dl_eval<true, 5>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_tr_dl_eval<true, 6>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 7: hipLaunchKernelGGL((k_tr_dl_eval<true, 7>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 8: hipLaunchKernelGGL((k_tr_dl_eval<true, 8>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_tr_dl_eval<true, 0>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+        }
+    }
     const double pref = 3.0 / (4.0 * 3.14159265358979323846);
     hipLaunchKernelGGL(k_tr_combine, dim3((unsigned)((t->nt + TB - 1) / TB)), dim3(TB), 0, st, t->nt, a.S,
                        (const double*)t->psum, (const int64_t*)t->tperm, pref, u_out,
