@@ -829,6 +829,58 @@ __device__ __forceinline__ void far_tensor_dl(const DlArgs& a, int q, int l, flo
     }
 }
 
+// The FP64 double-layer far field of one proxy cluster on the tensor grid: z offsets
+// and their squares in registers, the twelve FP64 charges of a proxy (M row-major,
+// then N) staged one kx slab at a time.
+template <int DEG>
+__device__ __forceinline__ void far_tensor_dl64(const DlArgs& a, int q, int l, double* slab, double cx, double cy,
+                                                double cz, double xl, double yl, double zl, double q0x, double q0y,
+                                                double q0z, double& u0, double& u1, double& u2) {
+    constexpr int N1 = DEG + 1, N2 = N1 * N1;
+    const double* X1 = a.p1d + (int64_t)q * 3 * N1;
+    const double* M = a.pM + (int64_t)q * 9 * a.P;
+    const double* Nn = a.pN + (int64_t)q * 3 * a.P;
+    double DZ[N1], DZ2[N1];
+#pragma unroll
+    for (int kz = 0; kz < N1; ++kz) {
+        DZ[kz] = zl - (X1[2 * N1 + kz] - cz);
+        DZ2[kz] = DZ[kz] * DZ[kz];
+    }
+    for (int kx = 0; kx < N1; ++kx) {
+        wave_sync();
+        for (int e = l; e < 12 * N2; e += 64) {
+            const int pp = e / 12, c = e - 12 * pp, k = kx * N2 + pp;
+            slab[e] = c < 9 ? M[c * a.P + k] : Nn[(c - 9) * a.P + k];
+        }
+        wave_sync();
+        const double dx = xl - (X1[kx] - cx);
+        const double dx2 = dx * dx;
+        for (int ky = 0; ky < N1; ++ky) {
+            const double dy = yl - (X1[N1 + ky] - cy);
+            const double rxy = fma(dy, dy, dx2);
+            const double qxy = fma(dx, q0x, dy * q0y);
+#pragma unroll
+            for (int kz = 0; kz < N1; ++kz) {
+                const double* f = slab + 12 * (ky * N1 + kz);
+                const double dz = DZ[kz];
+                const double r2 = rxy + DZ2[kz];
+                const double ri = rsqrt64(r2);
+                const double ri2 = ri * ri, ri5 = ri2 * ri2 * ri;
+                const double m0 = fma(f[0], dx, fma(f[1], dy, f[2] * dz));
+                const double m1 = fma(f[3], dx, fma(f[4], dy, f[5] * dz));
+                const double m2 = fma(f[6], dx, fma(f[7], dy, f[8] * dz));
+                const double dMd = fma(dx, m0, fma(dy, m1, dz * m2));
+                const double dN = fma(dx, f[9], fma(dy, f[10], dz * f[11]));
+                const double dq0 = fma(dz, q0z, qxy);
+                const double kk = fma(-dq0, dN, dMd) * ri5;
+                u0 = fma(kk, dx, u0);
+                u1 = fma(kk, dy, u1);
+                u2 = fma(kk, dz, u2);
+            }
+        }
+    }
+}
+
 // Wave (b, h) takes part h of batch b's proxy and direct lists, as in k_tr_eval; the
 // parts' sums are added in part order, scaled and completed by k_tr_combine.  MIXED: proxies and direct pairs in
 // FP32 relative to the batch centre, each cluster's or chunk's sum added with Kahan
@@ -839,7 +891,7 @@ __device__ __forceinline__ void far_tensor_dl(const DlArgs& a, int q, int l, flo
 // the jump up to the discrete identity's defect.
 template <bool MIXED, int DEG = 0>
 __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(MIXED && DEG > 0 ? 4 : 1))) void k_tr_dl_eval(DlArgs a) {
-    __shared__ double lds_[EW][64][15];
+    __shared__ double lds_[EW][64][16];   // (an FP64 slab of degree <= 8: 12 (DEG+1)^2 <= 972 doubles)
     __shared__ float lfs[EW][64][16];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * EW + w;
@@ -847,7 +899,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(MIXED &
     if (b >= a.nb) return;
     const PartRange pr = part_range(a.px_off, a.dr_off, a.cut, a.S, a.SM, b, h);
     const int p_lo = pr.p_lo, p_hi = pr.p_hi, d_lo = pr.d_lo, d_hi = pr.d_hi;
-    double (*ld)[15] = lds_[w];
+    double (*ld)[16] = lds_[w];
     const Batch B = a.bt[b];
     const bool act = l < B.count;
     const int64_t ti = B.start + (act ? l : 0);
@@ -877,6 +929,10 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(MIXED &
         if constexpr (MIXED && DEG > 0) {
             far_tensor_dl<DEG>(a, q, l, reinterpret_cast<float4*>(&lf[0][0]), cx, cy, cz, fxl, fyl, fzl, fq0x, fq0y,
                                fq0z, S0, S1, S2, C0, C1, C2);
+            continue;
+        }
+        if constexpr (!MIXED && DEG > 0) {
+            far_tensor_dl64<DEG>(a, q, l, &ld[0][0], cx, cy, cz, xl, yl, zl, q0x, q0y, q0z, u0, u1, u2);
             continue;
         }
         if constexpr (MIXED) {
@@ -1476,7 +1532,14 @@ extern "C" int stokes_tree_dl_eval(stokes_tree* t, const double* src_normal, con
     a.near2 = t->st;
     const unsigned grid = (unsigned)(((int64_t)t->nb * a.S + EW - 1) / EW);
     if (!(flags & STOKES_PREC_MIXED)) {
-        hipLaunchKernelGGL(k_tr_dl_eval<false>, dim3(grid), dim3(64 * EW), 0, st, a);
+        switch (t->deg) {   // the tensor-grid far field for the common degrees
+            case 4: hipLaunchKernelGGL((k_tr_dl_eval<false, 4>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_tr_dl_eval<false, 5>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_tr_dl_eval<false, 6>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 7: hipLaunchKernelGGL((k_tr_dl_eval<false, 7>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            case 8: hipLaunchKernelGGL((k_tr_dl_eval<false, 8>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_tr_dl_eval<false, 0>), dim3(grid), dim3(64 * EW), 0, st, a); break;
+        }
     } else {
         switch (t->deg) {   // the tensor-grid far field for the common degrees
             case 4: hipLaunchKernelGGL((k_tr_dl_eval<true, 4>), dim3(grid), dim3(64 * EW), 0, st, a); break;
