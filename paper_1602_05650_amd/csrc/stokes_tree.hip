@@ -428,6 +428,53 @@ __device__ __forceinline__ void far_tensor(const EvalArgs& a, int q, int l, floa
     }
 }
 
+// The FP64 far field of one proxy cluster on the tensor grid: z offsets and their
+// squares in registers, the six FP64 charges of a proxy (F, then D) staged one kx slab
+// at a time.
+template <int DEG>
+__device__ __forceinline__ void far_tensor64(const EvalArgs& a, int q, int l, double* slab, double cx, double cy,
+                                             double cz, double xl, double yl, double zl, double& u0, double& u1,
+                                             double& u2) {
+    constexpr int N1 = DEG + 1, N2 = N1 * N1;
+    const double* X1 = a.p1d + (int64_t)q * 3 * N1;
+    const double* F = a.pF + (int64_t)q * 3 * a.P;
+    const double* D = a.pD + (int64_t)q * 3 * a.P;
+    double DZ[N1], DZ2[N1];
+#pragma unroll
+    for (int kz = 0; kz < N1; ++kz) {
+        DZ[kz] = zl - (X1[2 * N1 + kz] - cz);
+        DZ2[kz] = DZ[kz] * DZ[kz];
+    }
+    for (int kx = 0; kx < N1; ++kx) {
+        wave_sync();
+        for (int e = l; e < 6 * N2; e += 64) {
+            const int pp = e / 6, c = e - 6 * pp, k = kx * N2 + pp;
+            slab[e] = c < 3 ? F[c * a.P + k] : D[(c - 3) * a.P + k];
+        }
+        wave_sync();
+        const double dx = xl - (X1[kx] - cx);
+        const double dx2 = dx * dx;
+        for (int ky = 0; ky < N1; ++ky) {
+            const double dy = yl - (X1[N1 + ky] - cy);
+            const double rxy = fma(dy, dy, dx2);
+#pragma unroll
+            for (int kz = 0; kz < N1; ++kz) {
+                const double* f = slab + 6 * (ky * N1 + kz);
+                const double dz = DZ[kz];
+                const double r2 = rxy + DZ2[kz];
+                const double ri = rsqrt64(r2);
+                const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                const double dF = fma(dx, f[0], fma(dy, f[1], dz * f[2]));
+                const double dD = fma(dx, f[3], fma(dy, f[4], dz * f[5]));
+                const double g = fma(-3.0 * dD, ri5, dF * ri3);
+                u0 = fma(f[0], ri, fma(f[3], ri3, fma(g, dx, u0)));
+                u1 = fma(f[1], ri, fma(f[4], ri3, fma(g, dy, u1)));
+                u2 = fma(f[2], ri, fma(f[5], ri3, fma(g, dz, u2)));
+            }
+        }
+    }
+}
+
 // (5 waves per SIMD: 96 VGPRs without spills; 6 would spill)
 // EXF: same-fiber exclusion (targets = sources).  The near field skips every source of
 // the target's fiber; the target's own-fiber sources that the batch took through proxy
@@ -474,6 +521,10 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4
             kahan(S0, C0, p0);
             kahan(S1, C1, p1);
             kahan(S2, C2, p2);
+            continue;
+        }
+        if constexpr (!MIXED && DEG > 0) {
+            far_tensor64<DEG>(a, q, l, &ld[0][0], cx, cy, cz, x - cx, y - cy, z - cz, u0, u1, u2);
             continue;
         }
         const double* pos = a.px_pos + (int64_t)q * 3 * a.P;
@@ -1373,7 +1424,14 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
 template <bool EXF>
 static void launch_eval(bool mixed, int deg, unsigned grid, dim3 blk, hipStream_t st, const EvalArgs& a) {
     if (!mixed) {
-        hipLaunchKernelGGL((k_tr_eval<false, 0, EXF>), dim3(grid), blk, 0, st, a);
+        switch (deg) {
+            case 4: hipLaunchKernelGGL((k_tr_eval<false, 4, EXF>), dim3(grid), blk, 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_tr_eval<false, 5, EXF>), dim3(grid), blk, 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_tr_eval<false, 6, EXF>), dim3(grid), blk, 0, st, a); break;
+            case 7: hipLaunchKernelGGL((k_tr_eval<false, 7, EXF>), dim3(grid), blk, 0, st, a); break;
+            case 8: hipLaunchKernelGGL((k_tr_eval<false, 8, EXF>), dim3(grid), blk, 0, st, a); break;
+            default: hipLaunchKernelGGL((k_tr_eval<false, 0, EXF>), dim3(grid), blk, 0, st, a); break;
+        }
         return;
     }
     switch (deg) {   // the tensor-grid far field for the common degrees
