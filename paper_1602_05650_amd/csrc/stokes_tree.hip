@@ -482,9 +482,10 @@ __device__ __forceinline__ void far_tensor64(const EvalArgs& a, int q, int l, do
 // are subtracted as exact FP64 pairs, so that what remains of them is the
 // interpolation error of their share of the proxy charges.  Such sources are at least
 // (1 - theta) |c_B - c_C| from the target, so the subtraction is never singular.
-// (the EXF variant, 4 waves: its extra state would spill at 96 VGPRs)
+// (the mixed EXF variant also at 5 waves: a few values spill, and it measured 2-4%
+// faster than at 4; the FP64 EXF variant stays at 4)
 template <bool MIXED, int DEG, bool EXF = false>
-__global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF ? 4 : 5))) void k_tr_eval(EvalArgs a) {
+__global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && !MIXED ? 4 : 5))) void k_tr_eval(EvalArgs a) {
     __shared__ __align__(16) float lfs[EW][64][12];    // (a DEG <= 8 slab: 8 (DEG+1)^2 <= 768 floats)
     __shared__ double lds_[EW][64][10];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
