@@ -29,7 +29,7 @@
 namespace stokes {
 namespace tree {
 
-constexpr int TB = 256;        // threads per workgroup (4 waves, one batch per wave)
+constexpr int TB = 256;        // threads per workgroup of the element-wise kernels
 constexpr int MAX_DEG = 10;
 
 // The host-side construction (clusters, batches, interaction lists) is in
