@@ -582,7 +582,93 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const int ek = end_kind(g, f);
     const bool clamp = ek != 0;
     double* Bf = binv + (int64_t)f * m * m;
-    // phase 1: the block, column-major, into its own inverse slot (consecutive threads
+    // phase 1: the block, column-major, into its own inverse slot.
+    if constexpr (LOCAL) {
+        // Interior rows, as sums over the fiber's nodes k of L[k][j] R(k, c): the
+        // resampling table L (P4 for the position rows of component a, P2 for the
+        // tension rows) does not depend on the column, so a thread takes one column c of
+        // one row block, forms R(k, c) once per node and adds it to all the block's rows,
+        // whose L values every thread of the wave reads at the same LDS address.
+        for (int task = t; task < 4 * m; task += GJ64_T) {
+            const int rb = task / m, c = task - rb * m;   // rb: position component 0..2, or 3 (tension)
+            const bool xcol = c < n3;
+            const int ce = xcol ? c / n : 3, kc = xcol ? c - ce * n : c - n3;
+            const int nr = rb < 3 ? n - 4 : n - 2;
+            const double* L = rb < 3 ? p4t : p2t;
+            double acc[NB64 - 2];
+#pragma unroll
+            for (int jj = 0; jj < NB64 - 2; ++jj) acc[jj] = 0.0;
+            for (int k = 0; k < n; ++k) {
+                double R;
+                if (rb < 3) {
+                    const int a = rb;
+                    if (xcol) {
+                        const double Ake = (a == ce ? nal[k] : 0.0) + nbe[k] * nt[a][k] * nt[ce][k];
+                        R = Ake * d4[k * n + kc];
+                    } else {
+                        const double xa0 = nxa[0][kc], xa1 = nxa[1][kc], xa2 = nxa[2][kc];
+                        const double xaa = a == 0 ? xa0 : (a == 1 ? xa1 : xa2);
+                        const double tx = nt[0][k] * xa0 + nt[1][k] * xa1 + nt[2][k] * xa2;
+                        R = d1[k * n + kc] * (nal[k] * xaa + nbe[k] * nt[a][k] * tx);
+                    }
+                } else if (xcol) {
+                    const double x3 = s3 * d3[k * n + kc], x4 = s4 * d4[k * n + kc];
+                    const double xs2 = nxss[ce][k], xs3 = nxsss[ce][k];
+                    R = ncs[k] * 3.0 * E * xs2 * x3 + ncc[k] * 3.0 * E * (xs3 * x3 + xs2 * x4) +
+                        nal[k] * E * xs2 * x4;
+                } else {
+                    R = ncs[k] * s * d1[k * n + kc] + ncc[k] * s2 * d2[k * n + kc] -
+                        (k == kc ? nal[k] * nk2[k] : 0.0);
+                }
+                const double* Lk = L + k * n;
+#pragma unroll
+                for (int jj = 0; jj < NB64 - 2; ++jj)
+                    if (jj < nr) acc[jj] = fma(Lk[jj], R, acc[jj]);
+            }
+            const double sc = rb < 3 ? (xcol ? -e4 : -s2) : -1.0;
+#pragma unroll
+            for (int jj = 0; jj < NB64 - 2; ++jj)
+                if (jj < nr) {
+                    double v = acc[jj] * sc;
+                    if (rb < 3 && xcol && ce == rb) v += p4t[kc * n + jj] / g.dt;
+                    Bf[(int64_t)c * m + (rb < 3 ? rb * n + jj : n3 + jj)] = v;
+                }
+        }
+        // the boundary rows: the last four position rows of each component, the last two
+        // tension rows
+        const int xb0 = n > 4 ? n - 4 : 0, tb0 = n > 2 ? n - 2 : 0;
+        const int nbx = n - xb0, nbr = 3 * nbx + (n - tb0);
+        for (int e = t; e < nbr * m; e += GJ64_T) {
+            const int c = e / nbr, q = e - c * nbr;
+            const bool xcol = c < n3;
+            const int ce = xcol ? c / n : 3, kc = xcol ? c - ce * n : c - n3;
+            double v = 0.0;
+            int r;
+            if (q < 3 * nbx) {
+                const int a = q / nbx, j = xb0 + (q - a * nbx);
+                r = a * n + j;
+                if (xcol && ce == a) {
+                    const int b = j - (n - 4);
+                    const int node = b < 2 ? 0 : n - 1;
+                    if (clamp && b == 2)
+                        v = kc == n - 1 ? 1.0 : 0.0;
+                    else if (ek == 1 && b == 3)
+                        v = s * d1[(n - 1) * n + kc];
+                    else
+                        v = (b == 1 || (b == 3 && ek != 2)) ? s3 * d3[node * n + kc] : s2 * d2[node * n + kc];
+                }
+            } else {
+                const int j = tb0 + (q - 3 * nbx);
+                r = n3 + j;
+                if (clamp && j == n - 1)
+                    v = -clamp_entry(g, f, c, nullptr, s);
+                else if (!xcol)
+                    v = kc == (j == n - 2 ? 0 : n - 1) ? 1.0 : 0.0;
+            }
+            Bf[(int64_t)c * m + r] = v;
+        }
+    } else {
+    // (from the prepared products: consecutive threads
     // take consecutive rows of one column)
     for (int e = t; e < m * m; e += GJ64_T) {
         const int c = e / m, r = e - c * m;
@@ -653,6 +739,7 @@ __global__ __launch_bounds__(GJ64_T) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             }
         }
         Bf[e] = v;
+    }
     }
     __threadfence_block();
     __syncthreads();
