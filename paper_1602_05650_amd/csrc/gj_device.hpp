@@ -150,7 +150,7 @@ namespace stokes {
 constexpr int GJ64_T = 256;
 constexpr int GJ64_MAX = 128;
 
-struct Gj64Lds {
+struct alignas(16) Gj64Lds {   // (16-byte aligned: the pivot row is read as double2)
     double col[2][GJ64_MAX], row[2][GJ64_MAX], inv[2];
     unsigned wk[2][GJ64_T / 64];
     int perm[GJ64_MAX], dest[GJ64_MAX];
@@ -204,7 +204,17 @@ __device__ __forceinline__ void gj_invert64(int m, bool act, int r, int g, doubl
         const double crinv = (piv ? -1.0 : s.col[b][r]) * s.inv[b];
         if (act) {
 #pragma unroll
-            for (int jj = 0; jj < 64; ++jj) A[jj] = fma(-crinv, s.row[b][g * 64 + jj], A[jj]);
+            for (int jb = 0; jb < 64; jb += 16) {   // the pivot row in blocks of 16 (loads in flight together)
+                const double2* src = reinterpret_cast<const double2*>(&s.row[b][g * 64 + jb]);
+                double2 rv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) rv[q] = src[q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    A[jb + 2 * q] = fma(-crinv, rv[q].x, A[jb + 2 * q]);
+                    A[jb + 2 * q + 1] = fma(-crinv, rv[q].y, A[jb + 2 * q + 1]);
+                }
+            }
             const double v = reg_get(A, jp);
             reg_set(A, jp, mine ? -crinv : v);
         }
