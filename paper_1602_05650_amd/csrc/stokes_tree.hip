@@ -596,6 +596,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
     // share this LDS), so that a chunk of direct sources none of which lies on one of
     // them skips the per-pair fiber test
     int* fset = reinterpret_cast<int*>(&lf[0][0]) + 9 * 64;   // after the records and their fiber ids
+    float* tnl = &lf[0][0] + 10 * 64;                           // the staged sources' near thresholds
     int n_fset = 0;
     if constexpr (EXF) {
         wave_sync();
@@ -622,12 +623,14 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
                     const int fj = a.sfid[j];
                     for (int i = 0; i < n_fset; ++i) onf |= fset[i] == fj;
                 }
-                if (MIXED) {
+                if (MIXED) {   // records (y - c, c | s, -3 c); near thresholds apart
                     float4* r = reinterpret_cast<float4*>(&lf[0][0]) + 2 * l;
+                    const float cj = (float)a.sc[j];
                     r[0] = make_float4((float)(a.sxyz[j] - cx), (float)(a.sxyz[a.ns + j] - cy),
-                                       (float)(a.sxyz[2 * a.ns + j] - cz), (float)a.sc[j]);
+                                       (float)(a.sxyz[2 * a.ns + j] - cz), cj);
                     r[1] = make_float4((float)a.ss[j], (float)a.ss[a.ns + j], (float)a.ss[2 * a.ns + j],
-                                       a.st[j]);
+                                       -3.0f * cj);
+                    tnl[l] = a.st[j];
                     if (EXF) reinterpret_cast<int*>(&lf[0][0])[8 * 64 + l] = a.sfid[j];
                 } else {
                     ld[l][0] = a.sxyz[j];
@@ -648,11 +651,11 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
                 // can any pair of this chunk be near?  Box of the staged sources (wave
                 // reduction) against the batch's sphere, with the largest threshold.
                 const float4* rec = reinterpret_cast<const float4*>(&lf[0][0]);
-                const float4 own = rec[2 * l], own1 = rec[2 * l + 1];
+                const float4 own = rec[2 * l];
                 float b0 = l < m ? own.x : INFINITY, b1 = l < m ? own.y : INFINITY,
                       b2 = l < m ? own.z : INFINITY;
                 float e0 = l < m ? own.x : -INFINITY, e1 = l < m ? own.y : -INFINITY,
-                      e2 = l < m ? own.z : -INFINITY, tm = l < m ? own1.w : 0.f;
+                      e2 = l < m ? own.z : -INFINITY, tm = l < m ? tnl[l] : 0.f;
                 for (int o = 32; o > 0; o >>= 1) {
                     b0 = fminf(b0, __shfl_xor(b0, o));
                     b1 = fminf(b1, __shfl_xor(b1, o));
@@ -668,22 +671,28 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
                 if (gap > 0.f && gap * gap > 1.01f * tm) {
                     // no pair can be near: the branch-free loop, with the fiber test only
                     // where a source of the chunk lies on a target's fiber
+                    auto pair = [&](int k, auto fib) {
+                        if constexpr (decltype(fib)::value)
+                            if (fidl[k] == tf) return;
+                        const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
+                        const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float ri = __builtin_amdgcn_rsqf(r2);
+                        const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+                        const float ds = fmaf(dx, a1.x, fmaf(dy, a1.y, dz * a1.z));
+                        const float A = fmaf(a0.w, ri3, ri);
+                        const float Bc = ds * fmaf(a1.w, ri5, ri3);
+                        p0 = fmaf(A, a1.x, fmaf(Bc, dx, p0));
+                        p1 = fmaf(A, a1.y, fmaf(Bc, dy, p1));
+                        p2 = fmaf(A, a1.z, fmaf(Bc, dz, p2));
+                    };
                     auto far_pairs = [&](auto fib) {
+                        if (m == 64) {   // a full chunk: LDS addresses are immediate offsets
+#pragma unroll
+                            for (int k = 0; k < 64; ++k) pair(k, fib);
+                        } else {
 #pragma unroll 8
-                        for (int k = 0; k < m; ++k) {
-                            if constexpr (decltype(fib)::value)
-                                if (fidl[k] == tf) continue;
-                            const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
-                            const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
-                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                            const float ri = __builtin_amdgcn_rsqf(r2);
-                            const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
-                            const float ds = fmaf(dx, a1.x, fmaf(dy, a1.y, dz * a1.z));
-                            const float A = fmaf(a0.w, ri3, ri);
-                            const float Bc = ds * fmaf(-3.0f * a0.w, ri5, ri3);
-                            p0 = fmaf(A, a1.x, fmaf(Bc, dx, p0));
-                            p1 = fmaf(A, a1.y, fmaf(Bc, dy, p1));
-                            p2 = fmaf(A, a1.z, fmaf(Bc, dz, p2));
+                            for (int k = 0; k < m; ++k) pair(k, fib);
                         }
                     };
                     if (fchk)
@@ -696,7 +705,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
                         const float4 a0 = rec[2 * k], a1 = rec[2 * k + 1];
                         const float dx = xl - a0.x, dy = yl - a0.y, dz = zl - a0.z;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        if (r2 < a1.w) {
+                        if (r2 < tnl[k]) {
                             near |= 1ull << k;
                             continue;
                         }
@@ -704,7 +713,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
                         const float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
                         const float ds = fmaf(dx, a1.x, fmaf(dy, a1.y, dz * a1.z));
                         const float A = fmaf(a0.w, ri3, ri);
-                        const float Bc = ds * fmaf(-3.0f * a0.w, ri5, ri3);
+                        const float Bc = ds * fmaf(a1.w, ri5, ri3);
                         p0 = fmaf(A, a1.x, fmaf(Bc, dx, p0));
                         p1 = fmaf(A, a1.y, fmaf(Bc, dy, p1));
                         p2 = fmaf(A, a1.z, fmaf(Bc, dz, p2));
