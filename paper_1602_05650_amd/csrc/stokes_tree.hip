@@ -307,17 +307,22 @@ __device__ __forceinline__ void kahan(float& s, float& c, float x) {
 
 
 // FP64 single-layer pair (Stokeslet + doublet) into (ux, uy, uz).
+// (c3 = -3 c, when the caller has it at hand)
 __device__ __forceinline__ void pair64(double dx, double dy, double dz, double sx, double sy, double sz,
-                                       double c, double& ux, double& uy, double& uz) {
+                                       double c, double& ux, double& uy, double& uz, double c3) {
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double ri = rsqrt64(r2);
     const double ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
     const double ds = dx * sx + dy * sy + dz * sz;
     const double A = fma(c, ri3, ri);
-    const double B = ds * fma(-3.0 * c, ri5, ri3);
+    const double B = ds * fma(c3, ri5, ri3);
     ux = fma(A, sx, fma(B, dx, ux));
     uy = fma(A, sy, fma(B, dy, uy));
     uz = fma(A, sz, fma(B, dz, uz));
+}
+__device__ __forceinline__ void pair64(double dx, double dy, double dz, double sx, double sy, double sz,
+                                       double c, double& ux, double& uy, double& uz) {
+    pair64(dx, dy, dz, sx, sy, sz, c, ux, uy, uz, -3.0 * c);
 }
 
 // Make the wave's LDS writes visible to all of its lanes (each wave of a workgroup
@@ -641,6 +646,7 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
                     ld[l][5] = a.ss[2 * a.ns + j];
                     ld[l][6] = a.sc[j];
                     if (EXF) ld[l][7] = (double)a.sfid[j];
+                    ld[l][8] = -3.0 * a.sc[j];
                 }
             }
             wave_sync();
@@ -732,12 +738,45 @@ __global__ __launch_bounds__(64 * EW) __attribute__((amdgpu_waves_per_eu(EXF && 
                     pair64(dx, dy, dz, a.ss[j], a.ss[a.ns + j], a.ss[2 * a.ns + j], a.sc[j], u0, u1, u2);
                 }
             } else {
-                for (int k = 0; k < m; ++k) {
-                    if (j0s + k0 + k == self) continue;
-                    if (fchk && ld[k][7] == (double)tf) continue;
-                    const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
-                    if (dx == 0.0 && dy == 0.0 && dz == 0.0) continue;
-                    pair64(dx, dy, dz, ld[k][3], ld[k][4], ld[k][5], ld[k][6], u0, u1, u2);
+                // can a pair of this chunk be the target's own point or coincident?  Not
+                // when the box of the staged sources lies outside the batch's sphere (FP32
+                // offsets, with a margin for their rounding): then no per-pair test
+                const bool in = l < m;
+                float b0 = in ? (float)(ld[l][0] - cx) : INFINITY, b1 = in ? (float)(ld[l][1] - cy) : INFINITY,
+                      b2 = in ? (float)(ld[l][2] - cz) : INFINITY;
+                float e0 = in ? b0 : -INFINITY, e1 = in ? b1 : -INFINITY, e2 = in ? b2 : -INFINITY;
+                for (int o = 32; o > 0; o >>= 1) {
+                    b0 = fminf(b0, __shfl_xor(b0, o));
+                    b1 = fminf(b1, __shfl_xor(b1, o));
+                    b2 = fminf(b2, __shfl_xor(b2, o));
+                    e0 = fmaxf(e0, __shfl_xor(e0, o));
+                    e1 = fmaxf(e1, __shfl_xor(e1, o));
+                    e2 = fmaxf(e2, __shfl_xor(e2, o));
+                }
+                const float gx = fmaxf(0.f, fmaxf(b0, -e0)), gy = fmaxf(0.f, fmaxf(b1, -e1)),
+                            gz = fmaxf(0.f, fmaxf(b2, -e2));
+                const float rb = (float)B.r;
+                if (sqrtf(gx * gx + gy * gy + gz * gz) - rb > 1e-5f * rb) {
+                    if (fchk) {
+                        for (int k = 0; k < m; ++k) {
+                            if (ld[k][7] == (double)tf) continue;
+                            pair64(x - ld[k][0], y - ld[k][1], z - ld[k][2], ld[k][3], ld[k][4], ld[k][5], ld[k][6],
+                                   u0, u1, u2, ld[k][8]);
+                        }
+                    } else {
+#pragma unroll 4
+                        for (int k = 0; k < m; ++k)
+                            pair64(x - ld[k][0], y - ld[k][1], z - ld[k][2], ld[k][3], ld[k][4], ld[k][5], ld[k][6],
+                                   u0, u1, u2, ld[k][8]);
+                    }
+                } else {
+                    for (int k = 0; k < m; ++k) {
+                        if (j0s + k0 + k == self) continue;
+                        if (fchk && ld[k][7] == (double)tf) continue;
+                        const double dx = x - ld[k][0], dy = y - ld[k][1], dz = z - ld[k][2];
+                        if (dx == 0.0 && dy == 0.0 && dz == 0.0) continue;
+                        pair64(dx, dy, dz, ld[k][3], ld[k][4], ld[k][5], ld[k][6], u0, u1, u2, ld[k][8]);
+                    }
                 }
             }
         }
