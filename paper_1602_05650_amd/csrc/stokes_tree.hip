@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -1283,8 +1284,10 @@ extern "C" int stokes_tree_create(int64_t n_src, const double* src_xyz, int64_t 
     std::vector<int64_t> sperm, tperm;
     std::vector<Cluster> cl;
     std::vector<Batch> bt;
+    // the source tree and the target batches are independent: built side by side
+    std::thread batches([&] { build_batches(tx, n_trg, tperm, bt, plan_threads(n_trg)); });
     build_sources(hs, n_src, sperm, cl, leaf_size, plan_threads(n_src));
-    build_batches(tx, n_trg, tperm, bt, plan_threads(n_trg));
+    batches.join();
     const int n1 = degree + 1, P = n1 * n1 * n1;
     Lists lists;
     build_lists(bt, cl, theta, P, lists, plan_threads(n_trg));

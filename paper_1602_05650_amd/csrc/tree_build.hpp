@@ -285,19 +285,67 @@ inline void build_batches(const std::vector<double>& xyz, int64_t n, std::vector
     std::vector<Entry> order;
     std::vector<Node> tasks;
     {
-        std::vector<Node> stack{{0, n, 0}};
-        std::vector<Batch> one;
-        while (!stack.empty()) {
-            const Node g = stack.back();
-            stack.pop_back();
-            if (g.depth >= cut && g.count > BATCH) {
-                order.push_back({(int)tasks.size(), Batch{}});
-                tasks.push_back(g);
-                continue;
+        // the nodes above depth `cut`, expanded level by level with the nodes of a level
+        // on separate threads (they own disjoint ranges of p, so each sees what the
+        // serial walk would show it), then walked in the serial walk's order (upper half
+        // first) into batches and tasks
+        struct Top {
+            Node g;
+            int kid = -1;        // first of its two children (lower, upper), or -1
+            bool leaf = false;   // a batch
+            Batch b{};
+        };
+        std::vector<Top> top{{Node{0, n, 0}}};
+        std::vector<int> level{0};
+        for (int depth = 0; depth < cut && !level.empty(); ++depth) {
+            std::vector<std::vector<Node>> kids(level.size());
+            auto expand = [&](size_t i) {
+                std::vector<Node> stack;
+                std::vector<Batch> one;
+                visit(top[level[i]].g, stack, one);
+                if (!one.empty()) {
+                    top[level[i]].leaf = true;
+                    top[level[i]].b = one[0];
+                } else {
+                    kids[i] = stack;             // lower, upper
+                }
+            };
+            const int T = (int)std::max<int64_t>(1, std::min<int64_t>(n_threads, (int64_t)level.size()));
+            if (T == 1) {
+                for (size_t i = 0; i < level.size(); ++i) expand(i);
+            } else {
+                std::vector<std::thread> th;
+                auto run = [&](int t) {
+                    for (size_t i = (size_t)t; i < level.size(); i += (size_t)T) expand(i);
+                };
+                for (int t = 1; t < T; ++t) th.emplace_back(run, t);
+                run(0);
+                for (auto& x : th) x.join();
             }
-            one.clear();
-            visit(g, stack, one);
-            if (!one.empty()) order.push_back({-1, one[0]});
+            std::vector<int> next;
+            for (size_t i = 0; i < level.size(); ++i) {
+                if (kids[i].empty()) continue;
+                top[level[i]].kid = (int)top.size();
+                for (const Node& c : kids[i]) {
+                    top.push_back({c});
+                    if (c.depth < cut || c.count <= BATCH) next.push_back((int)top.size() - 1);
+                }
+            }
+            level.swap(next);
+        }
+        std::vector<int> stack{0};
+        while (!stack.empty()) {
+            const Top& u = top[stack.back()];
+            stack.pop_back();
+            if (u.leaf) {
+                order.push_back({-1, u.b});
+            } else if (u.kid >= 0) {
+                stack.push_back(u.kid);          // lower, then upper: the upper half is taken first
+                stack.push_back(u.kid + 1);
+            } else {
+                order.push_back({(int)tasks.size(), Batch{}});
+                tasks.push_back(u.g);
+            }
         }
     }
     std::vector<std::vector<Batch>> res(tasks.size());
